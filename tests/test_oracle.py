@@ -1,0 +1,343 @@
+"""Pins of the CPU oracle against what the paper and mathematics fix.
+
+Each test names the passage it follows.  None of these needs a GPU.
+"""
+import json
+import os
+from math import comb
+from types import SimpleNamespace as NS
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import pyref
+from paper_2404_03226_amd import synth
+from invariants import check_schedule
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def gold(name):
+    with open(os.path.join(GOLD, name)) as f:
+        return json.load(f)
+
+
+def wl(n, rp, col, n_cpu, n_gpu, dur, est=None):
+    dur = np.asarray(dur, np.int32).reshape(n, 2)
+    est = dur.copy() if est is None else np.asarray(est, np.int32).reshape(n, 2)
+    return NS(n=n, row_ptr=np.asarray(rp, np.int32), col=np.asarray(col, np.int32), dur=dur, est=est,
+              n_cpu=n_cpu, n_gpu=n_gpu)
+
+
+def csr(n, edges):
+    rp = np.zeros(n + 1, np.int64)
+    for a, _ in edges:
+        rp[a + 1] += 1
+    np.cumsum(rp, out=rp)
+    col = [b for a, b in sorted(edges, key=lambda e: e[0])]
+    return rp.astype(np.int32), np.asarray(col, np.int32)
+
+
+# ------------------------------------------------------------ worked examples
+
+def test_w1_attributes_and_unit_time():
+    g = gold("w1_attributes.json")
+    ia, ie, U = oracle.attributes(g["n"], g["row_ptr"], g["col"], g["est"], g["n_gpu"])
+    assert ia.tolist() == g["ia"] and ie.tolist() == g["ie_auto"] and U == g["unit_time_auto"]
+    for u, key in ((4, "ie_after_task1_u4"), (5, "ie_after_task1_u5")):
+        _, ie2, U2 = oracle.attributes(g["n"], g["row_ptr"], g["col"], g["est"], g["n_gpu"],
+                                       rem=g["rem_after_task1"], unit_time=u)
+        assert U2 == u
+        # IE is meaningful for unfinished tasks only
+        live = g["unfinished_after_task1"]
+        assert [ie2[v] for v in live] == [g[key][v] for v in live]
+
+
+def test_w2_fig1_analogue():
+    g = gold("w2_schedule.json")
+    w = wl(g["n"], g["row_ptr"], g["col"], g["n_cpu"], g["n_gpu"], np.ones((g["n"], 2)))
+    for pol in ("fifo", "inspirit"):
+        r = oracle.schedule(w, policy=pol, trace=True)
+        assert r["worker"].tolist() == g[pol]["worker"]
+        assert r["start"].tolist() == g[pol]["start"]
+        assert r["makespan"] == g[pol]["makespan"]
+        check_schedule(w, r["worker"], r["start"], r["finish"], r["makespan"])
+    tr = oracle.schedule(w, policy="inspirit", trace=True)["trace"]
+    assert tr["t"].tolist() == g["inspirit"]["trace_t"]
+    assert tr["nready"].tolist() == g["inspirit"]["trace_nready"]
+    assert tr["mode"].tolist() == g["inspirit"]["trace_mode"]
+    assert tr["cnt"].tolist() == g["inspirit"]["trace_cnt"]
+    assert oracle.brute_opt(w) == g["optimal_makespan"]
+
+
+def test_w3_regulator_table():
+    g = gold("w3_regulator.json")
+    mode, cnt, peak = oracle.regulate(g["t"], g["N"], g["W"], g["tau_bar"])
+    assert mode.tolist() == g["mode"]
+    assert cnt.tolist() == g["cnt"]
+    assert peak.tolist() == g["peak"]
+    reg = pyref.Regulator(g["W"], g["tau_bar"])
+    got = []
+    for t, N in zip(g["t"], g["N"]):
+        reg.observe(t, N)
+        got.append((reg.mode, reg.cnt, reg.peak))
+    assert got == list(zip(g["mode"], g["cnt"], g["peak"]))
+
+
+def test_regulator_explicit_parameters_override_defaults():
+    # k_inc = 1/1: a rise of 2 over 10 ticks is slow (EFI); of 20 over 10 is fast
+    mode, _, _ = oracle.regulate([0, 10, 20], [1, 3, 23], 4, 10, s_inc=1, k_num=1, k_den=1)
+    assert mode.tolist() == [0, 1, 0]
+    # a window of 5 ignores a change of 4
+    mode, _, peak = oracle.regulate([0, 10], [5, 9], 4, 10, s_inc=5)
+    assert mode.tolist() == [0, 0] and peak.tolist() == [5, 9]
+
+
+# ------------------------------------------------------------------ IA / IE
+
+def test_ia_figure_two_dependencies():
+    # Section 4.2 figure: A -> B, A -> C; completing A releases two dependencies
+    rp, col = csr(3, [(0, 1), (0, 2)])
+    ia, _, _ = oracle.attributes(3, rp, col, np.ones((3, 2)), 1)
+    assert ia[0] == 2
+
+
+@pytest.mark.parametrize("N", [2, 3, 7, 20])
+def test_complete_dag_source_ability(N):
+    # Section 4.3: fully connected DAG with one source; the source's ability
+    # counts every other task (exclusive reading: N - 1)
+    rp, col = csr(N, [(i, j) for i in range(N) for j in range(i + 1, N)])
+    ia, _, _ = oracle.attributes(N, rp, col, np.ones((N, 2)), 1)
+    assert ia[0] == N - 1
+    assert ia.tolist() == [N - 1 - i for i in range(N)]
+
+
+def _rand_small(seed, n, p):
+    return synth.random_dag(seed, n, n, p, dur_hi=40, n_gpu=1)
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_ie_limits_in_unit_time(seed):
+    # Section 4.2: U too low -> IE tends to zero; U too high -> IE converges
+    # to IA (exactly, for successors whose only remaining predecessor is v)
+    w = _rand_small(seed, 30, 0.2)
+    rp, col = oracle.canon(w.n, w.row_ptr, w.col)
+    tau = w.est[:, 1].astype(np.int64)
+    rem = np.bincount(col, minlength=w.n)
+    prev = None
+    for U in [1, 2, 3, 5, 8, 13, 21, 34, 55, 80, 81, 200]:
+        ia, ie, _ = oracle.attributes(w.n, rp, col, w.est, 1, unit_time=U)
+        for v in range(w.n):
+            succ = col[rp[v]:rp[v + 1]]
+            if succ.size and U < tau[v] + tau[succ].min():
+                assert ie[v] == 0
+        if prev is not None:
+            assert (ie >= prev).all()  # monotone in U
+        prev = ie
+    ia, ie, _ = oracle.attributes(w.n, rp, col, w.est, 1, unit_time=10 ** 6)
+    sole = np.array([int((rem[col[rp[v]:rp[v + 1]]] == 1).sum()) for v in range(w.n)])
+    assert (ie == sole).all()
+    assert (ia == np.diff(rp)).all()
+
+
+def test_ie_equals_ia_on_out_tree_at_large_u():
+    # every successor in an out-tree has v as its only predecessor
+    edges = [(0, 1), (0, 2), (1, 3), (1, 4), (1, 5), (2, 6)]
+    rp, col = csr(7, edges)
+    ia, ie, _ = oracle.attributes(7, rp, col, np.full((7, 2), 3), 1, unit_time=1000)
+    assert (ia == ie).all()
+
+
+def test_ie_uses_gpu_column_only_when_gpus_exist():
+    # Section 4.3: IE uses GPU times; with no GPU worker the CPU column stands in
+    rp, col = csr(2, [(0, 1)])
+    est = np.array([[10, 1], [10, 1]])
+    _, ie_g, _ = oracle.attributes(2, rp, col, est, 1, unit_time=5)
+    _, ie_c, _ = oracle.attributes(2, rp, col, est, 0, unit_time=5)
+    assert ie_g[0] == 1 and ie_c[0] == 0
+
+
+def test_auto_unit_time_maximises_score_over_ladder():
+    # brute force over the ladder with the oracle's own IE at fixed U
+    for seed in range(6):
+        w = _rand_small(seed + 20, 40, 0.15)
+        rp, col = oracle.canon(w.n, w.row_ptr, w.col)
+        _, _, U = oracle.attributes(w.n, rp, col, w.est, 1)
+        scores = {}
+        J = 0
+        while 2 ** J < 2 * int(w.est[:, 1].max()):
+            J += 1
+        for j in range(J + 1):
+            ia, ie, _ = oracle.attributes(w.n, rp, col, w.est, 1, unit_time=2 ** j)
+            scores[2 ** j] = int(((ie > 0) & (ie < ia)).sum())
+        best = max(scores.values())
+        assert U == max(u for u, s in scores.items() if s == best)
+
+
+# ------------------------------------------------------------- closed forms
+
+@pytest.mark.parametrize("policy", ["inspirit", "fifo", "ability", "efi"])
+def test_chain_picks_fastest_kind(policy):
+    n = 12
+    rp, col = csr(n, [(i, i + 1) for i in range(n - 1)])
+    st = synth.Stream(5, 1)
+    dur = st.randint(np.arange(2 * n).reshape(n, 2), 1, 50)
+    w = wl(n, rp, col, 3, 2, dur)
+    r = oracle.schedule(w, policy=policy)
+    assert r["makespan"] == int(dur.min(axis=1).sum())
+    check_schedule(w, r["worker"], r["start"], r["finish"], r["makespan"])
+
+
+@pytest.mark.parametrize("n,W", [(1, 1), (7, 3), (64, 8), (65, 8), (100, 7)])
+@pytest.mark.parametrize("policy", ["inspirit", "fifo"])
+def test_independent_unit_tasks(n, W, policy):
+    w = wl(n, np.zeros(n + 1), [], W, 0, np.ones((n, 2)))
+    r = oracle.schedule(w, policy=policy)
+    assert r["makespan"] == -(-n // W)
+
+
+def test_empty_dag():
+    w = wl(0, [0], [], 2, 1, np.zeros((0, 2)))
+    r = oracle.schedule(w)
+    assert r["makespan"] == 0 and r["worker"].size == 0
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_makespan_not_below_brute_force_optimum(seed):
+    n = 3 + seed % 6
+    w = synth.random_dag(31, seed, n, 0.3, dur_hi=6, n_cpu=1 + seed % 2, n_gpu=1)
+    opt = oracle.brute_opt(w)
+    lb = max(int(w.dur.min(axis=1).sum()) // (w.n_cpu + w.n_gpu), int(w.dur.min(axis=1).max()))
+    assert opt >= lb
+    for pol in ("inspirit", "fifo", "ability", "efi"):
+        r = oracle.schedule(w, policy=pol)
+        assert r["makespan"] >= opt
+
+
+def test_brute_force_exact_on_tiny_cases():
+    # one task, two kinds: the optimum is the faster kind
+    w = wl(1, [0, 0], [], 1, 1, [[7, 3]])
+    assert oracle.brute_opt(w) == 3
+    # two independent tasks on one CPU + one GPU: one on each kind
+    w = wl(2, [0, 0, 0], [], 1, 1, [[4, 5], [4, 5]])
+    assert oracle.brute_opt(w) == 5
+    # ... unless both fit on the faster kind back to back
+    w = wl(2, [0, 0, 0], [], 1, 1, [[9, 2], [9, 2]])
+    assert oracle.brute_opt(w) == 4
+
+
+def test_fifo_pops_in_push_order():
+    # Section 4.1: each worker takes its queue head; push order is (ready time, id)
+    for seed in range(10):
+        w = synth.random_dag(41, seed, 60, 0.06, dur_hi=30, n_cpu=3, n_gpu=1)
+        r = oracle.schedule(w, policy="fifo")
+        rp, col = oracle.canon(w.n, w.row_ptr, w.col)
+        ready = np.zeros(w.n, np.int64)
+        src = np.repeat(np.arange(w.n), np.diff(rp))
+        np.maximum.at(ready, col, r["finish"][src])
+        for wk in range(w.n_cpu + w.n_gpu):
+            idx = np.nonzero(r["worker"] == wk)[0]
+            by_start = idx[np.argsort(r["start"][idx], kind="stable")]
+            keys = list(zip(ready[by_start], by_start))
+            assert keys == sorted(keys)
+
+
+# ------------------------------------------------------------- invariants
+
+@pytest.mark.parametrize("policy", ["inspirit", "fifo", "ability", "efi"])
+def test_invariants_on_workloads(policy):
+    for w in (synth.cfg1(), synth.cfg2(nb=12), *synth.cfg3(select=[0, 1, 2])):
+        r = oracle.schedule(w, policy=policy, variant=oracle.HEAP)
+        check_schedule(w, r["worker"], r["start"], r["finish"], r["makespan"])
+
+
+def test_cfg2_cholesky_counts_closed_form():
+    for N in list(range(1, 13)) + [40]:
+        rp, col, ty = synth.cholesky_dag(N)
+        n_exp = N + 2 * comb(N, 2) + comb(N, 3)
+        m_exp = (N - 1) * (2 * N - 1) + 2 * comb(N, 3) + comb(N - 1, 3)
+        assert ty.size == n_exp and col.size == m_exp
+        assert (np.bincount(ty, minlength=4) == [N, comb(N, 2), comb(N, 2), comb(N, 3)]).all()
+        oracle.canon(ty.size, rp, col)  # acyclic, no repeats
+    assert synth.cfg2().n == 11480 and synth.cfg2().m == 31980
+
+
+# ------------------------------------------------- independent transcriptions
+
+@pytest.mark.parametrize("chunk", range(4))
+def test_c_plain_heap_and_python_twin_agree(chunk):
+    for i in range(chunk * 60, chunk * 60 + 60):
+        n = 1 + i % 37
+        w = synth.random_dag(7, i, n, 0.05 + (i % 5) * 0.05, n_cpu=1 + i % 3, n_gpu=i % 2, dur_hi=25,
+                             est_equal=(i % 3 != 0))
+        for pol in ("inspirit", "fifo", "ability", "efi"):
+            a = oracle.schedule(w, policy=pol, variant=oracle.PLAIN, trace=True)
+            b = oracle.schedule(w, policy=pol, variant=oracle.HEAP)
+            c = pyref.schedule(w.n, w.row_ptr, w.col, w.n_cpu, w.n_gpu, w.dur, w.est, policy=pol)
+            for k in ("worker", "start", "finish", "ie_at_pop", "mode_at_pop"):
+                assert np.array_equal(a[k], b[k]), (i, pol, k)
+                assert a[k].tolist() == c[k], (i, pol, k)
+            assert a["makespan"] == b["makespan"] == c["makespan"]
+            assert [tuple(x) for x in a["trace"].tolist()] == c["trace"]
+
+
+def test_plain_and_heap_agree_on_cholesky_and_layered():
+    for w in (synth.cfg1(), synth.cfg2(nb=20), *synth.cfg3(select=[5, 6])):
+        a = oracle.schedule(w, variant=oracle.PLAIN)
+        b = oracle.schedule(w, variant=oracle.HEAP)
+        for k in ("worker", "start", "finish", "ie_at_pop", "mode_at_pop"):
+            assert np.array_equal(a[k], b[k]), k
+
+
+def test_batch_driver_matches_single_runs():
+    ws = synth.cfg3(select=[3, 9, 17])
+    b = synth.concat(ws)
+    r = oracle.schedule_batch(b, threads=3)
+    for i, w in enumerate(ws):
+        s = oracle.schedule(w, variant=oracle.HEAP)
+        lo, hi = b.task_off[i], b.task_off[i + 1]
+        assert r["makespan"][i] == s["makespan"]
+        assert np.array_equal(r["start"][lo:hi], s["start"])
+
+
+# ------------------------------------------------------------- error paths
+
+def test_error_codes():
+    one = np.ones((3, 2))
+    rp, col = csr(3, [(0, 1), (1, 2), (2, 0)])
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.schedule(wl(3, rp, col, 1, 0, one))
+    assert e.value.code == oracle.E_CYCLE
+    for bad_rp, bad_col in (([0, 2, 1, 1], [1, 2]), ([1, 1, 1, 1], [1]), ([0, 1, 1, 1], [5]),
+                            ([0, 1, 1, 1], [0])):
+        with pytest.raises(oracle.OracleError) as e:
+            oracle.schedule(wl(3, bad_rp, bad_col, 1, 0, one))
+        assert e.value.code == oracle.E_INVAL
+    rp, col = csr(3, [(0, 1)])
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.schedule(wl(3, rp, col, 1, 0, [[1, 1], [0, 1], [1, 1]]))
+    assert e.value.code == oracle.E_RANGE
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.schedule(wl(3, rp, col, 0, 0, one))
+    assert e.value.code == oracle.E_RANGE
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.schedule(wl(3, rp, col, 1, 0, one), max_events=1)
+    assert e.value.code == oracle.E_HANG
+
+
+def test_duplicate_edges_are_merged():
+    rp = [0, 3, 3, 3]
+    a = oracle.schedule(wl(3, rp, [1, 1, 2], 1, 1, [[3, 2]] * 3))
+    b = oracle.schedule(wl(3, [0, 2, 2, 2], [1, 2], 1, 1, [[3, 2]] * 3))
+    assert np.array_equal(a["start"], b["start"])
+
+
+def test_generators_are_deterministic():
+    a, b = synth.cfg1(), synth.cfg1()
+    assert np.array_equal(a.col, b.col) and np.array_equal(a.dur, b.dur)
+    c = synth.cfg3(select=[7])[0]
+    d = synth.cfg3(select=[6, 7])[1]
+    assert np.array_equal(c.col, d.col)
+    sizes = synth.cfg3_sizes()
+    assert sizes.min() >= 200 and sizes.max() <= 20000 and sizes.size == 4096
