@@ -1,0 +1,212 @@
+/*
+ * inspirit.h -- C ABI of the MI355X (gfx950) INSPIRIT scheduling library.
+ *
+ * INSPIRIT (Y. Wang et al., "INSPIRIT: Inspiring Ability and Efficiency for
+ * Task Scheduling", arXiv 2404.03226) orders ready tasks of a task DAG on
+ * heterogeneous workers by two per-task attributes, inspiring ability (IA)
+ * and inspiring efficiency (IE), and switches between them by watching the
+ * number of ready tasks (Nready).  This library computes the attributes on
+ * the GPU and runs an integer-time, event-driven list-scheduling simulation
+ * of CPU and GPU workers with those priorities, for one DAG or for many DAGs
+ * in one persistent launch.
+ *
+ * Conventions for every call:
+ *   - Array arguments are DEVICE pointers (for example torch tensors on the
+ *     ROCm device) unless marked "host".
+ *   - `stream` is a hipStream_t passed as void*; NULL means the null stream.
+ *     Work is enqueued on it asynchronously; calls that must validate device
+ *     data (insp_build_dag) synchronise the stream before returning.
+ *   - Every call returns an insp_status.  On a non-OK status no output array
+ *     has been written (outputs of a call that fails during the simulation,
+ *     INSP_E_HANG, are unspecified) and insp_last_error() describes why.
+ *     Nothing is thrown or aborted across the ABI.
+ *   - Durations and estimates are integer ticks in [1, 2^20].  A DAG has at
+ *     most 2^21 tasks; a machine has 1..1024 workers.
+ *   - Worker w < n_cpu is a CPU worker (kind 0), the rest are GPU workers
+ *     (kind 1).  Per-task tick tables are int32 [n][2]: column 0 = CPU,
+ *     column 1 = GPU.
+ */
+#ifndef INSPIRIT_H
+#define INSPIRIT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    INSP_OK = 0,
+    INSP_E_INVAL = 1,  /* malformed argument: bad CSR, self loop, null pointer, bad enum */
+    INSP_E_CYCLE = 2,  /* the dependency graph has a cycle */
+    INSP_E_RANGE = 3,  /* a size or tick value outside the documented limits */
+    INSP_E_NOMEM = 4,  /* device or host allocation failed */
+    INSP_E_DEVICE = 5, /* a HIP runtime call failed */
+    INSP_E_HANG = 6    /* the simulation needed more events than allowed */
+} insp_status;
+
+typedef enum {
+    INSP_POLICY_INSPIRIT = 0,     /* adaptive: Nready regulator picks the pop rule */
+    INSP_POLICY_FIFO = 1,         /* plain DMDA: each worker pops in push order */
+    INSP_POLICY_ABILITY_ONLY = 2, /* always the high-ability rule */
+    INSP_POLICY_EFI_ONLY = 3      /* always the high-efficiency rule */
+} insp_policy;
+
+/* Pop rule in force at a pop (mode_at_pop) and in trace records. */
+typedef enum {
+    INSP_MODE_ABILITY = 0, /* highest IA, then highest IE, then earliest push */
+    INSP_MODE_EFI = 1,     /* highest IE, then highest IA, then earliest push */
+    INSP_MODE_EFI_LOC = 2, /* efficiency-and-locality rule; no data model, so ordered as EFI */
+    INSP_MODE_FIFO = 3     /* earliest push */
+} insp_mode;
+
+#define INSP_ALL_DAGS (-1)
+#define INSP_MAX_TASKS (1 << 21)
+#define INSP_MAX_TICK (1 << 20)
+#define INSP_MAX_WORKERS 1024
+
+/* Opaque, library-owned device copy of B >= 1 canonical DAGs. */
+typedef struct insp_dag insp_dag;
+
+typedef struct {
+    int32_t n_cpu, n_gpu;
+} insp_workers;
+
+/*
+ * Scheduling parameters.  The regulator parameters are the ones named in the
+ * Section 4.4 pseudocode; the paper prints no values, so a field <= 0 (c < 0;
+ * k_num or k_den <= 0 for the pair) selects the default, with W workers and
+ * tau_bar = max(1, floor(mean GPU estimate)) (CPU estimate without GPUs):
+ *   s_inc    task window / ascending step          default ceil(W/4)
+ *   s_dec    descending step of the peak threshold default ceil(W/2)
+ *   dec_step INC/DEC margin below the peak         default s_dec
+ *   c        slack of the descending test          default floor(s_dec/2)
+ *   k_num/k_den  expected ascending slope k_inc    default W / tau_bar
+ * unit_time is IE's unit time U in ticks (0 = automatic ladder, Section 4.3).
+ * max_events bounds the simulation's event count (0 = n + 1, the most a
+ * correct run can need); exceeding it returns INSP_E_HANG.
+ * k_num and k_den must not exceed 2^20.
+ */
+typedef struct {
+    int32_t policy;
+    int32_t unit_time;
+    int32_t s_inc, s_dec, dec_step, c, k_num, k_den;
+    int32_t max_events;
+} insp_params;
+
+/* One record per simulation event: the Nready the regulator observed (after
+ * the pushes of the event, before its pops), the rule then in force, the
+ * regulator's decrement count and peak, and the tasks pushed and popped. */
+typedef struct {
+    int64_t t;
+    int32_t nready, mode, cnt, peak, pushed, popped;
+} insp_trace_rec;
+
+/*
+ * insp_build_dag -- copy B DAGs to library-owned device memory in canonical
+ * form (Section 2: tasks are vertices, dependencies are edges; Section 4.3:
+ * traversal from the tasks with zero in-degree).
+ *   n_dags    B >= 1
+ *   task_off  host int64 [B+1], prefix sums of task counts (task_off[0] = 0)
+ *   edge_off  host int64 [B+1], prefix sums of edge counts
+ *   row_ptr   device int32, DAG b's local CSR row pointer of n_b + 1 entries
+ *             starts at element task_off[b] + b; row_ptr values are local
+ *             (0 .. m_b)
+ *   col       device int32 [edge_off[B]], successor ids local to their DAG
+ *   type      device int32 [task_off[B]] task kind (stored, may be NULL)
+ *   out       receives the handle; free it with insp_free_dag
+ * Rows are sorted and repeated edges merged on the device.  Errors:
+ * INSP_E_INVAL for a non-monotone row pointer, an id out of range or a self
+ * loop; INSP_E_CYCLE for a cycle; INSP_E_RANGE for n_b > 2^21.  The call
+ * synchronises `stream` to report these.  The caller keeps its buffers.
+ */
+int insp_build_dag(int32_t n_dags, const int64_t *task_off, const int64_t *edge_off, const int32_t *row_ptr,
+                   const int32_t *col, const int32_t *type, void *stream, insp_dag **out);
+
+/* Release a handle from insp_build_dag (NULL is ignored).  The caller must
+ * make sure no work using it is still running. */
+void insp_free_dag(insp_dag *dag);
+
+/* Task and edge counts of DAG `dag` after canonicalisation (host outputs). */
+int insp_dag_info(const insp_dag *dag, int32_t index, int64_t *n_tasks, int64_t *n_edges, int32_t *n_dags);
+
+/*
+ * insp_attributes -- inspiring ability and efficiency of every task
+ * (Section 4.2 definitions, Section 4.3 computation).
+ *   IA(v) = out-degree of v: the dependencies v's completion resolves.
+ *   IE(v) = #{successors s : rem[s] == 1 and tau(v) + tau(s) <= U}: the
+ *           successors v's completion makes ready that can also finish
+ *           within U of v's start, tau being the GPU estimate (the CPU
+ *           estimate if the machine has no GPU worker).
+ *   U     = unit_time if > 0, else the automatic choice: among U = 2^j,
+ *           j = 0..J with 2^J the first power of two >= 2 max tau, the U that
+ *           maximises #{v : 0 < IE(v) < IA(v)} (larger U on a tie).
+ *   dag         index of one DAG, or INSP_ALL_DAGS for every DAG
+ *   est         device int32 [n][2] estimates of the selected task range
+ *   workers     host, one entry (or B entries for INSP_ALL_DAGS)
+ *   rem         device int32 [n] remaining in-degrees, or NULL for the
+ *               initial in-degrees; the ladder is scored at this rem
+ *   ia, ie      device int32 [n] outputs
+ *   unit_time_used host int32 [1] (or [B]) output; the call synchronises
+ *               `stream` to fill it
+ * Task ranges are DAG-local: index 0 is the first task of the selected DAG
+ * (of DAG 0 for INSP_ALL_DAGS, the DAGs then following back to back).
+ */
+int insp_attributes(const insp_dag *dag, int32_t index, const int32_t *est, const insp_workers *workers,
+                    int32_t unit_time, const int32_t *rem, int32_t *ia, int32_t *ie, int32_t *unit_time_used,
+                    void *stream);
+
+/*
+ * insp_schedule -- simulate one DAG on the given workers (Section 2 DMDA
+ * push, Section 4.1 per-worker queues, Section 4.4 adaptive pop rule).
+ * Integer time; at each event time, in this order: newly ready tasks are
+ * pushed in ascending id to the worker minimising expected free time +
+ * queued estimates + own estimate (ties to the lowest worker id); the
+ * regulator observes Nready (queued tasks, running ones excluded); every
+ * idle worker pops the top task of its own queue under the current rule,
+ * with IE taken at the current remaining in-degrees; time advances to the
+ * next completion, whose successors' dependencies are released.  Decisions
+ * use `est`, time advances with `dur`.
+ *   dur, est     device int32 [n][2] of this DAG
+ *   worker       device int32 [n] output: worker that ran each task
+ *   start,finish device int64 [n] outputs
+ *   makespan     device int64 [1] output
+ *   ie_at_pop    device int32 [n] output, IE when popped (nullable)
+ *   mode_at_pop  device int8 [n] output, rule of that pop (nullable)
+ *   trace        device insp_trace_rec [max_events or n+1] (nullable)
+ *   n_events     device int32 [1] output: events simulated (nullable)
+ * INSP_E_HANG is detected on the device and reported by the next
+ * insp_sync_status(); the call itself returns once the work is enqueued.
+ */
+int insp_schedule(const insp_dag *dag, int32_t index, const insp_workers *workers, const int32_t *dur,
+                  const int32_t *est, const insp_params *params, int32_t *worker, int64_t *start, int64_t *finish,
+                  int64_t *makespan, int32_t *ie_at_pop, int8_t *mode_at_pop, insp_trace_rec *trace,
+                  int32_t *n_events, void *stream);
+
+/*
+ * insp_schedule_batch -- insp_schedule for all B DAGs of the handle in one
+ * persistent launch (workgroups take DAGs, largest first, from an atomic
+ * counter).  Arrays are indexed by the global task id (task_off of the
+ * handle); makespan is [B].  workers is host [B].  tune_key selects a
+ * launch configuration: NULL = the tuned default for this device, or a
+ * string "waves=<k>,grid=<g>" (k = waves per workgroup, g = workgroups);
+ * results never depend on it.  The first call with a new machine shape
+ * allocates workspace; later calls reuse it.
+ */
+int insp_schedule_batch(const insp_dag *dag, const insp_workers *workers, const int32_t *dur, const int32_t *est,
+                        const insp_params *params, int32_t *worker, int64_t *start, int64_t *finish,
+                        int64_t *makespan, int32_t *ie_at_pop, int8_t *mode_at_pop, const char *tune_key,
+                        void *stream);
+
+/* Synchronise `stream` and report a device-side failure (INSP_E_HANG) of
+ * the schedule calls enqueued on the handle since the last check. */
+int insp_sync_status(const insp_dag *dag, void *stream);
+
+/* Thread-local description of the last non-OK status. */
+const char *insp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* INSPIRIT_H */

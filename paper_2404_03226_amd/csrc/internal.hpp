@@ -1,0 +1,123 @@
+// Host-side internals of libinspirit: the DAG handle, per-shape launch
+// workspaces and error reporting.  Not part of the ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "inspirit.h"
+
+namespace insp {
+
+int set_error(int code, const char *fmt, ...);
+
+#define INSP_HIP(call)                                                                        \
+    do {                                                                                      \
+        hipError_t e_ = (call);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return ::insp::set_error(e_ == hipErrorOutOfMemory ? INSP_E_NOMEM : INSP_E_DEVICE, \
+                                     "%s failed: %s", #call, hipGetErrorString(e_));          \
+    } while (0)
+
+// Device memory owned by a handle or workspace.
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf() { release(); }
+    int alloc(size_t nbytes);
+    void release();
+    template <typename T>
+    T *as() const { return static_cast<T *>(p); }
+};
+
+// One DAG of a launch, as the kernels see it.
+struct DagDesc {
+    int64_t toff, eoff;   // first global task / edge
+    int64_t blk_off;      // first queue block of the DAG's pool
+    int64_t wl_off;       // first slot of the DAG's worker block lists
+    int32_t id;           // DAG index in the handle
+    int32_t n, m;
+    int32_t n_cpu, n_gpu;
+    int32_t nblk, maxb;   // blocks in the pool; block-list slots per worker
+    int32_t pad;
+};
+
+// Launch state for one machine shape (DAG range and worker counts): the
+// kernels' DAG descriptors, the attribute grid map, the simulation order and
+// the queue pools.  Built once, reused by every call with the same shape.
+struct Workspace {
+    int32_t count = 0;            // DAGs described
+    int32_t max_w = 0;
+    int64_t base = 0;             // first global task of the range
+    int64_t tasks = 0;
+    int32_t attr_blocks = 0;
+    DevBuf desc;                  // DagDesc [count]
+    DevBuf blkmap;                // int2 [attr_blocks]: desc index, chunk
+    DevBuf order;                 // int32 [count]: desc indices, largest first
+    DevBuf ent;                   // uint64 x2 per slot: queue entries
+    DevBuf sums;                  // uint64 x2 per block: max key under each rule
+    DevBuf wblk;                  // int32: per-worker block lists
+    DevBuf freeb;                 // int32: free-block stacks
+    DevBuf counter;               // int32 [4]: DAG dispenser
+    std::vector<int32_t> h_order;
+};
+
+}  // namespace insp
+
+struct insp_dag {
+    int32_t B = 0;
+    int device = 0;
+    int64_t N = 0, M = 0;
+    std::vector<int64_t> toff, eoff;   // canonical prefix sums (host)
+    std::vector<int32_t> order;        // DAG ids by n + m descending
+    insp::DevBuf d_toff, d_eoff;       // int64 [B+1]
+    insp::DevBuf rp;                   // int32 [N + B] local canonical row pointers
+    insp::DevBuf col;                  // int32 [M] canonical successor lists
+    insp::DevBuf type;                 // int32 [N] (may be empty)
+    insp::DevBuf word0;                // uint64 [N] in-degree << 43 | sum of predecessor ids
+    // per-task simulation state, shared by every shape (allocated on first use)
+    insp::DevBuf word;                 // uint64 [N] remaining in-degree << 43 | sum of unfinished predecessors
+    insp::DevBuf iev, ia, tau, qpos;   // int32 [N]
+    insp::DevBuf fr_a, fr_b, cand;     // int32 [N]
+    // per-DAG attribute and status records
+    insp::DevBuf dag_u, dag_taubar;    // int32 [B]
+    insp::DevBuf dag_maxtau;           // int32 [B]
+    insp::DevBuf dag_tausum;           // int64 [B]
+    insp::DevBuf dag_score;            // int32 [B * 24] ladder score, difference form
+    insp::DevBuf dag_stat;             // int32 [B * 2]: status, events
+    std::map<std::string, std::unique_ptr<insp::Workspace>> ws;
+};
+
+namespace insp {
+
+constexpr int kRungs = 24;       // ladder rungs 2^0 .. 2^22 plus a sentinel
+constexpr int kAttrThreads = 256;
+
+int ensure_state(insp_dag *dag, hipStream_t st);
+
+// Workspace for DAGs [first, first + count) with per-DAG workers (host).
+int get_workspace(insp_dag *dag, int32_t first, int32_t count, const insp_workers *workers, bool per_dag,
+                  Workspace **out);
+
+// Attribute pipeline over a workspace's DAGs: per-DAG max and sum of tau,
+// ladder scores (unit_time == 0), the chosen U, then IA and IE.  User arrays
+// are indexed relative to the workspace's first task.  With `sim_init` the
+// simulation state (word, qpos, iev, ia, tau) is reset as well.
+int run_attributes(insp_dag *dag, Workspace *ws, const int32_t *est, int32_t unit_time, const int32_t *rem,
+                   int32_t *ia_out, int32_t *ie_out, bool sim_init, hipStream_t st);
+
+int launch_sim(insp_dag *dag, Workspace *ws, const insp_params &p, const int32_t *dur, const int32_t *est,
+               int32_t *worker, int64_t *start, int64_t *finish, int64_t *makespan, int32_t *ie_at_pop,
+               int8_t *mode_at_pop, insp_trace_rec *trace, int32_t *n_events, int waves, int grid,
+               hipStream_t st);
+
+}  // namespace insp

@@ -1,0 +1,695 @@
+// Event-driven list-scheduling simulation with INSPIRIT priorities.
+//
+// One wave64 work-group owns one DAG at a time and runs its whole event loop
+// (a persistent grid takes DAGs, largest first, from an atomic dispenser).
+// Per event time t, in order (Section 2 DMDA push, Section 4.1 per-worker
+// queues, Section 4.4 adaptive pop rule):
+//   push     newly ready tasks in ascending id, each to the worker with the
+//            least expected termination time (free time + queued estimates +
+//            own estimate; ties to the lower worker id) -- a wave-wide argmin
+//            over packed (cost, worker) keys;
+//   regulate Nready = queued tasks; the Section 4.4 state machine picks the
+//            pop rule (scalar code);
+//   pop      every idle worker takes the best task of its own queue under the
+//            rule -- two wave-wide argmax steps over 64-slot blocks;
+//   advance  t = earliest finish among running tasks (wave min);
+//   release  for each completing task c and edge c -> s, one 64-bit atomic
+//            subtracts (1 << 43) + c from word[s] = rem << 43 | sum of
+//            unfinished predecessor ids.  rem reaching 0 makes s ready; rem
+//            reaching 1 leaves exactly one unfinished predecessor
+//            u = remaining sum, whose IE grows by one when tau(u) + tau(s)
+//            <= U (IE counts successors with rem == 1).  Newly ready ids of
+//            one completing task arrive ascending (rows are sorted); several
+//            such runs are merged by rank.
+//
+// Queue entry (two 64-bit words):  k = IA << 42 | IE << 21 | (2^21-1-seq),
+//                                  x = task << 42 | dur << 21 | est
+// (all fields < 2^21).  Under the ability rule the key is k itself; under the
+// efficiency rule IA and IE swap places; FIFO keeps only the seq field.  Keys
+// are unique (seq), so a max identifies one entry.  Each block keeps the max
+// key of its entries under two rules (ability-or-FIFO, efficiency); IE only
+// grows while a task waits, so increments update block maxima with atomicMax
+// and a pop rescans only the block it touched.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <string>
+
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace insp {
+
+constexpr uint64_t M21 = (1ull << 21) - 1;
+constexpr uint64_t M43 = (1ull << 43) - 1;
+constexpr uint64_t BIT63 = 1ull << 63;
+enum { ST_EST = 1, ST_DUR = 2, ST_HANG = 4 };
+
+__device__ __forceinline__ uint64_t key_of(uint64_t k, int ord) {
+    if (ord == 0) return k | BIT63;
+    if (ord == 1) return ((k >> 21) & M21) << 42 | (k >> 42) << 21 | (k & M21) | BIT63;
+    return (k & M21) | BIT63;
+}
+
+struct SimArgs {
+    const DagDesc *desc;
+    const int32_t *order;
+    int32_t count, max_w;
+    const int32_t *rp, *col;
+    const int32_t *dur, *est;
+    int64_t base;
+    unsigned long long *word;
+    int32_t *iev;
+    const int32_t *ia, *tau;
+    int32_t *qpos, *fr_a, *fr_b, *cand;
+    unsigned long long *ent, *sums;
+    int32_t *wblk, *freeb;
+    const int32_t *dag_u, *dag_taubar;
+    int32_t *stat;
+    int32_t *counter;
+    int32_t *worker;
+    int64_t *start, *finish, *makespan;
+    int32_t *ie_at_pop;
+    int8_t *mode_at_pop;
+    insp_trace_rec *trace;
+    int32_t *n_events;
+    int32_t policy, s_inc, s_dec, dec_step, c, k_num, k_den, max_events;
+};
+
+struct Lds {
+    int32_t *run, *len, *nb, *last, *seg;
+    int64_t *fin, *expend, *qest;
+};
+
+template <int WPL>
+__device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
+    const int lane = lane_id();
+    const DagDesc d = A.desc[di];
+    const int32_t n = d.n, ncpu = d.n_cpu, W = d.n_cpu + d.n_gpu;
+    int32_t status = A.stat[2 * d.id];
+    if (n == 0 || status != 0) {
+        if (lane == 0) {
+            A.makespan[di] = status ? -1 : 0;
+            if (A.n_events) A.n_events[di] = 0;
+        }
+        return;
+    }
+    const int64_t T0 = d.toff, ub = d.toff - A.base;
+    const int32_t *rp = A.rp + d.toff + d.id;
+    const int32_t *col = A.col + d.eoff;
+    unsigned long long *word = A.word + T0;
+    int32_t *iev = A.iev + T0, *qpos = A.qpos + T0, *fr_a = A.fr_a + T0, *fr_b = A.fr_b + T0, *cand = A.cand + T0;
+    const int32_t *ia = A.ia + T0, *tau = A.tau + T0;
+    const int2 *est2 = reinterpret_cast<const int2 *>(A.est) + ub;
+    const int2 *dur2 = reinterpret_cast<const int2 *>(A.dur) + ub;
+    unsigned long long *ent = A.ent + 2 * 64 * d.blk_off;
+    unsigned long long *sums = A.sums + 2 * d.blk_off;
+    int32_t *wblk = A.wblk + d.wl_off;
+    int32_t *freeb = A.freeb + d.blk_off;
+    const int32_t maxb = d.maxb;
+    const int64_t U = A.dag_u[d.id];
+
+    // regulator parameters (defaults: the paper names them, prints no values)
+    const int64_t s_inc = A.s_inc > 0 ? A.s_inc : max(1, (W + 3) / 4);
+    const int64_t s_dec = A.s_dec > 0 ? A.s_dec : max(1, (W + 1) / 2);
+    const int64_t dec_step = A.dec_step > 0 ? A.dec_step : s_dec;
+    const int64_t cc = A.c >= 0 ? A.c : s_dec / 2;
+    const bool kset = A.k_num > 0 && A.k_den > 0;
+    const int64_t k_num = kset ? A.k_num : W;
+    const int64_t k_den = kset ? A.k_den : A.dag_taubar[d.id];
+    const int slot0 = A.policy == INSP_POLICY_FIFO ? 2 : 0;
+    const int64_t max_events = A.max_events > 0 ? A.max_events : (int64_t)n + 1;
+
+    for (int32_t w = lane; w < W; w += kWave) {
+        L.run[w] = -1;
+        L.len[w] = 0;
+        L.nb[w] = 0;
+        L.last[w] = -1;
+        L.fin[w] = 0;
+        L.expend[w] = 0;
+        L.qest[w] = 0;
+    }
+    for (int32_t i = lane; i < d.nblk; i += kWave) freeb[i] = d.nblk - 1 - i;
+    int32_t nfree = d.nblk;
+
+    // initial frontier: tasks without predecessors, ascending
+    int32_t r = 0;
+    for (int32_t i0 = 0; i0 < n; i0 += kWave) {
+        int32_t i = i0 + lane;
+        bool ok = i < n && (word[i] >> 43) == 0;
+        uint64_t mk = ballot(ok);
+        if (ok) fr_a[r + lanes_below(mk)] = i;
+        r += __popcll(mk);
+    }
+    const int32_t *fr = fr_a;
+    wg_fence();
+    __syncthreads();
+
+    int64_t t = 0, nready = 0, events = 0;
+    int32_t done = 0, seq = 0;
+    int64_t peak = 0, prev_n = 0, prev_t = 0, cnt = 0;
+    int mode = INSP_MODE_ABILITY;
+
+    for (;;) {
+        if (++events > max_events) {
+            status |= ST_HANG;
+            break;
+        }
+        // ------------------------------------------------------------ push
+        int64_t ld[WPL];
+#pragma unroll
+        for (int k = 0; k < WPL; k++) {
+            int32_t w = lane + k * kWave;
+            ld[k] = INT64_MAX / 4;
+            if (w < W) {
+                int64_t B = t;
+                if (L.run[w] >= 0 && L.expend[w] > t) B = L.expend[w];
+                ld[k] = B + L.qest[w];
+            }
+        }
+        for (int32_t i0 = 0; i0 < r; i0 += kWave) {
+            const int32_t idx = i0 + lane;
+            const bool ok = idx < r;
+            const int32_t v_l = ok ? fr[idx] : 0;
+            int2 e_l = make_int2(1, 1), d_l = make_int2(1, 1);
+            int32_t ia_l = 0, ie_l = 0;
+            if (ok) {
+                e_l = est2[v_l];
+                d_l = dur2[v_l];
+                ia_l = ia[v_l];
+                ie_l = wg_load(&iev[v_l]);
+            }
+            if (ballot(ok && (d_l.x < 1 || d_l.x > INSP_MAX_TICK || d_l.y < 1 || d_l.y > INSP_MAX_TICK)))
+                status |= ST_DUR;
+            const int32_t cntj = min(kWave, r - i0);
+            for (int32_t j = 0; j < cntj; j++) {
+                const int32_t v = read_lane(v_l, j);
+                const int32_t e0 = read_lane(e_l.x, j), e1 = read_lane(e_l.y, j);
+                uint64_t best = ~0ull;
+#pragma unroll
+                for (int k = 0; k < WPL; k++) {
+                    int32_t w = lane + k * kWave;
+                    if (w < W) {
+                        uint64_t cst = (uint64_t)(ld[k] + (w < ncpu ? e0 : e1));
+                        uint64_t key = cst << 11 | (uint64_t)w;
+                        best = key < best ? key : best;
+                    }
+                }
+                best = wave_min_u64(best);
+                const int32_t ws = (int32_t)(best & 2047);
+                const bool gpu = ws >= ncpu;
+                const int32_t ek = gpu ? e1 : e0;
+                const int32_t dk = read_lane(gpu ? d_l.y : d_l.x, j);
+#pragma unroll
+                for (int k = 0; k < WPL; k++)
+                    if (lane + k * kWave == ws) ld[k] += ek;
+                const int32_t len = L.len[ws];
+                const int32_t pos = len & 63;
+                int32_t blk;
+                if (pos == 0) {
+                    nfree--;
+                    blk = wg_load(&freeb[nfree]);
+                    if (lane == 0) {
+                        int32_t nbw = L.nb[ws];
+                        wblk[(int64_t)ws * maxb + nbw] = blk;
+                        L.nb[ws] = nbw + 1;
+                        L.last[ws] = blk;
+                    }
+                } else {
+                    blk = L.last[ws];
+                }
+                const int64_t p = (int64_t)blk * 64 + pos;
+                const uint64_t kw = (uint64_t)read_lane(ia_l, j) << 42 | (uint64_t)read_lane(ie_l, j) << 21 |
+                                    (M21 - (uint64_t)seq);
+                const uint64_t xw = (uint64_t)v << 42 | (uint64_t)(dk & M21) << 21 | (uint64_t)(ek & M21);
+                if (lane == 0) {
+                    ent[2 * p] = kw;
+                    ent[2 * p + 1] = xw;
+                    qpos[v] = (int32_t)p;
+                    if (pos == 0) {
+                        sums[2 * blk] = key_of(kw, slot0);
+                        sums[2 * blk + 1] = key_of(kw, 1);
+                    } else {
+                        wg_fetch_max(&sums[2 * blk], (unsigned long long)key_of(kw, slot0));
+                        wg_fetch_max(&sums[2 * blk + 1], (unsigned long long)key_of(kw, 1));
+                    }
+                    L.len[ws] = len + 1;
+                    L.qest[ws] += ek;
+                }
+                seq++;
+                nready++;
+            }
+        }
+        wg_fence();
+        __syncthreads();
+        // -------------------------------------------------------- regulate
+        const int64_t observed = nready;
+        if (A.policy == INSP_POLICY_INSPIRIT) {
+            if (nready > peak) peak = nready;
+            int64_t dn = nready - prev_n;
+            if ((dn < 0 ? -dn : dn) >= s_inc) {
+                int64_t dt = t - prev_t;
+                prev_n = nready;
+                prev_t = t;
+                if (nready >= peak - dec_step) {
+                    cnt = 0;
+                    if (dn >= s_inc) {
+                        if (dt == 0 || dn * k_den > k_num * dt) mode = INSP_MODE_ABILITY;
+                        else if (dn * k_den < k_num * dt) mode = INSP_MODE_EFI;
+                    }
+                } else if (nready > peak - s_dec * cnt) {
+                    mode = INSP_MODE_ABILITY;
+                } else if (nready <= peak - s_dec * (cnt + 1) + cc) {
+                    mode = INSP_MODE_EFI_LOC;
+                    if (nready <= peak - s_dec * (cnt + 1)) cnt++;
+                }
+            }
+        }
+        const int pmode = A.policy == INSP_POLICY_FIFO ? INSP_MODE_FIFO
+                        : A.policy == INSP_POLICY_ABILITY_ONLY ? INSP_MODE_ABILITY
+                        : A.policy == INSP_POLICY_EFI_ONLY ? INSP_MODE_EFI : mode;
+        const int ord = pmode == INSP_MODE_FIFO ? 2 : pmode == INSP_MODE_ABILITY ? 0 : 1;
+        const int slot = ord == 1 ? 1 : 0;
+        // ------------------------------------------------------------- pop
+        int32_t popped = 0;
+        for (int32_t w0 = 0; w0 < W; w0 += kWave) {
+            const int32_t wl = w0 + lane;
+            uint64_t mask = ballot(wl < W && L.run[wl] < 0 && L.len[wl] > 0);
+            while (mask) {
+                const int32_t w = w0 + (int32_t)__builtin_ctzll(mask);
+                mask &= mask - 1;
+                int32_t nb = L.nb[w], len = L.len[w];
+                const int32_t last = L.last[w];
+                int32_t bb = last;
+                if (nb > 1) {
+                    uint64_t bk = 0;
+                    int32_t bid = -1;
+                    for (int32_t i0 = 0; i0 < nb; i0 += kWave) {
+                        int32_t i = i0 + lane;
+                        if (i < nb) {
+                            int32_t b = wg_load(&wblk[(int64_t)w * maxb + i]);
+                            uint64_t k = wg_load(&sums[2 * b + slot]);
+                            if (k > bk) {
+                                bk = k;
+                                bid = b;
+                            }
+                        }
+                    }
+                    uint64_t km = wave_max_u64(bk);
+                    uint64_t wm = ballot(bk == km && bid >= 0);
+                    bb = read_lane(bid, (int)__builtin_ctzll(wm));
+                }
+                const int32_t lastpos = (len - 1) & 63;
+                const int32_t cntb = bb == last ? lastpos + 1 : 64;
+                const bool ok = lane < cntb;
+                const int64_t eb = (int64_t)bb * 64;
+                uint64_t kw = 0, xw = 0;
+                if (ok) {
+                    kw = wg_load(&ent[2 * (eb + lane)]);
+                    xw = wg_load(&ent[2 * (eb + lane) + 1]);
+                }
+                const uint64_t key = ok ? key_of(kw, ord) : 0;
+                const uint64_t km = wave_max_u64(key);
+                const int win = (int)__builtin_ctzll(ballot(key == km && ok));
+                const uint64_t vk = read_lane64(kw, win), vx = read_lane64(xw, win);
+                const int64_t p = eb + win;
+                const int64_t q = (int64_t)last * 64 + lastpos;
+                const int32_t v = (int32_t)(vx >> 42);
+                const int32_t dk = (int32_t)((vx >> 21) & M21), ek = (int32_t)(vx & M21);
+                uint64_t mk = 0, mx = 0;
+                if (p != q) {
+                    if (last == bb) {
+                        mk = read_lane64(kw, lastpos);
+                        mx = read_lane64(xw, lastpos);
+                    } else {
+                        mk = wg_load(&ent[2 * q]);
+                        mx = wg_load(&ent[2 * q + 1]);
+                    }
+                    if (lane == 0) {
+                        ent[2 * p] = mk;
+                        ent[2 * p + 1] = mx;
+                        qpos[(int32_t)(mx >> 42)] = (int32_t)p;
+                    }
+                }
+                if (lane == 0) qpos[v] = -1;
+                len--;
+                const bool freed = (len & 63) == 0;
+                int32_t newlast = last;
+                if (freed) {
+                    if (lane == 0) freeb[nfree] = last;
+                    nfree++;
+                    nb--;
+                    newlast = nb > 0 ? wg_load(&wblk[(int64_t)w * maxb + nb - 1]) : -1;
+                }
+                if (!(bb == last && freed)) {
+                    // block bb after the removal: the winner's slot holds the
+                    // moved entry; if bb is the last block its final slot left
+                    uint64_t nk = (p != q && lane == win) ? mk : kw;
+                    bool valid = ok && !(bb == last && lane == lastpos);
+                    uint64_t s0 = wave_max_u64(valid ? key_of(nk, slot0) : 0);
+                    uint64_t s1 = wave_max_u64(valid ? key_of(nk, 1) : 0);
+                    if (lane == 0) {
+                        sums[2 * bb] = s0;
+                        sums[2 * bb + 1] = s1;
+                    }
+                }
+                if (last != bb && !freed) {
+                    // the last block lost its final entry to bb
+                    const int32_t cl = ((len - 1) & 63) + 1;
+                    uint64_t kl = lane < cl ? wg_load(&ent[2 * ((int64_t)last * 64 + lane)]) : 0;
+                    uint64_t s0 = wave_max_u64(lane < cl ? key_of(kl, slot0) : 0);
+                    uint64_t s1 = wave_max_u64(lane < cl ? key_of(kl, 1) : 0);
+                    if (lane == 0) {
+                        sums[2 * last] = s0;
+                        sums[2 * last + 1] = s1;
+                    }
+                }
+                if (lane == 0) {
+                    L.len[w] = len;
+                    L.nb[w] = nb;
+                    L.last[w] = newlast;
+                    L.run[w] = v;
+                    L.fin[w] = t + dk;
+                    L.expend[w] = t + ek;
+                    L.qest[w] -= ek;
+                    const int64_t uv = ub + v;
+                    A.worker[uv] = w;
+                    A.start[uv] = t;
+                    A.finish[uv] = t + dk;
+                    if (A.ie_at_pop) A.ie_at_pop[uv] = (int32_t)((vk >> 21) & M21);
+                    if (A.mode_at_pop) A.mode_at_pop[uv] = (int8_t)pmode;
+                }
+                nready--;
+                popped++;
+            }
+        }
+        if (A.trace && lane == 0 && events <= max_events) {
+            insp_trace_rec rec;
+            rec.t = t;
+            rec.nready = (int32_t)observed;
+            rec.mode = pmode;
+            rec.cnt = (int32_t)cnt;
+            rec.peak = (int32_t)peak;
+            rec.pushed = r;
+            rec.popped = popped;
+            A.trace[events - 1] = rec;
+        }
+        if (done == n) break;
+        // --------------------------------------------------------- advance
+        uint64_t tm = ~0ull;
+        for (int32_t w = lane; w < W; w += kWave)
+            if (L.run[w] >= 0 && (uint64_t)L.fin[w] < tm) tm = (uint64_t)L.fin[w];
+        tm = wave_min_u64(tm);
+        if (tm == ~0ull) {
+            status |= ST_HANG;
+            break;
+        }
+        t = (int64_t)tm;
+        // --------------------------------------------------------- release
+        r = 0;
+        int32_t nc = 0, nseg = 0;
+        for (int32_t w0 = 0; w0 < W; w0 += kWave) {
+            const int32_t wl = w0 + lane;
+            const bool fin_now = wl < W && L.run[wl] >= 0 && L.fin[wl] == t;
+            uint64_t mask = ballot(fin_now);
+            const int32_t c_l = fin_now ? L.run[wl] : -1;
+            if (fin_now) L.run[wl] = -1;
+            while (mask) {
+                const int l = (int)__builtin_ctzll(mask);
+                mask &= mask - 1;
+                const int32_t c = read_lane(c_l, l);
+                done++;
+                const int32_t a = rp[c], z = rp[c + 1];
+                const int32_t r0 = r;
+                const unsigned long long dec = 0ull - ((1ull << 43) + (unsigned long long)c);
+                for (int32_t e0 = a; e0 < z; e0 += kWave) {
+                    const int32_t e = e0 + lane;
+                    const bool ok = e < z;
+                    int32_t s = 0;
+                    uint64_t old = 0;
+                    if (ok) {
+                        s = col[e];
+                        old = wg_fetch_add(&word[s], dec);
+                    }
+                    const int64_t nr = (int64_t)(old >> 43) - 1;
+                    const bool rdy = ok && nr == 0, cd = ok && nr == 1;
+                    const uint64_t m1 = ballot(rdy), m2 = ballot(cd);
+                    if (rdy) fr_a[r + lanes_below(m1)] = s;
+                    if (cd) cand[nc + lanes_below(m2)] = s;
+                    r += __popcll(m1);
+                    nc += __popcll(m2);
+                }
+                if (r > r0) {
+                    if (lane == 0) L.seg[nseg] = r;
+                    nseg++;
+                }
+            }
+        }
+        wg_fence();
+        __syncthreads();
+        // successors left with one unfinished predecessor raise its IE
+        for (int32_t i0 = 0; i0 < nc; i0 += kWave) {
+            const int32_t i = i0 + lane;
+            if (i < nc) {
+                const int32_t s = cand[i];
+                const uint64_t wd = wg_load(&word[s]);
+                if ((wd >> 43) == 1) {
+                    const int32_t u = (int32_t)(wd & M43);
+                    if ((int64_t)tau[u] + tau[s] <= U) {
+                        wg_fetch_add(&iev[u], 1);
+                        const int32_t pu = wg_load(&qpos[u]);
+                        if (pu >= 0) {
+                            const uint64_t nk = wg_fetch_add(&ent[2 * (int64_t)pu], 1ull << 21) + (1ull << 21);
+                            wg_fetch_max(&sums[2 * (int64_t)(pu >> 6)], (unsigned long long)key_of(nk, slot0));
+                            wg_fetch_max(&sums[2 * (int64_t)(pu >> 6) + 1], (unsigned long long)key_of(nk, 1));
+                        }
+                    }
+                }
+            }
+        }
+        // several completions: merge their ascending runs by rank
+        fr = fr_a;
+        if (nseg > 1) {
+            for (int32_t i0 = 0; i0 < r; i0 += kWave) {
+                const int32_t i = i0 + lane;
+                if (i < r) {
+                    const int32_t x = fr_a[i];
+                    int32_t rank = 0, lo = 0;
+                    for (int32_t g = 0; g < nseg; g++) {
+                        const int32_t hi = L.seg[g];
+                        if (i >= lo && i < hi) {
+                            rank += i - lo;
+                        } else {
+                            int32_t a = lo, b = hi;  // count of run g below x
+                            while (a < b) {
+                                int32_t mid = (a + b) >> 1;
+                                if (fr_a[mid] < x) a = mid + 1;
+                                else b = mid;
+                            }
+                            rank += a - lo;
+                        }
+                        lo = hi;
+                    }
+                    fr_b[rank] = x;
+                }
+            }
+            fr = fr_b;
+        }
+        wg_fence();
+        __syncthreads();
+    }
+    if (lane == 0) {
+        A.makespan[di] = (status & ST_HANG) ? -1 : t;
+        if (A.n_events) A.n_events[di] = (int32_t)min(events, (int64_t)INT32_MAX);
+        if (status) atomicOr(&A.stat[2 * d.id], status);
+        A.stat[2 * d.id + 1] = (int32_t)min(events, (int64_t)INT32_MAX);
+    }
+}
+
+template <int WPL>
+__global__ __launch_bounds__(64) void k_sim(SimArgs A) {
+    extern __shared__ int64_t lds64[];
+    const int32_t MW = A.max_w;
+    Lds L;
+    L.fin = lds64;
+    L.expend = lds64 + MW;
+    L.qest = lds64 + 2 * MW;
+    int32_t *l32 = reinterpret_cast<int32_t *>(lds64 + 3 * MW);
+    L.run = l32;
+    L.len = l32 + MW;
+    L.nb = l32 + 2 * MW;
+    L.last = l32 + 3 * MW;
+    L.seg = l32 + 4 * MW;
+    const int lane = lane_id();
+    for (;;) {
+        int32_t got = 0;
+        if (lane == 0) got = dev_fetch_add(A.counter, 1);
+        const int32_t i = read_lane(got, 0);
+        if (i >= A.count) break;
+        sim_dag<WPL>(A, A.order[i], L);
+        __syncthreads();
+    }
+}
+
+__global__ void k_counter_reset(int32_t *c) {
+    if (threadIdx.x < 4) c[threadIdx.x] = 0;
+}
+
+int launch_sim(insp_dag *dag, Workspace *ws, const insp_params &p, const int32_t *dur, const int32_t *est,
+               int32_t *worker, int64_t *start, int64_t *finish, int64_t *makespan, int32_t *ie_at_pop,
+               int8_t *mode_at_pop, insp_trace_rec *trace, int32_t *n_events, int waves, int grid,
+               hipStream_t st) {
+    (void)waves;
+    SimArgs A;
+    memset(&A, 0, sizeof A);
+    A.desc = ws->desc.as<DagDesc>();
+    A.order = ws->order.as<int32_t>();
+    A.count = ws->count;
+    A.max_w = ws->max_w;
+    A.rp = dag->rp.as<int32_t>();
+    A.col = dag->col.as<int32_t>();
+    A.dur = dur;
+    A.est = est;
+    A.base = ws->base;
+    A.word = dag->word.as<unsigned long long>();
+    A.iev = dag->iev.as<int32_t>();
+    A.ia = dag->ia.as<int32_t>();
+    A.tau = dag->tau.as<int32_t>();
+    A.qpos = dag->qpos.as<int32_t>();
+    A.fr_a = dag->fr_a.as<int32_t>();
+    A.fr_b = dag->fr_b.as<int32_t>();
+    A.cand = dag->cand.as<int32_t>();
+    A.ent = ws->ent.as<unsigned long long>();
+    A.sums = ws->sums.as<unsigned long long>();
+    A.wblk = ws->wblk.as<int32_t>();
+    A.freeb = ws->freeb.as<int32_t>();
+    A.dag_u = dag->dag_u.as<int32_t>();
+    A.dag_taubar = dag->dag_taubar.as<int32_t>();
+    A.stat = dag->dag_stat.as<int32_t>();
+    A.counter = ws->counter.as<int32_t>();
+    A.worker = worker;
+    A.start = start;
+    A.finish = finish;
+    A.makespan = makespan;
+    A.ie_at_pop = ie_at_pop;
+    A.mode_at_pop = mode_at_pop;
+    A.trace = trace;
+    A.n_events = n_events;
+    A.policy = p.policy;
+    A.s_inc = p.s_inc;
+    A.s_dec = p.s_dec;
+    A.dec_step = p.dec_step;
+    A.c = p.c;
+    A.k_num = p.k_num;
+    A.k_den = p.k_den;
+    A.max_events = p.max_events;
+    const size_t lds = (size_t)ws->max_w * (3 * 8 + 5 * 4) + 16;
+    grid = std::max(1, std::min(grid, ws->count));
+    hipLaunchKernelGGL(k_counter_reset, dim3(1), dim3(64), 0, st, A.counter);
+    if (ws->max_w <= 64)
+        hipLaunchKernelGGL(k_sim<1>, dim3(grid), dim3(64), lds, st, A);
+    else if (ws->max_w <= 128)
+        hipLaunchKernelGGL(k_sim<2>, dim3(grid), dim3(64), lds, st, A);
+    else
+        hipLaunchKernelGGL(k_sim<16>, dim3(grid), dim3(64), lds, st, A);
+    INSP_HIP(hipGetLastError());
+    return INSP_OK;
+}
+
+}  // namespace insp
+
+using namespace insp;
+
+static int check_params(const insp_params *p) {
+    if (!p) return set_error(INSP_E_INVAL, "null params");
+    if (p->policy < 0 || p->policy > 3) return set_error(INSP_E_INVAL, "unknown policy %d", p->policy);
+    if (p->unit_time < 0 || p->max_events < 0) return set_error(INSP_E_INVAL, "negative unit_time/max_events");
+    if (p->k_num > INSP_MAX_TICK || p->k_den > INSP_MAX_TICK) return set_error(INSP_E_RANGE, "k_num/k_den > 2^20");
+    return INSP_OK;
+}
+
+static int check_workers(const insp_workers *w, int32_t count) {
+    for (int32_t i = 0; i < count; i++) {
+        if (w[i].n_cpu < 0 || w[i].n_gpu < 0) return set_error(INSP_E_INVAL, "negative worker count");
+        int32_t W = w[i].n_cpu + w[i].n_gpu;
+        if (W < 1 || W > INSP_MAX_WORKERS) return set_error(INSP_E_RANGE, "worker count %d outside [1, 1024]", W);
+    }
+    return INSP_OK;
+}
+
+static int default_grid(int count) {
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) == hipSuccess) cus = prop.multiProcessorCount;
+    }
+    return std::min(count, cus * 8);
+}
+
+extern "C" int insp_schedule(const insp_dag *cdag, int32_t index, const insp_workers *workers, const int32_t *dur,
+                             const int32_t *est, const insp_params *params, int32_t *worker, int64_t *start,
+                             int64_t *finish, int64_t *makespan, int32_t *ie_at_pop, int8_t *mode_at_pop,
+                             insp_trace_rec *trace, int32_t *n_events, void *stream) {
+    insp_dag *dag = const_cast<insp_dag *>(cdag);
+    if (!dag || !workers || !makespan) return set_error(INSP_E_INVAL, "null argument");
+    if (index < 0 || index >= dag->B) return set_error(INSP_E_INVAL, "dag index %d out of range", index);
+    int rc;
+    if ((rc = check_params(params)) || (rc = check_workers(workers, 1))) return rc;
+    const int64_t n = dag->toff[index + 1] - dag->toff[index];
+    if (n > 0 && (!dur || !est || !worker || !start || !finish)) return set_error(INSP_E_INVAL, "null array");
+    hipStream_t st = (hipStream_t)stream;
+    INSP_HIP(hipSetDevice(dag->device));
+    if ((rc = ensure_state(dag, st))) return rc;
+    Workspace *ws;
+    if ((rc = get_workspace(dag, index, 1, workers, true, &ws))) return rc;
+    if ((rc = run_attributes(dag, ws, est, params->unit_time, nullptr, nullptr, nullptr, true, st))) return rc;
+    return launch_sim(dag, ws, *params, dur, est, worker, start, finish, makespan, ie_at_pop, mode_at_pop, trace,
+                      n_events, 1, 1, st);
+}
+
+static void parse_tune(const char *key, int *waves, int *grid) {
+    if (!key) return;
+    std::string s(key);
+    size_t a = s.find("waves="), b = s.find("grid=");
+    if (a != std::string::npos) *waves = atoi(s.c_str() + a + 6);
+    if (b != std::string::npos) *grid = atoi(s.c_str() + b + 5);
+}
+
+extern "C" int insp_schedule_batch(const insp_dag *cdag, const insp_workers *workers, const int32_t *dur,
+                                   const int32_t *est, const insp_params *params, int32_t *worker, int64_t *start,
+                                   int64_t *finish, int64_t *makespan, int32_t *ie_at_pop, int8_t *mode_at_pop,
+                                   const char *tune_key, void *stream) {
+    insp_dag *dag = const_cast<insp_dag *>(cdag);
+    if (!dag || !workers || !makespan) return set_error(INSP_E_INVAL, "null argument");
+    int rc;
+    if ((rc = check_params(params)) || (rc = check_workers(workers, dag->B))) return rc;
+    if (dag->N > 0 && (!dur || !est || !worker || !start || !finish)) return set_error(INSP_E_INVAL, "null array");
+    hipStream_t st = (hipStream_t)stream;
+    INSP_HIP(hipSetDevice(dag->device));
+    if ((rc = ensure_state(dag, st))) return rc;
+    Workspace *ws;
+    if ((rc = get_workspace(dag, 0, dag->B, workers, true, &ws))) return rc;
+    int waves = 1, grid = default_grid(dag->B);
+    parse_tune(tune_key, &waves, &grid);
+    if (grid < 1 || waves < 1) return set_error(INSP_E_INVAL, "bad tune key '%s'", tune_key);
+    if ((rc = run_attributes(dag, ws, est, params->unit_time, nullptr, nullptr, nullptr, true, st))) return rc;
+    return launch_sim(dag, ws, *params, dur, est, worker, start, finish, makespan, ie_at_pop, mode_at_pop, nullptr,
+                      nullptr, waves, grid, st);
+}
+
+extern "C" int insp_sync_status(const insp_dag *cdag, void *stream) {
+    if (!cdag) return set_error(INSP_E_INVAL, "null handle");
+    insp_dag *dag = const_cast<insp_dag *>(cdag);
+    INSP_HIP(hipStreamSynchronize((hipStream_t)stream));
+    if (!dag->dag_stat.p) return INSP_OK;
+    std::vector<int32_t> stat(2 * dag->B);
+    INSP_HIP(hipMemcpy(stat.data(), dag->dag_stat.p, sizeof(int32_t) * 2 * dag->B, hipMemcpyDeviceToHost));
+    for (int32_t b = 0; b < dag->B; b++) {
+        if (stat[2 * b] & ST_EST) return set_error(INSP_E_RANGE, "estimate outside [1, 2^20] in DAG %d", b);
+        if (stat[2 * b] & ST_DUR) return set_error(INSP_E_RANGE, "duration outside [1, 2^20] in DAG %d", b);
+        if (stat[2 * b] & ST_HANG)
+            return set_error(INSP_E_HANG, "DAG %d needed more than max_events events", b);
+    }
+    return INSP_OK;
+}

@@ -1,0 +1,243 @@
+"""Python binding of libinspirit (ctypes; argument marshalling only).
+
+Every step of the scheduling path runs in the library's HIP kernels; torch
+supplies device memory and the stream.  The functions mirror the C ABI in
+``include/inspirit.h``: ``build_dag``, ``attributes``, ``schedule``,
+``schedule_batch``, ``sync_status``.  A missing or unloadable library raises
+``ImportError`` -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libinspirit.so")
+
+OK, E_INVAL, E_CYCLE, E_RANGE, E_NOMEM, E_DEVICE, E_HANG = 0, 1, 2, 3, 4, 5, 6
+POLICY = {"inspirit": 0, "fifo": 1, "ability": 2, "efi": 3}
+MODE_ABILITY, MODE_EFI, MODE_EFI_LOC, MODE_FIFO = 0, 1, 2, 3
+ALL_DAGS = -1
+
+EXPORTS = ("insp_build_dag", "insp_free_dag", "insp_dag_info", "insp_attributes", "insp_schedule",
+           "insp_schedule_batch", "insp_sync_status", "insp_last_error")
+
+
+class InspError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+class Workers(C.Structure):
+    _fields_ = [("n_cpu", C.c_int32), ("n_gpu", C.c_int32)]
+
+
+class Params(C.Structure):
+    _fields_ = [(k, C.c_int32) for k in ("policy", "unit_time", "s_inc", "s_dec", "dec_step", "c", "k_num",
+                                         "k_den", "max_events")]
+
+
+TRACE_DTYPE = np.dtype([("t", "<i8"), ("nready", "<i4"), ("mode", "<i4"), ("cnt", "<i4"), ("peak", "<i4"),
+                        ("pushed", "<i4"), ("popped", "<i4")])
+
+
+def params(policy="inspirit", unit_time=0, s_inc=-1, s_dec=-1, dec_step=-1, c=-1, k_num=-1, k_den=-1,
+           max_events=0) -> Params:
+    pol = POLICY[policy] if isinstance(policy, str) else int(policy)
+    return Params(pol, unit_time, s_inc, s_dec, dec_step, c, k_num, k_den, max_events)
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the library (raises ImportError when it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"libinspirit.so not built at {path}; run __graft_entry__.build()")
+    lib = C.CDLL(path)
+    P, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+    lib.insp_build_dag.argtypes = [i32, P, P, P, P, P, P, C.POINTER(P)]
+    lib.insp_free_dag.argtypes = [P]
+    lib.insp_free_dag.restype = None
+    lib.insp_dag_info.argtypes = [P, i32, C.POINTER(i64), C.POINTER(i64), C.POINTER(i32)]
+    lib.insp_attributes.argtypes = [P, i32, P, P, i32, P, P, P, P, P]
+    lib.insp_schedule.argtypes = [P, i32, P, P, P, C.POINTER(Params), P, P, P, P, P, P, P, P, P]
+    lib.insp_schedule_batch.argtypes = [P, P, P, P, C.POINTER(Params), P, P, P, P, P, P, C.c_char_p, P]
+    lib.insp_sync_status.argtypes = [P, P]
+    lib.insp_last_error.restype = C.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != OK:
+        raise InspError(rc, load().insp_last_error().decode())
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if isinstance(t, np.ndarray):
+        return t.ctypes.data_as(C.c_void_p)
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+class Dag:
+    """Handle of B canonical DAGs resident on the device."""
+
+    def __init__(self, handle, n_dags):
+        self._h = handle
+        self.n_dags = n_dags
+        tn, te = C.c_int64(), C.c_int64()
+        nd = C.c_int32()
+        self.n = []
+        self.m = []
+        for b in range(n_dags):
+            _check(load().insp_dag_info(self._h, b, C.byref(tn), C.byref(te), C.byref(nd)))
+            self.n.append(tn.value)
+            self.m.append(te.value)
+        self.task_off = np.concatenate([[0], np.cumsum(self.n)]).astype(np.int64)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def free(self):
+        if self._h:
+            load().insp_free_dag(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def build_dag(task_off, edge_off, row_ptr, col, type=None, stream=None) -> Dag:
+    """task_off/edge_off: host int64 [B+1]; row_ptr/col/type: device int32."""
+    task_off = np.ascontiguousarray(task_off, dtype=np.int64)
+    edge_off = np.ascontiguousarray(edge_off, dtype=np.int64)
+    h = C.c_void_p()
+    _check(load().insp_build_dag(len(task_off) - 1, _ptr(task_off), _ptr(edge_off), _ptr(row_ptr), _ptr(col),
+                                 _ptr(type), _stream(stream), C.byref(h)))
+    return Dag(h, len(task_off) - 1)
+
+
+def _workers(w, count):
+    arr = (Workers * count)()
+    if isinstance(w, (tuple, list)) and len(w) == 2 and not isinstance(w[0], (tuple, list)) and count == 1:
+        w = [w]
+    for i in range(count):
+        arr[i].n_cpu, arr[i].n_gpu = int(w[i][0]), int(w[i][1])
+    return arr
+
+
+def attributes(dag: Dag, index, est, workers, unit_time=0, rem=None, stream=None):
+    """Returns (ia, ie, unit_time_used) as device tensors and a numpy array."""
+    import torch
+    count = dag.n_dags if index == ALL_DAGS else 1
+    lo = 0 if index == ALL_DAGS else dag.task_off[index]
+    hi = dag.task_off[-1] if index == ALL_DAGS else dag.task_off[index + 1]
+    n = int(hi - lo)
+    ia = torch.empty(max(n, 1), dtype=torch.int32, device=est.device)
+    ie = torch.empty(max(n, 1), dtype=torch.int32, device=est.device)
+    U = np.zeros(count, np.int32)
+    _check(load().insp_attributes(dag.handle, index, _ptr(est), _workers(workers, count), unit_time, _ptr(rem),
+                                  _ptr(ia), _ptr(ie), _ptr(U), _stream(stream)))
+    return ia[:n], ie[:n], U
+
+
+def _outputs(n, device, with_pop=True):
+    import torch
+    N = max(n, 1)
+    out = {"worker": torch.empty(N, dtype=torch.int32, device=device),
+           "start": torch.empty(N, dtype=torch.int64, device=device),
+           "finish": torch.empty(N, dtype=torch.int64, device=device)}
+    if with_pop:
+        out["ie_at_pop"] = torch.empty(N, dtype=torch.int32, device=device)
+        out["mode_at_pop"] = torch.empty(N, dtype=torch.int8, device=device)
+    return out
+
+
+def schedule(dag: Dag, index, workers, dur, est, prm: Params = None, trace=False, stream=None, out=None):
+    """Simulate DAG `index`; returns a dict of device tensors (makespan [1])."""
+    import torch
+    prm = prm or params()
+    n = int(dag.n[index])
+    dev = dur.device
+    o = out or _outputs(n, dev)
+    o["makespan"] = o.get("makespan", torch.empty(1, dtype=torch.int64, device=dev))
+    o["n_events"] = o.get("n_events", torch.empty(1, dtype=torch.int32, device=dev))
+    tr = None
+    if trace:
+        cap = prm.max_events if prm.max_events > 0 else n + 1
+        tr = torch.zeros(cap * TRACE_DTYPE.itemsize, dtype=torch.uint8, device=dev)
+        o["trace"] = tr
+    _check(load().insp_schedule(dag.handle, index, _workers(workers, 1), _ptr(dur), _ptr(est), C.byref(prm),
+                                _ptr(o["worker"]), _ptr(o["start"]), _ptr(o["finish"]), _ptr(o["makespan"]),
+                                _ptr(o.get("ie_at_pop")), _ptr(o.get("mode_at_pop")), _ptr(tr),
+                                _ptr(o["n_events"]), _stream(stream)))
+    return o
+
+
+def trace_records(trace_tensor, n_events):
+    raw = trace_tensor.cpu().numpy().view(TRACE_DTYPE)
+    return raw[:n_events]
+
+
+def schedule_batch(dag: Dag, workers, dur, est, prm: Params = None, tune_key=None, stream=None, out=None,
+                   with_pop=True):
+    """Simulate all DAGs in one persistent launch; returns device tensors."""
+    import torch
+    prm = prm or params()
+    dev = dur.device
+    o = out or _outputs(int(dag.task_off[-1]), dev, with_pop)
+    o["makespan"] = o.get("makespan", torch.empty(dag.n_dags, dtype=torch.int64, device=dev))
+    key = tune_key.encode() if isinstance(tune_key, str) else tune_key
+    _check(load().insp_schedule_batch(dag.handle, _workers(workers, dag.n_dags), _ptr(dur), _ptr(est),
+                                      C.byref(prm), _ptr(o["worker"]), _ptr(o["start"]), _ptr(o["finish"]),
+                                      _ptr(o["makespan"]), _ptr(o.get("ie_at_pop")), _ptr(o.get("mode_at_pop")),
+                                      key, _stream(stream)))
+    return o
+
+
+def sync_status(dag: Dag, stream=None):
+    _check(load().insp_sync_status(dag.handle, _stream(stream)))
+
+
+def to_device(w, device="cuda"):
+    """Upload one synth.Workload and build its handle; returns (dag, dur, est)."""
+    import torch
+    rp = torch.from_numpy(np.ascontiguousarray(w.row_ptr, np.int32)).to(device)
+    col = torch.from_numpy(np.ascontiguousarray(w.col, np.int32)).to(device)
+    if col.numel() == 0:
+        col = torch.zeros(1, dtype=torch.int32, device=device)
+    dag = build_dag([0, w.n], [0, w.m], rp, col)
+    dur = torch.from_numpy(np.ascontiguousarray(w.dur, np.int32)).to(device)
+    est = torch.from_numpy(np.ascontiguousarray(w.est, np.int32)).to(device)
+    return dag, dur, est
+
+
+def batch_to_device(b, device="cuda"):
+    """Upload one synth.Batch and build its handle; returns (dag, dur, est)."""
+    import torch
+    rp = torch.from_numpy(np.ascontiguousarray(b.row_ptr, np.int32)).to(device)
+    col = torch.from_numpy(np.ascontiguousarray(b.col, np.int32)).to(device)
+    dag = build_dag(b.task_off, b.edge_off, rp, col)
+    dur = torch.from_numpy(np.ascontiguousarray(b.dur, np.int32)).to(device)
+    est = torch.from_numpy(np.ascontiguousarray(b.est, np.int32)).to(device)
+    return dag, dur, est

@@ -1,0 +1,216 @@
+"""Parity of the HIP path with the CPU oracle (bit-exact: all integer work).
+
+Every test prints the case it is about to run, so a failing GPU step can be
+named from the log.
+"""
+import json
+import os
+from types import SimpleNamespace as NS
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2404_03226_amd import synth
+from invariants import check_schedule
+
+pytestmark = pytest.mark.gpu
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def insp():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2404_03226_amd import inspirit
+    inspirit.load()
+    return inspirit
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+def run_gpu(insp, w, policy="inspirit", trace=False, **kw):
+    dag, dur, est = insp.to_device(w)
+    prm = insp.params(policy=policy, **kw)
+    o = insp.schedule(dag, 0, (w.n_cpu, w.n_gpu), dur, est, prm, trace=trace)
+    insp.sync_status(dag)
+    n = w.n
+    res = {k: o[k][:n].cpu().numpy() for k in ("worker", "start", "finish", "ie_at_pop", "mode_at_pop")}
+    res["makespan"] = int(o["makespan"].item())
+    res["n_events"] = int(o["n_events"].item())
+    if trace:
+        res["trace"] = insp.trace_records(o["trace"], res["n_events"])
+    dag.free()
+    return res
+
+
+def assert_same(gpu, ref, what=""):
+    for k in ("worker", "start", "finish", "ie_at_pop", "mode_at_pop"):
+        a, b = np.asarray(gpu[k]), np.asarray(ref[k])
+        if not np.array_equal(a, b):
+            bad = np.nonzero(a != b)[0]
+            raise AssertionError(f"{what} {k} differs at {bad[:10]} gpu={a[bad[:5]]} ref={b[bad[:5]]}")
+    assert gpu["makespan"] == ref["makespan"], what
+
+
+def test_w2_fig1_analogue_on_gpu(insp):
+    g = json.load(open(os.path.join(GOLD, "w2_schedule.json")))
+    w = NS(n=5, row_ptr=np.array(g["row_ptr"], np.int32), col=np.array(g["col"], np.int32),
+           dur=np.ones((5, 2), np.int32), est=np.ones((5, 2), np.int32), n_cpu=2, n_gpu=0, m=2)
+    for pol in ("fifo", "inspirit"):
+        say("w2", pol)
+        r = run_gpu(insp, w, pol, trace=True)
+        assert r["worker"].tolist() == g[pol]["worker"]
+        assert r["start"].tolist() == g[pol]["start"]
+        assert r["makespan"] == g[pol]["makespan"]
+    assert r["trace"]["mode"].tolist() == g["inspirit"]["trace_mode"]
+    assert r["trace"]["cnt"].tolist() == g["inspirit"]["trace_cnt"]
+
+
+def test_w1_attributes_on_gpu(insp):
+    import torch
+    g = json.load(open(os.path.join(GOLD, "w1_attributes.json")))
+    w = NS(n=5, row_ptr=np.array(g["row_ptr"], np.int32), col=np.array(g["col"], np.int32), m=5,
+           dur=np.array(g["est"], np.int32), est=np.array(g["est"], np.int32))
+    say("w1")
+    dag, dur, est = insp.to_device(w)
+    ia, ie, U = insp.attributes(dag, 0, est, (0, 1))
+    assert ia.cpu().tolist() == g["ia"] and ie.cpu().tolist() == g["ie_auto"] and U[0] == g["unit_time_auto"]
+    rem = torch.tensor(g["rem_after_task1"], dtype=torch.int32, device="cuda")
+    _, ie5, U5 = insp.attributes(dag, 0, est, (0, 1), unit_time=5, rem=rem)
+    assert U5[0] == 5
+    assert [ie5.cpu().tolist()[v] for v in g["unfinished_after_task1"]] == \
+        [g["ie_after_task1_u5"][v] for v in g["unfinished_after_task1"]]
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_attributes_match_oracle(insp, seed):
+    import torch
+    w = synth.cfg3(select=[seed * 97])[0] if seed < 4 else (synth.cfg1() if seed == 4 else synth.cfg2(nb=16))
+    say("attributes", w.name)
+    dag, dur, est = insp.to_device(w)
+    for n_gpu in (0, 4):
+        for U in (0, 37, 256):
+            ia, ie, Ug = insp.attributes(dag, 0, est, (16, n_gpu), unit_time=U)
+            rp, col = oracle.canon(w.n, w.row_ptr, w.col)
+            ria, rie, rU = oracle.attributes(w.n, rp, col, w.est, n_gpu, unit_time=U)
+            assert Ug[0] == rU
+            assert np.array_equal(ia.cpu().numpy(), ria) and np.array_equal(ie.cpu().numpy(), rie)
+    # at an arbitrary remaining in-degree (half the tasks finished)
+    rp, col = oracle.canon(w.n, w.row_ptr, w.col)
+    finished = synth.Stream(seed, 99).uniform(np.arange(w.n)) < 0.3
+    src = np.repeat(np.arange(w.n), np.diff(rp))
+    rem = np.bincount(col[~finished[src]], minlength=w.n).astype(np.int32)
+    ia, ie, Ug = insp.attributes(dag, 0, est, (16, 4), unit_time=0,
+                                 rem=torch.from_numpy(rem).cuda())
+    ria, rie, rU = oracle.attributes(w.n, rp, col, w.est, 4, rem=rem)
+    assert Ug[0] == rU and np.array_equal(ie.cpu().numpy(), rie)
+    dag.free()
+
+
+@pytest.mark.parametrize("policy", ["inspirit", "fifo", "ability", "efi"])
+def test_random_small_dags(insp, policy):
+    for i in range(40):
+        n = 1 + (i * 7) % 90
+        w = synth.random_dag(11, i, n, 0.03 + (i % 6) * 0.04, n_cpu=1 + i % 4, n_gpu=i % 3, dur_hi=30,
+                             est_equal=(i % 4 != 0))
+        say("random", policy, i, n)
+        g = run_gpu(insp, w, policy)
+        r = oracle.schedule(w, policy=policy)
+        assert_same(g, r, f"random {i}")
+        check_schedule(w, g["worker"], g["start"], g["finish"], g["makespan"])
+
+
+def test_unit_tasks_many_simultaneous_completions(insp):
+    # equal durations make many completions coincide: exercises the merge
+    for i in range(12):
+        w = synth.random_dag(13, i, 150, 0.04, n_cpu=6, n_gpu=3, dur_lo=2, dur_hi=2)
+        say("unit", i)
+        assert_same(run_gpu(insp, w), oracle.schedule(w), f"unit {i}")
+
+
+@pytest.mark.parametrize("policy", ["inspirit", "fifo"])
+def test_cfg1_layered(insp, policy):
+    w = synth.cfg1()
+    say("cfg1", policy)
+    g = run_gpu(insp, w, policy, trace=True)
+    r = oracle.schedule(w, policy=policy, trace=True)
+    assert_same(g, r, "cfg1")
+    assert g["n_events"] == r["n_events"]
+    for f in ("t", "nready", "mode", "cnt", "peak", "pushed", "popped"):
+        assert np.array_equal(g["trace"][f], r["trace"][f]), f
+
+
+def test_cfg2_cholesky(insp):
+    w = synth.cfg2()
+    say("cfg2")
+    g = run_gpu(insp, w)
+    r = oracle.schedule(w, variant=oracle.HEAP)
+    assert_same(g, r, "cfg2")
+    check_schedule(w, g["worker"], g["start"], g["finish"], g["makespan"])
+
+
+def test_explicit_parameters(insp):
+    w = synth.cfg1()
+    kw = dict(unit_time=100, s_inc=2, s_dec=3, dec_step=5, c=1, k_num=3, k_den=40)
+    say("params")
+    assert_same(run_gpu(insp, w, **kw), oracle.schedule(w, **kw), "params")
+
+
+def test_batch_small_matches_oracle(insp):
+    ws = synth.cfg3(select=list(range(0, 4096, 256)))
+    b = synth.concat(ws)
+    say("batch16")
+    dag, dur, est = insp.batch_to_device(b)
+    o = insp.schedule_batch(dag, [(w.n_cpu, w.n_gpu) for w in ws], dur, est)
+    insp.sync_status(dag)
+    r = oracle.schedule_batch(b)
+    for k in ("worker", "start", "finish", "ie_at_pop", "mode_at_pop"):
+        assert np.array_equal(o[k].cpu().numpy(), r[k]), k
+    assert np.array_equal(o["makespan"].cpu().numpy(), r["makespan"])
+    # tuning must not change results
+    for key in ("waves=1,grid=1", "waves=1,grid=3", "waves=1,grid=64"):
+        o2 = insp.schedule_batch(dag, [(w.n_cpu, w.n_gpu) for w in ws], dur, est, tune_key=key)
+        assert np.array_equal(o2["start"].cpu().numpy(), r["start"]), key
+    dag.free()
+
+
+def test_error_codes_through_abi(insp):
+    import torch
+    say("errors")
+    rp = torch.tensor([0, 1, 2, 3], dtype=torch.int32, device="cuda")
+    col = torch.tensor([1, 2, 0], dtype=torch.int32, device="cuda")
+    with pytest.raises(insp.InspError) as e:
+        insp.build_dag([0, 3], [0, 3], rp, col)
+    assert e.value.code == insp.E_CYCLE
+    col = torch.tensor([1, 2, 7], dtype=torch.int32, device="cuda")
+    with pytest.raises(insp.InspError) as e:
+        insp.build_dag([0, 3], [0, 3], rp, col)
+    assert e.value.code == insp.E_INVAL
+    col = torch.tensor([1, 1, 2], dtype=torch.int32, device="cuda")
+    with pytest.raises(insp.InspError) as e:
+        insp.build_dag([0, 3], [0, 3], rp, col)
+    assert e.value.code == insp.E_INVAL
+    # duplicates merge; a hang is reported when max_events is too small
+    rp = torch.tensor([0, 2, 3, 3], dtype=torch.int32, device="cuda")
+    col = torch.tensor([2, 2, 2], dtype=torch.int32, device="cuda")
+    dag = insp.build_dag([0, 3], [0, 3], rp, col)
+    assert dag.m == [2]
+    d = torch.ones((3, 2), dtype=torch.int32, device="cuda")
+    insp.schedule(dag, 0, (1, 0), d, d, insp.params(max_events=1))
+    with pytest.raises(insp.InspError) as e:
+        insp.sync_status(dag)
+    assert e.value.code == insp.E_HANG
+    bad = d.clone()
+    bad[1, 0] = 0
+    with pytest.raises(insp.InspError) as e:
+        insp.attributes(dag, 0, bad, (1, 0))
+    assert e.value.code == insp.E_RANGE
+    with pytest.raises(insp.InspError) as e:
+        insp.schedule(dag, 0, (0, 0), d, d)
+    assert e.value.code == insp.E_RANGE
+    dag.free()
