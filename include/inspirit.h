@@ -202,6 +202,18 @@ int insp_schedule_batch(const insp_dag *dag, const insp_workers *workers, const 
  * the schedule calls enqueued on the handle since the last check. */
 int insp_sync_status(const insp_dag *dag, void *stream);
 
+/*
+ * Kernel timing (for benchmarks and tuning).  While enabled, every kernel the
+ * library launches is bracketed by HIP events recorded on the caller's
+ * stream; insp_profile_read waits for the recorded events and returns the
+ * summed elapsed time and launch count of the kernels whose name starts with
+ * `kernel` ("sim", "attr_a", "attr_b", "attr_select", "" for all).
+ * insp_profile_enable(0) stops recording and drops pending records.  The
+ * recorder is process-wide and not meant for concurrent streams.
+ */
+int insp_profile_enable(int on);
+int insp_profile_read(const char *kernel, double *total_ms, int64_t *launches);
+
 /* Thread-local description of the last non-OK status. */
 const char *insp_last_error(void);
 

@@ -201,9 +201,14 @@ int run_attributes(insp_dag *dag, Workspace *ws, const int32_t *est, int32_t uni
                    int32_t *ia_out, int32_t *ie_out, bool sim_init, hipStream_t st) {
     AttrArgs a = make_args(dag, ws, est, unit_time, rem);
     hipLaunchKernelGGL(k_attr_clear, dim3((ws->count * kRungs + 255) / 256), dim3(256), 0, st, a, ws->count);
-    if (ws->attr_blocks > 0)
+    if (ws->attr_blocks > 0) {
+        ProfScope ps(st, "attr_a");
         hipLaunchKernelGGL(k_attr_a, dim3(ws->attr_blocks), dim3(kAttrThreads), 0, st, a);
-    hipLaunchKernelGGL(k_attr_select, dim3((ws->count + 63) / 64), dim3(64), 0, st, a, ws->count);
+    }
+    {
+        ProfScope ps(st, "attr_select");
+        hipLaunchKernelGGL(k_attr_select, dim3((ws->count + 63) / 64), dim3(64), 0, st, a, ws->count);
+    }
     AttrOut o;
     o.ia_out = ia_out;
     o.ie_out = ie_out;
@@ -213,8 +218,10 @@ int run_attributes(insp_dag *dag, Workspace *ws, const int32_t *est, int32_t uni
     o.iev = dag->iev.as<int32_t>();
     o.ia = dag->ia.as<int32_t>();
     o.tau = dag->tau.as<int32_t>();
-    if (ws->attr_blocks > 0)
+    if (ws->attr_blocks > 0) {
+        ProfScope ps(st, "attr_b");
         hipLaunchKernelGGL(k_attr_b, dim3(ws->attr_blocks), dim3(kAttrThreads), 0, st, a, o);
+    }
     INSP_HIP(hipGetLastError());
     return INSP_OK;
 }

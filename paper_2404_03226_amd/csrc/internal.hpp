@@ -104,6 +104,15 @@ constexpr int kAttrThreads = 256;
 
 int ensure_state(insp_dag *dag, hipStream_t st);
 
+// Kernel timing hook: brackets a launch with events when profiling is on.
+void prof_mark(hipStream_t st, const char *kernel, bool begin);
+struct ProfScope {
+    hipStream_t st;
+    const char *name;
+    ProfScope(hipStream_t s, const char *n) : st(s), name(n) { prof_mark(st, name, true); }
+    ~ProfScope() { prof_mark(st, name, false); }
+};
+
 // Workspace for DAGs [first, first + count) with per-DAG workers (host).
 int get_workspace(insp_dag *dag, int32_t first, int32_t count, const insp_workers *workers, bool per_dag,
                   Workspace **out);

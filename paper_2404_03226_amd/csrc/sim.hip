@@ -587,6 +587,7 @@ int launch_sim(insp_dag *dag, Workspace *ws, const insp_params &p, const int32_t
     const size_t lds = (size_t)ws->max_w * (3 * 8 + 5 * 4) + 16;
     grid = std::max(1, std::min(grid, ws->count));
     hipLaunchKernelGGL(k_counter_reset, dim3(1), dim3(64), 0, st, A.counter);
+    ProfScope ps(st, "sim");
     if (ws->max_w <= 64)
         hipLaunchKernelGGL(k_sim<1>, dim3(grid), dim3(64), lds, st, A);
     else if (ws->max_w <= 128)

@@ -22,7 +22,8 @@ MODE_ABILITY, MODE_EFI, MODE_EFI_LOC, MODE_FIFO = 0, 1, 2, 3
 ALL_DAGS = -1
 
 EXPORTS = ("insp_build_dag", "insp_free_dag", "insp_dag_info", "insp_attributes", "insp_schedule",
-           "insp_schedule_batch", "insp_sync_status", "insp_last_error")
+           "insp_schedule_batch", "insp_sync_status", "insp_profile_enable", "insp_profile_read",
+           "insp_last_error")
 
 
 class InspError(RuntimeError):
@@ -70,6 +71,8 @@ def load(path: str = LIB_PATH):
     lib.insp_schedule.argtypes = [P, i32, P, P, P, C.POINTER(Params), P, P, P, P, P, P, P, P, P]
     lib.insp_schedule_batch.argtypes = [P, P, P, P, C.POINTER(Params), P, P, P, P, P, P, C.c_char_p, P]
     lib.insp_sync_status.argtypes = [P, P]
+    lib.insp_profile_enable.argtypes = [C.c_int]
+    lib.insp_profile_read.argtypes = [C.c_char_p, C.POINTER(C.c_double), C.POINTER(i64)]
     lib.insp_last_error.restype = C.c_char_p
     _lib = lib
     return lib
@@ -217,6 +220,17 @@ def schedule_batch(dag: Dag, workers, dur, est, prm: Params = None, tune_key=Non
 
 def sync_status(dag: Dag, stream=None):
     _check(load().insp_sync_status(dag.handle, _stream(stream)))
+
+
+def profile_enable(on=True):
+    _check(load().insp_profile_enable(1 if on else 0))
+
+
+def profile_read(kernel=""):
+    """(total milliseconds, launches) of the library's kernels named `kernel*`."""
+    ms, n = C.c_double(), C.c_int64()
+    _check(load().insp_profile_read(kernel.encode(), C.byref(ms), C.byref(n)))
+    return ms.value, n.value
 
 
 def to_device(w, device="cuda"):
