@@ -143,8 +143,7 @@ __global__ void k_attr_select(AttrArgs a, int32_t count) {
 struct AttrOut {
     int32_t *ia_out, *ie_out;   // user arrays (nullable), relative to base
     int sim_init;
-    unsigned long long *word;
-    int32_t *qpos, *iev, *ia, *tau;
+    TaskRec *tr;
 };
 
 __global__ __launch_bounds__(kAttrThreads) void k_attr_b(AttrArgs a, AttrOut o) {
@@ -169,11 +168,15 @@ __global__ __launch_bounds__(kAttrThreads) void k_attr_b(AttrArgs a, AttrOut o) 
     if (o.ie_out) o.ie_out[ub + lv] = ie;
     if (o.sim_init) {
         const int64_t v = d.toff + lv;
-        o.word[v] = a.word0[v];
-        o.qpos[v] = -1;
-        o.iev[v] = ie;
-        o.ia[v] = z - e0;
-        o.tau[v] = tv;
+        TaskRec rec;
+        rec.word = a.word0[v];
+        rec.iev = ie;
+        rec.qpos = -1;
+        rec.ia = z - e0;
+        rec.tau = tv;
+        rec.rs = e0;
+        rec.pad = 0;
+        o.tr[v] = rec;
     }
 }
 
@@ -213,11 +216,7 @@ int run_attributes(insp_dag *dag, Workspace *ws, const int32_t *est, int32_t uni
     o.ia_out = ia_out;
     o.ie_out = ie_out;
     o.sim_init = sim_init ? 1 : 0;
-    o.word = dag->word.as<unsigned long long>();
-    o.qpos = dag->qpos.as<int32_t>();
-    o.iev = dag->iev.as<int32_t>();
-    o.ia = dag->ia.as<int32_t>();
-    o.tau = dag->tau.as<int32_t>();
+    o.tr = dag->tr.as<TaskRec>();
     if (ws->attr_blocks > 0) {
         ProfScope ps(st, "attr_b");
         hipLaunchKernelGGL(k_attr_b, dim3(ws->attr_blocks), dim3(kAttrThreads), 0, st, a, o);
@@ -228,16 +227,15 @@ int run_attributes(insp_dag *dag, Workspace *ws, const int32_t *est, int32_t uni
 
 int ensure_state(insp_dag *dag, hipStream_t st) {
     (void)st;
-    if (dag->word.p) return INSP_OK;
+    if (dag->tr.p) return INSP_OK;
     const int64_t N = std::max<int64_t>(dag->N, 1);
     int rc;
-    if ((rc = dag->word.alloc(8 * N)) || (rc = dag->iev.alloc(4 * N)) || (rc = dag->ia.alloc(4 * N)) ||
-        (rc = dag->tau.alloc(4 * N)) || (rc = dag->qpos.alloc(4 * N)) || (rc = dag->fr_a.alloc(4 * N)) ||
-        (rc = dag->fr_b.alloc(4 * N)) || (rc = dag->cand.alloc(4 * N)) || (rc = dag->dag_u.alloc(4 * dag->B)) ||
+    if ((rc = dag->tr.alloc(sizeof(TaskRec) * N)) || (rc = dag->fbuf.alloc(12 * N)) ||
+        (rc = dag->dag_u.alloc(4 * dag->B)) ||
         (rc = dag->dag_taubar.alloc(4 * dag->B)) || (rc = dag->dag_maxtau.alloc(4 * dag->B)) ||
         (rc = dag->dag_tausum.alloc(8 * dag->B)) || (rc = dag->dag_score.alloc(4 * kRungs * dag->B)) ||
         (rc = dag->dag_stat.alloc(8 * dag->B))) {
-        dag->word.release();
+        dag->tr.release();
         return rc;
     }
     return INSP_OK;
@@ -285,6 +283,7 @@ int get_workspace(insp_dag *dag, int32_t first, int32_t count, const insp_worker
         boff += d.nblk;
         wloff += (int64_t)(wk.n_cpu + wk.n_gpu) * d.maxb;
         w->max_w = std::max(w->max_w, wk.n_cpu + wk.n_gpu);
+        w->max_nblk = std::max<int64_t>(w->max_nblk, d.nblk);
         for (int32_t c = 0; c * kAttrThreads < d.n; c++) blk.push_back(make_int2(i, c));
     }
     w->attr_blocks = (int32_t)blk.size();
@@ -292,10 +291,11 @@ int get_workspace(insp_dag *dag, int32_t first, int32_t count, const insp_worker
     for (int32_t b : dag->order)
         if (b >= first && b < first + count) w->h_order.push_back(b - first);
     int rc;
+    w->total_wl = wloff;
     if ((rc = w->desc.alloc(sizeof(DagDesc) * count)) || (rc = w->blkmap.alloc(sizeof(int2) * blk.size())) ||
-        (rc = w->order.alloc(sizeof(int32_t) * count)) || (rc = w->ent.alloc(16 * 64 * (size_t)boff)) ||
-        (rc = w->sums.alloc(16 * (size_t)boff)) || (rc = w->wblk.alloc(4 * (size_t)wloff)) ||
-        (rc = w->freeb.alloc(4 * (size_t)boff)) || (rc = w->counter.alloc(16)))
+        (rc = w->order.alloc(sizeof(int32_t) * count)) || (rc = w->slots.alloc(sizeof(Slot) * 64 * (size_t)boff)) ||
+        (rc = w->sums.alloc(16 * (size_t)boff)) || (rc = w->paux.alloc(4 * (size_t)(wloff + boff))) ||
+        (rc = w->counter.alloc(16)))
         return rc;
     INSP_HIP(hipMemcpy(w->desc.p, desc.data(), sizeof(DagDesc) * count, hipMemcpyHostToDevice));
     if (!blk.empty()) INSP_HIP(hipMemcpy(w->blkmap.p, blk.data(), sizeof(int2) * blk.size(), hipMemcpyHostToDevice));

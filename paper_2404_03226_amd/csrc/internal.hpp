@@ -39,6 +39,23 @@ struct DevBuf {
     T *as() const { return static_cast<T *>(p); }
 };
 
+// Per-task simulation record: the release atomics and the candidate reads of a
+// task touch one 32-byte record.
+struct TaskRec {
+    unsigned long long word;  // remaining in-degree << 43 | sum of unfinished predecessor ids
+    int32_t iev;              // current inspiring efficiency
+    int32_t qpos;             // queue slot, or -1 when not queued
+    int32_t ia, tau, rs;      // out-degree, tau, first edge (fixed during a run)
+    int32_t pad;
+};
+
+// Queue slot: key word, payload word and the task's first edge.
+struct Slot {
+    unsigned long long k, x;
+    int32_t rs, pad0;
+    int32_t pad1, pad2;
+};
+
 // One DAG of a launch, as the kernels see it.
 struct DagDesc {
     int64_t toff, eoff;   // first global task / edge
@@ -57,16 +74,17 @@ struct DagDesc {
 struct Workspace {
     int32_t count = 0;            // DAGs described
     int32_t max_w = 0;
+    int64_t max_nblk = 0;
     int64_t base = 0;             // first global task of the range
+    int64_t total_wl = 0;         // block-list slots before the free-block stacks in paux
     int64_t tasks = 0;
     int32_t attr_blocks = 0;
     DevBuf desc;                  // DagDesc [count]
     DevBuf blkmap;                // int2 [attr_blocks]: desc index, chunk
     DevBuf order;                 // int32 [count]: desc indices, largest first
-    DevBuf ent;                   // uint64 x2 per slot: queue entries
+    DevBuf slots;                 // Slot [64 per block]: queue entries
     DevBuf sums;                  // uint64 x2 per block: max key under each rule
-    DevBuf wblk;                  // int32: per-worker block lists
-    DevBuf freeb;                 // int32: free-block stacks
+    DevBuf paux;                  // int32: per-worker block lists, then free-block stacks
     DevBuf counter;               // int32 [4]: DAG dispenser
     std::vector<int32_t> h_order;
 };
@@ -85,9 +103,8 @@ struct insp_dag {
     insp::DevBuf type;                 // int32 [N] (may be empty)
     insp::DevBuf word0;                // uint64 [N] in-degree << 43 | sum of predecessor ids
     // per-task simulation state, shared by every shape (allocated on first use)
-    insp::DevBuf word;                 // uint64 [N] remaining in-degree << 43 | sum of unfinished predecessors
-    insp::DevBuf iev, ia, tau, qpos;   // int32 [N]
-    insp::DevBuf fr_a, fr_b, cand;     // int32 [N]
+    insp::DevBuf tr;                   // TaskRec [N]
+    insp::DevBuf fbuf;                 // int32 [3 N]: frontier runs, merged frontier, candidates
     // per-DAG attribute and status records
     insp::DevBuf dag_u, dag_taubar;    // int32 [B]
     insp::DevBuf dag_maxtau;           // int32 [B]
@@ -120,13 +137,13 @@ int get_workspace(insp_dag *dag, int32_t first, int32_t count, const insp_worker
 // Attribute pipeline over a workspace's DAGs: per-DAG max and sum of tau,
 // ladder scores (unit_time == 0), the chosen U, then IA and IE.  User arrays
 // are indexed relative to the workspace's first task.  With `sim_init` the
-// simulation state (word, qpos, iev, ia, tau) is reset as well.
+// per-task simulation records are reset as well.
 int run_attributes(insp_dag *dag, Workspace *ws, const int32_t *est, int32_t unit_time, const int32_t *rem,
                    int32_t *ia_out, int32_t *ie_out, bool sim_init, hipStream_t st);
 
 int launch_sim(insp_dag *dag, Workspace *ws, const insp_params &p, const int32_t *dur, const int32_t *est,
                int32_t *worker, int64_t *start, int64_t *finish, int64_t *makespan, int32_t *ie_at_pop,
                int8_t *mode_at_pop, insp_trace_rec *trace, int32_t *n_events, int waves, int grid,
-               hipStream_t st);
+               int sum_cap, hipStream_t st);
 
 }  // namespace insp

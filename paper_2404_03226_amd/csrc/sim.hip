@@ -46,6 +46,14 @@ constexpr uint64_t M43 = (1ull << 43) - 1;
 constexpr uint64_t BIT63 = 1ull << 63;
 enum { ST_EST = 1, ST_DUR = 2, ST_HANG = 4 };
 
+#ifdef INSP_PHASE_CLOCKS
+// Diagnostic build only: per-DAG core-clock totals of each event phase.
+__device__ unsigned long long g_phase_clk[8192 * 10];
+#define PCLK(i) do { unsigned long long c_ = clock64(); pc[i] += c_ - pc_last; pc_last = c_; } while (0)
+#else
+#define PCLK(i) do {} while (0)
+#endif
+
 __device__ __forceinline__ uint64_t key_of(uint64_t k, int ord) {
     if (ord == 0) return k | BIT63;
     if (ord == 1) return ((k >> 21) & M21) << 42 | (k >> 42) << 21 | (k & M21) | BIT63;
@@ -55,16 +63,16 @@ __device__ __forceinline__ uint64_t key_of(uint64_t k, int ord) {
 struct SimArgs {
     const DagDesc *desc;
     const int32_t *order;
-    int32_t count, max_w;
-    const int32_t *rp, *col;
+    int32_t count, max_w, sum_cap, policy;
+    const int32_t *col;
     const int32_t *dur, *est;
     int64_t base;
-    unsigned long long *word;
-    int32_t *iev;
-    const int32_t *ia, *tau;
-    int32_t *qpos, *fr_a, *fr_b, *cand;
-    unsigned long long *ent, *sums;
-    int32_t *wblk, *freeb;
+    TaskRec *tr;
+    int32_t *fbuf;
+    Slot *slots;
+    unsigned long long *sums;
+    int32_t *paux;
+    int64_t freeb_base;
     const int32_t *dag_u, *dag_taubar;
     int32_t *stat;
     int32_t *counter;
@@ -74,16 +82,32 @@ struct SimArgs {
     int8_t *mode_at_pop;
     insp_trace_rec *trace;
     int32_t *n_events;
-    int32_t policy, s_inc, s_dec, dec_step, c, k_num, k_den, max_events;
+    int32_t s_inc, s_dec, dec_step, c, k_num, k_den, max_events;
 };
 
+// LDS-resident state of the DAG a work-group is simulating.
+constexpr int kLB = 16;   // block-list slots per worker kept in LDS (more spill to global)
+constexpr int kPF = 8;    // successors of a running task prefetched into registers at its pop
+constexpr int kFC = 256;  // frontier slots in LDS (larger frontiers use global memory)
+constexpr int kCC = 128;  // candidate slots in LDS
+
 struct Lds {
-    int32_t *run, *len, *nb, *last, *seg;
-    int64_t *fin, *expend, *qest;
+    int64_t *fin, *expend, *qest;                    // [MW]
+    int32_t *run, *len, *nb, *last, *seg, *rsr, *dgr; // [MW]
+    int32_t *blist;                                  // [MW * kLB]
+    unsigned long long *sum;                         // [2 * sum_cap] block max keys
+    int32_t *fr0, *fr1;                              // [kFC]
+    int32_t *cs, *cu;                                // [kCC]
 };
+
+__host__ __device__ constexpr size_t lds_bytes(int mw, int sc) {
+    return (size_t)mw * (3 * 8 + 7 * 4 + kLB * 4) + (size_t)sc * 16 + kFC * 8 + kCC * 8 + 64;
+}
 
 template <int WPL>
 __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
+    constexpr bool kPrefetch = WPL <= 2;
+    constexpr int PW = kPrefetch ? WPL : 1;
     const int lane = lane_id();
     const DagDesc d = A.desc[di];
     const int32_t n = d.n, ncpu = d.n_cpu, W = d.n_cpu + d.n_gpu;
@@ -95,31 +119,30 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
         }
         return;
     }
-    const int64_t T0 = d.toff, ub = d.toff - A.base;
-    const int32_t *rp = A.rp + d.toff + d.id;
+    const int64_t ub = d.toff - A.base;
     const int32_t *col = A.col + d.eoff;
-    unsigned long long *word = A.word + T0;
-    int32_t *iev = A.iev + T0, *qpos = A.qpos + T0, *fr_a = A.fr_a + T0, *fr_b = A.fr_b + T0, *cand = A.cand + T0;
-    const int32_t *ia = A.ia + T0, *tau = A.tau + T0;
+    TaskRec *tr = A.tr + d.toff;
+    int32_t *fbuf = A.fbuf + 3 * d.toff;      // [0,n) runs, [n,2n) merged, [2n,3n) candidates
     const int2 *est2 = reinterpret_cast<const int2 *>(A.est) + ub;
     const int2 *dur2 = reinterpret_cast<const int2 *>(A.dur) + ub;
-    unsigned long long *ent = A.ent + 2 * 64 * d.blk_off;
+    Slot *slots = A.slots + 64 * d.blk_off;
     unsigned long long *sums = A.sums + 2 * d.blk_off;
-    int32_t *wblk = A.wblk + d.wl_off;
-    int32_t *freeb = A.freeb + d.blk_off;
+    int32_t *wblk = A.paux + d.wl_off;
+    int32_t *freeb = A.paux + A.freeb_base + d.blk_off;
     const int32_t maxb = d.maxb;
-    const int64_t U = A.dag_u[d.id];
+    const int32_t SC = A.sum_cap;
+    const int32_t U = A.dag_u[d.id];
 
     // regulator parameters (defaults: the paper names them, prints no values)
-    const int64_t s_inc = A.s_inc > 0 ? A.s_inc : max(1, (W + 3) / 4);
-    const int64_t s_dec = A.s_dec > 0 ? A.s_dec : max(1, (W + 1) / 2);
-    const int64_t dec_step = A.dec_step > 0 ? A.dec_step : s_dec;
-    const int64_t cc = A.c >= 0 ? A.c : s_dec / 2;
+    const int32_t s_inc = A.s_inc > 0 ? A.s_inc : max(1, (W + 3) / 4);
+    const int32_t s_dec = A.s_dec > 0 ? A.s_dec : max(1, (W + 1) / 2);
+    const int32_t dec_step = A.dec_step > 0 ? A.dec_step : s_dec;
+    const int32_t cc = A.c >= 0 ? A.c : s_dec / 2;
     const bool kset = A.k_num > 0 && A.k_den > 0;
-    const int64_t k_num = kset ? A.k_num : W;
-    const int64_t k_den = kset ? A.k_den : A.dag_taubar[d.id];
+    const int32_t k_num = kset ? A.k_num : W;
+    const int32_t k_den = kset ? A.k_den : A.dag_taubar[d.id];
     const int slot0 = A.policy == INSP_POLICY_FIFO ? 2 : 0;
-    const int64_t max_events = A.max_events > 0 ? A.max_events : (int64_t)n + 1;
+    const int32_t max_events = A.max_events > 0 ? A.max_events : n + 1;
 
     for (int32_t w = lane; w < W; w += kWave) {
         L.run[w] = -1;
@@ -129,6 +152,8 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
         L.fin[w] = 0;
         L.expend[w] = 0;
         L.qest[w] = 0;
+        L.rsr[w] = 0;
+        L.dgr[w] = 0;
     }
     for (int32_t i = lane; i < d.nblk; i += kWave) freeb[i] = d.nblk - 1 - i;
     int32_t nfree = d.nblk;
@@ -137,21 +162,34 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
     int32_t r = 0;
     for (int32_t i0 = 0; i0 < n; i0 += kWave) {
         int32_t i = i0 + lane;
-        bool ok = i < n && (word[i] >> 43) == 0;
+        bool ok = i < n && (tr[i].word >> 43) == 0;
         uint64_t mk = ballot(ok);
-        if (ok) fr_a[r + lanes_below(mk)] = i;
+        if (ok) {
+            int32_t pos = r + lanes_below(mk);
+            fbuf[pos] = i;
+            if (pos < kFC) L.fr0[pos] = i;
+        }
         r += __popcll(mk);
     }
-    const int32_t *fr = fr_a;
+    bool merged = false;
+    int32_t pf[PW][kPF];
+#pragma unroll
+    for (int k = 0; k < PW; k++)
+#pragma unroll
+        for (int j = 0; j < kPF; j++) pf[k][j] = 0;
     wg_fence();
     __syncthreads();
 
-    int64_t t = 0, nready = 0, events = 0;
-    int32_t done = 0, seq = 0;
-    int64_t peak = 0, prev_n = 0, prev_t = 0, cnt = 0;
+    int64_t t = 0, prev_t = 0;
+    int32_t nready = 0, events = 0, done = 0, seq = 0;
+    int32_t peak = 0, prev_n = 0, cnt = 0;
     int mode = INSP_MODE_ABILITY;
+#ifdef INSP_PHASE_CLOCKS
+    unsigned long long pc[10] = {0}, pc_last = clock64();
+#endif
 
     for (;;) {
+        PCLK(9);
         if (++events > max_events) {
             status |= ST_HANG;
             break;
@@ -171,14 +209,19 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
         for (int32_t i0 = 0; i0 < r; i0 += kWave) {
             const int32_t idx = i0 + lane;
             const bool ok = idx < r;
-            const int32_t v_l = ok ? fr[idx] : 0;
+            int32_t v_l = 0;
+            if (ok) {
+                if (r <= kFC) v_l = merged ? L.fr1[idx] : L.fr0[idx];
+                else v_l = merged ? fbuf[n + idx] : fbuf[idx];
+            }
             int2 e_l = make_int2(1, 1), d_l = make_int2(1, 1);
-            int32_t ia_l = 0, ie_l = 0;
+            int32_t ia_l = 0, ie_l = 0, rs_l = 0;
             if (ok) {
                 e_l = est2[v_l];
                 d_l = dur2[v_l];
-                ia_l = ia[v_l];
-                ie_l = wg_load(&iev[v_l]);
+                ia_l = tr[v_l].ia;
+                rs_l = tr[v_l].rs;
+                ie_l = wg_load(&tr[v_l].iev);
             }
             if (ballot(ok && (d_l.x < 1 || d_l.x > INSP_MAX_TICK || d_l.y < 1 || d_l.y > INSP_MAX_TICK)))
                 status |= ST_DUR;
@@ -211,28 +254,40 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
                     nfree--;
                     blk = wg_load(&freeb[nfree]);
                     if (lane == 0) {
-                        int32_t nbw = L.nb[ws];
-                        wblk[(int64_t)ws * maxb + nbw] = blk;
+                        const int32_t nbw = L.nb[ws];
+                        if (nbw < kLB) L.blist[ws * kLB + nbw] = blk;
+                        else wblk[(int64_t)ws * maxb + nbw] = blk;
                         L.nb[ws] = nbw + 1;
                         L.last[ws] = blk;
                     }
                 } else {
                     blk = L.last[ws];
                 }
-                const int64_t p = (int64_t)blk * 64 + pos;
+                const int32_t p = blk * 64 + pos;
                 const uint64_t kw = (uint64_t)read_lane(ia_l, j) << 42 | (uint64_t)read_lane(ie_l, j) << 21 |
                                     (M21 - (uint64_t)seq);
                 const uint64_t xw = (uint64_t)v << 42 | (uint64_t)(dk & M21) << 21 | (uint64_t)(ek & M21);
+                const int32_t rs = read_lane(rs_l, j);
                 if (lane == 0) {
-                    ent[2 * p] = kw;
-                    ent[2 * p + 1] = xw;
-                    qpos[v] = (int32_t)p;
-                    if (pos == 0) {
-                        sums[2 * blk] = key_of(kw, slot0);
-                        sums[2 * blk + 1] = key_of(kw, 1);
+                    slots[p].k = kw;
+                    slots[p].x = xw;
+                    slots[p].rs = rs;
+                    tr[v].qpos = p;
+                    const uint64_t a0 = key_of(kw, slot0), a1 = key_of(kw, 1);
+                    if (blk < SC) {
+                        if (pos == 0) {
+                            L.sum[2 * blk] = a0;
+                            L.sum[2 * blk + 1] = a1;
+                        } else {
+                            atomicMax(&L.sum[2 * blk], (unsigned long long)a0);
+                            atomicMax(&L.sum[2 * blk + 1], (unsigned long long)a1);
+                        }
+                    } else if (pos == 0) {
+                        sums[2 * blk] = a0;
+                        sums[2 * blk + 1] = a1;
                     } else {
-                        wg_fetch_max(&sums[2 * blk], (unsigned long long)key_of(kw, slot0));
-                        wg_fetch_max(&sums[2 * blk + 1], (unsigned long long)key_of(kw, 1));
+                        wg_fetch_max(&sums[2 * blk], (unsigned long long)a0);
+                        wg_fetch_max(&sums[2 * blk + 1], (unsigned long long)a1);
                     }
                     L.len[ws] = len + 1;
                     L.qest[ws] += ek;
@@ -241,28 +296,31 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
                 nready++;
             }
         }
+        PCLK(0);
         wg_fence();
         __syncthreads();
+        PCLK(1);
         // -------------------------------------------------------- regulate
-        const int64_t observed = nready;
+        const int32_t observed = nready;
         if (A.policy == INSP_POLICY_INSPIRIT) {
             if (nready > peak) peak = nready;
-            int64_t dn = nready - prev_n;
+            const int32_t dn = nready - prev_n;
             if ((dn < 0 ? -dn : dn) >= s_inc) {
-                int64_t dt = t - prev_t;
+                const int64_t dt = t - prev_t;
                 prev_n = nready;
                 prev_t = t;
                 if (nready >= peak - dec_step) {
                     cnt = 0;
                     if (dn >= s_inc) {
-                        if (dt == 0 || dn * k_den > k_num * dt) mode = INSP_MODE_ABILITY;
-                        else if (dn * k_den < k_num * dt) mode = INSP_MODE_EFI;
+                        const int64_t lhs = (int64_t)dn * k_den, rhs = (int64_t)k_num * dt;
+                        if (dt == 0 || lhs > rhs) mode = INSP_MODE_ABILITY;
+                        else if (lhs < rhs) mode = INSP_MODE_EFI;
                     }
-                } else if (nready > peak - s_dec * cnt) {
+                } else if ((int64_t)nready > (int64_t)peak - (int64_t)s_dec * cnt) {
                     mode = INSP_MODE_ABILITY;
-                } else if (nready <= peak - s_dec * (cnt + 1) + cc) {
+                } else if ((int64_t)nready <= (int64_t)peak - (int64_t)s_dec * (cnt + 1) + cc) {
                     mode = INSP_MODE_EFI_LOC;
-                    if (nready <= peak - s_dec * (cnt + 1)) cnt++;
+                    if ((int64_t)nready <= (int64_t)peak - (int64_t)s_dec * (cnt + 1)) cnt++;
                 }
             }
         }
@@ -286,53 +344,66 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
                     uint64_t bk = 0;
                     int32_t bid = -1;
                     for (int32_t i0 = 0; i0 < nb; i0 += kWave) {
-                        int32_t i = i0 + lane;
+                        const int32_t i = i0 + lane;
                         if (i < nb) {
-                            int32_t b = wg_load(&wblk[(int64_t)w * maxb + i]);
-                            uint64_t k = wg_load(&sums[2 * b + slot]);
+                            const int32_t b = i < kLB ? L.blist[w * kLB + i] : wg_load(&wblk[(int64_t)w * maxb + i]);
+                            const uint64_t k = b < SC ? L.sum[2 * b + slot] : wg_load(&sums[2 * b + slot]);
                             if (k > bk) {
                                 bk = k;
                                 bid = b;
                             }
                         }
                     }
-                    uint64_t km = wave_max_u64(bk);
-                    uint64_t wm = ballot(bk == km && bid >= 0);
+                    const uint64_t km = wave_max_u64(bk);
+                    const uint64_t wm = ballot(bk == km && bid >= 0);
                     bb = read_lane(bid, (int)__builtin_ctzll(wm));
                 }
                 const int32_t lastpos = (len - 1) & 63;
                 const int32_t cntb = bb == last ? lastpos + 1 : 64;
                 const bool ok = lane < cntb;
-                const int64_t eb = (int64_t)bb * 64;
-                uint64_t kw = 0, xw = 0;
+                const int32_t eb = bb * 64, el = last * 64;
+                const bool okl = last != bb && lane <= lastpos;
+                uint64_t kw = 0, xw = 0, kl = 0, xl = 0;
+                int32_t rw = 0, rl = 0;
                 if (ok) {
-                    kw = wg_load(&ent[2 * (eb + lane)]);
-                    xw = wg_load(&ent[2 * (eb + lane) + 1]);
+                    kw = wg_load(&slots[eb + lane].k);
+                    xw = wg_load(&slots[eb + lane].x);
+                    rw = wg_load(&slots[eb + lane].rs);
+                }
+                if (okl) {
+                    kl = wg_load(&slots[el + lane].k);
+                    xl = wg_load(&slots[el + lane].x);
+                    rl = wg_load(&slots[el + lane].rs);
                 }
                 const uint64_t key = ok ? key_of(kw, ord) : 0;
                 const uint64_t km = wave_max_u64(key);
                 const int win = (int)__builtin_ctzll(ballot(key == km && ok));
                 const uint64_t vk = read_lane64(kw, win), vx = read_lane64(xw, win);
-                const int64_t p = eb + win;
-                const int64_t q = (int64_t)last * 64 + lastpos;
+                const int32_t vr = read_lane(rw, win);
+                const int32_t p = eb + win;
+                const int32_t q = el + lastpos;
                 const int32_t v = (int32_t)(vx >> 42);
                 const int32_t dk = (int32_t)((vx >> 21) & M21), ek = (int32_t)(vx & M21);
                 uint64_t mk = 0, mx = 0;
+                int32_t mr = 0;
                 if (p != q) {
                     if (last == bb) {
                         mk = read_lane64(kw, lastpos);
                         mx = read_lane64(xw, lastpos);
+                        mr = read_lane(rw, lastpos);
                     } else {
-                        mk = wg_load(&ent[2 * q]);
-                        mx = wg_load(&ent[2 * q + 1]);
+                        mk = read_lane64(kl, lastpos);
+                        mx = read_lane64(xl, lastpos);
+                        mr = read_lane(rl, lastpos);
                     }
                     if (lane == 0) {
-                        ent[2 * p] = mk;
-                        ent[2 * p + 1] = mx;
-                        qpos[(int32_t)(mx >> 42)] = (int32_t)p;
+                        slots[p].k = mk;
+                        slots[p].x = mx;
+                        slots[p].rs = mr;
+                        tr[(int32_t)(mx >> 42)].qpos = p;
                     }
                 }
-                if (lane == 0) qpos[v] = -1;
+                if (lane == 0) tr[v].qpos = -1;
                 len--;
                 const bool freed = (len & 63) == 0;
                 int32_t newlast = last;
@@ -340,31 +411,42 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
                     if (lane == 0) freeb[nfree] = last;
                     nfree++;
                     nb--;
-                    newlast = nb > 0 ? wg_load(&wblk[(int64_t)w * maxb + nb - 1]) : -1;
+                    newlast = nb <= 0 ? -1 : nb - 1 < kLB ? L.blist[w * kLB + nb - 1]
+                                                         : wg_load(&wblk[(int64_t)w * maxb + nb - 1]);
                 }
                 if (!(bb == last && freed)) {
                     // block bb after the removal: the winner's slot holds the
                     // moved entry; if bb is the last block its final slot left
-                    uint64_t nk = (p != q && lane == win) ? mk : kw;
-                    bool valid = ok && !(bb == last && lane == lastpos);
-                    uint64_t s0 = wave_max_u64(valid ? key_of(nk, slot0) : 0);
-                    uint64_t s1 = wave_max_u64(valid ? key_of(nk, 1) : 0);
+                    const uint64_t nk = (p != q && lane == win) ? mk : kw;
+                    const bool valid = ok && !(bb == last && lane == lastpos);
+                    const uint64_t s0 = wave_max_u64(valid ? key_of(nk, slot0) : 0);
+                    const uint64_t s1 = wave_max_u64(valid ? key_of(nk, 1) : 0);
                     if (lane == 0) {
-                        sums[2 * bb] = s0;
-                        sums[2 * bb + 1] = s1;
+                        if (bb < SC) {
+                            L.sum[2 * bb] = s0;
+                            L.sum[2 * bb + 1] = s1;
+                        } else {
+                            sums[2 * bb] = s0;
+                            sums[2 * bb + 1] = s1;
+                        }
                     }
                 }
                 if (last != bb && !freed) {
                     // the last block lost its final entry to bb
-                    const int32_t cl = ((len - 1) & 63) + 1;
-                    uint64_t kl = lane < cl ? wg_load(&ent[2 * ((int64_t)last * 64 + lane)]) : 0;
-                    uint64_t s0 = wave_max_u64(lane < cl ? key_of(kl, slot0) : 0);
-                    uint64_t s1 = wave_max_u64(lane < cl ? key_of(kl, 1) : 0);
+                    const bool valid = okl && lane != lastpos;
+                    const uint64_t s0 = wave_max_u64(valid ? key_of(kl, slot0) : 0);
+                    const uint64_t s1 = wave_max_u64(valid ? key_of(kl, 1) : 0);
                     if (lane == 0) {
-                        sums[2 * last] = s0;
-                        sums[2 * last + 1] = s1;
+                        if (last < SC) {
+                            L.sum[2 * last] = s0;
+                            L.sum[2 * last + 1] = s1;
+                        } else {
+                            sums[2 * last] = s0;
+                            sums[2 * last + 1] = s1;
+                        }
                     }
                 }
+                const int32_t deg = (int32_t)(vk >> 42);
                 if (lane == 0) {
                     L.len[w] = len;
                     L.nb[w] = nb;
@@ -373,6 +455,8 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
                     L.fin[w] = t + dk;
                     L.expend[w] = t + ek;
                     L.qest[w] -= ek;
+                    L.rsr[w] = vr;
+                    L.dgr[w] = deg;
                     const int64_t uv = ub + v;
                     A.worker[uv] = w;
                     A.start[uv] = t;
@@ -380,17 +464,30 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
                     if (A.ie_at_pop) A.ie_at_pop[uv] = (int32_t)((vk >> 21) & M21);
                     if (A.mode_at_pop) A.mode_at_pop[uv] = (int8_t)pmode;
                 }
+                if constexpr (kPrefetch) {
+                    // the running task's first successors, read now and used
+                    // when it completes
+                    if (lane == (w & 63)) {
+#pragma unroll
+                        for (int k = 0; k < PW; k++)
+                            if (k == (w >> 6)) {
+#pragma unroll
+                                for (int j = 0; j < kPF; j++) pf[k][j] = j < deg ? col[vr + j] : 0;
+                            }
+                    }
+                }
                 nready--;
                 popped++;
             }
         }
+        PCLK(2);
         if (A.trace && lane == 0 && events <= max_events) {
             insp_trace_rec rec;
             rec.t = t;
-            rec.nready = (int32_t)observed;
+            rec.nready = observed;
             rec.mode = pmode;
-            rec.cnt = (int32_t)cnt;
-            rec.peak = (int32_t)peak;
+            rec.cnt = cnt;
+            rec.peak = peak;
             rec.pushed = r;
             rec.popped = popped;
             A.trace[events - 1] = rec;
@@ -406,9 +503,10 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
             break;
         }
         t = (int64_t)tm;
+        PCLK(3);
         // --------------------------------------------------------- release
         r = 0;
-        int32_t nc = 0, nseg = 0;
+        int32_t nc = 0, nseg = 0, ndone = 0;
         for (int32_t w0 = 0; w0 < W; w0 += kWave) {
             const int32_t wl = w0 + lane;
             const bool fin_now = wl < W && L.run[wl] >= 0 && L.fin[wl] == t;
@@ -418,25 +516,52 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
             while (mask) {
                 const int l = (int)__builtin_ctzll(mask);
                 mask &= mask - 1;
+                const int32_t w = w0 + l;
                 const int32_t c = read_lane(c_l, l);
                 done++;
-                const int32_t a = rp[c], z = rp[c + 1];
+                ndone++;
+                const int32_t deg = L.dgr[w], rs = L.rsr[w];
                 const int32_t r0 = r;
                 const unsigned long long dec = 0ull - ((1ull << 43) + (unsigned long long)c);
-                for (int32_t e0 = a; e0 < z; e0 += kWave) {
+                for (int32_t e0 = 0; e0 < deg; e0 += kWave) {
                     const int32_t e = e0 + lane;
-                    const bool ok = e < z;
+                    const bool ok = e < deg;
                     int32_t s = 0;
-                    uint64_t old = 0;
-                    if (ok) {
-                        s = col[e];
-                        old = wg_fetch_add(&word[s], dec);
+                    if constexpr (kPrefetch) {
+                        if (e0 == 0) {
+#pragma unroll
+                            for (int k = 0; k < PW; k++)
+                                if (k == (w >> 6)) {
+#pragma unroll
+                                    for (int j = 0; j < kPF; j++) {
+                                        const int32_t y = read_lane(pf[k][j], w & 63);
+                                        if (lane == j) s = y;
+                                    }
+                                }
+                        }
+                        if (ok && e >= kPF) s = col[rs + e];
+                    } else {
+                        if (ok) s = col[rs + e];
                     }
-                    const int64_t nr = (int64_t)(old >> 43) - 1;
+                    uint64_t old = 0;
+                    if (ok) old = wg_fetch_add(&tr[s].word, dec);
+                    const int32_t nr = (int32_t)(old >> 43) - 1;
                     const bool rdy = ok && nr == 0, cd = ok && nr == 1;
                     const uint64_t m1 = ballot(rdy), m2 = ballot(cd);
-                    if (rdy) fr_a[r + lanes_below(m1)] = s;
-                    if (cd) cand[nc + lanes_below(m2)] = s;
+                    if (rdy) {
+                        const int32_t pos = r + lanes_below(m1);
+                        fbuf[pos] = s;
+                        if (pos < kFC) L.fr0[pos] = s;
+                    }
+                    if (cd) {
+                        const int32_t pos = nc + lanes_below(m2);
+                        if (pos < kCC) {
+                            L.cs[pos] = s;
+                            L.cu[pos] = (int32_t)((old + dec) & M43);
+                        } else {
+                            fbuf[2 * n + pos] = s;
+                        }
+                    }
                     r += __popcll(m1);
                     nc += __popcll(m2);
                 }
@@ -446,35 +571,53 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
                 }
             }
         }
+        PCLK(4);
         wg_fence();
         __syncthreads();
-        // successors left with one unfinished predecessor raise its IE
+        PCLK(5);
+        // successors left with one unfinished predecessor raise its IE; with a
+        // single completion the atomic's result already names that predecessor
+        const bool single = ndone == 1;
         for (int32_t i0 = 0; i0 < nc; i0 += kWave) {
             const int32_t i = i0 + lane;
             if (i < nc) {
-                const int32_t s = cand[i];
-                const uint64_t wd = wg_load(&word[s]);
-                if ((wd >> 43) == 1) {
-                    const int32_t u = (int32_t)(wd & M43);
-                    if ((int64_t)tau[u] + tau[s] <= U) {
-                        wg_fetch_add(&iev[u], 1);
-                        const int32_t pu = wg_load(&qpos[u]);
+                const int32_t s = i < kCC ? L.cs[i] : wg_load(&fbuf[2 * n + i]);
+                int32_t u = -1;
+                if (single && i < kCC) {
+                    u = L.cu[i];
+                } else {
+                    const uint64_t wd = wg_load(&tr[s].word);
+                    if ((wd >> 43) == 1) u = (int32_t)(wd & M43);
+                }
+                if (u >= 0) {
+                    const int32_t tu = tr[u].tau, ts = tr[s].tau;
+                    const int32_t pu = wg_load(&tr[u].qpos);
+                    if ((int64_t)tu + ts <= (int64_t)U) {
+                        wg_fetch_add(&tr[u].iev, 1);
                         if (pu >= 0) {
-                            const uint64_t nk = wg_fetch_add(&ent[2 * (int64_t)pu], 1ull << 21) + (1ull << 21);
-                            wg_fetch_max(&sums[2 * (int64_t)(pu >> 6)], (unsigned long long)key_of(nk, slot0));
-                            wg_fetch_max(&sums[2 * (int64_t)(pu >> 6) + 1], (unsigned long long)key_of(nk, 1));
+                            const uint64_t nk = wg_fetch_add(&slots[pu].k, 1ull << 21) + (1ull << 21);
+                            const int32_t bk = pu >> 6;
+                            if (bk < SC) {
+                                atomicMax(&L.sum[2 * bk], (unsigned long long)key_of(nk, slot0));
+                                atomicMax(&L.sum[2 * bk + 1], (unsigned long long)key_of(nk, 1));
+                            } else {
+                                wg_fetch_max(&sums[2 * bk], (unsigned long long)key_of(nk, slot0));
+                                wg_fetch_max(&sums[2 * bk + 1], (unsigned long long)key_of(nk, 1));
+                            }
                         }
                     }
                 }
             }
         }
+        PCLK(6);
         // several completions: merge their ascending runs by rank
-        fr = fr_a;
+        merged = false;
         if (nseg > 1) {
+            const bool in_lds = r <= kFC;
             for (int32_t i0 = 0; i0 < r; i0 += kWave) {
                 const int32_t i = i0 + lane;
                 if (i < r) {
-                    const int32_t x = fr_a[i];
+                    const int32_t x = in_lds ? L.fr0[i] : fbuf[i];
                     int32_t rank = 0, lo = 0;
                     for (int32_t g = 0; g < nseg; g++) {
                         const int32_t hi = L.seg[g];
@@ -483,27 +626,35 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
                         } else {
                             int32_t a = lo, b = hi;  // count of run g below x
                             while (a < b) {
-                                int32_t mid = (a + b) >> 1;
-                                if (fr_a[mid] < x) a = mid + 1;
+                                const int32_t mid = (a + b) >> 1;
+                                const int32_t y = in_lds ? L.fr0[mid] : fbuf[mid];
+                                if (y < x) a = mid + 1;
                                 else b = mid;
                             }
                             rank += a - lo;
                         }
                         lo = hi;
                     }
-                    fr_b[rank] = x;
+                    if (in_lds) L.fr1[rank] = x;
+                    else fbuf[n + rank] = x;
                 }
             }
-            fr = fr_b;
+            merged = true;
         }
+        PCLK(7);
         wg_fence();
         __syncthreads();
+        PCLK(8);
     }
+#ifdef INSP_PHASE_CLOCKS
+    if (lane == 0 && d.id < 8192)
+        for (int i = 0; i < 10; i++) g_phase_clk[d.id * 10 + i] = pc[i];
+#endif
     if (lane == 0) {
         A.makespan[di] = (status & ST_HANG) ? -1 : t;
-        if (A.n_events) A.n_events[di] = (int32_t)min(events, (int64_t)INT32_MAX);
+        if (A.n_events) A.n_events[di] = events;
         if (status) atomicOr(&A.stat[2 * d.id], status);
-        A.stat[2 * d.id + 1] = (int32_t)min(events, (int64_t)INT32_MAX);
+        A.stat[2 * d.id + 1] = events;
     }
 }
 
@@ -515,12 +666,20 @@ __global__ __launch_bounds__(64) void k_sim(SimArgs A) {
     L.fin = lds64;
     L.expend = lds64 + MW;
     L.qest = lds64 + 2 * MW;
-    int32_t *l32 = reinterpret_cast<int32_t *>(lds64 + 3 * MW);
+    L.sum = reinterpret_cast<unsigned long long *>(lds64 + 3 * MW);
+    int32_t *l32 = reinterpret_cast<int32_t *>(lds64 + 3 * MW + 2 * A.sum_cap);
     L.run = l32;
     L.len = l32 + MW;
     L.nb = l32 + 2 * MW;
     L.last = l32 + 3 * MW;
     L.seg = l32 + 4 * MW;
+    L.rsr = l32 + 5 * MW;
+    L.dgr = l32 + 6 * MW;
+    L.blist = l32 + 7 * MW;
+    L.fr0 = L.blist + MW * kLB;
+    L.fr1 = L.fr0 + kFC;
+    L.cs = L.fr1 + kFC;
+    L.cu = L.cs + kCC;
     const int lane = lane_id();
     for (;;) {
         int32_t got = 0;
@@ -539,7 +698,7 @@ __global__ void k_counter_reset(int32_t *c) {
 int launch_sim(insp_dag *dag, Workspace *ws, const insp_params &p, const int32_t *dur, const int32_t *est,
                int32_t *worker, int64_t *start, int64_t *finish, int64_t *makespan, int32_t *ie_at_pop,
                int8_t *mode_at_pop, insp_trace_rec *trace, int32_t *n_events, int waves, int grid,
-               hipStream_t st) {
+               int sum_cap, hipStream_t st) {
     (void)waves;
     SimArgs A;
     memset(&A, 0, sizeof A);
@@ -547,23 +706,16 @@ int launch_sim(insp_dag *dag, Workspace *ws, const insp_params &p, const int32_t
     A.order = ws->order.as<int32_t>();
     A.count = ws->count;
     A.max_w = ws->max_w;
-    A.rp = dag->rp.as<int32_t>();
     A.col = dag->col.as<int32_t>();
     A.dur = dur;
     A.est = est;
     A.base = ws->base;
-    A.word = dag->word.as<unsigned long long>();
-    A.iev = dag->iev.as<int32_t>();
-    A.ia = dag->ia.as<int32_t>();
-    A.tau = dag->tau.as<int32_t>();
-    A.qpos = dag->qpos.as<int32_t>();
-    A.fr_a = dag->fr_a.as<int32_t>();
-    A.fr_b = dag->fr_b.as<int32_t>();
-    A.cand = dag->cand.as<int32_t>();
-    A.ent = ws->ent.as<unsigned long long>();
+    A.tr = dag->tr.as<TaskRec>();
+    A.fbuf = dag->fbuf.as<int32_t>();
+    A.slots = ws->slots.as<Slot>();
     A.sums = ws->sums.as<unsigned long long>();
-    A.wblk = ws->wblk.as<int32_t>();
-    A.freeb = ws->freeb.as<int32_t>();
+    A.paux = ws->paux.as<int32_t>();
+    A.freeb_base = ws->total_wl;
     A.dag_u = dag->dag_u.as<int32_t>();
     A.dag_taubar = dag->dag_taubar.as<int32_t>();
     A.stat = dag->dag_stat.as<int32_t>();
@@ -584,7 +736,10 @@ int launch_sim(insp_dag *dag, Workspace *ws, const insp_params &p, const int32_t
     A.k_num = p.k_num;
     A.k_den = p.k_den;
     A.max_events = p.max_events;
-    const size_t lds = (size_t)ws->max_w * (3 * 8 + 5 * 4) + 16;
+    // block maxima in LDS: all of a single DAG's blocks up to 64 KB, or the
+    // low block ids of each DAG of a batch
+    A.sum_cap = (int32_t)std::min<int64_t>(ws->max_nblk, ws->count == 1 ? 4096 : sum_cap);
+    const size_t lds = lds_bytes(ws->max_w, A.sum_cap);
     grid = std::max(1, std::min(grid, ws->count));
     hipLaunchKernelGGL(k_counter_reset, dim3(1), dim3(64), 0, st, A.counter);
     ProfScope ps(st, "sim");
@@ -646,15 +801,16 @@ extern "C" int insp_schedule(const insp_dag *cdag, int32_t index, const insp_wor
     if ((rc = get_workspace(dag, index, 1, workers, true, &ws))) return rc;
     if ((rc = run_attributes(dag, ws, est, params->unit_time, nullptr, nullptr, nullptr, true, st))) return rc;
     return launch_sim(dag, ws, *params, dur, est, worker, start, finish, makespan, ie_at_pop, mode_at_pop, trace,
-                      n_events, 1, 1, st);
+                      n_events, 1, 1, 4096, st);
 }
 
-static void parse_tune(const char *key, int *waves, int *grid) {
+static void parse_tune(const char *key, int *waves, int *grid, int *sum_cap) {
     if (!key) return;
     std::string s(key);
-    size_t a = s.find("waves="), b = s.find("grid=");
+    size_t a = s.find("waves="), b = s.find("grid="), c = s.find("lds_blocks=");
     if (a != std::string::npos) *waves = atoi(s.c_str() + a + 6);
     if (b != std::string::npos) *grid = atoi(s.c_str() + b + 5);
+    if (c != std::string::npos) *sum_cap = atoi(s.c_str() + c + 11);
 }
 
 extern "C" int insp_schedule_batch(const insp_dag *cdag, const insp_workers *workers, const int32_t *dur,
@@ -671,13 +827,21 @@ extern "C" int insp_schedule_batch(const insp_dag *cdag, const insp_workers *wor
     if ((rc = ensure_state(dag, st))) return rc;
     Workspace *ws;
     if ((rc = get_workspace(dag, 0, dag->B, workers, true, &ws))) return rc;
-    int waves = 1, grid = default_grid(dag->B);
-    parse_tune(tune_key, &waves, &grid);
-    if (grid < 1 || waves < 1) return set_error(INSP_E_INVAL, "bad tune key '%s'", tune_key);
+    int waves = 1, grid = default_grid(dag->B), sum_cap = 512;
+    parse_tune(tune_key, &waves, &grid, &sum_cap);
+    if (grid < 1 || waves < 1 || sum_cap < 0 || sum_cap > 8192)
+        return set_error(INSP_E_INVAL, "bad tune key '%s'", tune_key);
     if ((rc = run_attributes(dag, ws, est, params->unit_time, nullptr, nullptr, nullptr, true, st))) return rc;
     return launch_sim(dag, ws, *params, dur, est, worker, start, finish, makespan, ie_at_pop, mode_at_pop, nullptr,
-                      nullptr, waves, grid, st);
+                      nullptr, waves, grid, sum_cap, st);
 }
+
+#ifdef INSP_PHASE_CLOCKS
+extern "C" int insp_debug_phase_clocks(unsigned long long *host, int count) {
+    INSP_HIP(hipMemcpyFromSymbol(host, HIP_SYMBOL(g_phase_clk), sizeof(unsigned long long) * 10 * count));
+    return INSP_OK;
+}
+#endif
 
 extern "C" int insp_sync_status(const insp_dag *cdag, void *stream) {
     if (!cdag) return set_error(INSP_E_INVAL, "null handle");
