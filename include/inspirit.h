@@ -214,6 +214,41 @@ int insp_sync_status(const insp_dag *dag, void *stream);
 int insp_profile_enable(int on);
 int insp_profile_read(const char *kernel, double *total_ms, int64_t *launches);
 
+/*
+ * Learned cost model (spec extension of the paper's per-type average
+ * execution times, Section 4.3): a 32 -> 256 -> 256 -> 2 ReLU network that
+ * predicts ln(duration) on the CPU and GPU worker kinds from 32 task
+ * features.  Weights, activations and activation gradients are bfloat16,
+ * accumulation, biases, outputs, gradients and the Adam state are fp32.
+ * Parameters are packed as W1 [32][256], b1 [256], W2 [256][256], b2 [256],
+ * W3 [256][2], b3 [2] (row-major, INSP_MLP_PARAMS floats).
+ *   insp_mlp_create     copy host fp32 initial parameters to a new model
+ *   insp_mlp_grads      loss (mean squared error over batch x 2 outputs) and
+ *                       its gradients for one batch, without updating; x is
+ *                       device fp32 [batch][32], t device fp32 [batch][2]
+ *                       (targets in ln ticks); grads device fp32 [PARAMS],
+ *                       y device fp32 [batch][2], loss device fp32 [1]
+ *                       (each nullable)
+ *   insp_mlp_train_step the same gradients followed by one Adam step
+ *                       (beta1 0.9, beta2 0.999, eps 1e-8, learning rate lr)
+ *   insp_mlp_predict    y = network(x) for n rows and/or integer estimates
+ *                       est = clamp(rint(exp(y)), 1, 2^20), int32 [n][2]
+ *   insp_mlp_state      copy parameters, Adam moments and step count to the
+ *                       host (to_host = 1) or from it (to_host = 0), for
+ *                       checkpoint and resume; any pointer may be NULL
+ * batch must be a positive multiple of 32.  Work runs on `stream`.
+ */
+#define INSP_MLP_PARAMS 74754
+typedef struct insp_mlp insp_mlp;
+int insp_mlp_create(const float *params, insp_mlp **out);
+void insp_mlp_free(insp_mlp *m);
+int insp_mlp_grads(insp_mlp *m, const float *x, const float *t, int32_t batch, float *grads, float *y, float *loss,
+                   void *stream);
+int insp_mlp_train_step(insp_mlp *m, const float *x, const float *t, int32_t batch, float lr, float *loss,
+                        void *stream);
+int insp_mlp_predict(insp_mlp *m, const float *x, int64_t n, float *y, int32_t *est, void *stream);
+int insp_mlp_state(insp_mlp *m, float *params, float *adam_m, float *adam_v, int64_t *step, int to_host);
+
 /* Thread-local description of the last non-OK status. */
 const char *insp_last_error(void);
 

@@ -1,0 +1,436 @@
+// Learned cost model: a 32 -> 256 -> 256 -> 2 ReLU network predicting the
+// natural log of a task's duration on each worker kind, trained with MSE and
+// Adam.  The paper drives inspiring efficiency with per-kind execution-time
+// estimates gathered by a cost model (Sections 4.3 and 5); this model replaces
+// the per-type average table when task features are available.
+//
+// Precision: weights, activations and activation gradients are stored as
+// bfloat16 (round to nearest even); products accumulate in fp32 on the MFMA
+// units (v_mfma_f32_16x16x32_bf16); biases, outputs, weight gradients, Adam
+// moments and master weights are fp32.
+//
+// Packed parameter order: W1 [32,256], b1 [256], W2 [256,256], b2 [256],
+// W3 [256,2], b3 [2].
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace insp {
+
+constexpr int kIn = 32, kHid = 256, kOut = 2;
+constexpr int64_t kOffW1 = 0, kOffB1 = kOffW1 + kIn * kHid, kOffW2 = kOffB1 + kHid, kOffB2 = kOffW2 + kHid * kHid,
+                  kOffW3 = kOffB2 + kHid, kOffB3 = kOffW3 + kHid * kOut, kParams = kOffB3 + kOut;
+static_assert(kParams == 74754, "parameter count");
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint16_t f2bf(float f) {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// ------------------------------------------------------------------ GEMM
+// C[m,n] = sum_k A(m,k) B(k,n), A(m,k) = A[m*sam + k*sak], B(k,n) =
+// B[k*sbk + n*sbn] (bf16), accumulated in fp32, then: + bias[n], ReLU,
+// * (mask(m,n) > 0), stored to C32 (fp32) and/or C16 (bf16); colsum[n] +=
+// the final fp32 values.  64 x 64 tile per 256-thread block; each wave owns a
+// 32 x 32 quarter as 2 x 2 MFMA 16x16x32 tiles; K advances 32 at a time
+// through LDS (A row-major, B transposed so both fragments are 16-byte reads).
+struct GemmArgs {
+    int M, N, K;
+    const uint16_t *A;
+    int64_t sam, sak;
+    const uint16_t *B;
+    int64_t sbk, sbn;
+    const float *bias;
+    int relu;
+    const uint16_t *mask;
+    int64_t smm, smn;
+    float *C32;
+    int64_t ldc;
+    uint16_t *C16;
+    int64_t ldc16;
+    float *colsum;
+};
+
+constexpr int kTM = 64, kTN = 64, kTK = 32, kLdsRow = kTK + 8;
+
+__global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
+    __shared__ __attribute__((aligned(16))) uint16_t As[kTM * kLdsRow];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[kTN * kLdsRow];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int m0 = blockIdx.y * kTM, n0 = blockIdx.x * kTN;
+    const int wm = (wv >> 1) * 32, wn = (wv & 1) * 32;
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; a++)
+#pragma unroll
+        for (int b = 0; b < 2; b++) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < g.K; k0 += kTK) {
+        // stage A [64 x 32] and B^T [64 x 32]: 8 elements per thread each
+#pragma unroll
+        for (int i = 0; i < 8; i++) {
+            const int e = tid * 8 + i, r = e / kTK, kk = e % kTK;
+            const int m = m0 + r, n = n0 + r, k = k0 + kk;
+            As[r * kLdsRow + kk] = (m < g.M && k < g.K) ? g.A[(int64_t)m * g.sam + (int64_t)k * g.sak] : 0;
+            Bs[r * kLdsRow + kk] = (n < g.N && k < g.K) ? g.B[(int64_t)k * g.sbk + (int64_t)n * g.sbn] : 0;
+        }
+        __syncthreads();
+        const int fr = lane & 15, fk = (lane >> 4) * 8;
+        bf16x8 af[2], bfr[2];
+#pragma unroll
+        for (int a = 0; a < 2; a++)
+            af[a] = *reinterpret_cast<const bf16x8 *>(&As[(wm + a * 16 + fr) * kLdsRow + fk]);
+#pragma unroll
+        for (int b = 0; b < 2; b++)
+            bfr[b] = *reinterpret_cast<const bf16x8 *>(&Bs[(wn + b * 16 + fr) * kLdsRow + fk]);
+#pragma unroll
+        for (int a = 0; a < 2; a++)
+#pragma unroll
+            for (int b = 0; b < 2; b++)
+                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[a], bfr[b], acc[a][b], 0, 0, 0);
+        __syncthreads();
+    }
+    // accumulator layout: value i of a lane is row 4*(lane/16)+i, column lane%16
+#pragma unroll
+    for (int b = 0; b < 2; b++) {
+        const int n = n0 + wn + b * 16 + (lane & 15);
+        float csum = 0.f;
+#pragma unroll
+        for (int a = 0; a < 2; a++)
+#pragma unroll
+            for (int i = 0; i < 4; i++) {
+                const int m = m0 + wm + a * 16 + (lane >> 4) * 4 + i;
+                if (m < g.M && n < g.N) {
+                    float v = acc[a][b][i];
+                    if (g.bias) v += g.bias[n];
+                    if (g.relu) v = fmaxf(v, 0.f);
+                    if (g.mask && !(bf2f(g.mask[(int64_t)m * g.smm + (int64_t)n * g.smn]) > 0.f)) v = 0.f;
+                    if (g.C32) g.C32[(int64_t)m * g.ldc + n] = v;
+                    if (g.C16) g.C16[(int64_t)m * g.ldc16 + n] = f2bf(v);
+                    csum += v;
+                }
+            }
+        if (g.colsum) {
+            csum += __shfl_xor(csum, 16, 64);
+            csum += __shfl_xor(csum, 32, 64);
+            if (lane < 16 && n < g.N) atomicAdd(&g.colsum[n], csum);
+        }
+    }
+}
+
+// -------------------------------------------------------------- helpers
+__global__ void k_to_bf16(const float *x, uint16_t *y, int64_t n) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) y[i] = f2bf(x[i]);
+}
+
+__global__ void k_fill(float *x, int64_t n, float v) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) x[i] = v;
+}
+
+// Output layer and loss gradient, one wave per row: Y = H2 W3 + b3; with a
+// target, dY = 2 (Y - T) / (2B), db3 += dY, loss += (Y - T)^2 / (2B), and
+// dH2 = (dY W3^T) * (H2 > 0) stored as bf16 with db2 += its fp32 value.
+__global__ __launch_bounds__(256) void k_out(const uint16_t *H2, const uint16_t *W3, const float *b3, int64_t rows,
+                                             float *Y, const float *T, float *grads, float *loss, uint16_t *dH2,
+                                             int32_t *est) {
+    __shared__ float db2s[kHid];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    if (T)
+        for (int i = tid; i < kHid; i += 256) db2s[i] = 0.f;
+    __syncthreads();
+    const int64_t r = blockIdx.x * 4LL + wv;
+    float w30[4], w31[4], h[4];
+    float s0 = 0.f, s1 = 0.f;
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+        const int i = lane * 4 + j;
+        w30[j] = bf2f(W3[i * 2]);
+        w31[j] = bf2f(W3[i * 2 + 1]);
+        h[j] = r < rows ? bf2f(H2[r * kHid + i]) : 0.f;
+        s0 += h[j] * w30[j];
+        s1 += h[j] * w31[j];
+    }
+    for (int off = 32; off >= 1; off >>= 1) {
+        s0 += __shfl_xor(s0, off, 64);
+        s1 += __shfl_xor(s1, off, 64);
+    }
+    const float y0 = s0 + b3[0], y1 = s1 + b3[1];
+    if (r < rows && lane == 0) {
+        if (Y) {
+            Y[2 * r] = y0;
+            Y[2 * r + 1] = y1;
+        }
+        if (est) {
+            // integer estimate: clamp(rint(exp(y)), 1, 2^20)
+            est[2 * r] = (int32_t)fminf(fmaxf(rintf(expf(y0)), 1.f), (float)(1 << 20));
+            est[2 * r + 1] = (int32_t)fminf(fmaxf(rintf(expf(y1)), 1.f), (float)(1 << 20));
+        }
+    }
+    if (T && r < rows) {
+        const float scale = 1.0f / (float)rows;  // 2 / (2 rows)
+        const float d0 = (y0 - T[2 * r]) * scale, d1 = (y1 - T[2 * r + 1]) * scale;
+        if (lane == 0) {
+            atomicAdd(&grads[kOffB3], d0);
+            atomicAdd(&grads[kOffB3 + 1], d1);
+            atomicAdd(loss, ((y0 - T[2 * r]) * (y0 - T[2 * r]) + (y1 - T[2 * r + 1]) * (y1 - T[2 * r + 1])) * 0.5f * scale);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const int i = lane * 4 + j;
+            float g = d0 * w30[j] + d1 * w31[j];
+            if (!(h[j] > 0.f)) g = 0.f;
+            dH2[r * kHid + i] = f2bf(g);
+            atomicAdd(&db2s[i], g);
+        }
+    }
+    if (T) {
+        __syncthreads();
+        for (int i = tid; i < kHid; i += 256) atomicAdd(&grads[kOffB2 + i], db2s[i]);
+    }
+}
+
+// dW3[i, c] = sum_r H2[r, i] dY[r, c]; dY recomputed from Y and T.
+__global__ __launch_bounds__(256) void k_dw3(const uint16_t *H2, const float *Y, const float *T, int64_t rows,
+                                             float *grads) {
+    const int i = blockIdx.x;  // hidden unit
+    const float scale = 1.0f / (float)rows;
+    float a0 = 0.f, a1 = 0.f;
+    for (int64_t r = threadIdx.x; r < rows; r += 256) {
+        const float h = bf2f(H2[r * kHid + i]);
+        a0 += h * (Y[2 * r] - T[2 * r]) * scale;
+        a1 += h * (Y[2 * r + 1] - T[2 * r + 1]) * scale;
+    }
+    __shared__ float s0[256], s1[256];
+    s0[threadIdx.x] = a0;
+    s1[threadIdx.x] = a1;
+    __syncthreads();
+    for (int off = 128; off >= 1; off >>= 1) {
+        if ((int)threadIdx.x < off) {
+            s0[threadIdx.x] += s0[threadIdx.x + off];
+            s1[threadIdx.x] += s1[threadIdx.x + off];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        grads[kOffW3 + 2 * i] = s0[0];
+        grads[kOffW3 + 2 * i + 1] = s1[0];
+    }
+}
+
+// Adam (Kingma and Ba) with bias correction, then the bf16 weight shadows.
+__global__ void k_adam(float *p, const float *g, float *m, float *v, int64_t n, float lr, float bc1, float bc2,
+                       uint16_t *w1, uint16_t *w2, uint16_t *w3) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float pi = p[i] - lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+    p[i] = pi;
+    if (i < kOffB1) w1[i - kOffW1] = f2bf(pi);
+    else if (i >= kOffW2 && i < kOffB2) w2[i - kOffW2] = f2bf(pi);
+    else if (i >= kOffW3 && i < kOffB3) w3[i - kOffW3] = f2bf(pi);
+}
+
+__global__ void k_shadow(const float *p, uint16_t *w1, uint16_t *w2, uint16_t *w3) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < kOffB1) w1[i] = f2bf(p[i]);
+    else if (i >= kOffW2 && i < kOffB2) w2[i - kOffW2] = f2bf(p[i]);
+    else if (i >= kOffW3 && i < kOffB3) w3[i - kOffW3] = f2bf(p[i]);
+}
+
+static unsigned blocks(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+static void gemm(hipStream_t st, const GemmArgs &g) {
+    dim3 grid((g.N + kTN - 1) / kTN, (g.M + kTM - 1) / kTM);
+    hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, st, g);
+}
+
+}  // namespace insp
+
+using namespace insp;
+
+struct insp_mlp {
+    int device = 0;
+    int64_t step = 0;
+    DevBuf p, g, m, v;            // fp32 [kParams]
+    DevBuf w1, w2, w3;            // bf16 shadows
+    DevBuf loss;                  // fp32 [1]
+    int64_t cap = 0;              // rows the activation buffers hold
+    DevBuf xb, h1, h2, dh2, dh1;  // bf16 activations and gradients
+    DevBuf y;                     // fp32 [cap, 2]
+};
+
+static int mlp_reserve(insp_mlp *m, int64_t rows) {
+    if (rows <= m->cap) return INSP_OK;
+    int rc;
+    if ((rc = m->xb.alloc(2 * kIn * rows)) || (rc = m->h1.alloc(2 * kHid * rows)) ||
+        (rc = m->h2.alloc(2 * kHid * rows)) || (rc = m->dh2.alloc(2 * kHid * rows)) ||
+        (rc = m->dh1.alloc(2 * kHid * rows)) || (rc = m->y.alloc(4 * kOut * rows)))
+        return rc;
+    m->cap = rows;
+    return INSP_OK;
+}
+
+// Forward over `rows` rows of fp32 features into the bf16 activation buffers.
+static void mlp_forward(insp_mlp *m, const float *x, int64_t rows, hipStream_t st) {
+    const float *P = m->p.as<float>();
+    hipLaunchKernelGGL(k_to_bf16, dim3(blocks(rows * kIn, 256)), dim3(256), 0, st, x, m->xb.as<uint16_t>(), rows * kIn);
+    GemmArgs g;
+    memset(&g, 0, sizeof g);
+    g.M = (int)rows; g.N = kHid; g.K = kIn;
+    g.A = m->xb.as<uint16_t>(); g.sam = kIn; g.sak = 1;
+    g.B = m->w1.as<uint16_t>(); g.sbk = kHid; g.sbn = 1;
+    g.bias = P + kOffB1; g.relu = 1;
+    g.C16 = m->h1.as<uint16_t>(); g.ldc16 = kHid;
+    gemm(st, g);
+    g.K = kHid;
+    g.A = m->h1.as<uint16_t>(); g.sam = kHid;
+    g.B = m->w2.as<uint16_t>();
+    g.bias = P + kOffB2;
+    g.C16 = m->h2.as<uint16_t>();
+    gemm(st, g);
+}
+
+// Loss and gradients of one batch into m->g (zeroed first); y out optional.
+static int mlp_backward(insp_mlp *m, const float *x, const float *t, int64_t B, hipStream_t st) {
+    float *G = m->g.as<float>();
+    hipLaunchKernelGGL(k_fill, dim3(blocks(kParams, 256)), dim3(256), 0, st, G, kParams, 0.f);
+    hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, st, m->loss.as<float>(), (int64_t)1, 0.f);
+    mlp_forward(m, x, B, st);
+    hipLaunchKernelGGL(k_out, dim3(blocks(B, 4)), dim3(256), 0, st, m->h2.as<uint16_t>(), m->w3.as<uint16_t>(),
+                       m->p.as<float>() + kOffB3, B, m->y.as<float>(), t, G, m->loss.as<float>(),
+                       m->dh2.as<uint16_t>(), (int32_t *)nullptr);
+    hipLaunchKernelGGL(k_dw3, dim3(kHid), dim3(256), 0, st, m->h2.as<uint16_t>(), m->y.as<float>(), t, B, G);
+    GemmArgs g;
+    memset(&g, 0, sizeof g);
+    // dW2 = H1^T dH2
+    g.M = kHid; g.N = kHid; g.K = (int)B;
+    g.A = m->h1.as<uint16_t>(); g.sam = 1; g.sak = kHid;
+    g.B = m->dh2.as<uint16_t>(); g.sbk = kHid; g.sbn = 1;
+    g.C32 = G + kOffW2; g.ldc = kHid;
+    gemm(st, g);
+    // dH1 = (dH2 W2^T) * (H1 > 0), db1 = column sums
+    memset(&g, 0, sizeof g);
+    g.M = (int)B; g.N = kHid; g.K = kHid;
+    g.A = m->dh2.as<uint16_t>(); g.sam = kHid; g.sak = 1;
+    g.B = m->w2.as<uint16_t>(); g.sbk = 1; g.sbn = kHid;
+    g.mask = m->h1.as<uint16_t>(); g.smm = kHid; g.smn = 1;
+    g.C16 = m->dh1.as<uint16_t>(); g.ldc16 = kHid;
+    g.colsum = G + kOffB1;
+    gemm(st, g);
+    // dW1 = X^T dH1
+    memset(&g, 0, sizeof g);
+    g.M = kIn; g.N = kHid; g.K = (int)B;
+    g.A = m->xb.as<uint16_t>(); g.sam = 1; g.sak = kIn;
+    g.B = m->dh1.as<uint16_t>(); g.sbk = kHid; g.sbn = 1;
+    g.C32 = G + kOffW1; g.ldc = kHid;
+    gemm(st, g);
+    INSP_HIP(hipGetLastError());
+    return INSP_OK;
+}
+
+extern "C" int insp_mlp_create(const float *params, insp_mlp **out) {
+    if (!params || !out) return set_error(INSP_E_INVAL, "null argument");
+    std::unique_ptr<insp_mlp> m(new insp_mlp());
+    INSP_HIP(hipGetDevice(&m->device));
+    int rc;
+    if ((rc = m->p.alloc(4 * kParams)) || (rc = m->g.alloc(4 * kParams)) || (rc = m->m.alloc(4 * kParams)) ||
+        (rc = m->v.alloc(4 * kParams)) || (rc = m->w1.alloc(2 * kIn * kHid)) || (rc = m->w2.alloc(2 * kHid * kHid)) ||
+        (rc = m->w3.alloc(2 * kHid * kOut)) || (rc = m->loss.alloc(4)))
+        return rc;
+    INSP_HIP(hipMemcpy(m->p.p, params, 4 * kParams, hipMemcpyHostToDevice));
+    INSP_HIP(hipMemset(m->m.p, 0, 4 * kParams));
+    INSP_HIP(hipMemset(m->v.p, 0, 4 * kParams));
+    hipLaunchKernelGGL(k_shadow, dim3(blocks(kParams, 256)), dim3(256), 0, 0, m->p.as<float>(), m->w1.as<uint16_t>(),
+                       m->w2.as<uint16_t>(), m->w3.as<uint16_t>());
+    INSP_HIP(hipGetLastError());
+    INSP_HIP(hipDeviceSynchronize());
+    *out = m.release();
+    return INSP_OK;
+}
+
+extern "C" void insp_mlp_free(insp_mlp *m) { delete m; }
+
+extern "C" int insp_mlp_grads(insp_mlp *m, const float *x, const float *t, int32_t batch, float *grads, float *y,
+                              float *loss, void *stream) {
+    if (!m || !x || !t || batch < 1 || batch % 32) return set_error(INSP_E_INVAL, "bad argument");
+    hipStream_t st = (hipStream_t)stream;
+    int rc;
+    if ((rc = mlp_reserve(m, batch)) || (rc = mlp_backward(m, x, t, batch, st))) return rc;
+    if (grads) INSP_HIP(hipMemcpyAsync(grads, m->g.p, 4 * kParams, hipMemcpyDeviceToDevice, st));
+    if (y) INSP_HIP(hipMemcpyAsync(y, m->y.p, 4 * kOut * (size_t)batch, hipMemcpyDeviceToDevice, st));
+    if (loss) INSP_HIP(hipMemcpyAsync(loss, m->loss.p, 4, hipMemcpyDeviceToDevice, st));
+    return INSP_OK;
+}
+
+extern "C" int insp_mlp_train_step(insp_mlp *m, const float *x, const float *t, int32_t batch, float lr, float *loss,
+                                   void *stream) {
+    if (!m || !x || !t || batch < 1 || batch % 32 || !(lr > 0.f)) return set_error(INSP_E_INVAL, "bad argument");
+    hipStream_t st = (hipStream_t)stream;
+    int rc;
+    if ((rc = mlp_reserve(m, batch)) || (rc = mlp_backward(m, x, t, batch, st))) return rc;
+    m->step++;
+    const float bc1 = 1.f - powf(0.9f, (float)m->step), bc2 = 1.f - powf(0.999f, (float)m->step);
+    hipLaunchKernelGGL(k_adam, dim3(blocks(kParams, 256)), dim3(256), 0, st, m->p.as<float>(), m->g.as<float>(),
+                       m->m.as<float>(), m->v.as<float>(), kParams, lr, bc1, bc2, m->w1.as<uint16_t>(),
+                       m->w2.as<uint16_t>(), m->w3.as<uint16_t>());
+    if (loss) INSP_HIP(hipMemcpyAsync(loss, m->loss.p, 4, hipMemcpyDeviceToDevice, st));
+    INSP_HIP(hipGetLastError());
+    return INSP_OK;
+}
+
+extern "C" int insp_mlp_predict(insp_mlp *m, const float *x, int64_t n, float *y, int32_t *est, void *stream) {
+    if (!m || (n > 0 && (!x || (!y && !est))) || n < 0) return set_error(INSP_E_INVAL, "bad argument");
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t chunk = 1 << 16;
+    int rc;
+    if ((rc = mlp_reserve(m, std::min<int64_t>(std::max<int64_t>(n, 1), chunk)))) return rc;
+    for (int64_t r0 = 0; r0 < n; r0 += chunk) {
+        const int64_t rows = std::min(chunk, n - r0);
+        mlp_forward(m, x + r0 * kIn, rows, st);
+        hipLaunchKernelGGL(k_out, dim3(blocks(rows, 4)), dim3(256), 0, st, m->h2.as<uint16_t>(),
+                           m->w3.as<uint16_t>(), m->p.as<float>() + kOffB3, rows, y ? y + r0 * kOut : nullptr,
+                           (const float *)nullptr, (float *)nullptr, (float *)nullptr, (uint16_t *)nullptr,
+                           est ? est + r0 * kOut : nullptr);
+    }
+    INSP_HIP(hipGetLastError());
+    return INSP_OK;
+}
+
+extern "C" int insp_mlp_state(insp_mlp *m, float *params, float *adam_m, float *adam_v, int64_t *step, int to_host) {
+    if (!m) return set_error(INSP_E_INVAL, "null model");
+    INSP_HIP(hipDeviceSynchronize());
+    const hipMemcpyKind k = to_host ? hipMemcpyDeviceToHost : hipMemcpyHostToDevice;
+    struct { float *h; DevBuf *d; } parts[3] = {{params, &m->p}, {adam_m, &m->m}, {adam_v, &m->v}};
+    for (auto &pp : parts)
+        if (pp.h) {
+            if (to_host) INSP_HIP(hipMemcpy(pp.h, pp.d->p, 4 * kParams, k));
+            else INSP_HIP(hipMemcpy(pp.d->p, pp.h, 4 * kParams, k));
+        }
+    if (step) {
+        if (to_host) *step = m->step;
+        else m->step = *step;
+    }
+    if (!to_host && params) {
+        hipLaunchKernelGGL(k_shadow, dim3(blocks(kParams, 256)), dim3(256), 0, 0, m->p.as<float>(),
+                           m->w1.as<uint16_t>(), m->w2.as<uint16_t>(), m->w3.as<uint16_t>());
+        INSP_HIP(hipGetLastError());
+        INSP_HIP(hipDeviceSynchronize());
+    }
+    return INSP_OK;
+}

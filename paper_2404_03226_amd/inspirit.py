@@ -23,7 +23,9 @@ ALL_DAGS = -1
 
 EXPORTS = ("insp_build_dag", "insp_free_dag", "insp_dag_info", "insp_attributes", "insp_schedule",
            "insp_schedule_batch", "insp_sync_status", "insp_profile_enable", "insp_profile_read",
-           "insp_last_error")
+           "insp_mlp_create", "insp_mlp_free", "insp_mlp_grads", "insp_mlp_train_step", "insp_mlp_predict",
+           "insp_mlp_state", "insp_last_error")
+MLP_PARAMS = 74754
 
 
 class InspError(RuntimeError):
@@ -73,6 +75,13 @@ def load(path: str = LIB_PATH):
     lib.insp_sync_status.argtypes = [P, P]
     lib.insp_profile_enable.argtypes = [C.c_int]
     lib.insp_profile_read.argtypes = [C.c_char_p, C.POINTER(C.c_double), C.POINTER(i64)]
+    lib.insp_mlp_create.argtypes = [P, C.POINTER(P)]
+    lib.insp_mlp_free.argtypes = [P]
+    lib.insp_mlp_free.restype = None
+    lib.insp_mlp_grads.argtypes = [P, P, P, i32, P, P, P, P]
+    lib.insp_mlp_train_step.argtypes = [P, P, P, i32, C.c_float, P, P]
+    lib.insp_mlp_predict.argtypes = [P, P, i64, P, P, P]
+    lib.insp_mlp_state.argtypes = [P, P, P, P, C.POINTER(i64), C.c_int]
     lib.insp_last_error.restype = C.c_char_p
     _lib = lib
     return lib
@@ -255,3 +264,56 @@ def batch_to_device(b, device="cuda"):
     dur = torch.from_numpy(np.ascontiguousarray(b.dur, np.int32)).to(device)
     est = torch.from_numpy(np.ascontiguousarray(b.est, np.int32)).to(device)
     return dag, dur, est
+
+
+class Mlp:
+    """Learned cost model on the device (see insp_mlp_* in the header)."""
+
+    def __init__(self, params):
+        flat = np.ascontiguousarray(np.concatenate([np.asarray(q, np.float32).reshape(-1) for q in params]))
+        assert flat.size == MLP_PARAMS
+        h = C.c_void_p()
+        _check(load().insp_mlp_create(_ptr(flat), C.byref(h)))
+        self._h = h
+
+    def free(self):
+        if getattr(self, "_h", None):
+            load().insp_mlp_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def grads(self, x, t, stream=None):
+        import torch
+        B = x.shape[0]
+        g = torch.empty(MLP_PARAMS, dtype=torch.float32, device=x.device)
+        y = torch.empty((B, 2), dtype=torch.float32, device=x.device)
+        loss = torch.empty(1, dtype=torch.float32, device=x.device)
+        _check(load().insp_mlp_grads(self._h, _ptr(x), _ptr(t), B, _ptr(g), _ptr(y), _ptr(loss), _stream(stream)))
+        return g, y, loss
+
+    def train_step(self, x, t, lr=1e-3, loss=None, stream=None):
+        _check(load().insp_mlp_train_step(self._h, _ptr(x), _ptr(t), x.shape[0], lr, _ptr(loss), _stream(stream)))
+
+    def predict(self, x, want_y=True, stream=None):
+        import torch
+        n = x.shape[0]
+        y = torch.empty((max(n, 1), 2), dtype=torch.float32, device=x.device) if want_y else None
+        est = torch.empty((max(n, 1), 2), dtype=torch.int32, device=x.device)
+        _check(load().insp_mlp_predict(self._h, _ptr(x), n, _ptr(y), _ptr(est), _stream(stream)))
+        return (y[:n] if want_y else None), est[:n]
+
+    def state(self):
+        p, m, v = (np.zeros(MLP_PARAMS, np.float32) for _ in range(3))
+        step = C.c_int64()
+        _check(load().insp_mlp_state(self._h, _ptr(p), _ptr(m), _ptr(v), C.byref(step), 1))
+        return p, m, v, step.value
+
+    def load_state(self, p, m, v, step):
+        p, m, v = (np.ascontiguousarray(a, np.float32) for a in (p, m, v))
+        st = C.c_int64(step)
+        _check(load().insp_mlp_state(self._h, _ptr(p), _ptr(m), _ptr(v), C.byref(st), 0))

@@ -383,3 +383,96 @@ def concat(ws: list) -> Batch:
                  np.concatenate([w.est for w in ws]).astype(np.int32),
                  np.array([w.n_cpu for w in ws], dtype=np.int32),
                  np.array([w.n_gpu for w in ws], dtype=np.int32))
+
+
+# ------------------------------------------------------- learned cost model
+
+N_FEAT = 32
+MLP_SHAPES = ((32, 256), (256,), (256, 256), (256,), (256, 2), (2,))
+"""Parameter tensors in packed order: W1, b1, W2, b2, W3, b3 (74,754 floats)."""
+
+
+def _normal(st: Stream, idx) -> np.ndarray:
+    """Standard normals by the Box-Muller transform of two stream values."""
+    idx = np.asarray(idx, dtype=np.uint64)
+    u1 = 1.0 - st.uniform(idx * np.uint64(2))
+    u2 = st.uniform(idx * np.uint64(2) + np.uint64(1))
+    return np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * np.pi * u2)
+
+
+def cost_coeffs(seed: int = 5) -> tuple:
+    """a_k, b_k ~ N(0, 1/28) for k = CPU, GPU: shape [2, 28] each."""
+    st = _sub(seed, 1000, _S_FEAT)
+    a = _normal(st, np.arange(56)).reshape(2, 28) / math.sqrt(28.0)
+    b = _normal(st, np.arange(56, 112)).reshape(2, 28) / math.sqrt(28.0)
+    return a, b
+
+
+def cost_features(seed: int, stream: int, types: np.ndarray) -> np.ndarray:
+    """x in R^32: one-hot of the type (4 dims) and 28 values from U[0, 1)."""
+    n = types.shape[0]
+    x = np.zeros((n, N_FEAT), dtype=np.float32)
+    x[np.arange(n), types] = 1.0
+    x[:, 4:] = _sub(seed, stream, _S_FEAT).uniform(np.arange(28 * n)).reshape(n, 28)
+    return x
+
+
+def cost_truth(seed: int, stream: int, types: np.ndarray, x: np.ndarray) -> np.ndarray:
+    """True ticks [n, 2]: ln d_k = ln base[type][k] + 0.8 tanh(a_k . x[4:] - sum(a_k)/2)
+    + 0.2 sin(2 pi b_k . x[4:]) + 0.2 z, z ~ N(0, 1); rounded half-to-even and
+    clamped to [1, 2^20].  base is the Cholesky per-kernel table."""
+    a, b = cost_coeffs(seed)
+    n = types.shape[0]
+    xr = x[:, 4:].astype(np.float64)
+    z = _normal(_sub(seed, stream, _S_JIT), np.arange(2 * n)).reshape(n, 2)
+    lnd = (np.log(CHOL_BASE[types].astype(np.float64)) + 0.8 * np.tanh(xr @ a.T - 0.5 * a.sum(axis=1))
+           + 0.2 * np.sin(2.0 * np.pi * (xr @ b.T)) + 0.2 * z)
+    return np.clip(np.rint(np.exp(lnd)), 1, 1 << 20).astype(np.int32)
+
+
+def cfg5_records(seed: int = 5, n: int = 1_000_000):
+    """Training records from Cholesky-style task mixes (40 x 40 tiles, repeated
+    DAG after DAG): features, types and true ticks; first 90% train, rest
+    validation."""
+    _, _, ty = cholesky_dag(40)
+    types = np.tile(ty, -(-n // ty.size))[:n].astype(np.int32)
+    x = cost_features(seed, 0, types)
+    ticks = cost_truth(seed, 0, types, x)
+    cut = (9 * n) // 10
+    return {"x": x, "types": types, "ticks": ticks, "n_train": cut}
+
+
+def plain_table(types: np.ndarray, ticks: np.ndarray, n_types: int = 4) -> np.ndarray:
+    """Per-(type, kind) integer mean of observed ticks (the table fallback)."""
+    tab = np.ones((n_types, 2), dtype=np.int32)
+    for t in range(n_types):
+        sel = types == t
+        if sel.any():
+            tab[t] = np.maximum(1, np.rint(ticks[sel].mean(axis=0))).astype(np.int32)
+    return tab
+
+
+def mlp_init(seed: int = 5) -> list:
+    """He-uniform weights U(-sqrt(6/fan_in), +sqrt(6/fan_in)), zero biases (fp32)."""
+    st = _sub(seed, 2000, _S_FEAT)
+    out, off = [], 0
+    for shp in MLP_SHAPES:
+        cnt = int(np.prod(shp))
+        if len(shp) == 2:
+            lim = math.sqrt(6.0 / shp[0])
+            w = (st.uniform(np.arange(off, off + cnt)) * 2.0 - 1.0) * lim
+        else:
+            w = np.zeros(cnt)
+        out.append(w.reshape(shp).astype(np.float32))
+        off += cnt
+    return out
+
+
+def cfg5_eval(seed: int = 5, n_dags: int = 4096):
+    """Evaluation workload: the layered batch's DAG shapes with their types
+    read as the four Cholesky kernels; per-task features and true ticks."""
+    ws = cfg3(seed=3, n_dags=n_dags)
+    b = concat(ws)
+    x = cost_features(seed, 7, b.type)
+    ticks = cost_truth(seed, 7, b.type, x)
+    return ws, b, x, ticks

@@ -1,0 +1,128 @@
+"""HIP cost-model kernels against the FP64 reference with bf16 rounding."""
+import numpy as np
+import pytest
+
+from oracle import mlp
+from paper_2404_03226_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def insp():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2404_03226_amd import inspirit
+    inspirit.load()
+    return inspirit
+
+
+def rel(a, b):
+    a, b = np.asarray(a, np.float64), np.asarray(b, np.float64)
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+
+
+def batch(n, seed=0):
+    rec = synth.cfg5_records(n=max(n, 2048))
+    X = rec["x"][:n]
+    T = np.log(rec["ticks"][:n].astype(np.float64)).astype(np.float32)
+    return X, T
+
+
+@pytest.mark.parametrize("B", [32, 96, 1024])
+def test_forward_backward_match_reference(insp, B):
+    import torch
+    print("[case] mlp grads", B, flush=True)
+    p = synth.mlp_init()
+    X, T = batch(B)
+    m = insp.Mlp(p)
+    g, y, loss = m.grads(torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda())
+    ref_loss, ref_g, c = mlp.loss_grads(p, X, T, bf=True)
+    assert rel(y.cpu().numpy(), c["Y"]) <= 1e-3
+    assert abs(loss.item() - ref_loss) <= 1e-3 * ref_loss
+    gg = mlp.unpack(g.cpu().numpy(), synth.MLP_SHAPES)
+    for name, a, b in zip(("W1", "b1", "W2", "b2", "W3", "b3"), gg, ref_g):
+        assert rel(a, b) <= 1e-3, name
+    m.free()
+
+
+def test_adam_step_matches_reference(insp):
+    import torch
+    print("[case] mlp adam", flush=True)
+    p = synth.mlp_init()
+    X, T = batch(256)
+    m = insp.Mlp(p)
+    m.train_step(torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda(), lr=1e-3)
+    torch.cuda.synchronize()
+    newp, _, _, step = m.state()
+    _, g, _ = mlp.loss_grads(p, X, T, bf=True)
+    zeros = [np.zeros_like(q, dtype=np.float64) for q in p]
+    ref, _, _ = mlp.adam([q.astype(np.float64) for q in p], g, zeros, zeros, 1)
+    assert step == 1
+    # first step moves every weight by ~lr * sign(g); compare the moves
+    moved = newp - mlp.pack(p)
+    assert rel(moved, mlp.pack(ref) - mlp.pack(p)) <= 2e-2
+    m.free()
+
+
+def test_predict_matches_reference_and_rounds(insp):
+    import torch
+    print("[case] mlp predict", flush=True)
+    p = synth.mlp_init()
+    rec = synth.cfg5_records(n=70000)  # spans two chunks of the predict path plus a tail
+    X = rec["x"][:70001 - 2]
+    m = insp.Mlp(p)
+    y, est = m.predict(torch.from_numpy(X).cuda())
+    y, est = y.cpu().numpy(), est.cpu().numpy()
+    ref = mlp.forward(p, X, bf=True)["Y"]
+    assert rel(y, ref) <= 1e-3
+    # integer decision taken from the kernel's own y in the same precision
+    e = np.exp(y.astype(np.float32))
+    ok = np.abs(e - np.floor(e) - 0.5) > 1e-3 * np.maximum(e, 1.0)
+    want = np.clip(np.rint(e), 1, 1 << 20).astype(np.int32)
+    assert np.array_equal(est[ok], want[ok])
+    m.free()
+
+
+def test_training_beats_the_per_type_table(insp):
+    import torch
+    print("[case] mlp training", flush=True)
+    rec = synth.cfg5_records(n=200_000)
+    ntr = rec["n_train"]
+    X = torch.from_numpy(rec["x"]).cuda()
+    LT = torch.from_numpy(np.log(rec["ticks"].astype(np.float64)).astype(np.float32)).cuda()
+    m = insp.Mlp(synth.mlp_init())
+    B = 1024
+    for ep in range(3):
+        for i in range(0, ntr - B + 1, B):
+            m.train_step(X[i:i + B], LT[i:i + B], lr=1e-3)
+    torch.cuda.synchronize()
+    y, _ = m.predict(X[ntr:])
+    val = LT[ntr:].cpu().numpy()
+    mse_mlp = float(np.mean((y.cpu().numpy() - val) ** 2))
+    tab = synth.plain_table(rec["types"][:ntr], rec["ticks"][:ntr])
+    mse_tab = float(np.mean((np.log(tab[rec["types"][ntr:]].astype(np.float64)) - val) ** 2))
+    print("val mse mlp", mse_mlp, "table", mse_tab, flush=True)
+    assert mse_mlp < mse_tab
+    m.free()
+
+
+def test_checkpoint_resume_is_bit_identical(insp):
+    import torch
+    print("[case] mlp resume", flush=True)
+    X, T = batch(4096)
+    Xd, Td = torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda()
+    a = insp.Mlp(synth.mlp_init())
+    for i in range(2):
+        a.train_step(Xd[i * 1024:(i + 1) * 1024], Td[i * 1024:(i + 1) * 1024])
+    torch.cuda.synchronize()
+    snap = a.state()
+    b = insp.Mlp(synth.mlp_init())
+    b.load_state(*snap)
+    for mdl in (a, b):
+        for i in range(2, 4):
+            mdl.train_step(Xd[i * 1024:(i + 1) * 1024], Td[i * 1024:(i + 1) * 1024])
+    torch.cuda.synchronize()
+    pa, pb = a.state()[0], b.state()[0]
+    assert np.array_equal(pa, pb)
