@@ -65,6 +65,9 @@ def main():
     ap.add_argument("--tune", default=None, help="launch shape, e.g. waves=1,grid=2048")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-verify", action="store_true")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-cost-model gap")
+    ap.add_argument("--no-tune", action="store_true", help="use the library's default launch shape")
+    ap.add_argument("--epochs", type=int, default=10)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: this build has no multi-GPU path "
@@ -88,8 +91,14 @@ def main():
     out["makespan"] = torch.empty(len(ws), dtype=torch.int64, device=dur.device)
     stream = torch.cuda.current_stream()
 
+    tune_key = args.tune
+    if tune_key is None and not args.no_tune and len(ws) > 1:
+        from paper_2404_03226_amd import autotune
+        tune_key = autotune.tune(dag, workers, dur, est, prm, out, verbose=False)
+        log(f"autotuned launch: {tune_key}")
+
     def step():
-        inspirit.schedule_batch(dag, workers, dur, est, prm, tune_key=args.tune, out=out)
+        inspirit.schedule_batch(dag, workers, dur, est, prm, tune_key=tune_key, out=out)
 
     for i in range(args.warmup):
         step()
@@ -160,7 +169,7 @@ def main():
         "dtype": "int64",
         "data": "synthetic",
         "config": {"workload": desc, "n_dags": len(ws), "tasks": N, "edges": M, "policy": args.policy,
-                   "launch": args.tune or "default"},
+                   "launch": tune_key or "default"},
         "bit_exact": bit_exact,
         "schedule_sha256": digest.hexdigest(),
         "roofline": roof,
@@ -168,8 +177,57 @@ def main():
         "cpu_baseline": cpu,
         "learned_gap": None,
     }
+    if args.workload == "batch" and not args.no_learned:
+        line["learned_gap"] = learned_gap(dag, workers, b, args.epochs)
     print(json.dumps(line), flush=True)
     dag.free()
+
+
+def learned_gap(dag, workers, b, epochs):
+    """Train the device MLP on 1M simulator records, predict per-kind ticks for
+    every task of the batch, and compare makespans against true durations for
+    est = truth, est = per-type table, est = MLP (all runs advance with truth)."""
+    import torch
+    from paper_2404_03226_amd import costmodel, inspirit, synth
+    t0 = time.time()
+    rec = synth.cfg5_records()
+    ntr = rec["n_train"]
+    x = torch.from_numpy(rec["x"]).cuda()
+    lt = torch.from_numpy(np.log(rec["ticks"].astype(np.float64)).astype(np.float32)).cuda()
+    mlp = inspirit.Mlp(synth.mlp_init())
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    steps = costmodel.train(mlp, x, lt, ntr, epochs=epochs, log=log)
+    ev1.record()
+    torch.cuda.synchronize()
+    train_ms = ev0.elapsed_time(ev1)
+    yv, _ = mlp.predict(x[ntr:])
+    val = lt[ntr:].cpu().numpy()
+    table = synth.plain_table(rec["types"][:ntr], rec["ticks"][:ntr])
+    mse_mlp = float(np.mean((yv.cpu().numpy() - val) ** 2))
+    mse_tab = float(np.mean((np.log(table[rec["types"][ntr:]].astype(np.float64)) - val) ** 2))
+    del x, lt
+    xe = synth.cost_features(5, 7, b.type)
+    ticks = synth.cost_truth(5, 7, b.type, xe)
+    log(f"cost model: trained {steps} steps in {train_ms / 1e3:.1f}s; eval features ready ({time.time() - t0:.0f}s)")
+    xd = torch.from_numpy(xe).cuda()
+    ev0.record()
+    _, est_mlp = mlp.predict(xd, want_y=False)
+    ev1.record()
+    torch.cuda.synchronize()
+    pred_ms = ev0.elapsed_time(ev1)
+    del xd
+    ms = costmodel.evaluate(dag, workers, b.type, ticks, est_mlp, table,
+                            lambda d, w, du, es: inspirit.schedule_batch(d, w, du, es))
+    gaps = costmodel.makespan_gaps(ms["true"], ms["plain"], ms["learned"])
+    gaps.update({"val_mse_ln_mlp": mse_mlp, "val_mse_ln_table": mse_tab, "train_steps": steps,
+                 "train_s": round(train_ms / 1e3, 2), "predict_ms": round(pred_ms, 2),
+                 "predict_tasks_per_s": round(len(b.type) / (pred_ms * 1e-3), 1),
+                 "predict_TFLOPs": round(148480 * len(b.type) / (pred_ms * 1e-3) / 1e12, 2),
+                 "train_TFLOPs": round(445440 * 1024 * steps / (train_ms * 1e-3) / 1e12, 2)})
+    mlp.free()
+    log(f"learned gap: {gaps}")
+    return gaps
 
 
 if __name__ == "__main__":

@@ -1,0 +1,74 @@
+"""Launch-shape autotuner for the batch simulation.
+
+Times candidate tuning keys (persistent work-groups, LDS-resident queue
+blocks per DAG) on the caller's own workload and caches the fastest per
+(device architecture, CU count, workload signature).  Every key yields the
+same schedule; only the time differs.
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+
+import numpy as np
+
+
+def _cache_path():
+    return os.environ.get("INSP_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "inspirit",
+                                                           "tune.json"))
+
+
+def signature(dag, workers, prm) -> str:
+    h = hashlib.sha1()
+    h.update(np.asarray(dag.n, np.int64).tobytes())
+    h.update(np.asarray(dag.m, np.int64).tobytes())
+    h.update(np.asarray(workers, np.int32).tobytes())
+    h.update(bytes([prm.policy & 0xFF]))
+    return h.hexdigest()[:16]
+
+
+def candidates(n_dags, cus):
+    grids = sorted({min(n_dags, cus * k) for k in (4, 8, 12, 16)})
+    return [f"waves=1,grid={g},lds_blocks={lb}" for g in grids for lb in (256, 512)]
+
+
+def tune(dag, workers, dur, est, prm, out, reps=2, use_cache=True, verbose=False) -> str:
+    import torch
+    from . import inspirit
+    props = torch.cuda.get_device_properties(torch.cuda.current_device())
+    arch = getattr(props, "gcnArchName", "gfx?")
+    key = f"{arch}:{props.multi_processor_count}:{signature(dag, workers, prm)}"
+    path = _cache_path()
+    cache = {}
+    if use_cache and os.path.exists(path):
+        try:
+            cache = json.load(open(path))
+        except (OSError, ValueError):
+            cache = {}
+    if key in cache:
+        return cache[key]
+    best, best_ms = None, float("inf")
+    for cand in candidates(dag.n_dags, props.multi_processor_count):
+        inspirit.schedule_batch(dag, workers, dur, est, prm, tune_key=cand, out=out)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            inspirit.schedule_batch(dag, workers, dur, est, prm, tune_key=cand, out=out)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        if verbose:
+            print(f"[tune] {cand}: {ms:.2f} ms", flush=True)
+        if ms < best_ms:
+            best, best_ms = cand, ms
+    cache[key] = best
+    try:
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        with open(path + ".tmp", "w") as f:
+            json.dump(cache, f, indent=1)
+        os.replace(path + ".tmp", path)
+    except OSError:
+        pass
+    return best

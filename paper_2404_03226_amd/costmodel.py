@@ -1,0 +1,45 @@
+"""Learned cost model pipeline: train the device MLP on simulator records and
+measure the makespan gap its estimates cause against true durations, beside
+the per-type average table (the paper's "average execution times")."""
+from __future__ import annotations
+
+import numpy as np
+
+from . import synth
+
+
+def train(mlp, x, log_ticks, n_train, epochs=10, batch=1024, lr=1e-3, log=None):
+    """Train on rows [0, n_train) in order, `epochs` passes (device tensors)."""
+    import torch
+    steps = 0
+    for ep in range(epochs):
+        for i in range(0, n_train - batch + 1, batch):
+            mlp.train_step(x[i:i + batch], log_ticks[i:i + batch], lr=lr)
+            steps += 1
+        if log:
+            torch.cuda.synchronize()
+            log(f"epoch {ep + 1}/{epochs} done ({steps} steps)")
+    torch.cuda.synchronize()
+    return steps
+
+
+def makespan_gaps(m_true, m_plain, m_learned):
+    m_true = np.asarray(m_true, np.float64)
+    gp = (np.asarray(m_plain) - m_true) / m_true
+    gl = (np.asarray(m_learned) - m_true) / m_true
+    return {"gap_plain": float(gp.mean()), "gap_learned": float(gl.mean()),
+            "paired_gain": float((gp - gl).mean()), "frac_improved": float((gl < gp).mean()),
+            "frac_worse": float((gl > gp).mean())}
+
+
+def evaluate(dag, workers, b_type, true_ticks, est_mlp, table, schedule_fn):
+    """Three batch runs on the same DAGs, all advancing with the true ticks:
+    est = true ticks, est = table[type], est = the MLP's estimates."""
+    import torch
+    dev = est_mlp.device
+    dur = torch.from_numpy(np.ascontiguousarray(true_ticks, np.int32)).to(dev)
+    est_tab = torch.from_numpy(np.ascontiguousarray(table[b_type], np.int32)).to(dev)
+    out = {}
+    for name, est in (("true", dur), ("plain", est_tab), ("learned", est_mlp)):
+        out[name] = schedule_fn(dag, workers, dur, est)["makespan"].cpu().numpy().copy()
+    return out

@@ -20,6 +20,7 @@ integer ticks.
 from __future__ import annotations
 
 import math
+import os
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -409,11 +410,21 @@ def cost_coeffs(seed: int = 5) -> tuple:
 
 
 def cost_features(seed: int, stream: int, types: np.ndarray) -> np.ndarray:
-    """x in R^32: one-hot of the type (4 dims) and 28 values from U[0, 1)."""
+    """x in R^32: one-hot of the type (4 dims) and 28 values from U[0, 1)
+    (value j of task i at counter 28 i + j; chunks are filled in parallel)."""
+    from concurrent.futures import ThreadPoolExecutor
     n = types.shape[0]
     x = np.zeros((n, N_FEAT), dtype=np.float32)
     x[np.arange(n), types] = 1.0
-    x[:, 4:] = _sub(seed, stream, _S_FEAT).uniform(np.arange(28 * n)).reshape(n, 28)
+    st = _sub(seed, stream, _S_FEAT)
+    step = 1 << 18
+
+    def fill(r0):
+        r1 = min(n, r0 + step)
+        x[r0:r1, 4:] = st.uniform(np.arange(28 * r0, 28 * r1, dtype=np.uint64)).reshape(r1 - r0, 28)
+
+    with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        list(ex.map(fill, range(0, n, step)))
     return x
 
 

@@ -214,3 +214,42 @@ def test_error_codes_through_abi(insp):
         insp.schedule(dag, 0, (0, 0), d, d)
     assert e.value.code == insp.E_RANGE
     dag.free()
+
+
+def test_batch_graph_replays_match_eager(insp):
+    # the batch step captured in a HIP graph, replayed several times with the
+    # program's own eager work and synchronisations in between
+    import torch
+    ws = synth.cfg3(select=list(range(7, 4096, 512)))
+    b = synth.concat(ws)
+    say("graph", len(ws))
+    dag, dur, est = insp.batch_to_device(b)
+    workers = [(w.n_cpu, w.n_gpu) for w in ws]
+    N = int(b.task_off[-1])
+    eager = insp.schedule_batch(dag, workers, dur, est)
+    torch.cuda.synchronize()
+    ref = {k: v.cpu().clone() for k, v in eager.items()}
+    out = insp._outputs(N, dur.device)
+    out["makespan"] = torch.empty(len(ws), dtype=torch.int64, device=dur.device)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        insp.schedule_batch(dag, workers, dur, est, out=out)   # warm: workspace exists
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        insp.schedule_batch(dag, workers, dur, est, out=out)
+    for rep in range(4):
+        for k in out:
+            out[k].zero_()
+        junk = insp.schedule_batch(dag, workers, dur, est)   # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for k in ("worker", "start", "finish", "ie_at_pop", "mode_at_pop", "makespan"):
+            assert torch.equal(out[k].cpu(), ref[k]), (rep, k)
+        del junk
+    r = oracle.schedule_batch(b)
+    assert np.array_equal(ref["makespan"].numpy(), r["makespan"])
+    dag.free()
