@@ -46,7 +46,7 @@ struct TaskRec {
     int32_t iev;              // current inspiring efficiency
     int32_t qpos;             // queue slot, or -1 when not queued
     int32_t ia, tau, rs;      // out-degree, tau, first edge (fixed during a run)
-    int32_t pad;
+    int32_t seq;              // push sequence number once queued
 };
 
 // Queue slot: key word, payload word and the task's first edge.

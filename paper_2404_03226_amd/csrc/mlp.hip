@@ -40,8 +40,9 @@ __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint
 // ------------------------------------------------------------------ GEMM
 // C[m,n] = sum_k A(m,k) B(k,n), A(m,k) = A[m*sam + k*sak], B(k,n) =
 // B[k*sbk + n*sbn] (bf16), accumulated in fp32, then: + bias[n], ReLU,
-// * (mask(m,n) > 0), stored to C32 (fp32) and/or C16 (bf16); colsum[n] +=
-// the final fp32 values.  64 x 64 tile per 256-thread block; each wave owns a
+// * (mask(m,n) > 0), stored to C32 (fp32) and/or C16 (bf16); colpart gets
+// each 64-row tile's column sums of the final fp32 values (summed later in a
+// fixed order, so training is bit-reproducible).  64 x 64 tile per 256-thread block; each wave owns a
 // 32 x 32 quarter as 2 x 2 MFMA 16x16x32 tiles; K advances 32 at a time
 // through LDS (A row-major, B transposed so both fragments are 16-byte reads).
 struct GemmArgs {
@@ -58,7 +59,7 @@ struct GemmArgs {
     int64_t ldc;
     uint16_t *C16;
     int64_t ldc16;
-    float *colsum;
+    float *colpart;  // [ceil(M/64)][N] per-tile column sums of the final values
 };
 
 constexpr int kTM = 64, kTN = 64, kTK = 32, kLdsRow = kTK + 8;
@@ -66,6 +67,7 @@ constexpr int kTM = 64, kTN = 64, kTK = 32, kLdsRow = kTK + 8;
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
     __shared__ __attribute__((aligned(16))) uint16_t As[kTM * kLdsRow];
     __shared__ __attribute__((aligned(16))) uint16_t Bs[kTN * kLdsRow];
+    __shared__ float cpart[2 * kTN];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int m0 = blockIdx.y * kTM, n0 = blockIdx.x * kTN;
     const int wm = (wv >> 1) * 32, wn = (wv & 1) * 32;
@@ -119,12 +121,28 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
                     csum += v;
                 }
             }
-        if (g.colsum) {
-            csum += __shfl_xor(csum, 16, 64);
-            csum += __shfl_xor(csum, 32, 64);
-            if (lane < 16 && n < g.N) atomicAdd(&g.colsum[n], csum);
+        if (g.colpart) {
+            // rows of this lane group, then the four lane groups in order
+            const float c0 = __shfl(csum, (lane & 15), 64), c1 = __shfl(csum, (lane & 15) + 16, 64);
+            const float c2 = __shfl(csum, (lane & 15) + 32, 64), c3 = __shfl(csum, (lane & 15) + 48, 64);
+            if (lane < 16) cpart[(wv >> 1) * kTN + wn + b * 16 + lane] = ((c0 + c1) + c2) + c3;
         }
     }
+    if (g.colpart) {
+        __syncthreads();
+        // the two row halves of the tile, in order; one partial per M-tile
+        if (tid < kTN && n0 + tid < g.N)
+            g.colpart[(int64_t)blockIdx.y * g.N + n0 + tid] = cpart[tid] + cpart[kTN + tid];
+    }
+}
+
+// Sum `rows` partial rows of `cols` columns in row order (deterministic).
+__global__ void k_colreduce(const float *part, int rows, int cols, float *out) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= cols) return;
+    float s = 0.f;
+    for (int r = 0; r < rows; r++) s += part[(int64_t)r * cols + c];
+    out[c] = s;
 }
 
 // -------------------------------------------------------------- helpers
@@ -138,17 +156,16 @@ __global__ void k_fill(float *x, int64_t n, float v) {
     if (i < n) x[i] = v;
 }
 
-// Output layer and loss gradient, one wave per row: Y = H2 W3 + b3; with a
-// target, dY = 2 (Y - T) / (2B), db3 += dY, loss += (Y - T)^2 / (2B), and
-// dH2 = (dY W3^T) * (H2 > 0) stored as bf16 with db2 += its fp32 value.
+// Output layer and loss gradient, one wave per row (4 rows per block):
+// Y = H2 W3 + b3; with a target T: dY = 2 (Y - T) / (2B), dH2 = (dY W3^T) *
+// (H2 > 0) stored as bf16, and per-block partials (in row order) of db2,
+// db3 and the loss into `part` [blocks][kHid + 3].
 __global__ __launch_bounds__(256) void k_out(const uint16_t *H2, const uint16_t *W3, const float *b3, int64_t rows,
-                                             float *Y, const float *T, float *grads, float *loss, uint16_t *dH2,
+                                             float *Y, const float *T, float *part, uint16_t *dH2,
                                              int32_t *est) {
-    __shared__ float db2s[kHid];
+    __shared__ float rowg[4][kHid];
+    __shared__ float rowx[4][3];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    if (T)
-        for (int i = tid; i < kHid; i += 256) db2s[i] = 0.f;
-    __syncthreads();
     const int64_t r = blockIdx.x * 4LL + wv;
     float w30[4], w31[4], h[4];
     float s0 = 0.f, s1 = 0.f;
@@ -177,27 +194,40 @@ __global__ __launch_bounds__(256) void k_out(const uint16_t *H2, const uint16_t 
             est[2 * r + 1] = (int32_t)fminf(fmaxf(rintf(expf(y1)), 1.f), (float)(1 << 20));
         }
     }
-    if (T && r < rows) {
-        const float scale = 1.0f / (float)rows;  // 2 / (2 rows)
-        const float d0 = (y0 - T[2 * r]) * scale, d1 = (y1 - T[2 * r + 1]) * scale;
-        if (lane == 0) {
-            atomicAdd(&grads[kOffB3], d0);
-            atomicAdd(&grads[kOffB3 + 1], d1);
-            atomicAdd(loss, ((y0 - T[2 * r]) * (y0 - T[2 * r]) + (y1 - T[2 * r + 1]) * (y1 - T[2 * r + 1])) * 0.5f * scale);
-        }
+    if (!T) return;
+    const float scale = 1.0f / (float)rows;  // 2 / (2 rows)
+    float d0 = 0.f, d1 = 0.f, l2 = 0.f;
+    if (r < rows) {
+        const float e0 = y0 - T[2 * r], e1 = y1 - T[2 * r + 1];
+        d0 = e0 * scale;
+        d1 = e1 * scale;
+        l2 = (e0 * e0 + e1 * e1) * 0.5f * scale;
+    }
 #pragma unroll
-        for (int j = 0; j < 4; j++) {
-            const int i = lane * 4 + j;
-            float g = d0 * w30[j] + d1 * w31[j];
-            if (!(h[j] > 0.f)) g = 0.f;
-            dH2[r * kHid + i] = f2bf(g);
-            atomicAdd(&db2s[i], g);
-        }
+    for (int j = 0; j < 4; j++) {
+        const int i = lane * 4 + j;
+        float gv = d0 * w30[j] + d1 * w31[j];
+        if (!(h[j] > 0.f) || r >= rows) gv = 0.f;
+        if (r < rows) dH2[r * kHid + i] = f2bf(gv);
+        rowg[wv][i] = gv;
     }
-    if (T) {
-        __syncthreads();
-        for (int i = tid; i < kHid; i += 256) atomicAdd(&grads[kOffB2 + i], db2s[i]);
+    if (lane == 0) {
+        rowx[wv][0] = d0;
+        rowx[wv][1] = d1;
+        rowx[wv][2] = l2;
     }
+    __syncthreads();
+    float *pp = part + (int64_t)blockIdx.x * (kHid + 3);
+    pp[tid] = ((rowg[0][tid] + rowg[1][tid]) + rowg[2][tid]) + rowg[3][tid];
+    if (tid < 3) pp[kHid + tid] = ((rowx[0][tid] + rowx[1][tid]) + rowx[2][tid]) + rowx[3][tid];
+}
+
+// Place the reduced db2, db3 and loss.
+__global__ void k_unpack_out(const float *red, float *grads, float *loss) {
+    const int i = threadIdx.x;
+    grads[kOffB2 + i] = red[i];
+    if (i < 2) grads[kOffB3 + i] = red[kHid + i];
+    if (i == 0) loss[0] = red[kHid + 2];
 }
 
 // dW3[i, c] = sum_r H2[r, i] dY[r, c]; dY recomputed from Y and T.
@@ -273,6 +303,7 @@ struct insp_mlp {
     int64_t cap = 0;              // rows the activation buffers hold
     DevBuf xb, h1, h2, dh2, dh1;  // bf16 activations and gradients
     DevBuf y;                     // fp32 [cap, 2]
+    DevBuf part;                  // fp32 partial sums for the fixed-order reductions
 };
 
 static int mlp_reserve(insp_mlp *m, int64_t rows) {
@@ -280,7 +311,8 @@ static int mlp_reserve(insp_mlp *m, int64_t rows) {
     int rc;
     if ((rc = m->xb.alloc(2 * kIn * rows)) || (rc = m->h1.alloc(2 * kHid * rows)) ||
         (rc = m->h2.alloc(2 * kHid * rows)) || (rc = m->dh2.alloc(2 * kHid * rows)) ||
-        (rc = m->dh1.alloc(2 * kHid * rows)) || (rc = m->y.alloc(4 * kOut * rows)))
+        (rc = m->dh1.alloc(2 * kHid * rows)) || (rc = m->y.alloc(4 * kOut * rows)) ||
+        (rc = m->part.alloc(4 * ((rows + 3) / 4 + 1) * (kHid + 3))))
         return rc;
     m->cap = rows;
     return INSP_OK;
@@ -306,15 +338,20 @@ static void mlp_forward(insp_mlp *m, const float *x, int64_t rows, hipStream_t s
     gemm(st, g);
 }
 
-// Loss and gradients of one batch into m->g (zeroed first); y out optional.
+// Loss and gradients of one batch into m->g; y out optional.  Every sum is
+// taken in a fixed order, so a step is bit-reproducible.
 static int mlp_backward(insp_mlp *m, const float *x, const float *t, int64_t B, hipStream_t st) {
     float *G = m->g.as<float>();
-    hipLaunchKernelGGL(k_fill, dim3(blocks(kParams, 256)), dim3(256), 0, st, G, kParams, 0.f);
-    hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, st, m->loss.as<float>(), (int64_t)1, 0.f);
+    float *part = m->part.as<float>();
     mlp_forward(m, x, B, st);
-    hipLaunchKernelGGL(k_out, dim3(blocks(B, 4)), dim3(256), 0, st, m->h2.as<uint16_t>(), m->w3.as<uint16_t>(),
-                       m->p.as<float>() + kOffB3, B, m->y.as<float>(), t, G, m->loss.as<float>(),
-                       m->dh2.as<uint16_t>(), (int32_t *)nullptr);
+    const int ob = (int)((B + 3) / 4);
+    hipLaunchKernelGGL(k_out, dim3(ob), dim3(256), 0, st, m->h2.as<uint16_t>(), m->w3.as<uint16_t>(),
+                       m->p.as<float>() + kOffB3, B, m->y.as<float>(), t, part, m->dh2.as<uint16_t>(),
+                       (int32_t *)nullptr);
+    // db2 (256 columns), db3 (2) and the loss (1) from the block partials
+    hipLaunchKernelGGL(k_colreduce, dim3(2), dim3(256), 0, st, part, ob, kHid + 3, part + (int64_t)ob * (kHid + 3));
+    hipLaunchKernelGGL(k_unpack_out, dim3(1), dim3(256), 0, st, part + (int64_t)ob * (kHid + 3), G,
+                       m->loss.as<float>());
     hipLaunchKernelGGL(k_dw3, dim3(kHid), dim3(256), 0, st, m->h2.as<uint16_t>(), m->y.as<float>(), t, B, G);
     GemmArgs g;
     memset(&g, 0, sizeof g);
@@ -324,15 +361,16 @@ static int mlp_backward(insp_mlp *m, const float *x, const float *t, int64_t B, 
     g.B = m->dh2.as<uint16_t>(); g.sbk = kHid; g.sbn = 1;
     g.C32 = G + kOffW2; g.ldc = kHid;
     gemm(st, g);
-    // dH1 = (dH2 W2^T) * (H1 > 0), db1 = column sums
+    // dH1 = (dH2 W2^T) * (H1 > 0); db1 = column sums (per tile, then in order)
     memset(&g, 0, sizeof g);
     g.M = (int)B; g.N = kHid; g.K = kHid;
     g.A = m->dh2.as<uint16_t>(); g.sam = kHid; g.sak = 1;
     g.B = m->w2.as<uint16_t>(); g.sbk = 1; g.sbn = kHid;
     g.mask = m->h1.as<uint16_t>(); g.smm = kHid; g.smn = 1;
     g.C16 = m->dh1.as<uint16_t>(); g.ldc16 = kHid;
-    g.colsum = G + kOffB1;
+    g.colpart = part;
     gemm(st, g);
+    hipLaunchKernelGGL(k_colreduce, dim3(1), dim3(256), 0, st, part, (int)((B + kTM - 1) / kTM), kHid, G + kOffB1);
     // dW1 = X^T dH1
     memset(&g, 0, sizeof g);
     g.M = kIn; g.N = kHid; g.K = (int)B;
@@ -405,7 +443,7 @@ extern "C" int insp_mlp_predict(insp_mlp *m, const float *x, int64_t n, float *y
         mlp_forward(m, x + r0 * kIn, rows, st);
         hipLaunchKernelGGL(k_out, dim3(blocks(rows, 4)), dim3(256), 0, st, m->h2.as<uint16_t>(),
                            m->w3.as<uint16_t>(), m->p.as<float>() + kOffB3, rows, y ? y + r0 * kOut : nullptr,
-                           (const float *)nullptr, (float *)nullptr, (float *)nullptr, (uint16_t *)nullptr,
+                           (const float *)nullptr, (float *)nullptr, (uint16_t *)nullptr,
                            est ? est + r0 * kOut : nullptr);
     }
     INSP_HIP(hipGetLastError());

@@ -98,10 +98,11 @@ struct Lds {
     unsigned long long *sum;                         // [2 * sum_cap] block max keys
     int32_t *fr0, *fr1;                              // [kFC]
     int32_t *cs, *cu;                                // [kCC]
+    int32_t *pre;                                    // [8 * kWave] staged frontier rows
 };
 
 __host__ __device__ constexpr size_t lds_bytes(int mw, int sc) {
-    return (size_t)mw * (3 * 8 + 7 * 4 + kLB * 4) + (size_t)sc * 16 + kFC * 8 + kCC * 8 + 64;
+    return (size_t)mw * (3 * 8 + 7 * 4 + kLB * 4) + (size_t)sc * 16 + kFC * 8 + kCC * 8 + 8 * 64 * 4 + 64;
 }
 
 template <int WPL>
@@ -171,7 +172,7 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
         }
         r += __popcll(mk);
     }
-    bool merged = false;
+    bool merged = false, staged = false;
     int32_t pf[PW][kPF];
 #pragma unroll
     for (int k = 0; k < PW; k++)
@@ -210,18 +211,30 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
             const int32_t idx = i0 + lane;
             const bool ok = idx < r;
             int32_t v_l = 0;
-            if (ok) {
-                if (r <= kFC) v_l = merged ? L.fr1[idx] : L.fr0[idx];
-                else v_l = merged ? fbuf[n + idx] : fbuf[idx];
-            }
             int2 e_l = make_int2(1, 1), d_l = make_int2(1, 1);
             int32_t ia_l = 0, ie_l = 0, rs_l = 0;
-            if (ok) {
-                e_l = est2[v_l];
-                d_l = dur2[v_l];
-                ia_l = tr[v_l].ia;
-                rs_l = tr[v_l].rs;
-                ie_l = wg_load(&tr[v_l].iev);
+            if (staged) {
+                // rows loaded during the previous candidate round trip
+                if (ok) {
+                    v_l = L.pre[idx];
+                    e_l = make_int2(L.pre[64 + idx], L.pre[128 + idx]);
+                    d_l = make_int2(L.pre[192 + idx], L.pre[256 + idx]);
+                    ia_l = L.pre[320 + idx];
+                    rs_l = L.pre[384 + idx];
+                    ie_l = L.pre[448 + idx];
+                }
+            } else {
+                if (ok) {
+                    if (r <= kFC) v_l = merged ? L.fr1[idx] : L.fr0[idx];
+                    else v_l = merged ? fbuf[n + idx] : fbuf[idx];
+                }
+                if (ok) {
+                    e_l = est2[v_l];
+                    d_l = dur2[v_l];
+                    ia_l = tr[v_l].ia;
+                    rs_l = tr[v_l].rs;
+                    ie_l = wg_load(&tr[v_l].iev);
+                }
             }
             if (ballot(ok && (d_l.x < 1 || d_l.x > INSP_MAX_TICK || d_l.y < 1 || d_l.y > INSP_MAX_TICK)))
                 status |= ST_DUR;
@@ -273,6 +286,7 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
                     slots[p].x = xw;
                     slots[p].rs = rs;
                     tr[v].qpos = p;
+                    tr[v].seq = seq;
                     const uint64_t a0 = key_of(kw, slot0), a1 = key_of(kw, 1);
                     if (blk < SC) {
                         if (pos == 0) {
@@ -403,7 +417,7 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
                         tr[(int32_t)(mx >> 42)].qpos = p;
                     }
                 }
-                if (lane == 0) tr[v].qpos = -1;
+                if (lane == 0) tr[v].qpos = -2;  // running, then done
                 len--;
                 const bool freed = (len & 63) == 0;
                 int32_t newlast = last;
@@ -575,71 +589,202 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
         wg_fence();
         __syncthreads();
         PCLK(5);
-        // successors left with one unfinished predecessor raise its IE; with a
-        // single completion the atomic's result already names that predecessor
+        // successors left with one unfinished predecessor raise its IE.  The
+        // predecessor is named by the atomic's result (rem 1, remaining sum);
+        // that result is final unless a later completion of the same event
+        // made the successor ready, in which case it is not a candidate.
         const bool single = ndone == 1;
-        for (int32_t i0 = 0; i0 < nc; i0 += kWave) {
-            const int32_t i = i0 + lane;
-            if (i < nc) {
-                const int32_t s = i < kCC ? L.cs[i] : wg_load(&fbuf[2 * n + i]);
-                int32_t u = -1;
-                if (single && i < kCC) {
-                    u = L.cu[i];
-                } else {
-                    const uint64_t wd = wg_load(&tr[s].word);
-                    if ((wd >> 43) == 1) u = (int32_t)(wd & M43);
+        merged = false;
+        staged = false;
+        if (nc <= kWave && r <= kFC) {
+            // one round trip: candidate records and the next push's frontier rows
+            const bool hc = lane < nc;
+            const int32_t s = hc ? L.cs[lane] : 0;
+            int32_t u = hc ? L.cu[lane] : -1;
+            if (hc && !single)
+                for (int32_t k = 0; k < r; k++)
+                    if (L.fr0[k] == s) {
+                        u = -1;
+                        break;
+                    }
+            staged = r <= kWave;
+            const bool hf = staged && lane < r;
+            const int32_t fv = hf ? L.fr0[lane] : 0;
+            int32_t tu = 0, ts = 0, iu = 0, qu = -1, au = 0, sq = 0;
+            if (u >= 0) {
+                tu = tr[u].tau;
+                ts = tr[s].tau;
+                iu = wg_load(&tr[u].iev);
+                qu = wg_load(&tr[u].qpos);
+                au = tr[u].ia;
+                sq = wg_load(&tr[u].seq);
+            }
+            int2 fe = make_int2(1, 1), fd = make_int2(1, 1);
+            int32_t fa = 0, frs = 0, fie = 0;
+            if (hf) {
+                fe = est2[fv];
+                fd = dur2[fv];
+                fa = tr[fv].ia;
+                frs = tr[fv].rs;
+                fie = wg_load(&tr[fv].iev);
+            }
+            const bool cond = u >= 0 && (int64_t)tu + ts <= (int64_t)U;
+            // several successors may name the same predecessor: the first lane
+            // applies all of its increments
+            int32_t mult = 0;
+            bool lead = cond;
+            for (int32_t j = 0; j < nc; j++) {
+                const int32_t uj = read_lane(u, j);
+                const int32_t cj = read_lane(cond ? 1 : 0, j);
+                if (cj && cond && uj == u) {
+                    mult++;
+                    if (j < lane) lead = false;
                 }
-                if (u >= 0) {
-                    const int32_t tu = tr[u].tau, ts = tr[s].tau;
-                    const int32_t pu = wg_load(&tr[u].qpos);
-                    if ((int64_t)tu + ts <= (int64_t)U) {
-                        wg_fetch_add(&tr[u].iev, 1);
-                        if (pu >= 0) {
-                            const uint64_t nk = wg_fetch_add(&slots[pu].k, 1ull << 21) + (1ull << 21);
-                            const int32_t bk = pu >> 6;
-                            if (bk < SC) {
-                                atomicMax(&L.sum[2 * bk], (unsigned long long)key_of(nk, slot0));
-                                atomicMax(&L.sum[2 * bk + 1], (unsigned long long)key_of(nk, 1));
-                            } else {
-                                wg_fetch_max(&sums[2 * bk], (unsigned long long)key_of(nk, slot0));
-                                wg_fetch_max(&sums[2 * bk + 1], (unsigned long long)key_of(nk, 1));
-                            }
-                        }
+            }
+            if (lead) {
+                const int32_t nie = iu + mult;
+                tr[u].iev = nie;
+                if (qu >= 0) {
+                    const uint64_t nk = (uint64_t)au << 42 | (uint64_t)nie << 21 | (M21 - (uint64_t)sq);
+                    slots[qu].k = nk;
+                    const int32_t bk = qu >> 6;
+                    if (bk < SC) {
+                        atomicMax(&L.sum[2 * bk], (unsigned long long)key_of(nk, slot0));
+                        atomicMax(&L.sum[2 * bk + 1], (unsigned long long)key_of(nk, 1));
+                    } else {
+                        wg_fetch_max(&sums[2 * bk], (unsigned long long)key_of(nk, slot0));
+                        wg_fetch_max(&sums[2 * bk + 1], (unsigned long long)key_of(nk, 1));
                     }
                 }
             }
-        }
-        PCLK(6);
-        // several completions: merge their ascending runs by rank
-        merged = false;
-        if (nseg > 1) {
-            const bool in_lds = r <= kFC;
-            for (int32_t i0 = 0; i0 < r; i0 += kWave) {
-                const int32_t i = i0 + lane;
-                if (i < r) {
-                    const int32_t x = in_lds ? L.fr0[i] : fbuf[i];
+            // a raised predecessor that became ready in this very event: its
+            // staged row must carry the new IE
+            uint64_t lm = ballot(lead && qu == -1);
+            while (lm) {
+                const int l = (int)__builtin_ctzll(lm);
+                lm &= lm - 1;
+                const int32_t uu = read_lane(u, l), kk = read_lane(mult, l);
+                const uint64_t fm = ballot(hf && fv == uu);
+                if (fm && lane == (int)__builtin_ctzll(fm)) fie += kk;
+            }
+            int32_t pos = lane;
+            if (nseg > 1 && hf) {
+                // rank of this entry among the ascending runs of the completions
+                int32_t rank = 0, lo = 0;
+                for (int32_t g = 0; g < nseg; g++) {
+                    const int32_t hi = L.seg[g];
+                    if (lane >= lo && lane < hi) {
+                        rank += lane - lo;
+                    } else {
+                        int32_t a = lo, b = hi;
+                        while (a < b) {
+                            const int32_t mid = (a + b) >> 1;
+                            if (L.fr0[mid] < fv) a = mid + 1;
+                            else b = mid;
+                        }
+                        rank += a - lo;
+                    }
+                    lo = hi;
+                }
+                pos = rank;
+            }
+            if (!staged && nseg > 1) {
+                // frontier too large to stage: merge ids in LDS, rows loaded at push
+                for (int32_t i = lane; i < r; i += kWave) {
+                    const int32_t x = L.fr0[i];
                     int32_t rank = 0, lo = 0;
                     for (int32_t g = 0; g < nseg; g++) {
                         const int32_t hi = L.seg[g];
                         if (i >= lo && i < hi) {
                             rank += i - lo;
                         } else {
-                            int32_t a = lo, b = hi;  // count of run g below x
+                            int32_t a = lo, b = hi;
                             while (a < b) {
                                 const int32_t mid = (a + b) >> 1;
-                                const int32_t y = in_lds ? L.fr0[mid] : fbuf[mid];
-                                if (y < x) a = mid + 1;
+                                if (L.fr0[mid] < x) a = mid + 1;
                                 else b = mid;
                             }
                             rank += a - lo;
                         }
                         lo = hi;
                     }
-                    if (in_lds) L.fr1[rank] = x;
-                    else fbuf[n + rank] = x;
+                    L.fr1[rank] = x;
+                }
+                merged = true;
+            }
+            if (hf) {
+                L.pre[pos] = fv;
+                L.pre[64 + pos] = fe.x;
+                L.pre[128 + pos] = fe.y;
+                L.pre[192 + pos] = fd.x;
+                L.pre[256 + pos] = fd.y;
+                L.pre[320 + pos] = fa;
+                L.pre[384 + pos] = frs;
+                L.pre[448 + pos] = fie;
+            }
+        } else {
+            for (int32_t i0 = 0; i0 < nc; i0 += kWave) {
+                const int32_t i = i0 + lane;
+                if (i < nc) {
+                    const int32_t s = i < kCC ? L.cs[i] : wg_load(&fbuf[2 * n + i]);
+                    int32_t u = -1;
+                    if (single && i < kCC) {
+                        u = L.cu[i];
+                    } else {
+                        const uint64_t wd = wg_load(&tr[s].word);
+                        if ((wd >> 43) == 1) u = (int32_t)(wd & M43);
+                    }
+                    if (u >= 0) {
+                        const int32_t tu = tr[u].tau, ts = tr[s].tau;
+                        const int32_t pu = wg_load(&tr[u].qpos);
+                        if ((int64_t)tu + ts <= (int64_t)U) {
+                            wg_fetch_add(&tr[u].iev, 1);
+                            if (pu >= 0) {
+                                const uint64_t nk = wg_fetch_add(&slots[pu].k, 1ull << 21) + (1ull << 21);
+                                const int32_t bk = pu >> 6;
+                                if (bk < SC) {
+                                    atomicMax(&L.sum[2 * bk], (unsigned long long)key_of(nk, slot0));
+                                    atomicMax(&L.sum[2 * bk + 1], (unsigned long long)key_of(nk, 1));
+                                } else {
+                                    wg_fetch_max(&sums[2 * bk], (unsigned long long)key_of(nk, slot0));
+                                    wg_fetch_max(&sums[2 * bk + 1], (unsigned long long)key_of(nk, 1));
+                                }
+                            }
+                        }
+                    }
                 }
             }
-            merged = true;
+            wg_fence();
+            // several completions: merge their ascending runs by rank
+            if (nseg > 1) {
+                const bool in_lds = r <= kFC;
+                for (int32_t i0 = 0; i0 < r; i0 += kWave) {
+                    const int32_t i = i0 + lane;
+                    if (i < r) {
+                        const int32_t x = in_lds ? L.fr0[i] : fbuf[i];
+                        int32_t rank = 0, lo = 0;
+                        for (int32_t g = 0; g < nseg; g++) {
+                            const int32_t hi = L.seg[g];
+                            if (i >= lo && i < hi) {
+                                rank += i - lo;
+                            } else {
+                                int32_t a = lo, b = hi;  // count of run g below x
+                                while (a < b) {
+                                    const int32_t mid = (a + b) >> 1;
+                                    const int32_t y = in_lds ? L.fr0[mid] : fbuf[mid];
+                                    if (y < x) a = mid + 1;
+                                    else b = mid;
+                                }
+                                rank += a - lo;
+                            }
+                            lo = hi;
+                        }
+                        if (in_lds) L.fr1[rank] = x;
+                        else fbuf[n + rank] = x;
+                    }
+                }
+                merged = true;
+            }
         }
         PCLK(7);
         wg_fence();
@@ -680,6 +825,7 @@ __global__ __launch_bounds__(64) void k_sim(SimArgs A) {
     L.fr1 = L.fr0 + kFC;
     L.cs = L.fr1 + kFC;
     L.cu = L.cs + kCC;
+    L.pre = L.cu + kCC;
     const int lane = lane_id();
     for (;;) {
         int32_t got = 0;
