@@ -13,6 +13,7 @@
 // W3 [256,2], b3 [2].
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -283,6 +284,131 @@ __global__ void k_shadow(const float *p, uint16_t *w1, uint16_t *w2, uint16_t *w
     else if (i >= kOffW3 && i < kOffB3) w3[i - kOffW3] = f2bf(p[i]);
 }
 
+// Fused inference: y = W3^T relu(W2^T relu(W1^T x + b1) + b2) + b3 and the
+// integer estimates, for many rows.  One 256-thread block (4 waves) is
+// persistent over 64-row tiles; wave w owns hidden columns [64 w, 64 w + 64)
+// and keeps its W1 and W2 MFMA B-fragments in registers for the whole run.
+// Per tile: layer 1 (K = 32) from x straight into A-fragments, bf16 hidden
+// activations through LDS, layer 2 (K = 256) from LDS A-fragments, then the
+// two outputs as per-wave partial dot products summed in a fixed order.
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+constexpr int kRT = 64, kH1Row = kHid + 8;
+
+__global__ __launch_bounds__(256) void k_infer(const float *x, int64_t rows, const uint16_t *W1, const float *b1,
+                                               const uint16_t *W2, const float *b2, const uint16_t *W3,
+                                               const float *b3, float *Y, int32_t *est) {
+    __shared__ __attribute__((aligned(16))) uint16_t H1s[kRT * kH1Row];
+    __shared__ float yp[4][kRT][2];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int wn = wv * 64, lc = lane & 15, lk = (lane >> 4) * 8;
+    bf16x8 w1f[4], w2f[8][4];
+    float bias1[4], bias2[4], w30[4], w31[4];
+#pragma unroll
+    for (int ct = 0; ct < 4; ct++) {
+        const int n = wn + ct * 16 + lc;
+        u16x8 t;
+#pragma unroll
+        for (int i = 0; i < 8; i++) t[i] = W1[(lk + i) * kHid + n];
+        w1f[ct] = __builtin_bit_cast(bf16x8, t);
+#pragma unroll
+        for (int ks = 0; ks < 8; ks++) {
+#pragma unroll
+            for (int i = 0; i < 8; i++) t[i] = W2[(ks * 32 + lk + i) * kHid + n];
+            w2f[ks][ct] = __builtin_bit_cast(bf16x8, t);
+        }
+        bias1[ct] = b1[n];
+        bias2[ct] = b2[n];
+        w30[ct] = bf2f(W3[n * 2]);
+        w31[ct] = bf2f(W3[n * 2 + 1]);
+    }
+    const float b30 = b3[0], b31 = b3[1];
+    const int64_t tiles = (rows + kRT - 1) / kRT;
+    for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+        const int64_t r0 = tile * kRT;
+        // layer 1: A-fragment row lc of each 16-row tile, K = lk .. lk+7
+#pragma unroll
+        for (int rt = 0; rt < 4; rt++) {
+            const int64_t r = r0 + rt * 16 + lc;
+            u16x8 t;
+            if (r < rows) {
+                const float4 a = *reinterpret_cast<const float4 *>(x + r * kIn + lk);
+                const float4 b = *reinterpret_cast<const float4 *>(x + r * kIn + lk + 4);
+                t[0] = f2bf(a.x); t[1] = f2bf(a.y); t[2] = f2bf(a.z); t[3] = f2bf(a.w);
+                t[4] = f2bf(b.x); t[5] = f2bf(b.y); t[6] = f2bf(b.z); t[7] = f2bf(b.w);
+            } else {
+#pragma unroll
+                for (int i = 0; i < 8; i++) t[i] = 0;
+            }
+            const bf16x8 af = __builtin_bit_cast(bf16x8, t);
+#pragma unroll
+            for (int ct = 0; ct < 4; ct++) {
+                f32x4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, w1f[ct], f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+#pragma unroll
+                for (int i = 0; i < 4; i++) {
+                    const int row = rt * 16 + (lane >> 4) * 4 + i;
+                    H1s[row * kH1Row + wn + ct * 16 + lc] = f2bf(fmaxf(acc[i] + bias1[ct], 0.f));
+                }
+            }
+        }
+        __syncthreads();
+        // layer 2 and the output partials
+        float p0[4][4], p1[4][4];
+#pragma unroll
+        for (int rt = 0; rt < 4; rt++) {
+            f32x4 acc[4];
+#pragma unroll
+            for (int ct = 0; ct < 4; ct++) acc[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int ks = 0; ks < 8; ks++) {
+                const bf16x8 af = *reinterpret_cast<const bf16x8 *>(&H1s[(rt * 16 + lc) * kH1Row + ks * 32 + lk]);
+#pragma unroll
+                for (int ct = 0; ct < 4; ct++)
+                    acc[ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, w2f[ks][ct], acc[ct], 0, 0, 0);
+            }
+#pragma unroll
+            for (int i = 0; i < 4; i++) {
+                float s0 = 0.f, s1 = 0.f;
+#pragma unroll
+                for (int ct = 0; ct < 4; ct++) {
+                    const float h = bf2f(f2bf(fmaxf(acc[ct][i] + bias2[ct], 0.f)));
+                    s0 += h * w30[ct];
+                    s1 += h * w31[ct];
+                }
+                p0[rt][i] = s0;
+                p1[rt][i] = s1;
+            }
+        }
+        // sum over the 16 lanes sharing a row (different columns)
+#pragma unroll
+        for (int rt = 0; rt < 4; rt++)
+#pragma unroll
+            for (int i = 0; i < 4; i++) {
+                float s0 = p0[rt][i], s1 = p1[rt][i];
+#pragma unroll
+                for (int off = 1; off < 16; off <<= 1) {
+                    s0 += __shfl_xor(s0, off, 64);
+                    s1 += __shfl_xor(s1, off, 64);
+                }
+                if (lc == 0) {
+                    const int row = rt * 16 + (lane >> 4) * 4 + i;
+                    yp[wv][row][0] = s0;
+                    yp[wv][row][1] = s1;
+                }
+            }
+        __syncthreads();
+        if (tid < kRT * 2) {
+            const int row = tid >> 1, c = tid & 1;
+            const int64_t r = r0 + row;
+            if (r < rows) {
+                const float y = (((yp[0][row][c] + yp[1][row][c]) + yp[2][row][c]) + yp[3][row][c]) + (c ? b31 : b30);
+                if (Y) Y[2 * r + c] = y;
+                if (est) est[2 * r + c] = (int32_t)fminf(fmaxf(rintf(expf(y)), 1.f), (float)(1 << 20));
+            }
+        }
+        __syncthreads();
+    }
+}
+
 static unsigned blocks(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
 static void gemm(hipStream_t st, const GemmArgs &g) {
@@ -434,18 +560,19 @@ extern "C" int insp_mlp_train_step(insp_mlp *m, const float *x, const float *t, 
 
 extern "C" int insp_mlp_predict(insp_mlp *m, const float *x, int64_t n, float *y, int32_t *est, void *stream) {
     if (!m || (n > 0 && (!x || (!y && !est))) || n < 0) return set_error(INSP_E_INVAL, "bad argument");
+    if (n == 0) return INSP_OK;
     hipStream_t st = (hipStream_t)stream;
-    const int64_t chunk = 1 << 16;
-    int rc;
-    if ((rc = mlp_reserve(m, std::min<int64_t>(std::max<int64_t>(n, 1), chunk)))) return rc;
-    for (int64_t r0 = 0; r0 < n; r0 += chunk) {
-        const int64_t rows = std::min(chunk, n - r0);
-        mlp_forward(m, x + r0 * kIn, rows, st);
-        hipLaunchKernelGGL(k_out, dim3(blocks(rows, 4)), dim3(256), 0, st, m->h2.as<uint16_t>(),
-                           m->w3.as<uint16_t>(), m->p.as<float>() + kOffB3, rows, y ? y + r0 * kOut : nullptr,
-                           (const float *)nullptr, (float *)nullptr, (uint16_t *)nullptr,
-                           est ? est + r0 * kOut : nullptr);
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) == hipSuccess) cus = prop.multiProcessorCount;
     }
+    const int64_t tiles = (n + kRT - 1) / kRT;
+    const unsigned grid = (unsigned)std::min<int64_t>(tiles, (int64_t)cus * 2);
+    ProfScope ps(st, "mlp_infer");
+    hipLaunchKernelGGL(k_infer, dim3(grid), dim3(256), 0, st, x, n, m->w1.as<uint16_t>(), m->p.as<float>() + kOffB1,
+                       m->w2.as<uint16_t>(), m->p.as<float>() + kOffB2, m->w3.as<uint16_t>(),
+                       m->p.as<float>() + kOffB3, y, est);
     INSP_HIP(hipGetLastError());
     return INSP_OK;
 }

@@ -63,7 +63,7 @@ __device__ __forceinline__ uint64_t key_of(uint64_t k, int ord) {
 struct SimArgs {
     const DagDesc *desc;
     const int32_t *order;
-    int32_t count, max_w, sum_cap, policy;
+    int32_t count, max_w, sum_cap, policy, lb;
     const int32_t *col;
     const int32_t *dur, *est;
     int64_t base;
@@ -86,7 +86,6 @@ struct SimArgs {
 };
 
 // LDS-resident state of the DAG a work-group is simulating.
-constexpr int kLB = 16;   // block-list slots per worker kept in LDS (more spill to global)
 constexpr int kPF = 8;    // successors of a running task prefetched into registers at its pop
 constexpr int kFC = 256;  // frontier slots in LDS (larger frontiers use global memory)
 constexpr int kCC = 128;  // candidate slots in LDS
@@ -94,15 +93,15 @@ constexpr int kCC = 128;  // candidate slots in LDS
 struct Lds {
     int64_t *fin, *expend, *qest;                    // [MW]
     int32_t *run, *len, *nb, *last, *seg, *rsr, *dgr; // [MW]
-    int32_t *blist;                                  // [MW * kLB]
+    int32_t *blist;                                  // [MW * lb] first block ids of each worker
     unsigned long long *sum;                         // [2 * sum_cap] block max keys
     int32_t *fr0, *fr1;                              // [kFC]
     int32_t *cs, *cu;                                // [kCC]
     int32_t *pre;                                    // [8 * kWave] staged frontier rows
 };
 
-__host__ __device__ constexpr size_t lds_bytes(int mw, int sc) {
-    return (size_t)mw * (3 * 8 + 7 * 4 + kLB * 4) + (size_t)sc * 16 + kFC * 8 + kCC * 8 + 8 * 64 * 4 + 64;
+__host__ __device__ constexpr size_t lds_bytes(int mw, int sc, int lb) {
+    return (size_t)mw * (3 * 8 + 7 * 4 + (size_t)lb * 4) + (size_t)sc * 16 + kFC * 8 + kCC * 8 + 8 * 64 * 4 + 64;
 }
 
 template <int WPL>
@@ -132,6 +131,7 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
     int32_t *freeb = A.paux + A.freeb_base + d.blk_off;
     const int32_t maxb = d.maxb;
     const int32_t SC = A.sum_cap;
+    const int32_t kLB = A.lb;
     const int32_t U = A.dag_u[d.id];
 
     // regulator parameters (defaults: the paper names them, prints no values)
@@ -821,7 +821,7 @@ __global__ __launch_bounds__(64) void k_sim(SimArgs A) {
     L.rsr = l32 + 5 * MW;
     L.dgr = l32 + 6 * MW;
     L.blist = l32 + 7 * MW;
-    L.fr0 = L.blist + MW * kLB;
+    L.fr0 = L.blist + MW * A.lb;
     L.fr1 = L.fr0 + kFC;
     L.cs = L.fr1 + kFC;
     L.cu = L.cs + kCC;
@@ -884,17 +884,30 @@ int launch_sim(insp_dag *dag, Workspace *ws, const insp_params &p, const int32_t
     A.max_events = p.max_events;
     // block maxima in LDS: all of a single DAG's blocks up to 64 KB, or the
     // low block ids of each DAG of a batch
-    A.sum_cap = (int32_t)std::min<int64_t>(ws->max_nblk, ws->count == 1 ? 4096 : sum_cap);
-    const size_t lds = lds_bytes(ws->max_w, A.sum_cap);
+    // block maxima and block lists in LDS: generous for a single DAG (one
+    // work-group has the CU), a few blocks per DAG for a batch
+    const bool one = ws->count == 1;
+    A.sum_cap = (int32_t)std::min<int64_t>(ws->max_nblk, one ? 4096 : sum_cap);
+    int64_t lb = 16;
+    if (one) {
+        const int64_t budget = 140 * 1024 - (int64_t)lds_bytes(ws->max_w, A.sum_cap, 0);
+        lb = std::max<int64_t>(16, budget / (4 * std::max(1, ws->max_w)));
+    }
+    A.lb = (int32_t)std::min<int64_t>(ws->max_nblk, lb);
+    const size_t lds = lds_bytes(ws->max_w, A.sum_cap, A.lb);
     grid = std::max(1, std::min(grid, ws->count));
     hipLaunchKernelGGL(k_counter_reset, dim3(1), dim3(64), 0, st, A.counter);
     ProfScope ps(st, "sim");
-    if (ws->max_w <= 64)
+    if (ws->max_w <= 64) {
+        if (lds > 65536) INSP_HIP(hipFuncSetAttribute((const void *)&k_sim<1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         hipLaunchKernelGGL(k_sim<1>, dim3(grid), dim3(64), lds, st, A);
-    else if (ws->max_w <= 128)
+    } else if (ws->max_w <= 128) {
+        if (lds > 65536) INSP_HIP(hipFuncSetAttribute((const void *)&k_sim<2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         hipLaunchKernelGGL(k_sim<2>, dim3(grid), dim3(64), lds, st, A);
-    else
+    } else {
+        if (lds > 65536) INSP_HIP(hipFuncSetAttribute((const void *)&k_sim<16>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         hipLaunchKernelGGL(k_sim<16>, dim3(grid), dim3(64), lds, st, A);
+    }
     INSP_HIP(hipGetLastError());
     return INSP_OK;
 }

@@ -253,3 +253,65 @@ def test_batch_graph_replays_match_eager(insp):
     r = oracle.schedule_batch(b)
     assert np.array_equal(ref["makespan"].numpy(), r["makespan"])
     dag.free()
+
+
+def _wide(n, seed):
+    # two layers: the first half is ready at once, so queues grow to
+    # thousands of entries per worker (block lists and block maxima spill
+    # out of LDS)
+    from paper_2404_03226_amd.synth import layered_dag, Stream
+    rp, col = layered_dag(seed, 0, n, 2, 1, 3)
+    st = Stream(seed, 5)
+    dur = st.randint(np.arange(2 * n).reshape(n, 2), 1, 40).astype(np.int32)
+    return NS(n=n, row_ptr=rp, col=col, dur=dur, est=dur.copy(), n_cpu=2, n_gpu=1, m=int(col.size),
+              type=np.zeros(n, np.int32), name=f"wide-{n}")
+
+
+def _hubs(seed):
+    # hub tasks whose successors each have exactly two hub predecessors: one
+    # completion leaves hundreds of successors with one unfinished predecessor
+    rng = np.random.default_rng(seed)
+    H, S = 8, 600
+    n = H + S
+    edges = []
+    for s in range(S):
+        a, b = rng.choice(H, 2, replace=False)
+        edges += [(a, H + s), (b, H + s)]
+    edges.sort()
+    rp = np.zeros(n + 1, np.int64)
+    for a, _ in edges:
+        rp[a + 1] += 1
+    rp = np.cumsum(rp).astype(np.int32)
+    col = np.array([b for _, b in edges], np.int32)
+    dur = rng.integers(1, 30, (n, 2)).astype(np.int32)
+    return NS(n=n, row_ptr=rp, col=col, dur=dur, est=dur.copy(), n_cpu=3, n_gpu=2, m=len(edges), name="hubs",
+              type=np.zeros(n, np.int32))
+
+
+def test_queue_spill_paths_single(insp):
+    for seed in (1, 2):
+        w = _wide(12000, seed)
+        say("wide single", seed)
+        assert_same(run_gpu(insp, w), oracle.schedule(w, variant=oracle.HEAP), "wide")
+
+
+def test_queue_spill_paths_batch_small_lds(insp):
+    ws = [_wide(6000 + 1000 * i, 10 + i) for i in range(3)] + [_hubs(3)] + synth.cfg3(select=[4, 44])
+    b = synth.concat(ws)
+    say("spill batch")
+    dag, dur, est = insp.batch_to_device(b)
+    r = oracle.schedule_batch(b)
+    for key in ("waves=1,grid=6,lds_blocks=4", "waves=1,grid=2,lds_blocks=0"):
+        o = insp.schedule_batch(dag, [(w.n_cpu, w.n_gpu) for w in ws], dur, est, tune_key=key)
+        insp.sync_status(dag)
+        for k in ("worker", "start", "finish", "ie_at_pop", "mode_at_pop"):
+            assert np.array_equal(o[k].cpu().numpy(), r[k]), (key, k)
+    dag.free()
+
+
+def test_many_candidates_per_event(insp):
+    for seed in range(3):
+        w = _hubs(seed)
+        say("hubs", seed)
+        for pol in ("inspirit", "efi"):
+            assert_same(run_gpu(insp, w, pol), oracle.schedule(w, policy=pol), f"hubs {seed} {pol}")
