@@ -75,31 +75,17 @@ __global__ __launch_bounds__(kAttrThreads) void k_attr_a(AttrArgs a) {
         if (e0 < 1 || e0 > INSP_MAX_TICK || e1 < 1 || e1 > INSP_MAX_TICK) bad = 1;
         tv = (uint32_t)(g ? e1 : e0);
         if (a.unit_time == 0) {
-            const int32_t e0 = r[lv], z = r[lv + 1];
+            int32_t e = r[lv], z = r[lv + 1];
             int32_t cnt1 = 0, lo = 0x7fffffff, hi = 0;
-            // four successors per step: ids first, then their gathers, so that
-            // eight independent loads are in flight
-            for (int32_t e = e0; e < z; e += 4) {
-                int32_t sv[4], rs[4], ts[4];
-#pragma unroll
-                for (int q = 0; q < 4; q++) sv[q] = e + q < z ? c[e + q] : -1;
-#pragma unroll
-                for (int q = 0; q < 4; q++) {
-                    rs[q] = 0;
-                    ts[q] = 0;
-                    if (sv[q] >= 0) {
-                        rs[q] = a.rem ? a.rem[ub + sv[q]] : (int32_t)(a.word0[d.toff + sv[q]] >> 43);
-                        ts[q] = a.est[2 * (ub + sv[q]) + g];
-                    }
+            for (; e < z; e++) {
+                int32_t s = c[e];
+                int32_t rs = a.rem ? a.rem[ub + s] : (int32_t)(a.word0[d.toff + s] >> 43);
+                if (rs == 1) {
+                    int32_t x = (int32_t)tv + a.est[2 * (ub + s) + g];
+                    cnt1++;
+                    lo = min(lo, x);
+                    hi = max(hi, x);
                 }
-#pragma unroll
-                for (int q = 0; q < 4; q++)
-                    if (sv[q] >= 0 && rs[q] == 1) {
-                        const int32_t x = (int32_t)tv + ts[q];
-                        cnt1++;
-                        lo = min(lo, x);
-                        hi = max(hi, x);
-                    }
             }
             if (cnt1 > 0) {
                 int jlo = ceil_log2(lo);
@@ -173,22 +159,10 @@ __global__ __launch_bounds__(kAttrThreads) void k_attr_b(AttrArgs a, AttrOut o) 
     const int32_t tv = a.est[2 * (ub + lv) + g];
     const int32_t e0 = r[lv], z = r[lv + 1];
     int32_t ie = 0;
-    for (int32_t e = e0; e < z; e += 4) {
-        int32_t sv[4], rs[4], ts[4];
-#pragma unroll
-        for (int q = 0; q < 4; q++) sv[q] = e + q < z ? c[e + q] : -1;
-#pragma unroll
-        for (int q = 0; q < 4; q++) {
-            rs[q] = 0;
-            ts[q] = 0;
-            if (sv[q] >= 0) {
-                rs[q] = a.rem ? a.rem[ub + sv[q]] : (int32_t)(a.word0[d.toff + sv[q]] >> 43);
-                ts[q] = a.est[2 * (ub + sv[q]) + g];
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < 4; q++)
-            if (sv[q] >= 0 && rs[q] == 1 && (int64_t)tv + ts[q] <= U) ie++;
+    for (int32_t e = e0; e < z; e++) {
+        int32_t s = c[e];
+        int32_t rs = a.rem ? a.rem[ub + s] : (int32_t)(a.word0[d.toff + s] >> 43);
+        if (rs == 1 && (int64_t)tv + a.est[2 * (ub + s) + g] <= U) ie++;
     }
     if (o.ia_out) o.ia_out[ub + lv] = z - e0;
     if (o.ie_out) o.ie_out[ub + lv] = ie;
