@@ -144,6 +144,6 @@ int run_attributes(insp_dag *dag, Workspace *ws, const int32_t *est, int32_t uni
 int launch_sim(insp_dag *dag, Workspace *ws, const insp_params &p, const int32_t *dur, const int32_t *est,
                int32_t *worker, int64_t *start, int64_t *finish, int64_t *makespan, int32_t *ie_at_pop,
                int8_t *mode_at_pop, insp_trace_rec *trace, int32_t *n_events, int waves, int grid,
-               int sum_cap, hipStream_t st);
+               int sum_cap, int slot_cap, hipStream_t st);
 
 }  // namespace insp

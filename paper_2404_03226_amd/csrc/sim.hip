@@ -63,7 +63,7 @@ __device__ __forceinline__ uint64_t key_of(uint64_t k, int ord) {
 struct SimArgs {
     const DagDesc *desc;
     const int32_t *order;
-    int32_t count, max_w, sum_cap, policy, lb;
+    int32_t count, max_w, sum_cap, policy, lb, slot_cap;
     const int32_t *col;
     const int32_t *dur, *est;
     int64_t base;
@@ -98,10 +98,13 @@ struct Lds {
     int32_t *fr0, *fr1;                              // [kFC]
     int32_t *cs, *cu;                                // [kCC]
     int32_t *pre;                                    // [8 * kWave] staged frontier rows
+    unsigned long long *sk, *sx;                     // [64 * slot_cap] queue slots of the low blocks
+    int32_t *srs;                                    // [64 * slot_cap]
 };
 
-__host__ __device__ constexpr size_t lds_bytes(int mw, int sc, int lb) {
-    return (size_t)mw * (3 * 8 + 7 * 4 + (size_t)lb * 4) + (size_t)sc * 16 + kFC * 8 + kCC * 8 + 8 * 64 * 4 + 64;
+__host__ __device__ constexpr size_t lds_bytes(int mw, int sc, int lb, int slc) {
+    return (size_t)mw * (3 * 8 + 7 * 4 + (size_t)lb * 4) + (size_t)sc * 16 + kFC * 8 + kCC * 8 + 8 * 64 * 4 +
+           (size_t)slc * 64 * 20 + 64;
 }
 
 template <int WPL>
@@ -132,6 +135,7 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
     const int32_t maxb = d.maxb;
     const int32_t SC = A.sum_cap;
     const int32_t kLB = A.lb;
+    const int32_t SLC = A.slot_cap;  // blocks [0, SLC) keep their slots in LDS
     const int32_t U = A.dag_u[d.id];
 
     // regulator parameters (defaults: the paper names them, prints no values)
@@ -282,9 +286,15 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
                 const uint64_t xw = (uint64_t)v << 42 | (uint64_t)(dk & M21) << 21 | (uint64_t)(ek & M21);
                 const int32_t rs = read_lane(rs_l, j);
                 if (lane == 0) {
-                    slots[p].k = kw;
-                    slots[p].x = xw;
-                    slots[p].rs = rs;
+                    if (blk < SLC) {
+                        L.sk[p] = kw;
+                        L.sx[p] = xw;
+                        L.srs[p] = rs;
+                    } else {
+                        slots[p].k = kw;
+                        slots[p].x = xw;
+                        slots[p].rs = rs;
+                    }
                     tr[v].qpos = p;
                     tr[v].seq = seq;
                     const uint64_t a0 = key_of(kw, slot0), a1 = key_of(kw, 1);
@@ -380,14 +390,26 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
                 uint64_t kw = 0, xw = 0, kl = 0, xl = 0;
                 int32_t rw = 0, rl = 0;
                 if (ok) {
-                    kw = wg_load(&slots[eb + lane].k);
-                    xw = wg_load(&slots[eb + lane].x);
-                    rw = wg_load(&slots[eb + lane].rs);
+                    if (bb < SLC) {
+                        kw = L.sk[eb + lane];
+                        xw = L.sx[eb + lane];
+                        rw = L.srs[eb + lane];
+                    } else {
+                        kw = wg_load(&slots[eb + lane].k);
+                        xw = wg_load(&slots[eb + lane].x);
+                        rw = wg_load(&slots[eb + lane].rs);
+                    }
                 }
                 if (okl) {
-                    kl = wg_load(&slots[el + lane].k);
-                    xl = wg_load(&slots[el + lane].x);
-                    rl = wg_load(&slots[el + lane].rs);
+                    if (last < SLC) {
+                        kl = L.sk[el + lane];
+                        xl = L.sx[el + lane];
+                        rl = L.srs[el + lane];
+                    } else {
+                        kl = wg_load(&slots[el + lane].k);
+                        xl = wg_load(&slots[el + lane].x);
+                        rl = wg_load(&slots[el + lane].rs);
+                    }
                 }
                 const uint64_t key = ok ? key_of(kw, ord) : 0;
                 const uint64_t km = wave_max_u64(key);
@@ -411,9 +433,15 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
                         mr = read_lane(rl, lastpos);
                     }
                     if (lane == 0) {
-                        slots[p].k = mk;
-                        slots[p].x = mx;
-                        slots[p].rs = mr;
+                        if (bb < SLC) {
+                            L.sk[p] = mk;
+                            L.sx[p] = mx;
+                            L.srs[p] = mr;
+                        } else {
+                            slots[p].k = mk;
+                            slots[p].x = mx;
+                            slots[p].rs = mr;
+                        }
                         tr[(int32_t)(mx >> 42)].qpos = p;
                     }
                 }
@@ -646,8 +674,9 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
                 tr[u].iev = nie;
                 if (qu >= 0) {
                     const uint64_t nk = (uint64_t)au << 42 | (uint64_t)nie << 21 | (M21 - (uint64_t)sq);
-                    slots[qu].k = nk;
                     const int32_t bk = qu >> 6;
+                    if (bk < SLC) L.sk[qu] = nk;
+                    else slots[qu].k = nk;
                     if (bk < SC) {
                         atomicMax(&L.sum[2 * bk], (unsigned long long)key_of(nk, slot0));
                         atomicMax(&L.sum[2 * bk + 1], (unsigned long long)key_of(nk, 1));
@@ -740,8 +769,10 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
                         if ((int64_t)tu + ts <= (int64_t)U) {
                             wg_fetch_add(&tr[u].iev, 1);
                             if (pu >= 0) {
-                                const uint64_t nk = wg_fetch_add(&slots[pu].k, 1ull << 21) + (1ull << 21);
                                 const int32_t bk = pu >> 6;
+                                const uint64_t nk = (bk < SLC ? (uint64_t)atomicAdd(&L.sk[pu], 1ull << 21)
+                                                              : (uint64_t)wg_fetch_add(&slots[pu].k, 1ull << 21)) +
+                                                    (1ull << 21);
                                 if (bk < SC) {
                                     atomicMax(&L.sum[2 * bk], (unsigned long long)key_of(nk, slot0));
                                     atomicMax(&L.sum[2 * bk + 1], (unsigned long long)key_of(nk, 1));
@@ -812,7 +843,9 @@ __global__ __launch_bounds__(64) void k_sim(SimArgs A) {
     L.expend = lds64 + MW;
     L.qest = lds64 + 2 * MW;
     L.sum = reinterpret_cast<unsigned long long *>(lds64 + 3 * MW);
-    int32_t *l32 = reinterpret_cast<int32_t *>(lds64 + 3 * MW + 2 * A.sum_cap);
+    L.sk = L.sum + 2 * A.sum_cap;
+    L.sx = L.sk + 64 * A.slot_cap;
+    int32_t *l32 = reinterpret_cast<int32_t *>(L.sx + 64 * A.slot_cap);
     L.run = l32;
     L.len = l32 + MW;
     L.nb = l32 + 2 * MW;
@@ -826,6 +859,7 @@ __global__ __launch_bounds__(64) void k_sim(SimArgs A) {
     L.cs = L.fr1 + kFC;
     L.cu = L.cs + kCC;
     L.pre = L.cu + kCC;
+    L.srs = L.pre + 8 * kWave;
     const int lane = lane_id();
     for (;;) {
         int32_t got = 0;
@@ -844,7 +878,7 @@ __global__ void k_counter_reset(int32_t *c) {
 int launch_sim(insp_dag *dag, Workspace *ws, const insp_params &p, const int32_t *dur, const int32_t *est,
                int32_t *worker, int64_t *start, int64_t *finish, int64_t *makespan, int32_t *ie_at_pop,
                int8_t *mode_at_pop, insp_trace_rec *trace, int32_t *n_events, int waves, int grid,
-               int sum_cap, hipStream_t st) {
+               int sum_cap, int slot_cap, hipStream_t st) {
     (void)waves;
     SimArgs A;
     memset(&A, 0, sizeof A);
@@ -884,17 +918,16 @@ int launch_sim(insp_dag *dag, Workspace *ws, const insp_params &p, const int32_t
     A.max_events = p.max_events;
     // block maxima in LDS: all of a single DAG's blocks up to 64 KB, or the
     // low block ids of each DAG of a batch
-    // block maxima and block lists in LDS: generous for a single DAG (one
-    // work-group has the CU), a few blocks per DAG for a batch
+    // LDS: block maxima, block lists and the slots of the low blocks --
+    // generous for a single DAG (one work-group owns the CU), a few blocks
+    // per DAG for a batch (tunable)
     const bool one = ws->count == 1;
-    A.sum_cap = (int32_t)std::min<int64_t>(ws->max_nblk, one ? 4096 : sum_cap);
-    int64_t lb = 16;
-    if (one) {
-        const int64_t budget = 140 * 1024 - (int64_t)lds_bytes(ws->max_w, A.sum_cap, 0);
-        lb = std::max<int64_t>(16, budget / (4 * std::max(1, ws->max_w)));
-    }
-    A.lb = (int32_t)std::min<int64_t>(ws->max_nblk, lb);
-    const size_t lds = lds_bytes(ws->max_w, A.sum_cap, A.lb);
+    A.sum_cap = (int32_t)std::min<int64_t>(ws->max_nblk, one ? 2048 : sum_cap);
+    A.lb = (int32_t)std::min<int64_t>(ws->max_nblk, one ? 64 : 16);
+    int64_t slc = slot_cap;
+    if (one) slc = (140 * 1024 - (int64_t)lds_bytes(ws->max_w, A.sum_cap, A.lb, 0)) / (64 * 20);
+    A.slot_cap = (int32_t)std::max<int64_t>(0, std::min<int64_t>(ws->max_nblk, slc));
+    const size_t lds = lds_bytes(ws->max_w, A.sum_cap, A.lb, A.slot_cap);
     grid = std::max(1, std::min(grid, ws->count));
     hipLaunchKernelGGL(k_counter_reset, dim3(1), dim3(64), 0, st, A.counter);
     ProfScope ps(st, "sim");
@@ -960,16 +993,17 @@ extern "C" int insp_schedule(const insp_dag *cdag, int32_t index, const insp_wor
     if ((rc = get_workspace(dag, index, 1, workers, true, &ws))) return rc;
     if ((rc = run_attributes(dag, ws, est, params->unit_time, nullptr, nullptr, nullptr, true, st))) return rc;
     return launch_sim(dag, ws, *params, dur, est, worker, start, finish, makespan, ie_at_pop, mode_at_pop, trace,
-                      n_events, 1, 1, 4096, st);
+                      n_events, 1, 1, 4096, 0, st);
 }
 
-static void parse_tune(const char *key, int *waves, int *grid, int *sum_cap) {
+static void parse_tune(const char *key, int *waves, int *grid, int *sum_cap, int *slot_cap) {
     if (!key) return;
     std::string s(key);
-    size_t a = s.find("waves="), b = s.find("grid="), c = s.find("lds_blocks=");
+    size_t a = s.find("waves="), b = s.find("grid="), c = s.find("lds_blocks="), d = s.find("lds_slots=");
     if (a != std::string::npos) *waves = atoi(s.c_str() + a + 6);
     if (b != std::string::npos) *grid = atoi(s.c_str() + b + 5);
     if (c != std::string::npos) *sum_cap = atoi(s.c_str() + c + 11);
+    if (d != std::string::npos) *slot_cap = atoi(s.c_str() + d + 10);
 }
 
 extern "C" int insp_schedule_batch(const insp_dag *cdag, const insp_workers *workers, const int32_t *dur,
@@ -986,13 +1020,14 @@ extern "C" int insp_schedule_batch(const insp_dag *cdag, const insp_workers *wor
     if ((rc = ensure_state(dag, st))) return rc;
     Workspace *ws;
     if ((rc = get_workspace(dag, 0, dag->B, workers, true, &ws))) return rc;
-    int waves = 1, grid = default_grid(dag->B), sum_cap = 512;
-    parse_tune(tune_key, &waves, &grid, &sum_cap);
-    if (grid < 1 || waves < 1 || sum_cap < 0 || sum_cap > 8192)
+    int waves = 1, grid = default_grid(dag->B), sum_cap = 256, slot_cap = 16;
+    parse_tune(tune_key, &waves, &grid, &sum_cap, &slot_cap);
+    if (grid < 1 || waves < 1 || sum_cap < 0 || sum_cap > 8192 || slot_cap < 0 ||
+        lds_bytes(1, sum_cap, 16, slot_cap) > 150 * 1024)
         return set_error(INSP_E_INVAL, "bad tune key '%s'", tune_key);
     if ((rc = run_attributes(dag, ws, est, params->unit_time, nullptr, nullptr, nullptr, true, st))) return rc;
     return launch_sim(dag, ws, *params, dur, est, worker, start, finish, makespan, ie_at_pop, mode_at_pop, nullptr,
-                      nullptr, waves, grid, sum_cap, st);
+                      nullptr, waves, grid, sum_cap, slot_cap, st);
 }
 
 #ifdef INSP_PHASE_CLOCKS

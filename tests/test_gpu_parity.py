@@ -301,7 +301,8 @@ def test_queue_spill_paths_batch_small_lds(insp):
     say("spill batch")
     dag, dur, est = insp.batch_to_device(b)
     r = oracle.schedule_batch(b)
-    for key in ("waves=1,grid=6,lds_blocks=4", "waves=1,grid=2,lds_blocks=0"):
+    for key in ("waves=1,grid=6,lds_blocks=4,lds_slots=3", "waves=1,grid=2,lds_blocks=0,lds_slots=0",
+                "waves=1,grid=3,lds_blocks=64,lds_slots=40"):
         o = insp.schedule_batch(dag, [(w.n_cpu, w.n_gpu) for w in ws], dur, est, tune_key=key)
         insp.sync_status(dag)
         for k in ("worker", "start", "finish", "ie_at_pop", "mode_at_pop"):

@@ -63,6 +63,7 @@ def test_w2_fig1_analogue():
         assert r["start"].tolist() == g[pol]["start"]
         assert r["makespan"] == g[pol]["makespan"]
         check_schedule(w, r["worker"], r["start"], r["finish"], r["makespan"])
+    assert oracle.schedule(w)["unit_time"] == g["unit_time"]
     tr = oracle.schedule(w, policy="inspirit", trace=True)["trace"]
     assert tr["t"].tolist() == g["inspirit"]["trace_t"]
     assert tr["nready"].tolist() == g["inspirit"]["trace_nready"]
@@ -341,3 +342,37 @@ def test_generators_are_deterministic():
     assert np.array_equal(c.col, d.col)
     sizes = synth.cfg3_sizes()
     assert sizes.min() >= 200 and sizes.max() <= 20000 and sizes.size == 4096
+
+
+def _small(name):
+    g = gold("w4_w7_small.json")[name]
+    n = g["n"]
+    dur = g.get("dur", g.get("est"))
+    return g, wl(n, g["row_ptr"], g["col"], g.get("n_cpu", 0), g.get("n_gpu", 0), dur,
+                 g.get("est", None))
+
+
+def test_w4_simultaneous_readiness_pushed_in_id_order():
+    g, w = _small("w4")
+    r = oracle.schedule(w)
+    assert r["worker"].tolist() == g["worker"] and r["start"].tolist() == g["start"]
+    assert r["makespan"] == g["makespan"]
+
+
+def test_w5_push_counts_the_running_task():
+    g, w = _small("w5")
+    for pol in ("inspirit", "fifo"):
+        r = oracle.schedule(w, policy=pol)
+        assert r["worker"].tolist() == g["worker"] and r["start"].tolist() == g["start"]
+
+
+def test_w6_ladder_reaches_twice_the_largest_tau():
+    g, w = _small("w6")
+    ia, ie, U = oracle.attributes(g["n"], g["row_ptr"], g["col"], g["est"], g["n_gpu"])
+    assert U == g["unit_time"] and ie.tolist() == g["ie"]
+
+
+def test_w7_first_rule_is_high_ability():
+    g, w = _small("w7")
+    r = oracle.schedule(w)
+    assert int(r["mode_at_pop"][0]) == g["mode_at_pop_first"]

@@ -1,0 +1,150 @@
+"""Plant plausible mistakes in copies of the oracle (on the CPU) and check that
+the pins catch each one: the pins would not pass a wrong oracle."""
+import ctypes as C
+import json
+import os
+import subprocess
+from types import SimpleNamespace as NS
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2404_03226_amd import synth
+from invariants import check_schedule
+
+SRC = os.path.join(os.path.dirname(oracle.__file__), "oracle.c")
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+MUTATIONS = {
+    "ie_strict_unit_time": ("if (rem[s] == 1 && tv + tau_of(est, n_gpu, s) <= U) c++;",
+                            "if (rem[s] == 1 && tv + tau_of(est, n_gpu, s) < U) c++;"),
+    "ie_wrong_remaining": ("if (rem[s] == 1 && tv + tau_of(est, n_gpu, s) <= U) c++;",
+                           "if (rem[s] >= 1 && tv + tau_of(est, n_gpu, s) <= U) c++;"),
+    "ladder_tie_smaller_u": ("if (score >= bestScore) { bestScore = score; bestU = U; }",
+                             "if (score > bestScore) { bestScore = score; bestU = U; }"),
+    "ladder_one_rung_short": ("while (((int64_t)1 << J) < 2 * maxtau) J++;",
+                              "while (((int64_t)1 << J) < maxtau) J++;"),
+    "dmda_tie_highest_worker": ("if (best < 0 || c < bestc) { best = w; bestc = c; }",
+                                "if (best < 0 || c <= bestc) { best = w; bestc = c; }"),
+    "dmda_ignores_running_task": ("if (run[w] >= 0 && exp_end[w] > t) B = exp_end[w];", ""),
+    "dmda_ignores_queue": ("int64_t c = B + qest[w] + est[2 * (int64_t)v + k];",
+                           "int64_t c = B + est[2 * (int64_t)v + k];"),
+    "tau_cpu_column": ("return est[2 * (int64_t)v + (n_gpu > 0 ? 1 : 0)];", "return est[2 * (int64_t)v];"),
+    "ability_order_reversed": ("if (ia_a != ia_b) return ia_a > ia_b;\n        if (ie_a != ie_b) return ie_a > ie_b;\n    } else if (order == 1) {",
+                               "if (ia_a != ia_b) return ia_a < ia_b;\n        if (ie_a != ie_b) return ie_a > ie_b;\n    } else if (order == 1) {"),
+    "fifo_tie_latest": ("return sq_a < sq_b;", "return sq_a > sq_b;"),
+    "reg_inc_margin_strict": ("if (N >= r->peak - r->dec_step) {", "if (N > r->peak - r->dec_step) {"),
+    "reg_slope_flipped": ("if (dt == 0 || dn * r->k_den > r->k_num * dt) r->mode = M_ABILITY;\n            else if (dn * r->k_den < r->k_num * dt) r->mode = M_EFI;",
+                          "if (dt == 0 || dn * r->k_den < r->k_num * dt) r->mode = M_ABILITY;\n            else if (dn * r->k_den > r->k_num * dt) r->mode = M_EFI;"),
+    "reg_no_decrement_count": ("if (N <= r->peak - r->s_dec * (r->cnt + 1)) r->cnt += 1;", ""),
+    "reg_no_window": ("if ((dn < 0 ? -dn : dn) < r->s_inc) return;", ""),
+    "reg_starts_efficiency": ("r->mode = M_ABILITY;  /* Section 3", "r->mode = M_EFI;  /* Section 3"),
+    "ready_not_sorted": ("qsort(newly, (size_t)n_new, sizeof(int32_t), cmp_i32);", ""),
+    "regulate_after_pop": ("int64_t observed = nready;", "int64_t observed = nready - 1;"),
+}
+
+
+def _build(tmp_path, name, old, new):
+    src = open(SRC).read()
+    assert src.count(old) == 1, name
+    d = tmp_path / name
+    d.mkdir()
+    (d / "o.c").write_text(src.replace(old, new))
+    so = d / "lib.so"
+    subprocess.check_call(["gcc", "-O1", "-std=c11", "-fPIC", "-shared", "-pthread", "-o", str(so), str(d / "o.c")])
+    return str(so)
+
+
+def _swap(path):
+    saved = oracle._lib
+    oracle._lib = None
+    real = oracle.build
+    oracle.build = lambda force=False: path
+    try:
+        oracle.lib()
+    finally:
+        oracle.build = real
+    return saved
+
+
+def pins():
+    """The pin suite: returns the names of failed pins."""
+    failed = []
+
+    def chk(name, fn):
+        try:
+            if fn() is False:
+                failed.append(name)
+        except Exception:
+            failed.append(name)
+
+    g1 = json.load(open(os.path.join(GOLD, "w1_attributes.json")))
+    chk("w1", lambda: oracle.attributes(g1["n"], g1["row_ptr"], g1["col"], g1["est"], 1)[1].tolist() == g1["ie_auto"]
+        and oracle.attributes(g1["n"], g1["row_ptr"], g1["col"], g1["est"], 1)[2] == g1["unit_time_auto"])
+    g2 = json.load(open(os.path.join(GOLD, "w2_schedule.json")))
+    w2 = NS(n=5, row_ptr=np.array(g2["row_ptr"]), col=np.array(g2["col"]), dur=np.ones((5, 2), np.int32),
+            est=np.ones((5, 2), np.int32), n_cpu=2, n_gpu=0)
+    for pol in ("fifo", "inspirit"):
+        chk("w2" + pol, lambda pol=pol: oracle.schedule(w2, policy=pol)["start"].tolist() == g2[pol]["start"]
+            and oracle.schedule(w2, policy=pol)["worker"].tolist() == g2[pol]["worker"])
+    chk("w2u", lambda: oracle.schedule(w2)["unit_time"] == g2["unit_time"])
+    chk("w1u5", lambda: oracle.attributes(g1["n"], g1["row_ptr"], g1["col"], g1["est"], 1, rem=g1["rem_after_task1"],
+                                          unit_time=5)[1].tolist()[2] == g1["ie_after_task1_u5"][2])
+    small = json.load(open(os.path.join(GOLD, "w4_w7_small.json")))
+
+    def mk(g):
+        dur = np.asarray(g.get("dur", g.get("est")), np.int32)
+        est = np.asarray(g.get("est", dur), np.int32)
+        return NS(n=g["n"], row_ptr=np.asarray(g["row_ptr"], np.int32), col=np.asarray(g["col"], np.int32),
+                  dur=dur, est=est, n_cpu=g.get("n_cpu", 0), n_gpu=g.get("n_gpu", 0))
+    for key in ("w4", "w5"):
+        g = small[key]
+        chk(key, lambda g=g: oracle.schedule(mk(g))["worker"].tolist() == g["worker"]
+            and oracle.schedule(mk(g))["start"].tolist() == g["start"])
+    g6 = small["w6"]
+    chk("w6", lambda: oracle.attributes(g6["n"], g6["row_ptr"], g6["col"], g6["est"], 1)[2] == g6["unit_time"]
+        and oracle.attributes(g6["n"], g6["row_ptr"], g6["col"], g6["est"], 1)[1].tolist() == g6["ie"])
+    chk("w7", lambda: int(oracle.schedule(mk(small["w7"]))["mode_at_pop"][0]) == small["w7"]["mode_at_pop_first"])
+    chk("w2trace", lambda: oracle.schedule(w2, trace=True)["trace"]["nready"].tolist() == g2["inspirit"]["trace_nready"])
+    g3 = json.load(open(os.path.join(GOLD, "w3_regulator.json")))
+    chk("w3", lambda: oracle.regulate(g3["t"], g3["N"], 4, 10)[0].tolist() == g3["mode"]
+        and oracle.regulate(g3["t"], g3["N"], 4, 10)[1].tolist() == g3["cnt"])
+    # chain: the fastest kind every time
+    n = 10
+    rp = np.arange(n + 1, dtype=np.int32).clip(max=n - 1)
+    rp[0] = 0
+    rp = np.array([0] + [i for i in range(1, n)] + [n - 1], np.int32)
+    col = np.arange(1, n, dtype=np.int32)
+    dur = synth.Stream(9, 9).randint(np.arange(2 * n).reshape(n, 2), 1, 40).astype(np.int32)
+    wc = NS(n=n, row_ptr=rp, col=col, dur=dur, est=dur, n_cpu=2, n_gpu=1)
+    chk("chain", lambda: oracle.schedule(wc)["makespan"] == int(dur.min(axis=1).sum()))
+    # independent unit tasks
+    wi = NS(n=13, row_ptr=np.zeros(14, np.int32), col=np.zeros(0, np.int32), dur=np.ones((13, 2), np.int32),
+            est=np.ones((13, 2), np.int32), n_cpu=4, n_gpu=0)
+    chk("indep", lambda: oracle.schedule(wi)["makespan"] == 4)
+    # invariants and brute force on small random DAGs
+    for i in range(6):
+        w = synth.random_dag(77, i, 7, 0.3, dur_hi=6, n_cpu=1, n_gpu=1)
+        def inv(w=w):
+            r = oracle.schedule(w)
+            check_schedule(w, r["worker"], r["start"], r["finish"], r["makespan"])
+            return r["makespan"] >= oracle.brute_opt(w)
+        chk(f"inv{i}", inv)
+    return failed
+
+
+@pytest.mark.parametrize("name", sorted(MUTATIONS))
+def test_pins_catch_planted_mistake(tmp_path, name):
+    old, new = MUTATIONS[name]
+    path = _build(tmp_path, name, old, new)
+    saved = _swap(path)
+    try:
+        failed = pins()
+    finally:
+        oracle._lib = saved
+    assert failed, f"no pin caught the planted mistake '{name}'"
+
+
+def test_unmutated_oracle_passes_every_pin():
+    assert pins() == []
