@@ -28,6 +28,15 @@ namespace insp {
 
 __device__ __forceinline__ int ceil_log2(int32_t x) { return x <= 1 ? 0 : 32 - __clz(x - 1); }
 
+// Work-groups are dealt to the 8 XCDs round-robin (block i runs on XCD i % 8),
+// and each XCD has its own L2.  Give XCD x a contiguous run of the chunk list
+// so the chunks of one DAG -- whose successor gathers hit the same few hundred
+// KB -- share one L2.  Bijective for any grid size.
+__device__ __forceinline__ int32_t xcd_chunk(int32_t i, int32_t nb) {
+    const int32_t x = i & 7, k = i >> 3, q = nb >> 3, rmd = nb & 7;
+    return x * q + min(x, rmd) + k;
+}
+
 struct AttrArgs {
     const DagDesc *desc;
     const int2 *blkmap;
@@ -62,7 +71,7 @@ __global__ __launch_bounds__(kAttrThreads) void k_attr_a(AttrArgs a) {
     if (tid < kRungs) hist[tid] = 0;
     if (tid == 0) bad = 0;
     __syncthreads();
-    const int2 bm = a.blkmap[blockIdx.x];
+    const int2 bm = a.blkmap[xcd_chunk(blockIdx.x, gridDim.x)];
     const DagDesc d = a.desc[bm.x];
     const int32_t lv = bm.y * kAttrThreads + tid;
     const int g = d.n_gpu > 0 ? 1 : 0;
@@ -147,7 +156,7 @@ struct AttrOut {
 };
 
 __global__ __launch_bounds__(kAttrThreads) void k_attr_b(AttrArgs a, AttrOut o) {
-    const int2 bm = a.blkmap[blockIdx.x];
+    const int2 bm = a.blkmap[xcd_chunk(blockIdx.x, gridDim.x)];
     const DagDesc d = a.desc[bm.x];
     const int32_t lv = bm.y * kAttrThreads + threadIdx.x;
     if (lv >= d.n) return;
