@@ -78,6 +78,45 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t x) {
     y = dpp32<0x143, 0xC>(x); x = x > y ? x : y;
     return __builtin_amdgcn_readlane(x, 63);
 }
+// DPP move whose masked-off or out-of-row lanes read `ident`: with the
+// operation's identity there the compiler folds the move into the max/min
+// itself (one v_max_u32_dpp per step instead of a move, a compare and a
+// select).  Only lane 63's result is used, which every step keeps exact.
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ uint32_t dpp_id(uint32_t x, uint32_t ident) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)ident, (int)x, CTRL, ROW_MASK, 0xF, false);
+}
+__device__ __forceinline__ uint32_t wave_max_u32f(uint32_t x) {
+    x = max(x, dpp_id<0xB1>(x, 0u));
+    x = max(x, dpp_id<0x4E>(x, 0u));
+    x = max(x, dpp_id<0x141>(x, 0u));
+    x = max(x, dpp_id<0x140>(x, 0u));
+    x = max(x, dpp_id<0x142, 0xA>(x, 0u));
+    x = max(x, dpp_id<0x143, 0xC>(x, 0u));
+    return __builtin_amdgcn_readlane(x, 63);
+}
+__device__ __forceinline__ uint32_t wave_min_u32f(uint32_t x) {
+    x = min(x, dpp_id<0xB1>(x, ~0u));
+    x = min(x, dpp_id<0x4E>(x, ~0u));
+    x = min(x, dpp_id<0x141>(x, ~0u));
+    x = min(x, dpp_id<0x140>(x, ~0u));
+    x = min(x, dpp_id<0x142, 0xA>(x, ~0u));
+    x = min(x, dpp_id<0x143, 0xC>(x, ~0u));
+    return __builtin_amdgcn_readlane(x, 63);
+}
+// 64-bit max as two 32-bit passes: the high words, then the low words of
+// the lanes that hold the maximal high word.
+__device__ __forceinline__ uint64_t wave_max_u64f(uint64_t x) {
+    const uint32_t hi = wave_max_u32f((uint32_t)(x >> 32));
+    const uint32_t lo = wave_max_u32f((uint32_t)(x >> 32) == hi ? (uint32_t)x : 0u);
+    return (uint64_t)hi << 32 | lo;
+}
+__device__ __forceinline__ uint64_t wave_min_u64f(uint64_t x) {
+    const uint32_t hi = wave_min_u32f((uint32_t)(x >> 32));
+    const uint32_t lo = wave_min_u32f((uint32_t)(x >> 32) == hi ? (uint32_t)x : ~0u);
+    return (uint64_t)hi << 32 | lo;
+}
+
 // Wave sum of a 64-bit value via row shifts (non-idempotent, so the DPP
 // moves use bound_ctrl and a zero identity).
 template <int CTRL, int ROW_MASK = 0xF>

@@ -100,11 +100,13 @@ struct Lds {
     int32_t *pre;                                    // [8 * kWave] staged frontier rows
     unsigned long long *sk, *sx;                     // [64 * slot_cap] queue slots of the low blocks
     int32_t *srs;                                    // [64 * slot_cap]
+    int32_t *fstk;                                   // [sum_cap] free block ids below sum_cap
+    uint8_t *stale;                                  // [sum_cap] block maxima to rebuild before use
 };
 
 __host__ __device__ constexpr size_t lds_bytes(int mw, int sc, int lb, int slc) {
-    return (size_t)mw * (3 * 8 + 7 * 4 + (size_t)lb * 4) + (size_t)sc * 16 + kFC * 8 + kCC * 8 + 8 * 64 * 4 +
-           (size_t)slc * 64 * 20 + 64;
+    return (size_t)mw * (3 * 8 + 7 * 4 + (size_t)lb * 4) + (size_t)sc * (16 + 4 + 1) + kFC * 8 + kCC * 8 +
+           8 * 64 * 4 + (size_t)slc * 64 * 20 + 64;
 }
 
 template <int WPL>
@@ -834,6 +836,798 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Machines of at most 64 workers: lane w holds worker w's state in registers
+// (running task, its finish and expected-end times, queue length, block count,
+// last block, the running task's row and first successors), so pushes, pops
+// and the advance read no memory for it.  Same event order and results as the
+// general loop above; the queue differs only in how a pop finds its maximum:
+//   - a worker with at most kScan blocks: every lane scans its column of all
+//     of the worker's blocks, then one wave max;
+//   - more blocks: per-block maxima pick the block first.  Maxima of blocks
+//     held in LDS are rebuilt lazily: a pop only marks the blocks it touched
+//     stale; pushes and IE increments keep raising them with atomicMax (which
+//     a later rebuild overwrites), and a many-block pop rebuilds the stale
+//     ones of its worker before comparing.  Maxima kept in global memory
+//     (block ids >= sum_cap) are rebuilt at once, as in the general loop.
+constexpr int kScan = 16;
+
+// Key words of the first `cnt` entries of block b, one per lane (0 above).
+// b is wave-uniform: the choice between LDS and global memory is a scalar
+// branch taken before the per-lane guard, so the two kinds of load never
+// share a destination register (which would make the LDS read wait for
+// every outstanding global access).
+__device__ __forceinline__ uint64_t block_keys(const Slot *slots, const Lds &L, int32_t slc, int32_t b, int32_t cnt) {
+    const int lane = lane_id();
+    uint64_t k = 0;
+    if (b < slc) {
+        if (lane < cnt) k = L.sk[b * 64 + lane];
+    } else {
+        if (lane < cnt) k = wg_load(&slots[b * 64 + lane].k);
+    }
+    return k;
+}
+
+// Best key under rule `ord` in column `lane` of the listed blocks (bits of
+// `m` select lanes of `bl`, which hold block ids), four loads in flight at a
+// time; FROM_LDS picks where the blocks' slots live.
+template <bool FROM_LDS>
+__device__ __forceinline__ void scan_columns(const Slot *slots, const Lds &L, uint64_t m, int32_t bl, int32_t lastw,
+                                             int32_t lastpos, int ord, uint64_t &best, int32_t &bp) {
+    const int lane = lane_id();
+    while (m) {
+        uint64_t kk[4];
+        int32_t pp[4];
+        bool ok[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            int32_t b = -1;
+            if (m) {
+                b = read_lane(bl, (int)__builtin_ctzll(m));
+                m &= m - 1;
+            }
+            const int32_t cntb = b < 0 ? 0 : b == lastw ? lastpos + 1 : 64;
+            pp[u] = b * 64 + lane;
+            ok[u] = lane < cntb;
+            kk[u] = 0;
+            if (ok[u]) kk[u] = FROM_LDS ? L.sk[pp[u]] : wg_load(&slots[pp[u]].k);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const uint64_t key = ok[u] ? key_of(kk[u], ord) : 0;
+            if (key > best) {
+                best = key;
+                bp = pp[u];
+            }
+        }
+    }
+}
+
+// Rebuild both maxima of block b from its first `cnt` entries (wave-wide).
+__device__ __forceinline__ void rebuild_max(const Slot *slots, const Lds &L, unsigned long long *sums, int32_t slc,
+                                            int32_t sc, int slot0, int32_t b, int32_t cnt) {
+    const int lane = lane_id();
+    const uint64_t k = block_keys(slots, L, slc, b, cnt);
+    const uint64_t s0 = wave_max_u64f(lane < cnt ? key_of(k, slot0) : 0);
+    const uint64_t s1 = wave_max_u64f(lane < cnt ? key_of(k, 1) : 0);
+    if (lane == 0) {
+        if (b < sc) {
+            L.sum[2 * b] = s0;
+            L.sum[2 * b + 1] = s1;
+            L.stale[b] = 0;
+        } else {
+            sums[2 * b] = s0;
+            sums[2 * b + 1] = s1;
+        }
+    }
+}
+
+__device__ void sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
+    const int lane = lane_id();
+    const DagDesc d = A.desc[di];
+    const int32_t n = d.n, ncpu = d.n_cpu, W = d.n_cpu + d.n_gpu;
+    int32_t status = A.stat[2 * d.id];
+    if (n == 0 || status != 0) {
+        if (lane == 0) {
+            A.makespan[di] = status ? -1 : 0;
+            if (A.n_events) A.n_events[di] = 0;
+        }
+        return;
+    }
+    const int64_t ub = d.toff - A.base;
+    const int32_t *col = A.col + d.eoff;
+    TaskRec *tr = A.tr + d.toff;
+    int32_t *fbuf = A.fbuf + 3 * d.toff;      // [0,n) runs, [n,2n) merged, [2n,3n) candidates
+    const int2 *est2 = reinterpret_cast<const int2 *>(A.est) + ub;
+    const int2 *dur2 = reinterpret_cast<const int2 *>(A.dur) + ub;
+    Slot *slots = A.slots + 64 * d.blk_off;
+    unsigned long long *sums = A.sums + 2 * d.blk_off;
+    int32_t *wblk = A.paux + d.wl_off;
+    int32_t *freeb = A.paux + A.freeb_base + d.blk_off;
+    const int32_t maxb = d.maxb;
+    const int32_t SC = A.sum_cap;
+    const int32_t kLB = A.lb;
+    const int32_t SLC = A.slot_cap;
+    const int32_t U = A.dag_u[d.id];
+
+    const int32_t s_inc = A.s_inc > 0 ? A.s_inc : max(1, (W + 3) / 4);
+    const int32_t s_dec = A.s_dec > 0 ? A.s_dec : max(1, (W + 1) / 2);
+    const int32_t dec_step = A.dec_step > 0 ? A.dec_step : s_dec;
+    const int32_t cc = A.c >= 0 ? A.c : s_dec / 2;
+    const bool kset = A.k_num > 0 && A.k_den > 0;
+    const int32_t k_num = kset ? A.k_num : W;
+    const int32_t k_den = kset ? A.k_den : A.dag_taubar[d.id];
+    const int slot0 = A.policy == INSP_POLICY_FIFO ? 2 : 0;
+    const int32_t max_events = A.max_events > 0 ? A.max_events : n + 1;
+
+    // this lane's worker
+    const bool wok = lane < W;
+    int32_t run = -1, len = 0, nb = 0, last = -1, rsr = 0, dgr = 0;
+    int64_t fin = 0, expend = 0, qest = 0;
+    int32_t pf[kPF];
+#pragma unroll
+    for (int j = 0; j < kPF; j++) pf[j] = 0;
+
+    // free block ids, lowest first: a stack in LDS below sum_cap, one in
+    // global memory above it
+    const int32_t nl = min(d.nblk, SC);
+    for (int32_t i = lane; i < nl; i += kWave) L.fstk[i] = nl - 1 - i;
+    for (int32_t i = lane; i < d.nblk - nl; i += kWave) freeb[i] = d.nblk - 1 - i;
+    int32_t nfl = nl, nfg = d.nblk - nl;
+
+    // initial frontier: tasks without predecessors, ascending
+    int32_t r = 0;
+    for (int32_t i0 = 0; i0 < n; i0 += kWave) {
+        int32_t i = i0 + lane;
+        bool ok = i < n && (tr[i].word >> 43) == 0;
+        uint64_t mk = ballot(ok);
+        if (ok) {
+            int32_t pos = r + lanes_below(mk);
+            fbuf[pos] = i;
+            if (pos < kFC) L.fr0[pos] = i;
+        }
+        r += __popcll(mk);
+    }
+    bool merged = false, staged = false;
+    wg_fence();
+
+    int64_t t = 0, prev_t = 0;
+    int32_t nready = 0, events = 0, done = 0, seq = 0;
+    int32_t peak = 0, prev_n = 0, cnt = 0;
+    int mode = INSP_MODE_ABILITY;
+#ifdef INSP_PHASE_CLOCKS
+    unsigned long long pc[10] = {0}, pc_last = clock64();
+#endif
+
+    for (;;) {
+        PCLK(9);
+        if (++events > max_events) {
+            status |= ST_HANG;
+            break;
+        }
+        // ------------------------------------------------------------ push
+        // this lane's load: free time (now, or the running task's expected
+        // end) plus the estimates queued on it
+        int64_t ld = 0;
+        if (wok) ld = (run >= 0 && expend > t ? expend : t) + qest;
+        for (int32_t i0 = 0; i0 < r; i0 += kWave) {
+            const int32_t idx = i0 + lane;
+            const bool ok = idx < r;
+            int32_t v_l = 0;
+            int2 e_l = make_int2(1, 1), d_l = make_int2(1, 1);
+            int32_t ia_l = 0, ie_l = 0, rs_l = 0;
+            if (staged) {
+                if (ok) {
+                    v_l = L.pre[idx];
+                    e_l = make_int2(L.pre[64 + idx], L.pre[128 + idx]);
+                    d_l = make_int2(L.pre[192 + idx], L.pre[256 + idx]);
+                    ia_l = L.pre[320 + idx];
+                    rs_l = L.pre[384 + idx];
+                    ie_l = L.pre[448 + idx];
+                }
+            } else {
+                if (ok) {
+                    if (r <= kFC) v_l = merged ? L.fr1[idx] : L.fr0[idx];
+                    else v_l = merged ? fbuf[n + idx] : fbuf[idx];
+                }
+                if (ok) {
+                    e_l = est2[v_l];
+                    d_l = dur2[v_l];
+                    ia_l = tr[v_l].ia;
+                    rs_l = tr[v_l].rs;
+                    ie_l = wg_load(&tr[v_l].iev);
+                }
+            }
+            if (ballot(ok && (d_l.x < 1 || d_l.x > INSP_MAX_TICK || d_l.y < 1 || d_l.y > INSP_MAX_TICK)))
+                status |= ST_DUR;
+            const int32_t cntj = min(kWave, r - i0);
+            int32_t pq = 0, sqj = 0, wsj = 0;  // lane j: slot, push order and worker of task j
+            for (int32_t j = 0; j < cntj; j++) {
+                const int32_t e0 = read_lane(e_l.x, j), e1 = read_lane(e_l.y, j);
+                // least expected termination, ties to the lower worker: a
+                // 32-bit key (cost - t) << 6 | worker while it fits
+                const int64_t rc = ld + (lane < ncpu ? e0 : e1) - t;
+                const uint32_t k32 = wok && rc < (1 << 26) ? (uint32_t)rc << 6 | (uint32_t)lane : ~0u;
+                const uint32_t m32 = wave_min_u32f(k32);
+                int32_t ws;
+                if (m32 != ~0u) {
+                    ws = (int32_t)(m32 & 63);
+                } else {
+                    const uint64_t k64 = wok ? (uint64_t)rc << 6 | (uint64_t)lane : ~0ull;
+                    ws = (int32_t)(wave_min_u64f(k64) & 63);
+                }
+                const int32_t ek = ws >= ncpu ? e1 : e0;
+                const int32_t lenw = read_lane(len, ws);
+                const int32_t pos = lenw & 63;
+                int32_t blk;
+                if (pos == 0) {
+                    if (nfl > 0) {
+                        nfl--;
+                        blk = L.fstk[nfl];
+                    } else {
+                        nfg--;
+                        blk = wg_load(&freeb[nfg]);
+                    }
+                    const int32_t nbw = read_lane(nb, ws);
+                    if (lane == 0) {
+                        if (nbw < kLB) L.blist[ws * kLB + nbw] = blk;
+                        else wblk[(int64_t)ws * maxb + nbw] = blk;
+                    }
+                    if (lane == ws) {
+                        nb = nbw + 1;
+                        last = blk;
+                    }
+                } else {
+                    blk = read_lane(last, ws);
+                }
+                if (lane == ws) {
+                    len = lenw + 1;
+                    qest += ek;
+                    ld += ek;
+                }
+                if (lane == j) {
+                    pq = blk * 64 + pos;
+                    sqj = seq;
+                    wsj = ws;
+                }
+                seq++;
+                nready++;
+            }
+            // the chunk's queue entries, task records and block maxima: lane j
+            // writes task j's.  The first entry of a new block sets its maxima,
+            // then every entry raises them -- the first one's lane too, so that
+            // within each lane the store precedes the atomic on that address
+            // and the compiler keeps the stores of some lanes ahead of the
+            // atomics of the others.
+            const int32_t bq = pq >> 6;
+            uint64_t a0 = 0, a1 = 0;
+            if (ok) {
+                const bool g = wsj >= ncpu;
+                const int32_t ekl = g ? e_l.y : e_l.x, dkl = g ? d_l.y : d_l.x;
+                const uint64_t kw = (uint64_t)ia_l << 42 | (uint64_t)ie_l << 21 | (M21 - (uint64_t)sqj);
+                const uint64_t xw = (uint64_t)v_l << 42 | (uint64_t)(dkl & M21) << 21 | (uint64_t)(ekl & M21);
+                if (bq < SLC) {
+                    L.sk[pq] = kw;
+                    L.sx[pq] = xw;
+                    L.srs[pq] = rs_l;
+                } else {
+                    slots[pq].k = kw;
+                    slots[pq].x = xw;
+                    slots[pq].rs = rs_l;
+                }
+                tr[v_l].qpos = pq;
+                tr[v_l].seq = sqj;
+                a0 = key_of(kw, slot0);
+                a1 = key_of(kw, 1);
+                if ((pq & 63) == 0) {
+                    if (bq < SC) {
+                        L.sum[2 * bq] = a0;
+                        L.sum[2 * bq + 1] = a1;
+                        L.stale[bq] = 0;
+                    } else {
+                        sums[2 * bq] = a0;
+                        sums[2 * bq + 1] = a1;
+                    }
+                }
+            }
+            if (ok) {
+                if (bq < SC) {
+                    atomicMax(&L.sum[2 * bq], (unsigned long long)a0);
+                    atomicMax(&L.sum[2 * bq + 1], (unsigned long long)a1);
+                } else {
+                    wg_fetch_max(&sums[2 * bq], (unsigned long long)a0);
+                    wg_fetch_max(&sums[2 * bq + 1], (unsigned long long)a1);
+                }
+            }
+        }
+        PCLK(0);
+        wg_fence();
+        PCLK(1);
+        // -------------------------------------------------------- regulate
+        const int32_t observed = nready;
+        if (A.policy == INSP_POLICY_INSPIRIT) {
+            if (nready > peak) peak = nready;
+            const int32_t dn = nready - prev_n;
+            if ((dn < 0 ? -dn : dn) >= s_inc) {
+                const int64_t dt = t - prev_t;
+                prev_n = nready;
+                prev_t = t;
+                if (nready >= peak - dec_step) {
+                    cnt = 0;
+                    if (dn >= s_inc) {
+                        const int64_t lhs = (int64_t)dn * k_den, rhs = (int64_t)k_num * dt;
+                        if (dt == 0 || lhs > rhs) mode = INSP_MODE_ABILITY;
+                        else if (lhs < rhs) mode = INSP_MODE_EFI;
+                    }
+                } else if ((int64_t)nready > (int64_t)peak - (int64_t)s_dec * cnt) {
+                    mode = INSP_MODE_ABILITY;
+                } else if ((int64_t)nready <= (int64_t)peak - (int64_t)s_dec * (cnt + 1) + cc) {
+                    mode = INSP_MODE_EFI_LOC;
+                    if ((int64_t)nready <= (int64_t)peak - (int64_t)s_dec * (cnt + 1)) cnt++;
+                }
+            }
+        }
+        const int pmode = A.policy == INSP_POLICY_FIFO ? INSP_MODE_FIFO
+                        : A.policy == INSP_POLICY_ABILITY_ONLY ? INSP_MODE_ABILITY
+                        : A.policy == INSP_POLICY_EFI_ONLY ? INSP_MODE_EFI : mode;
+        const int ord = pmode == INSP_MODE_FIFO ? 2 : pmode == INSP_MODE_ABILITY ? 0 : 1;
+        const int slot = ord == 1 ? 1 : 0;
+        // ------------------------------------------------------------- pop
+        int32_t popped = 0;
+        bool popnow = false;        // this lane's worker took a task in this event
+        int32_t iep = 0;            // ... with this IE
+        int32_t mvt = -1, mvp = 0;  // lane k: task moved into the hole of the k-th pop, and where
+        uint64_t idle = ballot(wok && run < 0 && len > 0);
+        while (idle) {
+            const int32_t w = (int32_t)__builtin_ctzll(idle);
+            idle &= idle - 1;
+            const int32_t nbw = read_lane(nb, w), lenw = read_lane(len, w), lastw = read_lane(last, w);
+            const int32_t lastpos = (lenw - 1) & 63;
+            int32_t p;
+            if (nbw <= kScan) {
+                // lane l compares entry l of every block of the worker: the
+                // blocks held in LDS, then those in global memory
+                int32_t bl = -1;
+                if (nbw <= kLB) {
+                    if (lane < nbw) bl = L.blist[w * kLB + lane];
+                } else {
+                    if (lane < nbw) bl = lane < kLB ? L.blist[w * kLB + lane] : wg_load(&wblk[(int64_t)w * maxb + lane]);
+                }
+                const uint64_t all = ballot(lane < nbw);
+                const uint64_t inl = ballot(lane < nbw && bl < SLC);
+                uint64_t best = 0;
+                int32_t bp = -1;
+                scan_columns<true>(slots, L, inl, bl, lastw, lastpos, ord, best, bp);
+                scan_columns<false>(slots, L, all & ~inl, bl, lastw, lastpos, ord, best, bp);
+                const uint64_t km = wave_max_u64f(best);
+                p = read_lane(bp, (int)__builtin_ctzll(ballot(best == km && bp >= 0)));
+            } else {
+                // many blocks: rebuild stale maxima, pick the block, scan it
+                uint64_t bk = 0;
+                int32_t bid = -1;
+                for (int32_t i0 = 0; i0 < nbw; i0 += kWave) {
+                    const int32_t i = i0 + lane;
+                    int32_t b = -1;
+                    if (i < nbw) b = i < kLB ? L.blist[w * kLB + i] : wg_load(&wblk[(int64_t)w * maxb + i]);
+                    bool st = false;
+                    if (b >= 0 && b < SC) st = L.stale[b] != 0;
+                    uint64_t sm = ballot(st);
+                    while (sm) {
+                        const int l = (int)__builtin_ctzll(sm);
+                        sm &= sm - 1;
+                        const int32_t sb = read_lane(b, l);
+                        rebuild_max(slots, L, sums, SLC, SC, slot0, sb, sb == lastw ? lastpos + 1 : 64);
+                    }
+                    if (b >= 0) {
+                        const uint64_t k = b < SC ? L.sum[2 * b + slot] : wg_load(&sums[2 * b + slot]);
+                        if (k > bk) {
+                            bk = k;
+                            bid = b;
+                        }
+                    }
+                }
+                const uint64_t kmb = wave_max_u64f(bk);
+                const int32_t bb = read_lane(bid, (int)__builtin_ctzll(ballot(bk == kmb && bid >= 0)));
+                const int32_t cntb = bb == lastw ? lastpos + 1 : 64;
+                const uint64_t kb = block_keys(slots, L, SLC, bb, cntb);
+                const uint64_t key = lane < cntb ? key_of(kb, ord) : 0;
+                const uint64_t km = wave_max_u64f(key);
+                p = bb * 64 + (int)__builtin_ctzll(ballot(key == km && lane < cntb));
+            }
+            // take the entry at p; the worker's final entry q fills the hole
+            const int32_t bb = p >> 6;
+            const int32_t q = lastw * 64 + lastpos;
+            uint64_t vk, vx, mk = 0, mx = 0;
+            int32_t vr, mr = 0;
+            if (bb < SLC) {
+                vk = L.sk[p];
+                vx = L.sx[p];
+                vr = L.srs[p];
+            } else {
+                vk = wg_load(&slots[p].k);
+                vx = wg_load(&slots[p].x);
+                vr = wg_load(&slots[p].rs);
+            }
+            if (p != q) {
+                if (lastw < SLC) {
+                    mk = L.sk[q];
+                    mx = L.sx[q];
+                    mr = L.srs[q];
+                } else {
+                    mk = wg_load(&slots[q].k);
+                    mx = wg_load(&slots[q].x);
+                    mr = wg_load(&slots[q].rs);
+                }
+            }
+            const int32_t v = (int32_t)(vx >> 42);
+            const int32_t dk = (int32_t)((vx >> 21) & M21), ek = (int32_t)(vx & M21);
+            const int32_t deg = (int32_t)(vk >> 42);
+            if (p != q) {
+                if (lane == 0) {
+                    if (bb < SLC) {
+                        L.sk[p] = mk;
+                        L.sx[p] = mx;
+                        L.srs[p] = mr;
+                    } else {
+                        slots[p].k = mk;
+                        slots[p].x = mx;
+                        slots[p].rs = mr;
+                    }
+                }
+                if (lane == popped) {
+                    mvt = (int32_t)(mx >> 42);
+                    mvp = p;
+                }
+            }
+            const int32_t nlen = lenw - 1;
+            const bool freed = (nlen & 63) == 0;
+            int32_t nbn = nbw, newlast = lastw;
+            if (freed) {
+                if (lane == 0) {
+                    if (lastw < SC) L.fstk[nfl] = lastw;
+                    else freeb[nfg] = lastw;
+                }
+                if (lastw < SC) nfl++;
+                else nfg++;
+                nbn = nbw - 1;
+                newlast = nbn <= 0 ? -1 : nbn - 1 < kLB ? L.blist[w * kLB + nbn - 1]
+                                                        : wg_load(&wblk[(int64_t)w * maxb + nbn - 1]);
+            }
+            // maxima of the blocks that changed: bb lost the winner (and took
+            // the final entry), the last block lost its final entry
+            if (!(bb == lastw && freed)) {
+                if (bb < SC) {
+                    if (lane == 0) L.stale[bb] = 1;
+                } else {
+                    rebuild_max(slots, L, sums, SLC, SC, slot0, bb, bb == lastw ? lastpos : 64);
+                }
+            }
+            if (lastw != bb && !freed) {
+                if (lastw < SC) {
+                    if (lane == 0) L.stale[lastw] = 1;
+                } else {
+                    rebuild_max(slots, L, sums, SLC, SC, slot0, lastw, lastpos);
+                }
+            }
+            if (lane == w) {
+                len = nlen;
+                nb = nbn;
+                last = newlast;
+                run = v;
+                fin = t + dk;
+                expend = t + ek;
+                qest -= ek;
+                rsr = vr;
+                dgr = deg;
+                iep = (int32_t)((vk >> 21) & M21);
+                popnow = true;
+            }
+            nready--;
+            popped++;
+        }
+        // the event's pops write their records with one store per array (a
+        // worker pops at most once per event, so the addresses differ), and
+        // prefetch the first successors of the tasks they started
+        if (popnow) {
+            tr[run].qpos = -2;  // running, then done
+            const int64_t uv = ub + run;
+            A.worker[uv] = lane;
+            A.start[uv] = t;
+            A.finish[uv] = fin;
+            if (A.ie_at_pop) A.ie_at_pop[uv] = iep;
+            if (A.mode_at_pop) A.mode_at_pop[uv] = (int8_t)pmode;
+#pragma unroll
+            for (int j = 0; j < kPF; j++) pf[j] = j < dgr ? col[rsr + j] : 0;
+        }
+        if (mvt >= 0) tr[mvt].qpos = mvp;
+        PCLK(2);
+        if (A.trace && lane == 0 && events <= max_events) {
+            insp_trace_rec rec;
+            rec.t = t;
+            rec.nready = observed;
+            rec.mode = pmode;
+            rec.cnt = cnt;
+            rec.peak = peak;
+            rec.pushed = r;
+            rec.popped = popped;
+            A.trace[events - 1] = rec;
+        }
+        if (done == n) break;
+        // --------------------------------------------------------- advance
+        // every running task ends within 2^20 ticks of t
+        const uint32_t dtm = wave_min_u32f(wok && run >= 0 ? (uint32_t)(fin - t) : ~0u);
+        if (dtm == ~0u) {
+            status |= ST_HANG;
+            break;
+        }
+        t += dtm;
+        PCLK(3);
+        // --------------------------------------------------------- release
+        r = 0;
+        int32_t nc = 0, nseg = 0, ndone = 0;
+        {
+            const bool fin_now = wok && run >= 0 && fin == t;
+            uint64_t mask = ballot(fin_now);
+            const int32_t c_l = fin_now ? run : -1;
+            if (fin_now) run = -1;
+            while (mask) {
+                const int l = (int)__builtin_ctzll(mask);
+                mask &= mask - 1;
+                const int32_t c = read_lane(c_l, l);
+                done++;
+                ndone++;
+                const int32_t deg = read_lane(dgr, l), rs = read_lane(rsr, l);
+                const int32_t r0 = r;
+                const unsigned long long dec = 0ull - ((1ull << 43) + (unsigned long long)c);
+                for (int32_t e0 = 0; e0 < deg; e0 += kWave) {
+                    const int32_t e = e0 + lane;
+                    const bool ok = e < deg;
+                    int32_t s = 0;
+                    if (e0 == 0) {
+#pragma unroll
+                        for (int j = 0; j < kPF; j++) {
+                            const int32_t y = read_lane(pf[j], l);
+                            if (lane == j) s = y;
+                        }
+                    }
+                    if (ok && e >= kPF) s = col[rs + e];
+                    uint64_t old = 0;
+                    if (ok) old = wg_fetch_add(&tr[s].word, dec);
+                    const int32_t nr = (int32_t)(old >> 43) - 1;
+                    const bool rdy = ok && nr == 0, cd = ok && nr == 1;
+                    const uint64_t m1 = ballot(rdy), m2 = ballot(cd);
+                    if (rdy) {
+                        const int32_t pos = r + lanes_below(m1);
+                        fbuf[pos] = s;
+                        if (pos < kFC) L.fr0[pos] = s;
+                    }
+                    if (cd) {
+                        const int32_t pos = nc + lanes_below(m2);
+                        if (pos < kCC) {
+                            L.cs[pos] = s;
+                            L.cu[pos] = (int32_t)((old + dec) & M43);
+                        } else {
+                            fbuf[2 * n + pos] = s;
+                        }
+                    }
+                    r += __popcll(m1);
+                    nc += __popcll(m2);
+                }
+                if (r > r0) {
+                    if (lane == 0) L.seg[nseg] = r;
+                    nseg++;
+                }
+            }
+        }
+        PCLK(4);
+        wg_fence();
+        PCLK(5);
+        // successors left with one unfinished predecessor raise its IE (as in
+        // the general loop)
+        const bool single = ndone == 1;
+        merged = false;
+        staged = false;
+        if (nc <= kWave && r <= kFC) {
+            const bool hc = lane < nc;
+            const int32_t s = hc ? L.cs[lane] : 0;
+            int32_t u = hc ? L.cu[lane] : -1;
+            if (hc && !single)
+                for (int32_t k = 0; k < r; k++)
+                    if (L.fr0[k] == s) {
+                        u = -1;
+                        break;
+                    }
+            staged = r <= kWave;
+            const bool hf = staged && lane < r;
+            const int32_t fv = hf ? L.fr0[lane] : 0;
+            int32_t tu = 0, ts = 0, iu = 0, qu = -1, au = 0, sq = 0;
+            if (u >= 0) {
+                tu = tr[u].tau;
+                ts = tr[s].tau;
+                iu = wg_load(&tr[u].iev);
+                qu = wg_load(&tr[u].qpos);
+                au = tr[u].ia;
+                sq = wg_load(&tr[u].seq);
+            }
+            int2 fe = make_int2(1, 1), fd = make_int2(1, 1);
+            int32_t fa = 0, frs = 0, fie = 0;
+            if (hf) {
+                fe = est2[fv];
+                fd = dur2[fv];
+                fa = tr[fv].ia;
+                frs = tr[fv].rs;
+                fie = wg_load(&tr[fv].iev);
+            }
+            const bool cond = u >= 0 && (int64_t)tu + ts <= (int64_t)U;
+            int32_t mult = 0;
+            bool lead = cond;
+            for (int32_t j = 0; j < nc; j++) {
+                const int32_t uj = read_lane(u, j);
+                const int32_t cj = read_lane(cond ? 1 : 0, j);
+                if (cj && cond && uj == u) {
+                    mult++;
+                    if (j < lane) lead = false;
+                }
+            }
+            if (lead) {
+                const int32_t nie = iu + mult;
+                tr[u].iev = nie;
+                if (qu >= 0) {
+                    const uint64_t nk = (uint64_t)au << 42 | (uint64_t)nie << 21 | (M21 - (uint64_t)sq);
+                    const int32_t bk = qu >> 6;
+                    if (bk < SLC) L.sk[qu] = nk;
+                    else slots[qu].k = nk;
+                    if (bk < SC) {
+                        atomicMax(&L.sum[2 * bk], (unsigned long long)key_of(nk, slot0));
+                        atomicMax(&L.sum[2 * bk + 1], (unsigned long long)key_of(nk, 1));
+                    } else {
+                        wg_fetch_max(&sums[2 * bk], (unsigned long long)key_of(nk, slot0));
+                        wg_fetch_max(&sums[2 * bk + 1], (unsigned long long)key_of(nk, 1));
+                    }
+                }
+            }
+            uint64_t lm = ballot(lead && qu == -1);
+            while (lm) {
+                const int l = (int)__builtin_ctzll(lm);
+                lm &= lm - 1;
+                const int32_t uu = read_lane(u, l), kk = read_lane(mult, l);
+                const uint64_t fm = ballot(hf && fv == uu);
+                if (fm && lane == (int)__builtin_ctzll(fm)) fie += kk;
+            }
+            int32_t pos = lane;
+            if (nseg > 1 && hf) {
+                int32_t rank = 0, lo = 0;
+                for (int32_t g = 0; g < nseg; g++) {
+                    const int32_t hi = L.seg[g];
+                    if (lane >= lo && lane < hi) {
+                        rank += lane - lo;
+                    } else {
+                        int32_t a = lo, b = hi;
+                        while (a < b) {
+                            const int32_t mid = (a + b) >> 1;
+                            if (L.fr0[mid] < fv) a = mid + 1;
+                            else b = mid;
+                        }
+                        rank += a - lo;
+                    }
+                    lo = hi;
+                }
+                pos = rank;
+            }
+            if (!staged && nseg > 1) {
+                for (int32_t i = lane; i < r; i += kWave) {
+                    const int32_t x = L.fr0[i];
+                    int32_t rank = 0, lo = 0;
+                    for (int32_t g = 0; g < nseg; g++) {
+                        const int32_t hi = L.seg[g];
+                        if (i >= lo && i < hi) {
+                            rank += i - lo;
+                        } else {
+                            int32_t a = lo, b = hi;
+                            while (a < b) {
+                                const int32_t mid = (a + b) >> 1;
+                                if (L.fr0[mid] < x) a = mid + 1;
+                                else b = mid;
+                            }
+                            rank += a - lo;
+                        }
+                        lo = hi;
+                    }
+                    L.fr1[rank] = x;
+                }
+                merged = true;
+            }
+            if (hf) {
+                L.pre[pos] = fv;
+                L.pre[64 + pos] = fe.x;
+                L.pre[128 + pos] = fe.y;
+                L.pre[192 + pos] = fd.x;
+                L.pre[256 + pos] = fd.y;
+                L.pre[320 + pos] = fa;
+                L.pre[384 + pos] = frs;
+                L.pre[448 + pos] = fie;
+            }
+        } else {
+            for (int32_t i0 = 0; i0 < nc; i0 += kWave) {
+                const int32_t i = i0 + lane;
+                if (i < nc) {
+                    const int32_t s = i < kCC ? L.cs[i] : wg_load(&fbuf[2 * n + i]);
+                    int32_t u = -1;
+                    if (single && i < kCC) {
+                        u = L.cu[i];
+                    } else {
+                        const uint64_t wd = wg_load(&tr[s].word);
+                        if ((wd >> 43) == 1) u = (int32_t)(wd & M43);
+                    }
+                    if (u >= 0) {
+                        const int32_t tu = tr[u].tau, ts = tr[s].tau;
+                        const int32_t pu = wg_load(&tr[u].qpos);
+                        if ((int64_t)tu + ts <= (int64_t)U) {
+                            wg_fetch_add(&tr[u].iev, 1);
+                            if (pu >= 0) {
+                                const int32_t bk = pu >> 6;
+                                const uint64_t nk = (bk < SLC ? (uint64_t)atomicAdd(&L.sk[pu], 1ull << 21)
+                                                              : (uint64_t)wg_fetch_add(&slots[pu].k, 1ull << 21)) +
+                                                    (1ull << 21);
+                                if (bk < SC) {
+                                    atomicMax(&L.sum[2 * bk], (unsigned long long)key_of(nk, slot0));
+                                    atomicMax(&L.sum[2 * bk + 1], (unsigned long long)key_of(nk, 1));
+                                } else {
+                                    wg_fetch_max(&sums[2 * bk], (unsigned long long)key_of(nk, slot0));
+                                    wg_fetch_max(&sums[2 * bk + 1], (unsigned long long)key_of(nk, 1));
+                                }
+                            }
+                        }
+                    }
+                }
+            }
+            wg_fence();
+            if (nseg > 1) {
+                const bool in_lds = r <= kFC;
+                for (int32_t i0 = 0; i0 < r; i0 += kWave) {
+                    const int32_t i = i0 + lane;
+                    if (i < r) {
+                        const int32_t x = in_lds ? L.fr0[i] : fbuf[i];
+                        int32_t rank = 0, lo = 0;
+                        for (int32_t g = 0; g < nseg; g++) {
+                            const int32_t hi = L.seg[g];
+                            if (i >= lo && i < hi) {
+                                rank += i - lo;
+                            } else {
+                                int32_t a = lo, b = hi;
+                                while (a < b) {
+                                    const int32_t mid = (a + b) >> 1;
+                                    const int32_t y = in_lds ? L.fr0[mid] : fbuf[mid];
+                                    if (y < x) a = mid + 1;
+                                    else b = mid;
+                                }
+                                rank += a - lo;
+                            }
+                            lo = hi;
+                        }
+                        if (in_lds) L.fr1[rank] = x;
+                        else fbuf[n + rank] = x;
+                    }
+                }
+                merged = true;
+            }
+        }
+        PCLK(7);
+        wg_fence();
+        PCLK(8);
+    }
+#ifdef INSP_PHASE_CLOCKS
+    if (lane == 0 && d.id < 8192)
+        for (int i = 0; i < 10; i++) g_phase_clk[d.id * 10 + i] = pc[i];
+#endif
+    if (lane == 0) {
+        A.makespan[di] = (status & ST_HANG) ? -1 : t;
+        if (A.n_events) A.n_events[di] = events;
+        if (status) atomicOr(&A.stat[2 * d.id], status);
+        A.stat[2 * d.id + 1] = events;
+    }
+}
+
 template <int WPL>
 __global__ __launch_bounds__(64) void k_sim(SimArgs A) {
     extern __shared__ int64_t lds64[];
@@ -860,13 +1654,16 @@ __global__ __launch_bounds__(64) void k_sim(SimArgs A) {
     L.cu = L.cs + kCC;
     L.pre = L.cu + kCC;
     L.srs = L.pre + 8 * kWave;
+    L.fstk = L.srs + 64 * A.slot_cap;
+    L.stale = reinterpret_cast<uint8_t *>(L.fstk + A.sum_cap);
     const int lane = lane_id();
     for (;;) {
         int32_t got = 0;
         if (lane == 0) got = dev_fetch_add(A.counter, 1);
         const int32_t i = read_lane(got, 0);
         if (i >= A.count) break;
-        sim_dag<WPL>(A, A.order[i], L);
+        if constexpr (WPL == 1) sim_lane(A, A.order[i], L);
+        else sim_dag<WPL>(A, A.order[i], L);
         __syncthreads();
     }
 }
