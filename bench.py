@@ -31,6 +31,9 @@ SIM_BYTES_PER_EDGE = 4 + 16 + 4
 # Attribute pass over n tasks and m edges: CSR 4(n+1) + 4m, rem 4n, tau 4n,
 # ia/ie out 8n.
 ATTR_BYTES = lambda n, m: 20 * n + 4 * m + 4
+# Unpacking the schedules: a 16-byte record read, worker/start/finish/IE/mode
+# written (4 + 8 + 8 + 4 + 1 bytes) per task.
+REC_BYTES_PER_TASK = 16 + 25
 
 
 def log(*a):
@@ -116,7 +119,7 @@ def main():
     inspirit.sync_status(dag)
     ms = ev0.elapsed_time(ev1) / args.steps
     kern = {}
-    for k in ("sim", "attr_a", "attr_b", "attr_select"):
+    for k in ("sim", "attr_a", "attr_b", "attr_select", "rec"):
         tot, cnt = inspirit.profile_read(k)
         if cnt:
             kern[k] = {"avg_ms": tot / cnt, "launches": cnt}
@@ -125,7 +128,8 @@ def main():
 
     sim_bytes = SIM_BYTES_PER_TASK * N + SIM_BYTES_PER_EDGE * M
     attr_bytes = ATTR_BYTES(N, M)
-    for k, nbytes in (("sim", sim_bytes), ("attr_a", attr_bytes), ("attr_b", attr_bytes)):
+    for k, nbytes in (("sim", sim_bytes), ("attr_a", attr_bytes), ("attr_b", attr_bytes),
+                      ("rec", REC_BYTES_PER_TASK * N)):
         if k in kern:
             kern[k]["algorithmic_bytes"] = nbytes
             kern[k]["achieved_GBs"] = nbytes / (kern[k]["avg_ms"] * 1e-3) / 1e9

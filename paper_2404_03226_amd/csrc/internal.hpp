@@ -41,13 +41,20 @@ struct DevBuf {
 
 // Per-task simulation record: the release atomics and the candidate reads of a
 // task touch one 32-byte record.
+// Per-task simulation record (32 bytes, 32-byte aligned).  Bytes 16..31 are
+// one aligned vector (IE, IA, tau, first edge) read together; bytes 8..15
+// (queue slot, push order) likewise.  Once the task is popped its dependency
+// word and push order are dead, and bytes 0..15 hold its schedule instead:
+//   word = start | duration << 42,  qpos = -2 - worker,
+//   seq  = IE at pop | mode << 22.
 struct TaskRec {
     unsigned long long word;  // remaining in-degree << 43 | sum of unfinished predecessor ids
-    int32_t iev;              // current inspiring efficiency
-    int32_t qpos;             // queue slot, or -1 when not queued
-    int32_t ia, tau, rs;      // out-degree, tau, first edge (fixed during a run)
+    int32_t qpos;             // queue slot; -1 before the push; <= -2 once popped
     int32_t seq;              // push sequence number once queued
+    int32_t iev;              // current inspiring efficiency
+    int32_t ia, tau, rs;      // out-degree, tau, first edge (fixed during a run)
 };
+static_assert(sizeof(TaskRec) == 32, "TaskRec layout");
 
 // Queue slot: key word, payload word and the task's first edge.
 struct Slot {

@@ -48,7 +48,7 @@ enum { ST_EST = 1, ST_DUR = 2, ST_HANG = 4 };
 
 #ifdef INSP_PHASE_CLOCKS
 // Diagnostic build only: per-DAG core-clock totals of each event phase.
-__device__ unsigned long long g_phase_clk[8192 * 10];
+__device__ unsigned long long g_phase_clk[8192 * 16];
 #define PCLK(i) do { unsigned long long c_ = clock64(); pc[i] += c_ - pc_last; pc_last = c_; } while (0)
 #else
 #define PCLK(i) do {} while (0)
@@ -58,6 +58,28 @@ __device__ __forceinline__ uint64_t key_of(uint64_t k, int ord) {
     if (ord == 0) return k | BIT63;
     if (ord == 1) return ((k >> 21) & M21) << 42 | (k >> 42) << 21 | (k & M21) | BIT63;
     return (k & M21) | BIT63;
+}
+
+// Makes the compiler wait for a global load inside the branch that issued it.
+// A value read from LDS on one side of a uniform branch and from global memory
+// on the other otherwise arrives at the join with a pending global load, and
+// every later use waits for all outstanding global accesses -- stores
+// included -- even when the LDS side ran.
+template <typename T>
+__device__ __forceinline__ void settle(const T &x) {
+    asm volatile("" ::"v"(x));
+}
+
+// The popped task's schedule, written over its dead dependency word and
+// push order (see TaskRec): one 16-byte store.
+__device__ __forceinline__ void put_record(TaskRec *r, int64_t start, int32_t dur, int32_t w, int32_t ie, int mode) {
+    const uint64_t wd = (uint64_t)start | (uint64_t)dur << 42;
+    int4 q;
+    q.x = (int32_t)(uint32_t)wd;
+    q.y = (int32_t)(uint32_t)(wd >> 32);
+    q.z = -2 - w;
+    q.w = ie | mode << 22;
+    *reinterpret_cast<int4 *>(r) = q;
 }
 
 struct SimArgs {
@@ -76,10 +98,7 @@ struct SimArgs {
     const int32_t *dag_u, *dag_taubar;
     int32_t *stat;
     int32_t *counter;
-    int32_t *worker;
-    int64_t *start, *finish, *makespan;
-    int32_t *ie_at_pop;
-    int8_t *mode_at_pop;
+    int64_t *makespan;
     insp_trace_rec *trace;
     int32_t *n_events;
     int32_t s_inc, s_dec, dec_step, c, k_num, k_den, max_events;
@@ -192,7 +211,7 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
     int32_t peak = 0, prev_n = 0, cnt = 0;
     int mode = INSP_MODE_ABILITY;
 #ifdef INSP_PHASE_CLOCKS
-    unsigned long long pc[10] = {0}, pc_last = clock64();
+    unsigned long long pc[16] = {0}, pc_last = clock64();
 #endif
 
     for (;;) {
@@ -447,7 +466,6 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
                         tr[(int32_t)(mx >> 42)].qpos = p;
                     }
                 }
-                if (lane == 0) tr[v].qpos = -2;  // running, then done
                 len--;
                 const bool freed = (len & 63) == 0;
                 int32_t newlast = last;
@@ -501,12 +519,7 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
                     L.qest[w] -= ek;
                     L.rsr[w] = vr;
                     L.dgr[w] = deg;
-                    const int64_t uv = ub + v;
-                    A.worker[uv] = w;
-                    A.start[uv] = t;
-                    A.finish[uv] = t + dk;
-                    if (A.ie_at_pop) A.ie_at_pop[uv] = (int32_t)((vk >> 21) & M21);
-                    if (A.mode_at_pop) A.mode_at_pop[uv] = (int8_t)pmode;
+                    put_record(&tr[v], t, dk, w, (int32_t)((vk >> 21) & M21), pmode);  // running, then done
                 }
                 if constexpr (kPrefetch) {
                     // the running task's first successors, read now and used
@@ -826,7 +839,7 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
     }
 #ifdef INSP_PHASE_CLOCKS
     if (lane == 0 && d.id < 8192)
-        for (int i = 0; i < 10; i++) g_phase_clk[d.id * 10 + i] = pc[i];
+        for (int i = 0; i < 16; i++) g_phase_clk[d.id * 16 + i] = pc[i];
 #endif
     if (lane == 0) {
         A.makespan[di] = (status & ST_HANG) ? -1 : t;
@@ -841,44 +854,78 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
 // (running task, its finish and expected-end times, queue length, block count,
 // last block, the running task's row and first successors), so pushes, pops
 // and the advance read no memory for it.  Same event order and results as the
-// general loop above; the queue differs only in how a pop finds its maximum:
-//   - a worker with at most kScan blocks: every lane scans its column of all
-//     of the worker's blocks, then one wave max;
-//   - more blocks: per-block maxima pick the block first.  Maxima of blocks
-//     held in LDS are rebuilt lazily: a pop only marks the blocks it touched
-//     stale; pushes and IE increments keep raising them with atomicMax (which
-//     a later rebuild overwrites), and a many-block pop rebuilds the stale
-//     ones of its worker before comparing.  Maxima kept in global memory
-//     (block ids >= sum_cap) are rebuilt at once, as in the general loop.
+// general loop above, with two differences in the queue:
+//   - 32-bit keys.  IA and IE take `a` bits each (a = bit length of the DAG's
+//     largest out-degree; IE <= IA) and the push order `s` bits (s = bit length
+//     of n - 1), under a valid bit.  Each entry keeps both rules' keys,
+//       kA = V | IA << (a+s) | IE << s | (2^s-1-seq)   (ability; under the
+//                                                        FIFO policy V | (2^s-1-seq))
+//       kE = V | IE << (a+s) | IA << s | (2^s-1-seq)   (efficiency),
+//     so a pop compares plain words.  A DAG whose keys need more than 32 bits
+//     runs the general loop instead.
+//   - How a pop finds its maximum: a worker with at most kScan blocks has
+//     every lane scan its column of all of the worker's blocks, then one wave
+//     max; with more blocks, per-block maxima pick the block first.  Maxima of
+//     blocks held in LDS are rebuilt lazily: a pop only marks the blocks it
+//     touched stale; pushes and IE increments keep raising them with atomicMax
+//     (which a later rebuild overwrites), and a many-block pop rebuilds the
+//     stale ones of its worker before comparing.  Maxima kept in global memory
+//     (block ids >= sum_cap) are rebuilt at once.
 constexpr int kScan = 16;
 
-// Key words of the first `cnt` entries of block b, one per lane (0 above).
+// Key layout of one DAG.
+struct KeyFmt {
+    uint32_t sa, sb;    // shifts of the second and first key fields (s, a + s)
+    uint32_t smask;     // 2^s - 1
+    uint32_t amask;     // 2^a - 1
+    bool fifo;          // kA holds the FIFO key
+    __device__ __forceinline__ uint32_t ka(uint32_t ia, uint32_t ie, uint32_t seq) const {
+        return 0x80000000u | (fifo ? 0u : ia << sb | ie << sa) | (smask - seq);
+    }
+    __device__ __forceinline__ uint32_t ke(uint32_t ia, uint32_t ie, uint32_t seq) const {
+        return 0x80000000u | ie << sb | ia << sa | (smask - seq);
+    }
+    // increments of kA and kE when IE grows by one
+    __device__ __forceinline__ uint32_t da() const { return fifo ? 0u : 1u << sa; }
+    __device__ __forceinline__ uint32_t de() const { return 1u << sb; }
+};
+
+// The two key arrays of the LDS-resident slots and the 32-bit block maxima
+// (in the storage the general loop uses for its 64-bit keys and maxima).
+struct Keys32 {
+    uint32_t *ka, *ke;  // [64 * slot_cap]
+    uint32_t *mx;       // [2 * sum_cap]: max kA, max kE of each block
+};
+
+// Rule-`r` keys of the first `cnt` entries of block b, one per lane (0 above).
 // b is wave-uniform: the choice between LDS and global memory is a scalar
 // branch taken before the per-lane guard, so the two kinds of load never
 // share a destination register (which would make the LDS read wait for
 // every outstanding global access).
-__device__ __forceinline__ uint64_t block_keys(const Slot *slots, const Lds &L, int32_t slc, int32_t b, int32_t cnt) {
+__device__ __forceinline__ uint32_t block_keys32(const Slot *slots, const Keys32 &K, int32_t slc, int32_t b,
+                                                 int32_t cnt, int r) {
     const int lane = lane_id();
-    uint64_t k = 0;
+    uint32_t k = 0;
     if (b < slc) {
-        if (lane < cnt) k = L.sk[b * 64 + lane];
+        if (lane < cnt) k = (r ? K.ke : K.ka)[b * 64 + lane];
     } else {
-        if (lane < cnt) k = wg_load(&slots[b * 64 + lane].k);
+        if (lane < cnt) k = (uint32_t)(wg_load(&slots[b * 64 + lane].k) >> (r ? 32 : 0));
+        settle(k);
     }
     return k;
 }
 
-// Best key under rule `ord` in column `lane` of the listed blocks (bits of
-// `m` select lanes of `bl`, which hold block ids), four loads in flight at a
-// time; FROM_LDS picks where the blocks' slots live.
-template <bool FROM_LDS>
-__device__ __forceinline__ void scan_columns(const Slot *slots, const Lds &L, uint64_t m, int32_t bl, int32_t lastw,
-                                             int32_t lastpos, int ord, uint64_t &best, int32_t &bp) {
+// Best rule-R key in column `lane` of the listed blocks (bits of `m` select
+// lanes of `bl`, which hold block ids), four loads in flight at a time;
+// FROM_LDS picks where the blocks' slots live.
+template <bool FROM_LDS, int R>
+__device__ __forceinline__ void scan_columns(const Slot *slots, const Keys32 &K, uint64_t m, int32_t bl, int32_t lastw,
+                                             int32_t lastpos, uint32_t &best, int32_t &bp) {
     const int lane = lane_id();
+    const uint32_t *keys = R ? K.ke : K.ka;
     while (m) {
-        uint64_t kk[4];
+        uint32_t kk[4];
         int32_t pp[4];
-        bool ok[4];
 #pragma unroll
         for (int u = 0; u < 4; u++) {
             int32_t b = -1;
@@ -888,15 +935,13 @@ __device__ __forceinline__ void scan_columns(const Slot *slots, const Lds &L, ui
             }
             const int32_t cntb = b < 0 ? 0 : b == lastw ? lastpos + 1 : 64;
             pp[u] = b * 64 + lane;
-            ok[u] = lane < cntb;
-            kk[u] = 0;
-            if (ok[u]) kk[u] = FROM_LDS ? L.sk[pp[u]] : wg_load(&slots[pp[u]].k);
+            kk[u] = 0;  // below every valid key (they carry the top bit)
+            if (lane < cntb) kk[u] = FROM_LDS ? keys[pp[u]] : (uint32_t)(wg_load(&slots[pp[u]].k) >> (R ? 32 : 0));
         }
 #pragma unroll
         for (int u = 0; u < 4; u++) {
-            const uint64_t key = ok[u] ? key_of(kk[u], ord) : 0;
-            if (key > best) {
-                best = key;
+            if (kk[u] > best) {
+                best = kk[u];
                 bp = pp[u];
             }
         }
@@ -904,16 +949,16 @@ __device__ __forceinline__ void scan_columns(const Slot *slots, const Lds &L, ui
 }
 
 // Rebuild both maxima of block b from its first `cnt` entries (wave-wide).
-__device__ __forceinline__ void rebuild_max(const Slot *slots, const Lds &L, unsigned long long *sums, int32_t slc,
-                                            int32_t sc, int slot0, int32_t b, int32_t cnt) {
+__device__ __forceinline__ void rebuild_max32(const Slot *slots, const Keys32 &K, const Lds &L,
+                                              unsigned long long *sums, int32_t slc, int32_t sc, int32_t b,
+                                              int32_t cnt) {
     const int lane = lane_id();
-    const uint64_t k = block_keys(slots, L, slc, b, cnt);
-    const uint64_t s0 = wave_max_u64f(lane < cnt ? key_of(k, slot0) : 0);
-    const uint64_t s1 = wave_max_u64f(lane < cnt ? key_of(k, 1) : 0);
+    const uint32_t s0 = wave_max_u32f(block_keys32(slots, K, slc, b, cnt, 0));
+    const uint32_t s1 = wave_max_u32f(block_keys32(slots, K, slc, b, cnt, 1));
     if (lane == 0) {
         if (b < sc) {
-            L.sum[2 * b] = s0;
-            L.sum[2 * b + 1] = s1;
+            K.mx[2 * b] = s0;
+            K.mx[2 * b + 1] = s1;
             L.stale[b] = 0;
         } else {
             sums[2 * b] = s0;
@@ -922,7 +967,9 @@ __device__ __forceinline__ void rebuild_max(const Slot *slots, const Lds &L, uns
     }
 }
 
-__device__ void sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
+// Returns false, having changed nothing the general loop relies on, when the
+// DAG's keys do not fit in 32 bits.
+__device__ bool sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
     const int lane = lane_id();
     const DagDesc d = A.desc[di];
     const int32_t n = d.n, ncpu = d.n_cpu, W = d.n_cpu + d.n_gpu;
@@ -932,7 +979,7 @@ __device__ void sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
             A.makespan[di] = status ? -1 : 0;
             if (A.n_events) A.n_events[di] = 0;
         }
-        return;
+        return true;
     }
     const int64_t ub = d.toff - A.base;
     const int32_t *col = A.col + d.eoff;
@@ -948,6 +995,40 @@ __device__ void sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
     const int32_t SC = A.sum_cap;
     const int32_t kLB = A.lb;
     const int32_t SLC = A.slot_cap;
+
+    // initial frontier (tasks without predecessors, ascending) and the
+    // largest out-degree, which sizes the key fields
+    int32_t r = 0;
+    uint32_t mdeg = 0;
+    for (int32_t i0 = 0; i0 < n; i0 += kWave) {
+        int32_t i = i0 + lane;
+        bool ok = false;
+        if (i < n) {
+            ok = (tr[i].word >> 43) == 0;
+            mdeg = max(mdeg, (uint32_t)tr[i].ia);
+        }
+        uint64_t mk = ballot(ok);
+        if (ok) {
+            int32_t pos = r + lanes_below(mk);
+            fbuf[pos] = i;
+            if (pos < kFC) L.fr0[pos] = i;
+        }
+        r += __popcll(mk);
+    }
+    mdeg = wave_max_u32f(mdeg);
+    const uint32_t abits = mdeg == 0 ? 1 : 32 - __clz(mdeg);
+    const uint32_t sbits = n <= 1 ? 1 : 32 - __clz(n - 1);
+    if (1 + 2 * abits + sbits > 32) return false;
+    KeyFmt kf;
+    kf.sa = sbits;
+    kf.sb = abits + sbits;
+    kf.smask = (1u << sbits) - 1;
+    kf.amask = (1u << abits) - 1;
+    kf.fifo = A.policy == INSP_POLICY_FIFO;
+    Keys32 K;
+    K.ka = reinterpret_cast<uint32_t *>(L.sk);
+    K.ke = K.ka + 64 * SLC;
+    K.mx = reinterpret_cast<uint32_t *>(L.sum);
     const int32_t U = A.dag_u[d.id];
 
     const int32_t s_inc = A.s_inc > 0 ? A.s_inc : max(1, (W + 3) / 4);
@@ -957,7 +1038,6 @@ __device__ void sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
     const bool kset = A.k_num > 0 && A.k_den > 0;
     const int32_t k_num = kset ? A.k_num : W;
     const int32_t k_den = kset ? A.k_den : A.dag_taubar[d.id];
-    const int slot0 = A.policy == INSP_POLICY_FIFO ? 2 : 0;
     const int32_t max_events = A.max_events > 0 ? A.max_events : n + 1;
 
     // this lane's worker
@@ -975,19 +1055,6 @@ __device__ void sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
     for (int32_t i = lane; i < d.nblk - nl; i += kWave) freeb[i] = d.nblk - 1 - i;
     int32_t nfl = nl, nfg = d.nblk - nl;
 
-    // initial frontier: tasks without predecessors, ascending
-    int32_t r = 0;
-    for (int32_t i0 = 0; i0 < n; i0 += kWave) {
-        int32_t i = i0 + lane;
-        bool ok = i < n && (tr[i].word >> 43) == 0;
-        uint64_t mk = ballot(ok);
-        if (ok) {
-            int32_t pos = r + lanes_below(mk);
-            fbuf[pos] = i;
-            if (pos < kFC) L.fr0[pos] = i;
-        }
-        r += __popcll(mk);
-    }
     bool merged = false, staged = false;
     wg_fence();
 
@@ -996,7 +1063,7 @@ __device__ void sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
     int32_t peak = 0, prev_n = 0, cnt = 0;
     int mode = INSP_MODE_ABILITY;
 #ifdef INSP_PHASE_CLOCKS
-    unsigned long long pc[10] = {0}, pc_last = clock64();
+    unsigned long long pc[16] = {0}, pc_last = clock64();
 #endif
 
     for (;;) {
@@ -1033,9 +1100,10 @@ __device__ void sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
                 if (ok) {
                     e_l = est2[v_l];
                     d_l = dur2[v_l];
-                    ia_l = tr[v_l].ia;
-                    rs_l = tr[v_l].rs;
-                    ie_l = wg_load(&tr[v_l].iev);
+                    const int4 fx = *reinterpret_cast<const int4 *>(&tr[v_l].iev);  // IE, IA, tau, first edge
+                    ie_l = fx.x;
+                    ia_l = fx.y;
+                    rs_l = fx.w;
                 }
             }
             if (ballot(ok && (d_l.x < 1 || d_l.x > INSP_MAX_TICK || d_l.y < 1 || d_l.y > INSP_MAX_TICK)))
@@ -1067,6 +1135,7 @@ __device__ void sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
                     } else {
                         nfg--;
                         blk = wg_load(&freeb[nfg]);
+                        settle(blk);
                     }
                     const int32_t nbw = read_lane(nb, ws);
                     if (lane == 0) {
@@ -1100,29 +1169,29 @@ __device__ void sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
             // and the compiler keeps the stores of some lanes ahead of the
             // atomics of the others.
             const int32_t bq = pq >> 6;
-            uint64_t a0 = 0, a1 = 0;
+            uint32_t a0 = 0, a1 = 0;
             if (ok) {
                 const bool g = wsj >= ncpu;
                 const int32_t ekl = g ? e_l.y : e_l.x, dkl = g ? d_l.y : d_l.x;
-                const uint64_t kw = (uint64_t)ia_l << 42 | (uint64_t)ie_l << 21 | (M21 - (uint64_t)sqj);
+                a0 = kf.ka((uint32_t)ia_l, (uint32_t)ie_l, (uint32_t)sqj);
+                a1 = kf.ke((uint32_t)ia_l, (uint32_t)ie_l, (uint32_t)sqj);
                 const uint64_t xw = (uint64_t)v_l << 42 | (uint64_t)(dkl & M21) << 21 | (uint64_t)(ekl & M21);
                 if (bq < SLC) {
-                    L.sk[pq] = kw;
+                    K.ka[pq] = a0;
+                    K.ke[pq] = a1;
                     L.sx[pq] = xw;
                     L.srs[pq] = rs_l;
                 } else {
-                    slots[pq].k = kw;
+                    slots[pq].k = (uint64_t)a1 << 32 | a0;
                     slots[pq].x = xw;
                     slots[pq].rs = rs_l;
                 }
                 tr[v_l].qpos = pq;
                 tr[v_l].seq = sqj;
-                a0 = key_of(kw, slot0);
-                a1 = key_of(kw, 1);
                 if ((pq & 63) == 0) {
                     if (bq < SC) {
-                        L.sum[2 * bq] = a0;
-                        L.sum[2 * bq + 1] = a1;
+                        K.mx[2 * bq] = a0;
+                        K.mx[2 * bq + 1] = a1;
                         L.stale[bq] = 0;
                     } else {
                         sums[2 * bq] = a0;
@@ -1132,8 +1201,8 @@ __device__ void sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
             }
             if (ok) {
                 if (bq < SC) {
-                    atomicMax(&L.sum[2 * bq], (unsigned long long)a0);
-                    atomicMax(&L.sum[2 * bq + 1], (unsigned long long)a1);
+                    atomicMax(&K.mx[2 * bq], a0);
+                    atomicMax(&K.mx[2 * bq + 1], a1);
                 } else {
                     wg_fetch_max(&sums[2 * bq], (unsigned long long)a0);
                     wg_fetch_max(&sums[2 * bq + 1], (unsigned long long)a1);
@@ -1184,31 +1253,44 @@ __device__ void sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
             const int32_t nbw = read_lane(nb, w), lenw = read_lane(len, w), lastw = read_lane(last, w);
             const int32_t lastpos = (lenw - 1) & 63;
             int32_t p;
+            PCLK(10);
             if (nbw <= kScan) {
                 // lane l compares entry l of every block of the worker: the
-                // blocks held in LDS, then those in global memory
+                // blocks held in LDS, then those in global memory (a single
+                // block is the last one, known without reading the list)
+                // (at most 16 blocks: the list's LDS part holds them all, as its
+                // capacity is at least min(16, blocks in the pool))
                 int32_t bl = -1;
-                if (nbw <= kLB) {
-                    if (lane < nbw) bl = L.blist[w * kLB + lane];
-                } else {
-                    if (lane < nbw) bl = lane < kLB ? L.blist[w * kLB + lane] : wg_load(&wblk[(int64_t)w * maxb + lane]);
-                }
-                const uint64_t all = ballot(lane < nbw);
-                const uint64_t inl = ballot(lane < nbw && bl < SLC);
-                uint64_t best = 0;
+                if (nbw == 1) bl = lastw;
+                else if (lane < nbw) bl = L.blist[w * kLB + lane];
+                const uint64_t all = nbw == 1 ? 1ull : ballot(lane < nbw);
+                const uint64_t inl = nbw == 1 ? (lastw < SLC ? 1ull : 0ull) : ballot(lane < nbw && bl < SLC);
+                uint32_t best = 0;
                 int32_t bp = -1;
-                scan_columns<true>(slots, L, inl, bl, lastw, lastpos, ord, best, bp);
-                scan_columns<false>(slots, L, all & ~inl, bl, lastw, lastpos, ord, best, bp);
-                const uint64_t km = wave_max_u64f(best);
+                if (slot) {
+                    scan_columns<true, 1>(slots, K, inl, bl, lastw, lastpos, best, bp);
+                    scan_columns<false, 1>(slots, K, all & ~inl, bl, lastw, lastpos, best, bp);
+                } else {
+                    scan_columns<true, 0>(slots, K, inl, bl, lastw, lastpos, best, bp);
+                    scan_columns<false, 0>(slots, K, all & ~inl, bl, lastw, lastpos, best, bp);
+                }
+                const uint32_t km = wave_max_u32f(best);
                 p = read_lane(bp, (int)__builtin_ctzll(ballot(best == km && bp >= 0)));
             } else {
                 // many blocks: rebuild stale maxima, pick the block, scan it
-                uint64_t bk = 0;
+                uint32_t bk = 0;
                 int32_t bid = -1;
                 for (int32_t i0 = 0; i0 < nbw; i0 += kWave) {
                     const int32_t i = i0 + lane;
                     int32_t b = -1;
-                    if (i < nbw) b = i < kLB ? L.blist[w * kLB + i] : wg_load(&wblk[(int64_t)w * maxb + i]);
+                    if (i < nbw) {
+                        if (i < kLB) {
+                            b = L.blist[w * kLB + i];
+                        } else {
+                            b = wg_load(&wblk[(int64_t)w * maxb + i]);
+                            settle(b);
+                        }
+                    }
                     bool st = false;
                     if (b >= 0 && b < SC) st = L.stale[b] != 0;
                     uint64_t sm = ballot(st);
@@ -1216,60 +1298,77 @@ __device__ void sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
                         const int l = (int)__builtin_ctzll(sm);
                         sm &= sm - 1;
                         const int32_t sb = read_lane(b, l);
-                        rebuild_max(slots, L, sums, SLC, SC, slot0, sb, sb == lastw ? lastpos + 1 : 64);
+                        rebuild_max32(slots, K, L, sums, SLC, SC, sb, sb == lastw ? lastpos + 1 : 64);
                     }
                     if (b >= 0) {
-                        const uint64_t k = b < SC ? L.sum[2 * b + slot] : wg_load(&sums[2 * b + slot]);
+                        uint32_t k;
+                        if (b < SC) {
+                            k = K.mx[2 * b + slot];
+                        } else {
+                            k = (uint32_t)wg_load(&sums[2 * b + slot]);
+                            settle(k);
+                        }
                         if (k > bk) {
                             bk = k;
                             bid = b;
                         }
                     }
                 }
-                const uint64_t kmb = wave_max_u64f(bk);
+                const uint32_t kmb = wave_max_u32f(bk);
                 const int32_t bb = read_lane(bid, (int)__builtin_ctzll(ballot(bk == kmb && bid >= 0)));
                 const int32_t cntb = bb == lastw ? lastpos + 1 : 64;
-                const uint64_t kb = block_keys(slots, L, SLC, bb, cntb);
-                const uint64_t key = lane < cntb ? key_of(kb, ord) : 0;
-                const uint64_t km = wave_max_u64f(key);
+                const uint32_t key = block_keys32(slots, K, SLC, bb, cntb, slot);
+                const uint32_t km = wave_max_u32f(key);
                 p = bb * 64 + (int)__builtin_ctzll(ballot(key == km && lane < cntb));
             }
+            PCLK(11);
             // take the entry at p; the worker's final entry q fills the hole
             const int32_t bb = p >> 6;
             const int32_t q = lastw * 64 + lastpos;
-            uint64_t vk, vx, mk = 0, mx = 0;
+            uint32_t ve, ma = 0, me = 0;
+            uint64_t vx, mx = 0;
             int32_t vr, mr = 0;
             if (bb < SLC) {
-                vk = L.sk[p];
+                ve = K.ke[p];
                 vx = L.sx[p];
                 vr = L.srs[p];
             } else {
-                vk = wg_load(&slots[p].k);
+                ve = (uint32_t)(wg_load(&slots[p].k) >> 32);
                 vx = wg_load(&slots[p].x);
                 vr = wg_load(&slots[p].rs);
+                settle(ve);
+                settle(vx);
+                settle(vr);
             }
             if (p != q) {
                 if (lastw < SLC) {
-                    mk = L.sk[q];
+                    ma = K.ka[q];
+                    me = K.ke[q];
                     mx = L.sx[q];
                     mr = L.srs[q];
                 } else {
-                    mk = wg_load(&slots[q].k);
+                    const uint64_t mk = wg_load(&slots[q].k);
                     mx = wg_load(&slots[q].x);
                     mr = wg_load(&slots[q].rs);
+                    settle(mk);
+                    settle(mx);
+                    settle(mr);
+                    ma = (uint32_t)mk;
+                    me = (uint32_t)(mk >> 32);
                 }
             }
             const int32_t v = (int32_t)(vx >> 42);
             const int32_t dk = (int32_t)((vx >> 21) & M21), ek = (int32_t)(vx & M21);
-            const int32_t deg = (int32_t)(vk >> 42);
+            const int32_t deg = (int32_t)((ve >> kf.sa) & kf.amask);
             if (p != q) {
                 if (lane == 0) {
                     if (bb < SLC) {
-                        L.sk[p] = mk;
+                        K.ka[p] = ma;
+                        K.ke[p] = me;
                         L.sx[p] = mx;
                         L.srs[p] = mr;
                     } else {
-                        slots[p].k = mk;
+                        slots[p].k = (uint64_t)me << 32 | ma;
                         slots[p].x = mx;
                         slots[p].rs = mr;
                     }
@@ -1279,6 +1378,7 @@ __device__ void sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
                     mvp = p;
                 }
             }
+            PCLK(12);
             const int32_t nlen = lenw - 1;
             const bool freed = (nlen & 63) == 0;
             int32_t nbn = nbw, newlast = lastw;
@@ -1290,8 +1390,14 @@ __device__ void sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
                 if (lastw < SC) nfl++;
                 else nfg++;
                 nbn = nbw - 1;
-                newlast = nbn <= 0 ? -1 : nbn - 1 < kLB ? L.blist[w * kLB + nbn - 1]
-                                                        : wg_load(&wblk[(int64_t)w * maxb + nbn - 1]);
+                if (nbn <= 0) {
+                    newlast = -1;
+                } else if (nbn - 1 < kLB) {
+                    newlast = L.blist[w * kLB + nbn - 1];
+                } else {
+                    newlast = wg_load(&wblk[(int64_t)w * maxb + nbn - 1]);
+                    settle(newlast);
+                }
             }
             // maxima of the blocks that changed: bb lost the winner (and took
             // the final entry), the last block lost its final entry
@@ -1299,16 +1405,17 @@ __device__ void sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
                 if (bb < SC) {
                     if (lane == 0) L.stale[bb] = 1;
                 } else {
-                    rebuild_max(slots, L, sums, SLC, SC, slot0, bb, bb == lastw ? lastpos : 64);
+                    rebuild_max32(slots, K, L, sums, SLC, SC, bb, bb == lastw ? lastpos : 64);
                 }
             }
             if (lastw != bb && !freed) {
                 if (lastw < SC) {
                     if (lane == 0) L.stale[lastw] = 1;
                 } else {
-                    rebuild_max(slots, L, sums, SLC, SC, slot0, lastw, lastpos);
+                    rebuild_max32(slots, K, L, sums, SLC, SC, lastw, lastpos);
                 }
             }
+            PCLK(13);
             if (lane == w) {
                 len = nlen;
                 nb = nbn;
@@ -1319,27 +1426,24 @@ __device__ void sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
                 qest -= ek;
                 rsr = vr;
                 dgr = deg;
-                iep = (int32_t)((vk >> 21) & M21);
+                iep = (int32_t)((ve >> kf.sb) & kf.amask);
                 popnow = true;
             }
             nready--;
             popped++;
+            PCLK(14);
         }
-        // the event's pops write their records with one store per array (a
-        // worker pops at most once per event, so the addresses differ), and
-        // prefetch the first successors of the tasks they started
-        if (popnow) {
-            tr[run].qpos = -2;  // running, then done
-            const int64_t uv = ub + run;
-            A.worker[uv] = lane;
-            A.start[uv] = t;
-            A.finish[uv] = fin;
-            if (A.ie_at_pop) A.ie_at_pop[uv] = iep;
-            if (A.mode_at_pop) A.mode_at_pop[uv] = (int8_t)pmode;
+        // the event's pops write their records with one store (a worker pops
+        // at most once per event, so the addresses differ), and prefetch the
+        // first successors of the tasks they started
+        if (popnow) put_record(&tr[run], t, (int32_t)(fin - t), lane, iep, pmode);
+        if (popnow && dgr > 0) {
+            // entries past the row repeat its last successor (never used)
 #pragma unroll
-            for (int j = 0; j < kPF; j++) pf[j] = j < dgr ? col[rsr + j] : 0;
+            for (int j = 0; j < kPF; j++) pf[j] = col[rsr + min(j, dgr - 1)];
         }
         if (mvt >= 0) tr[mvt].qpos = mvp;
+        PCLK(15);
         PCLK(2);
         if (A.trace && lane == 0 && events <= max_events) {
             insp_trace_rec rec;
@@ -1442,21 +1546,25 @@ __device__ void sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
             const int32_t fv = hf ? L.fr0[lane] : 0;
             int32_t tu = 0, ts = 0, iu = 0, qu = -1, au = 0, sq = 0;
             if (u >= 0) {
-                tu = tr[u].tau;
+                // one wave owns the records, so plain vector loads see its stores
+                const int2 qs = *reinterpret_cast<const int2 *>(&tr[u].qpos);  // queue slot, push order
+                const int4 fx = *reinterpret_cast<const int4 *>(&tr[u].iev);   // IE, IA, tau, first edge
                 ts = tr[s].tau;
-                iu = wg_load(&tr[u].iev);
-                qu = wg_load(&tr[u].qpos);
-                au = tr[u].ia;
-                sq = wg_load(&tr[u].seq);
+                qu = qs.x;
+                sq = qs.y;
+                iu = fx.x;
+                au = fx.y;
+                tu = fx.z;
             }
             int2 fe = make_int2(1, 1), fd = make_int2(1, 1);
             int32_t fa = 0, frs = 0, fie = 0;
             if (hf) {
                 fe = est2[fv];
                 fd = dur2[fv];
-                fa = tr[fv].ia;
-                frs = tr[fv].rs;
-                fie = wg_load(&tr[fv].iev);
+                const int4 fx = *reinterpret_cast<const int4 *>(&tr[fv].iev);
+                fie = fx.x;
+                fa = fx.y;
+                frs = fx.w;
             }
             const bool cond = u >= 0 && (int64_t)tu + ts <= (int64_t)U;
             int32_t mult = 0;
@@ -1473,16 +1581,21 @@ __device__ void sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
                 const int32_t nie = iu + mult;
                 tr[u].iev = nie;
                 if (qu >= 0) {
-                    const uint64_t nk = (uint64_t)au << 42 | (uint64_t)nie << 21 | (M21 - (uint64_t)sq);
+                    const uint32_t na = kf.ka((uint32_t)au, (uint32_t)nie, (uint32_t)sq);
+                    const uint32_t ne = kf.ke((uint32_t)au, (uint32_t)nie, (uint32_t)sq);
                     const int32_t bk = qu >> 6;
-                    if (bk < SLC) L.sk[qu] = nk;
-                    else slots[qu].k = nk;
-                    if (bk < SC) {
-                        atomicMax(&L.sum[2 * bk], (unsigned long long)key_of(nk, slot0));
-                        atomicMax(&L.sum[2 * bk + 1], (unsigned long long)key_of(nk, 1));
+                    if (bk < SLC) {
+                        K.ka[qu] = na;
+                        K.ke[qu] = ne;
                     } else {
-                        wg_fetch_max(&sums[2 * bk], (unsigned long long)key_of(nk, slot0));
-                        wg_fetch_max(&sums[2 * bk + 1], (unsigned long long)key_of(nk, 1));
+                        slots[qu].k = (uint64_t)ne << 32 | na;
+                    }
+                    if (bk < SC) {
+                        atomicMax(&K.mx[2 * bk], na);
+                        atomicMax(&K.mx[2 * bk + 1], ne);
+                    } else {
+                        wg_fetch_max(&sums[2 * bk], (unsigned long long)na);
+                        wg_fetch_max(&sums[2 * bk + 1], (unsigned long long)ne);
                     }
                 }
             }
@@ -1566,15 +1679,22 @@ __device__ void sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
                             wg_fetch_add(&tr[u].iev, 1);
                             if (pu >= 0) {
                                 const int32_t bk = pu >> 6;
-                                const uint64_t nk = (bk < SLC ? (uint64_t)atomicAdd(&L.sk[pu], 1ull << 21)
-                                                              : (uint64_t)wg_fetch_add(&slots[pu].k, 1ull << 21)) +
-                                                    (1ull << 21);
-                                if (bk < SC) {
-                                    atomicMax(&L.sum[2 * bk], (unsigned long long)key_of(nk, slot0));
-                                    atomicMax(&L.sum[2 * bk + 1], (unsigned long long)key_of(nk, 1));
+                                uint32_t na, ne;
+                                if (bk < SLC) {
+                                    na = atomicAdd(&K.ka[pu], kf.da()) + kf.da();
+                                    ne = atomicAdd(&K.ke[pu], kf.de()) + kf.de();
                                 } else {
-                                    wg_fetch_max(&sums[2 * bk], (unsigned long long)key_of(nk, slot0));
-                                    wg_fetch_max(&sums[2 * bk + 1], (unsigned long long)key_of(nk, 1));
+                                    const unsigned long long inc = (unsigned long long)kf.de() << 32 | kf.da();
+                                    const uint64_t nk = wg_fetch_add(&slots[pu].k, inc) + inc;
+                                    na = (uint32_t)nk;
+                                    ne = (uint32_t)(nk >> 32);
+                                }
+                                if (bk < SC) {
+                                    atomicMax(&K.mx[2 * bk], na);
+                                    atomicMax(&K.mx[2 * bk + 1], ne);
+                                } else {
+                                    wg_fetch_max(&sums[2 * bk], (unsigned long long)na);
+                                    wg_fetch_max(&sums[2 * bk + 1], (unsigned long long)ne);
                                 }
                             }
                         }
@@ -1618,7 +1738,7 @@ __device__ void sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
     }
 #ifdef INSP_PHASE_CLOCKS
     if (lane == 0 && d.id < 8192)
-        for (int i = 0; i < 10; i++) g_phase_clk[d.id * 10 + i] = pc[i];
+        for (int i = 0; i < 16; i++) g_phase_clk[d.id * 16 + i] = pc[i];
 #endif
     if (lane == 0) {
         A.makespan[di] = (status & ST_HANG) ? -1 : t;
@@ -1626,6 +1746,7 @@ __device__ void sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
         if (status) atomicOr(&A.stat[2 * d.id], status);
         A.stat[2 * d.id + 1] = events;
     }
+    return true;
 }
 
 template <int WPL>
@@ -1662,14 +1783,34 @@ __global__ __launch_bounds__(64) void k_sim(SimArgs A) {
         if (lane == 0) got = dev_fetch_add(A.counter, 1);
         const int32_t i = read_lane(got, 0);
         if (i >= A.count) break;
-        if constexpr (WPL == 1) sim_lane(A, A.order[i], L);
-        else sim_dag<WPL>(A, A.order[i], L);
+        if constexpr (WPL == 1) {
+            if (!sim_lane(A, A.order[i], L)) sim_dag<1>(A, A.order[i], L);
+        } else {
+            sim_dag<WPL>(A, A.order[i], L);
+        }
         __syncthreads();
     }
 }
 
 __global__ void k_counter_reset(int32_t *c) {
     if (threadIdx.x < 4) c[threadIdx.x] = 0;
+}
+
+// Unpack the schedules the simulation left in the task records into the
+// caller's arrays (tasks never popped -- a failed DAG -- are left alone).
+__global__ __launch_bounds__(256) void k_records(const TaskRec *tr, int64_t n, int32_t *worker, int64_t *start,
+                                                 int64_t *finish, int32_t *ie_at_pop, int8_t *mode_at_pop) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const int4 q = *reinterpret_cast<const int4 *>(tr + i);
+    if (q.z > -2) return;
+    const uint64_t wd = (uint64_t)(uint32_t)q.x | (uint64_t)(uint32_t)q.y << 32;
+    const int64_t s = (int64_t)(wd & ((1ull << 42) - 1));
+    worker[i] = -2 - q.z;
+    start[i] = s;
+    finish[i] = s + (int64_t)(wd >> 42);
+    if (ie_at_pop) ie_at_pop[i] = q.w & ((1 << 22) - 1);
+    if (mode_at_pop) mode_at_pop[i] = (int8_t)(q.w >> 22);
 }
 
 int launch_sim(insp_dag *dag, Workspace *ws, const insp_params &p, const int32_t *dur, const int32_t *est,
@@ -1697,12 +1838,7 @@ int launch_sim(insp_dag *dag, Workspace *ws, const insp_params &p, const int32_t
     A.dag_taubar = dag->dag_taubar.as<int32_t>();
     A.stat = dag->dag_stat.as<int32_t>();
     A.counter = ws->counter.as<int32_t>();
-    A.worker = worker;
-    A.start = start;
-    A.finish = finish;
     A.makespan = makespan;
-    A.ie_at_pop = ie_at_pop;
-    A.mode_at_pop = mode_at_pop;
     A.trace = trace;
     A.n_events = n_events;
     A.policy = p.policy;
@@ -1727,16 +1863,24 @@ int launch_sim(insp_dag *dag, Workspace *ws, const insp_params &p, const int32_t
     const size_t lds = lds_bytes(ws->max_w, A.sum_cap, A.lb, A.slot_cap);
     grid = std::max(1, std::min(grid, ws->count));
     hipLaunchKernelGGL(k_counter_reset, dim3(1), dim3(64), 0, st, A.counter);
-    ProfScope ps(st, "sim");
-    if (ws->max_w <= 64) {
-        if (lds > 65536) INSP_HIP(hipFuncSetAttribute((const void *)&k_sim<1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        hipLaunchKernelGGL(k_sim<1>, dim3(grid), dim3(64), lds, st, A);
-    } else if (ws->max_w <= 128) {
-        if (lds > 65536) INSP_HIP(hipFuncSetAttribute((const void *)&k_sim<2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        hipLaunchKernelGGL(k_sim<2>, dim3(grid), dim3(64), lds, st, A);
-    } else {
-        if (lds > 65536) INSP_HIP(hipFuncSetAttribute((const void *)&k_sim<16>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        hipLaunchKernelGGL(k_sim<16>, dim3(grid), dim3(64), lds, st, A);
+    {
+        ProfScope ps(st, "sim");
+        if (ws->max_w <= 64) {
+            if (lds > 65536) INSP_HIP(hipFuncSetAttribute((const void *)&k_sim<1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+            hipLaunchKernelGGL(k_sim<1>, dim3(grid), dim3(64), lds, st, A);
+        } else if (ws->max_w <= 128) {
+            if (lds > 65536) INSP_HIP(hipFuncSetAttribute((const void *)&k_sim<2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+            hipLaunchKernelGGL(k_sim<2>, dim3(grid), dim3(64), lds, st, A);
+        } else {
+            if (lds > 65536) INSP_HIP(hipFuncSetAttribute((const void *)&k_sim<16>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+            hipLaunchKernelGGL(k_sim<16>, dim3(grid), dim3(64), lds, st, A);
+        }
+    }
+    INSP_HIP(hipGetLastError());
+    if (ws->tasks > 0) {
+        ProfScope pr(st, "rec");
+        hipLaunchKernelGGL(k_records, dim3((unsigned)((ws->tasks + 255) / 256)), dim3(256), 0, st,
+                           dag->tr.as<TaskRec>() + ws->base, ws->tasks, worker, start, finish, ie_at_pop, mode_at_pop);
     }
     INSP_HIP(hipGetLastError());
     return INSP_OK;
@@ -1829,7 +1973,7 @@ extern "C" int insp_schedule_batch(const insp_dag *cdag, const insp_workers *wor
 
 #ifdef INSP_PHASE_CLOCKS
 extern "C" int insp_debug_phase_clocks(unsigned long long *host, int count) {
-    INSP_HIP(hipMemcpyFromSymbol(host, HIP_SYMBOL(g_phase_clk), sizeof(unsigned long long) * 10 * count));
+    INSP_HIP(hipMemcpyFromSymbol(host, HIP_SYMBOL(g_phase_clk), sizeof(unsigned long long) * 16 * count));
     return INSP_OK;
 }
 #endif

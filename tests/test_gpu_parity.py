@@ -295,6 +295,44 @@ def test_queue_spill_paths_single(insp):
         assert_same(run_gpu(insp, w), oracle.schedule(w, variant=oracle.HEAP), "wide")
 
 
+def _wide_keys(n, hub_deg, seed):
+    # layered DAG plus one hub task: the largest out-degree needs 8 bits and
+    # the push order 17, so 32-bit queue keys do not fit and the general loop
+    # (64-bit keys) runs even though the machine has few workers
+    from paper_2404_03226_amd.synth import layered_dag, Stream
+    rp, col = layered_dag(seed, 0, n, 40, 1, 4)
+    src = np.repeat(np.arange(n, dtype=np.int64), np.diff(rp))
+    hub_t = np.unique(Stream(seed, 6).randint(np.arange(hub_deg), n // 40, n - 1).astype(np.int64))
+    src = np.concatenate([src, np.zeros(hub_t.size, np.int64)])
+    dst = np.concatenate([col.astype(np.int64), hub_t])
+    key = np.unique(src * n + dst)
+    src, dst = key // n, key % n
+    rp2 = np.zeros(n + 1, np.int32)
+    np.add.at(rp2, src + 1, 1)
+    rp2 = np.cumsum(rp2).astype(np.int32)
+    dur = Stream(seed, 5).randint(np.arange(2 * n).reshape(n, 2), 1, 50).astype(np.int32)
+    return NS(n=n, row_ptr=rp2, col=dst.astype(np.int32), dur=dur, est=dur.copy(), n_cpu=6, n_gpu=2,
+              m=int(dst.size), type=np.zeros(n, np.int32), name=f"widekeys-{n}")
+
+
+def test_keys_wider_than_32_bits(insp):
+    w = _wide_keys(70000, 200, 3)
+    assert int(np.diff(w.row_ptr).max()) >= 128 and w.n - 1 >= 1 << 16
+    for pol in ("inspirit", "fifo"):
+        say("wide keys", pol)
+        assert_same(run_gpu(insp, w, pol), oracle.schedule(w, policy=pol, variant=oracle.HEAP), f"wide keys {pol}")
+    # and inside a batch beside DAGs that fit
+    ws = [w] + synth.cfg3(select=[7, 70])
+    b = synth.concat(ws)
+    dag, dur, est = insp.batch_to_device(b)
+    o = insp.schedule_batch(dag, [(x.n_cpu, x.n_gpu) for x in ws], dur, est)
+    insp.sync_status(dag)
+    r = oracle.schedule_batch(b)
+    for k in ("worker", "start", "finish", "ie_at_pop", "mode_at_pop"):
+        assert np.array_equal(o[k].cpu().numpy(), r[k]), k
+    dag.free()
+
+
 def test_queue_spill_paths_batch_small_lds(insp):
     ws = [_wide(6000 + 1000 * i, 10 + i) for i in range(3)] + [_hubs(3)] + synth.cfg3(select=[4, 44])
     b = synth.concat(ws)
