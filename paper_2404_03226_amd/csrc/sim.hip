@@ -1535,15 +1535,22 @@ __device__ bool sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
             const bool hc = lane < nc;
             const int32_t s = hc ? L.cs[lane] : 0;
             int32_t u = hc ? L.cu[lane] : -1;
-            if (hc && !single)
-                for (int32_t k = 0; k < r; k++)
-                    if (L.fr0[k] == s) {
-                        u = -1;
-                        break;
-                    }
             staged = r <= kWave;
             const bool hf = staged && lane < r;
             const int32_t fv = hf ? L.fr0[lane] : 0;
+            // a candidate made ready by a later completion of this event is none
+            if (!single) {
+                if (staged) {
+                    for (int32_t k = 0; k < r; k++)
+                        if (read_lane(fv, k) == s) u = -1;
+                } else if (hc) {
+                    for (int32_t k = 0; k < r; k++)
+                        if (L.fr0[k] == s) {
+                            u = -1;
+                            break;
+                        }
+                }
+            }
             int32_t tu = 0, ts = 0, iu = 0, qu = -1, au = 0, sq = 0;
             if (u >= 0) {
                 // one wave owns the records, so plain vector loads see its stores
@@ -1608,23 +1615,11 @@ __device__ bool sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
                 if (fm && lane == (int)__builtin_ctzll(fm)) fie += kk;
             }
             int32_t pos = lane;
-            if (nseg > 1 && hf) {
-                int32_t rank = 0, lo = 0;
-                for (int32_t g = 0; g < nseg; g++) {
-                    const int32_t hi = L.seg[g];
-                    if (lane >= lo && lane < hi) {
-                        rank += lane - lo;
-                    } else {
-                        int32_t a = lo, b = hi;
-                        while (a < b) {
-                            const int32_t mid = (a + b) >> 1;
-                            if (L.fr0[mid] < fv) a = mid + 1;
-                            else b = mid;
-                        }
-                        rank += a - lo;
-                    }
-                    lo = hi;
-                }
+            if (nseg > 1 && staged) {
+                // rank in the merged ascending order (the event's ready ids are
+                // distinct): how many of them are smaller
+                int32_t rank = 0;
+                for (int32_t k = 0; k < r; k++) rank += read_lane(fv, k) < fv ? 1 : 0;
                 pos = rank;
             }
             if (!staged && nseg > 1) {
@@ -1749,8 +1744,8 @@ __device__ bool sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
     return true;
 }
 
-template <int WPL>
-__global__ __launch_bounds__(64) void k_sim(SimArgs A) {
+// The work-group's LDS, carved in the order lds_bytes() counts it.
+__device__ __forceinline__ Lds carve_lds(const SimArgs &A) {
     extern __shared__ int64_t lds64[];
     const int32_t MW = A.max_w;
     Lds L;
@@ -1777,6 +1772,12 @@ __global__ __launch_bounds__(64) void k_sim(SimArgs A) {
     L.srs = L.pre + 8 * kWave;
     L.fstk = L.srs + 64 * A.slot_cap;
     L.stale = reinterpret_cast<uint8_t *>(L.fstk + A.sum_cap);
+    return L;
+}
+
+template <int WPL>
+__global__ __launch_bounds__(64) void k_sim(SimArgs A) {
+    const Lds L = carve_lds(A);
     const int lane = lane_id();
     for (;;) {
         int32_t got = 0;
@@ -1784,7 +1785,8 @@ __global__ __launch_bounds__(64) void k_sim(SimArgs A) {
         const int32_t i = read_lane(got, 0);
         if (i >= A.count) break;
         if constexpr (WPL == 1) {
-            if (!sim_lane(A, A.order[i], L)) sim_dag<1>(A, A.order[i], L);
+            if (!sim_lane(A, A.order[i], L))
+                sim_dag<1>(A, A.order[i], L);  // keys need 64 bits
         } else {
             sim_dag<WPL>(A, A.order[i], L);
         }
