@@ -22,6 +22,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_batch4096.txt")
+SIM_SOURCES = [os.path.join(ROOT, "paper_2404_03226_amd", "csrc", f) for f in ("sim.hip", "common.hpp", "internal.hpp")]
 # Algorithmic bytes of the simulation kernel: per task, the
 # est/dur rows, ia/ie reads, queue entry write and read, queue slot, outputs,
 # row pointer pair and frontier slot; per edge, the successor id, the 64-bit
@@ -38,6 +40,40 @@ REC_BYTES_PER_TASK = 16 + 25
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def sources_sha256():
+    h = hashlib.sha256()
+    for f in SIM_SOURCES:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch of the simulation kernel from the committed
+    rocprofv3 counter summary, or None when the kernel's sources changed
+    since the counters were taken."""
+    try:
+        for line in open(TRAFFIC_FILE):
+            if line.startswith("# bench: "):
+                kv = dict(x.split("=", 1) for x in line[len("# bench: "):].split())
+                if kv.get("sources_sha256") == sources_sha256():
+                    return int(kv["traffic_bytes"])
+    except (OSError, ValueError, KeyError):
+        pass
+    return None
+
+
+def copy_calibration():
+    """A plain device copy of 256 MiB, three times: the counters' reading of
+    known traffic (FETCH_SIZE / WRITE_SIZE scale factors)."""
+    import torch
+    x = torch.ones(256 << 20, dtype=torch.uint8, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": 256 << 20, "copies": 3}), flush=True)
 
 
 def workload(name):
@@ -71,7 +107,15 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-cost-model gap")
     ap.add_argument("--no-tune", action="store_true", help="use the library's default launch shape")
     ap.add_argument("--epochs", type=int, default=10)
+    ap.add_argument("--copy-calibration", action="store_true", help="only run the counter calibration copy")
+    ap.add_argument("--print-sources-sha256", action="store_true")
     args = ap.parse_args()
+    if args.print_sources_sha256:
+        print(sources_sha256())
+        return
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: this build has no multi-GPU path "
               f"(asked for --gpus {args.gpus}); run with --gpus 1", file=sys.stderr)
@@ -136,7 +180,8 @@ def main():
     dom = max(kern, key=lambda k: kern[k]["avg_ms"])
     roof = {"bound": "hbm", "kernel": dom, "achieved": round(kern[dom].get("achieved_GBs", 0.0), 2),
             "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(kern[dom].get("achieved_GBs", 0.0) / HBM_PEAK_GBS, 5), "traffic": None,
+            "frac": round(kern[dom].get("achieved_GBs", 0.0) / HBM_PEAK_GBS, 5),
+            "traffic": measured_traffic() if dom == "sim" else None,
             "note": "the simulation is latency-bound along each DAG's chain of events; see DESIGN.md"}
 
     res = {k: out[k][:N].cpu().numpy() for k in ("worker", "start", "finish", "ie_at_pop", "mode_at_pop")}
