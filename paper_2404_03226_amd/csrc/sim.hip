@@ -865,7 +865,10 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
 //     runs the general loop instead.
 //   - How a pop finds its maximum: a worker with at most kScan blocks has
 //     every lane scan its column of all of the worker's blocks, then one wave
-//     max; with more blocks, per-block maxima pick the block first.  Maxima of
+//     max; with more blocks, per-block maxima pick the block first.  Every
+//     slot without a live entry holds zero keys (all blocks are zeroed when
+//     the DAG starts, and a pop zeroes the slot it empties), so scans read
+//     whole blocks unpredicated: valid keys carry the top bit.  Maxima of
 //     blocks held in LDS are rebuilt lazily: a pop only marks the blocks it
 //     touched stale; pushes and IE increments keep raising them with atomicMax
 //     (which a later rebuild overwrites), and a many-block pop rebuilds the
@@ -897,19 +900,17 @@ struct Keys32 {
     uint32_t *mx;       // [2 * sum_cap]: max kA, max kE of each block
 };
 
-// Rule-`r` keys of the first `cnt` entries of block b, one per lane (0 above).
-// b is wave-uniform: the choice between LDS and global memory is a scalar
-// branch taken before the per-lane guard, so the two kinds of load never
-// share a destination register (which would make the LDS read wait for
-// every outstanding global access).
-__device__ __forceinline__ uint32_t block_keys32(const Slot *slots, const Keys32 &K, int32_t slc, int32_t b,
-                                                 int32_t cnt, int r) {
+// Rule-`r` keys of block b, one per lane (zero in empty slots).  b is
+// wave-uniform: the choice between LDS and global memory is a scalar branch,
+// and the global side waits for its load itself, so the LDS side carries no
+// wait for outstanding global accesses.
+__device__ __forceinline__ uint32_t block_keys32(const Slot *slots, const Keys32 &K, int32_t slc, int32_t b, int r) {
     const int lane = lane_id();
-    uint32_t k = 0;
+    uint32_t k;
     if (b < slc) {
-        if (lane < cnt) k = (r ? K.ke : K.ka)[b * 64 + lane];
+        k = (r ? K.ke : K.ka)[b * 64 + lane];
     } else {
-        if (lane < cnt) k = (uint32_t)(wg_load(&slots[b * 64 + lane].k) >> (r ? 32 : 0));
+        k = (uint32_t)(wg_load(&slots[b * 64 + lane].k) >> (r ? 32 : 0));
         settle(k);
     }
     return k;
@@ -919,24 +920,23 @@ __device__ __forceinline__ uint32_t block_keys32(const Slot *slots, const Keys32
 // lanes of `bl`, which hold block ids), four loads in flight at a time;
 // FROM_LDS picks where the blocks' slots live.
 template <bool FROM_LDS, int R>
-__device__ __forceinline__ void scan_columns(const Slot *slots, const Keys32 &K, uint64_t m, int32_t bl, int32_t lastw,
-                                             int32_t lastpos, uint32_t &best, int32_t &bp) {
+__device__ __forceinline__ void scan_columns(const Slot *slots, const Keys32 &K, uint64_t m, int32_t bl,
+                                             uint32_t &best, int32_t &bp) {
     const int lane = lane_id();
     const uint32_t *keys = R ? K.ke : K.ka;
+    const int32_t b_last = read_lane(bl, 63 - (int)__builtin_clzll(m | 1));  // any listed block
     while (m) {
         uint32_t kk[4];
         int32_t pp[4];
 #pragma unroll
         for (int u = 0; u < 4; u++) {
-            int32_t b = -1;
+            int32_t b = b_last;  // padding re-reads a listed block: no effect on the max
             if (m) {
                 b = read_lane(bl, (int)__builtin_ctzll(m));
                 m &= m - 1;
             }
-            const int32_t cntb = b < 0 ? 0 : b == lastw ? lastpos + 1 : 64;
             pp[u] = b * 64 + lane;
-            kk[u] = 0;  // below every valid key (they carry the top bit)
-            if (lane < cntb) kk[u] = FROM_LDS ? keys[pp[u]] : (uint32_t)(wg_load(&slots[pp[u]].k) >> (R ? 32 : 0));
+            kk[u] = FROM_LDS ? keys[pp[u]] : (uint32_t)(wg_load(&slots[pp[u]].k) >> (R ? 32 : 0));
         }
 #pragma unroll
         for (int u = 0; u < 4; u++) {
@@ -950,11 +950,10 @@ __device__ __forceinline__ void scan_columns(const Slot *slots, const Keys32 &K,
 
 // Rebuild both maxima of block b from its first `cnt` entries (wave-wide).
 __device__ __forceinline__ void rebuild_max32(const Slot *slots, const Keys32 &K, const Lds &L,
-                                              unsigned long long *sums, int32_t slc, int32_t sc, int32_t b,
-                                              int32_t cnt) {
+                                              unsigned long long *sums, int32_t slc, int32_t sc, int32_t b) {
     const int lane = lane_id();
-    const uint32_t s0 = wave_max_u32f(block_keys32(slots, K, slc, b, cnt, 0));
-    const uint32_t s1 = wave_max_u32f(block_keys32(slots, K, slc, b, cnt, 1));
+    const uint32_t s0 = wave_max_u32f(block_keys32(slots, K, slc, b, 0));
+    const uint32_t s1 = wave_max_u32f(block_keys32(slots, K, slc, b, 1));
     if (lane == 0) {
         if (b < sc) {
             K.mx[2 * b] = s0;
@@ -1054,6 +1053,15 @@ __device__ bool sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
     for (int32_t i = lane; i < nl; i += kWave) L.fstk[i] = nl - 1 - i;
     for (int32_t i = lane; i < d.nblk - nl; i += kWave) freeb[i] = d.nblk - 1 - i;
     int32_t nfl = nl, nfg = d.nblk - nl;
+    // every slot starts empty (zero keys)
+    for (int32_t b = 0; b < d.nblk; b++) {
+        if (b < SLC) {
+            K.ka[b * 64 + lane] = 0;
+            K.ke[b * 64 + lane] = 0;
+        } else {
+            slots[b * 64 + lane].k = 0;
+        }
+    }
 
     bool merged = false, staged = false;
     wg_fence();
@@ -1267,12 +1275,32 @@ __device__ bool sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
                 const uint64_t inl = nbw == 1 ? (lastw < SLC ? 1ull : 0ull) : ballot(lane < nbw && bl < SLC);
                 uint32_t best = 0;
                 int32_t bp = -1;
-                if (slot) {
-                    scan_columns<true, 1>(slots, K, inl, bl, lastw, lastpos, best, bp);
-                    scan_columns<false, 1>(slots, K, all & ~inl, bl, lastw, lastpos, best, bp);
+                if (inl == all) {
+                    // every block in LDS: blocks i .. i+3 of the list, the
+                    // padding past the list re-reading its last block
+                    const uint32_t *keys = slot ? K.ke : K.ka;
+                    for (int32_t i = 0; i < nbw; i += 4) {
+                        uint32_t kk[4];
+                        int32_t pp[4];
+#pragma unroll
+                        for (int u = 0; u < 4; u++) {
+                            pp[u] = read_lane(bl, min(i + u, nbw - 1)) * 64 + lane;
+                            kk[u] = keys[pp[u]];
+                        }
+#pragma unroll
+                        for (int u = 0; u < 4; u++) {
+                            if (kk[u] > best) {
+                                best = kk[u];
+                                bp = pp[u];
+                            }
+                        }
+                    }
+                } else if (slot) {
+                    if (inl) scan_columns<true, 1>(slots, K, inl, bl, best, bp);
+                    scan_columns<false, 1>(slots, K, all & ~inl, bl, best, bp);
                 } else {
-                    scan_columns<true, 0>(slots, K, inl, bl, lastw, lastpos, best, bp);
-                    scan_columns<false, 0>(slots, K, all & ~inl, bl, lastw, lastpos, best, bp);
+                    if (inl) scan_columns<true, 0>(slots, K, inl, bl, best, bp);
+                    scan_columns<false, 0>(slots, K, all & ~inl, bl, best, bp);
                 }
                 const uint32_t km = wave_max_u32f(best);
                 p = read_lane(bp, (int)__builtin_ctzll(ballot(best == km && bp >= 0)));
@@ -1298,7 +1326,7 @@ __device__ bool sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
                         const int l = (int)__builtin_ctzll(sm);
                         sm &= sm - 1;
                         const int32_t sb = read_lane(b, l);
-                        rebuild_max32(slots, K, L, sums, SLC, SC, sb, sb == lastw ? lastpos + 1 : 64);
+                        rebuild_max32(slots, K, L, sums, SLC, SC, sb);
                     }
                     if (b >= 0) {
                         uint32_t k;
@@ -1317,7 +1345,7 @@ __device__ bool sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
                 const uint32_t kmb = wave_max_u32f(bk);
                 const int32_t bb = read_lane(bid, (int)__builtin_ctzll(ballot(bk == kmb && bid >= 0)));
                 const int32_t cntb = bb == lastw ? lastpos + 1 : 64;
-                const uint32_t key = block_keys32(slots, K, SLC, bb, cntb, slot);
+                const uint32_t key = block_keys32(slots, K, SLC, bb, slot);
                 const uint32_t km = wave_max_u32f(key);
                 p = bb * 64 + (int)__builtin_ctzll(ballot(key == km && lane < cntb));
             }
@@ -1378,6 +1406,15 @@ __device__ bool sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
                     mvp = p;
                 }
             }
+            // the worker's final slot is now empty
+            if (lane == 0) {
+                if (lastw < SLC) {
+                    K.ka[q] = 0;
+                    K.ke[q] = 0;
+                } else {
+                    slots[q].k = 0;
+                }
+            }
             PCLK(12);
             const int32_t nlen = lenw - 1;
             const bool freed = (nlen & 63) == 0;
@@ -1405,14 +1442,14 @@ __device__ bool sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
                 if (bb < SC) {
                     if (lane == 0) L.stale[bb] = 1;
                 } else {
-                    rebuild_max32(slots, K, L, sums, SLC, SC, bb, bb == lastw ? lastpos : 64);
+                    rebuild_max32(slots, K, L, sums, SLC, SC, bb);
                 }
             }
             if (lastw != bb && !freed) {
                 if (lastw < SC) {
                     if (lane == 0) L.stale[lastw] = 1;
                 } else {
-                    rebuild_max32(slots, K, L, sums, SLC, SC, lastw, lastpos);
+                    rebuild_max32(slots, K, L, sums, SLC, SC, lastw);
                 }
             }
             PCLK(13);
