@@ -4,7 +4,7 @@ A step is one pass of the whole hot path over the batch: the attribute pass
 (IA, IE, unit-time ladder) and the persistent simulation of every DAG, from
 inputs already resident in HBM.  Prints one JSON line.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload batch|large|cholesky|layered]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload batch|large|cholesky|lu|layered]
 """
 from __future__ import annotations
 
@@ -77,7 +77,28 @@ def copy_calibration():
     print(json.dumps({"copy_bytes": 256 << 20, "copies": 3}), flush=True)
 
 
-def workload(name):
+def nready_profile(rec, bins=24):
+    """Nready over simulated time: per time bin, the mean and maximum of the
+    observed ready count, the share of events under each pop rule, and the
+    pushes and pops (the per-event trace the kernel records)."""
+    t = rec["t"].astype(np.float64)
+    edges = np.linspace(0.0, max(t.max(), 1.0), bins + 1)
+    idx = np.clip(np.searchsorted(edges, t, side="right") - 1, 0, bins - 1)
+    out = []
+    for b in range(bins):
+        m = idx == b
+        if not m.any():
+            continue
+        mode = rec["mode"][m]
+        out.append({"t0": int(edges[b]), "events": int(m.sum()),
+                    "nready_mean": round(float(rec["nready"][m].mean()), 1), "nready_max": int(rec["nready"][m].max()),
+                    "ability": round(float(np.mean(mode == 0)), 3), "efficiency": round(float(np.mean(mode == 1)), 3),
+                    "efficiency_local": round(float(np.mean(mode == 2)), 3),
+                    "pushed": int(rec["pushed"][m].sum()), "popped": int(rec["popped"][m].sum())})
+    return out
+
+
+def workload(name, nb=40):
     from paper_2404_03226_amd import synth
     if name == "batch":
         ws = synth.cfg3()
@@ -87,8 +108,11 @@ def workload(name):
         ws = [synth.cfg4()]
         desc = "one power-law DAG, 2,000,000 tasks, out-degree ~ d^-2.1 on [1, 4180], 64 CPU + 8 GPU (seed 4)"
     elif name == "cholesky":
-        ws = [synth.cfg2()]
-        desc = "tiled Cholesky 40x40 (11,480 tasks), 24 CPU + 4 GPU, +-10% duration jitter (seed 2)"
+        ws = [synth.cfg2(nb=nb)]
+        desc = f"tiled Cholesky {nb}x{nb} ({ws[0].n:,} tasks), 24 CPU + 4 GPU, +-10% duration jitter (seed 2)"
+    elif name == "lu":
+        ws = [synth.lu_workload(nb=nb)]
+        desc = f"tiled LU {nb}x{nb} without pivoting ({ws[0].n:,} tasks), 24 CPU + 4 GPU, +-10% duration jitter (seed 6)"
     else:
         ws = [synth.cfg1()]
         desc = "one layered DAG, 1,000 tasks in 20 layers, 8 CPU + 2 GPU (seed 1)"
@@ -100,7 +124,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="batch", choices=["batch", "large", "cholesky", "layered"])
+    ap.add_argument("--workload", default="batch", choices=["batch", "large", "cholesky", "lu", "layered"])
     ap.add_argument("--policy", default="inspirit")
     ap.add_argument("--tune", default=None, help="launch shape, e.g. waves=1,grid=2048")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -109,6 +133,12 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="use the library's default launch shape")
     ap.add_argument("--epochs", type=int, default=10)
     ap.add_argument("--copy-calibration", action="store_true", help="only run the counter calibration copy")
+    ap.add_argument("--no-graph", action="store_true", help="skip timing hipGraph replays of the step")
+    ap.add_argument("--nb", type=int, default=40, help="tiles per side for the cholesky and lu workloads")
+    ap.add_argument("--compare-policies", action="store_true",
+                    help="makespans under each pop rule against the plain DMDA (FIFO) baseline, checked against the oracle")
+    ap.add_argument("--trace", action="store_true",
+                    help="single DAG: record the per-event trace, check it against the oracle's, report Nready over time")
     ap.add_argument("--print-sources-sha256", action="store_true")
     args = ap.parse_args()
     if args.print_sources_sha256:
@@ -127,7 +157,7 @@ def main():
     from paper_2404_03226_amd import inspirit, synth
 
     t0 = time.time()
-    ws, desc = workload(args.workload)
+    ws, desc = workload(args.workload, args.nb)
     b = synth.concat(ws)
     N, M = int(b.task_off[-1]), int(b.edge_off[-1])
     log(f"workload {args.workload}: {len(ws)} DAGs, {N} tasks, {M} edges (generated in {time.time() - t0:.1f}s)")
@@ -185,6 +215,31 @@ def main():
             "traffic": measured_traffic() if dom == "sim" else None,
             "note": "the simulation is latency-bound along each DAG's chain of events; see DESIGN.md"}
 
+    graph = None
+    if not args.no_graph and args.workload == "batch":
+        # the same step captured in a HIP graph (its launches replayed as one)
+        s2 = torch.cuda.Stream()
+        s2.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s2):
+            step()
+        torch.cuda.current_stream().wait_stream(s2)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            step()
+        for i in range(args.warmup):
+            g.replay()
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        for i in range(args.steps):
+            g.replay()
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        gms = ev0.elapsed_time(ev1) / args.steps
+        graph = {"ms_per_step": round(gms, 4), "tasks_per_s": round(N / (gms * 1e-3), 1), "replays": args.steps}
+        log(f"hipGraph replays: {gms:.3f} ms/step")
+        inspirit.sync_status(dag)
+
     res = {k: out[k][:N].cpu().numpy() for k in ("worker", "start", "finish", "ie_at_pop", "mode_at_pop")}
     res["makespan"] = out["makespan"].cpu().numpy()
     digest = hashlib.sha256(b"".join(res[k].tobytes() for k in ("worker", "start", "finish", "makespan")))
@@ -225,12 +280,49 @@ def main():
         "roofline": roof,
         "kernels": kern,
         "cpu_baseline": cpu,
+        "graph_replay": graph,
+        "nready_trace": None,
+        "policies_vs_dmda": None,
         "learned_gap": None,
     }
+    if args.compare_policies:
+        line["policies_vs_dmda"] = compare_policies(dag, workers, b, dur, est, threads)
+    if args.trace and len(ws) == 1:
+        w = ws[0]
+        o = inspirit.schedule(dag, 0, (w.n_cpu, w.n_gpu), dur, est, prm, trace=True)
+        inspirit.sync_status(dag)
+        nev = int(o["n_events"].item())
+        rec = inspirit.trace_records(o["trace"], nev)
+        ref = oracle.schedule(w, policy=args.policy, variant=oracle.HEAP, trace=True)["trace"]
+        same = bool(len(ref) == nev and all(np.array_equal(rec[f], ref[f]) for f in ref.dtype.names))
+        line["nready_trace"] = {"events": nev, "bit_exact": same, "profile": nready_profile(rec)}
     if args.workload == "batch" and not args.no_learned:
         line["learned_gap"] = learned_gap(dag, workers, b, args.epochs)
     print(json.dumps(line), flush=True)
     dag.free()
+
+
+def compare_policies(dag, workers, b, dur, est, threads):
+    """Per-DAG makespan under each pop rule relative to the plain DMDA push
+    with FIFO queues (the method's baseline): speedup = M_dmda / M_policy.
+    Every makespan is checked against the oracle's."""
+    import oracle
+    from paper_2404_03226_amd import inspirit
+    ms, exact = {}, True
+    for pol in ("fifo", "inspirit", "ability", "efi"):
+        o = inspirit.schedule_batch(dag, workers, dur, est, inspirit.params(policy=pol))
+        inspirit.sync_status(dag)
+        ms[pol] = o["makespan"].cpu().numpy().astype(np.float64)
+        ref = oracle.schedule_batch(b, policy=pol, variant=oracle.HEAP, threads=threads)["makespan"]
+        exact = exact and bool(np.array_equal(ms[pol], ref))
+    out = {"makespans_bit_exact": exact}
+    for pol in ("inspirit", "ability", "efi"):
+        sp = ms["fifo"] / ms[pol]
+        out[pol] = {"geo_mean_speedup": round(float(np.exp(np.mean(np.log(sp)))), 4),
+                    "max_speedup": round(float(sp.max()), 4), "min_speedup": round(float(sp.min()), 4),
+                    "frac_faster": round(float(np.mean(sp > 1)), 4), "frac_slower": round(float(np.mean(sp < 1)), 4)}
+    log(f"policies vs DMDA: {out}")
+    return out
 
 
 def learned_gap(dag, workers, b, epochs):

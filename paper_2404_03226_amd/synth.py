@@ -273,6 +273,81 @@ def cfg2(seed: int = 2, nb: int = 40) -> Workload:
                     est.astype(np.int32), 24, 4, {"nb": nb})
 
 
+LU_BASE = np.array([[240, 90], [300, 30], [560, 25]], dtype=np.int32)
+"""Per-kernel ticks (rows GETRF, TRSM, GEMM; columns CPU, GPU).  The paper
+prints no kernel times: a proposal in the proportions of CHOL_BASE (GETRF
+about twice POTRF's flops, TRSM and GEMM as in Cholesky)."""
+
+
+def lu_dag(nb: int) -> tuple:
+    """Right-looking tiled LU without pivoting in sequential-task-flow order.
+
+    Step k submits GETRF(k), then the row-panel TRSM(k, k, j) for j > k, then
+    the column-panel TRSM(k, i, k) for i > k, then GEMM(k, i, j) for i, j > k
+    (row-major).  Edges follow the read-after-write hazards on tiles:
+    GETRF(k) <- GEMM(k-1, k, k); TRSM(k, k, j) <- GETRF(k), GEMM(k-1, k, j);
+    TRSM(k, i, k) <- GETRF(k), GEMM(k-1, i, k);
+    GEMM(k, i, j) <- TRSM(k, i, k), TRSM(k, k, j), GEMM(k-1, i, j).
+    Types: 0 GETRF, 1 TRSM, 2 GEMM.  nb(nb+1)(2nb+1)/6 tasks.
+    """
+    ids = {}
+    types = []
+
+    def add(key, ty):
+        ids[key] = len(types)
+        types.append(ty)
+
+    for k in range(nb):
+        add(("F", k), 0)
+        for j in range(k + 1, nb):
+            add(("T", k, k, j), 1)
+        for i in range(k + 1, nb):
+            add(("T", k, i, k), 1)
+        for i in range(k + 1, nb):
+            for j in range(k + 1, nb):
+                add(("G", k, i, j), 2)
+    n = len(types)
+    succ = [[] for _ in range(n)]
+
+    def edge(a, b):
+        succ[ids[a]].append(ids[b])
+
+    for k in range(nb):
+        if k > 0:
+            edge(("G", k - 1, k, k), ("F", k))
+        for j in range(k + 1, nb):
+            edge(("F", k), ("T", k, k, j))
+            if k > 0:
+                edge(("G", k - 1, k, j), ("T", k, k, j))
+        for i in range(k + 1, nb):
+            edge(("F", k), ("T", k, i, k))
+            if k > 0:
+                edge(("G", k - 1, i, k), ("T", k, i, k))
+        for i in range(k + 1, nb):
+            for j in range(k + 1, nb):
+                edge(("T", k, i, k), ("G", k, i, j))
+                edge(("T", k, k, j), ("G", k, i, j))
+                if k > 0:
+                    edge(("G", k - 1, i, j), ("G", k, i, j))
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum([len(x) for x in succ], out=row_ptr[1:])
+    col = np.array([x for row in succ for x in row], dtype=np.int32)
+    return row_ptr.astype(np.int32), col, np.array(types, dtype=np.int32)
+
+
+def lu_workload(seed: int = 6, nb: int = 40) -> Workload:
+    """Tiled LU, ``nb`` x ``nb`` tiles; ``est = LU_BASE[type]`` and ``dur = est
+    + U{-floor(est/10)..floor(est/10)}`` per task and kind; 24 CPU + 4 GPU."""
+    row_ptr, col, ty = lu_dag(nb)
+    n = ty.shape[0]
+    est = LU_BASE[ty].astype(np.int64)
+    jit = est // 10
+    st = _sub(seed, 0, _S_JIT)
+    idx = np.arange(2 * n).reshape(n, 2)
+    dur = est + st.randint(idx, -jit, jit)
+    return Workload(f"lu-{nb}", n, row_ptr, col, ty, dur.astype(np.int32), est.astype(np.int32), 24, 4, {"nb": nb})
+
+
 # ------------------------------------------------------------------ batch
 
 def cfg3_sizes(seed: int = 3, n_dags: int = 4096) -> np.ndarray:

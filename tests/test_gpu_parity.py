@@ -154,6 +154,16 @@ def test_cfg2_cholesky(insp):
     check_schedule(w, g["worker"], g["start"], g["finish"], g["makespan"])
 
 
+@pytest.mark.parametrize("policy", ["inspirit", "fifo"])
+def test_lu_tiled(insp, policy):
+    w = synth.lu_workload(nb=24)
+    say("lu", policy)
+    g = run_gpu(insp, w, policy)
+    r = oracle.schedule(w, policy=policy, variant=oracle.HEAP)
+    assert_same(g, r, "lu")
+    check_schedule(w, g["worker"], g["start"], g["finish"], g["makespan"])
+
+
 def test_explicit_parameters(insp):
     w = synth.cfg1()
     kw = dict(unit_time=100, s_inc=2, s_dec=3, dec_step=5, c=1, k_num=3, k_den=40)

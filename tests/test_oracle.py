@@ -264,6 +264,66 @@ def test_cfg2_cholesky_counts_closed_form():
     assert synth.cfg2().n == 11480 and synth.cfg2().m == 31980
 
 
+def _stf_edges(tasks):
+    """Dependencies of a sequential task flow derived generically: each task
+    lists the tiles it reads and writes; an edge joins the last writer of a
+    tile to a later reader or writer of it, and every reader since that write
+    to a later writer."""
+    last_w, readers, edges = {}, {}, set()
+    for t, (rd, wr) in enumerate(tasks):
+        for tile in rd | wr:
+            if tile in last_w:
+                edges.add((last_w[tile], t))
+        for tile in wr:
+            for r in readers.get(tile, ()):
+                if r != t:
+                    edges.add((r, t))
+        for tile in rd:
+            readers.setdefault(tile, set()).add(t)
+        for tile in wr:
+            last_w[tile] = t
+            readers[tile] = set()
+    return edges
+
+
+def test_lu_dag_matches_generic_task_flow():
+    # tiled LU without pivoting as tile accesses, in the generator's order
+    for nb in range(1, 7):
+        tasks = []
+        for k in range(nb):
+            tasks.append(({(k, k)}, {(k, k)}))                                  # GETRF
+            for j in range(k + 1, nb):
+                tasks.append(({(k, k), (k, j)}, {(k, j)}))                      # row TRSM
+            for i in range(k + 1, nb):
+                tasks.append(({(k, k), (i, k)}, {(i, k)}))                      # column TRSM
+            for i in range(k + 1, nb):
+                for j in range(k + 1, nb):
+                    tasks.append(({(i, k), (k, j), (i, j)}, {(i, j)}))          # GEMM
+        rp, col, ty = synth.lu_dag(nb)
+        got = {(u, int(v)) for u in range(ty.size) for v in col[rp[u]:rp[u + 1]]}
+        assert got == _stf_edges(tasks), nb
+        assert ty.size == nb * (nb + 1) * (2 * nb + 1) // 6
+        oracle.canon(ty.size, rp, col)
+    w = synth.lu_workload()
+    assert w.n == 22140 and w.m == 63180
+
+
+def test_cholesky_dag_matches_generic_task_flow():
+    for nb in range(1, 7):
+        tasks = []
+        for k in range(nb):
+            tasks.append(({(k, k)}, {(k, k)}))                                  # POTRF
+            for i in range(k + 1, nb):
+                tasks.append(({(k, k), (i, k)}, {(i, k)}))                      # TRSM
+            for i in range(k + 1, nb):
+                tasks.append(({(i, k), (i, i)}, {(i, i)}))                      # SYRK
+                for j in range(k + 1, i):
+                    tasks.append(({(i, k), (j, k), (i, j)}, {(i, j)}))          # GEMM
+        rp, col, ty = synth.cholesky_dag(nb)
+        got = {(u, int(v)) for u in range(ty.size) for v in col[rp[u]:rp[u + 1]]}
+        assert got == _stf_edges(tasks), nb
+
+
 # ------------------------------------------------- independent transcriptions
 
 @pytest.mark.parametrize("chunk", range(4))
