@@ -13,9 +13,9 @@
 //   pop      every idle worker takes the best task of its own queue under the
 //            rule -- two wave-wide argmax steps over 64-slot blocks;
 //   advance  t = earliest finish among running tasks (wave min);
-//   release  for each completing task c and edge c -> s, one 64-bit atomic
-//            subtracts (1 << 43) + c from word[s] = rem << 43 | sum of
-//            unfinished predecessor ids.  rem reaching 0 makes s ready; rem
+//   release  for each completing task c and edge c -> s, one 64-bit
+//            read-modify-write (the wave owns the DAG) subtracts (1 << 43) + c
+//            from word[s] = rem << 43 | sum of unfinished predecessor ids.  rem reaching 0 makes s ready; rem
 //            reaching 1 leaves exactly one unfinished predecessor
 //            u = remaining sum, whose IE grows by one when tau(u) + tau(s)
 //            <= U (IE counts successors with rem == 1).  Newly ready ids of
@@ -48,7 +48,7 @@ enum { ST_EST = 1, ST_DUR = 2, ST_HANG = 4 };
 
 #ifdef INSP_PHASE_CLOCKS
 // Diagnostic build only: per-DAG core-clock totals of each event phase.
-__device__ unsigned long long g_phase_clk[8192 * 16];
+__device__ unsigned long long g_phase_clk[8192 * 32];
 #define PCLK(i) do { unsigned long long c_ = clock64(); pc[i] += c_ - pc_last; pc_last = c_; } while (0)
 #else
 #define PCLK(i) do {} while (0)
@@ -211,7 +211,7 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
     int32_t peak = 0, prev_n = 0, cnt = 0;
     int mode = INSP_MODE_ABILITY;
 #ifdef INSP_PHASE_CLOCKS
-    unsigned long long pc[16] = {0}, pc_last = clock64();
+    unsigned long long pc[32] = {0}, pc_last = clock64();
 #endif
 
     for (;;) {
@@ -600,8 +600,15 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
                     } else {
                         if (ok) s = col[rs + e];
                     }
+                    // one wave owns the DAG's words and a row's successors are
+                    // distinct (rows are deduplicated), so a plain
+                    // read-modify-write replaces the atomic (a wave's accesses
+                    // to one address complete in program order)
                     uint64_t old = 0;
-                    if (ok) old = wg_fetch_add(&tr[s].word, dec);
+                    if (ok) {
+                        old = tr[s].word;
+                        tr[s].word = old + dec;
+                    }
                     const int32_t nr = (int32_t)(old >> 43) - 1;
                     const bool rdy = ok && nr == 0, cd = ok && nr == 1;
                     const uint64_t m1 = ballot(rdy), m2 = ballot(cd);
@@ -839,7 +846,7 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
     }
 #ifdef INSP_PHASE_CLOCKS
     if (lane == 0 && d.id < 8192)
-        for (int i = 0; i < 16; i++) g_phase_clk[d.id * 16 + i] = pc[i];
+        for (int i = 0; i < 32; i++) g_phase_clk[d.id * 32 + i] = pc[i];
 #endif
     if (lane == 0) {
         A.makespan[di] = (status & ST_HANG) ? -1 : t;
@@ -1071,7 +1078,7 @@ __device__ bool sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
     int32_t peak = 0, prev_n = 0, cnt = 0;
     int mode = INSP_MODE_ABILITY;
 #ifdef INSP_PHASE_CLOCKS
-    unsigned long long pc[16] = {0}, pc_last = clock64();
+    unsigned long long pc[32] = {0}, pc_last = clock64();
 #endif
 
     for (;;) {
@@ -1116,6 +1123,7 @@ __device__ bool sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
             }
             if (ballot(ok && (d_l.x < 1 || d_l.x > INSP_MAX_TICK || d_l.y < 1 || d_l.y > INSP_MAX_TICK)))
                 status |= ST_DUR;
+            PCLK(16);
             const int32_t cntj = min(kWave, r - i0);
             int32_t pq = 0, sqj = 0, wsj = 0;  // lane j: slot, push order and worker of task j
             for (int32_t j = 0; j < cntj; j++) {
@@ -1170,6 +1178,7 @@ __device__ bool sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
                 seq++;
                 nready++;
             }
+            PCLK(17);
             // the chunk's queue entries, task records and block maxima: lane j
             // writes task j's.  The first entry of a new block sets its maxima,
             // then every entry raises them -- the first one's lane too, so that
@@ -1532,11 +1541,20 @@ __device__ bool sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
                         }
                     }
                     if (ok && e >= kPF) s = col[rs + e];
+                    PCLK(19);
+                    // one wave owns the DAG's words and a row's successors are
+                    // distinct (rows are deduplicated), so a plain
+                    // read-modify-write replaces the atomic (a wave's accesses
+                    // to one address complete in program order)
                     uint64_t old = 0;
-                    if (ok) old = wg_fetch_add(&tr[s].word, dec);
+                    if (ok) {
+                        old = tr[s].word;
+                        tr[s].word = old + dec;
+                    }
                     const int32_t nr = (int32_t)(old >> 43) - 1;
                     const bool rdy = ok && nr == 0, cd = ok && nr == 1;
                     const uint64_t m1 = ballot(rdy), m2 = ballot(cd);
+                    PCLK(20);
                     if (rdy) {
                         const int32_t pos = r + lanes_below(m1);
                         fbuf[pos] = s;
@@ -1588,6 +1606,7 @@ __device__ bool sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
                         }
                 }
             }
+            PCLK(22);
             int32_t tu = 0, ts = 0, iu = 0, qu = -1, au = 0, sq = 0;
             if (u >= 0) {
                 // one wave owns the records, so plain vector loads see its stores
@@ -1611,14 +1630,20 @@ __device__ bool sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
                 frs = fx.w;
             }
             const bool cond = u >= 0 && (int64_t)tu + ts <= (int64_t)U;
-            int32_t mult = 0;
+            PCLK(23);
+            int32_t mult = cond ? 1 : 0;
             bool lead = cond;
-            for (int32_t j = 0; j < nc; j++) {
-                const int32_t uj = read_lane(u, j);
-                const int32_t cj = read_lane(cond ? 1 : 0, j);
-                if (cj && cond && uj == u) {
-                    mult++;
-                    if (j < lane) lead = false;
+            if (nc > 1) {
+                // several successors may name the same predecessor: the
+                // first lane applies all of its increments
+                mult = 0;
+                for (int32_t j = 0; j < nc; j++) {
+                    const int32_t uj = read_lane(u, j);
+                    const int32_t cj = read_lane(cond ? 1 : 0, j);
+                    if (cj && cond && uj == u) {
+                        mult++;
+                        if (j < lane) lead = false;
+                    }
                 }
             }
             if (lead) {
@@ -1643,6 +1668,7 @@ __device__ bool sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
                     }
                 }
             }
+            PCLK(24);
             uint64_t lm = ballot(lead && qu == -1);
             while (lm) {
                 const int l = (int)__builtin_ctzll(lm);
@@ -1770,7 +1796,7 @@ __device__ bool sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
     }
 #ifdef INSP_PHASE_CLOCKS
     if (lane == 0 && d.id < 8192)
-        for (int i = 0; i < 16; i++) g_phase_clk[d.id * 16 + i] = pc[i];
+        for (int i = 0; i < 32; i++) g_phase_clk[d.id * 32 + i] = pc[i];
 #endif
     if (lane == 0) {
         A.makespan[di] = (status & ST_HANG) ? -1 : t;
@@ -2012,7 +2038,7 @@ extern "C" int insp_schedule_batch(const insp_dag *cdag, const insp_workers *wor
 
 #ifdef INSP_PHASE_CLOCKS
 extern "C" int insp_debug_phase_clocks(unsigned long long *host, int count) {
-    INSP_HIP(hipMemcpyFromSymbol(host, HIP_SYMBOL(g_phase_clk), sizeof(unsigned long long) * 16 * count));
+    INSP_HIP(hipMemcpyFromSymbol(host, HIP_SYMBOL(g_phase_clk), sizeof(unsigned long long) * 32 * count));
     return INSP_OK;
 }
 #endif
