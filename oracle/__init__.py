@@ -32,7 +32,7 @@ _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 OK, E_INVAL, E_CYCLE, E_RANGE, E_NOMEM, E_HANG = 0, 1, 2, 3, 4, 6
-POLICY = {"inspirit": 0, "fifo": 1, "ability": 2, "efi": 3}
+POLICY = {"inspirit": 0, "fifo": 1, "ability": 2, "efi": 3, "heft": 4}
 MODE_ABILITY, MODE_EFI, MODE_EFI_LOC, MODE_FIFO = 0, 1, 2, 3
 PLAIN, HEAP = 0, 1
 

@@ -37,8 +37,8 @@
 #include <string.h>
 
 enum { ORC_OK = 0, ORC_E_INVAL = 1, ORC_E_CYCLE = 2, ORC_E_RANGE = 3, ORC_E_NOMEM = 4, ORC_E_HANG = 6 };
-enum { POL_INSPIRIT = 0, POL_FIFO = 1, POL_ABILITY = 2, POL_EFI = 3 };
-enum { M_ABILITY = 0, M_EFI = 1, M_EFI_LOC = 2, M_FIFO = 3 };
+enum { POL_INSPIRIT = 0, POL_FIFO = 1, POL_ABILITY = 2, POL_EFI = 3, POL_RANK = 4 };
+enum { M_ABILITY = 0, M_EFI = 1, M_EFI_LOC = 2, M_FIFO = 3, M_RANK = 4 };
 enum { ORC_PLAIN = 0, ORC_HEAP = 1 };
 
 #define ORC_MAX_N (1 << 21)
@@ -261,12 +261,16 @@ typedef struct { hent *a; int64_t len, cap; } heap;
 
 typedef struct {
     const int32_t *ia, *ie, *seq;
-    int order;  /* 0: ability first, 1: efficiency first, 2: push order */
+    int order;  /* 0: ability first, 1: efficiency first, 2: push order, 3: upward rank */
+    const int64_t *rank;
 } hctx;
 
 /* Pop priority (Section 4.4 pop rules; ties fall back to FIFO, Section 4.1):
  * ability rule (IA, IE, earlier push), efficiency rule (IE, IA, earlier
- * push), FIFO (earlier push).  Returns 1 when a outranks b. */
+ * push), FIFO (earlier push); the HEFT baseline of Section 6 compares the
+ * upward rank (then earlier push).  Returns 1 when a outranks b. */
+static int outranks_r(int order, int64_t r_a, int64_t r_b, int32_t ia_a, int32_t ie_a, int32_t sq_a, int32_t ia_b,
+                      int32_t ie_b, int32_t sq_b);
 static int outranks(int order, int32_t ia_a, int32_t ie_a, int32_t sq_a, int32_t ia_b, int32_t ie_b, int32_t sq_b) {
     if (order == 0) {
         if (ia_a != ia_b) return ia_a > ia_b;
@@ -277,9 +281,56 @@ static int outranks(int order, int32_t ia_a, int32_t ie_a, int32_t sq_a, int32_t
     }
     return sq_a < sq_b;
 }
+static int outranks_r(int order, int64_t r_a, int64_t r_b, int32_t ia_a, int32_t ie_a, int32_t sq_a, int32_t ia_b,
+                      int32_t ie_b, int32_t sq_b) {
+    if (order == 3 && r_a != r_b) return r_a > r_b;
+    if (order == 3) return sq_a < sq_b;
+    return outranks(order, ia_a, ie_a, sq_a, ia_b, ie_b, sq_b);
+}
 
 static int hless(const hctx *c, hent x, hent y) {  /* x below y in the max-heap */
-    return outranks(c->order, c->ia[y.v], y.ie, c->seq[y.v], c->ia[x.v], x.ie, c->seq[x.v]);
+    return outranks_r(c->order, c->rank ? c->rank[y.v] : 0, c->rank ? c->rank[x.v] : 0, c->ia[y.v], y.ie,
+                      c->seq[y.v], c->ia[x.v], x.ie, c->seq[x.v]);
+}
+
+/* HEFT upward rank (Topcuoglu, Hariri and Wu 2002), with no communication
+ * cost (no data model here): rank(v) = mean cost of v over the machine's
+ * workers + the largest rank of its successors.  Kept multiplied by the
+ * worker count W to stay integer (the order is unchanged):
+ *   R(v) = n_cpu * est_cpu(v) + n_gpu * est_gpu(v) + max over successors R(s).
+ * Successors first: a Kahn order from the sinks (reverse topological). */
+static int upward_rank(int32_t n, const int32_t *rp, const int32_t *col, const int32_t *est, int32_t n_cpu,
+                       int32_t n_gpu, int64_t *R) {
+    int32_t *left = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    int32_t *order = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    int32_t *prp = (int32_t *)calloc((size_t)n + 1, sizeof(int32_t));
+    int32_t *pcol = (int32_t *)malloc(sizeof(int32_t) * (size_t)(rp[n] > 0 ? rp[n] : 1));
+    int32_t *fill = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    int rc = ORC_OK;
+    if (!left || !order || !prp || !pcol || !fill) { rc = ORC_E_NOMEM; goto out; }
+    for (int32_t e = 0; e < rp[n]; e++) prp[col[e] + 1]++;
+    for (int32_t v = 0; v < n; v++) prp[v + 1] += prp[v];
+    memcpy(fill, prp, sizeof(int32_t) * (size_t)n);
+    for (int32_t v = 0; v < n; v++)
+        for (int32_t e = rp[v]; e < rp[v + 1]; e++) pcol[fill[col[e]]++] = v;
+    int32_t head = 0, tail = 0;
+    for (int32_t v = 0; v < n; v++) {
+        left[v] = rp[v + 1] - rp[v];
+        if (left[v] == 0) order[tail++] = v;
+    }
+    while (head < tail) {
+        int32_t v = order[head++];
+        int64_t best = 0;
+        for (int32_t e = rp[v]; e < rp[v + 1]; e++)
+            if (R[col[e]] > best) best = R[col[e]];
+        R[v] = (int64_t)n_cpu * est[2 * (int64_t)v] + (int64_t)n_gpu * est[2 * (int64_t)v + 1] + best;
+        for (int32_t e = prp[v]; e < prp[v + 1]; e++)
+            if (--left[pcol[e]] == 0) order[tail++] = pcol[e];
+    }
+    if (tail != n) rc = ORC_E_CYCLE;
+out:
+    free(left); free(order); free(prp); free(pcol); free(fill);
+    return rc;
 }
 
 static int hpush(heap *h, const hctx *c, hent x) {
@@ -383,10 +434,13 @@ static int simulate(int32_t n, const int32_t *rp, const int32_t *col, int32_t n_
     heap *H = (heap *)calloc((size_t)W * 2, sizeof(heap));
     int32_t *prp = NULL, *pcol = NULL, *touched = NULL;
     int32_t *done_now = (int32_t *)malloc(sizeof(int32_t) * (size_t)W);
-    if (!rem || !ia || !ie || !seq || !state || !qw || !newly || !run || !exp_end || !qest || !Q || !H || !done_now) {
+    int64_t *R = p->policy == POL_RANK ? (int64_t *)calloc((size_t)n, sizeof(int64_t)) : NULL;
+    if (!rem || !ia || !ie || !seq || !state || !qw || !newly || !run || !exp_end || !qest || !Q || !H || !done_now ||
+        (p->policy == POL_RANK && !R)) {
         rc = ORC_E_NOMEM;
         goto out;
     }
+    if (R && (rc = upward_rank(n, rp, col, est, n_cpu, n_gpu, R))) goto out;
     for (int32_t e = 0; e < rp[n]; e++) rem[col[e]]++;
     int32_t U;
     rc = orc_attributes(n, rp, col, est, n_gpu, rem, p->unit_time, ia, ie, &U);
@@ -423,7 +477,9 @@ static int simulate(int32_t n, const int32_t *rp, const int32_t *col, int32_t n_
     int32_t seqctr = 0, done = 0;
     int64_t events = 0;
     int mode_fixed = p->policy == POL_FIFO ? M_FIFO : p->policy == POL_ABILITY ? M_ABILITY
-                   : p->policy == POL_EFI ? M_EFI : -1;
+                   : p->policy == POL_EFI ? M_EFI : p->policy == POL_RANK ? M_RANK : -1;
+    /* keys that never change while queued: push order, upward rank */
+    int static_key = mode_fixed == M_FIFO || mode_fixed == M_RANK;
 
     for (;;) {
         if (++events > max_events) { rc = ORC_E_HANG; goto out; }
@@ -447,16 +503,17 @@ static int simulate(int32_t n, const int32_t *rp, const int32_t *col, int32_t n_
             if (variant == ORC_PLAIN) {
                 if (ivec_push(&Q[best], v)) { rc = ORC_E_NOMEM; goto out; }
             } else {
-                hctx c0 = {ia, ie, seq, mode_fixed == M_FIFO ? 2 : 0}, c1 = {ia, ie, seq, 1};
+                hctx c0 = {ia, ie, seq, mode_fixed == M_FIFO ? 2 : mode_fixed == M_RANK ? 3 : 0, R},
+                     c1 = {ia, ie, seq, 1, R};
                 if (hpush(&H[2 * best], &c0, (hent){v, ie[v]})) { rc = ORC_E_NOMEM; goto out; }
-                if (mode_fixed != M_FIFO && hpush(&H[2 * best + 1], &c1, (hent){v, ie[v]})) { rc = ORC_E_NOMEM; goto out; }
+                if (!static_key && hpush(&H[2 * best + 1], &c1, (hent){v, ie[v]})) { rc = ORC_E_NOMEM; goto out; }
             }
         }
         /* 2. regulate */
         int64_t observed = nready;
         if (p->policy == POL_INSPIRIT) reg_step(&reg, t, nready);
         int mode = mode_fixed >= 0 ? mode_fixed : reg.mode;
-        int order = mode == M_FIFO ? 2 : mode == M_ABILITY ? 0 : 1;
+        int order = mode == M_RANK ? 3 : mode == M_FIFO ? 2 : mode == M_ABILITY ? 0 : 1;
         /* 3. pop */
         int32_t popped = 0;
         for (int32_t w = 0; w < W; w++) {
@@ -470,7 +527,9 @@ static int simulate(int32_t n, const int32_t *rp, const int32_t *col, int32_t n_
                 for (int64_t i = 0; i < Q[w].len; i++) {
                     int32_t x = Q[w].a[i];
                     int32_t x_ie = ie_def(rp, col, est, n_gpu, rem, U, x);
-                    if (bi < 0 || outranks(order, ia[x], x_ie, seq[x], ia[Q[w].a[bi]], b_ie, seq[Q[w].a[bi]])) {
+                    int32_t y = bi < 0 ? x : Q[w].a[bi];
+                    if (bi < 0 || outranks_r(order, R ? R[x] : 0, R ? R[y] : 0, ia[x], x_ie, seq[x], ia[y], b_ie,
+                                             seq[y])) {
                         bi = i;
                         b_ie = x_ie;
                     }
@@ -481,10 +540,10 @@ static int simulate(int32_t n, const int32_t *rp, const int32_t *col, int32_t n_
                 Q[w].len--;
             } else {
                 heap *h = &H[2 * w + (order == 1 ? 1 : 0)];
-                hctx c = {ia, ie, seq, order};
+                hctx c = {ia, ie, seq, order, R};
                 while (h->len > 0) {
                     hent top = hpop(h, &c);
-                    if (state[top.v] == ST_QUEUED && (order == 2 || top.ie == ie[top.v])) { v = top.v; break; }
+                    if (state[top.v] == ST_QUEUED && (order >= 2 || top.ie == ie[top.v])) { v = top.v; break; }
                 }
                 if (v < 0) continue;
                 v_ie = ie[v];
@@ -548,8 +607,8 @@ static int simulate(int32_t n, const int32_t *rp, const int32_t *col, int32_t n_
                     if (state[pcol[e]] != ST_DONE) { u = pcol[e]; break; }
                 if ((int64_t)tau_of(est, n_gpu, u) + tau_of(est, n_gpu, s) > U) continue;
                 ie[u]++;
-                if (state[u] == ST_QUEUED && mode_fixed != M_FIFO) {
-                    hctx c0 = {ia, ie, seq, 0}, c1 = {ia, ie, seq, 1};
+                if (state[u] == ST_QUEUED && !static_key) {
+                    hctx c0 = {ia, ie, seq, 0, R}, c1 = {ia, ie, seq, 1, R};
                     if (hpush(&H[2 * qw[u]], &c0, (hent){u, ie[u]}) ||
                         hpush(&H[2 * qw[u] + 1], &c1, (hent){u, ie[u]})) { rc = ORC_E_NOMEM; goto out; }
                 }
@@ -561,7 +620,7 @@ static int simulate(int32_t n, const int32_t *rp, const int32_t *col, int32_t n_
 
 out:
     free(rem); free(ia); free(ie); free(seq); free(state); free(qw); free(newly); free(run);
-    free(exp_end); free(qest); free(done_now); free(prp); free(pcol); free(touched);
+    free(exp_end); free(qest); free(done_now); free(prp); free(pcol); free(touched); free(R);
     if (Q) for (int32_t w = 0; w < W; w++) free(Q[w].a);
     if (H) for (int32_t w = 0; w < 2 * W; w++) free(H[w].a);
     free(Q);
@@ -571,7 +630,7 @@ out:
 
 static int check_params(int32_t n, int32_t n_cpu, int32_t n_gpu, const int32_t *dur, const int32_t *est,
                         const orc_params *p) {
-    if (n_cpu < 0 || n_gpu < 0 || p->policy < 0 || p->policy > 3 || p->unit_time < 0 || p->max_events < 0)
+    if (n_cpu < 0 || n_gpu < 0 || p->policy < 0 || p->policy > 4 || p->unit_time < 0 || p->max_events < 0)
         return ORC_E_INVAL;
     int32_t W = n_cpu + n_gpu;
     if (W < 1 || W > ORC_MAX_W) return ORC_E_RANGE;

@@ -436,3 +436,68 @@ def test_w7_first_rule_is_high_ability():
     g, w = _small("w7")
     r = oracle.schedule(w)
     assert int(r["mode_at_pop"][0]) == g["mode_at_pop_first"]
+
+
+# ------------------------------------------------------------- HEFT baseline
+
+def _rank_reference(w):
+    """Upward rank from its definition, by memoised recursion over successors:
+    R(v) = n_cpu * est_cpu(v) + n_gpu * est_gpu(v) + max over successors R(s)."""
+    import functools
+    import sys
+    sys.setrecursionlimit(10000)
+    rp, col = oracle.canon(w.n, w.row_ptr, w.col)
+    est = np.asarray(w.est, np.int64).reshape(w.n, 2)
+
+    @functools.lru_cache(maxsize=None)
+    def R(v):
+        succ = col[rp[v]:rp[v + 1]]
+        return int(w.n_cpu * est[v, 0] + w.n_gpu * est[v, 1]) + max((R(int(s)) for s in succ), default=0)
+    return [R(v) for v in range(w.n)], rp, col
+
+
+def test_w8_heft_hand_worked():
+    g = gold("w8_heft.json")["w8"]
+    w = wl(g["n"], g["row_ptr"], g["col"], g["n_cpu"], g["n_gpu"], g["dur"])
+    assert _rank_reference(w)[0] == g["rank"]
+    for variant in (oracle.PLAIN, oracle.HEAP):
+        r = oracle.schedule(w, policy="heft", variant=variant)
+        assert r["worker"].tolist() == g["heft"]["worker"] and r["start"].tolist() == g["heft"]["start"]
+        assert r["makespan"] == g["heft"]["makespan"]
+        assert set(r["mode_at_pop"].tolist()) == {g["heft"]["mode_at_pop"]}
+    f = oracle.schedule(w, policy="fifo")
+    assert f["start"].tolist() == g["fifo"]["start"] and f["makespan"] == g["fifo"]["makespan"]
+
+
+@pytest.mark.parametrize("chunk", range(3))
+def test_heft_pops_the_highest_rank_of_each_queue(chunk):
+    # property of any HEFT schedule: a task is popped from its worker's queue
+    # when no task waiting in that queue (pushed, not yet started) has a higher
+    # rank, or an equal rank and an earlier readiness time (an earlier push).
+    # Ranks come from the definition above, not from the oracle.
+    for i in range(chunk * 40, chunk * 40 + 40):
+        n = 2 + i % 40
+        w = synth.random_dag(21, i, n, 0.05 + (i % 5) * 0.06, n_cpu=1 + i % 3, n_gpu=i % 3, dur_hi=30,
+                             est_equal=(i % 2 == 0))
+        R, rp, col = _rank_reference(w)
+        r = oracle.schedule(w, policy="heft", variant=oracle.HEAP)
+        start, finish, worker = r["start"], r["finish"], r["worker"]
+        ready = np.zeros(n, np.int64)
+        for v in range(n):
+            for s in col[rp[v]:rp[v + 1]]:
+                ready[s] = max(ready[s], finish[v])
+        for v in range(n):
+            waiting = [u for u in range(n) if worker[u] == worker[v] and ready[u] <= start[v] <= start[u]]
+            assert max(R[u] for u in waiting) == R[v], (i, v)
+            assert not any(R[u] == R[v] and ready[u] < ready[v] for u in waiting), (i, v)
+        check_schedule(w, worker, start, finish, r["makespan"])
+
+
+def test_heft_plain_and_heap_agree():
+    for i in range(60):
+        w = synth.random_dag(23, i, 1 + i % 45, 0.04 + (i % 6) * 0.05, n_cpu=1 + i % 4, n_gpu=i % 3, dur_hi=40,
+                             est_equal=(i % 3 != 0))
+        a = oracle.schedule(w, policy="heft", variant=oracle.PLAIN)
+        b = oracle.schedule(w, policy="heft", variant=oracle.HEAP)
+        for k in ("worker", "start", "finish", "ie_at_pop", "mode_at_pop"):
+            assert np.array_equal(a[k], b[k]), (i, k)

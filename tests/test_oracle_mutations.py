@@ -33,7 +33,7 @@ MUTATIONS = {
     "tau_cpu_column": ("return est[2 * (int64_t)v + (n_gpu > 0 ? 1 : 0)];", "return est[2 * (int64_t)v];"),
     "ability_order_reversed": ("if (ia_a != ia_b) return ia_a > ia_b;\n        if (ie_a != ie_b) return ie_a > ie_b;\n    } else if (order == 1) {",
                                "if (ia_a != ia_b) return ia_a < ia_b;\n        if (ie_a != ie_b) return ie_a > ie_b;\n    } else if (order == 1) {"),
-    "fifo_tie_latest": ("return sq_a < sq_b;", "return sq_a > sq_b;"),
+    "fifo_tie_latest": ("    }\n    return sq_a < sq_b;", "    }\n    return sq_a > sq_b;"),
     "reg_inc_margin_strict": ("if (N >= r->peak - r->dec_step) {", "if (N > r->peak - r->dec_step) {"),
     "reg_slope_flipped": ("if (dt == 0 || dn * r->k_den > r->k_num * dt) r->mode = M_ABILITY;\n            else if (dn * r->k_den < r->k_num * dt) r->mode = M_EFI;",
                           "if (dt == 0 || dn * r->k_den < r->k_num * dt) r->mode = M_ABILITY;\n            else if (dn * r->k_den > r->k_num * dt) r->mode = M_EFI;"),
@@ -42,6 +42,12 @@ MUTATIONS = {
     "reg_starts_efficiency": ("r->mode = M_ABILITY;  /* Section 3", "r->mode = M_EFI;  /* Section 3"),
     "ready_not_sorted": ("qsort(newly, (size_t)n_new, sizeof(int32_t), cmp_i32);", ""),
     "regulate_after_pop": ("int64_t observed = nready;", "int64_t observed = nready - 1;"),
+    "rank_no_successor_term": ("(int64_t)n_gpu * est[2 * (int64_t)v + 1] + best;",
+                               "(int64_t)n_gpu * est[2 * (int64_t)v + 1];"),
+    "rank_gpu_column_dropped": ("(int64_t)n_gpu * est[2 * (int64_t)v + 1] + best;", "best;"),
+    "rank_lowest_first": ("if (order == 3 && r_a != r_b) return r_a > r_b;",
+                          "if (order == 3 && r_a != r_b) return r_a < r_b;"),
+    "rank_tie_latest_push": ("if (order == 3) return sq_a < sq_b;", "if (order == 3) return sq_a > sq_b;"),
 }
 
 
@@ -123,6 +129,15 @@ def pins():
     wi = NS(n=13, row_ptr=np.zeros(14, np.int32), col=np.zeros(0, np.int32), dur=np.ones((13, 2), np.int32),
             est=np.ones((13, 2), np.int32), n_cpu=4, n_gpu=0)
     chk("indep", lambda: oracle.schedule(wi)["makespan"] == 4)
+    # HEFT: the single-worker fixture, and the rank-order pop property with
+    # ranks recomputed from their definition on mixed machines
+    g8 = json.load(open(os.path.join(GOLD, "w8_heft.json")))["w8"]
+    w8 = NS(n=g8["n"], row_ptr=np.asarray(g8["row_ptr"], np.int32), col=np.asarray(g8["col"], np.int32),
+            dur=np.asarray(g8["dur"], np.int32), est=np.asarray(g8["dur"], np.int32), n_cpu=1, n_gpu=0)
+    chk("w8", lambda: oracle.schedule(w8, policy="heft")["start"].tolist() == g8["heft"]["start"])
+    for i in range(8):
+        w = synth.random_dag(31, i, 12, 0.25, dur_hi=20, n_cpu=1 + i % 2, n_gpu=1, est_equal=(i % 2 == 0))
+        chk(f"heft{i}", lambda w=w: _heft_pops_by_rank(w))
     # invariants and brute force on small random DAGs
     for i in range(6):
         w = synth.random_dag(77, i, 7, 0.3, dur_hi=6, n_cpu=1, n_gpu=1)
@@ -132,6 +147,25 @@ def pins():
             return r["makespan"] >= oracle.brute_opt(w)
         chk(f"inv{i}", inv)
     return failed
+
+
+def _heft_pops_by_rank(w):
+    rp, col = oracle.canon(w.n, w.row_ptr, w.col)
+    est = np.asarray(w.est, np.int64).reshape(w.n, 2)
+    R = [0] * w.n
+    for v in range(w.n - 1, -1, -1):  # random_dag edges run from lower to higher ids
+        R[v] = int(w.n_cpu * est[v, 0] + w.n_gpu * est[v, 1]) + max((R[s] for s in col[rp[v]:rp[v + 1]]), default=0)
+    r = oracle.schedule(w, policy="heft")
+    start, finish, worker = r["start"], r["finish"], r["worker"]
+    ready = np.zeros(w.n, np.int64)
+    for v in range(w.n):
+        for s in col[rp[v]:rp[v + 1]]:
+            ready[s] = max(ready[s], finish[v])
+    for v in range(w.n):
+        waiting = [u for u in range(w.n) if worker[u] == worker[v] and ready[u] <= start[v] <= start[u]]
+        if max(R[u] for u in waiting) != R[v] or any(R[u] == R[v] and ready[u] < ready[v] for u in waiting):
+            return False
+    return True
 
 
 @pytest.mark.parametrize("name", sorted(MUTATIONS))
