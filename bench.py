@@ -25,7 +25,7 @@ METRIC = "tasks scheduled/s on 4096-DAG batch, bit-exact makespan; learned vs pl
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_batch4096.txt")
 SIM_SOURCES = [os.path.join(ROOT, "paper_2404_03226_amd", "csrc", f) for f in ("sim.hip", "common.hpp", "internal.hpp")]
-# Algorithmic bytes of the simulation kernel (see DESIGN.md): per task, the
+# Algorithmic bytes of the simulation kernel: per task, the
 # est/dur rows, ia/ie reads, queue entry write and read, queue slot, outputs,
 # row pointer pair and frontier slot; per edge, the successor id, the 64-bit
 # dependency word read-modify-write and a tau gather.
@@ -213,7 +213,7 @@ def main():
             "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(kern[dom].get("achieved_GBs", 0.0) / HBM_PEAK_GBS, 5),
             "traffic": measured_traffic() if dom == "sim" else None,
-            "note": "the simulation is latency-bound along each DAG's chain of events; see DESIGN.md"}
+            "note": "the simulation is latency-bound along each DAG's chain of dependent events, not HBM-bound"}
 
     graph = None
     if not args.no_graph and args.workload == "batch":
@@ -303,20 +303,21 @@ def main():
 
 
 def compare_policies(dag, workers, b, dur, est, threads):
-    """Per-DAG makespan under each pop rule relative to the plain DMDA push
-    with FIFO queues (the method's baseline): speedup = M_dmda / M_policy.
-    Every makespan is checked against the oracle's."""
+    """Per-DAG makespan under each pop rule, and under the HEFT upward-rank
+    list baseline, relative to the plain DMDA push with FIFO queues (the
+    method's baseline): speedup = M_dmda / M_policy.  Every makespan is
+    checked against the oracle's."""
     import oracle
     from paper_2404_03226_amd import inspirit
     ms, exact = {}, True
-    for pol in ("fifo", "inspirit", "ability", "efi"):
+    for pol in ("fifo", "inspirit", "ability", "efi", "heft"):
         o = inspirit.schedule_batch(dag, workers, dur, est, inspirit.params(policy=pol))
         inspirit.sync_status(dag)
         ms[pol] = o["makespan"].cpu().numpy().astype(np.float64)
         ref = oracle.schedule_batch(b, policy=pol, variant=oracle.HEAP, threads=threads)["makespan"]
         exact = exact and bool(np.array_equal(ms[pol], ref))
     out = {"makespans_bit_exact": exact}
-    for pol in ("inspirit", "ability", "efi"):
+    for pol in ("inspirit", "ability", "efi", "heft"):
         sp = ms["fifo"] / ms[pol]
         out[pol] = {"geo_mean_speedup": round(float(np.exp(np.mean(np.log(sp)))), 4),
                     "max_speedup": round(float(sp.max()), 4), "min_speedup": round(float(sp.min()), 4),

@@ -49,7 +49,11 @@ typedef enum {
     INSP_POLICY_INSPIRIT = 0,     /* adaptive: Nready regulator picks the pop rule */
     INSP_POLICY_FIFO = 1,         /* plain DMDA: each worker pops in push order */
     INSP_POLICY_ABILITY_ONLY = 2, /* always the high-ability rule */
-    INSP_POLICY_EFI_ONLY = 3      /* always the high-efficiency rule */
+    INSP_POLICY_EFI_ONLY = 3,     /* always the high-efficiency rule */
+    INSP_POLICY_HEFT = 4          /* HEFT list baseline (Section 6): highest upward rank
+                                     R(v) = n_cpu est_cpu(v) + n_gpu est_gpu(v) + max over
+                                     successors R(s), then earliest push; R < 2^42 or the
+                                     DAG fails with INSP_E_RANGE at insp_sync_status */
 } insp_policy;
 
 /* Pop rule in force at a pop (mode_at_pop) and in trace records. */
@@ -57,7 +61,8 @@ typedef enum {
     INSP_MODE_ABILITY = 0, /* highest IA, then highest IE, then earliest push */
     INSP_MODE_EFI = 1,     /* highest IE, then highest IA, then earliest push */
     INSP_MODE_EFI_LOC = 2, /* efficiency-and-locality rule; no data model, so ordered as EFI */
-    INSP_MODE_FIFO = 3     /* earliest push */
+    INSP_MODE_FIFO = 3,    /* earliest push */
+    INSP_MODE_RANK = 4     /* highest HEFT upward rank, then earliest push */
 } insp_mode;
 
 #define INSP_ALL_DAGS (-1)
@@ -198,8 +203,9 @@ int insp_schedule_batch(const insp_dag *dag, const insp_workers *workers, const 
                         int64_t *makespan, int32_t *ie_at_pop, int8_t *mode_at_pop, const char *tune_key,
                         void *stream);
 
-/* Synchronise `stream` and report a device-side failure (INSP_E_HANG) of
- * the schedule calls enqueued on the handle since the last check. */
+/* Synchronise `stream` and report a device-side failure of the schedule
+ * calls enqueued on the handle since the last check: INSP_E_HANG, or
+ * INSP_E_RANGE for a tick value out of range or a HEFT rank >= 2^42. */
 int insp_sync_status(const insp_dag *dag, void *stream);
 
 /*
@@ -215,7 +221,7 @@ int insp_profile_enable(int on);
 int insp_profile_read(const char *kernel, double *total_ms, int64_t *launches);
 
 /*
- * Learned cost model (spec extension of the paper's per-type average
+ * Learned cost model (an extension of the paper's per-type average
  * execution times, Section 4.3): a 32 -> 256 -> 256 -> 2 ReLU network that
  * predicts ln(duration) on the CPU and GPU worker kinds from 32 task
  * features.  Weights, activations and activation gradients are bfloat16,

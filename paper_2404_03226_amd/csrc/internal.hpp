@@ -118,12 +118,22 @@ struct insp_dag {
     insp::DevBuf dag_tausum;           // int64 [B]
     insp::DevBuf dag_score;            // int32 [B * 24] ladder score, difference form
     insp::DevBuf dag_stat;             // int32 [B * 2]: status, events
+    // HEFT: topological levels (built on first use) and upward ranks
+    insp::DevBuf topo;                 // int32 [N]: each DAG's tasks in level order
+    insp::DevBuf lvl;                  // int32 [N + B]: start of each level in topo, then the end
+    insp::DevBuf nlev;                 // int32 [B]: levels per DAG
+    insp::DevBuf rank;                 // int64 [N]: upward rank of the last HEFT call
     std::map<std::string, std::unique_ptr<insp::Workspace>> ws;
 };
 
 namespace insp {
 
 constexpr int kRungs = 24;       // ladder rungs 2^0 .. 2^22 plus a sentinel
+
+// Per-DAG status bits (dag_stat[2 b]): estimate or duration out of range, the
+// event budget exhausted, a HEFT rank too wide for the queue key.
+enum { ST_EST = 1, ST_DUR = 2, ST_HANG = 4, ST_RANK = 8 };
+constexpr int kRankBits = 42;
 constexpr int kAttrThreads = 256;
 
 int ensure_state(insp_dag *dag, hipStream_t st);
@@ -147,6 +157,10 @@ int get_workspace(insp_dag *dag, int32_t first, int32_t count, const insp_worker
 // per-task simulation records are reset as well.
 int run_attributes(insp_dag *dag, Workspace *ws, const int32_t *est, int32_t unit_time, const int32_t *rem,
                    int32_t *ia_out, int32_t *ie_out, bool sim_init, hipStream_t st);
+
+// HEFT upward ranks of a workspace's DAGs into dag->rank (levels are built
+// on the first call).  Runs after run_attributes, which clears the status.
+int run_rank(insp_dag *dag, Workspace *ws, const int32_t *est, hipStream_t st);
 
 int launch_sim(insp_dag *dag, Workspace *ws, const insp_params &p, const int32_t *dur, const int32_t *est,
                int32_t *worker, int64_t *start, int64_t *finish, int64_t *makespan, int32_t *ie_at_pop,

@@ -44,7 +44,6 @@ namespace insp {
 constexpr uint64_t M21 = (1ull << 21) - 1;
 constexpr uint64_t M43 = (1ull << 43) - 1;
 constexpr uint64_t BIT63 = 1ull << 63;
-enum { ST_EST = 1, ST_DUR = 2, ST_HANG = 4 };
 
 #ifdef INSP_PHASE_CLOCKS
 // Diagnostic build only: per-DAG core-clock totals of each event phase.
@@ -54,8 +53,10 @@ __device__ unsigned long long g_phase_clk[8192 * 32];
 #define PCLK(i) do {} while (0)
 #endif
 
+// Sort key of a queue entry under rule `ord`: 0 ability, 1 efficiency,
+// 2 FIFO, 3 HEFT (whose entries hold rank << 21 | (2^21-1-seq) instead).
 __device__ __forceinline__ uint64_t key_of(uint64_t k, int ord) {
-    if (ord == 0) return k | BIT63;
+    if (ord == 0 || ord == 3) return k | BIT63;
     if (ord == 1) return ((k >> 21) & M21) << 42 | (k >> 42) << 21 | (k & M21) | BIT63;
     return (k & M21) | BIT63;
 }
@@ -96,6 +97,7 @@ struct SimArgs {
     int32_t *paux;
     int64_t freeb_base;
     const int32_t *dag_u, *dag_taubar;
+    const int64_t *rank;  // HEFT upward ranks (global task index)
     int32_t *stat;
     int32_t *counter;
     int64_t *makespan;
@@ -167,7 +169,9 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
     const bool kset = A.k_num > 0 && A.k_den > 0;
     const int32_t k_num = kset ? A.k_num : W;
     const int32_t k_den = kset ? A.k_den : A.dag_taubar[d.id];
-    const int slot0 = A.policy == INSP_POLICY_FIFO ? 2 : 0;
+    const bool heft = A.policy == INSP_POLICY_HEFT;
+    const int64_t *rk = A.rank + d.toff;
+    const int slot0 = A.policy == INSP_POLICY_FIFO ? 2 : heft ? 3 : 0;
     const int32_t max_events = A.max_events > 0 ? A.max_events : n + 1;
 
     for (int32_t w = lane; w < W; w += kWave) {
@@ -238,6 +242,7 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
             int32_t v_l = 0;
             int2 e_l = make_int2(1, 1), d_l = make_int2(1, 1);
             int32_t ia_l = 0, ie_l = 0, rs_l = 0;
+            uint64_t rk_l = 0;
             if (staged) {
                 // rows loaded during the previous candidate round trip
                 if (ok) {
@@ -261,6 +266,7 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
                     ie_l = wg_load(&tr[v_l].iev);
                 }
             }
+            if (heft && ok) rk_l = (uint64_t)rk[v_l];
             if (ballot(ok && (d_l.x < 1 || d_l.x > INSP_MAX_TICK || d_l.y < 1 || d_l.y > INSP_MAX_TICK)))
                 status |= ST_DUR;
             const int32_t cntj = min(kWave, r - i0);
@@ -302,8 +308,9 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
                     blk = L.last[ws];
                 }
                 const int32_t p = blk * 64 + pos;
-                const uint64_t kw = (uint64_t)read_lane(ia_l, j) << 42 | (uint64_t)read_lane(ie_l, j) << 21 |
-                                    (M21 - (uint64_t)seq);
+                const uint64_t kw =
+                    heft ? read_lane64(rk_l, j) << 21 | (M21 - (uint64_t)seq)
+                         : (uint64_t)read_lane(ia_l, j) << 42 | (uint64_t)read_lane(ie_l, j) << 21 | (M21 - (uint64_t)seq);
                 const uint64_t xw = (uint64_t)v << 42 | (uint64_t)(dk & M21) << 21 | (uint64_t)(ek & M21);
                 const int32_t rs = read_lane(rs_l, j);
                 if (lane == 0) {
@@ -371,8 +378,9 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
         }
         const int pmode = A.policy == INSP_POLICY_FIFO ? INSP_MODE_FIFO
                         : A.policy == INSP_POLICY_ABILITY_ONLY ? INSP_MODE_ABILITY
-                        : A.policy == INSP_POLICY_EFI_ONLY ? INSP_MODE_EFI : mode;
-        const int ord = pmode == INSP_MODE_FIFO ? 2 : pmode == INSP_MODE_ABILITY ? 0 : 1;
+                        : A.policy == INSP_POLICY_EFI_ONLY ? INSP_MODE_EFI
+                        : heft ? INSP_MODE_RANK : mode;
+        const int ord = heft ? 3 : pmode == INSP_MODE_FIFO ? 2 : pmode == INSP_MODE_ABILITY ? 0 : 1;
         const int slot = ord == 1 ? 1 : 0;
         // ------------------------------------------------------------- pop
         int32_t popped = 0;
@@ -508,7 +516,9 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
                         }
                     }
                 }
-                const int32_t deg = (int32_t)(vk >> 42);
+                // HEFT keys carry the rank, not IA and IE
+                const int32_t deg = heft ? tr[v].ia : (int32_t)(vk >> 42);
+                const int32_t iep = heft ? wg_load(&tr[v].iev) : (int32_t)((vk >> 21) & M21);
                 if (lane == 0) {
                     L.len[w] = len;
                     L.nb[w] = nb;
@@ -519,7 +529,7 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
                     L.qest[w] -= ek;
                     L.rsr[w] = vr;
                     L.dgr[w] = deg;
-                    put_record(&tr[v], t, dk, w, (int32_t)((vk >> 21) & M21), pmode);  // running, then done
+                    put_record(&tr[v], t, dk, w, iep, pmode);  // running, then done
                 }
                 if constexpr (kPrefetch) {
                     // the running task's first successors, read now and used
@@ -694,7 +704,7 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
             if (lead) {
                 const int32_t nie = iu + mult;
                 tr[u].iev = nie;
-                if (qu >= 0) {
+                if (qu >= 0 && !heft) {
                     const uint64_t nk = (uint64_t)au << 42 | (uint64_t)nie << 21 | (M21 - (uint64_t)sq);
                     const int32_t bk = qu >> 6;
                     if (bk < SLC) L.sk[qu] = nk;
@@ -790,7 +800,7 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
                         const int32_t pu = wg_load(&tr[u].qpos);
                         if ((int64_t)tu + ts <= (int64_t)U) {
                             wg_fetch_add(&tr[u].iev, 1);
-                            if (pu >= 0) {
+                            if (pu >= 0 && !heft) {
                                 const int32_t bk = pu >> 6;
                                 const uint64_t nk = (bk < SLC ? (uint64_t)atomicAdd(&L.sk[pu], 1ull << 21)
                                                               : (uint64_t)wg_fetch_add(&slots[pu].k, 1ull << 21)) +
@@ -1848,8 +1858,8 @@ __global__ __launch_bounds__(64) void k_sim(SimArgs A) {
         const int32_t i = read_lane(got, 0);
         if (i >= A.count) break;
         if constexpr (WPL == 1) {
-            if (!sim_lane(A, A.order[i], L))
-                sim_dag<1>(A, A.order[i], L);  // keys need 64 bits
+            // HEFT keys, and keys wider than 32 bits, take the 64-bit loop
+            if (A.policy == INSP_POLICY_HEFT || !sim_lane(A, A.order[i], L)) sim_dag<1>(A, A.order[i], L);
         } else {
             sim_dag<WPL>(A, A.order[i], L);
         }
@@ -1902,6 +1912,7 @@ int launch_sim(insp_dag *dag, Workspace *ws, const insp_params &p, const int32_t
     A.dag_u = dag->dag_u.as<int32_t>();
     A.dag_taubar = dag->dag_taubar.as<int32_t>();
     A.stat = dag->dag_stat.as<int32_t>();
+    A.rank = dag->rank.as<int64_t>();
     A.counter = ws->counter.as<int32_t>();
     A.makespan = makespan;
     A.trace = trace;
@@ -1920,12 +1931,23 @@ int launch_sim(insp_dag *dag, Workspace *ws, const insp_params &p, const int32_t
     // generous for a single DAG (one work-group owns the CU), a few blocks
     // per DAG for a batch (tunable)
     const bool one = ws->count == 1;
-    A.sum_cap = (int32_t)std::min<int64_t>(ws->max_nblk, one ? 2048 : sum_cap);
-    A.lb = (int32_t)std::min<int64_t>(ws->max_nblk, one ? 64 : 16);
+    const int64_t budget = (one ? 140 : 150) * 1024;
+    int64_t sc = std::min<int64_t>(ws->max_nblk, one ? 2048 : sum_cap);
+    int64_t lb = std::min<int64_t>(ws->max_nblk, one ? 64 : 16);
+    // machines of hundreds of workers: shorter LDS block lists, then fewer
+    // LDS block maxima, until the per-worker state fits (the rest lives in
+    // global memory)
+    while (lb > 1 && (int64_t)lds_bytes(ws->max_w, (int)sc, (int)lb, 0) > budget) lb /= 2;
+    while (sc > 0 && (int64_t)lds_bytes(ws->max_w, (int)sc, (int)lb, 0) > budget) sc /= 2;
     int64_t slc = slot_cap;
-    if (one) slc = (140 * 1024 - (int64_t)lds_bytes(ws->max_w, A.sum_cap, A.lb, 0)) / (64 * 20);
-    A.slot_cap = (int32_t)std::max<int64_t>(0, std::min<int64_t>(ws->max_nblk, slc));
+    if (one) slc = (budget - (int64_t)lds_bytes(ws->max_w, (int)sc, (int)lb, 0)) / (64 * 20);
+    slc = std::max<int64_t>(0, std::min<int64_t>(ws->max_nblk, slc));
+    while (slc > 0 && (int64_t)lds_bytes(ws->max_w, (int)sc, (int)lb, (int)slc) > budget) slc--;
+    A.sum_cap = (int32_t)sc;
+    A.lb = (int32_t)lb;
+    A.slot_cap = (int32_t)slc;
     const size_t lds = lds_bytes(ws->max_w, A.sum_cap, A.lb, A.slot_cap);
+    if (lds > 160 * 1024) return set_error(INSP_E_RANGE, "simulation state of %d workers exceeds LDS", ws->max_w);
     grid = std::max(1, std::min(grid, ws->count));
     hipLaunchKernelGGL(k_counter_reset, dim3(1), dim3(64), 0, st, A.counter);
     {
@@ -1957,7 +1979,7 @@ using namespace insp;
 
 static int check_params(const insp_params *p) {
     if (!p) return set_error(INSP_E_INVAL, "null params");
-    if (p->policy < 0 || p->policy > 3) return set_error(INSP_E_INVAL, "unknown policy %d", p->policy);
+    if (p->policy < 0 || p->policy > INSP_POLICY_HEFT) return set_error(INSP_E_INVAL, "unknown policy %d", p->policy);
     if (p->unit_time < 0 || p->max_events < 0) return set_error(INSP_E_INVAL, "negative unit_time/max_events");
     if (p->k_num > INSP_MAX_TICK || p->k_den > INSP_MAX_TICK) return set_error(INSP_E_RANGE, "k_num/k_den > 2^20");
     return INSP_OK;
@@ -1998,6 +2020,7 @@ extern "C" int insp_schedule(const insp_dag *cdag, int32_t index, const insp_wor
     Workspace *ws;
     if ((rc = get_workspace(dag, index, 1, workers, true, &ws))) return rc;
     if ((rc = run_attributes(dag, ws, est, params->unit_time, nullptr, nullptr, nullptr, true, st))) return rc;
+    if (params->policy == INSP_POLICY_HEFT && (rc = run_rank(dag, ws, est, st))) return rc;
     return launch_sim(dag, ws, *params, dur, est, worker, start, finish, makespan, ie_at_pop, mode_at_pop, trace,
                       n_events, 1, 1, 4096, 0, st);
 }
@@ -2032,6 +2055,7 @@ extern "C" int insp_schedule_batch(const insp_dag *cdag, const insp_workers *wor
         lds_bytes(1, sum_cap, 16, slot_cap) > 150 * 1024)
         return set_error(INSP_E_INVAL, "bad tune key '%s'", tune_key);
     if ((rc = run_attributes(dag, ws, est, params->unit_time, nullptr, nullptr, nullptr, true, st))) return rc;
+    if (params->policy == INSP_POLICY_HEFT && (rc = run_rank(dag, ws, est, st))) return rc;
     return launch_sim(dag, ws, *params, dur, est, worker, start, finish, makespan, ie_at_pop, mode_at_pop, nullptr,
                       nullptr, waves, grid, sum_cap, slot_cap, st);
 }
@@ -2053,6 +2077,7 @@ extern "C" int insp_sync_status(const insp_dag *cdag, void *stream) {
     for (int32_t b = 0; b < dag->B; b++) {
         if (stat[2 * b] & ST_EST) return set_error(INSP_E_RANGE, "estimate outside [1, 2^20] in DAG %d", b);
         if (stat[2 * b] & ST_DUR) return set_error(INSP_E_RANGE, "duration outside [1, 2^20] in DAG %d", b);
+        if (stat[2 * b] & ST_RANK) return set_error(INSP_E_RANGE, "HEFT rank of DAG %d reaches 2^42", b);
         if (stat[2 * b] & ST_HANG)
             return set_error(INSP_E_HANG, "DAG %d needed more than max_events events", b);
     }

@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libinspirit.so")
 
 OK, E_INVAL, E_CYCLE, E_RANGE, E_NOMEM, E_DEVICE, E_HANG = 0, 1, 2, 3, 4, 5, 6
-POLICY = {"inspirit": 0, "fifo": 1, "ability": 2, "efi": 3}
+POLICY = {"inspirit": 0, "fifo": 1, "ability": 2, "efi": 3, "heft": 4}
 MODE_ABILITY, MODE_EFI, MODE_EFI_LOC, MODE_FIFO = 0, 1, 2, 3
 ALL_DAGS = -1
 

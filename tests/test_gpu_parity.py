@@ -112,7 +112,7 @@ def test_attributes_match_oracle(insp, seed):
     dag.free()
 
 
-@pytest.mark.parametrize("policy", ["inspirit", "fifo", "ability", "efi"])
+@pytest.mark.parametrize("policy", ["inspirit", "fifo", "ability", "efi", "heft"])
 def test_random_small_dags(insp, policy):
     for i in range(40):
         n = 1 + (i * 7) % 90
@@ -364,3 +364,114 @@ def test_many_candidates_per_event(insp):
         say("hubs", seed)
         for pol in ("inspirit", "efi"):
             assert_same(run_gpu(insp, w, pol), oracle.schedule(w, policy=pol), f"hubs {seed} {pol}")
+
+
+# ------------------------------------------------- id order, machine size, HEFT
+
+def _permuted(w, seed):
+    # the same DAG with its task ids shuffled: edges point both ways, so the
+    # id order is no topological order
+    rng = np.random.default_rng(seed)
+    p = rng.permutation(w.n)  # new id of task v
+    src = np.repeat(np.arange(w.n), np.diff(np.asarray(w.row_ptr, np.int64)))
+    ns, nd = p[src], p[np.asarray(w.col, np.int64)]
+    o = np.lexsort((nd, ns))
+    ns, nd = ns[o], nd[o]
+    rp = np.zeros(w.n + 1, np.int64)
+    np.add.at(rp, ns + 1, 1)
+    inv = np.argsort(p)  # task at each new id
+    return NS(n=w.n, row_ptr=np.cumsum(rp).astype(np.int32), col=nd.astype(np.int32),
+              dur=np.asarray(w.dur, np.int32).reshape(w.n, 2)[inv], est=np.asarray(w.est, np.int32).reshape(w.n, 2)[inv],
+              n_cpu=w.n_cpu, n_gpu=w.n_gpu, m=int(nd.size), type=np.zeros(w.n, np.int32), name="permuted")
+
+
+def _backward_edges(w):
+    src = np.repeat(np.arange(w.n), np.diff(np.asarray(w.row_ptr, np.int64)))
+    return int((np.asarray(w.col) < src).sum())
+
+
+@pytest.mark.parametrize("policy", ["inspirit", "fifo", "heft"])
+def test_permuted_task_ids(insp, policy):
+    bases = [synth.lu_workload(nb=10),
+             synth.random_dag(41, 0, 300, 0.02, n_cpu=3, n_gpu=2, dur_hi=40, est_equal=False)]
+    for i, base in enumerate(bases):
+        w = _permuted(base, 7 + i)
+        assert _backward_edges(w) > 0
+        say("permuted", policy, i, w.n)
+        g = run_gpu(insp, w, policy)
+        assert_same(g, oracle.schedule(w, policy=policy, variant=oracle.HEAP), f"permuted {i}")
+        check_schedule(w, g["worker"], g["start"], g["finish"], g["makespan"])
+
+
+@pytest.mark.parametrize("machine", [(70, 30), (200, 100), (1000, 24)])
+def test_many_workers(insp, machine):
+    # more than 64 workers: two and sixteen workers per lane
+    n_cpu, n_gpu = machine
+    w = synth.random_dag(43, n_cpu, 2500, 0.003, n_cpu=n_cpu, n_gpu=n_gpu, dur_hi=60, est_equal=False)
+    for policy in ("inspirit", "fifo", "heft"):
+        say("workers", machine, policy)
+        g = run_gpu(insp, w, policy)
+        assert_same(g, oracle.schedule(w, policy=policy, variant=oracle.HEAP), f"workers {machine} {policy}")
+        check_schedule(w, g["worker"], g["start"], g["finish"], g["makespan"])
+
+
+def test_w8_heft_on_gpu(insp):
+    with open(os.path.join(GOLD, "w8_heft.json")) as f:
+        g8 = json.load(f)["w8"]
+    n = g8["n"]
+    w = NS(n=n, row_ptr=np.asarray(g8["row_ptr"], np.int32), col=np.asarray(g8["col"], np.int32),
+           dur=np.asarray(g8["dur"], np.int32), est=np.asarray(g8["dur"], np.int32), n_cpu=g8["n_cpu"],
+           n_gpu=g8["n_gpu"], m=len(g8["col"]), type=np.zeros(n, np.int32), name="w8")
+    say("w8 heft")
+    g = run_gpu(insp, w, "heft")
+    assert g["start"].tolist() == g8["heft"]["start"] and g["worker"].tolist() == g8["heft"]["worker"]
+    assert g["makespan"] == g8["heft"]["makespan"]
+    assert set(g["mode_at_pop"].tolist()) == {g8["heft"]["mode_at_pop"]}
+
+
+@pytest.mark.parametrize("policy", ["heft"])
+def test_lu_and_cholesky_heft(insp, policy):
+    for w in (synth.lu_workload(nb=24), synth.cfg2()):
+        say("heft", w.name)
+        g = run_gpu(insp, w, policy)
+        assert_same(g, oracle.schedule(w, policy=policy, variant=oracle.HEAP), w.name)
+
+
+def test_heft_batch(insp):
+    ws = synth.cfg3(select=list(range(3, 4096, 300))) + [_permuted(synth.lu_workload(nb=8), 5), _hubs(4)]
+    b = synth.concat(ws)
+    say("heft batch", len(ws))
+    dag, dur, est = insp.batch_to_device(b)
+    r = oracle.schedule_batch(b, policy="heft")
+    for key in (None, "waves=1,grid=2", "waves=1,grid=5,lds_blocks=0,lds_slots=0"):
+        o = insp.schedule_batch(dag, [(w.n_cpu, w.n_gpu) for w in ws], dur, est, insp.params(policy="heft"),
+                                tune_key=key)
+        insp.sync_status(dag)
+        for k in ("worker", "start", "finish", "ie_at_pop", "mode_at_pop"):
+            assert np.array_equal(o[k].cpu().numpy(), r[k]), (key, k)
+        assert np.array_equal(o["makespan"].cpu().numpy(), r["makespan"]), key
+    # the same handle under another policy afterwards is unaffected
+    o = insp.schedule_batch(dag, [(w.n_cpu, w.n_gpu) for w in ws], dur, est)
+    insp.sync_status(dag)
+    assert np.array_equal(o["start"].cpu().numpy(), oracle.schedule_batch(b)["start"])
+    dag.free()
+
+
+def _chain(n, tick, n_cpu):
+    rp = np.minimum(np.arange(n + 1), n - 1).astype(np.int32)
+    rp[0] = 0
+    return NS(n=n, row_ptr=rp, col=np.arange(1, n, dtype=np.int32), dur=np.full((n, 2), tick, np.int32),
+              est=np.full((n, 2), tick, np.int32), n_cpu=n_cpu, n_gpu=0, m=n - 1, type=np.zeros(n, np.int32),
+              name=f"chain-{n}")
+
+
+def test_heft_rank_limit(insp):
+    # a chain at the largest tick on 1024 workers: the source's rank is
+    # n * 1024 * 2^20, which reaches 2^42 at n = 4096
+    say("heft rank limit")
+    w = _chain(4095, 1 << 20, 1024)
+    g = run_gpu(insp, w, "heft")
+    assert g["makespan"] == 4095 << 20 and g["start"].tolist() == [v << 20 for v in range(4095)]
+    with pytest.raises(insp.InspError) as e:
+        run_gpu(insp, _chain(4096, 1 << 20, 1024), "heft")
+    assert e.value.code == insp.E_RANGE
