@@ -18,6 +18,15 @@ pure-Python twin in ``pyref.py``):
   schedule    -- pinned by closed forms (chains, independent unit tasks),
                  schedule invariants, brute-force optimal makespans on DAGs of
                  at most 8 tasks, and the Fig. 1 analogue W2.
+  heft        -- pinned by the hand-worked fixture W8, the rank-order pop
+                 property with ranks recomputed from their definition, and
+                 planted mistakes.
+  transitive  -- pinned by the complete-DAG statement (Section 4.3: the
+                 source scores every task), the U limits of Section 4.2,
+                 chain and out-tree closed forms, path enumeration and a
+                 reachability-matrix closure on small DAGs, the hand-worked
+                 fixture W9, and planted mistakes.  Its unit-time ladder, like
+                 the direct one, is pinned only by brute force of the score.
 """
 from __future__ import annotations
 
@@ -53,15 +62,19 @@ def build(force: bool = False) -> str:
     return _LIB
 
 
+ATTR_MODE = {"direct": 0, "transitive": 1}
+
+
 class Params(C.Structure):
     _fields_ = [(k, C.c_int32) for k in ("policy", "unit_time", "s_inc", "s_dec", "dec_step", "c",
-                                         "k_num", "k_den", "max_events")]
+                                         "k_num", "k_den", "max_events", "attr_mode")]
 
 
 def params(policy="inspirit", unit_time=0, s_inc=-1, s_dec=-1, dec_step=-1, c=-1, k_num=-1, k_den=-1,
-           max_events=0) -> Params:
+           max_events=0, attr_mode="direct") -> Params:
     pol = POLICY[policy] if isinstance(policy, str) else int(policy)
-    return Params(pol, unit_time, s_inc, s_dec, dec_step, c, k_num, k_den, max_events)
+    am = ATTR_MODE[attr_mode] if isinstance(attr_mode, str) else int(attr_mode)
+    return Params(pol, unit_time, s_inc, s_dec, dec_step, c, k_num, k_den, max_events, am)
 
 
 TRACE_DTYPE = np.dtype([("t", "<i8"), ("nready", "<i4"), ("mode", "<i4"), ("cnt", "<i4"), ("peak", "<i4"),
@@ -78,6 +91,7 @@ def lib():
         i32, i64 = C.c_int32, C.c_int64
         _lib.orc_canon.argtypes = [i32, P, P, P, P]
         _lib.orc_attributes.argtypes = [i32, P, P, P, i32, P, i32, P, P, P]
+        _lib.orc_transitive.argtypes = [i32, P, P, P, i32, i32, P, P, P, P]
         _lib.orc_regulate_seq.argtypes = [i32, P, P, C.POINTER(Params), i32, i64, P, P, P]
         _lib.orc_schedule.argtypes = [i32, P, P, i32, i32, P, P, C.POINTER(Params), i32, P, P, P, P, P, P, P,
                                       i32, P, P]
@@ -116,6 +130,20 @@ def attributes(n, row_ptr, col, est, n_gpu, rem=None, unit_time=0):
     if rc:
         raise OracleError(rc, "attributes")
     return ia[:n], ie[:n], int(U[0])
+
+
+def transitive(n, row_ptr, col, est, n_gpu, unit_time=0):
+    """Transitive attributes on a canonical CSR: (ia_t, ie_t, U_used, longest
+    path).  See orc_transitive."""
+    row_ptr, col, est = _i32(row_ptr), _i32(col), _i32(est).reshape(-1)
+    ia = np.zeros(max(n, 1), np.int32)
+    ie = np.zeros(max(n, 1), np.int32)
+    U = np.zeros(1, np.int32)
+    cp = np.zeros(1, np.int64)
+    rc = lib().orc_transitive(n, _p(row_ptr), _p(col), _p(est), n_gpu, unit_time, _p(ia), _p(ie), _p(U), _p(cp))
+    if rc:
+        raise OracleError(rc, "transitive")
+    return ia[:n], ie[:n], int(U[0]), int(cp[0])
 
 
 def regulate(ts, Ns, W, tau_bar, **kw):

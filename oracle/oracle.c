@@ -20,7 +20,11 @@
  *     with the least expected termination time; Section 4.1: per-worker
  *     queues, FIFO head by default, attribute-driven precedence), with the
  *     Nready regulator of Section 4.4 choosing between the high-ability and
- *     the high-efficiency pop rule.
+ *     the high-efficiency pop rule;
+ *   - the transitive reading of the attributes (all descendants, and the
+ *     descendants finishing within a unit-time window, Sections 4.3 and 7),
+ *     used as fixed keys when a schedule asks for them;
+ *   - the HEFT upward-rank list baseline the paper compares against.
  * Readings taken where the paper is silent or garbled are listed at the
  * function that applies them.
  *
@@ -44,11 +48,13 @@ enum { ORC_PLAIN = 0, ORC_HEAP = 1 };
 #define ORC_MAX_N (1 << 21)
 #define ORC_MAX_TICK (1 << 20)
 #define ORC_MAX_W 1024
+#define ORC_MAX_PATH (1 << 30) /* transitive attributes: longest path in ticks, exclusive */
 
 typedef struct {
     int32_t policy, unit_time;
     int32_t s_inc, s_dec, dec_step, c, k_num, k_den;
     int32_t max_events;
+    int32_t attr_mode;  /* 0: direct attributes; 1: transitive (static) attributes */
 } orc_params;
 
 typedef struct {
@@ -182,6 +188,105 @@ int orc_attributes(int32_t n, const int32_t *rp, const int32_t *col, const int32
     *U_used = (int32_t)U;
     free(rem);
     return ORC_OK;
+}
+
+/* ------------------------------------------------ transitive attributes */
+
+/* A topological order (Kahn, from the tasks without predecessors). */
+static int topo_order(int32_t n, const int32_t *rp, const int32_t *col, int32_t *order) {
+    int32_t *left = (int32_t *)calloc((size_t)n + 1, sizeof(int32_t));
+    if (!left) return ORC_E_NOMEM;
+    for (int32_t e = 0; e < rp[n]; e++) left[col[e]]++;
+    int32_t head = 0, tail = 0;
+    for (int32_t v = 0; v < n; v++)
+        if (left[v] == 0) order[tail++] = v;
+    while (head < tail) {
+        int32_t v = order[head++];
+        for (int32_t e = rp[v]; e < rp[v + 1]; e++)
+            if (--left[col[e]] == 0) order[tail++] = col[e];
+    }
+    free(left);
+    return tail == n ? ORC_OK : ORC_E_CYCLE;
+}
+
+/* Transitive reading of the two attributes (Section 4.3: the source of a
+ * fully connected DAG scores the number of its tasks; Section 4.2: with a
+ * large unit time IE converges to IA; Section 7: IE looks at a time window
+ * after the task).  With D(v) = v and every task reachable from v:
+ *   IA_T(v)    = |D(v)|;
+ *   EF_v(d)    = the longest tau-weighted path from v to d, both ends
+ *                included -- d's earliest finish when v starts at time 0
+ *                and workers are unlimited;
+ *   IE_T(v; U) = #{d in D(v) : EF_v(d) <= U}.
+ * Both are computed once on the whole DAG (offline, Section 4.3), one
+ * forward pass per source v over a topological order.  With unit_time == 0
+ * U is chosen on the ladder U = 2^j, j = 0..J, 2^J the first power of two
+ * at least the DAG's longest path (where every IE_T has reached IA_T): the U
+ * with the most tasks whose IE_T is neither 0 nor IA_T, the larger U on a
+ * tie.  The longest path must stay below 2^30 ticks (ORC_E_RANGE). */
+int orc_transitive(int32_t n, const int32_t *rp, const int32_t *col, const int32_t *est, int32_t n_gpu,
+                   int32_t unit_time, int32_t *ia, int32_t *ie, int32_t *U_used, int64_t *longest) {
+    if (n < 0 || unit_time < 0) return ORC_E_INVAL;
+    if (check_ticks(n, est)) return ORC_E_RANGE;
+    int32_t *order = (int32_t *)malloc(sizeof(int32_t) * ((size_t)n + 1));
+    int32_t *pos = (int32_t *)malloc(sizeof(int32_t) * ((size_t)n + 1));
+    int64_t *EF = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+    int32_t *hist = (int32_t *)calloc((size_t)n * 64 + 1, sizeof(int32_t)); /* members by ceil(log2 EF) */
+    int rc = ORC_OK;
+    if (!order || !pos || !EF || !hist) { rc = ORC_E_NOMEM; goto out; }
+    if ((rc = topo_order(n, rp, col, order))) goto out;
+    for (int32_t i = 0; i < n; i++) pos[order[i]] = i;
+    int64_t cp = 0;
+    for (int32_t v = 0; v < n; v++) {
+        memset(EF, 0, sizeof(int64_t) * (size_t)n);
+        EF[v] = tau_of(est, n_gpu, v);
+        int32_t members = 0, within = 0;
+        for (int32_t i = pos[v]; i < n; i++) {
+            int32_t u = order[i];
+            if (EF[u] == 0) continue;  /* not reachable from v */
+            members++;
+            if (EF[u] > cp) cp = EF[u];
+            if (unit_time > 0 && EF[u] <= unit_time) within++;
+            int b = 0;
+            while (((int64_t)1 << b) < EF[u]) b++;
+            if (b < 64) hist[(int64_t)v * 64 + b]++;
+            for (int32_t e = rp[u]; e < rp[u + 1]; e++) {
+                int32_t s = col[e];
+                int64_t f = EF[u] + tau_of(est, n_gpu, s);
+                if (f > EF[s]) EF[s] = f;
+            }
+        }
+        ia[v] = members;
+        ie[v] = within;
+    }
+    if (longest) *longest = cp;
+    if (cp >= ORC_MAX_PATH) { rc = ORC_E_RANGE; goto out; }
+    int64_t U = unit_time;
+    if (unit_time == 0) {
+        int J = 0;
+        while (((int64_t)1 << J) < cp) J++;
+        int64_t bestScore = -1;
+        int bestJ = 0;
+        for (int j = 0; j <= J; j++) {
+            int64_t score = 0;
+            for (int32_t v = 0; v < n; v++) {
+                int32_t cum = 0;
+                for (int b = 0; b <= j; b++) cum += hist[(int64_t)v * 64 + b];
+                if (cum > 0 && cum < ia[v]) score++;
+            }
+            if (score >= bestScore) { bestScore = score; bestJ = j; }
+        }
+        U = (int64_t)1 << bestJ;
+        for (int32_t v = 0; v < n; v++) {
+            int32_t cum = 0;
+            for (int b = 0; b <= bestJ; b++) cum += hist[(int64_t)v * 64 + b];
+            ie[v] = cum;
+        }
+    }
+    if (U_used) *U_used = (int32_t)U;
+out:
+    free(order); free(pos); free(EF); free(hist);
+    return rc;
 }
 
 /* ------------------------------------------------------------ regulator */
@@ -443,7 +548,11 @@ static int simulate(int32_t n, const int32_t *rp, const int32_t *col, int32_t n_
     if (R && (rc = upward_rank(n, rp, col, est, n_cpu, n_gpu, R))) goto out;
     for (int32_t e = 0; e < rp[n]; e++) rem[col[e]]++;
     int32_t U;
-    rc = orc_attributes(n, rp, col, est, n_gpu, rem, p->unit_time, ia, ie, &U);
+    /* direct attributes follow the remaining in-degrees; transitive ones are
+       fixed for the whole run */
+    const int ie_static = p->attr_mode == 1;
+    if (ie_static) rc = orc_transitive(n, rp, col, est, n_gpu, p->unit_time, ia, ie, &U, NULL);
+    else rc = orc_attributes(n, rp, col, est, n_gpu, rem, p->unit_time, ia, ie, &U);
     if (rc) goto out;
     if (U_out) *U_out = U;
     int64_t tau_sum = 0;
@@ -526,7 +635,7 @@ static int simulate(int32_t n, const int32_t *rp, const int32_t *col, int32_t n_
                 int32_t b_ie = 0;
                 for (int64_t i = 0; i < Q[w].len; i++) {
                     int32_t x = Q[w].a[i];
-                    int32_t x_ie = ie_def(rp, col, est, n_gpu, rem, U, x);
+                    int32_t x_ie = ie_static ? ie[x] : ie_def(rp, col, est, n_gpu, rem, U, x);
                     int32_t y = bi < 0 ? x : Q[w].a[bi];
                     if (bi < 0 || outranks_r(order, R ? R[x] : 0, R ? R[y] : 0, ia[x], x_ie, seq[x], ia[y], b_ie,
                                              seq[y])) {
@@ -596,7 +705,7 @@ static int simulate(int32_t n, const int32_t *rp, const int32_t *col, int32_t n_
             }
         }
         qsort(newly, (size_t)n_new, sizeof(int32_t), cmp_i32);
-        if (variant == ORC_HEAP) {
+        if (variant == ORC_HEAP && !ie_static) {
             /* successors that dropped to one remaining predecessor this event */
             qsort(touched, (size_t)nt, sizeof(int32_t), cmp_i32);
             for (int32_t i = 0; i < nt; i++) {
@@ -630,7 +739,8 @@ out:
 
 static int check_params(int32_t n, int32_t n_cpu, int32_t n_gpu, const int32_t *dur, const int32_t *est,
                         const orc_params *p) {
-    if (n_cpu < 0 || n_gpu < 0 || p->policy < 0 || p->policy > 4 || p->unit_time < 0 || p->max_events < 0)
+    if (n_cpu < 0 || n_gpu < 0 || p->policy < 0 || p->policy > 4 || p->unit_time < 0 || p->max_events < 0 ||
+        p->attr_mode < 0 || p->attr_mode > 1)
         return ORC_E_INVAL;
     int32_t W = n_cpu + n_gpu;
     if (W < 1 || W > ORC_MAX_W) return ORC_E_RANGE;

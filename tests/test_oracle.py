@@ -501,3 +501,204 @@ def test_heft_plain_and_heap_agree():
         b = oracle.schedule(w, policy="heft", variant=oracle.HEAP)
         for k in ("worker", "start", "finish", "ie_at_pop", "mode_at_pop"):
             assert np.array_equal(a[k], b[k]), (i, k)
+
+
+# ------------------------------------------------- transitive attributes (f1)
+
+def _paths_reference(n, rp, col, tau):
+    """IA_T and every EF_v(d) by enumerating all paths out of v (exponential;
+    tiny DAGs only) -- no dynamic programming, no topological order."""
+    succ = [list(col[rp[v]:rp[v + 1]]) for v in range(n)]
+    EF = [dict() for _ in range(n)]
+
+    def walk(v, d, acc):
+        acc += int(tau[d])
+        if acc > EF[v].get(d, 0):
+            EF[v][d] = acc
+        for s in succ[d]:
+            walk(v, s, acc)
+    for v in range(n):
+        walk(v, v, 0)
+    return EF
+
+
+def _reach_closure(n, rp, col):
+    """D(v) sizes from the boolean closure of (I + A), squared until stable."""
+    M = np.eye(n, dtype=bool)
+    for v in range(n):
+        M[v, col[rp[v]:rp[v + 1]]] = True
+    while True:
+        M2 = (M.astype(np.int64) @ M.astype(np.int64)) > 0
+        if (M2 == M).all():
+            return M.sum(axis=1)
+        M = M2
+
+
+@pytest.mark.parametrize("N", [1, 2, 5, 12])
+def test_transitive_complete_dag_source_scores_every_task(N):
+    # Section 4.3: in a fully connected DAG with one source, the source's
+    # inspiring ability equals the number of tasks
+    rp, col = csr(N, [(i, j) for i in range(N) for j in range(i + 1, N)])
+    ia, _, _, cp = oracle.transitive(N, rp, col, np.ones((N, 2)), 1)
+    assert ia[0] == N and ia.tolist() == [N - i for i in range(N)]
+    assert cp == N
+
+
+def test_w9_transitive_hand_worked():
+    g = gold("w9_transitive.json")["w9"]
+    ia, ie, U, cp = oracle.transitive(g["n"], g["row_ptr"], g["col"], g["est"], g["n_gpu"], unit_time=7)
+    assert ia.tolist() == g["ia_t"] and ie.tolist() == g["ie_t_u7"] and U == 7 and cp == g["longest_path"]
+    ia, ie, U, _ = oracle.transitive(g["n"], g["row_ptr"], g["col"], g["est"], g["n_gpu"])
+    assert U == g["unit_time_auto"] and ie.tolist() == g["ie_t_auto"]
+
+
+@pytest.mark.parametrize("key", ["w10_tie", "w10_top"])
+def test_w10_transitive_ladder_edges(key):
+    g = gold("w9_transitive.json")[key]
+    _, ie, U, _ = oracle.transitive(g["n"], g["row_ptr"], g["col"], g["est"], g["n_gpu"])
+    assert U == g["unit_time_auto"] and ie.tolist() == g["ie_t_auto"]
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_transitive_matches_path_enumeration(seed):
+    w = synth.random_dag(51, seed, 3 + seed % 7, 0.35, n_cpu=1, n_gpu=seed % 2, dur_hi=12, est_equal=False)
+    rp, col = oracle.canon(w.n, w.row_ptr, w.col)
+    tau = w.est[:, 1 if w.n_gpu else 0]
+    EF = _paths_reference(w.n, rp, col, tau)
+    assert [len(e) for e in EF] == _reach_closure(w.n, rp, col).tolist()
+    cp = max(max(e.values()) for e in EF)
+    for U in (1, 5, 13, 30, cp, cp + 7):
+        ia, ie, _, cp2 = oracle.transitive(w.n, rp, col, w.est, w.n_gpu, unit_time=U)
+        assert cp2 == cp
+        assert ia.tolist() == [len(e) for e in EF]
+        assert ie.tolist() == [sum(x <= U for x in e.values()) for e in EF], U
+
+
+def test_transitive_unit_time_limits():
+    # Section 4.2: too small a unit time drives IE towards zero; too large a
+    # one makes it converge to IA
+    for seed in range(6):
+        w = synth.random_dag(52, seed, 40, 0.1, n_cpu=2, n_gpu=1, dur_hi=30, est_equal=False)
+        rp, col = oracle.canon(w.n, w.row_ptr, w.col)
+        _, _, _, cp = oracle.transitive(w.n, rp, col, w.est, 1, unit_time=1)
+        prev = None
+        for U in sorted({1, 2, 3, 8, 40, 200, max(cp - 1, 1), cp, cp + 1}):
+            ia, ie, _, _ = oracle.transitive(w.n, rp, col, w.est, 1, unit_time=U)
+            tau = w.est[:, 1]
+            assert ((tau > U) <= (ie == 0)).all()  # a task slower than U counts nothing
+            if prev is not None:
+                assert (ie >= prev).all()
+            prev = ie
+            if U >= cp:
+                assert (ie == ia).all()
+
+
+def test_transitive_chain_closed_form():
+    n = 30
+    rp, col = csr(n, [(i, i + 1) for i in range(n - 1)])
+    est = synth.Stream(53, 1).randint(np.arange(2 * n).reshape(n, 2), 1, 20).astype(np.int32)
+    tau = est[:, 1].astype(np.int64)
+    for U in (3, 17, 60, 400):
+        ia, ie, _, cp = oracle.transitive(n, rp, col, est, 1, unit_time=U)
+        assert ia.tolist() == [n - i for i in range(n)] and cp == tau.sum()
+        cum = np.concatenate([[0], np.cumsum(tau)])
+        # tasks i..j finish within U of i's start while cum[j+1] - cum[i] <= U
+        want = [int(np.searchsorted(cum, cum[i] + U, side="right")) - 1 - i for i in range(n)]
+        assert ie.tolist() == want
+
+
+def test_transitive_out_tree_closed_form():
+    # in an out-tree every descendant has a single path from v: EF is the sum
+    # of tau along it, and D(v) is v's subtree
+    rng = np.random.default_rng(54)
+    n = 60
+    parent = [-1] + [int(rng.integers(0, v)) for v in range(1, n)]
+    rp, col = csr(n, [(parent[v], v) for v in range(1, n)])
+    est = rng.integers(1, 15, (n, 2)).astype(np.int32)
+    tau = est[:, 1].astype(np.int64)
+    depth_sum = np.zeros(n, np.int64)
+    for v in range(n):
+        depth_sum[v] = tau[v] + (depth_sum[parent[v]] if parent[v] >= 0 else 0)
+    anc = [set() for _ in range(n)]
+    for v in range(n):
+        u = v
+        while u >= 0:
+            anc[v].add(u)
+            u = parent[u]
+    U = 25
+    ia, ie, _, _ = oracle.transitive(n, rp, col, est, 1, unit_time=U)
+    for v in range(n):
+        sub = [d for d in range(n) if v in anc[d]]
+        assert ia[v] == len(sub)
+        # EF_v(d) = depth_sum[d] - depth_sum[v] + tau[v]
+        assert ie[v] == sum(depth_sum[d] - depth_sum[v] + tau[v] <= U for d in sub)
+
+
+def test_transitive_auto_unit_time_maximises_score_over_ladder():
+    for seed in range(6):
+        w = synth.random_dag(55, seed, 35, 0.12, n_cpu=1, n_gpu=1, dur_hi=25, est_equal=False)
+        rp, col = oracle.canon(w.n, w.row_ptr, w.col)
+        _, ie_auto, U, cp = oracle.transitive(w.n, rp, col, w.est, 1)
+        J = 0
+        while 2 ** J < cp:
+            J += 1
+        scores = {}
+        for j in range(J + 1):
+            ia, ie, _, _ = oracle.transitive(w.n, rp, col, w.est, 1, unit_time=2 ** j)
+            scores[2 ** j] = int(((ie > 0) & (ie < ia)).sum())
+        best = max(scores.values())
+        assert U == max(u for u, s in scores.items() if s == best)
+        assert np.array_equal(ie_auto, oracle.transitive(w.n, rp, col, w.est, 1, unit_time=U)[1])
+
+
+def test_transitive_longest_path_limit():
+    # the longest path must stay below 2^30 ticks
+    n = 1100
+    rp, col = csr(n, [(i, i + 1) for i in range(n - 1)])
+    est = np.full((n, 2), 1 << 20, np.int32)
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.transitive(n, rp, col, est, 1)
+    assert e.value.code == oracle.E_RANGE
+    ia, _, _, _ = oracle.transitive(1023, *csr(1023, [(i, i + 1) for i in range(1022)]), est[:1023], 1)
+    assert ia[0] == 1023
+
+
+@pytest.mark.parametrize("chunk", range(2))
+def test_transitive_schedule_pops_by_static_keys(chunk):
+    # with transitive attributes the keys never change while a task waits:
+    # under the ability-only rule a pop takes the waiting task with the
+    # largest (IA_T, IE_T), ties to the earlier readiness; attributes come
+    # from path enumeration, not from the oracle
+    for i in range(chunk * 25, chunk * 25 + 25):
+        n = 3 + i % 8
+        w = synth.random_dag(56, i, n, 0.3, n_cpu=1 + i % 2, n_gpu=i % 2, dur_hi=15, est_equal=(i % 2 == 0))
+        rp, col = oracle.canon(w.n, w.row_ptr, w.col)
+        EF = _paths_reference(n, rp, col, w.est[:, 1 if w.n_gpu else 0])
+        U = 12
+        ia = [len(e) for e in EF]
+        ie = [sum(x <= U for x in e.values()) for e in EF]
+        for variant in (oracle.PLAIN, oracle.HEAP):
+            r = oracle.schedule(w, policy="ability", variant=variant, attr_mode="transitive", unit_time=U)
+            start, finish, worker = r["start"], r["finish"], r["worker"]
+            assert r["ie_at_pop"].tolist() == ie
+            ready = np.zeros(n, np.int64)
+            for v in range(n):
+                for s in col[rp[v]:rp[v + 1]]:
+                    ready[s] = max(ready[s], finish[v])
+            for v in range(n):
+                waiting = [u for u in range(n) if worker[u] == worker[v] and ready[u] <= start[v] <= start[u]]
+                top = max((ia[u], ie[u]) for u in waiting)
+                assert (ia[v], ie[v]) == top, (i, v)
+                assert not any((ia[u], ie[u]) == top and ready[u] < ready[v] for u in waiting), (i, v)
+            check_schedule(w, worker, start, finish, r["makespan"])
+
+
+def test_transitive_schedule_plain_and_heap_agree():
+    for i in range(40):
+        w = synth.random_dag(57, i, 2 + i % 40, 0.05 + (i % 5) * 0.05, n_cpu=1 + i % 3, n_gpu=i % 3, dur_hi=30,
+                             est_equal=(i % 2 == 0))
+        for pol in ("inspirit", "efi"):
+            a = oracle.schedule(w, policy=pol, variant=oracle.PLAIN, attr_mode="transitive")
+            b = oracle.schedule(w, policy=pol, variant=oracle.HEAP, attr_mode="transitive")
+            for k in ("worker", "start", "finish", "ie_at_pop", "mode_at_pop"):
+                assert np.array_equal(a[k], b[k]), (i, pol, k)

@@ -48,6 +48,14 @@ MUTATIONS = {
     "rank_lowest_first": ("if (order == 3 && r_a != r_b) return r_a > r_b;",
                           "if (order == 3 && r_a != r_b) return r_a < r_b;"),
     "rank_tie_latest_push": ("if (order == 3) return sq_a < sq_b;", "if (order == 3) return sq_a > sq_b;"),
+    "trans_exclusive_count": ("            members++;\n", "            if (u != v) members++;\n"),
+    "trans_shortest_path": ("if (f > EF[s]) EF[s] = f;", "if (EF[s] == 0 || f < EF[s]) EF[s] = f;"),
+    "trans_window_strict": ("if (unit_time > 0 && EF[u] <= unit_time) within++;",
+                            "if (unit_time > 0 && EF[u] < unit_time) within++;"),
+    "trans_ladder_short": ("while (((int64_t)1 << J) < cp) J++;", "while (((int64_t)1 << J) < cp / 2) J++;"),
+    "trans_ladder_tie_smaller": ("if (score >= bestScore) { bestScore = score; bestJ = j; }",
+                                 "if (score > bestScore) { bestScore = score; bestJ = j; }"),
+    "trans_source_excluded": ("EF[v] = tau_of(est, n_gpu, v);", "EF[v] = 1;"),
 }
 
 
@@ -138,6 +146,25 @@ def pins():
     for i in range(8):
         w = synth.random_dag(31, i, 12, 0.25, dur_hi=20, n_cpu=1 + i % 2, n_gpu=1, est_equal=(i % 2 == 0))
         chk(f"heft{i}", lambda w=w: _heft_pops_by_rank(w))
+    # transitive attributes: the hand-worked fixture at a fixed and at the
+    # automatic unit time, and the complete-DAG statement
+    g9 = json.load(open(os.path.join(GOLD, "w9_transitive.json")))["w9"]
+    chk("w9u7", lambda: oracle.transitive(5, g9["row_ptr"], g9["col"], g9["est"], 1, unit_time=7)[:2][0].tolist()
+        == g9["ia_t"] and oracle.transitive(5, g9["row_ptr"], g9["col"], g9["est"], 1, unit_time=7)[1].tolist()
+        == g9["ie_t_u7"])
+    chk("w9auto", lambda: oracle.transitive(5, g9["row_ptr"], g9["col"], g9["est"], 1)[2] == g9["unit_time_auto"]
+        and oracle.transitive(5, g9["row_ptr"], g9["col"], g9["est"], 1)[1].tolist() == g9["ie_t_auto"])
+    for key in ("w10_tie", "w10_top"):
+        gk = json.load(open(os.path.join(GOLD, "w9_transitive.json")))[key]
+        chk(key, lambda gk=gk: oracle.transitive(gk["n"], gk["row_ptr"], gk["col"], gk["est"], 1)[2]
+            == gk["unit_time_auto"])
+    Nc = 7
+    rpc = np.array([0] + [sum(Nc - 1 - i for i in range(k + 1)) for k in range(Nc)], np.int32)
+    colc = np.array([j for i in range(Nc) for j in range(i + 1, Nc)], np.int32)
+    chk("complete", lambda: int(oracle.transitive(Nc, rpc, colc, np.ones((Nc, 2), np.int32), 1)[0][0]) == Nc)
+    for i in range(6):
+        w = synth.random_dag(58, i, 14, 0.2, dur_hi=20, n_cpu=1, n_gpu=1, est_equal=False)
+        chk(f"tladder{i}", lambda w=w: _transitive_ladder_ok(w))
     # invariants and brute force on small random DAGs
     for i in range(6):
         w = synth.random_dag(77, i, 7, 0.3, dur_hi=6, n_cpu=1, n_gpu=1)
@@ -147,6 +174,22 @@ def pins():
             return r["makespan"] >= oracle.brute_opt(w)
         chk(f"inv{i}", inv)
     return failed
+
+
+def _transitive_ladder_ok(w):
+    # the automatic U is the best-scoring rung of 2^0 .. 2^J (2^J >= longest
+    # path), the larger on a tie, scored with the oracle's fixed-U attributes
+    rp, col = oracle.canon(w.n, w.row_ptr, w.col)
+    _, _, U, cp = oracle.transitive(w.n, rp, col, w.est, 1)
+    J = 0
+    while 2 ** J < cp:
+        J += 1
+    scores = {}
+    for j in range(J + 1):
+        ia, ie, _, _ = oracle.transitive(w.n, rp, col, w.est, 1, unit_time=2 ** j)
+        scores[2 ** j] = int(((ie > 0) & (ie < ia)).sum())
+    best = max(scores.values())
+    return U == max(u for u, s in scores.items() if s == best)
 
 
 def _heft_pops_by_rank(w):
