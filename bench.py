@@ -139,6 +139,8 @@ def main():
                     help="makespans under each pop rule against the plain DMDA (FIFO) baseline, checked against the oracle")
     ap.add_argument("--trace", action="store_true",
                     help="single DAG: record the per-event trace, check it against the oracle's, report Nready over time")
+    ap.add_argument("--transitive", action="store_true",
+                    help="also time the transitive attribute pass and the schedule ordered by it (sampled check)")
     ap.add_argument("--print-sources-sha256", action="store_true")
     args = ap.parse_args()
     if args.print_sources_sha256:
@@ -284,6 +286,7 @@ def main():
         "nready_trace": None,
         "policies_vs_dmda": None,
         "learned_gap": None,
+        "transitive": None,
     }
     if args.compare_policies:
         line["policies_vs_dmda"] = compare_policies(dag, workers, b, dur, est, threads)
@@ -296,10 +299,87 @@ def main():
         ref = oracle.schedule(w, policy=args.policy, variant=oracle.HEAP, trace=True)["trace"]
         same = bool(len(ref) == nev and all(np.array_equal(rec[f], ref[f]) for f in ref.dtype.names))
         line["nready_trace"] = {"events": nev, "bit_exact": same, "profile": nready_profile(rec)}
+    if args.transitive:
+        line["transitive"] = transitive_measure(dag, workers, ws, b, dur, est, args.steps, args.warmup, tune_key)
     if args.workload == "batch" and not args.no_learned:
         line["learned_gap"] = learned_gap(dag, workers, b, args.epochs)
     print(json.dumps(line), flush=True)
     dag.free()
+
+
+def transitive_measure(dag, workers, ws, b, dur, est, steps, warmup, tune_key):
+    """Time the transitive attribute pass over every DAG (and the schedule
+    whose queues it orders), check a sample of DAGs against the oracle, and
+    time the oracle on that sample."""
+    import torch
+    import oracle
+    from paper_2404_03226_amd import inspirit
+    N = int(b.task_off[-1])
+    for _ in range(max(warmup, 1)):
+        ia, ie, U, lp = inspirit.transitive_attributes(dag, inspirit.ALL_DAGS, est, workers)
+    inspirit.profile_enable(True)
+    t0 = time.time()
+    for _ in range(steps):
+        ia, ie, U, lp = inspirit.transitive_attributes(dag, inspirit.ALL_DAGS, est, workers)
+    wall = (time.time() - t0) / steps
+    tot, cnt = inspirit.profile_read("trans")
+    inspirit.profile_enable(False)
+    k_ms = tot / max(cnt, 1)
+    ia_h, ie_h = ia.cpu().numpy(), ie.cpu().numpy()
+    pairs = int(ia_h.astype(np.int64).sum())
+    # the schedule ordered by the transitive attributes
+    prm = inspirit.params(attr_mode="transitive")
+    out = inspirit._outputs(N, dur.device)
+    out["makespan"] = torch.empty(len(ws), dtype=torch.int64, device=dur.device)
+    for _ in range(max(warmup, 1)):
+        inspirit.schedule_batch(dag, workers, dur, est, prm, tune_key=tune_key, out=out)
+    inspirit.sync_status(dag)
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(steps):
+        inspirit.schedule_batch(dag, workers, dur, est, prm, tune_key=tune_key, out=out)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    inspirit.sync_status(dag)
+    sched_ms = ev0.elapsed_time(ev1) / steps
+    # sampled check: every 64th DAG and the largest, attributes and schedules
+    big = int(np.argmax([w.n for w in ws]))
+    sample = sorted(set(range(0, len(ws), 64)) | {big})
+    res = {k: out[k].cpu().numpy() for k in ("worker", "start", "finish", "ie_at_pop", "mode_at_pop", "makespan")}
+    exact, t_cpu, n_cpu_tasks = True, 0.0, 0
+    for k in sample:
+        w = ws[k]
+        a, z = int(b.task_off[k]), int(b.task_off[k + 1])
+        rp, col = oracle.canon(w.n, w.row_ptr, w.col)
+        t1 = time.time()
+        ria, rie, rU, rcp = oracle.transitive(w.n, rp, col, w.est, w.n_gpu)
+        t_cpu += time.time() - t1
+        n_cpu_tasks += w.n
+        exact &= bool(np.array_equal(ia_h[a:z], ria) and np.array_equal(ie_h[a:z], rie) and U[k] == rU
+                      and lp[k] == rcp)
+        r = oracle.schedule(w, variant=oracle.HEAP, attr_mode="transitive")
+        exact &= bool(all(np.array_equal(res[f][a:z], r[f]) for f in ("worker", "start", "finish", "ie_at_pop",
+                                                                        "mode_at_pop")))
+        exact &= int(res["makespan"][k]) == r["makespan"]
+    # k_trans: per descendant pair one LDS read and one clear, and one LDS
+    # atomicMax per edge out of it; edges approximated by the mean out-degree
+    lds_ops = pairs * (2.0 + b.edge_off[-1] / max(N, 1))
+    lds_peak = 256 * 32 * 2.4e9  # CUs x LDS banks x clock
+    t = {"attr_ms_per_call": round(wall * 1e3, 3), "k_trans_avg_ms": round(k_ms, 3),
+         "tasks_per_s": round(N / wall, 1), "descendant_pairs": pairs,
+         "pairs_per_s": round(pairs / (k_ms * 1e-3), 1),
+         "lds_roofline": {"bound": "lds", "achieved": round(lds_ops / (k_ms * 1e-3) / 1e12, 3),
+                          "peak": round(lds_peak / 1e12, 2), "unit": "Tops/s",
+                          "frac": round(lds_ops / (k_ms * 1e-3) / lds_peak, 4),
+                          "note": "LDS operations estimated from the mean out-degree"},
+         "schedule_ms_per_step": round(sched_ms, 3), "schedule_tasks_per_s": round(N / (sched_ms * 1e-3), 1),
+         "sample_bit_exact": exact, "sample": f"{len(sample)} DAGs ({n_cpu_tasks} tasks): every 64th and the largest",
+         "cpu_baseline": {"value": round(n_cpu_tasks / t_cpu, 1), "unit": "tasks/s", "cores": 1, "kind": "oracle",
+                          "sample": "the sampled DAGs' transitive attributes, C oracle, one thread"}}
+    log(f"transitive: {t}")
+    return t
 
 
 def compare_policies(dag, workers, b, dur, est, threads):

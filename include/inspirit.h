@@ -69,6 +69,13 @@ typedef enum {
 #define INSP_MAX_TASKS (1 << 21)
 #define INSP_MAX_TICK (1 << 20)
 #define INSP_MAX_WORKERS 1024
+#define INSP_MAX_TRANSITIVE_TASKS (1 << 15)
+
+/* Which reading of the attributes orders the queues (insp_params.attr_mode). */
+typedef enum {
+    INSP_ATTR_DIRECT = 0,    /* IA = out-degree, IE over successors at the current in-degrees */
+    INSP_ATTR_TRANSITIVE = 1 /* fixed IA_T, IE_T of insp_transitive_attributes */
+} insp_attr_mode;
 
 /* Opaque, library-owned device copy of B >= 1 canonical DAGs. */
 typedef struct insp_dag insp_dag;
@@ -91,12 +98,16 @@ typedef struct {
  * max_events bounds the simulation's event count (0 = n + 1, the most a
  * correct run can need); exceeding it returns INSP_E_HANG.
  * k_num and k_den must not exceed 2^20.
+ * attr_mode picks the attribute reading the queues are ordered by: with
+ * INSP_ATTR_TRANSITIVE the keys are IA_T and IE_T (insp_transitive_attributes,
+ * unit_time being their window U), fixed for the run.
  */
 typedef struct {
     int32_t policy;
     int32_t unit_time;
     int32_t s_inc, s_dec, dec_step, c, k_num, k_den;
     int32_t max_events;
+    int32_t attr_mode; /* insp_attr_mode; TRANSITIVE needs DAGs of <= INSP_MAX_TRANSITIVE_TASKS */
 } insp_params;
 
 /* One record per simulation event: the Nready the regulator observed (after
@@ -160,6 +171,33 @@ int insp_dag_info(const insp_dag *dag, int32_t index, int64_t *n_tasks, int64_t 
 int insp_attributes(const insp_dag *dag, int32_t index, const int32_t *est, const insp_workers *workers,
                     int32_t unit_time, const int32_t *rem, int32_t *ia, int32_t *ie, int32_t *unit_time_used,
                     void *stream);
+
+/*
+ * insp_transitive_attributes -- the transitive reading of the attributes
+ * (Section 4.3: the source of a fully connected DAG scores the number of its
+ * tasks; Section 4.2: with a large unit time IE converges to IA; Section 7:
+ * IE looks at a time window after the task), on the whole graph:
+ *   D(v)       = v and every task reachable from v;
+ *   IA_T(v)    = |D(v)|;
+ *   EF_v(d)    = the longest tau-weighted path from v to d, both ends
+ *                included (d's earliest finish when v starts at 0 on
+ *                unlimited workers), tau as for insp_attributes;
+ *   IE_T(v; U) = #{d in D(v) : EF_v(d) <= U}.
+ *   U = unit_time if > 0, else the ladder U = 2^j, j = 0..J, 2^J the first
+ *       power of two at least the DAG's longest path, maximising
+ *       #{v : 0 < IE_T(v) < IA_T(v)} (the larger U on a tie).
+ *   index, est, workers, ia, ie   as for insp_attributes (no rem: the
+ *                                 attributes are fixed for a run)
+ *   unit_time_used host int32 [1] (or [B]) output
+ *   longest_path   host int64 [1] (or [B]) output, nullable
+ * The call synchronises `stream`.  INSP_E_RANGE for a DAG of more than
+ * INSP_MAX_TRANSITIVE_TASKS tasks, a longest path of 2^30 ticks or more, or
+ * an estimate out of range.  Cost: one pass over D(v) per task, O(n (n + m))
+ * per DAG at worst.  The first call on a handle builds the DAGs' level order.
+ */
+int insp_transitive_attributes(const insp_dag *dag, int32_t index, const int32_t *est, const insp_workers *workers,
+                               int32_t unit_time, int32_t *ia, int32_t *ie, int32_t *unit_time_used,
+                               int64_t *longest_path, void *stream);
 
 /*
  * insp_schedule -- simulate one DAG on the given workers (Section 2 DMDA

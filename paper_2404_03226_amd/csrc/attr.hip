@@ -269,6 +269,7 @@ int get_workspace(insp_dag *dag, int32_t first, int32_t count, const insp_worker
     }
     std::unique_ptr<Workspace> w(new Workspace());
     w->count = count;
+    w->first = first;
     w->base = dag->toff[first];
     w->tasks = dag->toff[first + count] - dag->toff[first];
     std::vector<DagDesc> desc(count);

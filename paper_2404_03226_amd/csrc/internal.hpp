@@ -80,6 +80,7 @@ struct DagDesc {
 // the queue pools.  Built once, reused by every call with the same shape.
 struct Workspace {
     int32_t count = 0;            // DAGs described
+    int32_t first = 0;            // first DAG of the range
     int32_t max_w = 0;
     int64_t max_nblk = 0;
     int64_t base = 0;             // first global task of the range
@@ -93,6 +94,7 @@ struct Workspace {
     DevBuf sums;                  // uint64 x2 per block: max key under each rule
     DevBuf paux;                  // int32: per-worker block lists, then free-block stacks
     DevBuf counter;               // int32 [4]: DAG dispenser
+    DevBuf tlong, tu;             // transitive attributes: longest path per DAG (+ a counter), chosen U
     std::vector<int32_t> h_order;
 };
 
@@ -123,6 +125,14 @@ struct insp_dag {
     insp::DevBuf lvl;                  // int32 [N + B]: start of each level in topo, then the end
     insp::DevBuf nlev;                 // int32 [B]: levels per DAG
     insp::DevBuf rank;                 // int64 [N]: upward rank of the last HEFT call
+    // transitive attributes: positions in level order (built on first use),
+    // per-call tau by position and ladder counts, attributes for the simulation
+    insp::DevBuf prow;                 // int2 [N]: row of the task at each position
+    insp::DevBuf plev;                 // int32 [N]: level of each position
+    insp::DevBuf pcol;                 // int32 [M]: position of each edge's target
+    insp::DevBuf ptau;                 // int32 [N]: tau by position
+    insp::DevBuf tcum;                 // int32 [N * kTRungs]: members within 2^j
+    insp::DevBuf tia, tie;             // int32 [N]: transitive IA, IE of the last schedule call
     std::map<std::string, std::unique_ptr<insp::Workspace>> ws;
 };
 
@@ -132,8 +142,9 @@ constexpr int kRungs = 24;       // ladder rungs 2^0 .. 2^22 plus a sentinel
 
 // Per-DAG status bits (dag_stat[2 b]): estimate or duration out of range, the
 // event budget exhausted, a HEFT rank too wide for the queue key.
-enum { ST_EST = 1, ST_DUR = 2, ST_HANG = 4, ST_RANK = 8 };
+enum { ST_EST = 1, ST_DUR = 2, ST_HANG = 4, ST_RANK = 8, ST_PATH = 16 };
 constexpr int kRankBits = 42;
+constexpr int kTRungs = 32;  // transitive ladder rungs 2^0 .. 2^31
 constexpr int kAttrThreads = 256;
 
 int ensure_state(insp_dag *dag, hipStream_t st);
@@ -161,6 +172,17 @@ int run_attributes(insp_dag *dag, Workspace *ws, const int32_t *est, int32_t uni
 // HEFT upward ranks of a workspace's DAGs into dag->rank (levels are built
 // on the first call).  Runs after run_attributes, which clears the status.
 int run_rank(insp_dag *dag, Workspace *ws, const int32_t *est, hipStream_t st);
+
+// Kahn levels of every DAG of the handle (built once).
+int ensure_levels(insp_dag *dag, hipStream_t st);
+
+// Transitive IA and IE of a workspace's DAGs into ia / ie (task-indexed
+// relative to the workspace's first task); the chosen U per DAG lands in
+// ws->tu, the longest path in ws->tlong.  With clear_status the DAGs' status
+// words are reset first (a standalone call); a schedule keeps the bits the
+// attribute pass set.
+int run_transitive(insp_dag *dag, Workspace *ws, const int32_t *est, int32_t unit_time, int32_t *ia, int32_t *ie,
+                   bool clear_status, hipStream_t st);
 
 int launch_sim(insp_dag *dag, Workspace *ws, const insp_params &p, const int32_t *dur, const int32_t *est,
                int32_t *worker, int64_t *start, int64_t *finish, int64_t *makespan, int32_t *ie_at_pop,

@@ -101,7 +101,7 @@ __global__ __launch_bounds__(kRankThreads) void k_rank(const DagDesc *desc, cons
 }
 
 // Levels of every DAG of the handle, built on the first HEFT call.
-static int ensure_levels(insp_dag *dag, hipStream_t st) {
+int ensure_levels(insp_dag *dag, hipStream_t st) {
     if (dag->nlev.p) return INSP_OK;
     const int64_t N = std::max<int64_t>(dag->N, 1);
     DevBuf indeg, nlev;

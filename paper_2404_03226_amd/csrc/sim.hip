@@ -98,6 +98,8 @@ struct SimArgs {
     int64_t freeb_base;
     const int32_t *dag_u, *dag_taubar;
     const int64_t *rank;  // HEFT upward ranks (global task index)
+    const int32_t *tia, *tie;  // transitive IA, IE (global task index)
+    int32_t attr_mode;
     int32_t *stat;
     int32_t *counter;
     int64_t *makespan;
@@ -170,7 +172,11 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
     const int32_t k_num = kset ? A.k_num : W;
     const int32_t k_den = kset ? A.k_den : A.dag_taubar[d.id];
     const bool heft = A.policy == INSP_POLICY_HEFT;
+    const bool tattr = A.attr_mode == INSP_ATTR_TRANSITIVE;
+    const bool trans = !heft && tattr;  // keys built from the transitive attributes
+    const bool skey = heft || trans;  // keys fixed while queued
     const int64_t *rk = A.rank + d.toff;
+    const int32_t *tia = A.tia + d.toff, *tie = A.tie + d.toff;
     const int slot0 = A.policy == INSP_POLICY_FIFO ? 2 : heft ? 3 : 0;
     const int32_t max_events = A.max_events > 0 ? A.max_events : n + 1;
 
@@ -267,6 +273,10 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
                 }
             }
             if (heft && ok) rk_l = (uint64_t)rk[v_l];
+            if (trans && ok) {
+                ia_l = tia[v_l];
+                ie_l = tie[v_l];
+            }
             if (ballot(ok && (d_l.x < 1 || d_l.x > INSP_MAX_TICK || d_l.y < 1 || d_l.y > INSP_MAX_TICK)))
                 status |= ST_DUR;
             const int32_t cntj = min(kWave, r - i0);
@@ -516,9 +526,10 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
                         }
                     }
                 }
-                // HEFT keys carry the rank, not IA and IE
-                const int32_t deg = heft ? tr[v].ia : (int32_t)(vk >> 42);
-                const int32_t iep = heft ? wg_load(&tr[v].iev) : (int32_t)((vk >> 21) & M21);
+                // fixed keys carry the rank or the transitive attributes, not
+                // the out-degree
+                const int32_t deg = skey ? tr[v].ia : (int32_t)(vk >> 42);
+                const int32_t iep = tattr ? tie[v] : heft ? wg_load(&tr[v].iev) : (int32_t)((vk >> 21) & M21);
                 if (lane == 0) {
                     L.len[w] = len;
                     L.nb[w] = nb;
@@ -704,7 +715,7 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
             if (lead) {
                 const int32_t nie = iu + mult;
                 tr[u].iev = nie;
-                if (qu >= 0 && !heft) {
+                if (qu >= 0 && !skey) {
                     const uint64_t nk = (uint64_t)au << 42 | (uint64_t)nie << 21 | (M21 - (uint64_t)sq);
                     const int32_t bk = qu >> 6;
                     if (bk < SLC) L.sk[qu] = nk;
@@ -800,7 +811,7 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
                         const int32_t pu = wg_load(&tr[u].qpos);
                         if ((int64_t)tu + ts <= (int64_t)U) {
                             wg_fetch_add(&tr[u].iev, 1);
-                            if (pu >= 0 && !heft) {
+                            if (pu >= 0 && !skey) {
                                 const int32_t bk = pu >> 6;
                                 const uint64_t nk = (bk < SLC ? (uint64_t)atomicAdd(&L.sk[pu], 1ull << 21)
                                                               : (uint64_t)wg_fetch_add(&slots[pu].k, 1ull << 21)) +
@@ -1858,8 +1869,10 @@ __global__ __launch_bounds__(64) void k_sim(SimArgs A) {
         const int32_t i = read_lane(got, 0);
         if (i >= A.count) break;
         if constexpr (WPL == 1) {
-            // HEFT keys, and keys wider than 32 bits, take the 64-bit loop
-            if (A.policy == INSP_POLICY_HEFT || !sim_lane(A, A.order[i], L)) sim_dag<1>(A, A.order[i], L);
+            // fixed keys (HEFT, transitive attributes) and keys wider than 32
+            // bits take the 64-bit loop
+            if (A.policy == INSP_POLICY_HEFT || A.attr_mode == INSP_ATTR_TRANSITIVE || !sim_lane(A, A.order[i], L))
+                sim_dag<1>(A, A.order[i], L);
         } else {
             sim_dag<WPL>(A, A.order[i], L);
         }
@@ -1913,6 +1926,9 @@ int launch_sim(insp_dag *dag, Workspace *ws, const insp_params &p, const int32_t
     A.dag_taubar = dag->dag_taubar.as<int32_t>();
     A.stat = dag->dag_stat.as<int32_t>();
     A.rank = dag->rank.as<int64_t>();
+    A.tia = dag->tia.as<int32_t>();
+    A.tie = dag->tie.as<int32_t>();
+    A.attr_mode = p.attr_mode;
     A.counter = ws->counter.as<int32_t>();
     A.makespan = makespan;
     A.trace = trace;
@@ -1977,8 +1993,22 @@ int launch_sim(insp_dag *dag, Workspace *ws, const insp_params &p, const int32_t
 
 using namespace insp;
 
+// Transitive attributes of the range into the handle's arrays, read by the
+// simulation as fixed keys.
+static int run_sim_transitive(insp_dag *dag, Workspace *ws, const int32_t *est, int32_t unit_time, hipStream_t st) {
+    const int64_t N = std::max<int64_t>(dag->N, 1);
+    int rc;
+    if ((!dag->tia.p && (rc = dag->tia.alloc(sizeof(int32_t) * N))) ||
+        (!dag->tie.p && (rc = dag->tie.alloc(sizeof(int32_t) * N))))
+        return rc;
+    return run_transitive(dag, ws, est, unit_time, dag->tia.as<int32_t>() + ws->base,
+                          dag->tie.as<int32_t>() + ws->base, false, st);
+}
+
 static int check_params(const insp_params *p) {
     if (!p) return set_error(INSP_E_INVAL, "null params");
+    if (p->attr_mode < 0 || p->attr_mode > INSP_ATTR_TRANSITIVE)
+        return set_error(INSP_E_INVAL, "unknown attr_mode %d", p->attr_mode);
     if (p->policy < 0 || p->policy > INSP_POLICY_HEFT) return set_error(INSP_E_INVAL, "unknown policy %d", p->policy);
     if (p->unit_time < 0 || p->max_events < 0) return set_error(INSP_E_INVAL, "negative unit_time/max_events");
     if (p->k_num > INSP_MAX_TICK || p->k_den > INSP_MAX_TICK) return set_error(INSP_E_RANGE, "k_num/k_den > 2^20");
@@ -2021,6 +2051,8 @@ extern "C" int insp_schedule(const insp_dag *cdag, int32_t index, const insp_wor
     if ((rc = get_workspace(dag, index, 1, workers, true, &ws))) return rc;
     if ((rc = run_attributes(dag, ws, est, params->unit_time, nullptr, nullptr, nullptr, true, st))) return rc;
     if (params->policy == INSP_POLICY_HEFT && (rc = run_rank(dag, ws, est, st))) return rc;
+    if (params->attr_mode == INSP_ATTR_TRANSITIVE && (rc = run_sim_transitive(dag, ws, est, params->unit_time, st)))
+        return rc;
     return launch_sim(dag, ws, *params, dur, est, worker, start, finish, makespan, ie_at_pop, mode_at_pop, trace,
                       n_events, 1, 1, 4096, 0, st);
 }
@@ -2056,6 +2088,8 @@ extern "C" int insp_schedule_batch(const insp_dag *cdag, const insp_workers *wor
         return set_error(INSP_E_INVAL, "bad tune key '%s'", tune_key);
     if ((rc = run_attributes(dag, ws, est, params->unit_time, nullptr, nullptr, nullptr, true, st))) return rc;
     if (params->policy == INSP_POLICY_HEFT && (rc = run_rank(dag, ws, est, st))) return rc;
+    if (params->attr_mode == INSP_ATTR_TRANSITIVE && (rc = run_sim_transitive(dag, ws, est, params->unit_time, st)))
+        return rc;
     return launch_sim(dag, ws, *params, dur, est, worker, start, finish, makespan, ie_at_pop, mode_at_pop, nullptr,
                       nullptr, waves, grid, sum_cap, slot_cap, st);
 }
@@ -2078,6 +2112,7 @@ extern "C" int insp_sync_status(const insp_dag *cdag, void *stream) {
         if (stat[2 * b] & ST_EST) return set_error(INSP_E_RANGE, "estimate outside [1, 2^20] in DAG %d", b);
         if (stat[2 * b] & ST_DUR) return set_error(INSP_E_RANGE, "duration outside [1, 2^20] in DAG %d", b);
         if (stat[2 * b] & ST_RANK) return set_error(INSP_E_RANGE, "HEFT rank of DAG %d reaches 2^42", b);
+        if (stat[2 * b] & ST_PATH) return set_error(INSP_E_RANGE, "longest path of DAG %d reaches 2^30 ticks", b);
         if (stat[2 * b] & ST_HANG)
             return set_error(INSP_E_HANG, "DAG %d needed more than max_events events", b);
     }

@@ -18,10 +18,13 @@ LIB_PATH = os.path.join(_HERE, "libinspirit.so")
 
 OK, E_INVAL, E_CYCLE, E_RANGE, E_NOMEM, E_DEVICE, E_HANG = 0, 1, 2, 3, 4, 5, 6
 POLICY = {"inspirit": 0, "fifo": 1, "ability": 2, "efi": 3, "heft": 4}
-MODE_ABILITY, MODE_EFI, MODE_EFI_LOC, MODE_FIFO = 0, 1, 2, 3
+MODE_ABILITY, MODE_EFI, MODE_EFI_LOC, MODE_FIFO, MODE_RANK = 0, 1, 2, 3, 4
+ATTR_MODE = {"direct": 0, "transitive": 1}
+MAX_TRANSITIVE_TASKS = 1 << 15
 ALL_DAGS = -1
 
-EXPORTS = ("insp_build_dag", "insp_free_dag", "insp_dag_info", "insp_attributes", "insp_schedule",
+EXPORTS = ("insp_build_dag", "insp_free_dag", "insp_dag_info", "insp_attributes", "insp_transitive_attributes",
+           "insp_schedule",
            "insp_schedule_batch", "insp_sync_status", "insp_profile_enable", "insp_profile_read",
            "insp_mlp_create", "insp_mlp_free", "insp_mlp_grads", "insp_mlp_train_step", "insp_mlp_predict",
            "insp_mlp_state", "insp_last_error")
@@ -40,7 +43,7 @@ class Workers(C.Structure):
 
 class Params(C.Structure):
     _fields_ = [(k, C.c_int32) for k in ("policy", "unit_time", "s_inc", "s_dec", "dec_step", "c", "k_num",
-                                         "k_den", "max_events")]
+                                         "k_den", "max_events", "attr_mode")]
 
 
 TRACE_DTYPE = np.dtype([("t", "<i8"), ("nready", "<i4"), ("mode", "<i4"), ("cnt", "<i4"), ("peak", "<i4"),
@@ -48,9 +51,10 @@ TRACE_DTYPE = np.dtype([("t", "<i8"), ("nready", "<i4"), ("mode", "<i4"), ("cnt"
 
 
 def params(policy="inspirit", unit_time=0, s_inc=-1, s_dec=-1, dec_step=-1, c=-1, k_num=-1, k_den=-1,
-           max_events=0) -> Params:
+           max_events=0, attr_mode="direct") -> Params:
     pol = POLICY[policy] if isinstance(policy, str) else int(policy)
-    return Params(pol, unit_time, s_inc, s_dec, dec_step, c, k_num, k_den, max_events)
+    am = ATTR_MODE[attr_mode] if isinstance(attr_mode, str) else int(attr_mode)
+    return Params(pol, unit_time, s_inc, s_dec, dec_step, c, k_num, k_den, max_events, am)
 
 
 _lib = None
@@ -70,6 +74,7 @@ def load(path: str = LIB_PATH):
     lib.insp_free_dag.restype = None
     lib.insp_dag_info.argtypes = [P, i32, C.POINTER(i64), C.POINTER(i64), C.POINTER(i32)]
     lib.insp_attributes.argtypes = [P, i32, P, P, i32, P, P, P, P, P]
+    lib.insp_transitive_attributes.argtypes = [P, i32, P, P, i32, P, P, P, P, P]
     lib.insp_schedule.argtypes = [P, i32, P, P, P, C.POINTER(Params), P, P, P, P, P, P, P, P, P]
     lib.insp_schedule_batch.argtypes = [P, P, P, P, C.POINTER(Params), P, P, P, P, P, P, C.c_char_p, P]
     lib.insp_sync_status.argtypes = [P, P]
@@ -171,6 +176,23 @@ def attributes(dag: Dag, index, est, workers, unit_time=0, rem=None, stream=None
     _check(load().insp_attributes(dag.handle, index, _ptr(est), _workers(workers, count), unit_time, _ptr(rem),
                                   _ptr(ia), _ptr(ie), _ptr(U), _stream(stream)))
     return ia[:n], ie[:n], U
+
+
+def transitive_attributes(dag: Dag, index, est, workers, unit_time=0, stream=None):
+    """Transitive (ia_t, ie_t) as device tensors, and the unit time used and
+    the longest path of each selected DAG as numpy arrays."""
+    import torch
+    count = dag.n_dags if index == ALL_DAGS else 1
+    lo = 0 if index == ALL_DAGS else dag.task_off[index]
+    hi = dag.task_off[-1] if index == ALL_DAGS else dag.task_off[index + 1]
+    n = int(hi - lo)
+    ia = torch.empty(max(n, 1), dtype=torch.int32, device=est.device)
+    ie = torch.empty(max(n, 1), dtype=torch.int32, device=est.device)
+    U = np.zeros(count, np.int32)
+    lp = np.zeros(count, np.int64)
+    _check(load().insp_transitive_attributes(dag.handle, index, _ptr(est), _workers(workers, count), unit_time,
+                                             _ptr(ia), _ptr(ie), _ptr(U), _ptr(lp), _stream(stream)))
+    return ia[:n], ie[:n], U, lp
 
 
 def _outputs(n, device, with_pop=True):

@@ -475,3 +475,139 @@ def test_heft_rank_limit(insp):
     with pytest.raises(insp.InspError) as e:
         run_gpu(insp, _chain(4096, 1 << 20, 1024), "heft")
     assert e.value.code == insp.E_RANGE
+
+
+# ------------------------------------------------------- transitive attributes
+
+def _trans_pair(insp, w, unit_time=0):
+    dag, dur, est = insp.to_device(w)
+    ia, ie, U, lp = insp.transitive_attributes(dag, 0, est, (w.n_cpu, w.n_gpu), unit_time=unit_time)
+    dag.free()
+    rp, col = oracle.canon(w.n, w.row_ptr, w.col)
+    ref = oracle.transitive(w.n, rp, col, w.est, w.n_gpu, unit_time=unit_time)
+    return (ia.cpu().numpy(), ie.cpu().numpy(), int(U[0]), int(lp[0])), ref
+
+
+def _assert_trans(got, ref, what):
+    for k, (a, b) in enumerate(zip(got, ref)):
+        assert np.array_equal(np.asarray(a), np.asarray(b)), (what, ("ia", "ie", "U", "longest")[k])
+
+
+def _from_gold(g, n_cpu=1):
+    n = g["n"]
+    est = np.asarray(g["est"], np.int32)
+    return NS(n=n, row_ptr=np.asarray(g["row_ptr"], np.int32), col=np.asarray(g["col"], np.int32), dur=est,
+              est=est, n_cpu=n_cpu, n_gpu=g["n_gpu"], m=len(g["col"]), type=np.zeros(n, np.int32), name="gold")
+
+
+def test_transitive_fixtures_on_gpu(insp):
+    with open(os.path.join(GOLD, "w9_transitive.json")) as f:
+        g = json.load(f)
+    say("transitive fixtures")
+    w9 = _from_gold(g["w9"])
+    got, _ = _trans_pair(insp, w9, unit_time=7)
+    assert got[0].tolist() == g["w9"]["ia_t"] and got[1].tolist() == g["w9"]["ie_t_u7"] and got[3] == 11
+    got, _ = _trans_pair(insp, w9)
+    assert got[2] == g["w9"]["unit_time_auto"] and got[1].tolist() == g["w9"]["ie_t_auto"]
+    for key in ("w10_tie", "w10_top"):
+        got, _ = _trans_pair(insp, _from_gold(g[key]))
+        assert got[2] == g[key]["unit_time_auto"] and got[1].tolist() == g[key]["ie_t_auto"], key
+    # Section 4.3: the source of a fully connected DAG scores every task
+    N = 40
+    rp = np.array([0] + list(np.cumsum([N - 1 - i for i in range(N)])), np.int32)
+    col = np.array([j for i in range(N) for j in range(i + 1, N)], np.int32)
+    wc = NS(n=N, row_ptr=rp, col=col, dur=np.ones((N, 2), np.int32), est=np.ones((N, 2), np.int32), n_cpu=2,
+            n_gpu=1, m=int(col.size), type=np.zeros(N, np.int32), name="complete")
+    got, ref = _trans_pair(insp, wc)
+    assert got[0][0] == N
+    _assert_trans(got, ref, "complete")
+
+
+def test_transitive_random_match_oracle(insp):
+    for i in range(24):
+        n = 1 + (i * 37) % 700
+        w = synth.random_dag(61, i, n, 4.0 / max(n, 4), n_cpu=2, n_gpu=i % 2, dur_hi=40, est_equal=(i % 3 == 0))
+        if i % 4 == 3:
+            w = _permuted(w, i)
+        for U in (0, 1 + (i * 13) % 90):
+            say("transitive random", i, n, U)
+            got, ref = _trans_pair(insp, w, unit_time=U)
+            _assert_trans(got, ref, f"random {i} U={U}")
+
+
+def test_transitive_batch_match_oracle(insp):
+    # all DAGs of a batch in one call, the largest of the layered batch included
+    sel = [0, 3, 700, 1500]
+    pool = synth.cfg3(select=list(range(0, 4096, 97)))
+    big = max(pool, key=lambda w: w.n)
+    ws = synth.cfg3(select=sel) + [big, _permuted(synth.lu_workload(nb=8), 3)]
+    b = synth.concat(ws)
+    say("transitive batch", [w.n for w in ws])
+    dag, dur, est = insp.batch_to_device(b)
+    ia, ie, U, lp = insp.transitive_attributes(dag, insp.ALL_DAGS, est, [(w.n_cpu, w.n_gpu) for w in ws])
+    ia, ie = ia.cpu().numpy(), ie.cpu().numpy()
+    dag.free()
+    for k, w in enumerate(ws):
+        a, z = int(b.task_off[k]), int(b.task_off[k + 1])
+        rp, col = oracle.canon(w.n, w.row_ptr, w.col)
+        ria, rie, rU, rcp = oracle.transitive(w.n, rp, col, w.est, w.n_gpu)
+        assert np.array_equal(ia[a:z], ria) and np.array_equal(ie[a:z], rie), k
+        assert U[k] == rU and lp[k] == rcp, k
+
+
+@pytest.mark.parametrize("policy", ["inspirit", "ability", "efi", "fifo", "heft"])
+def test_transitive_schedule_match_oracle(insp, policy):
+    for i in range(16):
+        n = 2 + (i * 29) % 300
+        w = synth.random_dag(62, i, n, 3.0 / max(n, 3), n_cpu=1 + i % 4, n_gpu=i % 3, dur_hi=30,
+                             est_equal=(i % 2 == 0))
+        say("transitive schedule", policy, i, n)
+        kw = dict(attr_mode="transitive", unit_time=0 if i % 2 else 25)
+        g = run_gpu(insp, w, policy, **kw)
+        assert_same(g, oracle.schedule(w, policy=policy, variant=oracle.HEAP, **kw), f"trans {policy} {i}")
+        check_schedule(w, g["worker"], g["start"], g["finish"], g["makespan"])
+
+
+def test_transitive_schedule_batch(insp):
+    ws = synth.cfg3(select=list(range(5, 4096, 400))) + [_hubs(6)]
+    b = synth.concat(ws)
+    say("transitive schedule batch", len(ws))
+    dag, dur, est = insp.batch_to_device(b)
+    prm = insp.params(attr_mode="transitive")
+    o = insp.schedule_batch(dag, [(w.n_cpu, w.n_gpu) for w in ws], dur, est, prm)
+    insp.sync_status(dag)
+    r = oracle.schedule_batch(b, attr_mode="transitive")
+    for k in ("worker", "start", "finish", "ie_at_pop", "mode_at_pop"):
+        assert np.array_equal(o[k].cpu().numpy(), r[k]), k
+    assert np.array_equal(o["makespan"].cpu().numpy(), r["makespan"])
+    # the direct attributes afterwards on the same handle are unaffected
+    o = insp.schedule_batch(dag, [(w.n_cpu, w.n_gpu) for w in ws], dur, est)
+    insp.sync_status(dag)
+    assert np.array_equal(o["start"].cpu().numpy(), oracle.schedule_batch(b)["start"])
+    dag.free()
+
+
+def test_transitive_range_errors(insp):
+    say("transitive range")
+    # longest path 1100 * 2^20 ticks >= 2^30
+    w = _chain(1100, 1 << 20, 2)
+    dag, dur, est = insp.to_device(w)
+    with pytest.raises(insp.InspError) as e:
+        insp.transitive_attributes(dag, 0, est, (2, 0))
+    assert e.value.code == insp.E_RANGE
+    insp.schedule(dag, 0, (2, 0), dur, est, insp.params(attr_mode="transitive"))
+    with pytest.raises(insp.InspError) as e:
+        insp.sync_status(dag)
+    assert e.value.code == insp.E_RANGE
+    dag.free()
+    # 1023 such tasks stay below
+    w = _chain(1023, 1 << 20, 2)
+    got, ref = _trans_pair(insp, w)
+    _assert_trans(got, ref, "chain 1023")
+    # more tasks than the transitive pass takes
+    w = _chain(insp.MAX_TRANSITIVE_TASKS + 1, 1, 1)
+    dag, dur, est = insp.to_device(w)
+    with pytest.raises(insp.InspError) as e:
+        insp.transitive_attributes(dag, 0, est, (1, 0))
+    assert e.value.code == insp.E_RANGE
+    dag.free()
