@@ -27,6 +27,13 @@ pure-Python twin in ``pyref.py``):
                  reachability-matrix closure on small DAGs, the hand-worked
                  fixture W9, and planted mistakes.  Its unit-time ladder, like
                  the direct one, is pinned only by brute force of the score.
+  data model  -- pinned by the hand-worked fixtures W11 (transfer term,
+                 arrival wait, locality rule) and W12 (transfers overlap the
+                 queue and are not shared), reduction to the plain model when
+                 no transfer can cost anything, a start-time bound recomputed
+                 from the inputs' homes, and planted mistakes.  The model
+                 itself is a reading (the paper gives no formulas), so its
+                 parity against the paper is partial.
 """
 from __future__ import annotations
 
@@ -41,7 +48,7 @@ _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 OK, E_INVAL, E_CYCLE, E_RANGE, E_NOMEM, E_HANG = 0, 1, 2, 3, 4, 6
-POLICY = {"inspirit": 0, "fifo": 1, "ability": 2, "efi": 3, "heft": 4}
+POLICY = {"inspirit": 0, "fifo": 1, "ability": 2, "efi": 3, "heft": 4, "locality": 5}
 MODE_ABILITY, MODE_EFI, MODE_EFI_LOC, MODE_FIFO = 0, 1, 2, 3
 PLAIN, HEAP = 0, 1
 
@@ -67,14 +74,18 @@ ATTR_MODE = {"direct": 0, "transitive": 1}
 
 class Params(C.Structure):
     _fields_ = [(k, C.c_int32) for k in ("policy", "unit_time", "s_inc", "s_dec", "dec_step", "c",
-                                         "k_num", "k_den", "max_events", "attr_mode")]
+                                         "k_num", "k_den", "max_events", "attr_mode", "data_bw")] + \
+               [("data_kib", C.c_void_p)]
 
 
 def params(policy="inspirit", unit_time=0, s_inc=-1, s_dec=-1, dec_step=-1, c=-1, k_num=-1, k_den=-1,
-           max_events=0, attr_mode="direct") -> Params:
+           max_events=0, attr_mode="direct", data_bw=0, data_kib=None) -> Params:
+    """data_bw > 0 turns the data model on; data_kib (int32 numpy array, one
+    entry per task, kept alive by the caller) gives each task's output KiB."""
     pol = POLICY[policy] if isinstance(policy, str) else int(policy)
     am = ATTR_MODE[attr_mode] if isinstance(attr_mode, str) else int(attr_mode)
-    return Params(pol, unit_time, s_inc, s_dec, dec_step, c, k_num, k_den, max_events, am)
+    return Params(pol, unit_time, s_inc, s_dec, dec_step, c, k_num, k_den, max_events, am, data_bw,
+                  None if data_kib is None else data_kib.ctypes.data)
 
 
 TRACE_DTYPE = np.dtype([("t", "<i8"), ("nready", "<i4"), ("mode", "<i4"), ("cnt", "<i4"), ("peak", "<i4"),
@@ -160,7 +171,8 @@ def schedule(w, policy="inspirit", variant=PLAIN, trace=False, **kw):
     """Schedule one synth.Workload (or any object with n, row_ptr, col, dur,
     est, n_cpu, n_gpu).  Returns a dict of numpy outputs."""
     n = int(w.n)
-    p = params(policy=policy, **kw)
+    kib = _i32(w.data_kib) if kw.get("data_bw", 0) > 0 else None
+    p = params(policy=policy, data_kib=kib, **kw)
     rp, col = _i32(w.row_ptr), _i32(w.col)
     dur, est = _i32(w.dur).reshape(-1), _i32(w.est).reshape(-1)
     N = max(n, 1)
@@ -188,7 +200,8 @@ def schedule(w, policy="inspirit", variant=PLAIN, trace=False, **kw):
 
 def schedule_batch(batch, policy="inspirit", variant=HEAP, threads=None, **kw):
     """Schedule a synth.Batch on host threads; returns concatenated outputs."""
-    p = params(policy=policy, **kw)
+    kib = _i32(batch.data_kib) if kw.get("data_bw", 0) > 0 else None
+    p = params(policy=policy, data_kib=kib, **kw)
     B = batch.n_dags
     ntot = int(batch.task_off[-1])
     N = max(ntot, 1)

@@ -24,7 +24,9 @@
  *   - the transitive reading of the attributes (all descendants, and the
  *     descendants finishing within a unit-time window, Sections 4.3 and 7),
  *     used as fixed keys when a schedule asks for them;
- *   - the HEFT upward-rank list baseline the paper compares against.
+ *   - the HEFT upward-rank list baseline the paper compares against;
+ *   - a data model: per-task output items on memory nodes, DMDA's transfer
+ *     term at push and the efficiency-with-locality pop rule.
  * Readings taken where the paper is silent or garbled are listed at the
  * function that applies them.
  *
@@ -41,7 +43,7 @@
 #include <string.h>
 
 enum { ORC_OK = 0, ORC_E_INVAL = 1, ORC_E_CYCLE = 2, ORC_E_RANGE = 3, ORC_E_NOMEM = 4, ORC_E_HANG = 6 };
-enum { POL_INSPIRIT = 0, POL_FIFO = 1, POL_ABILITY = 2, POL_EFI = 3, POL_RANK = 4 };
+enum { POL_INSPIRIT = 0, POL_FIFO = 1, POL_ABILITY = 2, POL_EFI = 3, POL_RANK = 4, POL_LOCALITY = 5 };
 enum { M_ABILITY = 0, M_EFI = 1, M_EFI_LOC = 2, M_FIFO = 3, M_RANK = 4 };
 enum { ORC_PLAIN = 0, ORC_HEAP = 1 };
 
@@ -55,6 +57,8 @@ typedef struct {
     int32_t s_inc, s_dec, dec_step, c, k_num, k_den;
     int32_t max_events;
     int32_t attr_mode;  /* 0: direct attributes; 1: transitive (static) attributes */
+    int32_t data_bw;    /* data model: bytes moved per tick between memory nodes (0 = no data model) */
+    const int32_t *data_kib; /* data model: KiB of each task's output item */
 } orc_params;
 
 typedef struct {
@@ -491,6 +495,25 @@ static int ivec_push(ivec *q, int32_t x) {
 
 enum { ST_WAIT = 0, ST_QUEUED = 1, ST_RUN = 2, ST_DONE = 3 };
 
+/* Data model (the paper names DMDA's data-transfer term, Section 2, and a
+ * data-locality pop rule, Section 4.4, without formulas; this reading keeps
+ * both to integer ticks).  Memory node of worker w: 0 (host) for the CPU
+ * workers, 1 + (w - n_cpu) for GPU worker w.  Task u leaves one output item of
+ * data_kib[u] KiB on the node of the worker that ran it, its home; items are
+ * not replicated.  A consumer on another node moves it in
+ * xc(u) = ceil(1024 data_kib[u] / bw) ticks. */
+static int node_of(int32_t w, int32_t n_cpu) { return w < n_cpu ? 0 : 1 + (w - n_cpu); }
+
+static int64_t xfer_in(const orc_params *p, const int32_t *prp, const int32_t *pcol, const int32_t *home,
+                       int32_t v, int node) {
+    int64_t x = 0;
+    for (int32_t e = prp[v]; e < prp[v + 1]; e++) {
+        int32_t u = pcol[e];
+        if (home[u] != node) x += ((int64_t)1024 * p->data_kib[u] + p->data_bw - 1) / p->data_bw;
+    }
+    return x;
+}
+
 /*
  * Simulate one DAG (canonical CSR) on n_cpu CPU workers (kind 0, ids
  * 0..n_cpu-1) and n_gpu GPU workers (kind 1).  Integer time; one iteration
@@ -510,6 +533,14 @@ enum { ST_WAIT = 0, ST_QUEUED = 1, ST_RUN = 2, ST_DONE = 3 };
  *      successors' dependencies (Section 2).
  * Decisions use est, time advances with dur.  Returns ORC_E_HANG when more
  * than max_events iterations would be needed.
+ * With the data model (data_bw > 0): the push cost adds X(v, w), the transfer
+ * ticks of v's inputs whose home is not w's node (DMDA's transfer penalty);
+ * the queue's expected length still grows by the estimate alone, the
+ * transfers starting at the push and overlapping other work, so v's inputs
+ * arrive at arr(v) = t + X(v, chosen w).  A task popped at t starts at
+ * max(t, arr(v)).  The efficiency-with-locality rule takes the tasks whose
+ * inputs have arrived first, then the efficiency order.  X above 2^20 ticks
+ * is ORC_E_RANGE.
  */
 static int simulate(int32_t n, const int32_t *rp, const int32_t *col, int32_t n_cpu, int32_t n_gpu,
                     const int32_t *dur, const int32_t *est, const orc_params *p, int variant, int32_t *worker,
@@ -540,8 +571,11 @@ static int simulate(int32_t n, const int32_t *rp, const int32_t *col, int32_t n_
     int32_t *prp = NULL, *pcol = NULL, *touched = NULL;
     int32_t *done_now = (int32_t *)malloc(sizeof(int32_t) * (size_t)W);
     int64_t *R = p->policy == POL_RANK ? (int64_t *)calloc((size_t)n, sizeof(int64_t)) : NULL;
+    const int data = p->data_bw > 0;
+    int64_t *arr = data ? (int64_t *)calloc((size_t)n, sizeof(int64_t)) : NULL;
+    int32_t *home = data ? (int32_t *)calloc((size_t)n, sizeof(int32_t)) : NULL;
     if (!rem || !ia || !ie || !seq || !state || !qw || !newly || !run || !exp_end || !qest || !Q || !H || !done_now ||
-        (p->policy == POL_RANK && !R)) {
+        (p->policy == POL_RANK && !R) || (data && (!arr || !home))) {
         rc = ORC_E_NOMEM;
         goto out;
     }
@@ -562,8 +596,8 @@ static int simulate(int32_t n, const int32_t *rp, const int32_t *col, int32_t n_
     orc_reg reg;
     reg_init(&reg, p, W, tau_bar);
 
-    if (variant == ORC_HEAP) {
-        /* predecessor lists, to find a successor's last unfinished predecessor */
+    if (variant == ORC_HEAP || data) {
+        /* predecessor lists: a successor's last unfinished predecessor; inputs */
         prp = (int32_t *)calloc((size_t)n + 1, sizeof(int32_t));
         pcol = (int32_t *)malloc(sizeof(int32_t) * (size_t)(rp[n] > 0 ? rp[n] : 1));
         touched = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
@@ -586,7 +620,8 @@ static int simulate(int32_t n, const int32_t *rp, const int32_t *col, int32_t n_
     int32_t seqctr = 0, done = 0;
     int64_t events = 0;
     int mode_fixed = p->policy == POL_FIFO ? M_FIFO : p->policy == POL_ABILITY ? M_ABILITY
-                   : p->policy == POL_EFI ? M_EFI : p->policy == POL_RANK ? M_RANK : -1;
+                   : p->policy == POL_EFI ? M_EFI : p->policy == POL_RANK ? M_RANK
+                   : p->policy == POL_LOCALITY ? M_EFI_LOC : -1;
     /* keys that never change while queued: push order, upward rank */
     int static_key = mode_fixed == M_FIFO || mode_fixed == M_RANK;
 
@@ -595,14 +630,17 @@ static int simulate(int32_t n, const int32_t *rp, const int32_t *col, int32_t n_
         /* 1. push */
         for (int32_t i = 0; i < n_new; i++) {
             int32_t v = newly[i], best = -1;
-            int64_t bestc = 0;
+            int64_t bestc = 0, bestx = 0;
             for (int32_t w = 0; w < W; w++) {
                 int k = w < n_cpu ? 0 : 1;
                 int64_t B = t;
                 if (run[w] >= 0 && exp_end[w] > t) B = exp_end[w];
-                int64_t c = B + qest[w] + est[2 * (int64_t)v + k];
-                if (best < 0 || c < bestc) { best = w; bestc = c; }
+                int64_t x = data ? xfer_in(p, prp, pcol, home, v, node_of(w, n_cpu)) : 0;
+                int64_t c = B + qest[w] + est[2 * (int64_t)v + k] + x;
+                if (best < 0 || c < bestc) { best = w; bestc = c; bestx = x; }
             }
+            if (bestx > ORC_MAX_TICK) { rc = ORC_E_RANGE; goto out; }
+            if (data) arr[v] = t + bestx;
             int k = best < n_cpu ? 0 : 1;
             seq[v] = seqctr++;
             state[v] = ST_QUEUED;
@@ -629,6 +667,8 @@ static int simulate(int32_t n, const int32_t *rp, const int32_t *col, int32_t n_
             if (run[w] >= 0) continue;
             int k = w < n_cpu ? 0 : 1;
             int32_t v = -1, v_ie = 0;
+            /* efficiency with locality: inputs already on the node first */
+            const int loc = data && mode == M_EFI_LOC;
             if (variant == ORC_PLAIN) {
                 if (Q[w].len == 0) continue;
                 int64_t bi = -1;
@@ -637,8 +677,10 @@ static int simulate(int32_t n, const int32_t *rp, const int32_t *col, int32_t n_
                     int32_t x = Q[w].a[i];
                     int32_t x_ie = ie_static ? ie[x] : ie_def(rp, col, est, n_gpu, rem, U, x);
                     int32_t y = bi < 0 ? x : Q[w].a[bi];
-                    if (bi < 0 || outranks_r(order, R ? R[x] : 0, R ? R[y] : 0, ia[x], x_ie, seq[x], ia[y], b_ie,
-                                             seq[y])) {
+                    int here_x = loc && arr[x] <= t, here_y = loc && arr[y] <= t;
+                    if (bi < 0 || here_x > here_y ||
+                        (here_x == here_y && outranks_r(order, R ? R[x] : 0, R ? R[y] : 0, ia[x], x_ie, seq[x],
+                                                        ia[y], b_ie, seq[y]))) {
                         bi = i;
                         b_ie = x_ie;
                     }
@@ -650,7 +692,17 @@ static int simulate(int32_t n, const int32_t *rp, const int32_t *col, int32_t n_
             } else {
                 heap *h = &H[2 * w + (order == 1 ? 1 : 0)];
                 hctx c = {ia, ie, seq, order, R};
-                while (h->len > 0) {
+                if (loc) {
+                    /* the best queued task whose inputs have arrived, by a
+                       scan of the heap's live entries (it stays in the heap
+                       and is skipped once running) */
+                    for (int64_t i = 0; i < h->len; i++) {
+                        hent x = h->a[i];
+                        if (state[x.v] != ST_QUEUED || x.ie != ie[x.v] || arr[x.v] > t) continue;
+                        if (v < 0 || outranks(1, ia[x.v], x.ie, seq[x.v], ia[v], ie[v], seq[v])) v = x.v;
+                    }
+                }
+                while (v < 0 && h->len > 0) {
                     hent top = hpop(h, &c);
                     if (state[top.v] == ST_QUEUED && (order >= 2 || top.ie == ie[top.v])) { v = top.v; break; }
                 }
@@ -659,9 +711,11 @@ static int simulate(int32_t n, const int32_t *rp, const int32_t *col, int32_t n_
             }
             state[v] = ST_RUN;
             run[w] = v;
-            start[v] = t;
-            finish[v] = t + dur[2 * (int64_t)v + k];
-            exp_end[w] = t + est[2 * (int64_t)v + k];
+            int64_t s0 = data && arr[v] > t ? arr[v] : t;  /* waits for its inputs */
+            start[v] = s0;
+            finish[v] = s0 + dur[2 * (int64_t)v + k];
+            exp_end[w] = s0 + est[2 * (int64_t)v + k];
+            if (data) home[v] = node_of(w, n_cpu);
             qest[w] -= est[2 * (int64_t)v + k];
             worker[v] = w;
             if (ie_at_pop) ie_at_pop[v] = v_ie;
@@ -729,7 +783,7 @@ static int simulate(int32_t n, const int32_t *rp, const int32_t *col, int32_t n_
 
 out:
     free(rem); free(ia); free(ie); free(seq); free(state); free(qw); free(newly); free(run);
-    free(exp_end); free(qest); free(done_now); free(prp); free(pcol); free(touched); free(R);
+    free(exp_end); free(qest); free(done_now); free(prp); free(pcol); free(touched); free(R); free(arr); free(home);
     if (Q) for (int32_t w = 0; w < W; w++) free(Q[w].a);
     if (H) for (int32_t w = 0; w < 2 * W; w++) free(H[w].a);
     free(Q);
@@ -739,9 +793,12 @@ out:
 
 static int check_params(int32_t n, int32_t n_cpu, int32_t n_gpu, const int32_t *dur, const int32_t *est,
                         const orc_params *p) {
-    if (n_cpu < 0 || n_gpu < 0 || p->policy < 0 || p->policy > 4 || p->unit_time < 0 || p->max_events < 0 ||
-        p->attr_mode < 0 || p->attr_mode > 1)
+    if (n_cpu < 0 || n_gpu < 0 || p->policy < 0 || p->policy > 5 || p->unit_time < 0 || p->max_events < 0 ||
+        p->attr_mode < 0 || p->attr_mode > 1 || p->data_bw < 0 || (p->data_bw > 0 && !p->data_kib))
         return ORC_E_INVAL;
+    if (p->data_bw > 0)
+        for (int32_t v = 0; v < n; v++)
+            if (p->data_kib[v] < 0 || p->data_kib[v] > ORC_MAX_TICK) return ORC_E_RANGE;
     int32_t W = n_cpu + n_gpu;
     if (W < 1 || W > ORC_MAX_W) return ORC_E_RANGE;
     if (n > ORC_MAX_N) return ORC_E_RANGE;
@@ -796,8 +853,10 @@ static void *batch_worker(void *arg) {
         if (b >= j->B) break;
         int64_t t0 = j->toff[b], e0 = j->eoff[b];
         int32_t n = (int32_t)(j->toff[b + 1] - t0);
+        orc_params pb = *j->p;
+        if (pb.data_kib) pb.data_kib += t0;
         j->status[b] = orc_schedule(n, j->rp + t0 + b, j->col + e0, j->n_cpu[b], j->n_gpu[b], j->dur + 2 * t0,
-                                    j->est + 2 * t0, j->p, j->variant, j->worker + t0, j->start + t0,
+                                    j->est + 2 * t0, &pb, j->variant, j->worker + t0, j->start + t0,
                                     j->finish + t0, j->makespan + b, j->ie_at_pop ? j->ie_at_pop + t0 : NULL,
                                     j->mode_at_pop ? j->mode_at_pop + t0 : NULL, NULL, 0, NULL, NULL);
     }

@@ -702,3 +702,105 @@ def test_transitive_schedule_plain_and_heap_agree():
             b = oracle.schedule(w, policy=pol, variant=oracle.HEAP, attr_mode="transitive")
             for k in ("worker", "start", "finish", "ie_at_pop", "mode_at_pop"):
                 assert np.array_equal(a[k], b[k]), (i, pol, k)
+
+
+# ------------------------------------------------------------ data model (f2)
+
+def _data_w(g):
+    d = np.asarray(g["dur"], np.int32)
+    return NS(n=g["n"], row_ptr=np.asarray(g["row_ptr"], np.int32), col=np.asarray(g["col"], np.int32), dur=d,
+              est=d, n_cpu=g["n_cpu"], n_gpu=g["n_gpu"], data_kib=np.asarray(g["data_kib"], np.int32))
+
+
+@pytest.mark.parametrize("variant", [oracle.PLAIN, oracle.HEAP])
+def test_w11_data_model_hand_worked(variant):
+    g = gold("w11_data.json")["w11"]
+    w = _data_w(g)
+    for pol, key, bw in (("locality", "locality", g["data_bw"]), ("efi", "efi", g["data_bw"]),
+                         ("locality", "locality_no_data", 0)):
+        r = oracle.schedule(w, policy=pol, variant=variant, unit_time=g["unit_time"], data_bw=bw)
+        for f in ("worker", "start", "finish"):
+            assert r[f].tolist() == g[key][f], (key, f)
+        assert r["makespan"] == g[key]["makespan"], key
+        # a worker holding a task whose inputs are still moving is busy
+        # but not running it, so the non-idling property does not apply
+        check_schedule(w, r["worker"], r["start"], r["finish"], r["makespan"], non_idling=bw == 0)
+    r = oracle.schedule(w, policy="locality", variant=variant, unit_time=g["unit_time"], data_bw=g["data_bw"])
+    assert r["ie_at_pop"].tolist() == g["locality"]["ie_at_pop"]
+    assert set(r["mode_at_pop"].tolist()) == {g["locality"]["mode_at_pop"]}
+
+
+@pytest.mark.parametrize("variant", [oracle.PLAIN, oracle.HEAP])
+def test_w12_transfers_overlap_and_are_not_shared(variant):
+    g = gold("w11_data.json")["w12"]
+    r = oracle.schedule(_data_w(g), policy="fifo", variant=variant, data_bw=g["data_bw"])
+    for f in ("worker", "start", "finish"):
+        assert r[f].tolist() == g["fifo"][f], f
+    assert r["makespan"] == g["fifo"]["makespan"]
+
+
+def _with_data(w, seed, hi=64):
+    w.data_kib = synth.Stream(seed, 9).randint(np.arange(w.n), 0, hi).astype(np.int32)
+    return w
+
+
+@pytest.mark.parametrize("policy", ["inspirit", "fifo", "efi", "locality", "heft"])
+def test_data_model_reduces_to_the_plain_model(policy):
+    # no transfer ever costs anything when every item is empty, when all
+    # workers share one memory node (CPUs only, or a single GPU), so the
+    # schedules are those of the model without data
+    for i in range(20):
+        w = _with_data(synth.random_dag(71, i, 3 + i * 3, 0.12, n_cpu=1 + i % 3, n_gpu=1 + i % 2, dur_hi=30), i)
+        base = oracle.schedule(w, policy=policy, variant=oracle.HEAP)
+        w0 = NS(**{**vars(w), "data_kib": np.zeros(w.n, np.int32)})
+        r = oracle.schedule(w0, policy=policy, variant=oracle.HEAP, data_bw=100)
+        assert np.array_equal(r["start"], base["start"]) and np.array_equal(r["worker"], base["worker"]), i
+        for n_cpu, n_gpu in ((3, 0), (0, 1)):
+            wm = NS(**{**vars(w), "n_cpu": n_cpu, "n_gpu": n_gpu})
+            a = oracle.schedule(wm, policy=policy, variant=oracle.HEAP)
+            b = oracle.schedule(wm, policy=policy, variant=oracle.HEAP, data_bw=7)
+            assert np.array_equal(a["start"], b["start"]) and np.array_equal(a["worker"], b["worker"]), (i, n_cpu)
+
+
+@pytest.mark.parametrize("policy", ["inspirit", "locality", "fifo"])
+def test_data_model_start_covers_input_transfers(policy):
+    # every input moved from another memory node costs its ticks after the
+    # task became ready: start >= last input's finish + the sum of the remote
+    # inputs' transfer ticks (the transfers of one task run back to back)
+    for i in range(30):
+        bw = 256 + 512 * (i % 4)
+        w = _with_data(synth.random_dag(72, i, 5 + i * 2, 0.15, n_cpu=1 + i % 3, n_gpu=1 + i % 3, dur_hi=40,
+                                        est_equal=(i % 2 == 0)), 50 + i, hi=200)
+        r = oracle.schedule(w, policy=policy, variant=oracle.HEAP, data_bw=bw)
+        check_schedule(w, r["worker"], r["start"], r["finish"], r["makespan"], non_idling=False)
+        rp, col = oracle.canon(w.n, w.row_ptr, w.col)
+        node = np.where(r["worker"] < w.n_cpu, 0, 1 + r["worker"] - w.n_cpu)
+        preds = [[] for _ in range(w.n)]
+        for u in range(w.n):
+            for s in col[rp[u]:rp[u + 1]]:
+                preds[s].append(u)
+        for v in range(w.n):
+            if preds[v]:
+                ready = max(r["finish"][u] for u in preds[v])
+                x = sum(-(-1024 * int(w.data_kib[u]) // bw) for u in preds[v] if node[u] != node[v])
+                assert r["start"][v] >= ready + x, (i, v)
+
+
+def test_data_model_plain_and_heap_agree():
+    for i in range(40):
+        w = _with_data(synth.random_dag(73, i, 2 + i * 2, 0.1, n_cpu=1 + i % 4, n_gpu=i % 3, dur_hi=30,
+                                        est_equal=(i % 2 == 0)), 90 + i)
+        for pol in ("inspirit", "locality"):
+            for am in ("direct", "transitive"):
+                a = oracle.schedule(w, policy=pol, variant=oracle.PLAIN, data_bw=512, attr_mode=am)
+                b = oracle.schedule(w, policy=pol, variant=oracle.HEAP, data_bw=512, attr_mode=am)
+                for k in ("worker", "start", "finish", "ie_at_pop", "mode_at_pop"):
+                    assert np.array_equal(a[k], b[k]), (i, pol, am, k)
+
+
+def test_data_model_range_checks():
+    w = _with_data(synth.random_dag(74, 0, 6, 0.4, n_cpu=1, n_gpu=1), 1)
+    w.data_kib[0] = -1
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.schedule(w, data_bw=10)
+    assert e.value.code == oracle.E_RANGE

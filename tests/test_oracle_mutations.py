@@ -25,11 +25,11 @@ MUTATIONS = {
                              "if (score > bestScore) { bestScore = score; bestU = U; }"),
     "ladder_one_rung_short": ("while (((int64_t)1 << J) < 2 * maxtau) J++;",
                               "while (((int64_t)1 << J) < maxtau) J++;"),
-    "dmda_tie_highest_worker": ("if (best < 0 || c < bestc) { best = w; bestc = c; }",
-                                "if (best < 0 || c <= bestc) { best = w; bestc = c; }"),
+    "dmda_tie_highest_worker": ("if (best < 0 || c < bestc) { best = w; bestc = c; bestx = x; }",
+                                "if (best < 0 || c <= bestc) { best = w; bestc = c; bestx = x; }"),
     "dmda_ignores_running_task": ("if (run[w] >= 0 && exp_end[w] > t) B = exp_end[w];", ""),
-    "dmda_ignores_queue": ("int64_t c = B + qest[w] + est[2 * (int64_t)v + k];",
-                           "int64_t c = B + est[2 * (int64_t)v + k];"),
+    "dmda_ignores_queue": ("int64_t c = B + qest[w] + est[2 * (int64_t)v + k] + x;",
+                           "int64_t c = B + est[2 * (int64_t)v + k] + x;"),
     "tau_cpu_column": ("return est[2 * (int64_t)v + (n_gpu > 0 ? 1 : 0)];", "return est[2 * (int64_t)v];"),
     "ability_order_reversed": ("if (ia_a != ia_b) return ia_a > ia_b;\n        if (ie_a != ie_b) return ie_a > ie_b;\n    } else if (order == 1) {",
                                "if (ia_a != ia_b) return ia_a < ia_b;\n        if (ie_a != ie_b) return ie_a > ie_b;\n    } else if (order == 1) {"),
@@ -56,6 +56,15 @@ MUTATIONS = {
     "trans_ladder_tie_smaller": ("if (score >= bestScore) { bestScore = score; bestJ = j; }",
                                  "if (score > bestScore) { bestScore = score; bestJ = j; }"),
     "trans_source_excluded": ("EF[v] = tau_of(est, n_gpu, v);", "EF[v] = 1;"),
+    "data_no_transfer_term": ("int64_t c = B + qest[w] + est[2 * (int64_t)v + k] + x;",
+                              "int64_t c = B + qest[w] + est[2 * (int64_t)v + k];"),
+    "data_transfer_in_queue": ("            qest[best] += est[2 * (int64_t)v + k];",
+                               "            qest[best] += est[2 * (int64_t)v + k] + bestx;"),
+    "data_no_wait": ("int64_t s0 = data && arr[v] > t ? arr[v] : t;", "int64_t s0 = t;"),
+    "data_locality_ignored": ("const int loc = data && mode == M_EFI_LOC;", "const int loc = 0;"),
+    "data_all_host": ("static int node_of(int32_t w, int32_t n_cpu) { return w < n_cpu ? 0 : 1 + (w - n_cpu); }",
+                      "static int node_of(int32_t w, int32_t n_cpu) { return w < n_cpu ? 0 : 1; }"),
+    "data_home_of_consumer": ("if (home[u] != node) x +=", "if (home[u] == node) x +="),
 }
 
 
@@ -165,6 +174,24 @@ def pins():
     for i in range(6):
         w = synth.random_dag(58, i, 14, 0.2, dur_hi=20, n_cpu=1, n_gpu=1, est_equal=False)
         chk(f"tladder{i}", lambda w=w: _transitive_ladder_ok(w))
+    # data model: the hand-worked fixtures W11 and W12
+    gd = json.load(open(os.path.join(GOLD, "w11_data.json")))
+    for key, pol, fx, bw in (("w11", "locality", "locality", 1024), ("w11", "efi", "efi", 1024),
+                             ("w12", "fifo", "fifo", 1024)):
+        g = gd[key]
+        d = np.asarray(g["dur"], np.int32)
+        wd = NS(n=g["n"], row_ptr=np.asarray(g["row_ptr"], np.int32), col=np.asarray(g["col"], np.int32), dur=d,
+                est=d, n_cpu=g["n_cpu"], n_gpu=g["n_gpu"], data_kib=np.asarray(g["data_kib"], np.int32))
+        chk(f"{key}{pol}", lambda wd=wd, pol=pol, g=g, fx=fx, bw=bw: oracle.schedule(
+            wd, policy=pol, data_bw=bw, unit_time=g.get("unit_time", 0))["start"].tolist() == g[fx]["start"])
+    # two GPUs: an item moves between GPU memories as well
+    d2 = np.array([[50, 2], [50, 2], [50, 3]], np.int32)
+    w2g = NS(n=3, row_ptr=np.array([0, 0, 1, 1], np.int32), col=np.array([2], np.int32), dur=d2, est=d2, n_cpu=1,
+             n_gpu=2, data_kib=np.array([0, 9, 0], np.int32))
+    # t=0: task 0 -> GPU worker 1, task 1 -> GPU worker 2 (worker 1 now 2 ticks long); t=2: task 2 reads
+    # item 1, which lives on worker 2's memory: 2+3+9 on worker 1 against 2+3 on worker 2 (a tie, won by
+    # worker 1, if both GPUs shared one memory)
+    chk("twogpu", lambda: oracle.schedule(w2g, policy="fifo", data_bw=1024)["worker"].tolist() == [1, 2, 2])
     # invariants and brute force on small random DAGs
     for i in range(6):
         w = synth.random_dag(77, i, 7, 0.3, dur_hi=6, n_cpu=1, n_gpu=1)
