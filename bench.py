@@ -22,6 +22,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "tasks scheduled/s on 4096-DAG batch, bit-exact makespan; learned vs plain gap"
+# Data model preset: every task leaves one 960 x 960 fp32 tile (the paper's
+# Cholesky block); with a GPU GEMM tile at 25 ticks (~60 us), a tick is ~2.4
+# us, and a ~25 GB/s host link moves a tile in ~150 us = 60 ticks.
+TILE_KIB = 3600
+TILE_BW = 61440
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_batch4096.txt")
 SIM_SOURCES = [os.path.join(ROOT, "paper_2404_03226_amd", "csrc", f) for f in ("sim.hip", "common.hpp", "internal.hpp")]
@@ -141,6 +146,8 @@ def main():
                     help="single DAG: record the per-event trace, check it against the oracle's, report Nready over time")
     ap.add_argument("--transitive", action="store_true",
                     help="also time the transitive attribute pass and the schedule ordered by it (sampled check)")
+    ap.add_argument("--data", action="store_true",
+                    help="data model: every task leaves one 960x960 fp32 tile, moved at 60 KiB per tick")
     ap.add_argument("--print-sources-sha256", action="store_true")
     args = ap.parse_args()
     if args.print_sources_sha256:
@@ -166,7 +173,11 @@ def main():
     torch.cuda.set_device(0)
     dag, dur, est = inspirit.batch_to_device(b)
     workers = [(w.n_cpu, w.n_gpu) for w in ws]
-    prm = inspirit.params(policy=args.policy)
+    data_bw = TILE_BW if args.data else 0
+    if args.data:
+        b.data_kib = np.full(N, TILE_KIB, np.int32)
+        inspirit.set_task_data(dag, torch.from_numpy(b.data_kib).to(dur.device))
+    prm = inspirit.params(policy=args.policy, data_bw=data_bw)
     out = inspirit._outputs(N, dur.device)
     out["makespan"] = torch.empty(len(ws), dtype=torch.int64, device=dur.device)
     stream = torch.cuda.current_stream()
@@ -251,7 +262,7 @@ def main():
     threads = min(os.cpu_count() or 1, 16)
     if not args.no_cpu_baseline or not args.no_verify:
         t1 = time.time()
-        ref = oracle.schedule_batch(b, policy=args.policy, variant=oracle.HEAP, threads=threads)
+        ref = oracle.schedule_batch(b, policy=args.policy, variant=oracle.HEAP, threads=threads, data_bw=data_bw)
         wall = time.time() - t1
         log(f"oracle: {wall:.2f}s on {threads} threads")
         if not args.no_verify:
@@ -276,7 +287,8 @@ def main():
         "dtype": "int64",
         "data": "synthetic",
         "config": {"workload": desc, "n_dags": len(ws), "tasks": N, "edges": M, "policy": args.policy,
-                   "launch": tune_key or "default"},
+                   "launch": tune_key or "default",
+                   "data_model": (f"{TILE_KIB} KiB per task, {TILE_BW} B/tick" if args.data else None)},
         "bit_exact": bit_exact,
         "schedule_sha256": digest.hexdigest(),
         "roofline": roof,
@@ -289,14 +301,16 @@ def main():
         "transitive": None,
     }
     if args.compare_policies:
-        line["policies_vs_dmda"] = compare_policies(dag, workers, b, dur, est, threads)
+        line["policies_vs_dmda"] = compare_policies(dag, workers, b, dur, est, threads, data_bw)
     if args.trace and len(ws) == 1:
         w = ws[0]
         o = inspirit.schedule(dag, 0, (w.n_cpu, w.n_gpu), dur, est, prm, trace=True)
         inspirit.sync_status(dag)
         nev = int(o["n_events"].item())
         rec = inspirit.trace_records(o["trace"], nev)
-        ref = oracle.schedule(w, policy=args.policy, variant=oracle.HEAP, trace=True)["trace"]
+        if args.data:
+            w.data_kib = b.data_kib
+        ref = oracle.schedule(w, policy=args.policy, variant=oracle.HEAP, trace=True, data_bw=data_bw)["trace"]
         same = bool(len(ref) == nev and all(np.array_equal(rec[f], ref[f]) for f in ref.dtype.names))
         line["nready_trace"] = {"events": nev, "bit_exact": same, "profile": nready_profile(rec)}
     if args.transitive:
@@ -382,7 +396,7 @@ def transitive_measure(dag, workers, ws, b, dur, est, steps, warmup, tune_key):
     return t
 
 
-def compare_policies(dag, workers, b, dur, est, threads):
+def compare_policies(dag, workers, b, dur, est, threads, data_bw=0):
     """Per-DAG makespan under each pop rule, and under the HEFT upward-rank
     list baseline, relative to the plain DMDA push with FIFO queues (the
     method's baseline): speedup = M_dmda / M_policy.  Every makespan is
@@ -390,14 +404,15 @@ def compare_policies(dag, workers, b, dur, est, threads):
     import oracle
     from paper_2404_03226_amd import inspirit
     ms, exact = {}, True
-    for pol in ("fifo", "inspirit", "ability", "efi", "heft"):
-        o = inspirit.schedule_batch(dag, workers, dur, est, inspirit.params(policy=pol))
+    pols = ("fifo", "inspirit", "ability", "efi", "heft") + (("locality",) if data_bw else ())
+    for pol in pols:
+        o = inspirit.schedule_batch(dag, workers, dur, est, inspirit.params(policy=pol, data_bw=data_bw))
         inspirit.sync_status(dag)
         ms[pol] = o["makespan"].cpu().numpy().astype(np.float64)
-        ref = oracle.schedule_batch(b, policy=pol, variant=oracle.HEAP, threads=threads)["makespan"]
+        ref = oracle.schedule_batch(b, policy=pol, variant=oracle.HEAP, threads=threads, data_bw=data_bw)["makespan"]
         exact = exact and bool(np.array_equal(ms[pol], ref))
     out = {"makespans_bit_exact": exact}
-    for pol in ("inspirit", "ability", "efi", "heft"):
+    for pol in pols[1:]:
         sp = ms["fifo"] / ms[pol]
         out[pol] = {"geo_mean_speedup": round(float(np.exp(np.mean(np.log(sp)))), 4),
                     "max_speedup": round(float(sp.max()), 4), "min_speedup": round(float(sp.min()), 4),

@@ -50,17 +50,19 @@ typedef enum {
     INSP_POLICY_FIFO = 1,         /* plain DMDA: each worker pops in push order */
     INSP_POLICY_ABILITY_ONLY = 2, /* always the high-ability rule */
     INSP_POLICY_EFI_ONLY = 3,     /* always the high-efficiency rule */
-    INSP_POLICY_HEFT = 4          /* HEFT list baseline (Section 6): highest upward rank
+    INSP_POLICY_HEFT = 4,         /* HEFT list baseline (Section 6): highest upward rank
                                      R(v) = n_cpu est_cpu(v) + n_gpu est_gpu(v) + max over
                                      successors R(s), then earliest push; R < 2^42 or the
                                      DAG fails with INSP_E_RANGE at insp_sync_status */
+    INSP_POLICY_LOCALITY = 5      /* always the efficiency-with-locality rule */
 } insp_policy;
 
 /* Pop rule in force at a pop (mode_at_pop) and in trace records. */
 typedef enum {
     INSP_MODE_ABILITY = 0, /* highest IA, then highest IE, then earliest push */
     INSP_MODE_EFI = 1,     /* highest IE, then highest IA, then earliest push */
-    INSP_MODE_EFI_LOC = 2, /* efficiency-and-locality rule; no data model, so ordered as EFI */
+    INSP_MODE_EFI_LOC = 2, /* efficiency with locality: with the data model the tasks whose inputs
+                              have arrived first, then as EFI; without it, as EFI */
     INSP_MODE_FIFO = 3,    /* earliest push */
     INSP_MODE_RANK = 4     /* highest HEFT upward rank, then earliest push */
 } insp_mode;
@@ -101,6 +103,18 @@ typedef struct {
  * attr_mode picks the attribute reading the queues are ordered by: with
  * INSP_ATTR_TRANSITIVE the keys are IA_T and IE_T (insp_transitive_attributes,
  * unit_time being their window U), fixed for the run.
+ * data_bw > 0 turns on the data model (Section 2: DMDA weighs data transfers
+ * and the push starts them; Section 4.4: the efficiency-with-locality rule).
+ * The handle needs per-task output sizes (insp_set_task_data).  Memory node
+ * of a worker: the host for CPU workers, its own memory for each GPU worker.
+ * Task u leaves one output item of data_kib[u] KiB on its worker's node (not
+ * replicated); a consumer on another node moves it in
+ * ceil(1024 data_kib[u] / data_bw) ticks.  The push cost adds X(v, w), the
+ * ticks of v's inputs not on w's node; the queue length still grows by the
+ * estimate alone (the transfers start at the push and overlap other work);
+ * v's inputs arrive at t + X(v, chosen worker), and a popped task starts when
+ * they have arrived (its worker waits).  X above 2^20 ticks fails the DAG
+ * with INSP_E_RANGE at insp_sync_status.
  */
 typedef struct {
     int32_t policy;
@@ -108,6 +122,7 @@ typedef struct {
     int32_t s_inc, s_dec, dec_step, c, k_num, k_den;
     int32_t max_events;
     int32_t attr_mode; /* insp_attr_mode; TRANSITIVE needs DAGs of <= INSP_MAX_TRANSITIVE_TASKS */
+    int32_t data_bw;   /* data model: bytes moved per tick between memory nodes; 0 = no data model */
 } insp_params;
 
 /* One record per simulation event: the Nready the regulator observed (after
@@ -138,6 +153,15 @@ typedef struct {
  */
 int insp_build_dag(int32_t n_dags, const int64_t *task_off, const int64_t *edge_off, const int32_t *row_ptr,
                    const int32_t *col, const int32_t *type, void *stream, insp_dag **out);
+
+/*
+ * insp_set_task_data -- attach per-task output sizes to a handle for the data
+ * model (see insp_params.data_bw).
+ *   data_kib  device int32 [task_off[B]], KiB of each task's output item, in
+ *             [0, 2^20]; copied (the caller keeps its buffer); NULL detaches
+ * INSP_E_RANGE for a size out of range.  The call synchronises `stream`.
+ */
+int insp_set_task_data(insp_dag *dag, const int32_t *data_kib, void *stream);
 
 /* Release a handle from insp_build_dag (NULL is ignored).  The caller must
  * make sure no work using it is still running. */

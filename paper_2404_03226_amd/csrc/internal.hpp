@@ -133,6 +133,10 @@ struct insp_dag {
     insp::DevBuf ptau;                 // int32 [N]: tau by position
     insp::DevBuf tcum;                 // int32 [N * kTRungs]: members within 2^j
     insp::DevBuf tia, tie;             // int32 [N]: transitive IA, IE of the last schedule call
+    // data model: output KiB per task (insp_set_task_data), predecessor lists
+    insp::DevBuf dkib;                 // int32 [N]
+    insp::DevBuf pprp;                 // int32 [N + B]: local predecessor row pointers (as rp)
+    insp::DevBuf ppred;                // int32 [M]: predecessor ids (local)
     std::map<std::string, std::unique_ptr<insp::Workspace>> ws;
 };
 
@@ -142,7 +146,7 @@ constexpr int kRungs = 24;       // ladder rungs 2^0 .. 2^22 plus a sentinel
 
 // Per-DAG status bits (dag_stat[2 b]): estimate or duration out of range, the
 // event budget exhausted, a HEFT rank too wide for the queue key.
-enum { ST_EST = 1, ST_DUR = 2, ST_HANG = 4, ST_RANK = 8, ST_PATH = 16 };
+enum { ST_EST = 1, ST_DUR = 2, ST_HANG = 4, ST_RANK = 8, ST_PATH = 16, ST_XFER = 32 };
 constexpr int kRankBits = 42;
 constexpr int kTRungs = 32;  // transitive ladder rungs 2^0 .. 2^31
 constexpr int kAttrThreads = 256;
@@ -172,6 +176,9 @@ int run_attributes(insp_dag *dag, Workspace *ws, const int32_t *est, int32_t uni
 // HEFT upward ranks of a workspace's DAGs into dag->rank (levels are built
 // on the first call).  Runs after run_attributes, which clears the status.
 int run_rank(insp_dag *dag, Workspace *ws, const int32_t *est, hipStream_t st);
+
+// Predecessor lists of every DAG of the handle (built once).
+int ensure_preds(insp_dag *dag, hipStream_t st);
 
 // Kahn levels of every DAG of the handle (built once).
 int ensure_levels(insp_dag *dag, hipStream_t st);

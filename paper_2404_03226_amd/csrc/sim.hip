@@ -100,6 +100,9 @@ struct SimArgs {
     const int64_t *rank;  // HEFT upward ranks (global task index)
     const int32_t *tia, *tie;  // transitive IA, IE (global task index)
     int32_t attr_mode;
+    int32_t data_bw;           // data model: bytes per tick between memory nodes (0 = off)
+    const int32_t *dkib;       // data model: output KiB per task (global task index)
+    const int32_t *pprp, *ppred;  // predecessor lists (local row pointers as rp, ids as col)
     int32_t *stat;
     int32_t *counter;
     int64_t *makespan;
@@ -177,6 +180,10 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
     const bool skey = heft || trans;  // keys fixed while queued
     const int64_t *rk = A.rank + d.toff;
     const int32_t *tia = A.tia + d.toff, *tie = A.tie + d.toff;
+    // data model: inputs move between memory nodes (host for the CPU
+    // workers, one per GPU worker); see the push and the pop below
+    const bool data = A.data_bw > 0;
+    const int32_t *dkib = A.dkib + d.toff, *prp = A.pprp + d.toff + d.id, *pred = A.ppred + d.eoff;
     const int slot0 = A.policy == INSP_POLICY_FIFO ? 2 : heft ? 3 : 0;
     const int32_t max_events = A.max_events > 0 ? A.max_events : n + 1;
 
@@ -283,12 +290,40 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
             for (int32_t j = 0; j < cntj; j++) {
                 const int32_t v = read_lane(v_l, j);
                 const int32_t e0 = read_lane(e_l.x, j), e1 = read_lane(e_l.y, j);
+                // DMDA's transfer term: ticks to move the inputs whose home
+                // node is not the worker's (an item stays where it was made)
+                int64_t xk[WPL];
+#pragma unroll
+                for (int k = 0; k < WPL; k++) xk[k] = 0;
+                if (data) {
+                    const int32_t pa = prp[v], pz = prp[v + 1];
+                    for (int32_t c0 = pa; c0 < pz; c0 += kWave) {
+                        int32_t nu = 0;
+                        int64_t cu = 0;
+                        if (c0 + lane < pz) {
+                            const int32_t u = pred[c0 + lane];
+                            const int32_t wu = -2 - tr[u].qpos;  // worker of a finished task
+                            nu = wu < ncpu ? 0 : 1 + wu - ncpu;
+                            cu = ((int64_t)1024 * dkib[u] + A.data_bw - 1) / A.data_bw;
+                        }
+                        const int32_t cnt = min(kWave, pz - c0);
+                        for (int32_t jj = 0; jj < cnt; jj++) {
+                            const int32_t nj = read_lane(nu, jj);
+                            const int64_t cj = (int64_t)read_lane64((uint64_t)cu, jj);
+#pragma unroll
+                            for (int k = 0; k < WPL; k++) {
+                                const int32_t w = lane + k * kWave;
+                                if ((w < ncpu ? 0 : 1 + w - ncpu) != nj) xk[k] += cj;
+                            }
+                        }
+                    }
+                }
                 uint64_t best = ~0ull;
 #pragma unroll
                 for (int k = 0; k < WPL; k++) {
                     int32_t w = lane + k * kWave;
                     if (w < W) {
-                        uint64_t cst = (uint64_t)(ld[k] + (w < ncpu ? e0 : e1));
+                        uint64_t cst = (uint64_t)(ld[k] + (w < ncpu ? e0 : e1) + xk[k]);
                         uint64_t key = cst << 11 | (uint64_t)w;
                         best = key < best ? key : best;
                     }
@@ -296,6 +331,15 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
                 best = wave_min_u64(best);
                 const int32_t ws = (int32_t)(best & 2047);
                 const bool gpu = ws >= ncpu;
+                int64_t xs = 0;
+                if (data) {
+                    int64_t mine = 0;
+#pragma unroll
+                    for (int k = 0; k < WPL; k++)
+                        if (lane + k * kWave == ws) mine = xk[k];
+                    xs = (int64_t)read_lane64((uint64_t)mine, ws & 63);
+                    if (xs > INSP_MAX_TICK) status |= ST_XFER;
+                }
                 const int32_t ek = gpu ? e1 : e0;
                 const int32_t dk = read_lane(gpu ? d_l.y : d_l.x, j);
 #pragma unroll
@@ -335,6 +379,9 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
                     }
                     tr[v].qpos = p;
                     tr[v].seq = seq;
+                    // the dependency word is dead once a task is queued: it
+                    // holds the time its inputs arrive (transfers start now)
+                    if (data) tr[v].word = (unsigned long long)(t + xs);
                     const uint64_t a0 = key_of(kw, slot0), a1 = key_of(kw, 1);
                     if (blk < SC) {
                         if (pos == 0) {
@@ -389,7 +436,10 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
         const int pmode = A.policy == INSP_POLICY_FIFO ? INSP_MODE_FIFO
                         : A.policy == INSP_POLICY_ABILITY_ONLY ? INSP_MODE_ABILITY
                         : A.policy == INSP_POLICY_EFI_ONLY ? INSP_MODE_EFI
+                        : A.policy == INSP_POLICY_LOCALITY ? INSP_MODE_EFI_LOC
                         : heft ? INSP_MODE_RANK : mode;
+        // efficiency with locality: tasks whose inputs have arrived first
+        const bool loc = data && pmode == INSP_MODE_EFI_LOC;
         const int ord = heft ? 3 : pmode == INSP_MODE_FIFO ? 2 : pmode == INSP_MODE_ABILITY ? 0 : 1;
         const int slot = ord == 1 ? 1 : 0;
         // ------------------------------------------------------------- pop
@@ -403,7 +453,32 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
                 int32_t nb = L.nb[w], len = L.len[w];
                 const int32_t last = L.last[w];
                 int32_t bb = last;
-                if (nb > 1) {
+                bool lsel = false;
+                if (loc) {
+                    // the arrival times are not in the keys: scan every entry
+                    uint64_t bestk = 0;
+                    int32_t bestb = -1;
+                    const int32_t lp = (len - 1) & 63;
+                    for (int32_t i = 0; i < nb; i++) {
+                        const int32_t b = i < kLB ? L.blist[w * kLB + i] : wg_load(&wblk[(int64_t)w * maxb + i]);
+                        uint64_t kk = 0;
+                        if (lane < (b == last ? lp + 1 : 64)) {
+                            const uint64_t kv = b < SLC ? L.sk[b * 64 + lane] : wg_load(&slots[b * 64 + lane].k);
+                            const uint64_t xv = b < SLC ? L.sx[b * 64 + lane] : wg_load(&slots[b * 64 + lane].x);
+                            if ((int64_t)wg_load(&tr[(int32_t)(xv >> 42)].word) <= t) kk = key_of(kv, 1);
+                        }
+                        const uint64_t km = wave_max_u64(kk);
+                        if (km > bestk) {
+                            bestk = km;
+                            bestb = b;
+                        }
+                    }
+                    if (bestb >= 0) {
+                        bb = bestb;
+                        lsel = true;
+                    }
+                }
+                if (!lsel && nb > 1) {
                     uint64_t bk = 0;
                     int32_t bid = -1;
                     for (int32_t i0 = 0; i0 < nb; i0 += kWave) {
@@ -450,7 +525,9 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
                         rl = wg_load(&slots[el + lane].rs);
                     }
                 }
-                const uint64_t key = ok ? key_of(kw, ord) : 0;
+                bool here = true;
+                if (lsel && ok) here = (int64_t)wg_load(&tr[(int32_t)(xw >> 42)].word) <= t;
+                const uint64_t key = ok && here ? key_of(kw, ord) : 0;
                 const uint64_t km = wave_max_u64(key);
                 const int win = (int)__builtin_ctzll(ballot(key == km && ok));
                 const uint64_t vk = read_lane64(kw, win), vx = read_lane64(xw, win);
@@ -530,17 +607,21 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
                 // the out-degree
                 const int32_t deg = skey ? tr[v].ia : (int32_t)(vk >> 42);
                 const int32_t iep = tattr ? tie[v] : heft ? wg_load(&tr[v].iev) : (int32_t)((vk >> 21) & M21);
+                // a task whose inputs are still moving holds the worker until
+                // they arrive
+                int64_t s0 = t;
+                if (data) s0 = max(t, (int64_t)wg_load(&tr[v].word));
                 if (lane == 0) {
                     L.len[w] = len;
                     L.nb[w] = nb;
                     L.last[w] = newlast;
                     L.run[w] = v;
-                    L.fin[w] = t + dk;
-                    L.expend[w] = t + ek;
+                    L.fin[w] = s0 + dk;
+                    L.expend[w] = s0 + ek;
                     L.qest[w] -= ek;
                     L.rsr[w] = vr;
                     L.dgr[w] = deg;
-                    put_record(&tr[v], t, dk, w, iep, pmode);  // running, then done
+                    put_record(&tr[v], s0, dk, w, iep, pmode);  // running, then done
                 }
                 if constexpr (kPrefetch) {
                     // the running task's first successors, read now and used
@@ -1869,9 +1950,10 @@ __global__ __launch_bounds__(64) void k_sim(SimArgs A) {
         const int32_t i = read_lane(got, 0);
         if (i >= A.count) break;
         if constexpr (WPL == 1) {
-            // fixed keys (HEFT, transitive attributes) and keys wider than 32
-            // bits take the 64-bit loop
-            if (A.policy == INSP_POLICY_HEFT || A.attr_mode == INSP_ATTR_TRANSITIVE || !sim_lane(A, A.order[i], L))
+            // fixed keys (HEFT, transitive attributes), the data model, the
+            // locality policy and keys wider than 32 bits take the 64-bit loop
+            if (A.policy == INSP_POLICY_HEFT || A.policy == INSP_POLICY_LOCALITY ||
+                A.attr_mode == INSP_ATTR_TRANSITIVE || A.data_bw > 0 || !sim_lane(A, A.order[i], L))
                 sim_dag<1>(A, A.order[i], L);
         } else {
             sim_dag<WPL>(A, A.order[i], L);
@@ -1929,6 +2011,10 @@ int launch_sim(insp_dag *dag, Workspace *ws, const insp_params &p, const int32_t
     A.tia = dag->tia.as<int32_t>();
     A.tie = dag->tie.as<int32_t>();
     A.attr_mode = p.attr_mode;
+    A.data_bw = p.data_bw;
+    A.dkib = dag->dkib.as<int32_t>();
+    A.pprp = dag->pprp.as<int32_t>();
+    A.ppred = dag->ppred.as<int32_t>();
     A.counter = ws->counter.as<int32_t>();
     A.makespan = makespan;
     A.trace = trace;
@@ -2009,7 +2095,8 @@ static int check_params(const insp_params *p) {
     if (!p) return set_error(INSP_E_INVAL, "null params");
     if (p->attr_mode < 0 || p->attr_mode > INSP_ATTR_TRANSITIVE)
         return set_error(INSP_E_INVAL, "unknown attr_mode %d", p->attr_mode);
-    if (p->policy < 0 || p->policy > INSP_POLICY_HEFT) return set_error(INSP_E_INVAL, "unknown policy %d", p->policy);
+    if (p->data_bw < 0) return set_error(INSP_E_INVAL, "negative data_bw");
+    if (p->policy < 0 || p->policy > INSP_POLICY_LOCALITY) return set_error(INSP_E_INVAL, "unknown policy %d", p->policy);
     if (p->unit_time < 0 || p->max_events < 0) return set_error(INSP_E_INVAL, "negative unit_time/max_events");
     if (p->k_num > INSP_MAX_TICK || p->k_den > INSP_MAX_TICK) return set_error(INSP_E_RANGE, "k_num/k_den > 2^20");
     return INSP_OK;
@@ -2042,6 +2129,7 @@ extern "C" int insp_schedule(const insp_dag *cdag, int32_t index, const insp_wor
     if (index < 0 || index >= dag->B) return set_error(INSP_E_INVAL, "dag index %d out of range", index);
     int rc;
     if ((rc = check_params(params)) || (rc = check_workers(workers, 1))) return rc;
+    if (params->data_bw > 0 && !dag->dkib.p) return set_error(INSP_E_INVAL, "data_bw > 0 needs insp_set_task_data");
     const int64_t n = dag->toff[index + 1] - dag->toff[index];
     if (n > 0 && (!dur || !est || !worker || !start || !finish)) return set_error(INSP_E_INVAL, "null array");
     hipStream_t st = (hipStream_t)stream;
@@ -2053,6 +2141,7 @@ extern "C" int insp_schedule(const insp_dag *cdag, int32_t index, const insp_wor
     if (params->policy == INSP_POLICY_HEFT && (rc = run_rank(dag, ws, est, st))) return rc;
     if (params->attr_mode == INSP_ATTR_TRANSITIVE && (rc = run_sim_transitive(dag, ws, est, params->unit_time, st)))
         return rc;
+    if (params->data_bw > 0 && (rc = ensure_preds(dag, st))) return rc;
     return launch_sim(dag, ws, *params, dur, est, worker, start, finish, makespan, ie_at_pop, mode_at_pop, trace,
                       n_events, 1, 1, 4096, 0, st);
 }
@@ -2075,6 +2164,7 @@ extern "C" int insp_schedule_batch(const insp_dag *cdag, const insp_workers *wor
     if (!dag || !workers || !makespan) return set_error(INSP_E_INVAL, "null argument");
     int rc;
     if ((rc = check_params(params)) || (rc = check_workers(workers, dag->B))) return rc;
+    if (params->data_bw > 0 && !dag->dkib.p) return set_error(INSP_E_INVAL, "data_bw > 0 needs insp_set_task_data");
     if (dag->N > 0 && (!dur || !est || !worker || !start || !finish)) return set_error(INSP_E_INVAL, "null array");
     hipStream_t st = (hipStream_t)stream;
     INSP_HIP(hipSetDevice(dag->device));
@@ -2090,6 +2180,7 @@ extern "C" int insp_schedule_batch(const insp_dag *cdag, const insp_workers *wor
     if (params->policy == INSP_POLICY_HEFT && (rc = run_rank(dag, ws, est, st))) return rc;
     if (params->attr_mode == INSP_ATTR_TRANSITIVE && (rc = run_sim_transitive(dag, ws, est, params->unit_time, st)))
         return rc;
+    if (params->data_bw > 0 && (rc = ensure_preds(dag, st))) return rc;
     return launch_sim(dag, ws, *params, dur, est, worker, start, finish, makespan, ie_at_pop, mode_at_pop, nullptr,
                       nullptr, waves, grid, sum_cap, slot_cap, st);
 }
@@ -2113,6 +2204,8 @@ extern "C" int insp_sync_status(const insp_dag *cdag, void *stream) {
         if (stat[2 * b] & ST_DUR) return set_error(INSP_E_RANGE, "duration outside [1, 2^20] in DAG %d", b);
         if (stat[2 * b] & ST_RANK) return set_error(INSP_E_RANGE, "HEFT rank of DAG %d reaches 2^42", b);
         if (stat[2 * b] & ST_PATH) return set_error(INSP_E_RANGE, "longest path of DAG %d reaches 2^30 ticks", b);
+        if (stat[2 * b] & ST_XFER)
+            return set_error(INSP_E_RANGE, "input transfers of a task of DAG %d exceed 2^20 ticks", b);
         if (stat[2 * b] & ST_HANG)
             return set_error(INSP_E_HANG, "DAG %d needed more than max_events events", b);
     }

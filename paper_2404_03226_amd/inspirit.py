@@ -17,13 +17,14 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libinspirit.so")
 
 OK, E_INVAL, E_CYCLE, E_RANGE, E_NOMEM, E_DEVICE, E_HANG = 0, 1, 2, 3, 4, 5, 6
-POLICY = {"inspirit": 0, "fifo": 1, "ability": 2, "efi": 3, "heft": 4}
+POLICY = {"inspirit": 0, "fifo": 1, "ability": 2, "efi": 3, "heft": 4, "locality": 5}
 MODE_ABILITY, MODE_EFI, MODE_EFI_LOC, MODE_FIFO, MODE_RANK = 0, 1, 2, 3, 4
 ATTR_MODE = {"direct": 0, "transitive": 1}
 MAX_TRANSITIVE_TASKS = 1 << 15
 ALL_DAGS = -1
 
-EXPORTS = ("insp_build_dag", "insp_free_dag", "insp_dag_info", "insp_attributes", "insp_transitive_attributes",
+EXPORTS = ("insp_build_dag", "insp_set_task_data", "insp_free_dag", "insp_dag_info", "insp_attributes",
+           "insp_transitive_attributes",
            "insp_schedule",
            "insp_schedule_batch", "insp_sync_status", "insp_profile_enable", "insp_profile_read",
            "insp_mlp_create", "insp_mlp_free", "insp_mlp_grads", "insp_mlp_train_step", "insp_mlp_predict",
@@ -43,7 +44,7 @@ class Workers(C.Structure):
 
 class Params(C.Structure):
     _fields_ = [(k, C.c_int32) for k in ("policy", "unit_time", "s_inc", "s_dec", "dec_step", "c", "k_num",
-                                         "k_den", "max_events", "attr_mode")]
+                                         "k_den", "max_events", "attr_mode", "data_bw")]
 
 
 TRACE_DTYPE = np.dtype([("t", "<i8"), ("nready", "<i4"), ("mode", "<i4"), ("cnt", "<i4"), ("peak", "<i4"),
@@ -51,10 +52,10 @@ TRACE_DTYPE = np.dtype([("t", "<i8"), ("nready", "<i4"), ("mode", "<i4"), ("cnt"
 
 
 def params(policy="inspirit", unit_time=0, s_inc=-1, s_dec=-1, dec_step=-1, c=-1, k_num=-1, k_den=-1,
-           max_events=0, attr_mode="direct") -> Params:
+           max_events=0, attr_mode="direct", data_bw=0) -> Params:
     pol = POLICY[policy] if isinstance(policy, str) else int(policy)
     am = ATTR_MODE[attr_mode] if isinstance(attr_mode, str) else int(attr_mode)
-    return Params(pol, unit_time, s_inc, s_dec, dec_step, c, k_num, k_den, max_events, am)
+    return Params(pol, unit_time, s_inc, s_dec, dec_step, c, k_num, k_den, max_events, am, data_bw)
 
 
 _lib = None
@@ -70,6 +71,7 @@ def load(path: str = LIB_PATH):
     lib = C.CDLL(path)
     P, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
     lib.insp_build_dag.argtypes = [i32, P, P, P, P, P, P, C.POINTER(P)]
+    lib.insp_set_task_data.argtypes = [P, P, P]
     lib.insp_free_dag.argtypes = [P]
     lib.insp_free_dag.restype = None
     lib.insp_dag_info.argtypes = [P, i32, C.POINTER(i64), C.POINTER(i64), C.POINTER(i32)]
@@ -176,6 +178,12 @@ def attributes(dag: Dag, index, est, workers, unit_time=0, rem=None, stream=None
     _check(load().insp_attributes(dag.handle, index, _ptr(est), _workers(workers, count), unit_time, _ptr(rem),
                                   _ptr(ia), _ptr(ie), _ptr(U), _stream(stream)))
     return ia[:n], ie[:n], U
+
+
+def set_task_data(dag: Dag, data_kib, stream=None):
+    """Attach per-task output sizes (device int32 tensor, KiB, one per task of
+    the handle) for the data model; None detaches them."""
+    _check(load().insp_set_task_data(dag.handle, _ptr(data_kib), _stream(stream)))
 
 
 def transitive_attributes(dag: Dag, index, est, workers, unit_time=0, stream=None):

@@ -611,3 +611,126 @@ def test_transitive_range_errors(insp):
         insp.transitive_attributes(dag, 0, est, (1, 0))
     assert e.value.code == insp.E_RANGE
     dag.free()
+
+
+# ------------------------------------------------------------------ data model
+
+def _kib(w, seed, hi=64):
+    return synth.Stream(seed, 9).randint(np.arange(w.n), 0, hi).astype(np.int32)
+
+
+def run_gpu_data(insp, w, policy, data_bw, **kw):
+    import torch
+    dag, dur, est = insp.to_device(w)
+    insp.set_task_data(dag, torch.from_numpy(np.ascontiguousarray(w.data_kib, np.int32)).cuda())
+    o = insp.schedule(dag, 0, (w.n_cpu, w.n_gpu), dur, est, insp.params(policy=policy, data_bw=data_bw, **kw))
+    insp.sync_status(dag)
+    res = {k: o[k][:w.n].cpu().numpy() for k in ("worker", "start", "finish", "ie_at_pop", "mode_at_pop")}
+    res["makespan"] = int(o["makespan"].item())
+    dag.free()
+    return res
+
+
+def test_data_fixtures_on_gpu(insp):
+    with open(os.path.join(GOLD, "w11_data.json")) as f:
+        g = json.load(f)
+    say("data fixtures")
+    for key, pol, fx in (("w11", "locality", "locality"), ("w11", "efi", "efi"), ("w12", "fifo", "fifo")):
+        x = g[key]
+        d = np.asarray(x["dur"], np.int32)
+        w = NS(n=x["n"], row_ptr=np.asarray(x["row_ptr"], np.int32), col=np.asarray(x["col"], np.int32), dur=d,
+               est=d, n_cpu=x["n_cpu"], n_gpu=x["n_gpu"], m=len(x["col"]), type=np.zeros(x["n"], np.int32),
+               data_kib=np.asarray(x["data_kib"], np.int32), name=key)
+        r = run_gpu_data(insp, w, pol, x["data_bw"], unit_time=x.get("unit_time", 0))
+        for f in ("worker", "start", "finish"):
+            assert r[f].tolist() == x[fx][f], (key, pol, f)
+        assert r["makespan"] == x[fx]["makespan"], (key, pol)
+
+
+@pytest.mark.parametrize("policy", ["inspirit", "locality", "fifo", "efi", "heft"])
+def test_data_model_random_match_oracle(insp, policy):
+    for i in range(14):
+        n = 3 + (i * 41) % 400
+        w = synth.random_dag(81, i, n, 3.0 / max(n, 3), n_cpu=1 + i % 4, n_gpu=1 + i % 3, dur_hi=40,
+                             est_equal=(i % 2 == 0))
+        if i % 5 == 4:
+            w = _permuted(w, i)
+        w.data_kib = _kib(w, i, hi=40 + 30 * (i % 3))
+        bw = 256 * (1 + i % 4)
+        kw = dict(attr_mode="transitive") if i % 7 == 3 else {}
+        say("data random", policy, i, n, bw, kw)
+        g = run_gpu_data(insp, w, policy, bw, **kw)
+        r = oracle.schedule(w, policy=policy, variant=oracle.HEAP, data_bw=bw, **kw)
+        assert_same(g, r, f"data {policy} {i}")
+        check_schedule(w, g["worker"], g["start"], g["finish"], g["makespan"], non_idling=False)
+
+
+def test_data_model_cholesky_and_many_workers(insp):
+    w = synth.cfg2()
+    w.data_kib = np.full(w.n, 3600, np.int32)  # a 960 x 960 fp32 tile
+    for pol in ("inspirit", "locality"):
+        say("data cholesky", pol)
+        g = run_gpu_data(insp, w, pol, 1 << 20)
+        assert_same(g, oracle.schedule(w, policy=pol, variant=oracle.HEAP, data_bw=1 << 20), f"cholesky {pol}")
+    for n_cpu, n_gpu in ((70, 30), (200, 100)):
+        w = synth.random_dag(82, n_cpu, 1500, 0.004, n_cpu=n_cpu, n_gpu=n_gpu, dur_hi=60, est_equal=False)
+        w.data_kib = _kib(w, n_cpu, hi=100)
+        for pol in ("inspirit", "locality"):
+            say("data workers", n_cpu, n_gpu, pol)
+            g = run_gpu_data(insp, w, pol, 512)
+            assert_same(g, oracle.schedule(w, policy=pol, variant=oracle.HEAP, data_bw=512), f"workers {pol}")
+
+
+def test_data_model_batch(insp):
+    import torch
+    ws = synth.cfg3(select=list(range(11, 4096, 500))) + [_hubs(8)]
+    b = synth.concat(ws)
+    b.data_kib = np.concatenate([_kib(w, k, hi=80) for k, w in enumerate(ws)])
+    say("data batch", len(ws))
+    dag, dur, est = insp.batch_to_device(b)
+    insp.set_task_data(dag, torch.from_numpy(b.data_kib).cuda())
+    for pol in ("inspirit", "locality"):
+        r = oracle.schedule_batch(b, policy=pol, data_bw=700)
+        for key in (None, "waves=1,grid=3,lds_blocks=0,lds_slots=0"):
+            o = insp.schedule_batch(dag, [(w.n_cpu, w.n_gpu) for w in ws], dur, est,
+                                    insp.params(policy=pol, data_bw=700), tune_key=key)
+            insp.sync_status(dag)
+            for k in ("worker", "start", "finish", "ie_at_pop", "mode_at_pop"):
+                assert np.array_equal(o[k].cpu().numpy(), r[k]), (pol, key, k)
+    # without the data model the same handle schedules as before
+    o = insp.schedule_batch(dag, [(w.n_cpu, w.n_gpu) for w in ws], dur, est)
+    insp.sync_status(dag)
+    assert np.array_equal(o["start"].cpu().numpy(), oracle.schedule_batch(b)["start"])
+    dag.free()
+
+
+def test_data_model_errors(insp):
+    import torch
+    say("data errors")
+    w = synth.random_dag(83, 0, 20, 0.3, n_cpu=1, n_gpu=1)
+    dag, dur, est = insp.to_device(w)
+    with pytest.raises(insp.InspError) as e:
+        insp.schedule(dag, 0, (1, 1), dur, est, insp.params(data_bw=100))
+    assert e.value.code == insp.E_INVAL  # no sizes attached
+    bad = torch.zeros(w.n, dtype=torch.int32, device="cuda")
+    bad[3] = -1
+    with pytest.raises(insp.InspError) as e:
+        insp.set_task_data(dag, bad)
+    assert e.value.code == insp.E_RANGE
+    dag.free()
+    # three inputs, one on each memory node (the CPU's, then each GPU's): any
+    # worker moves two of them, 2 (2^19 + 1) ticks > 2^20
+    d = np.array([[1, 100], [100, 1], [100, 1], [1, 1]], np.int32)
+    w = NS(n=4, row_ptr=np.array([0, 1, 2, 3, 3], np.int32), col=np.array([3, 3, 3], np.int32), dur=d, est=d,
+           n_cpu=1, n_gpu=2, m=3, type=np.zeros(4, np.int32), data_kib=np.array([(1 << 19) + 1] * 3 + [0], np.int32))
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.schedule(w, data_bw=1024, policy="fifo")
+    assert e.value.code == oracle.E_RANGE
+    dag, dur, est = insp.to_device(w)
+    insp.set_task_data(dag, torch.from_numpy(w.data_kib).cuda())
+    insp.schedule(dag, 0, (1, 2), dur, est, insp.params(policy="fifo", data_bw=1024))
+    with pytest.raises(insp.InspError) as e:
+        insp.sync_status(dag)
+    assert e.value.code == insp.E_RANGE
+    insp.set_task_data(dag, None)
+    dag.free()
