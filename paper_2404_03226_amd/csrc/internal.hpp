@@ -131,6 +131,7 @@ struct insp_dag {
     insp::DevBuf plev;                 // int32 [N]: level of each position
     insp::DevBuf pcol;                 // int32 [M]: position of each edge's target
     insp::DevBuf ptau;                 // int32 [N]: tau by position
+    insp::DevBuf pedge;                // int2 [M]: each edge's target position and its tau
     insp::DevBuf tcum;                 // int32 [N * kTRungs]: members within 2^j
     insp::DevBuf tia, tie;             // int32 [N]: transitive IA, IE of the last schedule call
     // data model: output KiB per task (insp_set_task_data), predecessor lists

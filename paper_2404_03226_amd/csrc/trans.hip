@@ -28,9 +28,10 @@
 
 namespace insp {
 
-constexpr int kTT = 256;                 // threads per work-group
+constexpr int kTT = 512;                 // threads per work-group
 constexpr int kTW = kTT / kWave;
 constexpr uint32_t kPathCap = 1u << 30;  // paths saturate here (out of range)
+constexpr int kChunk = 4;                // sources taken per counter fetch
 
 struct TransArgs {
     const DagDesc *desc;
@@ -38,6 +39,7 @@ struct TransArgs {
     int64_t base, items;
     const int32_t *topo, *lvl, *nlev, *plev, *pcol;
     int32_t *ptau;
+    int2 *pedge;              // per edge: target position and its tau (this call's estimates)
     const int2 *prow;
     int32_t maxn;             // largest DAG of the launch (LDS entries)
     int32_t clear_status;
@@ -125,6 +127,21 @@ __global__ __launch_bounds__(256) void k_position_tau(TransArgs A) {
     A.ptau[D.toff + i] = min(max(D.n_gpu > 0 ? e.y : e.x, 1), INSP_MAX_TICK);
 }
 
+// Target position and tau of every edge of the launch's DAGs, packed so that
+// the pass reads one 8-byte word per edge.
+__global__ __launch_bounds__(256) void k_edge_tau(TransArgs A, int64_t e0, int64_t e1) {
+    const int64_t e = e0 + (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= e1) return;
+    int32_t lo = 0, hi = A.count - 1;  // last DAG whose edges start at or before e
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (A.desc[mid].eoff <= e) lo = mid;
+        else hi = mid - 1;
+    }
+    const int32_t s = A.pcol[e];
+    A.pedge[e] = make_int2(s, A.ptau[A.desc[lo].toff + s]);
+}
+
 __global__ void k_trans_clear(TransArgs A) {
     const int32_t d = blockIdx.x * 256 + threadIdx.x;
     if (d < A.count) {
@@ -158,20 +175,34 @@ __global__ __launch_bounds__(kTT) void k_trans(TransArgs A) {
     const bool automatic = A.unit_time == 0;
     const uint32_t ut = (uint32_t)A.unit_time;
     for (int32_t p = tid; p < A.maxn; p += kTT) EF[p] = 0;
+    // sources come kChunk at a time; the DAG of the previous source is kept
+    // (consecutive sources mostly share it), so the descriptor search runs
+    // once per DAG change
+    int64_t item = 0, chunk_end = 0;
+    int32_t d = -1;
+    DagDesc D;
+    D.toff = 0;
+    D.n = 0;
     for (;;) {
-        if (tid == 0) s_item = dev_fetch_add(A.counter, 1);
+        if (item >= chunk_end) {
+            if (tid == 0) s_item = dev_fetch_add(A.counter, kChunk);
+            __syncthreads();
+            item = s_item;
+            chunk_end = item + kChunk;
+        }
         if (tid < kTRungs) s_hist[tid] = 0;
         __syncthreads();
-        const int64_t item = s_item;
         if (item >= A.items) break;
-        const int32_t d = desc_of(A.desc, A.count, A.base, item);
-        const DagDesc D = A.desc[d];
+        if (d < 0 || item < D.toff - A.base || item >= D.toff - A.base + D.n) {
+            d = desc_of(A.desc, A.count, A.base, item);
+            D = A.desc[d];
+        }
         const int64_t u0 = D.toff - A.base, t0 = D.toff;
         const int32_t i = (int32_t)(item - u0);
         const int32_t *ls = A.lvl + t0 + D.id;
         const int32_t nl = A.nlev[D.id];
         const int32_t L0 = A.plev[t0 + i];
-        const int32_t *pcol = A.pcol + D.eoff;
+        const int2 *pedge = A.pedge + D.eoff;
         const int32_t *ptau = A.ptau + t0;
         const int2 *prow = A.prow + t0;
         if (tid == 0) {
@@ -189,6 +220,7 @@ __global__ __launch_bounds__(kTT) void k_trans(TransArgs A) {
             for (int32_t p = a + tid; p < z; p += kTT) {
                 const uint32_t ef = EF[p];
                 if (ef == 0) continue;  // not reachable from the source
+                const int2 row = prow[p];
                 EF[p] = 0;
                 members++;
                 mx = max(mx, ef);
@@ -198,12 +230,11 @@ __global__ __launch_bounds__(kTT) void k_trans(TransArgs A) {
                 } else {
                     within += ef <= ut ? 1u : 0u;
                 }
-                const int2 row = prow[p];
                 for (int32_t e = row.x; e < row.y; e++) {
-                    const int32_t s = pcol[e];
-                    const uint32_t f = min(ef + (uint32_t)ptau[s], kPathCap);
-                    atomicMax(&EF[s], f);
-                    myhi = max(myhi, s);
+                    const int2 st = pedge[e];
+                    const uint32_t f = min(ef + (uint32_t)st.y, kPathCap);
+                    atomicMax(&EF[st.x], f);
+                    myhi = max(myhi, st.x);
                 }
             }
             for (int o = 32; o > 0; o >>= 1) myhi = max(myhi, __shfl_xor(myhi, o));
@@ -225,6 +256,7 @@ __global__ __launch_bounds__(kTT) void k_trans(TransArgs A) {
             A.cum[(u0 + v) * kTRungs + tid] = c;
         }
         __syncthreads();
+        item++;
     }
 }
 
@@ -313,6 +345,7 @@ int run_transitive(insp_dag *dag, Workspace *ws, const int32_t *est, int32_t uni
     if ((rc = ensure_positions(dag, st))) return rc;
     const int64_t N = std::max<int64_t>(dag->N, 1);
     if (!dag->ptau.p && (rc = dag->ptau.alloc(sizeof(int32_t) * N))) return rc;
+    if (!dag->pedge.p && (rc = dag->pedge.alloc(sizeof(int2) * std::max<int64_t>(dag->M, 1)))) return rc;
     if (unit_time == 0 && dag->tcum.bytes < sizeof(int32_t) * kTRungs * (size_t)std::max<int64_t>(ws->tasks, 1) &&
         (rc = dag->tcum.alloc(sizeof(int32_t) * kTRungs * (size_t)std::max<int64_t>(ws->tasks, 1))))
         return rc;
@@ -333,6 +366,7 @@ int run_transitive(insp_dag *dag, Workspace *ws, const int32_t *est, int32_t uni
     A.plev = dag->plev.as<int32_t>();
     A.pcol = dag->pcol.as<int32_t>();
     A.ptau = dag->ptau.as<int32_t>();
+    A.pedge = dag->pedge.as<int2>();
     A.prow = dag->prow.as<int2>();
     A.est = est;
     A.maxn = maxn;
@@ -347,6 +381,9 @@ int run_transitive(insp_dag *dag, Workspace *ws, const int32_t *est, int32_t uni
     hipLaunchKernelGGL(k_trans_clear, dim3((unsigned)((ws->count + 255) / 256)), dim3(256), 0, st, A);
     if (ws->tasks > 0) {
         hipLaunchKernelGGL(k_position_tau, dim3((unsigned)((ws->tasks + 255) / 256)), dim3(256), 0, st, A);
+        const int64_t e0 = dag->eoff[ws->first], e1 = dag->eoff[ws->first + ws->count];
+        if (e1 > e0)
+            hipLaunchKernelGGL(k_edge_tau, dim3((unsigned)((e1 - e0 + 255) / 256)), dim3(256), 0, st, A, e0, e1);
         const size_t lds = sizeof(uint32_t) * (size_t)std::max(maxn, 1);
         int dev = 0, cus = 256;
         if (hipGetDevice(&dev) == hipSuccess) {
