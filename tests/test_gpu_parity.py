@@ -734,3 +734,72 @@ def test_data_model_errors(insp):
     assert e.value.code == insp.E_RANGE
     insp.set_task_data(dag, None)
     dag.free()
+
+
+# ------------------------------------------------------------------ edge cases
+
+def _empty(n_cpu=2, n_gpu=1):
+    return NS(n=0, row_ptr=np.zeros(1, np.int32), col=np.zeros(0, np.int32), dur=np.zeros((0, 2), np.int32),
+              est=np.zeros((0, 2), np.int32), n_cpu=n_cpu, n_gpu=n_gpu, m=0, type=np.zeros(0, np.int32),
+              name="empty")
+
+
+def _single(tick, n_cpu=1, n_gpu=1):
+    d = np.array([[tick, tick + 1]], np.int32)
+    return NS(n=1, row_ptr=np.zeros(2, np.int32), col=np.zeros(0, np.int32), dur=d, est=d, n_cpu=n_cpu,
+              n_gpu=n_gpu, m=0, type=np.zeros(1, np.int32), name="single")
+
+
+def test_batch_with_empty_and_single_task_dags(insp):
+    import torch
+    ws = [_empty(), _single(5)] + synth.cfg3(select=[9, 90]) + [_empty(1, 0), _single(3, 2, 0),
+                                                               synth.lu_workload(nb=5), _empty()]
+    b = synth.concat(ws)
+    b.data_kib = np.concatenate([np.full(w.n, 7 + k, np.int32) for k, w in enumerate(ws)])
+    workers = [(w.n_cpu, w.n_gpu) for w in ws]
+    dag, dur, est = insp.batch_to_device(b)
+    insp.set_task_data(dag, torch.from_numpy(b.data_kib).cuda())
+    for pol, kw in (("inspirit", {}), ("fifo", {}), ("heft", {}), ("inspirit", {"attr_mode": "transitive"}),
+                    ("locality", {"data_bw": 300}), ("inspirit", {"data_bw": 300})):
+        say("edge batch", pol, kw)
+        o = insp.schedule_batch(dag, workers, dur, est, insp.params(policy=pol, **kw))
+        insp.sync_status(dag)
+        r = oracle.schedule_batch(b, policy=pol, **kw)
+        for k in ("worker", "start", "finish", "ie_at_pop", "mode_at_pop"):
+            assert np.array_equal(o[k].cpu().numpy(), r[k]), (pol, kw, k)
+        ms = o["makespan"].cpu().numpy()
+        assert np.array_equal(ms, r["makespan"]) and ms[0] == 0 and ms[-1] == 0, (pol, kw)
+    ia, ie, U, lp = insp.transitive_attributes(dag, insp.ALL_DAGS, est, workers)
+    ia, ie = ia.cpu().numpy(), ie.cpu().numpy()
+    for k, w in enumerate(ws):
+        a, z = int(b.task_off[k]), int(b.task_off[k + 1])
+        if w.n == 0:
+            assert U[k] == 1 and lp[k] == 0, k
+            continue
+        rp, col = oracle.canon(w.n, w.row_ptr, w.col)
+        ria, rie, rU, rcp = oracle.transitive(w.n, rp, col, w.est, w.n_gpu)
+        assert np.array_equal(ia[a:z], ria) and np.array_equal(ie[a:z], rie) and U[k] == rU and lp[k] == rcp, k
+    ia, ie, U = insp.attributes(dag, insp.ALL_DAGS, est, workers)
+    ia, ie = ia.cpu().numpy(), ie.cpu().numpy()
+    for k, w in enumerate(ws):
+        a, z = int(b.task_off[k]), int(b.task_off[k + 1])
+        rp, col = oracle.canon(w.n, w.row_ptr, w.col)
+        ria, rie, rU = oracle.attributes(w.n, rp, col, w.est, w.n_gpu)
+        assert np.array_equal(ia[a:z], ria) and np.array_equal(ie[a:z], rie) and U[k] == rU, k
+    dag.free()
+
+
+def test_single_empty_dag(insp):
+    import torch
+    say("single empty dag")
+    w = _empty()
+    dag = insp.build_dag([0, 0], [0, 0], torch.zeros(1, dtype=torch.int32, device="cuda"),
+                         torch.zeros(1, dtype=torch.int32, device="cuda"))
+    d = torch.zeros((1, 2), dtype=torch.int32, device="cuda")
+    for pol, kw in (("inspirit", {}), ("heft", {}), ("inspirit", {"attr_mode": "transitive"})):
+        o = insp.schedule(dag, 0, (w.n_cpu, w.n_gpu), d, d, insp.params(policy=pol, **kw))
+        insp.sync_status(dag)
+        assert int(o["makespan"].item()) == 0
+    ia, ie, U, lp = insp.transitive_attributes(dag, 0, d, (2, 1))
+    assert U[0] == 1 and lp[0] == 0
+    dag.free()
