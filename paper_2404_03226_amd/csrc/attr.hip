@@ -305,6 +305,7 @@ int get_workspace(insp_dag *dag, int32_t first, int32_t count, const insp_worker
     if ((rc = w->desc.alloc(sizeof(DagDesc) * count)) || (rc = w->blkmap.alloc(sizeof(int2) * blk.size())) ||
         (rc = w->order.alloc(sizeof(int32_t) * count)) || (rc = w->slots.alloc(sizeof(Slot) * 64 * (size_t)boff)) ||
         (rc = w->sums.alloc(16 * (size_t)boff)) || (rc = w->paux.alloc(4 * (size_t)(wloff + boff))) ||
+        (rc = w->barr.alloc(8 * (size_t)boff)) ||
         (rc = w->counter.alloc(16)))
         return rc;
     INSP_HIP(hipMemcpy(w->desc.p, desc.data(), sizeof(DagDesc) * count, hipMemcpyHostToDevice));

@@ -93,6 +93,7 @@ struct Workspace {
     DevBuf slots;                 // Slot [64 per block]: queue entries
     DevBuf sums;                  // uint64 x2 per block: max key under each rule
     DevBuf paux;                  // int32: per-worker block lists, then free-block stacks
+    DevBuf barr;                  // int64 per block: latest input arrival (data model)
     DevBuf counter;               // int32 [4]: DAG dispenser
     DevBuf tlong, tu;             // transitive attributes: longest path per DAG (+ a counter), chosen U
     std::vector<int32_t> h_order;

@@ -103,6 +103,7 @@ struct SimArgs {
     int32_t data_bw;           // data model: bytes per tick between memory nodes (0 = off)
     const int32_t *dkib;       // data model: output KiB per task (global task index)
     const int32_t *pprp, *ppred;  // predecessor lists (local row pointers as rp, ids as col)
+    long long *barr;           // data model: per queue block, the latest input arrival pushed into it
     int32_t *stat;
     int32_t *counter;
     int64_t *makespan;
@@ -184,6 +185,7 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
     // workers, one per GPU worker); see the push and the pop below
     const bool data = A.data_bw > 0;
     const int32_t *dkib = A.dkib + d.toff, *prp = A.pprp + d.toff + d.id, *pred = A.ppred + d.eoff;
+    long long *barr = A.barr + d.blk_off;
     const int slot0 = A.policy == INSP_POLICY_FIFO ? 2 : heft ? 3 : 0;
     const int32_t max_events = A.max_events > 0 ? A.max_events : n + 1;
 
@@ -381,7 +383,11 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
                     tr[v].seq = seq;
                     // the dependency word is dead once a task is queued: it
                     // holds the time its inputs arrive (transfers start now)
-                    if (data) tr[v].word = (unsigned long long)(t + xs);
+                    if (data) {
+                        tr[v].word = (unsigned long long)(t + xs);
+                        // never lowered by pops: an upper bound for the block
+                        barr[blk] = pos == 0 ? t + xs : max(barr[blk], (long long)(t + xs));
+                    }
                     const uint64_t a0 = key_of(kw, slot0), a1 = key_of(kw, 1);
                     if (blk < SC) {
                         if (pos == 0) {
@@ -455,22 +461,43 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
                 int32_t bb = last;
                 bool lsel = false;
                 if (loc) {
-                    // the arrival times are not in the keys: scan every entry
+                    // the arrival times are not in the keys.  A block whose
+                    // latest input arrival has passed holds only tasks whose
+                    // inputs are in place, so its efficiency maximum stands;
+                    // the other blocks are scanned entry by entry
                     uint64_t bestk = 0;
                     int32_t bestb = -1;
                     const int32_t lp = (len - 1) & 63;
-                    for (int32_t i = 0; i < nb; i++) {
-                        const int32_t b = i < kLB ? L.blist[w * kLB + i] : wg_load(&wblk[(int64_t)w * maxb + i]);
+                    for (int32_t i0 = 0; i0 < nb; i0 += kWave) {
+                        const int32_t i = i0 + lane;
                         uint64_t kk = 0;
-                        if (lane < (b == last ? lp + 1 : 64)) {
-                            const uint64_t kv = b < SLC ? L.sk[b * 64 + lane] : wg_load(&slots[b * 64 + lane].k);
-                            const uint64_t xv = b < SLC ? L.sx[b * 64 + lane] : wg_load(&slots[b * 64 + lane].x);
-                            if ((int64_t)wg_load(&tr[(int32_t)(xv >> 42)].word) <= t) kk = key_of(kv, 1);
+                        int32_t b = -1;
+                        bool mix = false;
+                        if (i < nb) {
+                            b = i < kLB ? L.blist[w * kLB + i] : wg_load(&wblk[(int64_t)w * maxb + i]);
+                            if ((int64_t)wg_load(&barr[b]) <= t) kk = b < SC ? L.sum[2 * b + 1] : wg_load(&sums[2 * b + 1]);
+                            else mix = true;
                         }
                         const uint64_t km = wave_max_u64(kk);
                         if (km > bestk) {
                             bestk = km;
-                            bestb = b;
+                            bestb = read_lane(b, (int)__builtin_ctzll(ballot(kk == km && i < nb)));
+                        }
+                        uint64_t mm = ballot(mix);
+                        while (mm) {
+                            const int32_t bm = read_lane(b, (int)__builtin_ctzll(mm));
+                            mm &= mm - 1;
+                            uint64_t ke = 0;
+                            if (lane < (bm == last ? lp + 1 : 64)) {
+                                const uint64_t kv = bm < SLC ? L.sk[bm * 64 + lane] : wg_load(&slots[bm * 64 + lane].k);
+                                const uint64_t xv = bm < SLC ? L.sx[bm * 64 + lane] : wg_load(&slots[bm * 64 + lane].x);
+                                if ((int64_t)wg_load(&tr[(int32_t)(xv >> 42)].word) <= t) ke = key_of(kv, 1);
+                            }
+                            const uint64_t kme = wave_max_u64(ke);
+                            if (kme > bestk) {
+                                bestk = kme;
+                                bestb = bm;
+                            }
                         }
                     }
                     if (bestb >= 0) {
@@ -559,6 +586,8 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
                             slots[p].rs = mr;
                         }
                         tr[(int32_t)(mx >> 42)].qpos = p;
+                        // the moved entry keeps block bb's arrival bound valid
+                        if (data && last != bb) barr[bb] = max(barr[bb], barr[last]);
                     }
                 }
                 len--;
@@ -2015,6 +2044,7 @@ int launch_sim(insp_dag *dag, Workspace *ws, const insp_params &p, const int32_t
     A.dkib = dag->dkib.as<int32_t>();
     A.pprp = dag->pprp.as<int32_t>();
     A.ppred = dag->ppred.as<int32_t>();
+    A.barr = ws->barr.as<long long>();
     A.counter = ws->counter.as<int32_t>();
     A.makespan = makespan;
     A.trace = trace;

@@ -803,3 +803,28 @@ def test_single_empty_dag(insp):
     ia, ie, U, lp = insp.transitive_attributes(dag, 0, d, (2, 1))
     assert U[0] == 1 and lp[0] == 0
     dag.free()
+
+
+def test_data_model_long_queues(insp):
+    # layered DAGs of thousands of tasks moving 960 x 960 fp32 tiles: queues
+    # span several blocks and pops move entries between blocks, which must
+    # carry their inputs' arrival bounds along
+    ws = synth.cfg3(select=[0, 2])
+    b = synth.concat(ws)
+    b.data_kib = np.full(int(b.task_off[-1]), 3600, np.int32)
+    say("data long queues", [w.n for w in ws])
+    dag, dur, est = insp.batch_to_device(b)
+    insp.set_task_data(dag, torch_tensor(b.data_kib))
+    for pol in ("locality", "inspirit"):
+        o = insp.schedule_batch(dag, [(w.n_cpu, w.n_gpu) for w in ws], dur, est,
+                                insp.params(policy=pol, data_bw=61440))
+        insp.sync_status(dag)
+        r = oracle.schedule_batch(b, policy=pol, data_bw=61440)
+        for k in ("worker", "start", "finish", "ie_at_pop", "mode_at_pop"):
+            assert np.array_equal(o[k].cpu().numpy(), r[k]), (pol, k)
+    dag.free()
+
+
+def torch_tensor(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
