@@ -828,3 +828,49 @@ def test_data_model_long_queues(insp):
 def torch_tensor(a):
     import torch
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+# --------------------------------------------------------- full-size workloads
+
+def test_full_batch_4096(insp):
+    # the 4096-DAG batch at full size: every schedule (default and tuned
+    # launch shapes) and the full attribute pass of every DAG
+    ws = synth.cfg3()
+    b = synth.concat(ws)
+    say("full batch", len(ws), int(b.task_off[-1]))
+    dag, dur, est = insp.batch_to_device(b)
+    workers = [(w.n_cpu, w.n_gpu) for w in ws]
+    r = oracle.schedule_batch(b, threads=16)
+    for key in (None, "waves=1,grid=2048,lds_blocks=256,lds_slots=24"):
+        o = insp.schedule_batch(dag, workers, dur, est, tune_key=key)
+        insp.sync_status(dag)
+        for k in ("worker", "start", "finish", "ie_at_pop", "mode_at_pop"):
+            assert np.array_equal(o[k].cpu().numpy(), r[k]), (key, k)
+        assert np.array_equal(o["makespan"].cpu().numpy(), r["makespan"]), key
+    ia, ie, U = insp.attributes(dag, insp.ALL_DAGS, est, workers)
+    ia, ie = ia.cpu().numpy(), ie.cpu().numpy()
+    for k, w in enumerate(ws):
+        a, z = int(b.task_off[k]), int(b.task_off[k + 1])
+        rp, col = oracle.canon(w.n, w.row_ptr, w.col)
+        ria, rie, rU = oracle.attributes(w.n, rp, col, w.est, w.n_gpu)
+        assert np.array_equal(ia[a:z], ria) and np.array_equal(ie[a:z], rie) and U[k] == rU, k
+    dag.free()
+
+
+def test_full_powerlaw_2m(insp):
+    # the single 2M-task power-law DAG (72 workers: the 64-bit loop): the full
+    # schedule and the full attribute recompute
+    w = synth.cfg4()
+    say("powerlaw 2M", w.n, w.m)
+    dag, dur, est = insp.to_device(w)
+    o = insp.schedule(dag, 0, (w.n_cpu, w.n_gpu), dur, est, insp.params())
+    insp.sync_status(dag)
+    r = oracle.schedule(w, variant=oracle.HEAP)
+    for k in ("worker", "start", "finish", "ie_at_pop", "mode_at_pop"):
+        assert np.array_equal(o[k][:w.n].cpu().numpy(), r[k]), k
+    assert int(o["makespan"].item()) == r["makespan"]
+    rp, col = oracle.canon(w.n, w.row_ptr, w.col)
+    ia, ie, U = insp.attributes(dag, 0, est, (w.n_cpu, w.n_gpu))
+    ria, rie, rU = oracle.attributes(w.n, rp, col, w.est, w.n_gpu)
+    assert np.array_equal(ia.cpu().numpy(), ria) and np.array_equal(ie.cpu().numpy(), rie) and U[0] == rU
+    dag.free()
