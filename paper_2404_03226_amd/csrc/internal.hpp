@@ -139,6 +139,7 @@ struct insp_dag {
     insp::DevBuf dkib;                 // int32 [N]
     insp::DevBuf pprp;                 // int32 [N + B]: local predecessor row pointers (as rp)
     insp::DevBuf ppred;                // int32 [M]: predecessor ids (local)
+    insp::DevBuf dxc;                  // int32 [N]: transfer ticks of each output (per run)
     std::map<std::string, std::unique_ptr<insp::Workspace>> ws;
 };
 

@@ -104,6 +104,7 @@ struct SimArgs {
     const int32_t *dkib;       // data model: output KiB per task (global task index)
     const int32_t *pprp, *ppred;  // predecessor lists (local row pointers as rp, ids as col)
     long long *barr;           // data model: per queue block, the latest input arrival pushed into it
+    int32_t *dxc;              // data model: transfer ticks of each task's output (global task index)
     int32_t *stat;
     int32_t *counter;
     int64_t *makespan;
@@ -186,6 +187,9 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
     const bool data = A.data_bw > 0;
     const int32_t *dkib = A.dkib + d.toff, *prp = A.pprp + d.toff + d.id, *pred = A.ppred + d.eoff;
     long long *barr = A.barr + d.blk_off;
+    int32_t *dxc = A.dxc + d.toff;
+    // block arrival bounds matter only where the locality rule can be used
+    const bool lrule = data && (A.policy == INSP_POLICY_INSPIRIT || A.policy == INSP_POLICY_LOCALITY);
     const int slot0 = A.policy == INSP_POLICY_FIFO ? 2 : heft ? 3 : 0;
     const int32_t max_events = A.max_events > 0 ? A.max_events : n + 1;
 
@@ -202,6 +206,9 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
     }
     for (int32_t i = lane; i < d.nblk; i += kWave) freeb[i] = d.nblk - 1 - i;
     int32_t nfree = d.nblk;
+    if (data)  // each output's transfer ticks, once per run (no division at the pushes)
+        for (int32_t i = lane; i < n; i += kWave)
+            dxc[i] = (int32_t)(((int64_t)1024 * dkib[i] + A.data_bw - 1) / A.data_bw);
 
     // initial frontier: tasks without predecessors, ascending
     int32_t r = 0;
@@ -306,7 +313,7 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
                             const int32_t u = pred[c0 + lane];
                             const int32_t wu = -2 - tr[u].qpos;  // worker of a finished task
                             nu = wu < ncpu ? 0 : 1 + wu - ncpu;
-                            cu = ((int64_t)1024 * dkib[u] + A.data_bw - 1) / A.data_bw;
+                            cu = dxc[u];
                         }
                         const int32_t cnt = min(kWave, pz - c0);
                         for (int32_t jj = 0; jj < cnt; jj++) {
@@ -383,11 +390,9 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
                     tr[v].seq = seq;
                     // the dependency word is dead once a task is queued: it
                     // holds the time its inputs arrive (transfers start now)
-                    if (data) {
-                        tr[v].word = (unsigned long long)(t + xs);
-                        // never lowered by pops: an upper bound for the block
-                        barr[blk] = pos == 0 ? t + xs : max(barr[blk], (long long)(t + xs));
-                    }
+                    if (data) tr[v].word = (unsigned long long)(t + xs);
+                    // never lowered by pops: an upper bound for the block
+                    if (lrule) barr[blk] = pos == 0 ? t + xs : max(barr[blk], (long long)(t + xs));
                     const uint64_t a0 = key_of(kw, slot0), a1 = key_of(kw, 1);
                     if (blk < SC) {
                         if (pos == 0) {
@@ -587,7 +592,7 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
                         }
                         tr[(int32_t)(mx >> 42)].qpos = p;
                         // the moved entry keeps block bb's arrival bound valid
-                        if (data && last != bb) barr[bb] = max(barr[bb], barr[last]);
+                        if (lrule && last != bb) barr[bb] = max(barr[bb], barr[last]);
                     }
                 }
                 len--;
@@ -2045,6 +2050,7 @@ int launch_sim(insp_dag *dag, Workspace *ws, const insp_params &p, const int32_t
     A.pprp = dag->pprp.as<int32_t>();
     A.ppred = dag->ppred.as<int32_t>();
     A.barr = ws->barr.as<long long>();
+    A.dxc = dag->dxc.as<int32_t>();
     A.counter = ws->counter.as<int32_t>();
     A.makespan = makespan;
     A.trace = trace;
@@ -2172,6 +2178,8 @@ extern "C" int insp_schedule(const insp_dag *cdag, int32_t index, const insp_wor
     if (params->attr_mode == INSP_ATTR_TRANSITIVE && (rc = run_sim_transitive(dag, ws, est, params->unit_time, st)))
         return rc;
     if (params->data_bw > 0 && (rc = ensure_preds(dag, st))) return rc;
+    if (params->data_bw > 0 && !dag->dxc.p && (rc = dag->dxc.alloc(sizeof(int32_t) * std::max<int64_t>(dag->N, 1))))
+        return rc;
     return launch_sim(dag, ws, *params, dur, est, worker, start, finish, makespan, ie_at_pop, mode_at_pop, trace,
                       n_events, 1, 1, 4096, 0, st);
 }
@@ -2211,6 +2219,8 @@ extern "C" int insp_schedule_batch(const insp_dag *cdag, const insp_workers *wor
     if (params->attr_mode == INSP_ATTR_TRANSITIVE && (rc = run_sim_transitive(dag, ws, est, params->unit_time, st)))
         return rc;
     if (params->data_bw > 0 && (rc = ensure_preds(dag, st))) return rc;
+    if (params->data_bw > 0 && !dag->dxc.p && (rc = dag->dxc.alloc(sizeof(int32_t) * std::max<int64_t>(dag->N, 1))))
+        return rc;
     return launch_sim(dag, ws, *params, dur, est, worker, start, finish, makespan, ie_at_pop, mode_at_pop, nullptr,
                       nullptr, waves, grid, sum_cap, slot_cap, st);
 }
