@@ -7,7 +7,9 @@
 
 #include <algorithm>
 #include <cstring>
+#include <map>
 #include <memory>
+#include <mutex>
 #include <numeric>
 
 #include "common.hpp"
@@ -25,6 +27,20 @@ int set_error(int code, const char *fmt, ...) {
     va_end(ap);
     g_last_error = buf;
     return code;
+}
+
+int set_lds_limit(const void *kernel, size_t bytes) {
+    if (bytes <= 65536) return INSP_OK;
+    static std::mutex mu;
+    static std::map<std::pair<const void *, int>, size_t> done;
+    int dev = 0;
+    INSP_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(mu);
+    size_t &cur = done[{kernel, dev}];
+    if (bytes <= cur) return INSP_OK;
+    INSP_HIP(hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+    cur = bytes;
+    return INSP_OK;
 }
 
 int DevBuf::alloc(size_t nbytes) {

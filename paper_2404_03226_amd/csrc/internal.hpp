@@ -156,6 +156,11 @@ constexpr int kAttrThreads = 256;
 
 int ensure_state(insp_dag *dag, hipStream_t st);
 
+// Raise a kernel's dynamic LDS limit to at least `bytes` on the current
+// device, once: later launches of the same size make no attribute call (so a
+// warmed-up call can be captured in a graph).
+int set_lds_limit(const void *kernel, size_t bytes);
+
 // Kernel timing hook: brackets a launch with events when profiling is on.
 void prof_mark(hipStream_t st, const char *kernel, bool begin);
 struct ProfScope {

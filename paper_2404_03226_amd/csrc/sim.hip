@@ -2091,13 +2091,13 @@ int launch_sim(insp_dag *dag, Workspace *ws, const insp_params &p, const int32_t
     {
         ProfScope ps(st, "sim");
         if (ws->max_w <= 64) {
-            if (lds > 65536) INSP_HIP(hipFuncSetAttribute((const void *)&k_sim<1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+            if (int rc = set_lds_limit((const void *)&k_sim<1>, lds)) return rc;
             hipLaunchKernelGGL(k_sim<1>, dim3(grid), dim3(64), lds, st, A);
         } else if (ws->max_w <= 128) {
-            if (lds > 65536) INSP_HIP(hipFuncSetAttribute((const void *)&k_sim<2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+            if (int rc = set_lds_limit((const void *)&k_sim<2>, lds)) return rc;
             hipLaunchKernelGGL(k_sim<2>, dim3(grid), dim3(64), lds, st, A);
         } else {
-            if (lds > 65536) INSP_HIP(hipFuncSetAttribute((const void *)&k_sim<16>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+            if (int rc = set_lds_limit((const void *)&k_sim<16>, lds)) return rc;
             hipLaunchKernelGGL(k_sim<16>, dim3(grid), dim3(64), lds, st, A);
         }
     }

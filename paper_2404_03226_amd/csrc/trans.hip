@@ -392,8 +392,7 @@ int run_transitive(insp_dag *dag, Workspace *ws, const int32_t *est, int32_t uni
         }
         const int per_cu = std::max<int>(1, std::min<int>(8, (int)((160 * 1024) / (lds + 1024))));
         const int grid = (int)std::min<int64_t>(ws->tasks, (int64_t)cus * per_cu);
-        if (lds > 65536)
-            INSP_HIP(hipFuncSetAttribute((const void *)&k_trans, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        if ((rc = set_lds_limit((const void *)&k_trans, lds))) return rc;
         ProfScope ps(st, "trans");
         hipLaunchKernelGGL(k_trans, dim3(grid), dim3(kTT), lds, st, A);
     }

@@ -874,3 +874,47 @@ def test_full_powerlaw_2m(insp):
     ria, rie, rU = oracle.attributes(w.n, rp, col, w.est, w.n_gpu)
     assert np.array_equal(ia.cpu().numpy(), ria) and np.array_equal(ie.cpu().numpy(), rie) and U[0] == rU
     dag.free()
+
+
+@pytest.mark.parametrize("mode", ["heft", "transitive", "data", "locality"])
+def test_graph_replays_every_mode(insp, mode):
+    # the batch step of each policy, attribute reading and data model captured
+    # in a HIP graph (after a warm call, which builds the per-handle state),
+    # replayed with eager work on the same handle and synchronisations between
+    import torch
+    ws = synth.cfg3(select=list(range(13, 4096, 600))) + [_hubs(9)]
+    b = synth.concat(ws)
+    b.data_kib = np.concatenate([_kib(w, k, hi=90) for k, w in enumerate(ws)])
+    kw = {"heft": dict(policy="heft"), "transitive": dict(attr_mode="transitive"),
+          "data": dict(data_bw=600), "locality": dict(policy="locality", data_bw=600)}[mode]
+    say("graph mode", mode, len(ws))
+    dag, dur, est = insp.batch_to_device(b)
+    insp.set_task_data(dag, torch_tensor(b.data_kib))
+    workers = [(w.n_cpu, w.n_gpu) for w in ws]
+    prm = insp.params(**kw)
+    N = int(b.task_off[-1])
+    r = oracle.schedule_batch(b, **kw)
+    out = insp._outputs(N, dur.device)
+    out["makespan"] = torch.empty(len(ws), dtype=torch.int64, device=dur.device)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        insp.schedule_batch(dag, workers, dur, est, prm, out=out)  # warm
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        insp.schedule_batch(dag, workers, dur, est, prm, out=out)
+    for rep in range(3):
+        for k in out:
+            out[k].zero_()
+        junk = insp.schedule_batch(dag, workers, dur, est, prm)  # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for k in ("worker", "start", "finish", "ie_at_pop", "mode_at_pop"):
+            assert np.array_equal(out[k].cpu().numpy(), r[k]), (mode, rep, k)
+        assert np.array_equal(out["makespan"].cpu().numpy(), r["makespan"]), (mode, rep)
+        del junk
+    insp.sync_status(dag)
+    dag.free()
