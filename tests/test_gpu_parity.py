@@ -413,6 +413,9 @@ def test_many_workers(insp, machine):
         g = run_gpu(insp, w, policy)
         assert_same(g, oracle.schedule(w, policy=policy, variant=oracle.HEAP), f"workers {machine} {policy}")
         check_schedule(w, g["worker"], g["start"], g["finish"], g["makespan"])
+    say("workers", machine, "transitive")
+    g = run_gpu(insp, w, "inspirit", attr_mode="transitive")
+    assert_same(g, oracle.schedule(w, variant=oracle.HEAP, attr_mode="transitive"), f"workers {machine} transitive")
 
 
 def test_w8_heft_on_gpu(insp):
