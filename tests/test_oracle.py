@@ -804,3 +804,17 @@ def test_data_model_range_checks():
     with pytest.raises(oracle.OracleError) as e:
         oracle.schedule(w, data_bw=10)
     assert e.value.code == oracle.E_RANGE
+
+
+@pytest.mark.parametrize("case", ["heft", "transitive", "data", "locality"])
+def test_new_policies_never_beat_the_brute_force_optimum(case):
+    # any list schedule is a schedule: its makespan is at least the optimum
+    # over all schedules (and transfers only add waits to a schedule that
+    # stays feasible without them)
+    kw = {"heft": dict(policy="heft"), "transitive": dict(attr_mode="transitive"),
+          "data": dict(data_bw=256), "locality": dict(policy="locality", data_bw=256)}[case]
+    for i in range(12):
+        w = synth.random_dag(91, i, 3 + i % 5, 0.35, dur_hi=7, n_cpu=1, n_gpu=1 + i % 2)
+        w.data_kib = synth.Stream(92, i).randint(np.arange(w.n), 0, 3).astype(np.int32)
+        r = oracle.schedule(w, variant=oracle.HEAP, **kw)
+        assert r["makespan"] >= oracle.brute_opt(w), (case, i)
