@@ -299,6 +299,19 @@ int insp_profile_read(const char *kernel, double *total_ms, int64_t *launches);
  *                       (each nullable)
  *   insp_mlp_train_step the same gradients followed by one Adam step
  *                       (beta1 0.9, beta2 0.999, eps 1e-8, learning rate lr)
+ *   insp_mlp_train      `epochs` passes over rows [0, n) of device x [n][32]
+ *                       and t [n][2] in minibatches of `batch` rows (the
+ *                       last n mod batch rows are not used): the same result,
+ *                       bit for bit, as one insp_mlp_train_step per
+ *                       minibatch in order, with the steps replayed from a
+ *                       captured HIP graph of up to 32 steps.  loss (device,
+ *                       nullable) receives the last step's loss.  At most
+ *                       2^28 steps per call (INSP_E_RANGE); n < batch or
+ *                       epochs == 0 does nothing.  The graph is kept with
+ *                       the model and captured again when x, t, the step
+ *                       count, batch or lr change.  Host-synchronizes with
+ *                       `stream` once, at the start, while it uploads the
+ *                       step table.
  *   insp_mlp_predict    y = network(x) for n rows and/or integer estimates
  *                       est = clamp(rint(exp(y)), 1, 2^20), int32 [n][2]
  *   insp_mlp_state      copy parameters, Adam moments and step count to the
@@ -314,6 +327,8 @@ int insp_mlp_grads(insp_mlp *m, const float *x, const float *t, int32_t batch, f
                    void *stream);
 int insp_mlp_train_step(insp_mlp *m, const float *x, const float *t, int32_t batch, float lr, float *loss,
                         void *stream);
+int insp_mlp_train(insp_mlp *m, const float *x, const float *t, int64_t n, int32_t batch, int32_t epochs, float lr,
+                   float *loss, void *stream);
 int insp_mlp_predict(insp_mlp *m, const float *x, int64_t n, float *y, int32_t *est, void *stream);
 int insp_mlp_state(insp_mlp *m, float *params, float *adam_m, float *adam_v, int64_t *step, int to_host);
 

@@ -13,9 +13,10 @@ def train(mlp, x, log_ticks, n_train, epochs=10, batch=1024, lr=1e-3, log=None):
     import torch
     steps = 0
     for ep in range(epochs):
-        for i in range(0, n_train - batch + 1, batch):
-            mlp.train_step(x[i:i + batch], log_ticks[i:i + batch], lr=lr)
-            steps += 1
+        # one epoch = n_train // batch Adam steps in order, replayed from a
+        # captured graph (bit-identical to a train_step per minibatch)
+        mlp.train(x[:n_train], log_ticks[:n_train], batch=batch, epochs=1, lr=lr)
+        steps += n_train // batch
         if log:
             torch.cuda.synchronize()
             log(f"epoch {ep + 1}/{epochs} done ({steps} steps)")

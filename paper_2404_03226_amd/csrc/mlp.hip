@@ -24,6 +24,8 @@
 namespace insp {
 
 constexpr int kIn = 32, kHid = 256, kOut = 2;
+constexpr int64_t kMaxTrainSteps = 1 << 28;  // steps of one insp_mlp_train call
+constexpr int32_t kTrainChunk = 32;          // steps per captured graph
 constexpr int64_t kOffW1 = 0, kOffB1 = kOffW1 + kIn * kHid, kOffW2 = kOffB1 + kHid, kOffB2 = kOffW2 + kHid * kHid,
                   kOffW3 = kOffB2 + kHid, kOffB3 = kOffW3 + kHid * kOut, kParams = kOffB3 + kOut;
 static_assert(kParams == 74754, "parameter count");
@@ -260,10 +262,19 @@ __global__ __launch_bounds__(256) void k_dw3(const uint16_t *H2, const float *Y,
 }
 
 // Adam (Kingma and Ba) with bias correction, then the bf16 weight shadows.
+// With a table `tab` (graph-captured training) the corrections of the
+// current step are read from it instead: tab[0] is the step index i within
+// the call, tab[1 + 2i] and tab[2 + 2i] hold 1 - 0.9^step and 1 - 0.999^step
+// as computed by the host for the eager step, so both routes round alike.
 __global__ void k_adam(float *p, const float *g, float *m, float *v, int64_t n, float lr, float bc1, float bc2,
-                       uint16_t *w1, uint16_t *w2, uint16_t *w3) {
+                       uint16_t *w1, uint16_t *w2, uint16_t *w3, const int32_t *tab, int32_t tabn) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
+    if (tab) {
+        const int32_t s = min(max(tab[0], 0), tabn - 1);
+        bc1 = __int_as_float(tab[1 + 2 * s]);
+        bc2 = __int_as_float(tab[2 + 2 * s]);
+    }
     const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
     const float gi = g[i];
     const float mi = b1 * m[i] + (1.f - b1) * gi;
@@ -275,6 +286,22 @@ __global__ void k_adam(float *p, const float *g, float *m, float *v, int64_t n, 
     if (i < kOffB1) w1[i - kOffW1] = f2bf(pi);
     else if (i >= kOffW2 && i < kOffB2) w2[i - kOffW2] = f2bf(pi);
     else if (i >= kOffW3 && i < kOffB3) w3[i - kOffW3] = f2bf(pi);
+}
+
+// Advance the step index of graph-captured training (after the step's Adam).
+__global__ void k_next_step(int32_t *tab) {
+    if (threadIdx.x == 0) tab[0] += 1;
+}
+
+// Minibatch of graph-captured training: rows [o, o + rows) of x (to bf16)
+// and of t (copied), o = rows * (tab[0] mod steps), so one captured step
+// serves every minibatch of an epoch.
+__global__ void k_stage(const float *x, const float *t, const int32_t *tab, int32_t steps, int64_t rows,
+                        uint16_t *xb, float *ts) {
+    const int64_t o = rows * (int64_t)((uint32_t)tab[0] % (uint32_t)steps);
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < rows * kIn) xb[i] = f2bf(x[o * kIn + i]);
+    if (i < rows * kOut) ts[i] = t[o * kOut + i];
 }
 
 __global__ void k_shadow(const float *p, uint16_t *w1, uint16_t *w2, uint16_t *w3) {
@@ -430,6 +457,26 @@ struct insp_mlp {
     DevBuf xb, h1, h2, dh2, dh1;  // bf16 activations and gradients
     DevBuf y;                     // fp32 [cap, 2]
     DevBuf part;                  // fp32 partial sums for the fixed-order reductions
+    int64_t gen = 0;              // bumped whenever a buffer above moves
+    // graph-captured training
+    DevBuf ts;                    // fp32 [cap, 2] staged targets
+    DevBuf tab;                   // int32 step index, then the bias-correction table
+    hipStream_t cs = nullptr;     // capture stream
+    hipGraphExec_t exec = nullptr;
+    struct Key {
+        const float *x, *t;
+        int32_t steps, batch, chunk;
+        float lr;
+        int64_t gen;
+        bool operator==(const Key &o) const {
+            return x == o.x && t == o.t && steps == o.steps && batch == o.batch && chunk == o.chunk && lr == o.lr &&
+                   gen == o.gen;
+        }
+    } key{};
+    ~insp_mlp() {
+        if (exec) hipGraphExecDestroy(exec);
+        if (cs) hipStreamDestroy(cs);
+    }
 };
 
 static int mlp_reserve(insp_mlp *m, int64_t rows) {
@@ -438,16 +485,20 @@ static int mlp_reserve(insp_mlp *m, int64_t rows) {
     if ((rc = m->xb.alloc(2 * kIn * rows)) || (rc = m->h1.alloc(2 * kHid * rows)) ||
         (rc = m->h2.alloc(2 * kHid * rows)) || (rc = m->dh2.alloc(2 * kHid * rows)) ||
         (rc = m->dh1.alloc(2 * kHid * rows)) || (rc = m->y.alloc(4 * kOut * rows)) ||
-        (rc = m->part.alloc(4 * ((rows + 3) / 4 + 1) * (kHid + 3))))
+        (rc = m->part.alloc(4 * ((rows + 3) / 4 + 1) * (kHid + 3))) || (rc = m->ts.alloc(4 * kOut * rows)))
         return rc;
     m->cap = rows;
+    m->gen++;
     return INSP_OK;
 }
 
-// Forward over `rows` rows of fp32 features into the bf16 activation buffers.
+// Forward over `rows` rows of fp32 features into the bf16 activation buffers
+// (x == nullptr: the bf16 features are already staged in m->xb).
 static void mlp_forward(insp_mlp *m, const float *x, int64_t rows, hipStream_t st) {
     const float *P = m->p.as<float>();
-    hipLaunchKernelGGL(k_to_bf16, dim3(blocks(rows * kIn, 256)), dim3(256), 0, st, x, m->xb.as<uint16_t>(), rows * kIn);
+    if (x)
+        hipLaunchKernelGGL(k_to_bf16, dim3(blocks(rows * kIn, 256)), dim3(256), 0, st, x, m->xb.as<uint16_t>(),
+                           rows * kIn);
     GemmArgs g;
     memset(&g, 0, sizeof g);
     g.M = (int)rows; g.N = kHid; g.K = kIn;
@@ -465,10 +516,18 @@ static void mlp_forward(insp_mlp *m, const float *x, int64_t rows, hipStream_t s
 }
 
 // Loss and gradients of one batch into m->g; y out optional.  Every sum is
-// taken in a fixed order, so a step is bit-reproducible.
-static int mlp_backward(insp_mlp *m, const float *x, const float *t, int64_t B, hipStream_t st) {
+// taken in a fixed order, so a step is bit-reproducible.  With `tab` the
+// batch is minibatch tab[0] mod `steps` of x and t (graph-captured training).
+static int mlp_backward(insp_mlp *m, const float *x, const float *t, int64_t B, hipStream_t st,
+                        const int32_t *tab = nullptr, int32_t steps = 0) {
     float *G = m->g.as<float>();
     float *part = m->part.as<float>();
+    if (tab) {
+        hipLaunchKernelGGL(k_stage, dim3(blocks(B * kIn, 256)), dim3(256), 0, st, x, t, tab, steps, B,
+                           m->xb.as<uint16_t>(), m->ts.as<float>());
+        x = nullptr;
+        t = m->ts.as<float>();
+    }
     mlp_forward(m, x, B, st);
     const int ob = (int)((B + 3) / 4);
     hipLaunchKernelGGL(k_out, dim3(ob), dim3(256), 0, st, m->h2.as<uint16_t>(), m->w3.as<uint16_t>(),
@@ -552,9 +611,95 @@ extern "C" int insp_mlp_train_step(insp_mlp *m, const float *x, const float *t, 
     const float bc1 = 1.f - powf(0.9f, (float)m->step), bc2 = 1.f - powf(0.999f, (float)m->step);
     hipLaunchKernelGGL(k_adam, dim3(blocks(kParams, 256)), dim3(256), 0, st, m->p.as<float>(), m->g.as<float>(),
                        m->m.as<float>(), m->v.as<float>(), kParams, lr, bc1, bc2, m->w1.as<uint16_t>(),
-                       m->w2.as<uint16_t>(), m->w3.as<uint16_t>());
+                       m->w2.as<uint16_t>(), m->w3.as<uint16_t>(), (const int32_t *)nullptr, 0);
     if (loss) INSP_HIP(hipMemcpyAsync(loss, m->loss.p, 4, hipMemcpyDeviceToDevice, st));
     INSP_HIP(hipGetLastError());
+    return INSP_OK;
+}
+
+// One step of graph-captured training: minibatch tab[0] mod steps, Adam with
+// the tabled corrections, then the step index advances.
+static int train_enqueue(insp_mlp *m, const float *x, const float *t, int32_t steps, int32_t batch, float lr,
+                         int32_t tabn, hipStream_t st) {
+    int32_t *tab = m->tab.as<int32_t>();
+    int rc;
+    if ((rc = mlp_backward(m, x, t, batch, st, tab, steps))) return rc;
+    hipLaunchKernelGGL(k_adam, dim3(blocks(kParams, 256)), dim3(256), 0, st, m->p.as<float>(), m->g.as<float>(),
+                       m->m.as<float>(), m->v.as<float>(), kParams, lr, 1.f, 1.f, m->w1.as<uint16_t>(),
+                       m->w2.as<uint16_t>(), m->w3.as<uint16_t>(), (const int32_t *)tab, tabn);
+    hipLaunchKernelGGL(k_next_step, dim3(1), dim3(64), 0, st, tab);
+    INSP_HIP(hipGetLastError());
+    return INSP_OK;
+}
+
+// Captures `chunk` consecutive steps into m->exec (on the model's own
+// stream: capture leaves the caller's stream alone).
+static int train_capture(insp_mlp *m, const float *x, const float *t, int32_t steps, int32_t batch, float lr,
+                         int32_t chunk, int32_t tabn) {
+    if (m->exec) {
+        hipGraphExecDestroy(m->exec);
+        m->exec = nullptr;
+    }
+    if (!m->cs) INSP_HIP(hipStreamCreateWithFlags(&m->cs, hipStreamNonBlocking));
+    INSP_HIP(hipStreamBeginCapture(m->cs, hipStreamCaptureModeThreadLocal));
+    int rc = INSP_OK;
+    for (int32_t s = 0; s < chunk && rc == INSP_OK; s++) rc = train_enqueue(m, x, t, steps, batch, lr, tabn, m->cs);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(m->cs, &g);
+    if (rc == INSP_OK && e != hipSuccess) rc = set_error(INSP_E_DEVICE, hipGetErrorString(e));
+    if (rc == INSP_OK) {
+        const hipError_t ei = hipGraphInstantiate(&m->exec, g, nullptr, nullptr, 0);
+        if (ei != hipSuccess) {
+            m->exec = nullptr;
+            rc = set_error(INSP_E_DEVICE, hipGetErrorString(ei));
+        }
+    }
+    if (g) hipGraphDestroy(g);
+    return rc;
+}
+
+extern "C" int insp_mlp_train(insp_mlp *m, const float *x, const float *t, int64_t n, int32_t batch, int32_t epochs,
+                              float lr, float *loss, void *stream) {
+    if (!m || n < 0 || epochs < 0 || batch < 1 || batch % 32 || !(lr > 0.f) || (n > 0 && (!x || !t)))
+        return set_error(INSP_E_INVAL, "bad argument");
+    const int64_t steps = n / batch, total = steps * epochs;
+    if (total == 0) return INSP_OK;
+    if (total > kMaxTrainSteps) return set_error(INSP_E_RANGE, "more than 2^28 training steps in one call");
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t words = 1 + 2 * total;
+    int rc;
+    if (m->cap < batch || m->tab.bytes < (size_t)(4 * words)) {
+        INSP_HIP(hipStreamSynchronize(st));  // earlier work on the stream may still read the old buffers
+        if ((rc = mlp_reserve(m, batch))) return rc;
+        if (m->tab.bytes < (size_t)(4 * words)) {
+            if ((rc = m->tab.alloc(4 * words))) return rc;
+            m->gen++;
+        }
+    }
+    // step index 0, then the corrections of steps step+1 .. step+total, as
+    // the eager step computes them
+    std::vector<int32_t> h((size_t)words);
+    h[0] = 0;
+    for (int64_t s = 1; s <= total; s++) {
+        const float bc1 = 1.f - powf(0.9f, (float)(m->step + s)), bc2 = 1.f - powf(0.999f, (float)(m->step + s));
+        memcpy(&h[2 * s - 1], &bc1, 4);
+        memcpy(&h[2 * s], &bc2, 4);
+    }
+    INSP_HIP(hipMemcpyAsync(m->tab.p, h.data(), 4 * words, hipMemcpyHostToDevice, st));
+    INSP_HIP(hipStreamSynchronize(st));  // h is released on return
+    const int32_t chunk = (int32_t)std::min<int64_t>(total, kTrainChunk);
+    const int32_t tabn = (int32_t)((m->tab.bytes / 4 - 1) / 2);  // entries the table holds
+    const insp_mlp::Key k{x, t, (int32_t)steps, batch, chunk, lr, m->gen};
+    if (!m->exec || !(k == m->key)) {
+        m->key = insp_mlp::Key{};
+        if ((rc = train_capture(m, x, t, (int32_t)steps, batch, lr, chunk, tabn))) return rc;
+        m->key = k;
+    }
+    for (int64_t s = 0; s + chunk <= total; s += chunk) INSP_HIP(hipGraphLaunch(m->exec, st));
+    for (int64_t s = total - total % chunk; s < total; s++)
+        if ((rc = train_enqueue(m, x, t, (int32_t)steps, batch, lr, tabn, st))) return rc;
+    m->step += total;
+    if (loss) INSP_HIP(hipMemcpyAsync(loss, m->loss.p, 4, hipMemcpyDeviceToDevice, st));
     return INSP_OK;
 }
 

@@ -27,7 +27,7 @@ EXPORTS = ("insp_build_dag", "insp_set_task_data", "insp_free_dag", "insp_dag_in
            "insp_transitive_attributes",
            "insp_schedule",
            "insp_schedule_batch", "insp_sync_status", "insp_profile_enable", "insp_profile_read",
-           "insp_mlp_create", "insp_mlp_free", "insp_mlp_grads", "insp_mlp_train_step", "insp_mlp_predict",
+           "insp_mlp_create", "insp_mlp_free", "insp_mlp_grads", "insp_mlp_train_step", "insp_mlp_train", "insp_mlp_predict",
            "insp_mlp_state", "insp_last_error")
 MLP_PARAMS = 74754
 
@@ -87,6 +87,7 @@ def load(path: str = LIB_PATH):
     lib.insp_mlp_free.restype = None
     lib.insp_mlp_grads.argtypes = [P, P, P, i32, P, P, P, P]
     lib.insp_mlp_train_step.argtypes = [P, P, P, i32, C.c_float, P, P]
+    lib.insp_mlp_train.argtypes = [P, P, P, i64, i32, i32, C.c_float, P, P]
     lib.insp_mlp_predict.argtypes = [P, P, i64, P, P, P]
     lib.insp_mlp_state.argtypes = [P, P, P, P, C.POINTER(i64), C.c_int]
     lib.insp_last_error.restype = C.c_char_p
@@ -328,6 +329,11 @@ class Mlp:
 
     def train_step(self, x, t, lr=1e-3, loss=None, stream=None):
         _check(load().insp_mlp_train_step(self._h, _ptr(x), _ptr(t), x.shape[0], lr, _ptr(loss), _stream(stream)))
+
+    def train(self, x, t, batch=1024, epochs=1, lr=1e-3, loss=None, stream=None):
+        """`epochs` passes over all rows of x, t in minibatches (graph-captured)."""
+        _check(load().insp_mlp_train(self._h, _ptr(x), _ptr(t), x.shape[0], batch, epochs, lr, _ptr(loss),
+                                     _stream(stream)))
 
     def predict(self, x, want_y=True, stream=None):
         import torch

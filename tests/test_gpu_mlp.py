@@ -108,6 +108,40 @@ def test_training_beats_the_per_type_table(insp):
     m.free()
 
 
+@pytest.mark.parametrize("n,bsz,epochs", [(4096 + 100, 256, 3), (1024, 64, 1), (96, 32, 2)])
+def test_graph_training_matches_eager_steps(insp, n, bsz, epochs):
+    """insp_mlp_train against a loop of insp_mlp_train_step over the same
+    minibatches: parameters, Adam moments, step count and the last loss are
+    bit-identical.  Later calls with another batch (a new capture) and with
+    the same arguments (the kept graph, a fresh step table) continue from the
+    first; n < batch and epochs == 0 do nothing."""
+    import torch
+    print(f"[case] mlp graph training n={n} batch={bsz} epochs={epochs}", flush=True)
+    X, T = batch(n)
+    Xd, Td = torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda()
+    a = insp.Mlp(synth.mlp_init())
+    b = insp.Mlp(synth.mlp_init())
+    la = torch.zeros(1, dtype=torch.float32, device="cuda")
+    lb = torch.full((1,), -1.0, dtype=torch.float32, device="cuda")
+    for bs, ep in ((bsz, epochs), (32, 1), (32, 1)):
+        for _ in range(ep):
+            for i in range(0, n - bs + 1, bs):
+                a.train_step(Xd[i:i + bs], Td[i:i + bs], loss=la)
+        b.train(Xd, Td, batch=bs, epochs=ep, loss=lb)
+    b.train(Xd[:16], Td[:16], batch=32, epochs=4, loss=lb)  # no full minibatch
+    b.train(Xd, Td, batch=32, epochs=0, loss=lb)
+    torch.cuda.synchronize()
+    sa, sb = a.state(), b.state()
+    for u, v in zip(sa[:3], sb[:3]):
+        assert np.array_equal(u, v)
+    assert sa[3] == sb[3] == epochs * (n // bsz) + 2 * (n // 32)
+    assert la.item() == lb.item()
+    with pytest.raises(insp.InspError):
+        b.train(Xd, Td, batch=48)
+    a.free()
+    b.free()
+
+
 def test_checkpoint_resume_is_bit_identical(insp):
     import torch
     print("[case] mlp resume", flush=True)
