@@ -48,6 +48,11 @@ __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint
 // fixed order, so training is bit-reproducible).  64 x 64 tile per 256-thread block; each wave owns a
 // 32 x 32 quarter as 2 x 2 MFMA 16x16x32 tiles; K advances 32 at a time
 // through LDS (A row-major, B transposed so both fragments are 16-byte reads).
+// Staging reads 8 consecutive bf16 per thread (16 bytes) along whichever
+// index of an operand is contiguous in memory (amode/bmode 1: k, 2: m or n;
+// 0: element by element).  With ksplit > 1, block z of the grid's third
+// dimension sums K range [z kchunk, (z + 1) kchunk) into C32 + z pstride
+// (partials, reduced in z order by k_ksum); no epilogue then.
 struct GemmArgs {
     int M, N, K;
     const uint16_t *A;
@@ -63,13 +68,67 @@ struct GemmArgs {
     uint16_t *C16;
     int64_t ldc16;
     float *colpart;  // [ceil(M/64)][N] per-tile column sums of the final values
+    int amode, bmode;
+    int ksplit, kchunk;
+    int64_t pstride;
 };
 
 constexpr int kTM = 64, kTN = 64, kTK = 32, kLdsRow = kTK + 8;
 
+// K sub-tiles staged per global round trip.  Deeper panels (8, all of a
+// 256-deep K in one trip) measured no faster on the training shapes, whose
+// kernels sit near the per-launch floor, and cost 4x the LDS.
+constexpr int kSub = 1;
+
+// One operand tile, T[r][kk] = X(r0 + r, k0 + kk) with X(r, k) =
+// X[r sr + k sk], zero outside rows < R and k < kend, as 8 bf16 per thread:
+// mode 2 (sr == 1) thread = (k, 8 consecutive rows), one 16-byte read (the
+// host guarantees R % 8 == 0 and alignment); otherwise thread = (row, 8
+// consecutive k), one 16-byte read in mode 1 (sk == 1), 8 single reads in
+// mode 0.  Loading and storing are split so that a whole panel's reads are
+// in flight together.
+__device__ __forceinline__ uint4 load_tile(const uint16_t *X, int64_t sr, int64_t sk, int mode, int R, int r0, int k0,
+                                           int kend, int tid) {
+    uint4 v = {0u, 0u, 0u, 0u};
+    if (mode == 2) {
+        const int kk = tid >> 3, r = (tid & 7) * 8;
+        if (r0 + r < R && k0 + kk < kend)
+            v = *reinterpret_cast<const uint4 *>(X + (int64_t)(k0 + kk) * sk + (r0 + r));
+    } else if (mode == 1) {
+        const int r = tid >> 2, kk = (tid & 3) * 8;
+        if (r0 + r < R && k0 + kk < kend)
+            v = *reinterpret_cast<const uint4 *>(X + (int64_t)(r0 + r) * sr + (k0 + kk));
+    } else {
+        const int r = tid >> 2, kk = (tid & 3) * 8;
+        uint32_t h[8];
+#pragma unroll
+        for (int i = 0; i < 8; i++) {
+            const int rr = r0 + r, k = k0 + kk + i;
+            h[i] = (rr < R && k < kend) ? X[(int64_t)rr * sr + (int64_t)k * sk] : 0u;
+        }
+        v = uint4{h[0] | h[1] << 16, h[2] | h[3] << 16, h[4] | h[5] << 16, h[6] | h[7] << 16};
+    }
+    return v;
+}
+
+__device__ __forceinline__ void store_tile(uint4 v, int mode, int tid, uint16_t *T) {
+    if (mode == 2) {
+        const int kk = tid >> 3, r = (tid & 7) * 8;
+        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            T[(r + 2 * j) * kLdsRow + kk] = (uint16_t)(w[j] & 0xFFFFu);
+            T[(r + 2 * j + 1) * kLdsRow + kk] = (uint16_t)(w[j] >> 16);
+        }
+    } else {
+        const int r = tid >> 2, kk = (tid & 3) * 8;
+        *reinterpret_cast<uint4 *>(&T[r * kLdsRow + kk]) = v;
+    }
+}
+
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
-    __shared__ __attribute__((aligned(16))) uint16_t As[kTM * kLdsRow];
-    __shared__ __attribute__((aligned(16))) uint16_t Bs[kTN * kLdsRow];
+    __shared__ __attribute__((aligned(16))) uint16_t As[kSub][kTM * kLdsRow];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[kSub][kTN * kLdsRow];
     __shared__ float cpart[2 * kTN];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int m0 = blockIdx.y * kTM, n0 = blockIdx.x * kTN;
@@ -79,32 +138,60 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
     for (int a = 0; a < 2; a++)
 #pragma unroll
         for (int b = 0; b < 2; b++) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < g.K; k0 += kTK) {
-        // stage A [64 x 32] and B^T [64 x 32]: 8 elements per thread each
+    const int kbeg = g.ksplit > 1 ? (int)blockIdx.z * g.kchunk : 0;
+    const int kend = g.ksplit > 1 ? min(g.K, kbeg + g.kchunk) : g.K;
+    for (int k0 = kbeg; k0 < kend; k0 += kSub * kTK) {
+        // stage kSub tiles of A [64 x 32] and B^T [64 x 32]: all reads first
+        const int ns = min(kSub, (kend - k0 + kTK - 1) / kTK);
+        uint4 ra[kSub], rb[kSub];
 #pragma unroll
-        for (int i = 0; i < 8; i++) {
-            const int e = tid * 8 + i, r = e / kTK, kk = e % kTK;
-            const int m = m0 + r, n = n0 + r, k = k0 + kk;
-            As[r * kLdsRow + kk] = (m < g.M && k < g.K) ? g.A[(int64_t)m * g.sam + (int64_t)k * g.sak] : 0;
-            Bs[r * kLdsRow + kk] = (n < g.N && k < g.K) ? g.B[(int64_t)k * g.sbk + (int64_t)n * g.sbn] : 0;
+        for (int j = 0; j < kSub; j++) {
+            if (j >= ns) break;
+            ra[j] = load_tile(g.A, g.sam, g.sak, g.amode, g.M, m0, k0 + j * kTK, kend, tid);
+            rb[j] = load_tile(g.B, g.sbn, g.sbk, g.bmode, g.N, n0, k0 + j * kTK, kend, tid);
+        }
+#pragma unroll
+        for (int j = 0; j < kSub; j++) {
+            if (j >= ns) break;
+            store_tile(ra[j], g.amode, tid, As[j]);
+            store_tile(rb[j], g.bmode, tid, Bs[j]);
         }
         __syncthreads();
         const int fr = lane & 15, fk = (lane >> 4) * 8;
-        bf16x8 af[2], bfr[2];
 #pragma unroll
-        for (int a = 0; a < 2; a++)
-            af[a] = *reinterpret_cast<const bf16x8 *>(&As[(wm + a * 16 + fr) * kLdsRow + fk]);
+        for (int j = 0; j < kSub; j++) {
+            if (j >= ns) break;
+            bf16x8 af[2], bfr[2];
 #pragma unroll
-        for (int b = 0; b < 2; b++)
-            bfr[b] = *reinterpret_cast<const bf16x8 *>(&Bs[(wn + b * 16 + fr) * kLdsRow + fk]);
-#pragma unroll
-        for (int a = 0; a < 2; a++)
+            for (int a = 0; a < 2; a++)
+                af[a] = *reinterpret_cast<const bf16x8 *>(&As[j][(wm + a * 16 + fr) * kLdsRow + fk]);
 #pragma unroll
             for (int b = 0; b < 2; b++)
-                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[a], bfr[b], acc[a][b], 0, 0, 0);
+                bfr[b] = *reinterpret_cast<const bf16x8 *>(&Bs[j][(wn + b * 16 + fr) * kLdsRow + fk]);
+#pragma unroll
+            for (int a = 0; a < 2; a++)
+#pragma unroll
+                for (int b = 0; b < 2; b++)
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[a], bfr[b], acc[a][b], 0, 0, 0);
+        }
         __syncthreads();
     }
     // accumulator layout: value i of a lane is row 4*(lane/16)+i, column lane%16
+    if (g.ksplit > 1) {
+        float *P = g.C32 + (int64_t)blockIdx.z * g.pstride;
+#pragma unroll
+        for (int b = 0; b < 2; b++) {
+            const int n = n0 + wn + b * 16 + (lane & 15);
+#pragma unroll
+            for (int a = 0; a < 2; a++)
+#pragma unroll
+                for (int i = 0; i < 4; i++) {
+                    const int m = m0 + wm + a * 16 + (lane >> 4) * 4 + i;
+                    if (m < g.M && n < g.N) P[(int64_t)m * g.ldc + n] = acc[a][b][i];
+                }
+        }
+        return;
+    }
 #pragma unroll
     for (int b = 0; b < 2; b++) {
         const int n = n0 + wn + b * 16 + (lane & 15);
@@ -139,13 +226,31 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
     }
 }
 
-// Sum `rows` partial rows of `cols` columns in row order (deterministic).
-__global__ void k_colreduce(const float *part, int rows, int cols, float *out) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= cols) return;
+// Column c of a [rows][cols] array of partial sums, summed by a 1024-thread
+// block that owns 64 columns: wave w adds its contiguous share of the rows in
+// row order, then the 16 wave sums are added in wave order (a fixed order,
+// so the result is reproducible).  Every thread of the block must call it.
+__device__ __forceinline__ float col_sum(const float *part, int rows, int cols, int c) {
+    __shared__ float red[16][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int per = (rows + 15) / 16, r0 = min(rows, w * per), r1 = min(rows, r0 + per);
     float s = 0.f;
-    for (int r = 0; r < rows; r++) s += part[(int64_t)r * cols + c];
-    out[c] = s;
+    if (c < cols) {
+#pragma unroll 8
+        for (int r = r0; r < r1; r++) s += part[(int64_t)r * cols + c];
+    }
+    red[w][lane] = s;
+    __syncthreads();
+    float t = red[0][lane];
+#pragma unroll
+    for (int i = 1; i < 16; i++) t += red[i][lane];
+    return t;
+}
+
+__global__ __launch_bounds__(1024) void k_colreduce(const float *part, int rows, int cols, float *out) {
+    const int c = blockIdx.x * 64 + (threadIdx.x & 63);
+    const float t = col_sum(part, rows, cols, c);
+    if (threadIdx.x < 64 && c < cols) out[c] = t;
 }
 
 // -------------------------------------------------------------- helpers
@@ -225,12 +330,19 @@ __global__ __launch_bounds__(256) void k_out(const uint16_t *H2, const uint16_t 
     if (tid < 3) pp[kHid + tid] = ((rowx[0][tid] + rowx[1][tid]) + rowx[2][tid]) + rowx[3][tid];
 }
 
-// Place the reduced db2, db3 and loss.
-__global__ void k_unpack_out(const float *red, float *grads, float *loss) {
-    const int i = threadIdx.x;
-    grads[kOffB2 + i] = red[i];
-    if (i < 2) grads[kOffB3 + i] = red[kHid + i];
-    if (i == 0) loss[0] = red[kHid + 2];
+// db2, db3 and the loss from k_out's per-block partials [rows][kHid + 3].
+// Under graph-captured training (tab) this also advances the step index
+// tab[0]: the step's minibatch is staged by then and Adam reads tab[0] - 1.
+__global__ __launch_bounds__(1024) void k_reduce_out(const float *part, int rows, float *grads, float *loss,
+                                                      int32_t *tab) {
+    const int c = blockIdx.x * 64 + (threadIdx.x & 63);
+    const float t = col_sum(part, rows, kHid + 3, c);
+    if (threadIdx.x < 64) {
+        if (c < kHid) grads[kOffB2 + c] = t;
+        else if (c < kHid + 2) grads[kOffB3 + (c - kHid)] = t;
+        else if (c == kHid + 2) loss[0] = t;
+    }
+    if (tab && blockIdx.x == 0 && threadIdx.x == 0) tab[0] += 1;
 }
 
 // dW3[i, c] = sum_r H2[r, i] dY[r, c]; dY recomputed from Y and T.
@@ -263,15 +375,16 @@ __global__ __launch_bounds__(256) void k_dw3(const uint16_t *H2, const float *Y,
 
 // Adam (Kingma and Ba) with bias correction, then the bf16 weight shadows.
 // With a table `tab` (graph-captured training) the corrections of the
-// current step are read from it instead: tab[0] is the step index i within
-// the call, tab[1 + 2i] and tab[2 + 2i] hold 1 - 0.9^step and 1 - 0.999^step
-// as computed by the host for the eager step, so both routes round alike.
+// current step are read from it instead: tab[0] - 1 is the step index i
+// within the call (advanced by k_reduce_out), tab[1 + 2i] and tab[2 + 2i]
+// hold 1 - 0.9^step and 1 - 0.999^step as computed by the host for the eager
+// step, so both routes round alike.
 __global__ void k_adam(float *p, const float *g, float *m, float *v, int64_t n, float lr, float bc1, float bc2,
                        uint16_t *w1, uint16_t *w2, uint16_t *w3, const int32_t *tab, int32_t tabn) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
     if (tab) {
-        const int32_t s = min(max(tab[0], 0), tabn - 1);
+        const int32_t s = min(max(tab[0] - 1, 0), tabn - 1);
         bc1 = __int_as_float(tab[1 + 2 * s]);
         bc2 = __int_as_float(tab[2 + 2 * s]);
     }
@@ -286,11 +399,6 @@ __global__ void k_adam(float *p, const float *g, float *m, float *v, int64_t n, 
     if (i < kOffB1) w1[i - kOffW1] = f2bf(pi);
     else if (i >= kOffW2 && i < kOffB2) w2[i - kOffW2] = f2bf(pi);
     else if (i >= kOffW3 && i < kOffB3) w3[i - kOffW3] = f2bf(pi);
-}
-
-// Advance the step index of graph-captured training (after the step's Adam).
-__global__ void k_next_step(int32_t *tab) {
-    if (threadIdx.x == 0) tab[0] += 1;
 }
 
 // Minibatch of graph-captured training: rows [o, o + rows) of x (to bf16)
@@ -438,9 +546,50 @@ __global__ __launch_bounds__(256) void k_infer(const float *x, int64_t rows, con
 
 static unsigned blocks(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
-static void gemm(hipStream_t st, const GemmArgs &g) {
-    dim3 grid((g.N + kTN - 1) / kTN, (g.M + kTM - 1) / kTM);
-    hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, st, g);
+// out[i] = sum over z = 0 .. S-1, in order, of part[z pstride + i].
+__global__ void k_ksum(const float *part, int S, int64_t pstride, int64_t n, float *out) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float s = part[i];
+#pragma unroll 8
+    for (int z = 1; z < S; z++) s += part[z * pstride + i];
+    out[i] = s;
+}
+
+constexpr int64_t kKSplitFloats = 16 * kHid * kHid;  // split-K partial buffer
+
+static bool aligned16(const void *p) { return ((uintptr_t)p & 15) == 0; }
+
+// Launch C = A B.  A plain fp32 product with a contiguous C (ldc == N) and
+// few output tiles splits K over the partial buffer `kpart`
+// (kKSplitFloats floats) so that the grid fills the chip.
+static void gemm(hipStream_t st, GemmArgs g, float *kpart = nullptr) {
+    g.amode = (g.sak == 1 && g.sam % 8 == 0 && g.K % 8 == 0 && aligned16(g.A)) ? 1
+              : (g.sam == 1 && g.sak % 8 == 0 && g.M % 8 == 0 && aligned16(g.A)) ? 2 : 0;
+    g.bmode = (g.sbk == 1 && g.sbn % 8 == 0 && g.K % 8 == 0 && aligned16(g.B)) ? 1
+              : (g.sbn == 1 && g.sbk % 8 == 0 && g.N % 8 == 0 && aligned16(g.B)) ? 2 : 0;
+    const int gx = (g.N + kTN - 1) / kTN, gy = (g.M + kTM - 1) / kTM;
+    const int kt = (g.K + kTK - 1) / kTK;
+    int S = 1;
+    if (kpart && g.C32 && !g.C16 && !g.bias && !g.relu && !g.mask && !g.colpart && g.ldc == g.N) {
+        const int64_t mn = (int64_t)g.M * g.N;
+        S = std::min<int64_t>({(int64_t)kt, std::max(1, 256 / (gx * gy)), kKSplitFloats / std::max<int64_t>(mn, 1)});
+        if (S > 1) {
+            g.kchunk = ((kt + S - 1) / S) * kTK;
+            S = (g.K + g.kchunk - 1) / g.kchunk;
+        }
+    }
+    if (S <= 1) {
+        g.ksplit = 1;
+        hipLaunchKernelGGL(k_gemm, dim3(gx, gy), dim3(256), 0, st, g);
+        return;
+    }
+    float *out = g.C32;
+    g.ksplit = S;
+    g.pstride = (int64_t)g.M * g.N;
+    g.C32 = kpart;
+    hipLaunchKernelGGL(k_gemm, dim3(gx, gy, S), dim3(256), 0, st, g);
+    hipLaunchKernelGGL(k_ksum, dim3(blocks(g.pstride, 256)), dim3(256), 0, st, kpart, S, g.pstride, g.pstride, out);
 }
 
 }  // namespace insp
@@ -457,6 +606,7 @@ struct insp_mlp {
     DevBuf xb, h1, h2, dh2, dh1;  // bf16 activations and gradients
     DevBuf y;                     // fp32 [cap, 2]
     DevBuf part;                  // fp32 partial sums for the fixed-order reductions
+    DevBuf kpart;                 // fp32 [kKSplitFloats] split-K partial products
     int64_t gen = 0;              // bumped whenever a buffer above moves
     // graph-captured training
     DevBuf ts;                    // fp32 [cap, 2] staged targets
@@ -474,8 +624,8 @@ struct insp_mlp {
         }
     } key{};
     ~insp_mlp() {
-        if (exec) hipGraphExecDestroy(exec);
-        if (cs) hipStreamDestroy(cs);
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (cs) (void)hipStreamDestroy(cs);
     }
 };
 
@@ -519,7 +669,7 @@ static void mlp_forward(insp_mlp *m, const float *x, int64_t rows, hipStream_t s
 // taken in a fixed order, so a step is bit-reproducible.  With `tab` the
 // batch is minibatch tab[0] mod `steps` of x and t (graph-captured training).
 static int mlp_backward(insp_mlp *m, const float *x, const float *t, int64_t B, hipStream_t st,
-                        const int32_t *tab = nullptr, int32_t steps = 0) {
+                        int32_t *tab = nullptr, int32_t steps = 0) {
     float *G = m->g.as<float>();
     float *part = m->part.as<float>();
     if (tab) {
@@ -533,10 +683,10 @@ static int mlp_backward(insp_mlp *m, const float *x, const float *t, int64_t B, 
     hipLaunchKernelGGL(k_out, dim3(ob), dim3(256), 0, st, m->h2.as<uint16_t>(), m->w3.as<uint16_t>(),
                        m->p.as<float>() + kOffB3, B, m->y.as<float>(), t, part, m->dh2.as<uint16_t>(),
                        (int32_t *)nullptr);
-    // db2 (256 columns), db3 (2) and the loss (1) from the block partials
-    hipLaunchKernelGGL(k_colreduce, dim3(2), dim3(256), 0, st, part, ob, kHid + 3, part + (int64_t)ob * (kHid + 3));
-    hipLaunchKernelGGL(k_unpack_out, dim3(1), dim3(256), 0, st, part + (int64_t)ob * (kHid + 3), G,
-                       m->loss.as<float>());
+    // db2 (256 columns), db3 (2) and the loss (1) from the block partials;
+    // with tab the step index advances here
+    hipLaunchKernelGGL(k_reduce_out, dim3(blocks(kHid + 3, 64)), dim3(1024), 0, st, part, ob, G,
+                       m->loss.as<float>(), tab);
     hipLaunchKernelGGL(k_dw3, dim3(kHid), dim3(256), 0, st, m->h2.as<uint16_t>(), m->y.as<float>(), t, B, G);
     GemmArgs g;
     memset(&g, 0, sizeof g);
@@ -545,7 +695,7 @@ static int mlp_backward(insp_mlp *m, const float *x, const float *t, int64_t B, 
     g.A = m->h1.as<uint16_t>(); g.sam = 1; g.sak = kHid;
     g.B = m->dh2.as<uint16_t>(); g.sbk = kHid; g.sbn = 1;
     g.C32 = G + kOffW2; g.ldc = kHid;
-    gemm(st, g);
+    gemm(st, g, m->kpart.as<float>());
     // dH1 = (dH2 W2^T) * (H1 > 0); db1 = column sums (per tile, then in order)
     memset(&g, 0, sizeof g);
     g.M = (int)B; g.N = kHid; g.K = kHid;
@@ -555,14 +705,15 @@ static int mlp_backward(insp_mlp *m, const float *x, const float *t, int64_t B, 
     g.C16 = m->dh1.as<uint16_t>(); g.ldc16 = kHid;
     g.colpart = part;
     gemm(st, g);
-    hipLaunchKernelGGL(k_colreduce, dim3(1), dim3(256), 0, st, part, (int)((B + kTM - 1) / kTM), kHid, G + kOffB1);
+    hipLaunchKernelGGL(k_colreduce, dim3(blocks(kHid, 64)), dim3(1024), 0, st, part, (int)((B + kTM - 1) / kTM), kHid,
+                       G + kOffB1);
     // dW1 = X^T dH1
     memset(&g, 0, sizeof g);
     g.M = kIn; g.N = kHid; g.K = (int)B;
     g.A = m->xb.as<uint16_t>(); g.sam = 1; g.sak = kIn;
     g.B = m->dh1.as<uint16_t>(); g.sbk = kHid; g.sbn = 1;
     g.C32 = G + kOffW1; g.ldc = kHid;
-    gemm(st, g);
+    gemm(st, g, m->kpart.as<float>());
     INSP_HIP(hipGetLastError());
     return INSP_OK;
 }
@@ -574,7 +725,7 @@ extern "C" int insp_mlp_create(const float *params, insp_mlp **out) {
     int rc;
     if ((rc = m->p.alloc(4 * kParams)) || (rc = m->g.alloc(4 * kParams)) || (rc = m->m.alloc(4 * kParams)) ||
         (rc = m->v.alloc(4 * kParams)) || (rc = m->w1.alloc(2 * kIn * kHid)) || (rc = m->w2.alloc(2 * kHid * kHid)) ||
-        (rc = m->w3.alloc(2 * kHid * kOut)) || (rc = m->loss.alloc(4)))
+        (rc = m->w3.alloc(2 * kHid * kOut)) || (rc = m->loss.alloc(4)) || (rc = m->kpart.alloc(4 * kKSplitFloats)))
         return rc;
     INSP_HIP(hipMemcpy(m->p.p, params, 4 * kParams, hipMemcpyHostToDevice));
     INSP_HIP(hipMemset(m->m.p, 0, 4 * kParams));
@@ -617,8 +768,9 @@ extern "C" int insp_mlp_train_step(insp_mlp *m, const float *x, const float *t, 
     return INSP_OK;
 }
 
-// One step of graph-captured training: minibatch tab[0] mod steps, Adam with
-// the tabled corrections, then the step index advances.
+// One step of graph-captured training: minibatch tab[0] mod steps, the step
+// index advances once the minibatch is staged, Adam with the tabled
+// corrections of step tab[0] - 1.
 static int train_enqueue(insp_mlp *m, const float *x, const float *t, int32_t steps, int32_t batch, float lr,
                          int32_t tabn, hipStream_t st) {
     int32_t *tab = m->tab.as<int32_t>();
@@ -627,7 +779,6 @@ static int train_enqueue(insp_mlp *m, const float *x, const float *t, int32_t st
     hipLaunchKernelGGL(k_adam, dim3(blocks(kParams, 256)), dim3(256), 0, st, m->p.as<float>(), m->g.as<float>(),
                        m->m.as<float>(), m->v.as<float>(), kParams, lr, 1.f, 1.f, m->w1.as<uint16_t>(),
                        m->w2.as<uint16_t>(), m->w3.as<uint16_t>(), (const int32_t *)tab, tabn);
-    hipLaunchKernelGGL(k_next_step, dim3(1), dim3(64), 0, st, tab);
     INSP_HIP(hipGetLastError());
     return INSP_OK;
 }
@@ -637,7 +788,7 @@ static int train_enqueue(insp_mlp *m, const float *x, const float *t, int32_t st
 static int train_capture(insp_mlp *m, const float *x, const float *t, int32_t steps, int32_t batch, float lr,
                          int32_t chunk, int32_t tabn) {
     if (m->exec) {
-        hipGraphExecDestroy(m->exec);
+        (void)hipGraphExecDestroy(m->exec);
         m->exec = nullptr;
     }
     if (!m->cs) INSP_HIP(hipStreamCreateWithFlags(&m->cs, hipStreamNonBlocking));
@@ -654,7 +805,7 @@ static int train_capture(insp_mlp *m, const float *x, const float *t, int32_t st
             rc = set_error(INSP_E_DEVICE, hipGetErrorString(ei));
         }
     }
-    if (g) hipGraphDestroy(g);
+    if (g) (void)hipGraphDestroy(g);
     return rc;
 }
 
