@@ -317,7 +317,9 @@ int insp_profile_read(const char *kernel, double *total_ms, int64_t *launches);
  *   insp_mlp_state      copy parameters, Adam moments and step count to the
  *                       host (to_host = 1) or from it (to_host = 0), for
  *                       checkpoint and resume; any pointer may be NULL
- * batch must be a positive multiple of 32.  Work runs on `stream`.
+ * batch must be a positive multiple of 32.  Work runs on `stream`.  Calls on
+ * one model share its buffers and must not overlap; insp_mlp_free waits for
+ * the device before it releases them.
  */
 #define INSP_MLP_PARAMS 74754
 typedef struct insp_mlp insp_mlp;

@@ -624,6 +624,8 @@ struct insp_mlp {
         }
     } key{};
     ~insp_mlp() {
+        // work queued on the caller's streams may still use the graph and buffers
+        (void)hipDeviceSynchronize();
         if (exec) (void)hipGraphExecDestroy(exec);
         if (cs) (void)hipStreamDestroy(cs);
     }
