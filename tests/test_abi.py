@@ -79,6 +79,20 @@ def test_error_path_without_gpu(lib):
     lib.insp_free_dag(None)
 
 
+def test_cost_model_argument_checks_without_gpu(lib):
+    # every insp_mlp_* entry point rejects a missing model before any device call
+    from paper_2404_03226_amd import inspirit
+    E = inspirit.E_INVAL
+    assert lib.insp_mlp_create(None, None) == E
+    assert lib.insp_mlp_grads(None, None, None, 32, None, None, None, None) == E
+    assert lib.insp_mlp_train_step(None, None, None, 32, 1e-3, None, None) == E
+    assert lib.insp_mlp_train(None, None, None, 1024, 32, 1, 1e-3, None, None) == E
+    assert b"bad argument" in lib.insp_last_error()
+    assert lib.insp_mlp_predict(None, None, 0, None, None, None) == E
+    assert lib.insp_mlp_state(None, None, None, None, None, 1) == E
+    lib.insp_mlp_free(None)
+
+
 def test_missing_library_fails_loudly(tmp_path):
     from paper_2404_03226_amd import inspirit
     saved = inspirit._lib

@@ -138,6 +138,9 @@ def test_graph_training_matches_eager_steps(insp, n, bsz, epochs):
     assert la.item() == lb.item()
     with pytest.raises(insp.InspError):
         b.train(Xd, Td, batch=48)
+    with pytest.raises(insp.InspError, match="2\\^28"):
+        b.train(Xd[:32], Td[:32], batch=32, epochs=2 ** 28 + 1)
+    assert b.state()[3] == sb[3]
     a.free()
     b.free()
 
