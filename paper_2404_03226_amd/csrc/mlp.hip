@@ -33,11 +33,8 @@ static_assert(kParams == 74754, "parameter count");
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ uint16_t f2bf(float f) {
-    uint32_t u = __float_as_uint(f);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-}
+// fp32 -> bf16, round to nearest even (one v_cvt_pk_bf16_f32 on gfx950)
+__device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
 // ------------------------------------------------------------------ GEMM
@@ -458,26 +455,40 @@ __global__ __launch_bounds__(256) void k_infer(const float *x, int64_t rows, con
     }
     const float b30 = b3[0], b31 = b3[1];
     const int64_t tiles = (rows + kRT - 1) / kRT;
+    // features of the next tile are read while the current one is in layer 2
+    float4 xa[4], xb[4];
+    auto load_x = [&](int64_t t0) {
+#pragma unroll
+        for (int rt = 0; rt < 4; rt++) {
+            const int64_t r = t0 * kRT + rt * 16 + lc;
+            if (r < rows) {
+                xa[rt] = *reinterpret_cast<const float4 *>(x + r * kIn + lk);
+                xb[rt] = *reinterpret_cast<const float4 *>(x + r * kIn + lk + 4);
+            } else {
+                xa[rt] = float4{0.f, 0.f, 0.f, 0.f};
+                xb[rt] = float4{0.f, 0.f, 0.f, 0.f};
+            }
+        }
+    };
+    if ((int64_t)blockIdx.x < tiles) load_x(blockIdx.x);
     for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
         const int64_t r0 = tile * kRT;
         // layer 1: A-fragment row lc of each 16-row tile, K = lk .. lk+7
+        bf16x8 af1[4];
 #pragma unroll
         for (int rt = 0; rt < 4; rt++) {
-            const int64_t r = r0 + rt * 16 + lc;
             u16x8 t;
-            if (r < rows) {
-                const float4 a = *reinterpret_cast<const float4 *>(x + r * kIn + lk);
-                const float4 b = *reinterpret_cast<const float4 *>(x + r * kIn + lk + 4);
-                t[0] = f2bf(a.x); t[1] = f2bf(a.y); t[2] = f2bf(a.z); t[3] = f2bf(a.w);
-                t[4] = f2bf(b.x); t[5] = f2bf(b.y); t[6] = f2bf(b.z); t[7] = f2bf(b.w);
-            } else {
+            t[0] = f2bf(xa[rt].x); t[1] = f2bf(xa[rt].y); t[2] = f2bf(xa[rt].z); t[3] = f2bf(xa[rt].w);
+            t[4] = f2bf(xb[rt].x); t[5] = f2bf(xb[rt].y); t[6] = f2bf(xb[rt].z); t[7] = f2bf(xb[rt].w);
+            af1[rt] = __builtin_bit_cast(bf16x8, t);
+        }
+        if (tile + gridDim.x < tiles) load_x(tile + gridDim.x);
 #pragma unroll
-                for (int i = 0; i < 8; i++) t[i] = 0;
-            }
-            const bf16x8 af = __builtin_bit_cast(bf16x8, t);
+        for (int rt = 0; rt < 4; rt++) {
 #pragma unroll
             for (int ct = 0; ct < 4; ct++) {
-                f32x4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, w1f[ct], f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+                f32x4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af1[rt], w1f[ct], f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0,
+                                                                    0);
 #pragma unroll
                 for (int i = 0; i < 4; i++) {
                     const int row = rt * 16 + (lane >> 4) * 4 + i;
