@@ -417,26 +417,44 @@ __global__ void k_shadow(const float *p, uint16_t *w1, uint16_t *w2, uint16_t *w
 }
 
 // Fused inference: y = W3^T relu(W2^T relu(W1^T x + b1) + b2) + b3 and the
-// integer estimates, for many rows.  One 256-thread block (4 waves) is
-// persistent over 64-row tiles; wave w owns hidden columns [64 w, 64 w + 64)
-// and keeps its W1 and W2 MFMA B-fragments in registers for the whole run.
-// Per tile: layer 1 (K = 32) from x straight into A-fragments, bf16 hidden
-// activations through LDS, layer 2 (K = 256) from LDS A-fragments, then the
-// two outputs as per-wave partial dot products summed in a fixed order.
+// integer estimates, for many rows.  A block of NW waves is persistent over
+// 64-row tiles; wave w owns hidden columns [w C, w C + C), C = 256 / NW, of
+// both layers and keeps their W1 and W2 MFMA B-fragments in registers for the
+// whole run.  Per tile: layer 1 (K = 32) from x straight into A-fragments,
+// bf16 hidden activations through LDS, layer 2 (K = 256) from LDS
+// A-fragments, then the two outputs as per-wave partial dot products summed
+// in a fixed order.  With NW = 8 the fragments take half the registers of
+// NW = 4, so two waves share each SIMD and one's MFMA overlaps the other's
+// conversions and LDS traffic.
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 constexpr int kRT = 64, kH1Row = kHid + 8;
 
-__global__ __launch_bounds__(256) void k_infer(const float *x, int64_t rows, const uint16_t *W1, const float *b1,
-                                               const uint16_t *W2, const float *b2, const uint16_t *W3,
-                                               const float *b3, float *Y, int32_t *est) {
+// Sum over a DPP row (16 lanes), every lane getting the total: the butterfly
+// of lane distances 1, 2, 4, 8 with register moves instead of LDS permutes
+// (quad swaps, then the half-row and row mirrors, which pair the same partial
+// sums as distances 4 and 8 once every quad, then every half-row, is uniform).
+__device__ __forceinline__ float row16_sum(float v) {
+    v += __uint_as_float(dpp32<0xB1>(__float_as_uint(v)));   // quad_perm [1,0,3,2]
+    v += __uint_as_float(dpp32<0x4E>(__float_as_uint(v)));   // quad_perm [2,3,0,1]
+    v += __uint_as_float(dpp32<0x141>(__float_as_uint(v)));  // row_half_mirror
+    v += __uint_as_float(dpp32<0x140>(__float_as_uint(v)));  // row_mirror
+    return v;
+}
+constexpr int kInferWaves = 8;
+
+template <int NW>
+__global__ __launch_bounds__(64 * NW) void k_infer(const float *x, int64_t rows, const uint16_t *W1, const float *b1,
+                                                    const uint16_t *W2, const float *b2, const uint16_t *W3,
+                                                    const float *b3, float *Y, int32_t *est) {
+    constexpr int CT = kHid / NW / 16;  // 16-column MFMA tiles per wave
     __shared__ __attribute__((aligned(16))) uint16_t H1s[kRT * kH1Row];
-    __shared__ float yp[4][kRT][2];
+    __shared__ float yp[NW][kRT][2];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int wn = wv * 64, lc = lane & 15, lk = (lane >> 4) * 8;
-    bf16x8 w1f[4], w2f[8][4];
-    float bias1[4], bias2[4], w30[4], w31[4];
+    const int wn = wv * (kHid / NW), lc = lane & 15, lk = (lane >> 4) * 8;
+    bf16x8 w1f[CT], w2f[8][CT];
+    float bias1[CT], bias2[CT], w30[CT], w31[CT];
 #pragma unroll
-    for (int ct = 0; ct < 4; ct++) {
+    for (int ct = 0; ct < CT; ct++) {
         const int n = wn + ct * 16 + lc;
         u16x8 t;
 #pragma unroll
@@ -486,7 +504,7 @@ __global__ __launch_bounds__(256) void k_infer(const float *x, int64_t rows, con
 #pragma unroll
         for (int rt = 0; rt < 4; rt++) {
 #pragma unroll
-            for (int ct = 0; ct < 4; ct++) {
+            for (int ct = 0; ct < CT; ct++) {
                 f32x4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af1[rt], w1f[ct], f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0,
                                                                     0);
 #pragma unroll
@@ -501,21 +519,21 @@ __global__ __launch_bounds__(256) void k_infer(const float *x, int64_t rows, con
         float p0[4][4], p1[4][4];
 #pragma unroll
         for (int rt = 0; rt < 4; rt++) {
-            f32x4 acc[4];
+            f32x4 acc[CT];
 #pragma unroll
-            for (int ct = 0; ct < 4; ct++) acc[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+            for (int ct = 0; ct < CT; ct++) acc[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int ks = 0; ks < 8; ks++) {
                 const bf16x8 af = *reinterpret_cast<const bf16x8 *>(&H1s[(rt * 16 + lc) * kH1Row + ks * 32 + lk]);
 #pragma unroll
-                for (int ct = 0; ct < 4; ct++)
+                for (int ct = 0; ct < CT; ct++)
                     acc[ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, w2f[ks][ct], acc[ct], 0, 0, 0);
             }
 #pragma unroll
             for (int i = 0; i < 4; i++) {
                 float s0 = 0.f, s1 = 0.f;
 #pragma unroll
-                for (int ct = 0; ct < 4; ct++) {
+                for (int ct = 0; ct < CT; ct++) {
                     const float h = bf2f(f2bf(fmaxf(acc[ct][i] + bias2[ct], 0.f)));
                     s0 += h * w30[ct];
                     s1 += h * w31[ct];
@@ -529,12 +547,7 @@ __global__ __launch_bounds__(256) void k_infer(const float *x, int64_t rows, con
         for (int rt = 0; rt < 4; rt++)
 #pragma unroll
             for (int i = 0; i < 4; i++) {
-                float s0 = p0[rt][i], s1 = p1[rt][i];
-#pragma unroll
-                for (int off = 1; off < 16; off <<= 1) {
-                    s0 += __shfl_xor(s0, off, 64);
-                    s1 += __shfl_xor(s1, off, 64);
-                }
+                const float s0 = row16_sum(p0[rt][i]), s1 = row16_sum(p1[rt][i]);
                 if (lc == 0) {
                     const int row = rt * 16 + (lane >> 4) * 4 + i;
                     yp[wv][row][0] = s0;
@@ -546,7 +559,10 @@ __global__ __launch_bounds__(256) void k_infer(const float *x, int64_t rows, con
             const int row = tid >> 1, c = tid & 1;
             const int64_t r = r0 + row;
             if (r < rows) {
-                const float y = (((yp[0][row][c] + yp[1][row][c]) + yp[2][row][c]) + yp[3][row][c]) + (c ? b31 : b30);
+                float y = yp[0][row][c];
+#pragma unroll
+                for (int w = 1; w < NW; w++) y += yp[w][row][c];
+                y += c ? b31 : b30;
                 if (Y) Y[2 * r + c] = y;
                 if (est) est[2 * r + c] = (int32_t)fminf(fmaxf(rintf(expf(y)), 1.f), (float)(1 << 20));
             }
@@ -879,7 +895,7 @@ extern "C" int insp_mlp_predict(insp_mlp *m, const float *x, int64_t n, float *y
     const int64_t tiles = (n + kRT - 1) / kRT;
     const unsigned grid = (unsigned)std::min<int64_t>(tiles, (int64_t)cus * 2);
     ProfScope ps(st, "mlp_infer");
-    hipLaunchKernelGGL(k_infer, dim3(grid), dim3(256), 0, st, x, n, m->w1.as<uint16_t>(), m->p.as<float>() + kOffB1,
+    hipLaunchKernelGGL(k_infer<kInferWaves>, dim3(grid), dim3(64 * kInferWaves), 0, st, x, n, m->w1.as<uint16_t>(), m->p.as<float>() + kOffB1,
                        m->w2.as<uint16_t>(), m->p.as<float>() + kOffB2, m->w3.as<uint16_t>(),
                        m->p.as<float>() + kOffB3, y, est);
     INSP_HIP(hipGetLastError());
