@@ -452,7 +452,7 @@ __global__ __launch_bounds__(64 * NW) void k_infer(const float *x, int64_t rows,
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int wn = wv * (kHid / NW), lc = lane & 15, lk = (lane >> 4) * 8;
     bf16x8 w1f[CT], w2f[8][CT];
-    float bias1[CT], bias2[CT], w30[CT], w31[CT];
+    float bias1[CT][4], bias2[CT], w30[CT], w31[CT];
 #pragma unroll
     for (int ct = 0; ct < CT; ct++) {
         const int n = wn + ct * 16 + lc;
@@ -466,7 +466,8 @@ __global__ __launch_bounds__(64 * NW) void k_infer(const float *x, int64_t rows,
             for (int i = 0; i < 8; i++) t[i] = W2[(ks * 32 + lk + i) * kHid + n];
             w2f[ks][ct] = __builtin_bit_cast(bf16x8, t);
         }
-        bias1[ct] = b1[n];
+#pragma unroll
+        for (int i = 0; i < 4; i++) bias1[ct][i] = b1[wn + ct * 16 + (lane >> 4) * 4 + i];
         bias2[ct] = b2[n];
         w30[ct] = bf2f(W3[n * 2]);
         w31[ct] = bf2f(W3[n * 2 + 1]);
@@ -501,17 +502,20 @@ __global__ __launch_bounds__(64 * NW) void k_infer(const float *x, int64_t rows,
             af1[rt] = __builtin_bit_cast(bf16x8, t);
         }
         if (tile + gridDim.x < tiles) load_x(tile + gridDim.x);
+        // computed transposed (W1^T as the A operand), so that a lane holds 4
+        // consecutive hidden units of one row and stores them as one 8-byte write
 #pragma unroll
         for (int rt = 0; rt < 4; rt++) {
 #pragma unroll
             for (int ct = 0; ct < CT; ct++) {
-                f32x4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af1[rt], w1f[ct], f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0,
+                f32x4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1f[ct], af1[rt], f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0,
                                                                     0);
-#pragma unroll
-                for (int i = 0; i < 4; i++) {
-                    const int row = rt * 16 + (lane >> 4) * 4 + i;
-                    H1s[row * kH1Row + wn + ct * 16 + lc] = f2bf(fmaxf(acc[i] + bias1[ct], 0.f));
-                }
+                uint2 h;
+                h.x = (uint32_t)f2bf(fmaxf(acc[0] + bias1[ct][0], 0.f)) |
+                      (uint32_t)f2bf(fmaxf(acc[1] + bias1[ct][1], 0.f)) << 16;
+                h.y = (uint32_t)f2bf(fmaxf(acc[2] + bias1[ct][2], 0.f)) |
+                      (uint32_t)f2bf(fmaxf(acc[3] + bias1[ct][3], 0.f)) << 16;
+                *reinterpret_cast<uint2 *>(&H1s[(rt * 16 + lc) * kH1Row + wn + ct * 16 + (lane >> 4) * 4]) = h;
             }
         }
         __syncthreads();
