@@ -150,6 +150,8 @@ typedef struct {
  * INSP_E_INVAL for a non-monotone row pointer, an id out of range or a self
  * loop; INSP_E_CYCLE for a cycle; INSP_E_RANGE for n_b > 2^21.  The call
  * synchronises `stream` to report these.  The caller keeps its buffers.
+ * The handle lives on the device current at this call; the calls that take
+ * it make that device current before they launch.
  */
 int insp_build_dag(int32_t n_dags, const int64_t *task_off, const int64_t *edge_off, const int32_t *row_ptr,
                    const int32_t *col, const int32_t *type, void *stream, insp_dag **out);
@@ -317,9 +319,11 @@ int insp_profile_read(const char *kernel, double *total_ms, int64_t *launches);
  *   insp_mlp_state      copy parameters, Adam moments and step count to the
  *                       host (to_host = 1) or from it (to_host = 0), for
  *                       checkpoint and resume; any pointer may be NULL
- * batch must be a positive multiple of 32.  Work runs on `stream`.  Calls on
- * one model share its buffers and must not overlap; insp_mlp_free waits for
- * the device before it releases them.
+ * batch must be a positive multiple of 32.  Work runs on `stream`.  The
+ * model lives on the device current at insp_mlp_create, and grads,
+ * train_step, train and predict fail with INSP_E_INVAL when another device
+ * is current.  Calls on one model share its buffers and must not overlap;
+ * insp_mlp_free waits for the device before it releases them.
  */
 #define INSP_MLP_PARAMS 74754
 typedef struct insp_mlp insp_mlp;

@@ -773,11 +773,21 @@ extern "C" int insp_mlp_create(const float *params, insp_mlp **out) {
 
 extern "C" void insp_mlp_free(insp_mlp *m) { delete m; }
 
+// The model's buffers live on the device that was current at create: work
+// for it must be launched there.
+static int check_device(const insp_mlp *m) {
+    int dev = -1;
+    INSP_HIP(hipGetDevice(&dev));
+    if (dev != m->device) return set_error(INSP_E_INVAL, "the current device is not the model's device");
+    return INSP_OK;
+}
+
 extern "C" int insp_mlp_grads(insp_mlp *m, const float *x, const float *t, int32_t batch, float *grads, float *y,
                               float *loss, void *stream) {
     if (!m || !x || !t || batch < 1 || batch % 32) return set_error(INSP_E_INVAL, "bad argument");
     hipStream_t st = (hipStream_t)stream;
     int rc;
+    if ((rc = check_device(m))) return rc;
     if ((rc = mlp_reserve(m, batch)) || (rc = mlp_backward(m, x, t, batch, st))) return rc;
     if (grads) INSP_HIP(hipMemcpyAsync(grads, m->g.p, 4 * kParams, hipMemcpyDeviceToDevice, st));
     if (y) INSP_HIP(hipMemcpyAsync(y, m->y.p, 4 * kOut * (size_t)batch, hipMemcpyDeviceToDevice, st));
@@ -790,6 +800,7 @@ extern "C" int insp_mlp_train_step(insp_mlp *m, const float *x, const float *t, 
     if (!m || !x || !t || batch < 1 || batch % 32 || !(lr > 0.f)) return set_error(INSP_E_INVAL, "bad argument");
     hipStream_t st = (hipStream_t)stream;
     int rc;
+    if ((rc = check_device(m))) return rc;
     if ((rc = mlp_reserve(m, batch)) || (rc = mlp_backward(m, x, t, batch, st))) return rc;
     m->step++;
     const float bc1 = 1.f - powf(0.9f, (float)m->step), bc2 = 1.f - powf(0.999f, (float)m->step);
@@ -852,6 +863,7 @@ extern "C" int insp_mlp_train(insp_mlp *m, const float *x, const float *t, int64
     hipStream_t st = (hipStream_t)stream;
     const int64_t words = 1 + 2 * total;
     int rc;
+    if ((rc = check_device(m))) return rc;
     if (m->cap < batch || m->tab.bytes < (size_t)(4 * words)) {
         INSP_HIP(hipStreamSynchronize(st));  // earlier work on the stream may still read the old buffers
         if ((rc = mlp_reserve(m, batch))) return rc;
@@ -890,6 +902,7 @@ extern "C" int insp_mlp_train(insp_mlp *m, const float *x, const float *t, int64
 extern "C" int insp_mlp_predict(insp_mlp *m, const float *x, int64_t n, float *y, int32_t *est, void *stream) {
     if (!m || (n > 0 && (!x || (!y && !est))) || n < 0) return set_error(INSP_E_INVAL, "bad argument");
     if (n == 0) return INSP_OK;
+    if (int rc = check_device(m)) return rc;
     hipStream_t st = (hipStream_t)stream;
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) == hipSuccess) {
