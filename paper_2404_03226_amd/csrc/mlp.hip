@@ -420,8 +420,8 @@ __global__ void k_shadow(const float *p, uint16_t *w1, uint16_t *w2, uint16_t *w
 // integer estimates, for many rows.  A block of NW waves is persistent over
 // 64-row tiles; wave w owns hidden columns [w C, w C + C), C = 256 / NW, of
 // both layers and keeps their W1 and W2 MFMA B-fragments in registers for the
-// whole run.  Per tile: layer 1 (K = 32) from x straight into A-fragments,
-// bf16 hidden activations through LDS, layer 2 (K = 256) from LDS
+// whole run.  Per tile: layer 1 (K = 32) from x straight into MFMA
+// fragments, bf16 hidden activations through LDS, layer 2 (K = 256) from LDS
 // A-fragments, then the two outputs as per-wave partial dot products summed
 // in a fixed order.  With NW = 8 the fragments take half the registers of
 // NW = 4, so two waves share each SIMD and one's MFMA overlaps the other's
