@@ -85,6 +85,33 @@ def test_predict_matches_reference_and_rounds(insp):
     m.free()
 
 
+def test_predict_full_batch_sampled(insp):
+    """Prediction at the size the benchmark times (one row per task of the
+    4096-DAG batch: 17,723,451 rows, so a ragged last tile) in the same
+    launch, with nonzero biases; sampled rows, the first tile and the tail
+    against the FP64 reference, estimates by the same rounding rule."""
+    import torch
+    n = 17_723_451
+    print(f"[case] mlp predict full batch n={n}", flush=True)
+    rng = np.random.default_rng(11)
+    X = synth.cost_features(5, 7, rng.integers(0, 4, n).astype(np.int32))
+    p = synth.mlp_init()
+    for i in (1, 3, 5):
+        p[i] = rng.normal(0.0, 0.1, p[i].shape).astype(np.float32)
+    m = insp.Mlp(p)
+    y, est = m.predict(torch.from_numpy(X).cuda())
+    idx = np.unique(np.concatenate([rng.integers(0, n, 4000), np.arange(64), np.arange(n - 100, n)]))
+    sel = torch.from_numpy(idx).cuda()
+    y, est = y[sel].cpu().numpy(), est[sel].cpu().numpy()
+    ref = mlp.forward(p, X[idx], bf=True)["Y"]
+    assert rel(y, ref) <= 1e-3
+    e = np.exp(y.astype(np.float32))
+    ok = np.abs(e - np.floor(e) - 0.5) > 1e-3 * np.maximum(e, 1.0)
+    want = np.clip(np.rint(e), 1, 1 << 20).astype(np.int32)
+    assert np.array_equal(est[ok], want[ok])
+    m.free()
+
+
 def test_training_beats_the_per_type_table(insp):
     import torch
     print("[case] mlp training", flush=True)
