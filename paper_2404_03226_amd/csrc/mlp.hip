@@ -422,24 +422,15 @@ __global__ void k_shadow(const float *p, uint16_t *w1, uint16_t *w2, uint16_t *w
 // both layers and keeps their W1 and W2 MFMA B-fragments in registers for the
 // whole run.  Per tile: layer 1 (K = 32) from x straight into MFMA
 // fragments, bf16 hidden activations through LDS, layer 2 (K = 256) from LDS
-// A-fragments, then the two outputs as per-wave partial dot products summed
-// in a fixed order.  With NW = 8 the fragments take half the registers of
+// fragments, then the two outputs as per-wave partial dot products summed in
+// a fixed order.  Both layers are computed transposed (weights as the A
+// operand), so that a lane's accumulator holds consecutive hidden units of
+// one row.  With NW = 8 the fragments take half the registers of
 // NW = 4, so two waves share each SIMD and one's MFMA overlaps the other's
 // conversions and LDS traffic.
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 constexpr int kRT = 64, kH1Row = kHid + 8;
 
-// Sum over a DPP row (16 lanes), every lane getting the total: the butterfly
-// of lane distances 1, 2, 4, 8 with register moves instead of LDS permutes
-// (quad swaps, then the half-row and row mirrors, which pair the same partial
-// sums as distances 4 and 8 once every quad, then every half-row, is uniform).
-__device__ __forceinline__ float row16_sum(float v) {
-    v += __uint_as_float(dpp32<0xB1>(__float_as_uint(v)));   // quad_perm [1,0,3,2]
-    v += __uint_as_float(dpp32<0x4E>(__float_as_uint(v)));   // quad_perm [2,3,0,1]
-    v += __uint_as_float(dpp32<0x141>(__float_as_uint(v)));  // row_half_mirror
-    v += __uint_as_float(dpp32<0x140>(__float_as_uint(v)));  // row_mirror
-    return v;
-}
 constexpr int kInferWaves = 8;
 
 template <int NW>
@@ -452,7 +443,7 @@ __global__ __launch_bounds__(64 * NW) void k_infer(const float *x, int64_t rows,
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int wn = wv * (kHid / NW), lc = lane & 15, lk = (lane >> 4) * 8;
     bf16x8 w1f[CT], w2f[8][CT];
-    float bias1[CT][4], bias2[CT], w30[CT], w31[CT];
+    float bias1[CT][4], bias2[CT][4], w30[CT][4], w31[CT][4];
 #pragma unroll
     for (int ct = 0; ct < CT; ct++) {
         const int n = wn + ct * 16 + lc;
@@ -467,10 +458,14 @@ __global__ __launch_bounds__(64 * NW) void k_infer(const float *x, int64_t rows,
             w2f[ks][ct] = __builtin_bit_cast(bf16x8, t);
         }
 #pragma unroll
-        for (int i = 0; i < 4; i++) bias1[ct][i] = b1[wn + ct * 16 + (lane >> 4) * 4 + i];
-        bias2[ct] = b2[n];
-        w30[ct] = bf2f(W3[n * 2]);
-        w31[ct] = bf2f(W3[n * 2 + 1]);
+        for (int i = 0; i < 4; i++) {
+            // the hidden unit this lane's accumulator value i holds in either layer
+            const int h = wn + ct * 16 + (lane >> 4) * 4 + i;
+            bias1[ct][i] = b1[h];
+            bias2[ct][i] = b2[h];
+            w30[ct][i] = bf2f(W3[h * 2]);
+            w31[ct][i] = bf2f(W3[h * 2 + 1]);
+        }
     }
     const float b30 = b3[0], b31 = b3[1];
     const int64_t tiles = (rows + kRT - 1) / kRT;
@@ -519,8 +514,10 @@ __global__ __launch_bounds__(64 * NW) void k_infer(const float *x, int64_t rows,
             }
         }
         __syncthreads();
-        // layer 2 and the output partials
-        float p0[4][4], p1[4][4];
+        // layer 2, transposed as well: per 16-column tile a lane holds 4
+        // consecutive hidden units of row rt * 16 + lc, so its output partials
+        // cover 4 CT units and only the 4 lane groups of a row remain to be added
+        float p0[4], p1[4];
 #pragma unroll
         for (int rt = 0; rt < 4; rt++) {
             f32x4 acc[CT];
@@ -528,36 +525,36 @@ __global__ __launch_bounds__(64 * NW) void k_infer(const float *x, int64_t rows,
             for (int ct = 0; ct < CT; ct++) acc[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int ks = 0; ks < 8; ks++) {
-                const bf16x8 af = *reinterpret_cast<const bf16x8 *>(&H1s[(rt * 16 + lc) * kH1Row + ks * 32 + lk]);
+                const bf16x8 hf = *reinterpret_cast<const bf16x8 *>(&H1s[(rt * 16 + lc) * kH1Row + ks * 32 + lk]);
 #pragma unroll
                 for (int ct = 0; ct < CT; ct++)
-                    acc[ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, w2f[ks][ct], acc[ct], 0, 0, 0);
+                    acc[ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w2f[ks][ct], hf, acc[ct], 0, 0, 0);
             }
+            float s0 = 0.f, s1 = 0.f;
 #pragma unroll
-            for (int i = 0; i < 4; i++) {
-                float s0 = 0.f, s1 = 0.f;
+            for (int ct = 0; ct < CT; ct++)
 #pragma unroll
-                for (int ct = 0; ct < CT; ct++) {
-                    const float h = bf2f(f2bf(fmaxf(acc[ct][i] + bias2[ct], 0.f)));
-                    s0 += h * w30[ct];
-                    s1 += h * w31[ct];
+                for (int i = 0; i < 4; i++) {
+                    const float h = bf2f(f2bf(fmaxf(acc[ct][i] + bias2[ct][i], 0.f)));
+                    s0 += h * w30[ct][i];
+                    s1 += h * w31[ct][i];
                 }
-                p0[rt][i] = s0;
-                p1[rt][i] = s1;
+            p0[rt] = s0;
+            p1[rt] = s1;
+        }
+        // lanes lc, lc + 16, lc + 32, lc + 48 hold the same row
+#pragma unroll
+        for (int rt = 0; rt < 4; rt++) {
+            float s0 = p0[rt], s1 = p1[rt];
+            s0 += __shfl_xor(s0, 16, 64);
+            s1 += __shfl_xor(s1, 16, 64);
+            s0 += __shfl_xor(s0, 32, 64);
+            s1 += __shfl_xor(s1, 32, 64);
+            if (lane < 16) {
+                yp[wv][rt * 16 + lc][0] = s0;
+                yp[wv][rt * 16 + lc][1] = s1;
             }
         }
-        // sum over the 16 lanes sharing a row (different columns)
-#pragma unroll
-        for (int rt = 0; rt < 4; rt++)
-#pragma unroll
-            for (int i = 0; i < 4; i++) {
-                const float s0 = row16_sum(p0[rt][i]), s1 = row16_sum(p1[rt][i]);
-                if (lc == 0) {
-                    const int row = rt * 16 + (lane >> 4) * 4 + i;
-                    yp[wv][row][0] = s0;
-                    yp[wv][row][1] = s1;
-                }
-            }
         __syncthreads();
         if (tid < kRT * 2) {
             const int row = tid >> 1, c = tid & 1;
