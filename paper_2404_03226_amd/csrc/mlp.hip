@@ -33,8 +33,14 @@ static_assert(kParams == 74754, "parameter count");
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-// fp32 -> bf16, round to nearest even (one v_cvt_pk_bf16_f32 on gfx950)
+// fp32 -> bf16, round to nearest even (v_cvt_pk_bf16_f32 on gfx950); f2bf2
+// converts two values with one instruction, a in the low half
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
+__device__ __forceinline__ uint32_t f2bf2(float a, float b) {
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2_t{a, b}, bf16x2_t));
+}
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
 // ------------------------------------------------------------------ GEMM
@@ -491,9 +497,8 @@ __global__ __launch_bounds__(64 * NW) void k_infer(const float *x, int64_t rows,
         bf16x8 af1[4];
 #pragma unroll
         for (int rt = 0; rt < 4; rt++) {
-            u16x8 t;
-            t[0] = f2bf(xa[rt].x); t[1] = f2bf(xa[rt].y); t[2] = f2bf(xa[rt].z); t[3] = f2bf(xa[rt].w);
-            t[4] = f2bf(xb[rt].x); t[5] = f2bf(xb[rt].y); t[6] = f2bf(xb[rt].z); t[7] = f2bf(xb[rt].w);
+            const uint4 t = {f2bf2(xa[rt].x, xa[rt].y), f2bf2(xa[rt].z, xa[rt].w), f2bf2(xb[rt].x, xb[rt].y),
+                             f2bf2(xb[rt].z, xb[rt].w)};
             af1[rt] = __builtin_bit_cast(bf16x8, t);
         }
         if (tile + gridDim.x < tiles) load_x(tile + gridDim.x);
@@ -506,10 +511,8 @@ __global__ __launch_bounds__(64 * NW) void k_infer(const float *x, int64_t rows,
                 f32x4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1f[ct], af1[rt], f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0,
                                                                     0);
                 uint2 h;
-                h.x = (uint32_t)f2bf(fmaxf(acc[0] + bias1[ct][0], 0.f)) |
-                      (uint32_t)f2bf(fmaxf(acc[1] + bias1[ct][1], 0.f)) << 16;
-                h.y = (uint32_t)f2bf(fmaxf(acc[2] + bias1[ct][2], 0.f)) |
-                      (uint32_t)f2bf(fmaxf(acc[3] + bias1[ct][3], 0.f)) << 16;
+                h.x = f2bf2(fmaxf(acc[0] + bias1[ct][0], 0.f), fmaxf(acc[1] + bias1[ct][1], 0.f));
+                h.y = f2bf2(fmaxf(acc[2] + bias1[ct][2], 0.f), fmaxf(acc[3] + bias1[ct][3], 0.f));
                 *reinterpret_cast<uint2 *>(&H1s[(rt * 16 + lc) * kH1Row + wn + ct * 16 + (lane >> 4) * 4]) = h;
             }
         }
@@ -534,10 +537,15 @@ __global__ __launch_bounds__(64 * NW) void k_infer(const float *x, int64_t rows,
 #pragma unroll
             for (int ct = 0; ct < CT; ct++)
 #pragma unroll
-                for (int i = 0; i < 4; i++) {
-                    const float h = bf2f(f2bf(fmaxf(acc[ct][i] + bias2[ct][i], 0.f)));
-                    s0 += h * w30[ct][i];
-                    s1 += h * w31[ct][i];
+                for (int i = 0; i < 4; i += 2) {
+                    // the bf16 rounding of H2, two units per conversion
+                    const uint32_t q = f2bf2(fmaxf(acc[ct][i] + bias2[ct][i], 0.f),
+                                             fmaxf(acc[ct][i + 1] + bias2[ct][i + 1], 0.f));
+                    const float h0 = __uint_as_float(q << 16), h1 = __uint_as_float(q & 0xFFFF0000u);
+                    s0 += h0 * w30[ct][i];
+                    s1 += h0 * w31[ct][i];
+                    s0 += h1 * w30[ct][i + 1];
+                    s1 += h1 * w31[ct][i + 1];
                 }
             p0[rt] = s0;
             p1[rt] = s1;
