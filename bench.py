@@ -28,6 +28,7 @@ METRIC = "tasks scheduled/s on 4096-DAG batch, bit-exact makespan; learned vs pl
 TILE_KIB = 3600
 TILE_BW = 61440
 HBM_PEAK_GBS = 8000.0
+BF16_PEAK_TFLOPS = 2500.0  # dense bf16 MFMA
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_batch4096.txt")
 SIM_SOURCES = [os.path.join(ROOT, "paper_2404_03226_amd", "csrc", f) for f in ("sim.hip", "common.hpp", "internal.hpp")]
 # Algorithmic bytes of the simulation kernel: per task, the
@@ -466,6 +467,9 @@ def learned_gap(dag, workers, b, epochs):
                  "predict_tasks_per_s": round(len(b.type) / (pred_ms * 1e-3), 1),
                  "predict_TFLOPs": round(148480 * len(b.type) / (pred_ms * 1e-3) / 1e12, 2),
                  "train_TFLOPs": round(445440 * 1024 * steps / (train_ms * 1e-3) / 1e12, 2)})
+    # fractions of MI355X's dense bf16 MFMA peak (2.5 PFLOP/s)
+    gaps["predict_frac_bf16_peak"] = round(gaps["predict_TFLOPs"] / BF16_PEAK_TFLOPS, 4)
+    gaps["train_frac_bf16_peak"] = round(gaps["train_TFLOPs"] / BF16_PEAK_TFLOPS, 4)
     mlp.free()
     log(f"learned gap: {gaps}")
     return gaps
