@@ -85,6 +85,30 @@ def test_predict_matches_reference_and_rounds(insp):
     m.free()
 
 
+@pytest.mark.parametrize("n", [0, 1, 63, 64, 65])
+def test_predict_small_and_empty(insp, n):
+    """Fewer rows than one 64-row tile, exactly one, one plus a row, and none:
+    most persistent blocks get no tile; every row against the FP64 reference."""
+    import torch
+    print(f"[case] mlp predict n={n}", flush=True)
+    rng = np.random.default_rng(13)
+    p = synth.mlp_init()
+    for i in (1, 3, 5):
+        p[i] = rng.normal(0.0, 0.1, p[i].shape).astype(np.float32)
+    X, _ = batch(max(n, 1))
+    X = X[:n]
+    m = insp.Mlp(p)
+    y, est = m.predict(torch.from_numpy(np.ascontiguousarray(X)).cuda())
+    assert y.shape == (n, 2) and est.shape == (n, 2)
+    if n:
+        y, est = y.cpu().numpy(), est.cpu().numpy()
+        assert rel(y, mlp.forward(p, X, bf=True)["Y"]) <= 1e-3
+        e = np.exp(y.astype(np.float32))
+        ok = np.abs(e - np.floor(e) - 0.5) > 1e-3 * np.maximum(e, 1.0)
+        assert np.array_equal(est[ok], np.clip(np.rint(e), 1, 1 << 20).astype(np.int32)[ok])
+    m.free()
+
+
 def test_predict_full_batch_sampled(insp):
     """Prediction at the size the benchmark times (one row per task of the
     4096-DAG batch: 17,723,451 rows, so a ragged last tile) in the same
