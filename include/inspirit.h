@@ -315,7 +315,8 @@ int insp_profile_read(const char *kernel, double *total_ms, int64_t *launches);
  *                       `stream` once, at the start, while it uploads the
  *                       step table.
  *   insp_mlp_predict    y = network(x) for n rows and/or integer estimates
- *                       est = clamp(rint(exp(y)), 1, 2^20), int32 [n][2]
+ *                       est = clamp(rint(exp(y)), 1, 2^20), int32 [n][2];
+ *                       x must be 16-byte aligned (INSP_E_INVAL otherwise)
  *   insp_mlp_state      copy parameters, Adam moments and step count to the
  *                       host (to_host = 1) or from it (to_host = 0), for
  *                       checkpoint and resume; any pointer may be NULL

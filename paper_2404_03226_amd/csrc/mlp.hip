@@ -907,6 +907,8 @@ extern "C" int insp_mlp_train(insp_mlp *m, const float *x, const float *t, int64
 extern "C" int insp_mlp_predict(insp_mlp *m, const float *x, int64_t n, float *y, int32_t *est, void *stream) {
     if (!m || (n > 0 && (!x || (!y && !est))) || n < 0) return set_error(INSP_E_INVAL, "bad argument");
     if (n == 0) return INSP_OK;
+    // the features are read 16 bytes at a time
+    if ((uintptr_t)x & 15) return set_error(INSP_E_INVAL, "x must be 16-byte aligned");
     if (int rc = check_device(m)) return rc;
     hipStream_t st = (hipStream_t)stream;
     int dev = 0, cus = 256;

@@ -100,6 +100,11 @@ def test_predict_small_and_empty(insp, n):
     m = insp.Mlp(p)
     y, est = m.predict(torch.from_numpy(np.ascontiguousarray(X)).cuda())
     assert y.shape == (n, 2) and est.shape == (n, 2)
+    if n == 1:
+        # features at a 4-byte offset are refused, not read misaligned
+        buf = torch.zeros(33, dtype=torch.float32, device="cuda")
+        with pytest.raises(insp.InspError, match="aligned"):
+            m.predict(buf[1:].view(1, 32))
     if n:
         y, est = y.cpu().numpy(), est.cpu().numpy()
         assert rel(y, mlp.forward(p, X, bf=True)["Y"]) <= 1e-3
