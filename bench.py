@@ -459,8 +459,7 @@ def learned_gap(dag, workers, b, epochs):
         torch.cuda.synchronize()
         pred_ms = min(pred_ms, ev0.elapsed_time(ev1))
     del xd
-    ms = costmodel.evaluate(dag, workers, b.type, ticks, est_mlp, table,
-                            lambda d, w, du, es: inspirit.schedule_batch(d, w, du, es))
+    ms = costmodel.evaluate(dag, workers, b.type, ticks, est_mlp, table)
     gaps = costmodel.makespan_gaps(ms["true"], ms["plain"], ms["learned"])
     gaps.update({"val_mse_ln_mlp": mse_mlp, "val_mse_ln_table": mse_tab, "train_steps": steps,
                  "train_s": round(train_ms / 1e3, 2), "predict_ms": round(pred_ms, 2),

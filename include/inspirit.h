@@ -257,10 +257,13 @@ int insp_schedule(const insp_dag *dag, int32_t index, const insp_workers *worker
  * persistent launch (workgroups take DAGs, largest first, from an atomic
  * counter).  Arrays are indexed by the global task id (task_off of the
  * handle); makespan is [B].  workers is host [B].  tune_key selects a
- * launch configuration: NULL = the tuned default for this device, or a
- * string "waves=<k>,grid=<g>" (k = waves per workgroup, g = workgroups);
- * results never depend on it.  The first call with a new machine shape
- * allocates workspace; later calls reuse it.
+ * launch configuration: NULL = the library's default for this device, or a
+ * comma-separated string of "grid=<g>" (persistent work-groups, each one
+ * wave simulating one DAG at a time), "lds_blocks=<b>" (queue blocks per DAG
+ * whose maxima live in LDS, <= 8192), "lds_slots=<s>" (queue blocks per DAG
+ * whose entries live in LDS) and "waves=1" (the only accepted value; any
+ * other is INSP_E_INVAL).  Results never depend on it.  The first call with
+ * a new machine shape allocates workspace; later calls reuse it.
  */
 int insp_schedule_batch(const insp_dag *dag, const insp_workers *workers, const int32_t *dur, const int32_t *est,
                         const insp_params *params, int32_t *worker, int64_t *start, int64_t *finish,
@@ -268,8 +271,17 @@ int insp_schedule_batch(const insp_dag *dag, const insp_workers *workers, const 
                         void *stream);
 
 /* Synchronise `stream` and report a device-side failure of the schedule
- * calls enqueued on the handle since the last check: INSP_E_HANG, or
- * INSP_E_RANGE for a tick value out of range or a HEFT rank >= 2^42. */
+ * calls (insp_schedule, insp_schedule_batch) enqueued on the handle since the
+ * last check: INSP_E_HANG, or INSP_E_RANGE for a tick value out of range, a
+ * HEFT rank >= 2^42, a longest path >= 2^30 under transitive attributes or
+ * input transfers above 2^20 ticks.  Failures are kept across later schedule
+ * calls until this call reports them (the first one found is returned, and
+ * all are cleared).  A DAG that failed before its simulation started (an
+ * estimate, HEFT rank or longest path out of range) has makespan -1 and its
+ * other outputs untouched; one that hung has makespan -1 and its other
+ * outputs unspecified, as are the outputs of a DAG with a duration or a
+ * transfer out of range.  The standalone attribute calls report their own
+ * failures and do not affect this one. */
 int insp_sync_status(const insp_dag *dag, void *stream);
 
 /*
@@ -341,6 +353,15 @@ int insp_mlp_state(insp_mlp *m, float *params, float *adam_m, float *adam_v, int
 
 /* Thread-local description of the last non-OK status. */
 const char *insp_last_error(void);
+
+/*
+ * Testing hook for the allocation-failure paths: after `after` more device
+ * allocations made by the library succeed, the next one fails as if the
+ * device were out of memory (the call making it returns INSP_E_NOMEM), and
+ * injection then stops.  -1 turns injection off.  Process-wide; INSP_E_INVAL
+ * for after < -1.
+ */
+int insp_test_fail_alloc(int64_t after);
 
 #ifdef __cplusplus
 }

@@ -77,6 +77,24 @@ def adam(params, grads, m, v, step, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
     return out_p, out_m, out_v
 
 
+def train(params, X, T, batch=1024, epochs=1, lr=1e-3, bf=True):
+    """Minibatch training in order: `epochs` passes over the rows of X, T in
+    consecutive minibatches of `batch` rows (a last partial minibatch is not
+    used), one Adam step per minibatch on the float64 master parameters, the
+    network evaluated with bfloat16 stores when `bf`.  Returns (params, steps)."""
+    p = [np.asarray(q, np.float64).copy() for q in params]
+    m = [np.zeros_like(q) for q in p]
+    v = [np.zeros_like(q) for q in p]
+    step = 0
+    n = X.shape[0]
+    for _ in range(epochs):
+        for i in range(0, n - batch + 1, batch):
+            _, g, _ = loss_grads(p, X[i:i + batch], T[i:i + batch], bf)
+            step += 1
+            p, m, v = adam(p, g, m, v, step, lr=lr)
+    return p, step
+
+
 def ticks_from_log(y):
     """Integer estimates clamp(rint(exp(y)), 1, 2^20), ties to even."""
     return np.clip(np.rint(np.exp(np.asarray(y, np.float64))), 1, 1 << 20).astype(np.int32)

@@ -30,7 +30,7 @@ def signature(dag, workers, prm) -> str:
 
 def candidates(n_dags, cus):
     grids = sorted({min(n_dags, cus * k) for k in (4, 6, 8)})
-    return [f"waves=1,grid={g},lds_blocks=256,lds_slots={s}" for g in grids for s in (8, 16, 24)]
+    return [f"grid={g},lds_blocks=256,lds_slots={s}" for g in grids for s in (8, 16, 24)]
 
 
 def tune(dag, workers, dur, est, prm, out, reps=2, use_cache=True, verbose=False) -> str:

@@ -33,14 +33,27 @@ def makespan_gaps(m_true, m_plain, m_learned):
             "frac_worse": float((gl > gp).mean())}
 
 
-def evaluate(dag, workers, b_type, true_ticks, est_mlp, table, schedule_fn):
+def evaluate(dag, workers, b_type, true_ticks, est_mlp, table, tune_key=None, keep_schedules=False):
     """Three batch runs on the same DAGs, all advancing with the true ticks:
-    est = true ticks, est = table[type], est = the MLP's estimates."""
+    est = true ticks, est = table[type], est = the MLP's estimates.  Each run's
+    device status is checked (a failed DAG raises instead of entering the
+    gaps with makespan -1).  Returns the makespans per run, and with
+    `keep_schedules` also each run's host copy of the schedule."""
     import torch
+    from . import inspirit
     dev = est_mlp.device
     dur = torch.from_numpy(np.ascontiguousarray(true_ticks, np.int32)).to(dev)
     est_tab = torch.from_numpy(np.ascontiguousarray(table[b_type], np.int32)).to(dev)
-    out = {}
+    out, scheds = {}, {}
     for name, est in (("true", dur), ("plain", est_tab), ("learned", est_mlp)):
-        out[name] = schedule_fn(dag, workers, dur, est)["makespan"].cpu().numpy().copy()
-    return out
+        o = inspirit.schedule_batch(dag, workers, dur, est, tune_key=tune_key)
+        inspirit.sync_status(dag)
+        ms = o["makespan"].cpu().numpy().copy()
+        if (ms < 0).any():
+            raise RuntimeError(f"cost-model evaluation: {int((ms < 0).sum())} DAGs failed in the '{name}' run")
+        out[name] = ms
+        if keep_schedules:
+            n = int(dag.task_off[-1])
+            scheds[name] = {k: o[k][:n].cpu().numpy() for k in ("worker", "start", "finish")}
+            scheds[name]["makespan"] = ms
+    return (out, scheds) if keep_schedules else out

@@ -45,12 +45,16 @@ struct AttrArgs {
     const int32_t *est, *rem;   // user arrays, indexed relative to `base`
     int64_t base;
     int32_t unit_time;
-    int32_t *maxtau, *score, *u, *taubar, *stat;
+    int32_t *maxtau, *score, *u, *taubar;
+    int32_t *stat;    // this call's status words (stride 2)
+    int32_t *sticky;  // schedule calls: failures of earlier calls kept for insp_sync_status (nullable)
+    int32_t *anybad;  // [1]: some DAG of the call has an estimate out of range
     unsigned long long *tausum;
 };
 
 __global__ void k_attr_clear(AttrArgs a, int32_t count) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) *a.anybad = 0;
     if (i >= count * kRungs) return;
     int32_t id = a.desc[i / kRungs].id;
     int j = i % kRungs;
@@ -58,6 +62,9 @@ __global__ void k_attr_clear(AttrArgs a, int32_t count) {
     if (j == 0) {
         a.maxtau[id] = 0;
         a.tausum[id] = 0;
+        // a schedule call keeps the previous call's failures until they are
+        // reported: they move to the sticky word before the status restarts
+        if (a.sticky) a.sticky[id] |= a.stat[2 * id];
         a.stat[2 * id] = 0;
     }
 }
@@ -123,7 +130,10 @@ __global__ __launch_bounds__(kAttrThreads) void k_attr_a(AttrArgs a) {
         }
         atomicMax(&a.maxtau[d.id], (int32_t)bm2);
         atomicAdd(&a.tausum[d.id], bs);
-        if (bad) atomicOr(&a.stat[2 * d.id], 1);
+        if (bad) {
+            atomicOr(&a.stat[2 * d.id], ST_EST);
+            *a.anybad = 1;
+        }
     }
 }
 
@@ -160,6 +170,19 @@ __global__ __launch_bounds__(kAttrThreads) void k_attr_b(AttrArgs a, AttrOut o) 
     const DagDesc d = a.desc[bm.x];
     const int32_t lv = bm.y * kAttrThreads + threadIdx.x;
     if (lv >= d.n) return;
+    // an estimate out of range fails the call: an attribute-only call then
+    // writes no output at all; a schedule does not simulate that DAG, whose
+    // records are marked unscheduled so that no stale schedule reaches the
+    // caller's arrays
+    if (o.sim_init ? (a.stat[2 * d.id] & ST_EST) != 0 : *a.anybad != 0) {
+        if (o.sim_init) {
+            TaskRec rec;
+            memset(&rec, 0, sizeof rec);
+            rec.qpos = -1;
+            o.tr[d.toff + lv] = rec;
+        }
+        return;
+    }
     const int g = d.n_gpu > 0 ? 1 : 0;
     const int32_t *r = a.rp + d.toff + d.id;
     const int32_t *c = a.col + d.eoff;
@@ -205,6 +228,8 @@ static AttrArgs make_args(insp_dag *dag, Workspace *ws, const int32_t *est, int3
     a.u = dag->dag_u.as<int32_t>();
     a.taubar = dag->dag_taubar.as<int32_t>();
     a.stat = dag->dag_stat.as<int32_t>();
+    a.sticky = dag->dag_sticky.as<int32_t>();
+    a.anybad = ws->counter.as<int32_t>() + 3;
     a.tausum = dag->dag_tausum.as<unsigned long long>();
     return a;
 }
@@ -212,6 +237,12 @@ static AttrArgs make_args(insp_dag *dag, Workspace *ws, const int32_t *est, int3
 int run_attributes(insp_dag *dag, Workspace *ws, const int32_t *est, int32_t unit_time, const int32_t *rem,
                    int32_t *ia_out, int32_t *ie_out, bool sim_init, hipStream_t st) {
     AttrArgs a = make_args(dag, ws, est, unit_time, rem);
+    if (!sim_init) {
+        // an attribute-only call has status words of its own: it neither
+        // clears nor reports a schedule's pending failures
+        a.stat = dag->dag_astat.as<int32_t>();
+        a.sticky = nullptr;
+    }
     hipLaunchKernelGGL(k_attr_clear, dim3((ws->count * kRungs + 255) / 256), dim3(256), 0, st, a, ws->count);
     if (ws->attr_blocks > 0) {
         ProfScope ps(st, "attr_a");
@@ -243,10 +274,14 @@ int ensure_state(insp_dag *dag, hipStream_t st) {
         (rc = dag->dag_u.alloc(4 * dag->B)) ||
         (rc = dag->dag_taubar.alloc(4 * dag->B)) || (rc = dag->dag_maxtau.alloc(4 * dag->B)) ||
         (rc = dag->dag_tausum.alloc(8 * dag->B)) || (rc = dag->dag_score.alloc(4 * kRungs * dag->B)) ||
-        (rc = dag->dag_stat.alloc(8 * dag->B))) {
+        (rc = dag->dag_stat.alloc(8 * dag->B)) || (rc = dag->dag_astat.alloc(8 * dag->B)) ||
+        (rc = dag->dag_sticky.alloc(4 * dag->B))) {
         dag->tr.release();
         return rc;
     }
+    INSP_HIP(hipMemset(dag->dag_stat.p, 0, 8 * dag->B));
+    INSP_HIP(hipMemset(dag->dag_astat.p, 0, 8 * dag->B));
+    INSP_HIP(hipMemset(dag->dag_sticky.p, 0, 4 * dag->B));
     return INSP_OK;
 }
 
@@ -349,12 +384,13 @@ extern "C" int insp_attributes(const insp_dag *cdag, int32_t index, const int32_
     Workspace *ws;
     if ((rc = get_workspace(dag, first, count, workers, true, &ws))) return rc;
     if ((rc = run_attributes(dag, ws, est, unit_time, rem, ia, ie, false, st))) return rc;
-    std::vector<int32_t> stat(2 * dag->B);
-    INSP_HIP(hipMemcpyAsync(unit_time_used, dag->dag_u.as<int32_t>() + first, sizeof(int32_t) * count,
+    std::vector<int32_t> stat(2 * dag->B), uu(count);
+    INSP_HIP(hipMemcpyAsync(uu.data(), dag->dag_u.as<int32_t>() + first, sizeof(int32_t) * count,
                             hipMemcpyDeviceToHost, st));
-    INSP_HIP(hipMemcpyAsync(stat.data(), dag->dag_stat.p, sizeof(int32_t) * 2 * dag->B, hipMemcpyDeviceToHost, st));
+    INSP_HIP(hipMemcpyAsync(stat.data(), dag->dag_astat.p, sizeof(int32_t) * 2 * dag->B, hipMemcpyDeviceToHost, st));
     INSP_HIP(hipStreamSynchronize(st));
     for (int32_t i = first; i < first + count; i++)
-        if (stat[2 * i] & 1) return set_error(INSP_E_RANGE, "estimate outside [1, 2^20] in DAG %d", i);
+        if (stat[2 * i] & ST_EST) return set_error(INSP_E_RANGE, "estimate outside [1, 2^20] in DAG %d", i);
+    for (int32_t i = 0; i < count; i++) unit_time_used[i] = uu[i];
     return INSP_OK;
 }

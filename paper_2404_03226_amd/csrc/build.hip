@@ -6,6 +6,7 @@
 #include <hipcub/hipcub.hpp>
 
 #include <algorithm>
+#include <atomic>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -43,9 +44,20 @@ int set_lds_limit(const void *kernel, size_t bytes) {
     return INSP_OK;
 }
 
+// Allocation-failure injection (insp_test_fail_alloc): the number of device
+// allocations still allowed to succeed, or -1 for no injection.
+static std::atomic<int64_t> g_fail_after{-1};
+
 int DevBuf::alloc(size_t nbytes) {
     release();
     if (nbytes == 0) nbytes = 16;
+    for (int64_t k = g_fail_after.load(); k >= 0;) {
+        if (k == 0) {
+            g_fail_after.store(-1);
+            return set_error(INSP_E_NOMEM, "hipMalloc(%zu) failed: injected allocation failure", nbytes);
+        }
+        if (g_fail_after.compare_exchange_weak(k, k - 1)) break;
+    }
     hipError_t e = hipMalloc(&p, nbytes);
     if (e != hipSuccess) {
         p = nullptr;
@@ -182,6 +194,12 @@ static inline unsigned grid_for(int64_t n, int threads) { return (unsigned)((n +
 using namespace insp;
 
 extern "C" const char *insp_last_error(void) { return g_last_error.c_str(); }
+
+extern "C" int insp_test_fail_alloc(int64_t after) {
+    if (after < -1) return set_error(INSP_E_INVAL, "insp_test_fail_alloc: after must be >= -1");
+    g_fail_after.store(after);
+    return INSP_OK;
+}
 
 extern "C" void insp_free_dag(insp_dag *dag) { delete dag; }
 

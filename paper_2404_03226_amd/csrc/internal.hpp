@@ -9,6 +9,7 @@
 #include <map>
 #include <memory>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "inspirit.h"
@@ -35,6 +36,10 @@ struct DevBuf {
     ~DevBuf() { release(); }
     int alloc(size_t nbytes);
     void release();
+    void swap(DevBuf &o) {
+        std::swap(p, o.p);
+        std::swap(bytes, o.bytes);
+    }
     template <typename T>
     T *as() const { return static_cast<T *>(p); }
 };
@@ -120,7 +125,9 @@ struct insp_dag {
     insp::DevBuf dag_maxtau;           // int32 [B]
     insp::DevBuf dag_tausum;           // int64 [B]
     insp::DevBuf dag_score;            // int32 [B * 24] ladder score, difference form
-    insp::DevBuf dag_stat;             // int32 [B * 2]: status, events
+    insp::DevBuf dag_stat;             // int32 [B * 2]: status of the current schedule call, events
+    insp::DevBuf dag_astat;            // int32 [B * 2]: status of the current attribute-only call
+    insp::DevBuf dag_sticky;           // int32 [B]: schedule failures not yet reported by insp_sync_status
     // HEFT: topological levels (built on first use) and upward ranks
     insp::DevBuf topo;                 // int32 [N]: each DAG's tasks in level order
     insp::DevBuf lvl;                  // int32 [N + B]: start of each level in topo, then the end

@@ -667,14 +667,19 @@ struct insp_mlp {
     }
 };
 
+// Grow the per-row buffers to `rows`.  All-or-nothing: the new buffers are
+// allocated beside the old ones and swapped in only when every allocation
+// succeeded, so a failure (INSP_E_NOMEM) leaves the model as it was.
 static int mlp_reserve(insp_mlp *m, int64_t rows) {
     if (rows <= m->cap) return INSP_OK;
-    int rc;
-    if ((rc = m->xb.alloc(2 * kIn * rows)) || (rc = m->h1.alloc(2 * kHid * rows)) ||
-        (rc = m->h2.alloc(2 * kHid * rows)) || (rc = m->dh2.alloc(2 * kHid * rows)) ||
-        (rc = m->dh1.alloc(2 * kHid * rows)) || (rc = m->y.alloc(4 * kOut * rows)) ||
-        (rc = m->part.alloc(4 * ((rows + 3) / 4 + 1) * (kHid + 3))) || (rc = m->ts.alloc(4 * kOut * rows)))
-        return rc;
+    DevBuf *cur[8] = {&m->xb, &m->h1, &m->h2, &m->dh2, &m->dh1, &m->y, &m->part, &m->ts};
+    const size_t bytes[8] = {(size_t)(2 * kIn * rows),  (size_t)(2 * kHid * rows), (size_t)(2 * kHid * rows),
+                             (size_t)(2 * kHid * rows), (size_t)(2 * kHid * rows), (size_t)(4 * kOut * rows),
+                             (size_t)(4 * ((rows + 3) / 4 + 1) * (kHid + 3)), (size_t)(4 * kOut * rows)};
+    DevBuf fresh[8];
+    for (int i = 0; i < 8; i++)
+        if (int rc = fresh[i].alloc(bytes[i])) return rc;
+    for (int i = 0; i < 8; i++) cur[i]->swap(fresh[i]);  // the old buffers are released on return
     m->cap = rows;
     m->gen++;
     return INSP_OK;
@@ -873,7 +878,9 @@ extern "C" int insp_mlp_train(insp_mlp *m, const float *x, const float *t, int64
         INSP_HIP(hipStreamSynchronize(st));  // earlier work on the stream may still read the old buffers
         if ((rc = mlp_reserve(m, batch))) return rc;
         if (m->tab.bytes < (size_t)(4 * words)) {
-            if ((rc = m->tab.alloc(4 * words))) return rc;
+            DevBuf fresh;
+            if ((rc = fresh.alloc(4 * words))) return rc;
+            m->tab.swap(fresh);
             m->gen++;
         }
     }

@@ -2211,9 +2211,10 @@ extern "C" int insp_schedule_batch(const insp_dag *cdag, const insp_workers *wor
     if ((rc = get_workspace(dag, 0, dag->B, workers, true, &ws))) return rc;
     int waves = 1, grid = default_grid(dag->B), sum_cap = 256, slot_cap = 16;
     parse_tune(tune_key, &waves, &grid, &sum_cap, &slot_cap);
-    if (grid < 1 || waves < 1 || sum_cap < 0 || sum_cap > 8192 || slot_cap < 0 ||
-        lds_bytes(1, sum_cap, 16, slot_cap) > 150 * 1024)
+    if (grid < 1 || sum_cap < 0 || sum_cap > 8192 || slot_cap < 0 || lds_bytes(1, sum_cap, 16, slot_cap) > 150 * 1024)
         return set_error(INSP_E_INVAL, "bad tune key '%s'", tune_key);
+    // one wave simulates one DAG; no other shape is implemented
+    if (waves != 1) return set_error(INSP_E_INVAL, "tune key '%s': only waves=1 is supported", tune_key);
     if ((rc = run_attributes(dag, ws, est, params->unit_time, nullptr, nullptr, nullptr, true, st))) return rc;
     if (params->policy == INSP_POLICY_HEFT && (rc = run_rank(dag, ws, est, st))) return rc;
     if (params->attr_mode == INSP_ATTR_TRANSITIVE && (rc = run_sim_transitive(dag, ws, est, params->unit_time, st)))
@@ -2235,10 +2236,28 @@ extern "C" int insp_debug_phase_clocks(unsigned long long *host, int count) {
 extern "C" int insp_sync_status(const insp_dag *cdag, void *stream) {
     if (!cdag) return set_error(INSP_E_INVAL, "null handle");
     insp_dag *dag = const_cast<insp_dag *>(cdag);
-    INSP_HIP(hipStreamSynchronize((hipStream_t)stream));
+    hipStream_t st = (hipStream_t)stream;
+    INSP_HIP(hipSetDevice(dag->device));
+    INSP_HIP(hipStreamSynchronize(st));
     if (!dag->dag_stat.p) return INSP_OK;
-    std::vector<int32_t> stat(2 * dag->B);
-    INSP_HIP(hipMemcpy(stat.data(), dag->dag_stat.p, sizeof(int32_t) * 2 * dag->B, hipMemcpyDeviceToHost));
+    // the latest schedule's status words and the failures of earlier calls
+    // not yet reported; both are cleared once read
+    std::vector<int32_t> stat(2 * dag->B), sticky(dag->B);
+    INSP_HIP(hipMemcpyAsync(stat.data(), dag->dag_stat.p, sizeof(int32_t) * 2 * dag->B, hipMemcpyDeviceToHost, st));
+    INSP_HIP(hipMemcpyAsync(sticky.data(), dag->dag_sticky.p, sizeof(int32_t) * dag->B, hipMemcpyDeviceToHost, st));
+    INSP_HIP(hipStreamSynchronize(st));
+    bool any = false;
+    for (int32_t b = 0; b < dag->B; b++) {
+        any |= (stat[2 * b] | sticky[b]) != 0;
+        stat[2 * b] |= sticky[b];
+    }
+    if (any) {
+        std::vector<int32_t> zero(2 * dag->B, 0);
+        for (int32_t b = 0; b < dag->B; b++) zero[2 * b + 1] = stat[2 * b + 1];  // event counts stay
+        INSP_HIP(hipMemcpyAsync(dag->dag_stat.p, zero.data(), sizeof(int32_t) * 2 * dag->B, hipMemcpyHostToDevice, st));
+        INSP_HIP(hipMemsetAsync(dag->dag_sticky.p, 0, sizeof(int32_t) * dag->B, st));
+        INSP_HIP(hipStreamSynchronize(st));
+    }
     for (int32_t b = 0; b < dag->B; b++) {
         if (stat[2 * b] & ST_EST) return set_error(INSP_E_RANGE, "estimate outside [1, 2^20] in DAG %d", b);
         if (stat[2 * b] & ST_DUR) return set_error(INSP_E_RANGE, "duration outside [1, 2^20] in DAG %d", b);

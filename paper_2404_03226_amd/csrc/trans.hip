@@ -377,7 +377,9 @@ int run_transitive(insp_dag *dag, Workspace *ws, const int32_t *est, int32_t uni
     A.cum = unit_time == 0 ? dag->tcum.as<int32_t>() : nullptr;
     A.longest = ws->tlong.as<unsigned int>();
     A.counter = reinterpret_cast<int32_t *>(ws->tlong.as<unsigned int>() + ws->count);
-    A.stat = dag->dag_stat.as<int32_t>();
+    // a standalone call has status words of its own (it neither clears nor
+    // reports a schedule's pending failures)
+    A.stat = clear_status ? dag->dag_astat.as<int32_t>() : dag->dag_stat.as<int32_t>();
     hipLaunchKernelGGL(k_trans_clear, dim3((unsigned)((ws->count + 255) / 256)), dim3(256), 0, st, A);
     if (ws->tasks > 0) {
         hipLaunchKernelGGL(k_position_tau, dim3((unsigned)((ws->tasks + 255) / 256)), dim3(256), 0, st, A);
@@ -424,18 +426,32 @@ extern "C" int insp_transitive_attributes(const insp_dag *cdag, int32_t dag_inde
     if ((rc = ensure_state(dag, st))) return rc;
     Workspace *ws;
     if ((rc = get_workspace(dag, first, count, workers, true, &ws))) return rc;
-    if ((rc = run_transitive(dag, ws, est, unit_time, ia, ie, true, st))) return rc;
+    // computed into the handle's arrays and copied out once the call is known
+    // to succeed, so that a failing call leaves ia and ie untouched
+    const int64_t NN = std::max<int64_t>(dag->N, 1);
+    if ((!dag->tia.p && (rc = dag->tia.alloc(sizeof(int32_t) * NN))) ||
+        (!dag->tie.p && (rc = dag->tie.alloc(sizeof(int32_t) * NN))))
+        return rc;
+    int32_t *tia = dag->tia.as<int32_t>() + ws->base, *tie = dag->tie.as<int32_t>() + ws->base;
+    if ((rc = run_transitive(dag, ws, est, unit_time, tia, tie, true, st))) return rc;
     std::vector<int32_t> stat(2 * dag->B);
     std::vector<uint32_t> lp(count);
-    INSP_HIP(hipMemcpyAsync(unit_time_used, ws->tu.p, sizeof(int32_t) * count, hipMemcpyDeviceToHost, st));
+    std::vector<int32_t> uu(count);
+    INSP_HIP(hipMemcpyAsync(uu.data(), ws->tu.p, sizeof(int32_t) * count, hipMemcpyDeviceToHost, st));
     INSP_HIP(hipMemcpyAsync(lp.data(), ws->tlong.p, sizeof(uint32_t) * count, hipMemcpyDeviceToHost, st));
-    INSP_HIP(hipMemcpyAsync(stat.data(), dag->dag_stat.p, sizeof(int32_t) * 2 * dag->B, hipMemcpyDeviceToHost, st));
+    INSP_HIP(hipMemcpyAsync(stat.data(), dag->dag_astat.p, sizeof(int32_t) * 2 * dag->B, hipMemcpyDeviceToHost, st));
     INSP_HIP(hipStreamSynchronize(st));
-    if (longest_path)
-        for (int32_t i = 0; i < count; i++) longest_path[i] = lp[i];
     for (int32_t i = first; i < first + count; i++) {
         if (stat[2 * i] & ST_EST) return set_error(INSP_E_RANGE, "estimate outside [1, 2^20] in DAG %d", i);
         if (stat[2 * i] & ST_PATH) return set_error(INSP_E_RANGE, "longest path of DAG %d reaches 2^30 ticks", i);
     }
+    if (n > 0) {
+        INSP_HIP(hipMemcpyAsync(ia, tia, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, st));
+        INSP_HIP(hipMemcpyAsync(ie, tie, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, st));
+        INSP_HIP(hipStreamSynchronize(st));
+    }
+    for (int32_t i = 0; i < count; i++) unit_time_used[i] = uu[i];
+    if (longest_path)
+        for (int32_t i = 0; i < count; i++) longest_path[i] = lp[i];
     return INSP_OK;
 }

@@ -28,7 +28,7 @@ EXPORTS = ("insp_build_dag", "insp_set_task_data", "insp_free_dag", "insp_dag_in
            "insp_schedule",
            "insp_schedule_batch", "insp_sync_status", "insp_profile_enable", "insp_profile_read",
            "insp_mlp_create", "insp_mlp_free", "insp_mlp_grads", "insp_mlp_train_step", "insp_mlp_train", "insp_mlp_predict",
-           "insp_mlp_state", "insp_last_error")
+           "insp_mlp_state", "insp_last_error", "insp_test_fail_alloc")
 MLP_PARAMS = 74754
 
 
@@ -91,6 +91,7 @@ def load(path: str = LIB_PATH):
     lib.insp_mlp_predict.argtypes = [P, P, i64, P, P, P]
     lib.insp_mlp_state.argtypes = [P, P, P, P, C.POINTER(i64), C.c_int]
     lib.insp_last_error.restype = C.c_char_p
+    lib.insp_test_fail_alloc.argtypes = [i64]
     _lib = lib
     return lib
 
@@ -106,6 +107,43 @@ def _ptr(t):
     if isinstance(t, np.ndarray):
         return t.ctypes.data_as(C.c_void_p)
     return C.c_void_p(t.data_ptr())
+
+
+_DT = {"i32": "int32", "i64": "int64", "i8": "int8", "f32": "float32"}
+
+
+def _dev(t, what, dtype, cols=None, rows=None):
+    """Device tensor `t` as the library reads it: the named dtype, contiguous
+    (a strided view would be read as other rows), on a GPU, with `cols`
+    columns (a 2-D [rows, cols] tensor, or a flat one of rows * cols) and at
+    least `rows` rows.  Returns its pointer; None passes through."""
+    if t is None:
+        return None
+    import torch
+    want = getattr(torch, _DT[dtype])
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{what}: expected a torch tensor, got {type(t).__name__}")
+    if t.dtype != want:
+        raise TypeError(f"{what}: expected {want}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what}: tensor must be contiguous")
+    if t.device.type != "cuda":
+        raise ValueError(f"{what}: tensor must be on the GPU, got {t.device}")
+    if cols is not None:
+        if t.dim() == 2 and t.shape[1] != cols:
+            raise ValueError(f"{what}: expected {cols} columns, got shape {tuple(t.shape)}")
+        if t.dim() not in (1, 2) or t.numel() % cols:
+            raise ValueError(f"{what}: expected [n, {cols}], got shape {tuple(t.shape)}")
+    n = t.numel() // (cols or 1)
+    if rows is not None and n < rows:
+        raise ValueError(f"{what}: expected at least {rows} rows, got {n}")
+    return C.c_void_p(t.data_ptr())
+
+
+def test_fail_alloc(after: int):
+    """Testing hook: the device allocation after `after` more successful ones
+    fails with E_NOMEM (-1 turns injection off)."""
+    _check(load().insp_test_fail_alloc(int(after)))
 
 
 def _stream(stream):
@@ -176,15 +214,17 @@ def attributes(dag: Dag, index, est, workers, unit_time=0, rem=None, stream=None
     ia = torch.empty(max(n, 1), dtype=torch.int32, device=est.device)
     ie = torch.empty(max(n, 1), dtype=torch.int32, device=est.device)
     U = np.zeros(count, np.int32)
-    _check(load().insp_attributes(dag.handle, index, _ptr(est), _workers(workers, count), unit_time, _ptr(rem),
-                                  _ptr(ia), _ptr(ie), _ptr(U), _stream(stream)))
+    _check(load().insp_attributes(dag.handle, index, _dev(est, "est", "i32", 2, n), _workers(workers, count),
+                                  unit_time, _dev(rem, "rem", "i32", 1, n), _ptr(ia), _ptr(ie), _ptr(U),
+                                  _stream(stream)))
     return ia[:n], ie[:n], U
 
 
 def set_task_data(dag: Dag, data_kib, stream=None):
     """Attach per-task output sizes (device int32 tensor, KiB, one per task of
     the handle) for the data model; None detaches them."""
-    _check(load().insp_set_task_data(dag.handle, _ptr(data_kib), _stream(stream)))
+    _check(load().insp_set_task_data(dag.handle, _dev(data_kib, "data_kib", "i32", 1, int(dag.task_off[-1])),
+                                     _stream(stream)))
 
 
 def transitive_attributes(dag: Dag, index, est, workers, unit_time=0, stream=None):
@@ -199,8 +239,9 @@ def transitive_attributes(dag: Dag, index, est, workers, unit_time=0, stream=Non
     ie = torch.empty(max(n, 1), dtype=torch.int32, device=est.device)
     U = np.zeros(count, np.int32)
     lp = np.zeros(count, np.int64)
-    _check(load().insp_transitive_attributes(dag.handle, index, _ptr(est), _workers(workers, count), unit_time,
-                                             _ptr(ia), _ptr(ie), _ptr(U), _ptr(lp), _stream(stream)))
+    _check(load().insp_transitive_attributes(dag.handle, index, _dev(est, "est", "i32", 2, n),
+                                             _workers(workers, count), unit_time, _ptr(ia), _ptr(ie), _ptr(U),
+                                             _ptr(lp), _stream(stream)))
     return ia[:n], ie[:n], U, lp
 
 
@@ -230,10 +271,13 @@ def schedule(dag: Dag, index, workers, dur, est, prm: Params = None, trace=False
         cap = prm.max_events if prm.max_events > 0 else n + 1
         tr = torch.zeros(cap * TRACE_DTYPE.itemsize, dtype=torch.uint8, device=dev)
         o["trace"] = tr
-    _check(load().insp_schedule(dag.handle, index, _workers(workers, 1), _ptr(dur), _ptr(est), C.byref(prm),
-                                _ptr(o["worker"]), _ptr(o["start"]), _ptr(o["finish"]), _ptr(o["makespan"]),
-                                _ptr(o.get("ie_at_pop")), _ptr(o.get("mode_at_pop")), _ptr(tr),
-                                _ptr(o["n_events"]), _stream(stream)))
+    _check(load().insp_schedule(dag.handle, index, _workers(workers, 1), _dev(dur, "dur", "i32", 2, n),
+                                _dev(est, "est", "i32", 2, n), C.byref(prm),
+                                _dev(o["worker"], "worker", "i32", 1, n), _dev(o["start"], "start", "i64", 1, n),
+                                _dev(o["finish"], "finish", "i64", 1, n), _dev(o["makespan"], "makespan", "i64", 1, 1),
+                                _dev(o.get("ie_at_pop"), "ie_at_pop", "i32", 1, n),
+                                _dev(o.get("mode_at_pop"), "mode_at_pop", "i8", 1, n), _ptr(tr),
+                                _dev(o["n_events"], "n_events", "i32", 1, 1), _stream(stream)))
     return o
 
 
@@ -251,10 +295,14 @@ def schedule_batch(dag: Dag, workers, dur, est, prm: Params = None, tune_key=Non
     o = out or _outputs(int(dag.task_off[-1]), dev, with_pop)
     o["makespan"] = o.get("makespan", torch.empty(dag.n_dags, dtype=torch.int64, device=dev))
     key = tune_key.encode() if isinstance(tune_key, str) else tune_key
-    _check(load().insp_schedule_batch(dag.handle, _workers(workers, dag.n_dags), _ptr(dur), _ptr(est),
-                                      C.byref(prm), _ptr(o["worker"]), _ptr(o["start"]), _ptr(o["finish"]),
-                                      _ptr(o["makespan"]), _ptr(o.get("ie_at_pop")), _ptr(o.get("mode_at_pop")),
-                                      key, _stream(stream)))
+    n, B = int(dag.task_off[-1]), dag.n_dags
+    _check(load().insp_schedule_batch(dag.handle, _workers(workers, B), _dev(dur, "dur", "i32", 2, n),
+                                      _dev(est, "est", "i32", 2, n), C.byref(prm),
+                                      _dev(o["worker"], "worker", "i32", 1, n), _dev(o["start"], "start", "i64", 1, n),
+                                      _dev(o["finish"], "finish", "i64", 1, n),
+                                      _dev(o["makespan"], "makespan", "i64", 1, B),
+                                      _dev(o.get("ie_at_pop"), "ie_at_pop", "i32", 1, n),
+                                      _dev(o.get("mode_at_pop"), "mode_at_pop", "i8", 1, n), key, _stream(stream)))
     return o
 
 
@@ -324,23 +372,28 @@ class Mlp:
         g = torch.empty(MLP_PARAMS, dtype=torch.float32, device=x.device)
         y = torch.empty((B, 2), dtype=torch.float32, device=x.device)
         loss = torch.empty(1, dtype=torch.float32, device=x.device)
-        _check(load().insp_mlp_grads(self._h, _ptr(x), _ptr(t), B, _ptr(g), _ptr(y), _ptr(loss), _stream(stream)))
+        _check(load().insp_mlp_grads(self._h, _dev(x, "x", "f32", 32, B), _dev(t, "t", "f32", 2, B), B, _ptr(g),
+                                     _ptr(y), _ptr(loss), _stream(stream)))
         return g, y, loss
 
     def train_step(self, x, t, lr=1e-3, loss=None, stream=None):
-        _check(load().insp_mlp_train_step(self._h, _ptr(x), _ptr(t), x.shape[0], lr, _ptr(loss), _stream(stream)))
+        B = x.shape[0]
+        _check(load().insp_mlp_train_step(self._h, _dev(x, "x", "f32", 32, B), _dev(t, "t", "f32", 2, B), B, lr,
+                                          _dev(loss, "loss", "f32", 1, 1), _stream(stream)))
 
     def train(self, x, t, batch=1024, epochs=1, lr=1e-3, loss=None, stream=None):
         """`epochs` passes over all rows of x, t in minibatches (graph-captured)."""
-        _check(load().insp_mlp_train(self._h, _ptr(x), _ptr(t), x.shape[0], batch, epochs, lr, _ptr(loss),
-                                     _stream(stream)))
+        n = x.shape[0]
+        _check(load().insp_mlp_train(self._h, _dev(x, "x", "f32", 32, n), _dev(t, "t", "f32", 2, n), n, batch,
+                                     epochs, lr, _dev(loss, "loss", "f32", 1, 1), _stream(stream)))
 
     def predict(self, x, want_y=True, stream=None):
         import torch
         n = x.shape[0]
         y = torch.empty((max(n, 1), 2), dtype=torch.float32, device=x.device) if want_y else None
         est = torch.empty((max(n, 1), 2), dtype=torch.int32, device=x.device)
-        _check(load().insp_mlp_predict(self._h, _ptr(x), n, _ptr(y), _ptr(est), _stream(stream)))
+        _check(load().insp_mlp_predict(self._h, _dev(x, "x", "f32", 32, n), n, _ptr(y), _ptr(est),
+                                       _stream(stream)))
         return (y[:n] if want_y else None), est[:n]
 
     def state(self):

@@ -1,7 +1,15 @@
-"""HIP cost-model kernels against the FP64 reference with bf16 rounding."""
+"""HIP cost-model kernels against the FP64 reference with bf16 rounding.
+
+Every floating-point output is compared element by element against the
+reference within the per-element bound of tests/mlp_bounds.py (the fp32
+accumulation bound of each sum, propagated through the bfloat16 stores and
+ReLU masks); integer estimates are compared exactly wherever the kernel's
+own exp(y) is not within 1e-3 relative of a rounding tie.
+"""
 import numpy as np
 import pytest
 
+import mlp_bounds as mb
 from oracle import mlp
 from paper_2404_03226_amd import synth
 
@@ -18,9 +26,15 @@ def insp():
     return inspirit
 
 
-def rel(a, b):
-    a, b = np.asarray(a, np.float64), np.asarray(b, np.float64)
-    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+def close(got, ref, bound, what):
+    ok, worst, at = mb.within(got, ref, bound)
+    print(f"  {what}: worst |err| / bound = {worst:.3g}", flush=True)
+    assert ok, f"{what}: element {at} off by {worst:.3g} x its bound"
+
+
+def check_y(y, p, X):
+    c, E = mb.forward_bounds(p, X)
+    close(y, c["Y"], E["Y"], "y")
 
 
 def batch(n, seed=0):
@@ -38,12 +52,12 @@ def test_forward_backward_match_reference(insp, B):
     X, T = batch(B)
     m = insp.Mlp(p)
     g, y, loss = m.grads(torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda())
-    ref_loss, ref_g, c = mlp.loss_grads(p, X, T, bf=True)
-    assert rel(y.cpu().numpy(), c["Y"]) <= 1e-3
-    assert abs(loss.item() - ref_loss) <= 1e-3 * ref_loss
+    ref_loss, ref_g, c, E = mb.grad_bounds(p, X, T)
+    close(y.cpu().numpy(), c["Y"], E["Y"], "y")
+    close(np.array([loss.item()]), np.array([ref_loss]), np.array([E["loss"]]), "loss")
     gg = mlp.unpack(g.cpu().numpy(), synth.MLP_SHAPES)
-    for name, a, b in zip(("W1", "b1", "W2", "b2", "W3", "b3"), gg, ref_g):
-        assert rel(a, b) <= 1e-3, name
+    for name, a, b, e in zip(("W1", "b1", "W2", "b2", "W3", "b3"), gg, ref_g, E["grads"]):
+        close(a, b, e, "d" + name)
     m.free()
 
 
@@ -55,14 +69,18 @@ def test_adam_step_matches_reference(insp):
     m = insp.Mlp(p)
     m.train_step(torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda(), lr=1e-3)
     torch.cuda.synchronize()
-    newp, _, _, step = m.state()
-    _, g, _ = mlp.loss_grads(p, X, T, bf=True)
+    newp, am, av, step = m.state()
+    _, g, _, E = mb.grad_bounds(p, X, T)
     zeros = [np.zeros_like(q, dtype=np.float64) for q in p]
-    ref, _, _ = mlp.adam([q.astype(np.float64) for q in p], g, zeros, zeros, 1)
+    ref_p, ref_m, ref_v = mlp.adam([q.astype(np.float64) for q in p], g, zeros, zeros, 1)
+    A = mb.adam_bounds(mlp.pack(p), mlp.pack(g), mlp.pack(E["grads"]), 1e-3)
+    # the bound module's closed form of the first step is the reference's
+    assert np.allclose(A["p"], mlp.pack(ref_p), rtol=0, atol=1e-12)
+    assert np.allclose(A["m"], mlp.pack(ref_m), rtol=1e-12) and np.allclose(A["v"], mlp.pack(ref_v), rtol=1e-12)
     assert step == 1
-    # first step moves every weight by ~lr * sign(g); compare the moves
-    moved = newp - mlp.pack(p)
-    assert rel(moved, mlp.pack(ref) - mlp.pack(p)) <= 2e-2
+    close(newp, A["p"], A["Ep"], "params")
+    close(am, A["m"], A["Em"], "first moment")
+    close(av, A["v"], A["Ev"], "second moment")
     m.free()
 
 
@@ -75,8 +93,7 @@ def test_predict_matches_reference_and_rounds(insp):
     m = insp.Mlp(p)
     y, est = m.predict(torch.from_numpy(X).cuda())
     y, est = y.cpu().numpy(), est.cpu().numpy()
-    ref = mlp.forward(p, X, bf=True)["Y"]
-    assert rel(y, ref) <= 1e-3
+    check_y(y, p, X)
     # integer decision taken from the kernel's own y in the same precision
     e = np.exp(y.astype(np.float32))
     ok = np.abs(e - np.floor(e) - 0.5) > 1e-3 * np.maximum(e, 1.0)
@@ -107,7 +124,7 @@ def test_predict_small_and_empty(insp, n):
             m.predict(buf[1:].view(1, 32))
     if n:
         y, est = y.cpu().numpy(), est.cpu().numpy()
-        assert rel(y, mlp.forward(p, X, bf=True)["Y"]) <= 1e-3
+        check_y(y, p, X)
         e = np.exp(y.astype(np.float32))
         ok = np.abs(e - np.floor(e) - 0.5) > 1e-3 * np.maximum(e, 1.0)
         assert np.array_equal(est[ok], np.clip(np.rint(e), 1, 1 << 20).astype(np.int32)[ok])
@@ -132,8 +149,7 @@ def test_predict_full_batch_sampled(insp):
     idx = np.unique(np.concatenate([rng.integers(0, n, 4000), np.arange(64), np.arange(n - 100, n)]))
     sel = torch.from_numpy(idx).cuda()
     y, est = y[sel].cpu().numpy(), est[sel].cpu().numpy()
-    ref = mlp.forward(p, X[idx], bf=True)["Y"]
-    assert rel(y, ref) <= 1e-3
+    check_y(y, p, X[idx])
     e = np.exp(y.astype(np.float32))
     ok = np.abs(e - np.floor(e) - 0.5) > 1e-3 * np.maximum(e, 1.0)
     want = np.clip(np.rint(e), 1, 1 << 20).astype(np.int32)
@@ -219,3 +235,56 @@ def test_checkpoint_resume_is_bit_identical(insp):
     torch.cuda.synchronize()
     pa, pb = a.state()[0], b.state()[0]
     assert np.array_equal(pa, pb)
+
+
+def test_learned_estimates_schedules_and_gain(insp):
+    """The cost-model evaluation on 32 DAGs of the 4096-DAG batch.  (a) The
+    scheduler given the reference network's integer estimates, the per-type
+    table and the true ticks (every run advancing with the true ticks)
+    matches the oracle bit for bit.  (b) The network trained on the GPU by
+    the library's own forward, backward and Adam kernels, from the same
+    initial parameters and minibatches as the reference, gains over the
+    table: lower validation error and, with its estimates, schedules closer
+    to the true-estimate makespans on most DAGs."""
+    import torch
+    import learned
+    import oracle
+    from paper_2404_03226_amd import costmodel
+    print("[case] learned estimates: schedules and gain", flush=True)
+    rec, _, steps, table = learned.trained()
+    ws, b, x, ticks, est = learned.sample()
+    workers = [(w.n_cpu, w.n_gpu) for w in ws]
+    dag, dur, _ = insp.batch_to_device(b)
+    dur = torch.from_numpy(np.ascontiguousarray(ticks, np.int32)).cuda()
+    ms = {}
+    for name in ("true", "plain", "learned"):
+        e = torch.from_numpy(np.ascontiguousarray(est[name], np.int32)).cuda()
+        o = insp.schedule_batch(dag, workers, dur, e)
+        insp.sync_status(dag)
+        b.dur, b.est = ticks, est[name]
+        r = oracle.schedule_batch(b)
+        for k in ("worker", "start", "finish", "ie_at_pop", "mode_at_pop", "makespan"):
+            assert np.array_equal(o[k].cpu().numpy()[: len(r[k])], r[k]), (name, k)
+        ms[name] = r["makespan"]
+    ref_gaps = costmodel.makespan_gaps(ms["true"], ms["plain"], ms["learned"])
+    # (b) GPU training and inference
+    ntr = rec["n_train"]
+    X = torch.from_numpy(rec["x"]).cuda()
+    LT = torch.from_numpy(np.log(rec["ticks"].astype(np.float64)).astype(np.float32)).cuda()
+    m = insp.Mlp(synth.mlp_init())
+    m.train(X[:ntr], LT[:ntr], batch=1024, epochs=learned.EPOCHS, lr=learned.LR)
+    assert m.state()[3] == steps
+    y, _ = m.predict(X[ntr:])
+    val = LT[ntr:].cpu().numpy()
+    mse_mlp = float(np.mean((y.cpu().numpy() - val) ** 2))
+    mse_tab = float(np.mean((np.log(table[rec["types"][ntr:]].astype(np.float64)) - val) ** 2))
+    _, est_gpu = m.predict(torch.from_numpy(x).cuda(), want_y=False)
+    gms = costmodel.evaluate(dag, workers, b.type, ticks, est_gpu, table)
+    gaps = costmodel.makespan_gaps(gms["true"], gms["plain"], gms["learned"])
+    print("  reference network:", ref_gaps, flush=True)
+    print("  GPU-trained network:", gaps, "val mse", mse_mlp, "table", mse_tab, flush=True)
+    assert np.array_equal(gms["true"], ms["true"]) and np.array_equal(gms["plain"], ms["plain"])
+    assert mse_mlp < 0.8 * mse_tab
+    assert gaps["paired_gain"] > 0.01 and gaps["frac_improved"] > 0.75
+    m.free()
+    dag.free()

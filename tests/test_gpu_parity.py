@@ -125,6 +125,53 @@ def test_random_small_dags(insp, policy):
         check_schedule(w, g["worker"], g["start"], g["finish"], g["makespan"])
 
 
+def _long_tasks(n, n_cpu, n_gpu, edges, seed):
+    """n tasks of 2^19..2^20 ticks on a small machine: once every worker has
+    64 such tasks queued, each expected termination time exceeds 2^26 ticks
+    and the one-wave loop picks the push worker with its 64-bit argmin."""
+    st = synth.Stream(seed, 5)
+    src, dst = [], []
+    for k in range(edges):
+        a, b = sorted(int(x) for x in st.randint(np.array([2 * k, 2 * k + 1]), 0, n))
+        if a != b:
+            src.append(a)
+            dst.append(b)
+    order = np.lexsort((dst, src))
+    src, dst = np.asarray(src, np.int64)[order], np.asarray(dst, np.int32)[order]
+    rp = np.zeros(n + 1, np.int32)
+    np.add.at(rp, src + 1, 1)
+    rp = np.cumsum(rp).astype(np.int32)
+    lo = 1 << 19
+    dur = (lo + st.randint(np.arange(10_000, 10_000 + 2 * n), 0, lo + 1)).reshape(n, 2).astype(np.int32)
+    est = (lo + st.randint(np.arange(20_000, 20_000 + 2 * n), 0, lo + 1)).reshape(n, 2).astype(np.int32)
+    return synth.Workload(f"long{seed}", n, rp, dst, np.zeros(n, np.int32), dur, est, n_cpu, n_gpu)
+
+
+@pytest.mark.parametrize("case", [(300, 2, 1, 0), (400, 3, 1, 60), (260, 1, 1, 20)])
+def test_push_argmin_beyond_32_bit_costs(insp, case):
+    """Expected termination times above 2^26 ticks on every worker take the
+    push's 64-bit worker argmin (the 32-bit key holds (cost - t) << 6 only
+    below that): single DAG and batch, against the oracle."""
+    n, nc, ng, edges = case
+    w = _long_tasks(n, nc, ng, edges, seed=n)
+    say("push argmin 64-bit", case)
+    for policy in ("inspirit", "fifo"):
+        g = run_gpu(insp, w, policy)
+        r = oracle.schedule(w, policy=policy, variant=oracle.HEAP)
+        assert_same(g, r, f"long {case} {policy}")
+        check_schedule(w, g["worker"], g["start"], g["finish"], g["makespan"])
+    # queues reach 64 tasks per worker, so the wide costs really occur
+    assert n > 64 * (nc + ng) + 8
+    b = synth.concat([w, _long_tasks(n // 2, nc, ng, edges // 2, seed=n + 1)])
+    dag, dur, est = insp.batch_to_device(b)
+    o = insp.schedule_batch(dag, [(nc, ng), (nc, ng)], dur, est)
+    insp.sync_status(dag)
+    rb = oracle.schedule_batch(b)
+    for k in ("worker", "start", "finish", "ie_at_pop", "mode_at_pop", "makespan"):
+        assert np.array_equal(o[k].cpu().numpy()[: len(rb[k])], rb[k]), k
+    dag.free()
+
+
 def test_unit_tasks_many_simultaneous_completions(insp):
     # equal durations make many completions coincide: exercises the merge
     for i in range(12):
@@ -224,6 +271,143 @@ def test_error_codes_through_abi(insp):
         insp.schedule(dag, 0, (0, 0), d, d)
     assert e.value.code == insp.E_RANGE
     dag.free()
+
+
+def test_failures_are_kept_until_reported(insp):
+    """A schedule's device-side failure survives later schedule and
+    attribute calls on the handle until insp_sync_status reports it, and is
+    cleared once reported."""
+    import torch
+    say("sticky status")
+    ws = [synth.random_dag(31, i, 40, 0.1, n_cpu=2, n_gpu=1) for i in range(3)]
+    b = synth.concat(ws)
+    dag, dur, est = insp.batch_to_device(b)
+    workers = [(w.n_cpu, w.n_gpu) for w in ws]
+    insp.schedule(dag, 1, workers[1], dur[int(b.task_off[1]):], est[int(b.task_off[1]):], insp.params(max_events=3))
+    insp.schedule(dag, 0, workers[0], dur, est)                 # a later good schedule
+    insp.attributes(dag, insp.ALL_DAGS, est, workers)            # an attribute-only call
+    insp.schedule_batch(dag, workers, dur, est)                  # and a good batch
+    with pytest.raises(insp.InspError) as e:
+        insp.sync_status(dag)
+    assert e.value.code == insp.E_HANG and "DAG 1" in str(e.value)
+    insp.sync_status(dag)  # reported once, then cleared
+    insp.schedule_batch(dag, workers, dur, est, insp.params(max_events=5))
+    with pytest.raises(insp.InspError) as e:
+        insp.sync_status(dag)
+    assert e.value.code == insp.E_HANG
+    insp.sync_status(dag)
+    dag.free()
+
+
+def test_failing_calls_leave_outputs_untouched(insp):
+    """Every call that returns a non-OK status writes no output: attribute
+    and transitive attribute calls with an estimate out of range (the other
+    DAGs' outputs included) and argument errors of the schedule calls; a
+    schedule whose DAG fails on the device leaves that DAG's outputs alone
+    and sets its makespan to -1."""
+    import torch
+    say("outputs untouched")
+    ws = [synth.random_dag(32, i, 50, 0.1, n_cpu=2, n_gpu=1) for i in range(3)]
+    b = synth.concat(ws)
+    dag, dur, est = insp.batch_to_device(b)
+    N = int(b.task_off[-1])
+    workers = [(w.n_cpu, w.n_gpu) for w in ws]
+    bad = est.clone()
+    bad[int(b.task_off[2]) + 3, 1] = (1 << 20) + 1
+    lib = insp.load()
+    P = insp.C.c_void_p
+    ia = torch.full((N,), -7, dtype=torch.int32, device="cuda")
+    ie = torch.full((N,), -7, dtype=torch.int32, device="cuda")
+    U = np.full(3, -7, np.int32)
+    lp = np.full(3, -7, np.int64)
+    rc = lib.insp_attributes(dag.handle, insp.ALL_DAGS, P(bad.data_ptr()), insp._workers(workers, 3), 0, None,
+                             P(ia.data_ptr()), P(ie.data_ptr()), U.ctypes.data_as(P), insp._stream(None))
+    assert rc == insp.E_RANGE
+    rc = lib.insp_transitive_attributes(dag.handle, insp.ALL_DAGS, P(bad.data_ptr()), insp._workers(workers, 3), 0,
+                                        P(ia.data_ptr()), P(ie.data_ptr()), U.ctypes.data_as(P),
+                                        lp.ctypes.data_as(P), insp._stream(None))
+    assert rc == insp.E_RANGE
+    torch.cuda.synchronize()
+    assert (ia == -7).all() and (ie == -7).all() and (U == -7).all() and (lp == -7).all()
+    # a schedule call rejected on its arguments
+    o = {k: torch.full((N,), -7, dtype=t, device="cuda") for k, t in
+         (("worker", torch.int32), ("start", torch.int64), ("finish", torch.int64), ("ie_at_pop", torch.int32),
+          ("mode_at_pop", torch.int8))}
+    o["makespan"] = torch.full((3,), -7, dtype=torch.int64, device="cuda")
+    with pytest.raises(insp.InspError) as e:
+        insp.schedule_batch(dag, workers, dur, est, tune_key="waves=2", out=o)
+    assert e.value.code == insp.E_INVAL
+    with pytest.raises(insp.InspError) as e:
+        insp.schedule_batch(dag, workers, dur, est, insp.params(policy=9), out=o)
+    assert e.value.code == insp.E_INVAL
+    torch.cuda.synchronize()
+    assert all((o[k] == -7).all() for k in o)
+    # a DAG failing on the device: its outputs stay, the others are written
+    insp.schedule_batch(dag, workers, dur, bad, out=o)
+    with pytest.raises(insp.InspError) as e:
+        insp.sync_status(dag)
+    assert e.value.code == insp.E_RANGE
+    ms = o["makespan"].cpu().numpy()
+    assert ms[2] == -1 and ms[0] > 0 and ms[1] > 0
+    a2, z2 = int(b.task_off[2]), int(b.task_off[3])
+    for k in ("worker", "start", "finish", "ie_at_pop", "mode_at_pop"):
+        assert (o[k][a2:z2] == -7).all(), k
+    r = oracle.schedule_batch(synth.concat(ws[:2]))
+    assert np.array_equal(o["start"][:a2].cpu().numpy(), r["start"])
+    dag.free()
+
+
+def test_allocation_failures_return_nomem_and_leave_state_usable(insp):
+    """Injected device allocation failures (insp_test_fail_alloc): the call
+    returns E_NOMEM, and the handle or model keeps working -- in particular a
+    cost model whose buffers failed to grow still computes what a fresh
+    model computes."""
+    import torch
+    say("nomem")
+    w = synth.random_dag(33, 0, 60, 0.08, n_cpu=2, n_gpu=1)
+    for k in range(4):
+        insp.test_fail_alloc(k)
+        try:
+            with pytest.raises(insp.InspError) as e:
+                insp.to_device(w)
+            assert e.value.code == insp.E_NOMEM
+        finally:
+            insp.test_fail_alloc(-1)
+    dag, dur, est = insp.to_device(w)
+    insp.test_fail_alloc(1)
+    try:
+        with pytest.raises(insp.InspError) as e:
+            insp.schedule(dag, 0, (w.n_cpu, w.n_gpu), dur, est)
+        assert e.value.code == insp.E_NOMEM
+    finally:
+        insp.test_fail_alloc(-1)
+    g = run_gpu(insp, w)
+    assert_same(g, oracle.schedule(w), "after nomem")
+    dag.free()
+    # the cost model: reserve for 64 rows, then fail to grow to 2048
+    from paper_2404_03226_amd import synth as sy
+    rec = sy.cfg5_records(n=4096)
+    X = torch.from_numpy(rec["x"][:2048]).cuda()
+    T = torch.from_numpy(np.log(rec["ticks"][:2048].astype(np.float64)).astype(np.float32)).cuda()
+    a, ref = insp.Mlp(sy.mlp_init()), insp.Mlp(sy.mlp_init())
+    a.grads(X[:64], T[:64])
+    for k in range(8):
+        insp.test_fail_alloc(k)
+        try:
+            with pytest.raises(insp.InspError) as e:
+                a.grads(X, T)
+            assert e.value.code == insp.E_NOMEM
+        finally:
+            insp.test_fail_alloc(-1)
+    for B in (64, 2048):
+        ga, ya, la = a.grads(X[:B], T[:B])
+        gr, yr, lr_ = ref.grads(X[:B], T[:B])
+        assert torch.equal(ga, gr) and torch.equal(ya, yr) and torch.equal(la, lr_)
+    a.train(X, T, batch=64, epochs=1)
+    ref.train(X, T, batch=64, epochs=1)
+    assert np.array_equal(a.state()[0], ref.state()[0])
+    a.free()
+    ref.free()
 
 
 def test_batch_graph_replays_match_eager(insp):
