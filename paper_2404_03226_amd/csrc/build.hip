@@ -3,7 +3,6 @@
 // simulation, and the cycle check (Kahn traversal from the tasks with zero
 // in-degree, as in Section 4.3 of the paper).
 #include <hip/hip_runtime.h>
-#include <hipcub/hipcub.hpp>
 
 #include <algorithm>
 #include <atomic>
@@ -73,9 +72,21 @@ void DevBuf::release() {
     bytes = 0;
 }
 
-// Bits of a packed (row, target) sort key: targets are DAG-local ids < 2^21.
-constexpr int kColBits = 21;
 enum { ERR_ROWPTR = 1, ERR_COL = 2, ERR_SELF = 4 };
+
+// Canonical rows are built where the input rows lie: each row is sorted and
+// its repeats dropped into a scratch copy at the row's own input offset, its
+// canonical length counted; an exclusive scan of those lengths places the
+// canonical rows, and a last pass moves them there.  Rows are sorted by
+// whoever fits them: a thread in registers (up to kSmallRow entries), one
+// wave in LDS (kWaveRow), a 256-thread work-group in LDS (kBlockRow), and
+// above that a work-group marks the row's targets in a bitmap of the DAG's
+// tasks and reads them back in order (targets are distinct task ids).
+constexpr int kSmallRow = 16;
+constexpr int kWaveRow = 1024;
+constexpr int kBlockRow = 16384;
+constexpr int kHugeSlots = 16;  // work-groups (and bitmaps) for rows above kBlockRow
+constexpr int32_t kPad = 0x7fffffff;
 
 __device__ __forceinline__ int32_t dag_of(const int64_t *toff, int32_t B, int64_t v) {
     int32_t lo = 0, hi = B - 1;  // last b with toff[b] <= v
@@ -87,68 +98,285 @@ __device__ __forceinline__ int32_t dag_of(const int64_t *toff, int32_t B, int64_
     return lo;
 }
 
-// One thread per task: check the row pointer and the row's targets, and emit
-// one packed key per edge.
-__global__ void k_rows(int32_t B, const int64_t *toff, const int64_t *eoff, const int32_t *rp, const int32_t *col,
-                       uint64_t *keys, int32_t *err) {
-    int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (v >= toff[B]) return;
-    int32_t b = dag_of(toff, B, v);
-    int64_t lv = v - toff[b];
-    int32_t n = (int32_t)(toff[b + 1] - toff[b]);
-    int64_t m = eoff[b + 1] - eoff[b];
-    const int32_t *r = rp + toff[b] + b;
-    int32_t a = r[lv], z = r[lv + 1];
+struct RowArgs {
+    int32_t B;
+    const int64_t *toff, *eoff;  // task offsets, input edge offsets
+    const int32_t *rp, *col;     // the caller's CSR
+    int32_t *tmp;                // [M] sorted, deduplicated rows at their input offsets
+    int32_t *outdeg;             // [N] canonical row lengths
+    int32_t *err;
+    int32_t *nwide;              // rows longer than kSmallRow ...
+    int64_t *wide;               // ... listed here
+    uint32_t *bits;              // [kHugeSlots][bit_words] bitmaps for the longest rows
+    int64_t bit_words;
+};
+
+// Row v of the global task order: its DAG, local id, task count and input
+// row [a, z) (local edge indices).
+struct Row {
+    int32_t b, lv, n, a, z;
+};
+
+__device__ __forceinline__ Row row_of(const RowArgs &A, int64_t v) {
+    Row r;
+    r.b = dag_of(A.toff, A.B, v);
+    r.lv = (int32_t)(v - A.toff[r.b]);
+    r.n = (int32_t)(A.toff[r.b + 1] - A.toff[r.b]);
+    const int32_t *p = A.rp + A.toff[r.b] + r.b;
+    r.a = p[r.lv];
+    r.z = p[r.lv + 1];
+    return r;
+}
+
+__device__ __forceinline__ int check_target(int32_t s, int32_t n, int32_t lv) {
+    return (s < 0 || s >= n) ? ERR_COL : (s == lv ? ERR_SELF : 0);
+}
+
+// Bitonic sorting network over a register array (all indices fold to
+// constants once the loops are unrolled).
+template <int P>
+__device__ __forceinline__ void sort_registers(int32_t (&x)[P]) {
+#pragma unroll
+    for (int k = 2; k <= P; k <<= 1)
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1)
+#pragma unroll
+            for (int i = 0; i < P; i++) {
+                const int l = i ^ j;
+                if (l > i) {
+                    const int32_t lo = min(x[i], x[l]), hi = max(x[i], x[l]);
+                    const bool up = (i & k) == 0;
+                    x[i] = up ? lo : hi;
+                    x[l] = up ? hi : lo;
+                }
+            }
+}
+
+// One thread per task: validate the row pointer and, for short rows, the
+// targets; sort and deduplicate short rows in registers; list the others.
+__global__ __launch_bounds__(256) void k_rows(RowArgs A) {
+    const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (v >= A.toff[A.B]) return;
+    const Row r = row_of(A, v);
+    const int64_t m = A.eoff[r.b + 1] - A.eoff[r.b];
     int bad = 0;
-    if (lv == 0 && a != 0) bad |= ERR_ROWPTR;
-    if (lv == n - 1 && z != m) bad |= ERR_ROWPTR;
-    if (z < a || a < 0 || z > m) bad |= ERR_ROWPTR;
-    if (!bad) {
-        for (int32_t e = a; e < z; e++) {
-            int32_t s = col[eoff[b] + e];
-            if (s < 0 || s >= n) bad |= ERR_COL;
-            else if (s == lv) bad |= ERR_SELF;
-            keys[eoff[b] + e] = ((uint64_t)v << kColBits) | (uint32_t)(s & ((1 << kColBits) - 1));
+    if (r.lv == 0 && r.a != 0) bad |= ERR_ROWPTR;
+    if (r.lv == r.n - 1 && r.z != m) bad |= ERR_ROWPTR;
+    if (r.z < r.a || r.a < 0 || r.z > m) bad |= ERR_ROWPTR;
+    if (bad) {
+        atomicOr(A.err, bad);
+        A.outdeg[v] = 0;
+        return;
+    }
+    const int32_t deg = r.z - r.a;
+    if (deg > kSmallRow) {
+        A.wide[atomicAdd(A.nwide, 1)] = v;
+        return;
+    }
+    const int32_t *src = A.col + A.eoff[r.b] + r.a;
+    int32_t *dst = A.tmp + A.eoff[r.b] + r.a;
+    int32_t x[kSmallRow];
+#pragma unroll
+    for (int i = 0; i < kSmallRow; i++) {
+        x[i] = i < deg ? src[i] : kPad;
+        if (i < deg) bad |= check_target(x[i], r.n, r.lv);
+    }
+    sort_registers<kSmallRow>(x);
+    int32_t cnt = 0, prev = -1;
+#pragma unroll
+    for (int i = 0; i < kSmallRow; i++) {
+        if (i < deg && x[i] != prev) {
+            dst[cnt++] = x[i];
+            prev = x[i];
         }
     }
-    if (bad) atomicOr(err, bad);
+    A.outdeg[v] = cnt;
+    if (bad) atomicOr(A.err, bad);
 }
 
-// After sorting: flag the first copy of every (row, target) pair.
-__global__ void k_unique(int64_t M, const uint64_t *keys, int32_t *flag) {
-    int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (e >= M) return;
-    flag[e] = (e == 0 || keys[e] != keys[e - 1]) ? 1 : 0;
+// Bitonic sort of buf[0, P) in LDS by the work-group, then write the distinct
+// values of its first `deg` entries in order to dst; returns their count.
+template <int THREADS>
+__device__ int32_t sort_unique_lds(int32_t *buf, int32_t P, int32_t deg, int32_t *dst, int32_t *wcnt) {
+    const int tid = threadIdx.x;
+    for (int32_t k = 2; k <= P; k <<= 1)
+        for (int32_t j = k >> 1; j > 0; j >>= 1) {
+            for (int32_t i = tid; i < P; i += THREADS) {
+                const int32_t l = i ^ j;
+                if (l > i) {
+                    const int32_t a = buf[i], c = buf[l];
+                    const bool up = (i & k) == 0;
+                    if (up ? a > c : a < c) {
+                        buf[i] = c;
+                        buf[l] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    int32_t base = 0;
+    const int wv = tid / kWave;
+    for (int32_t i0 = 0; i0 < deg; i0 += THREADS) {
+        const int32_t i = i0 + tid;
+        const bool first = i < deg && (i == 0 || buf[i] != buf[i - 1]);
+        const uint64_t mk = ballot(first);
+        if ((tid & (kWave - 1)) == 0) wcnt[wv] = __popcll(mk);
+        __syncthreads();
+        int32_t off = base, tot = 0;
+        for (int w = 0; w < THREADS / kWave; w++) {
+            if (w < wv) off += wcnt[w];
+            tot += wcnt[w];
+        }
+        if (first) dst[off + lanes_below(mk)] = buf[i];
+        base += tot;
+        __syncthreads();
+    }
+    return base;
 }
 
-// Scatter unique edges, count canonical out-degrees, and accumulate the
-// in-degree and predecessor-id sum of each target.
-__global__ void k_scatter(int64_t M, const uint64_t *keys, const int32_t *flag, const int32_t *pos,
-                          const int64_t *toff, int32_t B, int32_t *col_out, int32_t *outdeg,
-                          unsigned long long *word0, int32_t *backward) {
-    int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (e >= M || !flag[e]) return;
-    uint64_t k = keys[e];
-    int64_t v = (int64_t)(k >> kColBits);
-    int32_t s = (int32_t)(k & ((1 << kColBits) - 1));
-    int32_t b = dag_of(toff, B, v);
-    int32_t lv = (int32_t)(v - toff[b]);
-    col_out[pos[e]] = s;
-    atomicAdd(&outdeg[v], 1);
-    // word0 = in-degree << 43 | sum of predecessor ids (fits: ids < 2^21)
-    atomicAdd(&word0[toff[b] + s], (1ull << 43) + (unsigned long long)lv);
-    if (s < lv) atomicOr(backward, 1 << 0), atomicOr(&backward[1 + (b >> 5)], 1 << (b & 31));
+// Rows of kSmallRow < deg <= LIMIT: one work-group of THREADS per listed row
+// (listed rows of other lengths are left to the other kernels).
+template <int THREADS, int LIMIT, int LOWER>
+__global__ __launch_bounds__(THREADS) void k_rows_lds(RowArgs A) {
+    __shared__ int32_t buf[LIMIT];
+    __shared__ int32_t wcnt[THREADS / kWave];
+    const int64_t v = A.wide[blockIdx.x];
+    const Row r = row_of(A, v);
+    const int32_t deg = r.z - r.a;
+    if (deg <= LOWER || deg > LIMIT) return;
+    const int32_t *src = A.col + A.eoff[r.b] + r.a;
+    int32_t P = 32;
+    while (P < deg) P <<= 1;
+    int bad = 0;
+    for (int32_t i = threadIdx.x; i < P; i += THREADS) {
+        const int32_t s = i < deg ? src[i] : kPad;
+        if (i < deg) bad |= check_target(s, r.n, r.lv);
+        buf[i] = s;
+    }
+    if (bad) atomicOr(A.err, bad);
+    __syncthreads();
+    const int32_t cnt = sort_unique_lds<THREADS>(buf, P, deg, A.tmp + A.eoff[r.b] + r.a, wcnt);
+    if (threadIdx.x == 0) A.outdeg[v] = cnt;
 }
 
-// Local row pointers from the global exclusive scan of out-degrees.
-__global__ void k_rowptr(int32_t B, const int64_t *toff, const int64_t *excl, const int32_t *outdeg,
-                         const int64_t *eoff_c, int32_t *rp_out) {
-    int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (v >= toff[B]) return;
-    int32_t b = dag_of(toff, B, v);
-    int64_t lv = v - toff[b];
-    rp_out[toff[b] + b + lv] = (int32_t)(excl[v] - eoff_c[b]);
-    if (lv == toff[b + 1] - toff[b] - 1) rp_out[toff[b] + b + lv + 1] = (int32_t)(excl[v] + outdeg[v] - eoff_c[b]);
+// Rows above kBlockRow: mark the targets in a bitmap of the DAG's tasks and
+// read them back in ascending order (a repeated target marks the same bit).
+__global__ __launch_bounds__(256) void k_rows_huge(RowArgs A, int32_t nlisted) {
+    __shared__ int64_t part[256 / kWave];
+    uint32_t *bm = A.bits + (int64_t)blockIdx.x * A.bit_words;
+    const int tid = threadIdx.x;
+    for (int32_t k = blockIdx.x; k < nlisted; k += gridDim.x) {
+        const int64_t v = A.wide[k];
+        const Row r = row_of(A, v);
+        const int32_t deg = r.z - r.a;
+        if (deg <= kBlockRow) continue;  // uniform over the work-group
+        const int32_t words = (r.n + 31) / 32;
+        for (int32_t w = tid; w < words; w += 256) bm[w] = 0;
+        __threadfence();
+        __syncthreads();
+        const int32_t *src = A.col + A.eoff[r.b] + r.a;
+        int bad = 0;
+        for (int32_t i = tid; i < deg; i += 256) {
+            const int32_t s = src[i];
+            const int e = check_target(s, r.n, r.lv);
+            bad |= e;
+            if (!(e & ERR_COL)) atomicOr(&bm[s >> 5], 1u << (s & 31));
+        }
+        if (bad) atomicOr(A.err, bad);
+        __threadfence();
+        __syncthreads();
+        // each thread reads back a contiguous run of words
+        const int32_t per = (words + 255) / 256, w0 = min(words, tid * per), w1 = min(words, w0 + per);
+        int64_t c = 0;
+        for (int32_t w = w0; w < w1; w++)
+            c += __popc(__hip_atomic_load(&bm[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        // block-wide exclusive scan of the counts
+        const int lane = tid & (kWave - 1), wv = tid / kWave;
+        int64_t inc = c;
+        for (int o = 1; o < kWave; o <<= 1) {
+            const int64_t y = __shfl_up(inc, o, kWave);
+            if (lane >= o) inc += y;
+        }
+        if (lane == kWave - 1) part[wv] = inc;
+        __syncthreads();
+        int64_t pos = inc - c, tot = 0;
+        for (int w = 0; w < 256 / kWave; w++) {
+            if (w < wv) pos += part[w];
+            tot += part[w];
+        }
+        int32_t *dst = A.tmp + A.eoff[r.b] + r.a;
+        for (int32_t w = w0; w < w1; w++) {
+            uint32_t x = __hip_atomic_load(&bm[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            while (x) {
+                dst[pos++] = w * 32 + (int32_t)__builtin_ctz(x);
+                x &= x - 1;
+            }
+        }
+        if (tid == 0) A.outdeg[v] = (int32_t)tot;
+        __syncthreads();  // part and the bitmap are reused by the next row
+    }
+}
+
+struct PlaceArgs {
+    int32_t B;
+    const int64_t *toff, *eoff;   // task offsets, input edge offsets
+    const int32_t *rp;            // the caller's row pointers
+    const int32_t *tmp, *outdeg;
+    const int64_t *excl;          // [N + 1] exclusive scan of outdeg: global canonical row starts
+    int32_t *col_out, *rp_out;
+    unsigned long long *word0;
+    int32_t *backward;            // [1 + ceil(B / 32)]: any edge to a lower id, per DAG bits
+};
+
+// Move row v's canonical targets to their place and account the edges in
+// the targets' dependency words (in-degree << 43 | sum of predecessor ids).
+__device__ __forceinline__ void place_edge(const PlaceArgs &A, int32_t b, int32_t lv, int32_t s, int64_t to,
+                                           bool &back) {
+    A.col_out[to] = s;
+    atomicAdd(&A.word0[A.toff[b] + s], (1ull << 43) + (unsigned long long)lv);
+    back |= s < lv;
+}
+
+// One thread per task: the canonical row pointer, and the row itself when
+// it is short.
+__global__ __launch_bounds__(256) void k_place(PlaceArgs A) {
+    const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (v >= A.toff[A.B]) return;
+    const int32_t b = dag_of(A.toff, A.B, v);
+    const int32_t lv = (int32_t)(v - A.toff[b]);
+    const int32_t n = (int32_t)(A.toff[b + 1] - A.toff[b]);
+    const int64_t e0 = A.excl[A.toff[b]];  // the DAG's first canonical edge
+    const int64_t at = A.excl[v];
+    const int32_t cnt = A.outdeg[v];
+    A.rp_out[A.toff[b] + b + lv] = (int32_t)(at - e0);
+    if (lv == n - 1) A.rp_out[A.toff[b] + b + n] = (int32_t)(at + cnt - e0);
+    const int32_t *p = A.rp + A.toff[b] + b;
+    if (p[lv + 1] - p[lv] > kSmallRow) return;  // a listed row: k_place_wide
+    const int32_t *src = A.tmp + A.eoff[b] + p[lv];
+    bool back = false;
+    for (int32_t i = 0; i < cnt; i++) place_edge(A, b, lv, src[i], at + i, back);
+    if (back) atomicOr(A.backward, 1), atomicOr(&A.backward[1 + (b >> 5)], 1 << (b & 31));
+}
+
+// One wave per listed (long) row.
+__global__ __launch_bounds__(64) void k_place_wide(PlaceArgs A, const int64_t *wide) {
+    const int64_t v = wide[blockIdx.x];
+    const int32_t b = dag_of(A.toff, A.B, v);
+    const int32_t lv = (int32_t)(v - A.toff[b]);
+    const int32_t *p = A.rp + A.toff[b] + b;
+    const int32_t *src = A.tmp + A.eoff[b] + p[lv];
+    const int64_t at = A.excl[v];
+    const int32_t cnt = A.outdeg[v];
+    bool back = false;
+    for (int32_t i = threadIdx.x; i < cnt; i += 64) place_edge(A, b, lv, src[i], at + i, back);
+    if (ballot(back) && threadIdx.x == 0)
+        atomicOr(A.backward, 1), atomicOr(&A.backward[1 + (b >> 5)], 1 << (b & 31));
+}
+
+// Each DAG's first canonical edge (and the total after the last DAG).
+__global__ void k_dag_edges(int32_t B, const int64_t *toff, const int64_t *excl, int64_t *eoff_c) {
+    const int32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b <= B) eoff_c[b] = excl[toff[b]];
 }
 
 // Kahn traversal of one DAG per work-group (used only when some edge points
@@ -213,27 +441,6 @@ extern "C" int insp_dag_info(const insp_dag *dag, int32_t index, int64_t *n_task
     return INSP_OK;
 }
 
-namespace {
-
-struct Scratch {
-    std::vector<void *> ptrs;
-    ~Scratch() {
-        for (void *p : ptrs) (void)hipFree(p);
-    }
-    template <typename T>
-    int get(T **out, size_t count) {
-        void *p = nullptr;
-        hipError_t e = hipMalloc(&p, std::max<size_t>(count * sizeof(T), 16));
-        if (e != hipSuccess)
-            return set_error(INSP_E_NOMEM, "hipMalloc(%zu) failed: %s", count * sizeof(T), hipGetErrorString(e));
-        ptrs.push_back(p);
-        *out = static_cast<T *>(p);
-        return INSP_OK;
-    }
-};
-
-}  // namespace
-
 extern "C" int insp_build_dag(int32_t n_dags, const int64_t *task_off, const int64_t *edge_off,
                               const int32_t *row_ptr, const int32_t *col, const int32_t *type, void *stream_,
                               insp_dag **out) {
@@ -241,12 +448,14 @@ extern "C" int insp_build_dag(int32_t n_dags, const int64_t *task_off, const int
     *out = nullptr;
     if (n_dags < 1 || !task_off || !edge_off) return set_error(INSP_E_INVAL, "need n_dags >= 1 and offsets");
     if (task_off[0] != 0 || edge_off[0] != 0) return set_error(INSP_E_INVAL, "offsets must start at 0");
+    int32_t max_n = 0;
     for (int32_t b = 0; b < n_dags; b++) {
         int64_t n = task_off[b + 1] - task_off[b], m = edge_off[b + 1] - edge_off[b];
         if (n < 0 || m < 0) return set_error(INSP_E_INVAL, "offsets of DAG %d decrease", b);
         if (n > INSP_MAX_TASKS) return set_error(INSP_E_RANGE, "DAG %d has %lld tasks (max 2^21)", b, (long long)n);
         if (m >= ((int64_t)1 << 31)) return set_error(INSP_E_RANGE, "DAG %d has too many edges", b);
         if (n == 0 && m != 0) return set_error(INSP_E_INVAL, "DAG %d has edges but no tasks", b);
+        max_n = std::max<int32_t>(max_n, (int32_t)n);
     }
     const int64_t N = task_off[n_dags], M = edge_off[n_dags];
     if (N > 0 && (!row_ptr || (M > 0 && !col))) return set_error(INSP_E_INVAL, "null row_ptr/col");
@@ -258,109 +467,113 @@ extern "C" int insp_build_dag(int32_t n_dags, const int64_t *task_off, const int
     d->N = N;
     d->toff.assign(task_off, task_off + n_dags + 1);
     int rc;
-    if ((rc = d->d_toff.alloc(sizeof(int64_t) * (n_dags + 1)))) return rc;
-    INSP_HIP(hipMemcpyAsync(d->d_toff.p, task_off, sizeof(int64_t) * (n_dags + 1), hipMemcpyHostToDevice, st));
-    Scratch s;
-    int64_t *d_eoff_in;
-    if ((rc = s.get(&d_eoff_in, n_dags + 1))) return rc;
-    INSP_HIP(hipMemcpyAsync(d_eoff_in, edge_off, sizeof(int64_t) * (n_dags + 1), hipMemcpyHostToDevice, st));
-
-    uint64_t *keys, *keys_sorted;
-    int32_t *err, *flag, *pos, *outdeg, *backward;
-    int64_t *excl;
     const int nbw = 1 + (n_dags + 31) / 32;
-    if ((rc = s.get(&keys, M)) || (rc = s.get(&keys_sorted, M)) || (rc = s.get(&err, 1)) ||
-        (rc = s.get(&flag, M)) || (rc = s.get(&pos, M + 1)) || (rc = s.get(&outdeg, N)) ||
-        (rc = s.get(&backward, nbw)) || (rc = s.get(&excl, N + 1)))
+    DevBuf eoff_in, tmp, outdeg, excl, err, nwide, wide, backward, eoff_c;
+    if ((rc = d->d_toff.alloc(sizeof(int64_t) * (n_dags + 1))) || (rc = eoff_in.alloc(sizeof(int64_t) * (n_dags + 1))) ||
+        (rc = tmp.alloc(sizeof(int32_t) * M)) || (rc = outdeg.alloc(sizeof(int32_t) * N)) ||
+        (rc = excl.alloc(sizeof(int64_t) * (N + 1))) || (rc = err.alloc(sizeof(int32_t))) ||
+        (rc = nwide.alloc(sizeof(int32_t))) || (rc = wide.alloc(sizeof(int64_t) * N)) ||
+        (rc = backward.alloc(sizeof(int32_t) * nbw)) || (rc = eoff_c.alloc(sizeof(int64_t) * (n_dags + 1))))
         return rc;
-    INSP_HIP(hipMemsetAsync(err, 0, sizeof(int32_t), st));
-    INSP_HIP(hipMemsetAsync(backward, 0, sizeof(int32_t) * nbw, st));
-    INSP_HIP(hipMemsetAsync(outdeg, 0, sizeof(int32_t) * std::max<int64_t>(N, 1), st));
-    if ((rc = d->word0.alloc(sizeof(uint64_t) * N))) return rc;
-    INSP_HIP(hipMemsetAsync(d->word0.p, 0, sizeof(uint64_t) * std::max<int64_t>(N, 1), st));
+    INSP_HIP(hipMemcpyAsync(d->d_toff.p, task_off, sizeof(int64_t) * (n_dags + 1), hipMemcpyHostToDevice, st));
+    INSP_HIP(hipMemcpyAsync(eoff_in.p, edge_off, sizeof(int64_t) * (n_dags + 1), hipMemcpyHostToDevice, st));
+    INSP_HIP(hipMemsetAsync(err.p, 0, sizeof(int32_t), st));
+    INSP_HIP(hipMemsetAsync(nwide.p, 0, sizeof(int32_t), st));
+    INSP_HIP(hipMemsetAsync(backward.p, 0, sizeof(int32_t) * nbw, st));
 
-    if (N > 0)
-        hipLaunchKernelGGL(k_rows, dim3(grid_for(N, 256)), dim3(256), 0, st, n_dags, d->d_toff.as<int64_t>(),
-                           d_eoff_in, row_ptr, col, keys, err);
+    // Sort and deduplicate every row where it lies; validate the CSR.
+    RowArgs ra;
+    ra.B = n_dags;
+    ra.toff = d->d_toff.as<int64_t>();
+    ra.eoff = eoff_in.as<int64_t>();
+    ra.rp = row_ptr;
+    ra.col = col;
+    ra.tmp = tmp.as<int32_t>();
+    ra.outdeg = outdeg.as<int32_t>();
+    ra.err = err.as<int32_t>();
+    ra.nwide = nwide.as<int32_t>();
+    ra.wide = wide.as<int64_t>();
+    ra.bits = nullptr;
+    ra.bit_words = 0;
+    if (N > 0) hipLaunchKernelGGL(k_rows, dim3(grid_for(N, 256)), dim3(256), 0, st, ra);
     INSP_HIP(hipGetLastError());
-    int32_t h_err = 0;
-    INSP_HIP(hipMemcpyAsync(&h_err, err, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    int32_t h_err = 0, h_wide = 0;
+    INSP_HIP(hipMemcpyAsync(&h_err, err.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    INSP_HIP(hipMemcpyAsync(&h_wide, nwide.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     INSP_HIP(hipStreamSynchronize(st));
+    if (!(h_err & ERR_ROWPTR) && h_wide > 0) {
+        // the listed rows: a wave each up to kWaveRow entries, a work-group
+        // each up to kBlockRow, bitmaps above (each kernel skips the others' rows)
+        hipLaunchKernelGGL((k_rows_lds<64, kWaveRow, kSmallRow>), dim3((unsigned)h_wide), dim3(64), 0, st, ra);
+        hipLaunchKernelGGL((k_rows_lds<256, kBlockRow, kWaveRow>), dim3((unsigned)h_wide), dim3(256), 0, st, ra);
+        DevBuf bits;
+        ra.bit_words = (max_n + 31) / 32;
+        if ((rc = bits.alloc(sizeof(uint32_t) * ra.bit_words * kHugeSlots))) return rc;
+        ra.bits = bits.as<uint32_t>();
+        hipLaunchKernelGGL(k_rows_huge, dim3((unsigned)std::min(h_wide, kHugeSlots)), dim3(256), 0, st, ra, h_wide);
+        INSP_HIP(hipGetLastError());
+        INSP_HIP(hipMemcpyAsync(&h_err, err.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        INSP_HIP(hipStreamSynchronize(st));  // before the bitmaps are released
+    }
     if (h_err & ERR_ROWPTR) return set_error(INSP_E_INVAL, "row_ptr is not a valid CSR row pointer");
     if (h_err & ERR_COL) return set_error(INSP_E_INVAL, "successor id out of range");
     if (h_err & ERR_SELF) return set_error(INSP_E_INVAL, "self loop");
 
-    // Sort packed (global row, local target) keys: rows become contiguous
-    // and ascending, targets ascending inside a row, repeats adjacent.
-    int end_bit = kColBits;
-    while (end_bit < 64 && (((uint64_t)std::max<int64_t>(N, 1)) >> (end_bit - kColBits)) != 0) end_bit++;
-    size_t tmp_bytes = 0;
-    if (M > 0) {
-        INSP_HIP(hipcub::DeviceRadixSort::SortKeys(nullptr, tmp_bytes, keys, keys_sorted, (int)M, 0, end_bit, st));
-        uint8_t *tmp;
-        if ((rc = s.get(&tmp, tmp_bytes))) return rc;
-        INSP_HIP(hipcub::DeviceRadixSort::SortKeys(tmp, tmp_bytes, keys, keys_sorted, (int)M, 0, end_bit, st));
-        hipLaunchKernelGGL(k_unique, dim3(grid_for(M, 256)), dim3(256), 0, st, M, keys_sorted, flag);
-        size_t t2 = 0;
-        INSP_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, t2, flag, pos, (int)M, st));
-        uint8_t *tmp2;
-        if ((rc = s.get(&tmp2, t2))) return rc;
-        INSP_HIP(hipcub::DeviceScan::ExclusiveSum(tmp2, t2, flag, pos, (int)M, st));
-    }
-    int32_t h_last[2] = {0, 0};
-    if (M > 0) {
-        INSP_HIP(hipMemcpyAsync(&h_last[0], pos + M - 1, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-        INSP_HIP(hipMemcpyAsync(&h_last[1], flag + M - 1, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    }
-    INSP_HIP(hipStreamSynchronize(st));
-    const int64_t Mc = M > 0 ? (int64_t)h_last[0] + h_last[1] : 0;
-    d->M = Mc;
-    if ((rc = d->col.alloc(sizeof(int32_t) * Mc))) return rc;
-    if (M > 0)
-        hipLaunchKernelGGL(k_scatter, dim3(grid_for(M, 256)), dim3(256), 0, st, M, keys_sorted, flag, pos,
-                           d->d_toff.as<int64_t>(), n_dags, d->col.as<int32_t>(), outdeg,
-                           d->word0.as<unsigned long long>(), backward);
+    // Place the canonical rows: an exclusive scan of their lengths gives the
+    // global row starts; DAG b's local row pointers subtract its first edge.
+    if ((rc = exclusive_scan(outdeg.as<int32_t>(), N, excl.as<int64_t>(), st))) return rc;
+    hipLaunchKernelGGL(k_dag_edges, dim3(grid_for(n_dags + 1, 256)), dim3(256), 0, st, n_dags,
+                       d->d_toff.as<int64_t>(), excl.as<int64_t>(), eoff_c.as<int64_t>());
     INSP_HIP(hipGetLastError());
-
-    // Canonical row pointers: global exclusive scan of out-degrees, made
-    // local by subtracting each DAG's first canonical edge.
-    std::vector<int32_t> h_outdeg(N);
-    if (N > 0) INSP_HIP(hipMemcpyAsync(h_outdeg.data(), outdeg, sizeof(int32_t) * N, hipMemcpyDeviceToHost, st));
-    INSP_HIP(hipStreamSynchronize(st));
-    std::vector<int64_t> h_excl(N + 1, 0);
-    for (int64_t v = 0; v < N; v++) h_excl[v + 1] = h_excl[v] + h_outdeg[v];
     d->eoff.resize(n_dags + 1);
-    for (int32_t b = 0; b <= n_dags; b++) d->eoff[b] = h_excl[task_off[b]];
-    if ((rc = d->d_eoff.alloc(sizeof(int64_t) * (n_dags + 1)))) return rc;
-    INSP_HIP(hipMemcpyAsync(d->d_eoff.p, d->eoff.data(), sizeof(int64_t) * (n_dags + 1), hipMemcpyHostToDevice, st));
-    INSP_HIP(hipMemcpyAsync(excl, h_excl.data(), sizeof(int64_t) * (N + 1), hipMemcpyHostToDevice, st));
-    if ((rc = d->rp.alloc(sizeof(int32_t) * (N + n_dags)))) return rc;
+    INSP_HIP(hipMemcpyAsync(d->eoff.data(), eoff_c.p, sizeof(int64_t) * (n_dags + 1), hipMemcpyDeviceToHost, st));
+    INSP_HIP(hipStreamSynchronize(st));
+    const int64_t Mc = d->eoff[n_dags];
+    d->M = Mc;
+    if ((rc = d->col.alloc(sizeof(int32_t) * Mc)) || (rc = d->rp.alloc(sizeof(int32_t) * (N + n_dags))) ||
+        (rc = d->word0.alloc(sizeof(uint64_t) * N)) || (rc = d->d_eoff.alloc(sizeof(int64_t) * (n_dags + 1))))
+        return rc;
+    INSP_HIP(hipMemcpyAsync(d->d_eoff.p, eoff_c.p, sizeof(int64_t) * (n_dags + 1), hipMemcpyDeviceToDevice, st));
     INSP_HIP(hipMemsetAsync(d->rp.p, 0, sizeof(int32_t) * (N + n_dags), st));  // empty DAGs: rp = {0}
-    if (N > 0)
-        hipLaunchKernelGGL(k_rowptr, dim3(grid_for(N, 256)), dim3(256), 0, st, n_dags, d->d_toff.as<int64_t>(),
-                           excl, outdeg, d->d_eoff.as<int64_t>(), d->rp.as<int32_t>());
+    INSP_HIP(hipMemsetAsync(d->word0.p, 0, sizeof(uint64_t) * std::max<int64_t>(N, 1), st));
+    PlaceArgs pa;
+    pa.B = n_dags;
+    pa.toff = d->d_toff.as<int64_t>();
+    pa.eoff = eoff_in.as<int64_t>();
+    pa.rp = row_ptr;
+    pa.tmp = tmp.as<int32_t>();
+    pa.outdeg = outdeg.as<int32_t>();
+    pa.excl = excl.as<int64_t>();
+    pa.col_out = d->col.as<int32_t>();
+    pa.rp_out = d->rp.as<int32_t>();
+    pa.word0 = d->word0.as<unsigned long long>();
+    pa.backward = backward.as<int32_t>();
+    if (N > 0) hipLaunchKernelGGL(k_place, dim3(grid_for(N, 256)), dim3(256), 0, st, pa);
+    if (h_wide > 0)
+        hipLaunchKernelGGL(k_place_wide, dim3((unsigned)h_wide), dim3(64), 0, st, pa, (const int64_t *)wide.as<int64_t>());
     INSP_HIP(hipGetLastError());
 
     // Cycle check: with every edge pointing to a higher id the id order is a
     // topological order; otherwise run Kahn's traversal on the DAGs concerned.
     std::vector<int32_t> h_back(nbw);
-    INSP_HIP(hipMemcpyAsync(h_back.data(), backward, sizeof(int32_t) * nbw, hipMemcpyDeviceToHost, st));
+    INSP_HIP(hipMemcpyAsync(h_back.data(), backward.p, sizeof(int32_t) * nbw, hipMemcpyDeviceToHost, st));
     INSP_HIP(hipStreamSynchronize(st));
     if (h_back[0]) {
         std::vector<int32_t> todo;
         for (int32_t b = 0; b < n_dags; b++)
             if (h_back[1 + (b >> 5)] >> (b & 31) & 1) todo.push_back(b);
-        int32_t *d_todo, *indeg, *queue, *visited;
-        if ((rc = s.get(&d_todo, todo.size())) || (rc = s.get(&indeg, N)) || (rc = s.get(&queue, N)) ||
-            (rc = s.get(&visited, todo.size())))
+        DevBuf d_todo, indeg, queue, visited;
+        if ((rc = d_todo.alloc(sizeof(int32_t) * todo.size())) || (rc = indeg.alloc(sizeof(int32_t) * N)) ||
+            (rc = queue.alloc(sizeof(int32_t) * N)) || (rc = visited.alloc(sizeof(int32_t) * todo.size())))
             return rc;
-        INSP_HIP(hipMemcpyAsync(d_todo, todo.data(), sizeof(int32_t) * todo.size(), hipMemcpyHostToDevice, st));
-        hipLaunchKernelGGL(k_kahn, dim3((unsigned)todo.size()), dim3(256), 0, st, d_todo, d->d_toff.as<int64_t>(),
-                           d->d_eoff.as<int64_t>(), d->rp.as<int32_t>(), d->col.as<int32_t>(),
-                           d->word0.as<unsigned long long>(), indeg, queue, visited);
+        INSP_HIP(hipMemcpyAsync(d_todo.p, todo.data(), sizeof(int32_t) * todo.size(), hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL(k_kahn, dim3((unsigned)todo.size()), dim3(256), 0, st, d_todo.as<int32_t>(),
+                           d->d_toff.as<int64_t>(), d->d_eoff.as<int64_t>(), d->rp.as<int32_t>(), d->col.as<int32_t>(),
+                           d->word0.as<unsigned long long>(), indeg.as<int32_t>(), queue.as<int32_t>(),
+                           visited.as<int32_t>());
         INSP_HIP(hipGetLastError());
         std::vector<int32_t> h_vis(todo.size());
-        INSP_HIP(hipMemcpyAsync(h_vis.data(), visited, sizeof(int32_t) * todo.size(), hipMemcpyDeviceToHost, st));
+        INSP_HIP(hipMemcpyAsync(h_vis.data(), visited.p, sizeof(int32_t) * todo.size(), hipMemcpyDeviceToHost, st));
         INSP_HIP(hipStreamSynchronize(st));
         for (size_t i = 0; i < todo.size(); i++) {
             int32_t b = todo[i];

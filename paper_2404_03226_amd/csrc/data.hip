@@ -1,7 +1,6 @@
 // Data model support: per-task output sizes on the handle, and predecessor
 // lists (a task's inputs are its predecessors' outputs), built once.
 #include <hip/hip_runtime.h>
-#include <hipcub/hipcub.hpp>
 
 #include <algorithm>
 
@@ -62,9 +61,9 @@ __global__ __launch_bounds__(256) void k_check_kib(int64_t N, const int32_t *kib
 int ensure_preds(insp_dag *dag, hipStream_t st) {
     if (dag->ppred.p) return INSP_OK;
     const int64_t N = std::max<int64_t>(dag->N, 1), M = std::max<int64_t>(dag->M, 1);
-    DevBuf indeg, excl, fill, tmp, ppred;
+    DevBuf indeg, excl, fill, ppred;
     int rc;
-    if ((rc = indeg.alloc(sizeof(int64_t) * N)) || (rc = excl.alloc(sizeof(int64_t) * N)) ||
+    if ((rc = indeg.alloc(sizeof(int64_t) * N)) || (rc = excl.alloc(sizeof(int64_t) * (N + 1))) ||
         (rc = fill.alloc(sizeof(int32_t) * N)) || (rc = dag->pprp.alloc(sizeof(int32_t) * (N + dag->B))) ||
         (rc = ppred.alloc(sizeof(int32_t) * M)))
         return rc;
@@ -74,12 +73,7 @@ int ensure_preds(insp_dag *dag, hipStream_t st) {
         const unsigned g = (unsigned)((dag->N + 255) / 256);
         hipLaunchKernelGGL(k_indeg, dim3(g), dim3(256), 0, st, dag->N, dag->word0.as<unsigned long long>(),
                            indeg.as<int64_t>());
-        size_t tb = 0;
-        INSP_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tb, indeg.as<int64_t>(), excl.as<int64_t>(), (int)dag->N,
-                                                  st));
-        if ((rc = tmp.alloc(tb))) return rc;
-        INSP_HIP(hipcub::DeviceScan::ExclusiveSum(tmp.p, tb, indeg.as<int64_t>(), excl.as<int64_t>(), (int)dag->N,
-                                                  st));
+        if ((rc = exclusive_scan(indeg.as<int64_t>(), dag->N, excl.as<int64_t>(), st))) return rc;
         hipLaunchKernelGGL(k_pred_rows, dim3(g), dim3(256), 0, st, dag->B, dag->d_toff.as<int64_t>(),
                            dag->d_eoff.as<int64_t>(), excl.as<int64_t>(), indeg.as<int64_t>(), dag->pprp.as<int32_t>());
         hipLaunchKernelGGL(k_pred_fill, dim3(g), dim3(256), 0, st, dag->B, dag->d_toff.as<int64_t>(),

@@ -192,6 +192,11 @@ int run_attributes(insp_dag *dag, Workspace *ws, const int32_t *est, int32_t uni
 // on the first call).  Runs after run_attributes, which clears the status.
 int run_rank(insp_dag *dag, Workspace *ws, const int32_t *est, hipStream_t st);
 
+// Exclusive prefix sum of n values into out[0 .. n] (out[n] = the total),
+// enqueued on `st` (the call may synchronise `st` before it returns).
+int exclusive_scan(const int32_t *in, int64_t n, int64_t *out, hipStream_t st);
+int exclusive_scan(const int64_t *in, int64_t n, int64_t *out, hipStream_t st);
+
 // Predecessor lists of every DAG of the handle (built once).
 int ensure_preds(insp_dag *dag, hipStream_t st);
 

@@ -132,7 +132,7 @@ def _long_tasks(n, n_cpu, n_gpu, edges, seed):
     st = synth.Stream(seed, 5)
     src, dst = [], []
     for k in range(edges):
-        a, b = sorted(int(x) for x in st.randint(np.array([2 * k, 2 * k + 1]), 0, n))
+        a, b = sorted(int(x) for x in st.randint(np.array([2 * k, 2 * k + 1]), 0, n - 1))
         if a != b:
             src.append(a)
             dst.append(b)
@@ -142,8 +142,8 @@ def _long_tasks(n, n_cpu, n_gpu, edges, seed):
     np.add.at(rp, src + 1, 1)
     rp = np.cumsum(rp).astype(np.int32)
     lo = 1 << 19
-    dur = (lo + st.randint(np.arange(10_000, 10_000 + 2 * n), 0, lo + 1)).reshape(n, 2).astype(np.int32)
-    est = (lo + st.randint(np.arange(20_000, 20_000 + 2 * n), 0, lo + 1)).reshape(n, 2).astype(np.int32)
+    dur = (lo + st.randint(np.arange(10_000, 10_000 + 2 * n), 0, lo)).reshape(n, 2).astype(np.int32)
+    est = (lo + st.randint(np.arange(20_000, 20_000 + 2 * n), 0, lo)).reshape(n, 2).astype(np.int32)
     return synth.Workload(f"long{seed}", n, rp, dst, np.zeros(n, np.int32), dur, est, n_cpu, n_gpu)
 
 
@@ -271,6 +271,91 @@ def test_error_codes_through_abi(insp):
         insp.schedule(dag, 0, (0, 0), d, d)
     assert e.value.code == insp.E_RANGE
     dag.free()
+
+
+def _wide_rows_dag(n, lengths, seed, backward=False):
+    """A DAG whose first rows have the given lengths (targets drawn with
+    repeats, in random order, from later ids -- or from any other id when
+    `backward`, ids then relabelled so that the graph stays acyclic), the
+    other rows 0..3 later targets."""
+    st = synth.Stream(seed, 9)
+    rows = []
+    k = 0
+    for v in range(n):
+        d = lengths[v] if v < len(lengths) else int(st.randint(np.array([k]), 0, 3)[0])
+        k += 1
+        lo = v + 1
+        if lo >= n or d == 0:
+            rows.append(np.zeros(0, np.int64))
+            continue
+        t = st.randint(np.arange(k, k + d), lo, n - 1)
+        k += d
+        rows.append(t)
+    rp = np.concatenate([[0], np.cumsum([len(r) for r in rows])]).astype(np.int32)
+    col = np.concatenate(rows).astype(np.int32) if rp[-1] else np.zeros(0, np.int32)
+    if backward:
+        # relabel ids by a permutation: edges then point both ways, no cycle
+        perm = np.argsort(st.uniform(np.arange(10 ** 7, 10 ** 7 + n)))
+        inv = np.empty(n, np.int64)
+        inv[perm] = np.arange(n)
+        new_rows = [None] * n
+        for v in range(n):
+            new_rows[inv[v]] = inv[col[rp[v]:rp[v + 1]]]
+        rp = np.concatenate([[0], np.cumsum([len(r) for r in new_rows])]).astype(np.int32)
+        col = np.concatenate(new_rows).astype(np.int32)
+    ty = np.zeros(n, np.int32)
+    dur = (1 + st.randint(np.arange(3 * 10 ** 7, 3 * 10 ** 7 + 2 * n), 0, 50)).reshape(n, 2).astype(np.int32)
+    return synth.Workload(f"wide{seed}", n, rp, col, ty, dur, dur.copy(), 6, 2)
+
+
+@pytest.mark.parametrize("backward", [False, True])
+def test_build_rows_of_every_length(insp, backward):
+    """Canonical rows (sorted, repeats merged) whatever sorts them: rows of
+    up to 16 targets in registers, up to 1,024 by one wave, up to 16,384 by a
+    work-group, longer ones through a bitmap -- each length at and past its
+    limit, with repeated targets, and with ids relabelled so that edges point
+    both ways (the Kahn check).  Out-degrees against the oracle's canonical
+    CSR, schedules against the oracle."""
+    import torch
+    lengths = [0, 1, 16, 17, 1024, 1025, 16384, 16385, 40000, 3, 200]
+    w = _wide_rows_dag(60000, lengths, seed=41 + backward, backward=backward)
+    say("build rows", backward, w.m)
+    rp, col = oracle.canon(w.n, w.row_ptr, w.col)
+    dag, dur, est = insp.to_device(w)
+    assert dag.m == [len(col)]
+    ia, ie, U = insp.attributes(dag, 0, est, (w.n_cpu, w.n_gpu))
+    ria, rie, rU = oracle.attributes(w.n, rp, col, w.est, w.n_gpu)
+    assert np.array_equal(ia.cpu().numpy(), np.diff(rp)) and np.array_equal(ie.cpu().numpy(), rie) and U[0] == rU
+    dag.free()
+    g = run_gpu(insp, w)
+    assert_same(g, oracle.schedule(w, variant=oracle.HEAP), "wide rows")
+
+
+@pytest.mark.parametrize("where", [1, 5, 7, 8])
+def test_build_rejects_bad_targets_in_long_rows(insp, where):
+    """A self loop or an id out of range in a row of each sorting path is
+    refused (E_INVAL); a back edge closing a cycle through a long row is
+    E_CYCLE."""
+    import torch
+    lengths = [0, 1, 16, 17, 1024, 1025, 16384, 16385, 40000]
+    w = _wide_rows_dag(50000, lengths, seed=43)
+    say("build bad target", where)
+    a = int(w.row_ptr[where])
+    for bad, code in ((where, insp.E_INVAL), (w.n + 3, insp.E_INVAL), (-1, insp.E_INVAL), (0, insp.E_CYCLE)):
+        col = w.col.copy()
+        col[a + (int(w.row_ptr[where + 1]) - a) // 2] = bad
+        if code == insp.E_CYCLE:
+            # where -> 0 closes a cycle only if 0 reaches `where`: add 0 -> where
+            rows = [list(col[w.row_ptr[v]:w.row_ptr[v + 1]]) for v in range(w.n)]
+            rows[0] = [where]
+            rp = np.concatenate([[0], np.cumsum([len(r) for r in rows])]).astype(np.int32)
+            col = np.concatenate([np.asarray(r, np.int32) for r in rows])
+        else:
+            rp = w.row_ptr
+        with pytest.raises(insp.InspError) as e:
+            insp.build_dag([0, w.n], [0, len(col)], torch.from_numpy(np.asarray(rp, np.int32)).cuda(),
+                           torch.from_numpy(np.asarray(col, np.int32)).cuda())
+        assert e.value.code == code, (bad, e.value)
 
 
 def test_failures_are_kept_until_reported(insp):
