@@ -270,6 +270,35 @@ int insp_schedule_batch(const insp_dag *dag, const insp_workers *workers, const 
                         int64_t *makespan, int32_t *ie_at_pop, int8_t *mode_at_pop, const char *tune_key,
                         void *stream);
 
+/*
+ * insp_schedule_batch_noalloc -- insp_schedule_batch for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation.  Same arguments, results and status
+ * reporting (insp_sync_status) as insp_schedule_batch; the caller passes the
+ * inputs and outputs as before.  The call allocates nothing: the per-call
+ * state -- task records (32 B per task), frontier buffers (12 B per task),
+ * per-DAG attribute records and launch tables, and the queue pools (about
+ * 2,076 B per 64-task block, ceil(n/64) + W blocks and 4 W (ceil(n/64) + 1) B
+ * of block lists per DAG of n tasks on W workers) -- is carved out of one
+ * static device array of INSP_NOALLOC_SCRATCH_BYTES per GPU, which the
+ * library holds from the first call on that GPU until the process ends.  A
+ * batch needing more fails with INSP_E_RANGE before any device work.  Only
+ * the direct attributes without the data model are served (policies
+ * INSPIRIT, FIFO, ABILITY_ONLY and EFI_ONLY, attr_mode DIRECT, data_bw 0);
+ * the HEFT and locality policies, transitive attributes and the data model
+ * build handle state on first use and are INSP_E_INVAL here.  The launch
+ * tables are uploaded (and the stream synchronised) only when the handle or
+ * the machine shape differs from the previous call's on the same GPU.  All
+ * calls on one GPU share the array, which keeps the last call's contents:
+ * calls that overlap on one GPU (other streams, other host threads) race and
+ * must be serialised by the caller.
+ */
+#define INSP_NOALLOC_SCRATCH_BYTES ((int64_t)64 << 20)
+int insp_schedule_batch_noalloc(const insp_dag *dag, const insp_workers *workers, const int32_t *dur,
+                                const int32_t *est, const insp_params *params, int32_t *worker, int64_t *start,
+                                int64_t *finish, int64_t *makespan, int32_t *ie_at_pop, int8_t *mode_at_pop,
+                                const char *tune_key, void *stream);
+
 /* Synchronise `stream` and report a device-side failure of the schedule
  * calls (insp_schedule, insp_schedule_batch) enqueued on the handle since the
  * last check: INSP_E_HANG, or INSP_E_RANGE for a tick value out of range, a

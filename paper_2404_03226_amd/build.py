@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libinspirit.so")
-SOURCES = ["build.hip", "scan.hip", "attr.hip", "rank.hip", "trans.hip", "data.hip", "sim.hip", "prof.hip", "mlp.hip"]
+SOURCES = ["build.hip", "scan.hip", "attr.hip", "rank.hip", "trans.hip", "data.hip", "sim.hip", "noalloc.hip", "prof.hip", "mlp.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-Wall",

@@ -223,14 +223,14 @@ static AttrArgs make_args(insp_dag *dag, Workspace *ws, const int32_t *est, int3
     a.rem = rem;
     a.base = ws->base;
     a.unit_time = unit_time;
-    a.maxtau = dag->dag_maxtau.as<int32_t>();
-    a.score = dag->dag_score.as<int32_t>();
-    a.u = dag->dag_u.as<int32_t>();
-    a.taubar = dag->dag_taubar.as<int32_t>();
+    a.maxtau = ws->dag_maxtau;
+    a.score = ws->dag_score;
+    a.u = ws->dag_u;
+    a.taubar = ws->dag_taubar;
     a.stat = dag->dag_stat.as<int32_t>();
     a.sticky = dag->dag_sticky.as<int32_t>();
     a.anybad = ws->counter.as<int32_t>() + 3;
-    a.tausum = dag->dag_tausum.as<unsigned long long>();
+    a.tausum = ws->dag_tausum;
     return a;
 }
 
@@ -256,12 +256,23 @@ int run_attributes(insp_dag *dag, Workspace *ws, const int32_t *est, int32_t uni
     o.ia_out = ia_out;
     o.ie_out = ie_out;
     o.sim_init = sim_init ? 1 : 0;
-    o.tr = dag->tr.as<TaskRec>();
+    o.tr = ws->tr;
     if (ws->attr_blocks > 0) {
         ProfScope ps(st, "attr_b");
         hipLaunchKernelGGL(k_attr_b, dim3(ws->attr_blocks), dim3(kAttrThreads), 0, st, a, o);
     }
     INSP_HIP(hipGetLastError());
+    return INSP_OK;
+}
+
+int alloc_status(insp_dag *dag) {
+    int rc;
+    if ((rc = dag->dag_stat.alloc(8 * dag->B)) || (rc = dag->dag_astat.alloc(8 * dag->B)) ||
+        (rc = dag->dag_sticky.alloc(4 * dag->B)))
+        return rc;
+    INSP_HIP(hipMemset(dag->dag_stat.p, 0, 8 * dag->B));
+    INSP_HIP(hipMemset(dag->dag_astat.p, 0, 8 * dag->B));
+    INSP_HIP(hipMemset(dag->dag_sticky.p, 0, 4 * dag->B));
     return INSP_OK;
 }
 
@@ -273,15 +284,10 @@ int ensure_state(insp_dag *dag, hipStream_t st) {
     if ((rc = dag->tr.alloc(sizeof(TaskRec) * N)) || (rc = dag->fbuf.alloc(12 * N)) ||
         (rc = dag->dag_u.alloc(4 * dag->B)) ||
         (rc = dag->dag_taubar.alloc(4 * dag->B)) || (rc = dag->dag_maxtau.alloc(4 * dag->B)) ||
-        (rc = dag->dag_tausum.alloc(8 * dag->B)) || (rc = dag->dag_score.alloc(4 * kRungs * dag->B)) ||
-        (rc = dag->dag_stat.alloc(8 * dag->B)) || (rc = dag->dag_astat.alloc(8 * dag->B)) ||
-        (rc = dag->dag_sticky.alloc(4 * dag->B))) {
+        (rc = dag->dag_tausum.alloc(8 * dag->B)) || (rc = dag->dag_score.alloc(4 * kRungs * dag->B))) {
         dag->tr.release();
         return rc;
     }
-    INSP_HIP(hipMemset(dag->dag_stat.p, 0, 8 * dag->B));
-    INSP_HIP(hipMemset(dag->dag_astat.p, 0, 8 * dag->B));
-    INSP_HIP(hipMemset(dag->dag_sticky.p, 0, 4 * dag->B));
     return INSP_OK;
 }
 
@@ -292,28 +298,20 @@ static void pool_shape(int32_t n, int32_t W, int32_t *nblk, int32_t *maxb) {
     *maxb = (n + 63) / 64 + 1;
 }
 
-int get_workspace(insp_dag *dag, int32_t first, int32_t count, const insp_workers *workers, bool per_dag,
-                  Workspace **out) {
-    std::string key = std::to_string(first) + ":" + std::to_string(count);
-    for (int32_t i = 0; i < (per_dag ? count : 1); i++)
-        key += ":" + std::to_string(workers[i].n_cpu) + "," + std::to_string(workers[i].n_gpu);
-    auto it = dag->ws.find(key);
-    if (it != dag->ws.end()) {
-        *out = it->second.get();
-        return INSP_OK;
-    }
-    std::unique_ptr<Workspace> w(new Workspace());
+int64_t workspace_shape(const insp_dag *dag, int32_t first, int32_t count, const insp_workers *workers,
+                        bool per_dag, Workspace *w, std::vector<DagDesc> *desc, std::vector<int2> *blk) {
     w->count = count;
     w->first = first;
     w->base = dag->toff[first];
     w->tasks = dag->toff[first + count] - dag->toff[first];
-    std::vector<DagDesc> desc(count);
-    std::vector<int2> blk;
+    desc->assign(count, DagDesc());
+    blk->clear();
+    w->h_order.clear();
     int64_t boff = 0, wloff = 0;
     for (int32_t i = 0; i < count; i++) {
         const insp_workers &wk = workers[per_dag ? i : 0];
         int32_t b = first + i;
-        DagDesc &d = desc[i];
+        DagDesc &d = (*desc)[i];
         memset(&d, 0, sizeof d);
         d.id = b;
         d.toff = dag->toff[b];
@@ -329,25 +327,53 @@ int get_workspace(insp_dag *dag, int32_t first, int32_t count, const insp_worker
         wloff += (int64_t)(wk.n_cpu + wk.n_gpu) * d.maxb;
         w->max_w = std::max(w->max_w, wk.n_cpu + wk.n_gpu);
         w->max_nblk = std::max<int64_t>(w->max_nblk, d.nblk);
-        for (int32_t c = 0; c * kAttrThreads < d.n; c++) blk.push_back(make_int2(i, c));
+        for (int32_t c = 0; c * kAttrThreads < d.n; c++) blk->push_back(make_int2(i, c));
     }
-    w->attr_blocks = (int32_t)blk.size();
+    w->attr_blocks = (int32_t)blk->size();
     // simulation order: largest DAGs first
     for (int32_t b : dag->order)
         if (b >= first && b < first + count) w->h_order.push_back(b - first);
-    int rc;
     w->total_wl = wloff;
-    if ((rc = w->desc.alloc(sizeof(DagDesc) * count)) || (rc = w->blkmap.alloc(sizeof(int2) * blk.size())) ||
-        (rc = w->order.alloc(sizeof(int32_t) * count)) || (rc = w->slots.alloc(sizeof(Slot) * 64 * (size_t)boff)) ||
-        (rc = w->sums.alloc(16 * (size_t)boff)) || (rc = w->paux.alloc(4 * (size_t)(wloff + boff))) ||
-        (rc = w->barr.alloc(8 * (size_t)boff)) ||
-        (rc = w->counter.alloc(16)))
-        return rc;
-    INSP_HIP(hipMemcpy(w->desc.p, desc.data(), sizeof(DagDesc) * count, hipMemcpyHostToDevice));
-    if (!blk.empty()) INSP_HIP(hipMemcpy(w->blkmap.p, blk.data(), sizeof(int2) * blk.size(), hipMemcpyHostToDevice));
-    INSP_HIP(hipMemcpy(w->order.p, w->h_order.data(), sizeof(int32_t) * count, hipMemcpyHostToDevice));
-    *out = w.get();
-    dag->ws[key] = std::move(w);
+    return boff;
+}
+
+int get_workspace(insp_dag *dag, int32_t first, int32_t count, const insp_workers *workers, bool per_dag,
+                  Workspace **out) {
+    std::string key = std::to_string(first) + ":" + std::to_string(count);
+    for (int32_t i = 0; i < (per_dag ? count : 1); i++)
+        key += ":" + std::to_string(workers[i].n_cpu) + "," + std::to_string(workers[i].n_gpu);
+    auto it = dag->ws.find(key);
+    Workspace *w = nullptr;
+    if (it != dag->ws.end()) {
+        w = it->second.get();
+    } else {
+        std::unique_ptr<Workspace> nw(new Workspace());
+        std::vector<DagDesc> desc;
+        std::vector<int2> blk;
+        const int64_t boff = workspace_shape(dag, first, count, workers, per_dag, nw.get(), &desc, &blk);
+        int rc;
+        if ((rc = nw->desc.alloc(sizeof(DagDesc) * count)) || (rc = nw->blkmap.alloc(sizeof(int2) * blk.size())) ||
+            (rc = nw->order.alloc(sizeof(int32_t) * count)) || (rc = nw->slots.alloc(sizeof(Slot) * 64 * (size_t)boff)) ||
+            (rc = nw->sums.alloc(16 * (size_t)boff)) || (rc = nw->paux.alloc(4 * (size_t)(nw->total_wl + boff))) ||
+            (rc = nw->barr.alloc(8 * (size_t)boff)) ||
+            (rc = nw->counter.alloc(16)))
+            return rc;
+        INSP_HIP(hipMemcpy(nw->desc.p, desc.data(), sizeof(DagDesc) * count, hipMemcpyHostToDevice));
+        if (!blk.empty())
+            INSP_HIP(hipMemcpy(nw->blkmap.p, blk.data(), sizeof(int2) * blk.size(), hipMemcpyHostToDevice));
+        INSP_HIP(hipMemcpy(nw->order.p, nw->h_order.data(), sizeof(int32_t) * count, hipMemcpyHostToDevice));
+        w = nw.get();
+        dag->ws[key] = std::move(nw);
+    }
+    // the handle's per-call state (ensure_state has run)
+    w->tr = dag->tr.as<TaskRec>();
+    w->fbuf = dag->fbuf.as<int32_t>();
+    w->dag_u = dag->dag_u.as<int32_t>();
+    w->dag_taubar = dag->dag_taubar.as<int32_t>();
+    w->dag_maxtau = dag->dag_maxtau.as<int32_t>();
+    w->dag_score = dag->dag_score.as<int32_t>();
+    w->dag_tausum = dag->dag_tausum.as<unsigned long long>();
+    *out = w;
     return INSP_OK;
 }
 
@@ -385,7 +411,7 @@ extern "C" int insp_attributes(const insp_dag *cdag, int32_t index, const int32_
     if ((rc = get_workspace(dag, first, count, workers, true, &ws))) return rc;
     if ((rc = run_attributes(dag, ws, est, unit_time, rem, ia, ie, false, st))) return rc;
     std::vector<int32_t> stat(2 * dag->B), uu(count);
-    INSP_HIP(hipMemcpyAsync(uu.data(), dag->dag_u.as<int32_t>() + first, sizeof(int32_t) * count,
+    INSP_HIP(hipMemcpyAsync(uu.data(), ws->dag_u + first, sizeof(int32_t) * count,
                             hipMemcpyDeviceToHost, st));
     INSP_HIP(hipMemcpyAsync(stat.data(), dag->dag_astat.p, sizeof(int32_t) * 2 * dag->B, hipMemcpyDeviceToHost, st));
     INSP_HIP(hipStreamSynchronize(st));

@@ -67,9 +67,10 @@ int DevBuf::alloc(size_t nbytes) {
 }
 
 void DevBuf::release() {
-    if (p) (void)hipFree(p);
+    if (p && own) (void)hipFree(p);
     p = nullptr;
     bytes = 0;
+    own = true;
 }
 
 enum { ERR_ROWPTR = 1, ERR_COL = 2, ERR_SELF = 4 };
@@ -462,6 +463,8 @@ extern "C" int insp_build_dag(int32_t n_dags, const int64_t *task_off, const int
     hipStream_t st = (hipStream_t)stream_;
 
     std::unique_ptr<insp_dag> d(new insp_dag());
+    static std::atomic<uint64_t> next_serial{1};
+    d->serial = next_serial.fetch_add(1);
     d->B = n_dags;
     INSP_HIP(hipGetDevice(&d->device));
     d->N = N;
@@ -581,6 +584,7 @@ extern "C" int insp_build_dag(int32_t n_dags, const int64_t *task_off, const int
                 return set_error(INSP_E_CYCLE, "DAG %d has a dependency cycle", b);
         }
     }
+    if ((rc = alloc_status(d.get()))) return rc;
     if (type && N > 0) {
         if ((rc = d->type.alloc(sizeof(int32_t) * N))) return rc;
         INSP_HIP(hipMemcpyAsync(d->type.p, type, sizeof(int32_t) * N, hipMemcpyDeviceToDevice, st));

@@ -26,19 +26,29 @@ int set_error(int code, const char *fmt, ...);
                                      "%s failed: %s", #call, hipGetErrorString(e_));          \
     } while (0)
 
-// Device memory owned by a handle or workspace.
+// Device memory owned by a handle or workspace, or borrowed from memory the
+// library does not free (the static scratch array).
 struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
+    bool own = true;
     DevBuf() = default;
     DevBuf(const DevBuf &) = delete;
     DevBuf &operator=(const DevBuf &) = delete;
     ~DevBuf() { release(); }
     int alloc(size_t nbytes);
     void release();
+    // Point at `nbytes` of memory owned elsewhere; release() then forgets it.
+    void borrow(void *q, size_t nbytes) {
+        release();
+        p = q;
+        bytes = nbytes;
+        own = false;
+    }
     void swap(DevBuf &o) {
         std::swap(p, o.p);
         std::swap(bytes, o.bytes);
+        std::swap(own, o.own);
     }
     template <typename T>
     T *as() const { return static_cast<T *>(p); }
@@ -102,6 +112,14 @@ struct Workspace {
     DevBuf counter;               // int32 [4]: DAG dispenser
     DevBuf tlong, tu;             // transitive attributes: longest path per DAG (+ a counter), chosen U
     std::vector<int32_t> h_order;
+    // Per-call state the attribute pass and the simulation write, indexed by
+    // global task or DAG id: the handle's buffers, or regions of the static
+    // scratch array for the allocation-free batch call.
+    TaskRec *tr = nullptr;             // [N]
+    int32_t *fbuf = nullptr;           // [3 N]
+    int32_t *dag_u = nullptr, *dag_taubar = nullptr, *dag_maxtau = nullptr;  // [B]
+    int32_t *dag_score = nullptr;      // [B * kRungs]
+    unsigned long long *dag_tausum = nullptr;  // [B]
 };
 
 }  // namespace insp
@@ -109,6 +127,7 @@ struct Workspace {
 struct insp_dag {
     int32_t B = 0;
     int device = 0;
+    uint64_t serial = 0;               // unique per handle in the process
     int64_t N = 0, M = 0;
     std::vector<int64_t> toff, eoff;   // canonical prefix sums (host)
     std::vector<int32_t> order;        // DAG ids by n + m descending
@@ -125,6 +144,7 @@ struct insp_dag {
     insp::DevBuf dag_maxtau;           // int32 [B]
     insp::DevBuf dag_tausum;           // int64 [B]
     insp::DevBuf dag_score;            // int32 [B * 24] ladder score, difference form
+    // status words (allocated with the handle)
     insp::DevBuf dag_stat;             // int32 [B * 2]: status of the current schedule call, events
     insp::DevBuf dag_astat;            // int32 [B * 2]: status of the current attribute-only call
     insp::DevBuf dag_sticky;           // int32 [B]: schedule failures not yet reported by insp_sync_status
@@ -163,6 +183,9 @@ constexpr int kAttrThreads = 256;
 
 int ensure_state(insp_dag *dag, hipStream_t st);
 
+// The handle's status words, zeroed (called once, by insp_build_dag).
+int alloc_status(insp_dag *dag);
+
 // Raise a kernel's dynamic LDS limit to at least `bytes` on the current
 // device, once: later launches of the same size make no attribute call (so a
 // warmed-up call can be captured in a graph).
@@ -180,6 +203,12 @@ struct ProfScope {
 // Workspace for DAGs [first, first + count) with per-DAG workers (host).
 int get_workspace(insp_dag *dag, int32_t first, int32_t count, const insp_workers *workers, bool per_dag,
                   Workspace **out);
+
+// The host side of a workspace: sizes, simulation order, the DAG descriptors
+// and the attribute grid map (no device memory touched).  total_wl and the
+// returned block count size the queue pools.
+int64_t workspace_shape(const insp_dag *dag, int32_t first, int32_t count, const insp_workers *workers,
+                        bool per_dag, Workspace *w, std::vector<DagDesc> *desc, std::vector<int2> *blk);
 
 // Attribute pipeline over a workspace's DAGs: per-DAG max and sum of tau,
 // ladder scores (unit_time == 0), the chosen U, then IA and IE.  User arrays
@@ -210,6 +239,17 @@ int ensure_levels(insp_dag *dag, hipStream_t st);
 // attribute pass set.
 int run_transitive(insp_dag *dag, Workspace *ws, const int32_t *est, int32_t unit_time, int32_t *ia, int32_t *ie,
                    bool clear_status, hipStream_t st);
+
+// Launch shape of a batch call.
+struct BatchLaunch {
+    int grid = 1, sum_cap = 0, slot_cap = 0;
+};
+
+// Argument checks and the launch shape of a batch schedule call (host only;
+// makes the handle's device current).
+int batch_prologue(insp_dag *dag, const insp_workers *workers, const int32_t *dur, const int32_t *est,
+                   const insp_params *params, const int32_t *worker, const int64_t *start, const int64_t *finish,
+                   const int64_t *makespan, const char *tune_key, BatchLaunch *launch);
 
 int launch_sim(insp_dag *dag, Workspace *ws, const insp_params &p, const int32_t *dur, const int32_t *est,
                int32_t *worker, int64_t *start, int64_t *finish, int64_t *makespan, int32_t *ie_at_pop,

@@ -2032,14 +2032,14 @@ int launch_sim(insp_dag *dag, Workspace *ws, const insp_params &p, const int32_t
     A.dur = dur;
     A.est = est;
     A.base = ws->base;
-    A.tr = dag->tr.as<TaskRec>();
-    A.fbuf = dag->fbuf.as<int32_t>();
+    A.tr = ws->tr;
+    A.fbuf = ws->fbuf;
     A.slots = ws->slots.as<Slot>();
     A.sums = ws->sums.as<unsigned long long>();
     A.paux = ws->paux.as<int32_t>();
     A.freeb_base = ws->total_wl;
-    A.dag_u = dag->dag_u.as<int32_t>();
-    A.dag_taubar = dag->dag_taubar.as<int32_t>();
+    A.dag_u = ws->dag_u;
+    A.dag_taubar = ws->dag_taubar;
     A.stat = dag->dag_stat.as<int32_t>();
     A.rank = dag->rank.as<int64_t>();
     A.tia = dag->tia.as<int32_t>();
@@ -2105,7 +2105,7 @@ int launch_sim(insp_dag *dag, Workspace *ws, const insp_params &p, const int32_t
     if (ws->tasks > 0) {
         ProfScope pr(st, "rec");
         hipLaunchKernelGGL(k_records, dim3((unsigned)((ws->tasks + 255) / 256)), dim3(256), 0, st,
-                           dag->tr.as<TaskRec>() + ws->base, ws->tasks, worker, start, finish, ie_at_pop, mode_at_pop);
+                           ws->tr + ws->base, ws->tasks, worker, start, finish, ie_at_pop, mode_at_pop);
     }
     INSP_HIP(hipGetLastError());
     return INSP_OK;
@@ -2194,27 +2194,44 @@ static void parse_tune(const char *key, int *waves, int *grid, int *sum_cap, int
     if (d != std::string::npos) *slot_cap = atoi(s.c_str() + d + 10);
 }
 
-extern "C" int insp_schedule_batch(const insp_dag *cdag, const insp_workers *workers, const int32_t *dur,
-                                   const int32_t *est, const insp_params *params, int32_t *worker, int64_t *start,
-                                   int64_t *finish, int64_t *makespan, int32_t *ie_at_pop, int8_t *mode_at_pop,
-                                   const char *tune_key, void *stream) {
-    insp_dag *dag = const_cast<insp_dag *>(cdag);
+namespace insp {
+
+int batch_prologue(insp_dag *dag, const insp_workers *workers, const int32_t *dur, const int32_t *est,
+                   const insp_params *params, const int32_t *worker, const int64_t *start, const int64_t *finish,
+                   const int64_t *makespan, const char *tune_key, BatchLaunch *launch) {
     if (!dag || !workers || !makespan) return set_error(INSP_E_INVAL, "null argument");
     int rc;
     if ((rc = check_params(params)) || (rc = check_workers(workers, dag->B))) return rc;
     if (params->data_bw > 0 && !dag->dkib.p) return set_error(INSP_E_INVAL, "data_bw > 0 needs insp_set_task_data");
     if (dag->N > 0 && (!dur || !est || !worker || !start || !finish)) return set_error(INSP_E_INVAL, "null array");
-    hipStream_t st = (hipStream_t)stream;
     INSP_HIP(hipSetDevice(dag->device));
-    if ((rc = ensure_state(dag, st))) return rc;
-    Workspace *ws;
-    if ((rc = get_workspace(dag, 0, dag->B, workers, true, &ws))) return rc;
     int waves = 1, grid = default_grid(dag->B), sum_cap = 256, slot_cap = 16;
     parse_tune(tune_key, &waves, &grid, &sum_cap, &slot_cap);
     if (grid < 1 || sum_cap < 0 || sum_cap > 8192 || slot_cap < 0 || lds_bytes(1, sum_cap, 16, slot_cap) > 150 * 1024)
         return set_error(INSP_E_INVAL, "bad tune key '%s'", tune_key);
     // one wave simulates one DAG; no other shape is implemented
     if (waves != 1) return set_error(INSP_E_INVAL, "tune key '%s': only waves=1 is supported", tune_key);
+    launch->grid = grid;
+    launch->sum_cap = sum_cap;
+    launch->slot_cap = slot_cap;
+    return INSP_OK;
+}
+
+}  // namespace insp
+
+extern "C" int insp_schedule_batch(const insp_dag *cdag, const insp_workers *workers, const int32_t *dur,
+                                   const int32_t *est, const insp_params *params, int32_t *worker, int64_t *start,
+                                   int64_t *finish, int64_t *makespan, int32_t *ie_at_pop, int8_t *mode_at_pop,
+                                   const char *tune_key, void *stream) {
+    insp_dag *dag = const_cast<insp_dag *>(cdag);
+    BatchLaunch bl;
+    int rc;
+    if ((rc = batch_prologue(dag, workers, dur, est, params, worker, start, finish, makespan, tune_key, &bl)))
+        return rc;
+    hipStream_t st = (hipStream_t)stream;
+    if ((rc = ensure_state(dag, st))) return rc;
+    Workspace *ws;
+    if ((rc = get_workspace(dag, 0, dag->B, workers, true, &ws))) return rc;
     if ((rc = run_attributes(dag, ws, est, params->unit_time, nullptr, nullptr, nullptr, true, st))) return rc;
     if (params->policy == INSP_POLICY_HEFT && (rc = run_rank(dag, ws, est, st))) return rc;
     if (params->attr_mode == INSP_ATTR_TRANSITIVE && (rc = run_sim_transitive(dag, ws, est, params->unit_time, st)))
@@ -2223,7 +2240,7 @@ extern "C" int insp_schedule_batch(const insp_dag *cdag, const insp_workers *wor
     if (params->data_bw > 0 && !dag->dxc.p && (rc = dag->dxc.alloc(sizeof(int32_t) * std::max<int64_t>(dag->N, 1))))
         return rc;
     return launch_sim(dag, ws, *params, dur, est, worker, start, finish, makespan, ie_at_pop, mode_at_pop, nullptr,
-                      nullptr, waves, grid, sum_cap, slot_cap, st);
+                      nullptr, 1, bl.grid, bl.sum_cap, bl.slot_cap, st);
 }
 
 #ifdef INSP_PHASE_CLOCKS

@@ -26,7 +26,7 @@ ALL_DAGS = -1
 EXPORTS = ("insp_build_dag", "insp_set_task_data", "insp_free_dag", "insp_dag_info", "insp_attributes",
            "insp_transitive_attributes",
            "insp_schedule",
-           "insp_schedule_batch", "insp_sync_status", "insp_profile_enable", "insp_profile_read",
+           "insp_schedule_batch", "insp_schedule_batch_noalloc", "insp_sync_status", "insp_profile_enable", "insp_profile_read",
            "insp_mlp_create", "insp_mlp_free", "insp_mlp_grads", "insp_mlp_train_step", "insp_mlp_train", "insp_mlp_predict",
            "insp_mlp_state", "insp_last_error", "insp_test_fail_alloc")
 MLP_PARAMS = 74754
@@ -79,6 +79,7 @@ def load(path: str = LIB_PATH):
     lib.insp_transitive_attributes.argtypes = [P, i32, P, P, i32, P, P, P, P, P]
     lib.insp_schedule.argtypes = [P, i32, P, P, P, C.POINTER(Params), P, P, P, P, P, P, P, P, P]
     lib.insp_schedule_batch.argtypes = [P, P, P, P, C.POINTER(Params), P, P, P, P, P, P, C.c_char_p, P]
+    lib.insp_schedule_batch_noalloc.argtypes = lib.insp_schedule_batch.argtypes
     lib.insp_sync_status.argtypes = [P, P]
     lib.insp_profile_enable.argtypes = [C.c_int]
     lib.insp_profile_read.argtypes = [C.c_char_p, C.POINTER(C.c_double), C.POINTER(i64)]
@@ -289,6 +290,20 @@ def trace_records(trace_tensor, n_events):
 def schedule_batch(dag: Dag, workers, dur, est, prm: Params = None, tune_key=None, stream=None, out=None,
                    with_pop=True):
     """Simulate all DAGs in one persistent launch; returns device tensors."""
+    return _batch(load().insp_schedule_batch, dag, workers, dur, est, prm, tune_key, stream, out, with_pop)
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def schedule_batch_noalloc(dag: Dag, workers, dur, est, prm: Params = None, tune_key=None, stream=None, out=None,
+                           with_pop=True):
+    """schedule_batch through the allocation-free entry point (per-call state
+    in the library's static scratch array); pass `out` to allocate nothing."""
+    return _batch(load().insp_schedule_batch_noalloc, dag, workers, dur, est, prm, tune_key, stream, out, with_pop)
+
+
+def _batch(fn, dag, workers, dur, est, prm, tune_key, stream, out, with_pop):
     import torch
     prm = prm or params()
     dev = dur.device
@@ -296,13 +311,13 @@ def schedule_batch(dag: Dag, workers, dur, est, prm: Params = None, tune_key=Non
     o["makespan"] = o.get("makespan", torch.empty(dag.n_dags, dtype=torch.int64, device=dev))
     key = tune_key.encode() if isinstance(tune_key, str) else tune_key
     n, B = int(dag.task_off[-1]), dag.n_dags
-    _check(load().insp_schedule_batch(dag.handle, _workers(workers, B), _dev(dur, "dur", "i32", 2, n),
-                                      _dev(est, "est", "i32", 2, n), C.byref(prm),
-                                      _dev(o["worker"], "worker", "i32", 1, n), _dev(o["start"], "start", "i64", 1, n),
-                                      _dev(o["finish"], "finish", "i64", 1, n),
-                                      _dev(o["makespan"], "makespan", "i64", 1, B),
-                                      _dev(o.get("ie_at_pop"), "ie_at_pop", "i32", 1, n),
-                                      _dev(o.get("mode_at_pop"), "mode_at_pop", "i8", 1, n), key, _stream(stream)))
+    _check(fn(dag.handle, _workers(workers, B), _dev(dur, "dur", "i32", 2, n),
+              _dev(est, "est", "i32", 2, n), C.byref(prm),
+              _dev(o["worker"], "worker", "i32", 1, n), _dev(o["start"], "start", "i64", 1, n),
+              _dev(o["finish"], "finish", "i64", 1, n),
+              _dev(o["makespan"], "makespan", "i64", 1, B),
+              _dev(o.get("ie_at_pop"), "ie_at_pop", "i32", 1, n),
+              _dev(o.get("mode_at_pop"), "mode_at_pop", "i8", 1, n), key, _stream(stream)))
     return o
 
 
