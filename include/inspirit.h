@@ -24,7 +24,8 @@
  *     most 2^21 tasks; a machine has 1..1024 workers.
  *   - Worker w < n_cpu is a CPU worker (kind 0), the rest are GPU workers
  *     (kind 1).  Per-task tick tables are int32 [n][2]: column 0 = CPU,
- *     column 1 = GPU.
+ *     column 1 = GPU; they are read a row (8 bytes) at a time and must be
+ *     8-byte aligned (INSP_E_INVAL otherwise).
  */
 #ifndef INSPIRIT_H
 #define INSPIRIT_H

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <atomic>
 #include <cstring>
 #include <map>
@@ -418,6 +419,108 @@ __global__ void k_kahn(const int32_t *dags, const int64_t *toff, const int64_t *
 
 static inline unsigned grid_for(int64_t n, int threads) { return (unsigned)((n + threads - 1) / threads); }
 
+// Hub rows of the large DAGs: rows with more than kHubDeg successors get a
+// wave each in the grid-wide attribute pass, the longest first.
+__global__ void k_hub_count(const int32_t *r, int32_t n, int32_t *cnt) {
+    const int32_t v = blockIdx.x * 256 + threadIdx.x;
+    if (v >= n) return;
+    cnt[v] = r[v + 1] - r[v] > kHubDeg ? 1 : 0;
+}
+
+__global__ void k_hub_fill(const int32_t *r, int32_t n, const int64_t *off, int32_t *rows, int32_t *degs) {
+    const int32_t v = blockIdx.x * 256 + threadIdx.x;
+    if (v >= n || off[v + 1] == off[v]) return;
+    rows[off[v]] = v;
+    degs[off[v]] = r[v + 1] - r[v];
+}
+
+int build_hubs(insp_dag *dag, hipStream_t st) {
+    const int32_t B = dag->B;
+    dag->hub0.assign(B, 0);
+    dag->nhub.assign(B, 0);
+    dag->long0.assign(B, 0);
+    dag->nlong.assign(B, 0);
+    const int32_t max_n = large_rows(dag);
+    if (max_n == 0) return INSP_OK;
+    DevBuf cnt, off, rows, degs;
+    int rc;
+    if ((rc = cnt.alloc(sizeof(int32_t) * max_n)) || (rc = off.alloc(sizeof(int64_t) * (max_n + 1))) ||
+        (rc = rows.alloc(sizeof(int32_t) * max_n)) || (rc = degs.alloc(sizeof(int32_t) * max_n)))
+        return rc;
+    const int32_t *rp = dag->rp.as<int32_t>();
+    std::vector<int4> all;
+    for (int32_t b = 0; b < B; b++) {
+        const int32_t n = (int32_t)(dag->toff[b + 1] - dag->toff[b]);
+        dag->hub0[b] = (int32_t)all.size();
+        if (n < kGridMin) continue;
+        const int32_t *r = rp + dag->toff[b] + b;
+        hipLaunchKernelGGL(k_hub_count, dim3((n + 255) / 256), dim3(256), 0, st, r, n, cnt.as<int32_t>());
+        if ((rc = exclusive_scan(cnt.as<int32_t>(), n, off.as<int64_t>(), st))) return rc;
+        hipLaunchKernelGGL(k_hub_fill, dim3((n + 255) / 256), dim3(256), 0, st, r, n, off.as<int64_t>(),
+                           rows.as<int32_t>(), degs.as<int32_t>());
+        int64_t h = 0;
+        INSP_HIP(hipMemcpyAsync(&h, off.as<int64_t>() + n, sizeof h, hipMemcpyDeviceToHost, st));
+        INSP_HIP(hipStreamSynchronize(st));
+        std::vector<int32_t> hr(h), hd(h);
+        if (h > 0) {
+            INSP_HIP(hipMemcpyAsync(hr.data(), rows.p, sizeof(int32_t) * h, hipMemcpyDeviceToHost, st));
+            INSP_HIP(hipMemcpyAsync(hd.data(), degs.p, sizeof(int32_t) * h, hipMemcpyDeviceToHost, st));
+            INSP_HIP(hipStreamSynchronize(st));
+        }
+        // entries: whole rows, or the pieces of rows longer than kPieceMin;
+        // the longest work first
+        std::vector<int4> ent;
+        for (int64_t i = 0; i < h; i++) {
+            const int32_t np = hd[i] > kPieceMin ? (hd[i] + kPiece - 1) / kPiece : 1;
+            for (int32_t k = 0; k < np; k++) ent.push_back(make_int4(hr[i], k, np, 0));
+        }
+        std::stable_sort(ent.begin(), ent.end(), [&](const int4 &x, const int4 &y) {
+            auto len = [&](const int4 &e) {
+                const int32_t dg = hd[std::lower_bound(hr.begin(), hr.end(), e.x) - hr.begin()];
+                return e.z > 1 ? std::min(kPiece, dg - e.y * kPiece) : dg;
+            };
+            return len(x) > len(y);
+        });
+        dag->nhub[b] = (int32_t)ent.size();
+        all.insert(all.end(), ent.begin(), ent.end());
+    }
+    // piece slots: each long row's pieces get consecutive slots
+    {
+        std::map<std::pair<int32_t, int32_t>, int32_t> first;  // (DAG, row) -> first slot
+        int32_t next = 0;
+        std::vector<int4> lr;
+        for (int32_t b = 0, i = 0; b < B; b++) {
+            dag->long0[b] = (int32_t)lr.size();
+            for (int32_t k = 0; k < dag->nhub[b]; k++, i++) {
+                int4 &e = all[i];
+                if (e.z <= 1) continue;
+                auto key = std::make_pair(b, e.x);
+                auto it = first.find(key);
+                if (it == first.end()) {
+                    it = first.emplace(key, next).first;
+                    lr.push_back(make_int4(e.x, 0, e.z, next));
+                    next += e.z;
+                }
+                e.w = it->second;
+            }
+            dag->nlong[b] = (int32_t)lr.size() - dag->long0[b];
+        }
+        if (next > 0 && (rc = dag->pslot.alloc(sizeof(int32_t) * 4 * (size_t)next))) return rc;
+        if (!lr.empty()) {
+            if ((rc = dag->lrow.alloc(sizeof(int4) * lr.size()))) return rc;
+            INSP_HIP(hipMemcpyAsync(dag->lrow.p, lr.data(), sizeof(int4) * lr.size(), hipMemcpyHostToDevice, st));
+            INSP_HIP(hipStreamSynchronize(st));
+        }
+    }
+    if (!all.empty()) {
+        if ((rc = dag->hub.alloc(sizeof(int4) * all.size()))) return rc;
+        INSP_HIP(hipMemcpyAsync(dag->hub.p, all.data(), sizeof(int4) * all.size(), hipMemcpyHostToDevice, st));
+    }
+    INSP_HIP(hipGetLastError());
+    INSP_HIP(hipStreamSynchronize(st));
+    return INSP_OK;
+}
+
 }  // namespace insp
 
 using namespace insp;
@@ -584,7 +687,7 @@ extern "C" int insp_build_dag(int32_t n_dags, const int64_t *task_off, const int
                 return set_error(INSP_E_CYCLE, "DAG %d has a dependency cycle", b);
         }
     }
-    if ((rc = alloc_status(d.get()))) return rc;
+    if ((rc = alloc_status(d.get())) || (rc = build_hubs(d.get(), st))) return rc;
     if (type && N > 0) {
         if ((rc = d->type.alloc(sizeof(int32_t) * N))) return rc;
         INSP_HIP(hipMemcpyAsync(d->type.p, type, sizeof(int32_t) * N, hipMemcpyDeviceToDevice, st));

@@ -132,6 +132,20 @@ __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t x) {
     return x;
 }
 
+// Inclusive prefix sum over the wave (Hillis-Steele within each 16-lane row
+// by row shifts, then the row totals carried by row broadcasts).  All 64
+// lanes must be active.
+__device__ __forceinline__ int32_t wave_incl_scan(int32_t x) {
+    uint32_t v = (uint32_t)x;
+    v += dpp32_zero<0x111>(v);        // row_shr:1
+    v += dpp32_zero<0x112>(v);        // row_shr:2
+    v += dpp32_zero<0x114>(v);        // row_shr:4
+    v += dpp32_zero<0x118>(v);        // row_shr:8
+    v += dpp32_zero<0x142, 0xA>(v);   // row_bcast15 into rows 1 and 3
+    v += dpp32_zero<0x143, 0xC>(v);   // row_bcast31 into rows 2 and 3
+    return (int32_t)v;
+}
+
 // Work-group-scope atomics: every per-DAG array is touched by exactly one
 // work-group during a simulation, so L2-resident atomics at work-group scope
 // are sufficient and avoid device-scope coherence traffic.

@@ -87,12 +87,14 @@ struct DagDesc {
     int32_t n, m;
     int32_t n_cpu, n_gpu;
     int32_t nblk, maxb;   // blocks in the pool; block-list slots per worker
-    int32_t pad;
+    int32_t path;         // attribute pass: 0 = one work-group per DAG, 1 = the whole grid (large DAG)
+    int32_t hub0, nhub;   // large DAG: its hub rows (first index in the handle's list, count)
+    int32_t long0, nlong; // ... and those cut into pieces
 };
 
 // Launch state for one machine shape (DAG range and worker counts): the
-// kernels' DAG descriptors, the attribute grid map, the simulation order and
-// the queue pools.  Built once, reused by every call with the same shape.
+// kernels' DAG descriptors, the attribute and simulation orders and the
+// queue pools.  Built once, reused by every call with the same shape.
 struct Workspace {
     int32_t count = 0;            // DAGs described
     int32_t first = 0;            // first DAG of the range
@@ -101,17 +103,20 @@ struct Workspace {
     int64_t base = 0;             // first global task of the range
     int64_t total_wl = 0;         // block-list slots before the free-block stacks in paux
     int64_t tasks = 0;
-    int32_t attr_blocks = 0;
+    int32_t n_small = 0;          // non-empty DAGs of the per-DAG attribute pass
+    int32_t max_small = 0;        // tasks of the largest of them
     DevBuf desc;                  // DagDesc [count]
-    DevBuf blkmap;                // int2 [attr_blocks]: desc index, chunk
     DevBuf order;                 // int32 [count]: desc indices, largest first
+    DevBuf sorder;                // int32 [n_small]: desc indices of the per-DAG pass, largest first
     DevBuf slots;                 // Slot [64 per block]: queue entries
     DevBuf sums;                  // uint64 x2 per block: max key under each rule
     DevBuf paux;                  // int32: per-worker block lists, then free-block stacks
     DevBuf barr;                  // int64 per block: latest input arrival (data model)
     DevBuf counter;               // int32 [4]: DAG dispenser
     DevBuf tlong, tu;             // transitive attributes: longest path per DAG (+ a counter), chosen U
-    std::vector<int32_t> h_order;
+    std::vector<int32_t> h_order, h_sorder;
+    std::vector<int32_t> h_large;      // desc indices of the DAGs of the grid-wide attribute pass
+    std::vector<DagDesc> h_desc;
     // Per-call state the attribute pass and the simulation write, indexed by
     // global task or DAG id: the handle's buffers, or regions of the static
     // scratch array for the allocation-free batch call.
@@ -120,6 +125,10 @@ struct Workspace {
     int32_t *dag_u = nullptr, *dag_taubar = nullptr, *dag_maxtau = nullptr;  // [B]
     int32_t *dag_score = nullptr;      // [B * kRungs]
     unsigned long long *dag_tausum = nullptr;  // [B]
+    int32_t *dag_done = nullptr;       // [B]: finished blocks of the grid-wide attribute pass
+    int32_t *apart = nullptr;          // [kBigGrid * 32]: its per-block partial results
+    uint32_t *apkg = nullptr;          // [rows of the largest large DAG]: its task words
+    unsigned long long *asumm = nullptr;  // [same]: its rows' pass-A summaries
 };
 
 }  // namespace insp
@@ -144,6 +153,17 @@ struct insp_dag {
     insp::DevBuf dag_maxtau;           // int32 [B]
     insp::DevBuf dag_tausum;           // int64 [B]
     insp::DevBuf dag_score;            // int32 [B * 24] ladder score, difference form
+    insp::DevBuf dag_done;             // int32 [B]: finished blocks of the grid-wide attribute pass
+    insp::DevBuf apart;                // int32 [kBigGrid * 32]: its per-block partial results
+    insp::DevBuf apkg;                 // uint32 [rows of the largest large DAG]: task words of the grid pass
+    insp::DevBuf asumm;                // uint64 [same]: pass-A row summaries of the grid pass
+    // large DAGs (at least kGridMin tasks): rows with more than kHubDeg
+    // successors, longest first (built with the handle)
+    std::vector<int32_t> hub0, nhub;   // per DAG: first entry, entries
+    insp::DevBuf hub;                  // int4 [entries]: DAG-local row, piece, pieces, first piece slot
+    insp::DevBuf pslot;                // int32 [4 * entries]: partial results of the pieces of long rows
+    std::vector<int32_t> long0, nlong; // per DAG: first long row, long rows
+    insp::DevBuf lrow;                 // int4 [long rows]: row, 0, pieces, first piece slot
     // status words (allocated with the handle)
     insp::DevBuf dag_stat;             // int32 [B * 2]: status of the current schedule call, events
     insp::DevBuf dag_astat;            // int32 [B * 2]: status of the current attribute-only call
@@ -180,8 +200,19 @@ enum { ST_EST = 1, ST_DUR = 2, ST_HANG = 4, ST_RANK = 8, ST_PATH = 16, ST_XFER =
 constexpr int kRankBits = 42;
 constexpr int kTRungs = 32;  // transitive ladder rungs 2^0 .. 2^31
 constexpr int kAttrThreads = 256;
+constexpr int32_t kGridMin = 32768;  // DAGs this large take the grid-wide attribute pass
+constexpr int32_t kHubDeg = 64;      // ... where rows with more successors get a wave each
+constexpr int32_t kPieceMin = 1024;  // ... or, this long, one wave per piece
+constexpr int32_t kPiece = 512;      // successors per piece
+constexpr int kBigGrid = 2048;       // work-groups of the grid-wide pass
+
+// Hub rows of the handle's large DAGs (insp_build_dag).
+int build_hubs(insp_dag *dag, hipStream_t st);
 
 int ensure_state(insp_dag *dag, hipStream_t st);
+
+// Tasks of the handle's largest DAG of the grid-wide attribute pass (0: none).
+int32_t large_rows(const insp_dag *dag);
 
 // The handle's status words, zeroed (called once, by insp_build_dag).
 int alloc_status(insp_dag *dag);
@@ -205,10 +236,10 @@ int get_workspace(insp_dag *dag, int32_t first, int32_t count, const insp_worker
                   Workspace **out);
 
 // The host side of a workspace: sizes, simulation order, the DAG descriptors
-// and the attribute grid map (no device memory touched).  total_wl and the
+// (no device memory touched).  total_wl and the
 // returned block count size the queue pools.
 int64_t workspace_shape(const insp_dag *dag, int32_t first, int32_t count, const insp_workers *workers,
-                        bool per_dag, Workspace *w, std::vector<DagDesc> *desc, std::vector<int2> *blk);
+                        bool per_dag, Workspace *w, std::vector<DagDesc> *desc);
 
 // Attribute pipeline over a workspace's DAGs: per-DAG max and sum of tau,
 // ladder scores (unit_time == 0), the chosen U, then IA and IE.  User arrays

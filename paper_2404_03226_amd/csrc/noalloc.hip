@@ -64,9 +64,9 @@ int prepare(insp_dag *dag, const insp_workers *workers, DeviceScratch *ds, hipSt
     Workspace &w = ds->ws;
     w.max_w = 0;
     w.max_nblk = 0;
+    w.max_small = 0;
     std::vector<DagDesc> desc;
-    std::vector<int2> blk;
-    const int64_t boff = workspace_shape(dag, 0, dag->B, workers, true, &w, &desc, &blk);
+    const int64_t boff = workspace_shape(dag, 0, dag->B, workers, true, &w, &desc);
     const size_t N = (size_t)std::max<int64_t>(dag->N, 1), B = (size_t)dag->B;
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -76,8 +76,10 @@ int prepare(insp_dag *dag, const insp_workers *workers, DeviceScratch *ds, hipSt
     };
     const size_t o_tr = take(sizeof(TaskRec) * N), o_fbuf = take(12 * N);
     const size_t o_u = take(4 * B), o_taubar = take(4 * B), o_maxtau = take(4 * B), o_tausum = take(8 * B);
-    const size_t o_score = take(4 * kRungs * B);
-    const size_t o_desc = take(sizeof(DagDesc) * B), o_blk = take(sizeof(int2) * blk.size()), o_order = take(4 * B);
+    const size_t o_score = take(4 * kRungs * B), o_done = take(4 * B);
+    const size_t o_desc = take(sizeof(DagDesc) * B), o_order = take(4 * B), o_sorder = take(4 * B);
+    const size_t o_apart = take(4 * 32 * kBigGrid);
+    const size_t big = (size_t)large_rows(dag), o_apkg = take(4 * big), o_asumm = take(8 * big);
     const size_t o_slots = take(sizeof(Slot) * 64 * (size_t)boff), o_sums = take(16 * (size_t)boff);
     const size_t o_paux = take(4 * (size_t)(w.total_wl + boff)), o_barr = take(8 * (size_t)boff);
     const size_t o_counter = take(16);
@@ -94,9 +96,13 @@ int prepare(insp_dag *dag, const insp_workers *workers, DeviceScratch *ds, hipSt
     w.dag_maxtau = reinterpret_cast<int32_t *>(p + o_maxtau);
     w.dag_tausum = reinterpret_cast<unsigned long long *>(p + o_tausum);
     w.dag_score = reinterpret_cast<int32_t *>(p + o_score);
+    w.dag_done = reinterpret_cast<int32_t *>(p + o_done);
+    w.apart = reinterpret_cast<int32_t *>(p + o_apart);
+    w.apkg = reinterpret_cast<uint32_t *>(p + o_apkg);
+    w.asumm = reinterpret_cast<unsigned long long *>(p + o_asumm);
     w.desc.borrow(p + o_desc, sizeof(DagDesc) * B);
-    w.blkmap.borrow(p + o_blk, sizeof(int2) * blk.size());
     w.order.borrow(p + o_order, 4 * B);
+    w.sorder.borrow(p + o_sorder, 4 * B);
     w.slots.borrow(p + o_slots, sizeof(Slot) * 64 * (size_t)boff);
     w.sums.borrow(p + o_sums, 16 * (size_t)boff);
     w.paux.borrow(p + o_paux, 4 * (size_t)(w.total_wl + boff));
@@ -106,9 +112,9 @@ int prepare(insp_dag *dag, const insp_workers *workers, DeviceScratch *ds, hipSt
     // the copies are ordered after them on the same stream, and the stream is
     // synchronised before the host vectors go away
     INSP_HIP(hipMemcpyAsync(w.desc.p, desc.data(), sizeof(DagDesc) * B, hipMemcpyHostToDevice, st));
-    if (!blk.empty())
-        INSP_HIP(hipMemcpyAsync(w.blkmap.p, blk.data(), sizeof(int2) * blk.size(), hipMemcpyHostToDevice, st));
     INSP_HIP(hipMemcpyAsync(w.order.p, w.h_order.data(), 4 * B, hipMemcpyHostToDevice, st));
+    if (w.n_small > 0)
+        INSP_HIP(hipMemcpyAsync(w.sorder.p, w.h_sorder.data(), 4 * (size_t)w.n_small, hipMemcpyHostToDevice, st));
     INSP_HIP(hipStreamSynchronize(st));
     ds->shape.swap(shape);
     ds->serial = dag->serial;

@@ -2168,6 +2168,7 @@ extern "C" int insp_schedule(const insp_dag *cdag, int32_t index, const insp_wor
     if (params->data_bw > 0 && !dag->dkib.p) return set_error(INSP_E_INVAL, "data_bw > 0 needs insp_set_task_data");
     const int64_t n = dag->toff[index + 1] - dag->toff[index];
     if (n > 0 && (!dur || !est || !worker || !start || !finish)) return set_error(INSP_E_INVAL, "null array");
+    if ((((uintptr_t)dur | (uintptr_t)est) & 7) != 0) return set_error(INSP_E_INVAL, "dur/est rows must be 8-byte aligned");
     hipStream_t st = (hipStream_t)stream;
     INSP_HIP(hipSetDevice(dag->device));
     if ((rc = ensure_state(dag, st))) return rc;
@@ -2204,6 +2205,7 @@ int batch_prologue(insp_dag *dag, const insp_workers *workers, const int32_t *du
     if ((rc = check_params(params)) || (rc = check_workers(workers, dag->B))) return rc;
     if (params->data_bw > 0 && !dag->dkib.p) return set_error(INSP_E_INVAL, "data_bw > 0 needs insp_set_task_data");
     if (dag->N > 0 && (!dur || !est || !worker || !start || !finish)) return set_error(INSP_E_INVAL, "null array");
+    if ((((uintptr_t)dur | (uintptr_t)est) & 7) != 0) return set_error(INSP_E_INVAL, "dur/est rows must be 8-byte aligned");
     INSP_HIP(hipSetDevice(dag->device));
     int waves = 1, grid = default_grid(dag->B), sum_cap = 256, slot_cap = 16;
     parse_tune(tune_key, &waves, &grid, &sum_cap, &slot_cap);

@@ -112,6 +112,81 @@ def test_attributes_match_oracle(insp, seed):
     dag.free()
 
 
+def _hub_dag(seed, n, hubs):
+    """A DAG of n tasks whose first rows have the given out-degrees (hub rows
+    cut into pieces by the grid-wide attribute pass, straddling piece
+    boundaries) and every other row 0-6 later targets; ticks U{1..500}."""
+    st = synth.Stream(seed, 1)
+    rows = []
+    for v in range(n):
+        d = hubs[v] if v < len(hubs) else int(st.randint(np.array([v]), 0, 6)[0])
+        d = min(d, n - 1 - v)
+        t = v + 1 + np.sort(synth.Stream(seed, 2 + v).u64(np.arange(3 * d + 8)) % max(n - 1 - v, 1))
+        t = np.unique(t)[:d].astype(np.int32)
+        rows.append(t)
+    rp = np.zeros(n + 1, np.int32)
+    rp[1:] = np.cumsum([len(t) for t in rows])
+    col = np.concatenate(rows).astype(np.int32)
+    est = (synth.Stream(seed, 3).u64(np.arange(2 * n)) % 500 + 1).astype(np.int32).reshape(n, 2)
+    return NS(n=n, row_ptr=rp, col=col, dur=est.copy(), est=est, n_cpu=6, n_gpu=2, m=len(col),
+              type=np.zeros(n, np.int32), name=f"hubs-{n}")
+
+
+@pytest.mark.parametrize("case", ["hubs", "powerlaw"])
+def test_grid_attribute_pass_with_hub_rows(insp, case):
+    # DAGs of at least 32,768 tasks take the grid-wide attribute pass, where
+    # rows of more than 64 successors get a wave each
+    import torch
+    if case == "hubs":
+        w = _hub_dag(7, 40000, [4180, 65, 256, 257, 64, 512, 513, 1, 0, 300] + [70] * 60 + [2000])
+    else:
+        w = synth.cfg4(n=60000)
+    say("grid attributes", w.name, w.n, w.m)
+    dag, dur, est = insp.to_device(w)
+    rp, col = oracle.canon(w.n, w.row_ptr, w.col)
+    for n_gpu in (0, 2):
+        for U in (0, 100, 1 << 20):
+            ia, ie, Ug = insp.attributes(dag, 0, est, (6, n_gpu), unit_time=U)
+            ria, rie, rU = oracle.attributes(w.n, rp, col, w.est, n_gpu, unit_time=U)
+            assert Ug[0] == rU, (n_gpu, U)
+            assert np.array_equal(ia.cpu().numpy(), ria) and np.array_equal(ie.cpu().numpy(), rie), (n_gpu, U)
+    finished = synth.Stream(11, 99).uniform(np.arange(w.n)) < 0.4
+    src = np.repeat(np.arange(w.n), np.diff(rp))
+    rem = np.bincount(col[~finished[src]], minlength=w.n).astype(np.int32)
+    ia, ie, Ug = insp.attributes(dag, 0, est, (6, 2), unit_time=0, rem=torch.from_numpy(rem).cuda())
+    ria, rie, rU = oracle.attributes(w.n, rp, col, w.est, 2, rem=rem)
+    assert Ug[0] == rU and np.array_equal(ie.cpu().numpy(), rie)
+    # the schedule reads the records the grid pass writes
+    r = oracle.schedule(w, variant=oracle.HEAP)
+    g = run_gpu(insp, w)
+    assert_same(g, r, w.name)
+    dag.free()
+
+
+def test_attribute_paths_in_one_batch(insp):
+    # small DAGs (one work-group each) beside a large one (the whole grid) and
+    # an empty one, in one call: attributes of every DAG and every schedule
+    ws = synth.cfg3(select=[3, 700, 2048]) + [_hub_dag(9, 33000, [3000, 100, 65])] + [_empty()] + \
+        synth.cfg3(select=[4095])
+    b = synth.concat(ws)
+    say("mixed attribute paths", [w.n for w in ws])
+    dag, dur, est = insp.batch_to_device(b)
+    workers = [(w.n_cpu, w.n_gpu) for w in ws]
+    ia, ie, U = insp.attributes(dag, insp.ALL_DAGS, est, workers)
+    ia, ie = ia.cpu().numpy(), ie.cpu().numpy()
+    for k, w in enumerate(ws):
+        a, z = int(b.task_off[k]), int(b.task_off[k + 1])
+        rp, col = oracle.canon(w.n, w.row_ptr, w.col)
+        ria, rie, rU = oracle.attributes(w.n, rp, col, w.est, w.n_gpu)
+        assert np.array_equal(ia[a:z], ria) and np.array_equal(ie[a:z], rie) and U[k] == rU, k
+    o = insp.schedule_batch(dag, workers, dur, est)
+    insp.sync_status(dag)
+    r = oracle.schedule_batch(b)
+    for k in ("worker", "start", "finish", "ie_at_pop", "mode_at_pop", "makespan"):
+        assert np.array_equal(o[k].cpu().numpy()[:len(r[k])], r[k]), k
+    dag.free()
+
+
 @pytest.mark.parametrize("policy", ["inspirit", "fifo", "ability", "efi", "heft"])
 def test_random_small_dags(insp, policy):
     for i in range(40):
