@@ -262,9 +262,14 @@ int insp_schedule(const insp_dag *dag, int32_t index, const insp_workers *worker
  * comma-separated string of "grid=<g>" (persistent work-groups, each one
  * wave simulating one DAG at a time), "lds_blocks=<b>" (queue blocks per DAG
  * whose maxima live in LDS, <= 8192), "lds_slots=<s>" (queue blocks per DAG
- * whose entries live in LDS) and "waves=1" (the only accepted value; any
- * other is INSP_E_INVAL).  Results never depend on it.  The first call with
- * a new machine shape allocates workspace; later calls reuse it.
+ * whose entries live in LDS), "prio=<k>" (the k largest DAGs run at raised
+ * wave priority), "scan=<k>" (<= 16: a pop reads every queue entry of a
+ * worker with at most k queue blocks, and picks a block by its maximum
+ * first above that) and "waves=1" (the only accepted value; any other is
+ * INSP_E_INVAL).  Each work-group of the launch is one wave that simulates
+ * and, for machines of at most 64 workers, one that reads ahead for it.
+ * Results never depend on the key.  The first call with a new machine shape
+ * allocates workspace; later calls reuse it.
  */
 int insp_schedule_batch(const insp_dag *dag, const insp_workers *workers, const int32_t *dur, const int32_t *est,
                         const insp_params *params, int32_t *worker, int64_t *start, int64_t *finish,
@@ -277,7 +282,8 @@ int insp_schedule_batch(const insp_dag *dag, const insp_workers *workers, const 
  * harnesses that forbid allocation.  Same arguments, results and status
  * reporting (insp_sync_status) as insp_schedule_batch; the caller passes the
  * inputs and outputs as before.  The call allocates nothing: the per-call
- * state -- task records (32 B per task), frontier buffers (12 B per task),
+ * state -- task records (32 B per task), dependency words (8 B per task),
+ * frontier buffers (12 B per task),
  * per-DAG attribute records and launch tables, and the queue pools (about
  * 2,076 B per 64-task block, ceil(n/64) + W blocks and 4 W (ceil(n/64) + 1) B
  * of block lists per DAG of n tasks on W workers) -- is carved out of one

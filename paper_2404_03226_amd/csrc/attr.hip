@@ -96,6 +96,7 @@ struct AttrOut {
     int32_t *ia_out, *ie_out;   // user arrays (nullable), relative to base
     int sim_init;
     TaskRec *tr;
+    unsigned long long *dep;    // the simulation's dependency words
 };
 
 // Status words, per-DAG accumulators and the defaults (U for an empty DAG).
@@ -294,7 +295,8 @@ __device__ __forceinline__ void write_row(const AttrArgs &a, const AttrOut &o, c
             memset(&rec, 0, sizeof rec);
             rec.qpos = -1;
         } else {
-            rec.word = a.word0[t];
+            o.dep[t] = a.word0[t];
+            rec.word = 0;
             rec.iev = ie;
             rec.qpos = -1;
             rec.ia = deg;
@@ -807,6 +809,7 @@ int run_attributes(insp_dag *dag, Workspace *ws, const int32_t *est, int32_t uni
     o.ie_out = ie_out;
     o.sim_init = sim_init ? 1 : 0;
     o.tr = ws->tr;
+    o.dep = ws->dep;
     ProfScope whole(st, "pass_attr");
     {
         ProfScope ps(st, "attr_clear");
@@ -879,7 +882,7 @@ int ensure_state(insp_dag *dag, hipStream_t st) {
     if (dag->tr.p) return INSP_OK;
     const int64_t N = std::max<int64_t>(dag->N, 1);
     int rc;
-    if ((rc = dag->tr.alloc(sizeof(TaskRec) * N)) || (rc = dag->fbuf.alloc(12 * N)) ||
+    if ((rc = dag->tr.alloc(sizeof(TaskRec) * N)) || (rc = dag->dep.alloc(8 * N)) || (rc = dag->fbuf.alloc(12 * N)) ||
         (rc = dag->dag_u.alloc(4 * dag->B)) ||
         (rc = dag->dag_taubar.alloc(4 * dag->B)) || (rc = dag->dag_maxtau.alloc(4 * dag->B)) ||
         (rc = dag->dag_tausum.alloc(8 * dag->B)) || (rc = dag->dag_score.alloc(4 * kRungs * dag->B)) ||
@@ -980,6 +983,7 @@ int get_workspace(insp_dag *dag, int32_t first, int32_t count, const insp_worker
     }
     // the handle's per-call state (ensure_state has run)
     w->tr = dag->tr.as<TaskRec>();
+    w->dep = dag->dep.as<unsigned long long>();
     w->fbuf = dag->fbuf.as<int32_t>();
     w->dag_u = dag->dag_u.as<int32_t>();
     w->dag_taubar = dag->dag_taubar.as<int32_t>();

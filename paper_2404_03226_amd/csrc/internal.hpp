@@ -54,16 +54,17 @@ struct DevBuf {
     T *as() const { return static_cast<T *>(p); }
 };
 
-// Per-task simulation record: the release atomics and the candidate reads of a
-// task touch one 32-byte record.
 // Per-task simulation record (32 bytes, 32-byte aligned).  Bytes 16..31 are
 // one aligned vector (IE, IA, tau, first edge) read together; bytes 8..15
-// (queue slot, push order) likewise.  Once the task is popped its dependency
-// word and push order are dead, and bytes 0..15 hold its schedule instead:
+// (queue slot, push order) likewise.  The dependency word lives apart, in a
+// dense 8-byte array (the structure every release touches, kept small for
+// the caches).  Once the task is popped, bytes 0..15 hold its schedule:
 //   word = start | duration << 42,  qpos = -2 - worker,
 //   seq  = IE at pop | mode << 22.
+// While the task is queued under the data model, `word` holds the arrival
+// time of its inputs.
 struct TaskRec {
-    unsigned long long word;  // remaining in-degree << 43 | sum of unfinished predecessor ids
+    unsigned long long word;  // schedule once popped (see above)
     int32_t qpos;             // queue slot; -1 before the push; <= -2 once popped
     int32_t seq;              // push sequence number once queued
     int32_t iev;              // current inspiring efficiency
@@ -71,11 +72,35 @@ struct TaskRec {
 };
 static_assert(sizeof(TaskRec) == 32, "TaskRec layout");
 
-// Queue slot: key word, payload word and the task's first edge.
+// Queue slot: key word, payload word and the task's first edge (32 bytes of
+// pool per slot, the size the allocators reserve).
 struct Slot {
     unsigned long long k, x;
     int32_t rs, pad0;
     int32_t pad1, pad2;
+};
+
+// The global queue pool as three arrays -- keys, payloads, first edges --
+// so that a pop's scan of a block's keys reads 512 contiguous bytes.
+struct SlotPool {
+    unsigned long long *k, *x;
+    int32_t *rs;
+    // the pool in `bytes` of memory sized as Slot [slots]
+    __host__ __device__ static SlotPool over(void *p, size_t bytes) {
+        const size_t n = bytes / sizeof(Slot);
+        SlotPool s;
+        s.k = static_cast<unsigned long long *>(p);
+        s.x = s.k + n;
+        s.rs = reinterpret_cast<int32_t *>(s.x + n);
+        return s;
+    }
+    __host__ __device__ SlotPool at(int64_t off) const {
+        SlotPool s;
+        s.k = k + off;
+        s.x = x + off;
+        s.rs = rs + off;
+        return s;
+    }
 };
 
 // One DAG of a launch, as the kernels see it.
@@ -121,6 +146,7 @@ struct Workspace {
     // global task or DAG id: the handle's buffers, or regions of the static
     // scratch array for the allocation-free batch call.
     TaskRec *tr = nullptr;             // [N]
+    unsigned long long *dep = nullptr; // [N]: dependency words (remaining in-degree << 43 | sum of unfinished predecessors)
     int32_t *fbuf = nullptr;           // [3 N]
     int32_t *dag_u = nullptr, *dag_taubar = nullptr, *dag_maxtau = nullptr;  // [B]
     int32_t *dag_score = nullptr;      // [B * kRungs]
@@ -147,6 +173,7 @@ struct insp_dag {
     insp::DevBuf word0;                // uint64 [N] in-degree << 43 | sum of predecessor ids
     // per-task simulation state, shared by every shape (allocated on first use)
     insp::DevBuf tr;                   // TaskRec [N]
+    insp::DevBuf dep;                  // uint64 [N]: dependency words of the simulation
     insp::DevBuf fbuf;                 // int32 [3 N]: frontier runs, merged frontier, candidates
     // per-DAG attribute and status records
     insp::DevBuf dag_u, dag_taubar;    // int32 [B]
@@ -273,7 +300,7 @@ int run_transitive(insp_dag *dag, Workspace *ws, const int32_t *est, int32_t uni
 
 // Launch shape of a batch call.
 struct BatchLaunch {
-    int grid = 1, sum_cap = 0, slot_cap = 0;
+    int grid = 1, sum_cap = 0, slot_cap = 0, prio = 0, scan = 16;
 };
 
 // Argument checks and the launch shape of a batch schedule call (host only;
@@ -285,6 +312,6 @@ int batch_prologue(insp_dag *dag, const insp_workers *workers, const int32_t *du
 int launch_sim(insp_dag *dag, Workspace *ws, const insp_params &p, const int32_t *dur, const int32_t *est,
                int32_t *worker, int64_t *start, int64_t *finish, int64_t *makespan, int32_t *ie_at_pop,
                int8_t *mode_at_pop, insp_trace_rec *trace, int32_t *n_events, int waves, int grid,
-               int sum_cap, int slot_cap, hipStream_t st);
+               int sum_cap, int slot_cap, hipStream_t st, int prio_top, int scan_max);
 
 }  // namespace insp

@@ -74,7 +74,7 @@ int prepare(insp_dag *dag, const insp_workers *workers, DeviceScratch *ds, hipSt
         off += (std::max<size_t>(bytes, 16) + 255) & ~(size_t)255;
         return o;
     };
-    const size_t o_tr = take(sizeof(TaskRec) * N), o_fbuf = take(12 * N);
+    const size_t o_tr = take(sizeof(TaskRec) * N), o_dep = take(8 * N), o_fbuf = take(12 * N);
     const size_t o_u = take(4 * B), o_taubar = take(4 * B), o_maxtau = take(4 * B), o_tausum = take(8 * B);
     const size_t o_score = take(4 * kRungs * B), o_done = take(4 * B);
     const size_t o_desc = take(sizeof(DagDesc) * B), o_order = take(4 * B), o_sorder = take(4 * B);
@@ -90,6 +90,7 @@ int prepare(insp_dag *dag, const insp_workers *workers, DeviceScratch *ds, hipSt
                          off, kScratchBytes);
     unsigned char *p = ds->ptr;
     w.tr = reinterpret_cast<TaskRec *>(p + o_tr);
+    w.dep = reinterpret_cast<unsigned long long *>(p + o_dep);
     w.fbuf = reinterpret_cast<int32_t *>(p + o_fbuf);
     w.dag_u = reinterpret_cast<int32_t *>(p + o_u);
     w.dag_taubar = reinterpret_cast<int32_t *>(p + o_taubar);
@@ -148,5 +149,5 @@ extern "C" int insp_schedule_batch_noalloc(const insp_dag *cdag, const insp_work
     if ((rc = prepare(dag, workers, ds, st))) return rc;
     if ((rc = run_attributes(dag, &ds->ws, est, params->unit_time, nullptr, nullptr, nullptr, true, st))) return rc;
     return launch_sim(dag, &ds->ws, *params, dur, est, worker, start, finish, makespan, ie_at_pop, mode_at_pop,
-                      nullptr, nullptr, 1, bl.grid, bl.sum_cap, bl.slot_cap, st);
+                      nullptr, nullptr, 1, bl.grid, bl.sum_cap, bl.slot_cap, st, bl.prio, bl.scan);
 }

@@ -91,8 +91,9 @@ struct SimArgs {
     const int32_t *dur, *est;
     int64_t base;
     TaskRec *tr;
+    unsigned long long *dep;   // dependency words: remaining in-degree << 43 | sum of unfinished predecessor ids
     int32_t *fbuf;
-    Slot *slots;
+    SlotPool slots;
     unsigned long long *sums;
     int32_t *paux;
     int64_t freeb_base;
@@ -111,6 +112,8 @@ struct SimArgs {
     insp_trace_rec *trace;
     int32_t *n_events;
     int32_t s_inc, s_dec, dec_step, c, k_num, k_den, max_events;
+    int32_t prio_top;          // DAGs dispensed before this one run at raised wave priority
+    int32_t scan_max;          // a pop scans every entry of a worker with at most this many blocks (<= kScan)
 };
 
 // LDS-resident state of the DAG a work-group is simulating.
@@ -130,11 +133,12 @@ struct Lds {
     int32_t *srs;                                    // [64 * slot_cap]
     int32_t *fstk;                                   // [sum_cap] free block ids below sum_cap
     uint8_t *stale;                                  // [sum_cap] block maxima to rebuild before use
+    int32_t *hs;                                     // [4] DAG index, simulation finished, helper sink
 };
 
 __host__ __device__ constexpr size_t lds_bytes(int mw, int sc, int lb, int slc) {
     return (size_t)mw * (3 * 8 + 7 * 4 + (size_t)lb * 4) + (size_t)sc * (16 + 4 + 1) + kFC * 8 + kCC * 8 +
-           8 * 64 * 4 + (size_t)slc * 64 * 20 + 64;
+           8 * 64 * 4 + (size_t)slc * 64 * 20 + 64 + 32;
 }
 
 template <int WPL>
@@ -155,10 +159,11 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
     const int64_t ub = d.toff - A.base;
     const int32_t *col = A.col + d.eoff;
     TaskRec *tr = A.tr + d.toff;
+    unsigned long long *dep = A.dep + d.toff;
     int32_t *fbuf = A.fbuf + 3 * d.toff;      // [0,n) runs, [n,2n) merged, [2n,3n) candidates
     const int2 *est2 = reinterpret_cast<const int2 *>(A.est) + ub;
     const int2 *dur2 = reinterpret_cast<const int2 *>(A.dur) + ub;
-    Slot *slots = A.slots + 64 * d.blk_off;
+    const SlotPool slots = A.slots.at(64 * d.blk_off);
     unsigned long long *sums = A.sums + 2 * d.blk_off;
     int32_t *wblk = A.paux + d.wl_off;
     int32_t *freeb = A.paux + A.freeb_base + d.blk_off;
@@ -214,7 +219,7 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
     int32_t r = 0;
     for (int32_t i0 = 0; i0 < n; i0 += kWave) {
         int32_t i = i0 + lane;
-        bool ok = i < n && (tr[i].word >> 43) == 0;
+        bool ok = i < n && (dep[i] >> 43) == 0;
         uint64_t mk = ballot(ok);
         if (ok) {
             int32_t pos = r + lanes_below(mk);
@@ -230,7 +235,7 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
 #pragma unroll
         for (int j = 0; j < kPF; j++) pf[k][j] = 0;
     wg_fence();
-    __syncthreads();
+    __builtin_amdgcn_wave_barrier();
 
     int64_t t = 0, prev_t = 0;
     int32_t nready = 0, events = 0, done = 0, seq = 0;
@@ -382,9 +387,9 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
                         L.sx[p] = xw;
                         L.srs[p] = rs;
                     } else {
-                        slots[p].k = kw;
-                        slots[p].x = xw;
-                        slots[p].rs = rs;
+                        slots.k[p] = kw;
+                        slots.x[p] = xw;
+                        slots.rs[p] = rs;
                     }
                     tr[v].qpos = p;
                     tr[v].seq = seq;
@@ -418,7 +423,7 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
         }
         PCLK(0);
         wg_fence();
-        __syncthreads();
+        __builtin_amdgcn_wave_barrier();
         PCLK(1);
         // -------------------------------------------------------- regulate
         const int32_t observed = nready;
@@ -494,8 +499,8 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
                             mm &= mm - 1;
                             uint64_t ke = 0;
                             if (lane < (bm == last ? lp + 1 : 64)) {
-                                const uint64_t kv = bm < SLC ? L.sk[bm * 64 + lane] : wg_load(&slots[bm * 64 + lane].k);
-                                const uint64_t xv = bm < SLC ? L.sx[bm * 64 + lane] : wg_load(&slots[bm * 64 + lane].x);
+                                const uint64_t kv = bm < SLC ? L.sk[bm * 64 + lane] : wg_load(&slots.k[bm * 64 + lane]);
+                                const uint64_t xv = bm < SLC ? L.sx[bm * 64 + lane] : wg_load(&slots.x[bm * 64 + lane]);
                                 if ((int64_t)wg_load(&tr[(int32_t)(xv >> 42)].word) <= t) ke = key_of(kv, 1);
                             }
                             const uint64_t kme = wave_max_u64(ke);
@@ -541,9 +546,9 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
                         xw = L.sx[eb + lane];
                         rw = L.srs[eb + lane];
                     } else {
-                        kw = wg_load(&slots[eb + lane].k);
-                        xw = wg_load(&slots[eb + lane].x);
-                        rw = wg_load(&slots[eb + lane].rs);
+                        kw = wg_load(&slots.k[eb + lane]);
+                        xw = wg_load(&slots.x[eb + lane]);
+                        rw = wg_load(&slots.rs[eb + lane]);
                     }
                 }
                 if (okl) {
@@ -552,9 +557,9 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
                         xl = L.sx[el + lane];
                         rl = L.srs[el + lane];
                     } else {
-                        kl = wg_load(&slots[el + lane].k);
-                        xl = wg_load(&slots[el + lane].x);
-                        rl = wg_load(&slots[el + lane].rs);
+                        kl = wg_load(&slots.k[el + lane]);
+                        xl = wg_load(&slots.x[el + lane]);
+                        rl = wg_load(&slots.rs[el + lane]);
                     }
                 }
                 bool here = true;
@@ -586,9 +591,9 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
                             L.sx[p] = mx;
                             L.srs[p] = mr;
                         } else {
-                            slots[p].k = mk;
-                            slots[p].x = mx;
-                            slots[p].rs = mr;
+                            slots.k[p] = mk;
+                            slots.x[p] = mx;
+                            slots.rs[p] = mr;
                         }
                         tr[(int32_t)(mx >> 42)].qpos = p;
                         // the moved entry keeps block bb's arrival bound valid
@@ -742,8 +747,8 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
                     // to one address complete in program order)
                     uint64_t old = 0;
                     if (ok) {
-                        old = tr[s].word;
-                        tr[s].word = old + dec;
+                        old = dep[s];
+                        dep[s] = old + dec;
                     }
                     const int32_t nr = (int32_t)(old >> 43) - 1;
                     const bool rdy = ok && nr == 0, cd = ok && nr == 1;
@@ -773,7 +778,7 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
         }
         PCLK(4);
         wg_fence();
-        __syncthreads();
+        __builtin_amdgcn_wave_barrier();
         PCLK(5);
         // successors left with one unfinished predecessor raise its IE.  The
         // predecessor is named by the atomic's result (rem 1, remaining sum);
@@ -834,7 +839,7 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
                     const uint64_t nk = (uint64_t)au << 42 | (uint64_t)nie << 21 | (M21 - (uint64_t)sq);
                     const int32_t bk = qu >> 6;
                     if (bk < SLC) L.sk[qu] = nk;
-                    else slots[qu].k = nk;
+                    else slots.k[qu] = nk;
                     if (bk < SC) {
                         atomicMax(&L.sum[2 * bk], (unsigned long long)key_of(nk, slot0));
                         atomicMax(&L.sum[2 * bk + 1], (unsigned long long)key_of(nk, 1));
@@ -918,7 +923,7 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
                     if (single && i < kCC) {
                         u = L.cu[i];
                     } else {
-                        const uint64_t wd = wg_load(&tr[s].word);
+                        const uint64_t wd = wg_load(&dep[s]);
                         if ((wd >> 43) == 1) u = (int32_t)(wd & M43);
                     }
                     if (u >= 0) {
@@ -929,7 +934,7 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
                             if (pu >= 0 && !skey) {
                                 const int32_t bk = pu >> 6;
                                 const uint64_t nk = (bk < SLC ? (uint64_t)atomicAdd(&L.sk[pu], 1ull << 21)
-                                                              : (uint64_t)wg_fetch_add(&slots[pu].k, 1ull << 21)) +
+                                                              : (uint64_t)wg_fetch_add(&slots.k[pu], 1ull << 21)) +
                                                     (1ull << 21);
                                 if (bk < SC) {
                                     atomicMax(&L.sum[2 * bk], (unsigned long long)key_of(nk, slot0));
@@ -977,7 +982,7 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
         }
         PCLK(7);
         wg_fence();
-        __syncthreads();
+        __builtin_amdgcn_wave_barrier();
         PCLK(8);
     }
 #ifdef INSP_PHASE_CLOCKS
@@ -1017,7 +1022,7 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
 //     (which a later rebuild overwrites), and a many-block pop rebuilds the
 //     stale ones of its worker before comparing.  Maxima kept in global memory
 //     (block ids >= sum_cap) are rebuilt at once.
-constexpr int kScan = 16;
+constexpr int kScan = 16;  // the most a launch may scan (tune key "scan=")
 
 // Key layout of one DAG.
 struct KeyFmt {
@@ -1047,13 +1052,13 @@ struct Keys32 {
 // wave-uniform: the choice between LDS and global memory is a scalar branch,
 // and the global side waits for its load itself, so the LDS side carries no
 // wait for outstanding global accesses.
-__device__ __forceinline__ uint32_t block_keys32(const Slot *slots, const Keys32 &K, int32_t slc, int32_t b, int r) {
+__device__ __forceinline__ uint32_t block_keys32(const SlotPool &slots, const Keys32 &K, int32_t slc, int32_t b, int r) {
     const int lane = lane_id();
     uint32_t k;
     if (b < slc) {
         k = (r ? K.ke : K.ka)[b * 64 + lane];
     } else {
-        k = (uint32_t)(wg_load(&slots[b * 64 + lane].k) >> (r ? 32 : 0));
+        k = (uint32_t)(wg_load(&slots.k[b * 64 + lane]) >> (r ? 32 : 0));
         settle(k);
     }
     return k;
@@ -1063,7 +1068,7 @@ __device__ __forceinline__ uint32_t block_keys32(const Slot *slots, const Keys32
 // lanes of `bl`, which hold block ids), four loads in flight at a time;
 // FROM_LDS picks where the blocks' slots live.
 template <bool FROM_LDS, int R>
-__device__ __forceinline__ void scan_columns(const Slot *slots, const Keys32 &K, uint64_t m, int32_t bl,
+__device__ __forceinline__ void scan_columns(const SlotPool &slots, const Keys32 &K, uint64_t m, int32_t bl,
                                              uint32_t &best, int32_t &bp) {
     const int lane = lane_id();
     const uint32_t *keys = R ? K.ke : K.ka;
@@ -1079,7 +1084,7 @@ __device__ __forceinline__ void scan_columns(const Slot *slots, const Keys32 &K,
                 m &= m - 1;
             }
             pp[u] = b * 64 + lane;
-            kk[u] = FROM_LDS ? keys[pp[u]] : (uint32_t)(wg_load(&slots[pp[u]].k) >> (R ? 32 : 0));
+            kk[u] = FROM_LDS ? keys[pp[u]] : (uint32_t)(wg_load(&slots.k[pp[u]]) >> (R ? 32 : 0));
         }
 #pragma unroll
         for (int u = 0; u < 4; u++) {
@@ -1092,7 +1097,7 @@ __device__ __forceinline__ void scan_columns(const Slot *slots, const Keys32 &K,
 }
 
 // Rebuild both maxima of block b from its first `cnt` entries (wave-wide).
-__device__ __forceinline__ void rebuild_max32(const Slot *slots, const Keys32 &K, const Lds &L,
+__device__ __forceinline__ void rebuild_max32(const SlotPool &slots, const Keys32 &K, const Lds &L,
                                               unsigned long long *sums, int32_t slc, int32_t sc, int32_t b) {
     const int lane = lane_id();
     const uint32_t s0 = wave_max_u32f(block_keys32(slots, K, slc, b, 0));
@@ -1126,10 +1131,11 @@ __device__ bool sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
     const int64_t ub = d.toff - A.base;
     const int32_t *col = A.col + d.eoff;
     TaskRec *tr = A.tr + d.toff;
+    unsigned long long *dep = A.dep + d.toff;
     int32_t *fbuf = A.fbuf + 3 * d.toff;      // [0,n) runs, [n,2n) merged, [2n,3n) candidates
     const int2 *est2 = reinterpret_cast<const int2 *>(A.est) + ub;
     const int2 *dur2 = reinterpret_cast<const int2 *>(A.dur) + ub;
-    Slot *slots = A.slots + 64 * d.blk_off;
+    const SlotPool slots = A.slots.at(64 * d.blk_off);
     unsigned long long *sums = A.sums + 2 * d.blk_off;
     int32_t *wblk = A.paux + d.wl_off;
     int32_t *freeb = A.paux + A.freeb_base + d.blk_off;
@@ -1146,7 +1152,7 @@ __device__ bool sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
         int32_t i = i0 + lane;
         bool ok = false;
         if (i < n) {
-            ok = (tr[i].word >> 43) == 0;
+            ok = (dep[i] >> 43) == 0;
             mdeg = max(mdeg, (uint32_t)tr[i].ia);
         }
         uint64_t mk = ballot(ok);
@@ -1202,7 +1208,7 @@ __device__ bool sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
             K.ka[b * 64 + lane] = 0;
             K.ke[b * 64 + lane] = 0;
         } else {
-            slots[b * 64 + lane].k = 0;
+            slots.k[b * 64 + lane] = 0;
         }
     }
 
@@ -1335,9 +1341,9 @@ __device__ bool sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
                     L.sx[pq] = xw;
                     L.srs[pq] = rs_l;
                 } else {
-                    slots[pq].k = (uint64_t)a1 << 32 | a0;
-                    slots[pq].x = xw;
-                    slots[pq].rs = rs_l;
+                    slots.k[pq] = (uint64_t)a1 << 32 | a0;
+                    slots.x[pq] = xw;
+                    slots.rs[pq] = rs_l;
                 }
                 tr[v_l].qpos = pq;
                 tr[v_l].seq = sqj;
@@ -1407,7 +1413,7 @@ __device__ bool sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
             const int32_t lastpos = (lenw - 1) & 63;
             int32_t p;
             PCLK(10);
-            if (nbw <= kScan) {
+            if (nbw <= A.scan_max) {
                 // lane l compares entry l of every block of the worker: the
                 // blocks held in LDS, then those in global memory (a single
                 // block is the last one, known without reading the list)
@@ -1506,9 +1512,9 @@ __device__ bool sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
                 vx = L.sx[p];
                 vr = L.srs[p];
             } else {
-                ve = (uint32_t)(wg_load(&slots[p].k) >> 32);
-                vx = wg_load(&slots[p].x);
-                vr = wg_load(&slots[p].rs);
+                ve = (uint32_t)(wg_load(&slots.k[p]) >> 32);
+                vx = wg_load(&slots.x[p]);
+                vr = wg_load(&slots.rs[p]);
                 settle(ve);
                 settle(vx);
                 settle(vr);
@@ -1520,9 +1526,9 @@ __device__ bool sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
                     mx = L.sx[q];
                     mr = L.srs[q];
                 } else {
-                    const uint64_t mk = wg_load(&slots[q].k);
-                    mx = wg_load(&slots[q].x);
-                    mr = wg_load(&slots[q].rs);
+                    const uint64_t mk = wg_load(&slots.k[q]);
+                    mx = wg_load(&slots.x[q]);
+                    mr = wg_load(&slots.rs[q]);
                     settle(mk);
                     settle(mx);
                     settle(mr);
@@ -1541,9 +1547,9 @@ __device__ bool sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
                         L.sx[p] = mx;
                         L.srs[p] = mr;
                     } else {
-                        slots[p].k = (uint64_t)me << 32 | ma;
-                        slots[p].x = mx;
-                        slots[p].rs = mr;
+                        slots.k[p] = (uint64_t)me << 32 | ma;
+                        slots.x[p] = mx;
+                        slots.rs[p] = mr;
                     }
                 }
                 if (lane == popped) {
@@ -1557,7 +1563,7 @@ __device__ bool sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
                     K.ka[q] = 0;
                     K.ke[q] = 0;
                 } else {
-                    slots[q].k = 0;
+                    slots.k[q] = 0;
                 }
             }
             PCLK(12);
@@ -1625,6 +1631,11 @@ __device__ bool sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
             for (int j = 0; j < kPF; j++) pf[j] = col[rsr + min(j, dgr - 1)];
         }
         if (mvt >= 0) tr[mvt].qpos = mvp;
+        // the running tasks, for the work-group's prefetching wave
+        if (wok) {
+            L.run[lane] = run;
+            L.fin[lane] = fin;
+        }
         PCLK(15);
         PCLK(2);
         if (A.trace && lane == 0 && events <= max_events) {
@@ -1684,8 +1695,8 @@ __device__ bool sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
                     // to one address complete in program order)
                     uint64_t old = 0;
                     if (ok) {
-                        old = tr[s].word;
-                        tr[s].word = old + dec;
+                        old = dep[s];
+                        dep[s] = old + dec;
                     }
                     const int32_t nr = (int32_t)(old >> 43) - 1;
                     const bool rdy = ok && nr == 0, cd = ok && nr == 1;
@@ -1793,7 +1804,7 @@ __device__ bool sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
                         K.ka[qu] = na;
                         K.ke[qu] = ne;
                     } else {
-                        slots[qu].k = (uint64_t)ne << 32 | na;
+                        slots.k[qu] = (uint64_t)ne << 32 | na;
                     }
                     if (bk < SC) {
                         atomicMax(&K.mx[2 * bk], na);
@@ -1863,7 +1874,7 @@ __device__ bool sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
                     if (single && i < kCC) {
                         u = L.cu[i];
                     } else {
-                        const uint64_t wd = wg_load(&tr[s].word);
+                        const uint64_t wd = wg_load(&dep[s]);
                         if ((wd >> 43) == 1) u = (int32_t)(wd & M43);
                     }
                     if (u >= 0) {
@@ -1879,7 +1890,7 @@ __device__ bool sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
                                     ne = atomicAdd(&K.ke[pu], kf.de()) + kf.de();
                                 } else {
                                     const unsigned long long inc = (unsigned long long)kf.de() << 32 | kf.da();
-                                    const uint64_t nk = wg_fetch_add(&slots[pu].k, inc) + inc;
+                                    const uint64_t nk = wg_fetch_add(&slots.k[pu], inc) + inc;
                                     na = (uint32_t)nk;
                                     ne = (uint32_t)(nk >> 32);
                                 }
@@ -1971,26 +1982,125 @@ __device__ __forceinline__ Lds carve_lds(const SimArgs &A) {
     L.srs = L.pre + 8 * kWave;
     L.fstk = L.srs + 64 * A.slot_cap;
     L.stale = reinterpret_cast<uint8_t *>(L.fstk + A.sum_cap);
+    L.hs = reinterpret_cast<int32_t *>(L.stale + ((A.sum_cap + 15) & ~15));
     return L;
 }
 
+// The work-group's second wave, while the first simulates DAG di: it reads
+// ahead for the running tasks that finish first -- their successor lists,
+// the successors' dependency words, and the records and estimate rows the
+// release of those tasks will read (of successors about to become ready,
+// and of the remaining predecessor of those about to have one left) -- so
+// that the simulating wave finds them in the caches.  It only reads, and it
+// stops when the simulating wave marks the DAG finished.
+constexpr int kAhead = 4;          // running tasks read ahead for, earliest finish first
+constexpr int kAheadEdges = 16;    // successors read per task
+constexpr int64_t kHelperSpin = 1ll << 40;
+
+__device__ void read_ahead(const SimArgs &A, int32_t di, const Lds &L) {
+    const DagDesc d = A.desc[di];
+    const int lane = lane_id();
+    const int32_t W = d.n_cpu + d.n_gpu;
+    const bool wok = lane < W && W <= kWave && d.n > 0;
+    const int64_t ub = d.toff - A.base;
+    const int32_t *col = A.col + d.eoff;
+    const TaskRec *tr = A.tr + d.toff;
+    const unsigned long long *dep = A.dep + d.toff;
+    const int2 *est2 = reinterpret_cast<const int2 *>(A.est) + ub;
+    const int2 *dur2 = reinterpret_cast<const int2 *>(A.dur) + ub;
+    int32_t pref = -1;  // the last task read ahead for this lane's worker
+    uint32_t sink = 0;
+    for (int64_t it = 0; it < kHelperSpin; it++) {
+        if (__hip_atomic_load(&L.hs[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) break;
+        const int32_t c = wok ? __hip_atomic_load(&L.run[lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) : -1;
+        const int64_t f = c >= 0 ? __hip_atomic_load(&L.fin[lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)
+                                 : INT64_MAX;
+        // the kAhead-th earliest finish among the running tasks
+        uint64_t thr = 0;
+        {
+            uint64_t prev = 0;
+            bool first = true;
+            for (int k = 0; k < kAhead; k++) {
+                const uint64_t m = wave_min_u64f(first || (uint64_t)f > prev ? (uint64_t)f : ~0ull);
+                if (m == ~0ull) break;
+                thr = m;
+                prev = m;
+                first = false;
+            }
+        }
+        const bool go = c >= 0 && c != pref && c < d.n && (uint64_t)f <= thr;
+        if (!ballot(go)) {
+            __builtin_amdgcn_s_sleep(4);
+            continue;
+        }
+        if (go) {
+            pref = c;
+            const int4 fx = *reinterpret_cast<const int4 *>(&tr[c].iev);  // IE, IA, tau, first edge
+            const int32_t deg = min(fx.y, kAheadEdges), rs = fx.w;
+            int32_t sv[kAheadEdges];
+            unsigned long long dw[kAheadEdges];
+#pragma unroll
+            for (int j = 0; j < kAheadEdges; j++) sv[j] = deg > 0 ? col[rs + min(j, deg - 1)] : c;
+#pragma unroll
+            for (int j = 0; j < kAheadEdges; j++) dw[j] = dep[sv[j]];
+#pragma unroll
+            for (int j = 0; j < kAheadEdges; j++) {
+                if (j >= deg) break;
+                const uint32_t rem = (uint32_t)(dw[j] >> 43);
+                if (rem == 1) {
+                    const int2 e = est2[sv[j]], u = dur2[sv[j]];
+                    const int4 q = *reinterpret_cast<const int4 *>(&tr[sv[j]].iev);
+                    const int2 qs = *reinterpret_cast<const int2 *>(&tr[sv[j]].qpos);
+                    sink ^= (uint32_t)(e.x ^ u.y ^ q.x ^ qs.x);
+                } else if (rem == 2) {
+                    const int32_t pu = (int32_t)((dw[j] & ((1ull << 43) - 1)) - (unsigned long long)c);
+                    if (pu >= 0 && pu < d.n) {
+                        const int4 q = *reinterpret_cast<const int4 *>(&tr[pu].iev);
+                        const int2 qs = *reinterpret_cast<const int2 *>(&tr[pu].qpos);
+                        sink ^= (uint32_t)(q.x ^ qs.y);
+                    }
+                    sink ^= (uint32_t)tr[sv[j]].tau;
+                }
+            }
+        }
+    }
+    L.hs[2] = (int32_t)sink;  // keeps the reads
+}
+
 template <int WPL>
-__global__ __launch_bounds__(64) void k_sim(SimArgs A) {
+__global__ __launch_bounds__(WPL == 1 ? 2 * kWave : kWave) void k_sim(SimArgs A) {
     const Lds L = carve_lds(A);
     const int lane = lane_id();
+    // one wave simulates; under the one-wave loop's launch a second wave reads ahead
+    const bool helper = WPL == 1 && threadIdx.x >= kWave;
     for (;;) {
-        int32_t got = 0;
-        if (lane == 0) got = dev_fetch_add(A.counter, 1);
-        const int32_t i = read_lane(got, 0);
+        if (threadIdx.x == 0) {
+            L.hs[0] = dev_fetch_add(A.counter, 1);
+            L.hs[1] = 0;
+        }
+        if (threadIdx.x < kWave)
+            for (int32_t w = lane; w < A.max_w * WPL && w < kWave; w += kWave) L.run[w] = -1;
+        __syncthreads();
+        const int32_t i = L.hs[0];
         if (i >= A.count) break;
-        if constexpr (WPL == 1) {
-            // fixed keys (HEFT, transitive attributes), the data model, the
-            // locality policy and keys wider than 32 bits take the 64-bit loop
-            if (A.policy == INSP_POLICY_HEFT || A.policy == INSP_POLICY_LOCALITY ||
-                A.attr_mode == INSP_ATTR_TRANSITIVE || A.data_bw > 0 || !sim_lane(A, A.order[i], L))
-                sim_dag<1>(A, A.order[i], L);
+        if (helper) {
+            read_ahead(A, A.order[i], L);
         } else {
-            sim_dag<WPL>(A, A.order[i], L);
+            // the largest DAGs (dispensed first) set the batch's critical path:
+            // their waves win instruction issue over co-resident waves
+            if (i < A.prio_top) __builtin_amdgcn_s_setprio(3);
+            else __builtin_amdgcn_s_setprio(0);
+            if constexpr (WPL == 1) {
+                // fixed keys (HEFT, transitive attributes), the data model, the
+                // locality policy and keys wider than 32 bits take the 64-bit loop
+                if (A.policy == INSP_POLICY_HEFT || A.policy == INSP_POLICY_LOCALITY ||
+                    A.attr_mode == INSP_ATTR_TRANSITIVE || A.data_bw > 0 || !sim_lane(A, A.order[i], L))
+                    sim_dag<1>(A, A.order[i], L);
+            } else {
+                sim_dag<WPL>(A, A.order[i], L);
+            }
+            wg_fence();
+            if (lane == 0) __hip_atomic_store(&L.hs[1], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         }
         __syncthreads();
     }
@@ -2020,7 +2130,7 @@ __global__ __launch_bounds__(256) void k_records(const TaskRec *tr, int64_t n, i
 int launch_sim(insp_dag *dag, Workspace *ws, const insp_params &p, const int32_t *dur, const int32_t *est,
                int32_t *worker, int64_t *start, int64_t *finish, int64_t *makespan, int32_t *ie_at_pop,
                int8_t *mode_at_pop, insp_trace_rec *trace, int32_t *n_events, int waves, int grid,
-               int sum_cap, int slot_cap, hipStream_t st) {
+               int sum_cap, int slot_cap, hipStream_t st, int prio_top, int scan_max) {
     (void)waves;
     SimArgs A;
     memset(&A, 0, sizeof A);
@@ -2033,8 +2143,9 @@ int launch_sim(insp_dag *dag, Workspace *ws, const insp_params &p, const int32_t
     A.est = est;
     A.base = ws->base;
     A.tr = ws->tr;
+    A.dep = ws->dep;
     A.fbuf = ws->fbuf;
-    A.slots = ws->slots.as<Slot>();
+    A.slots = SlotPool::over(ws->slots.p, ws->slots.bytes);
     A.sums = ws->sums.as<unsigned long long>();
     A.paux = ws->paux.as<int32_t>();
     A.freeb_base = ws->total_wl;
@@ -2063,6 +2174,8 @@ int launch_sim(insp_dag *dag, Workspace *ws, const insp_params &p, const int32_t
     A.k_num = p.k_num;
     A.k_den = p.k_den;
     A.max_events = p.max_events;
+    A.prio_top = prio_top;
+    A.scan_max = scan_max;
     // block maxima in LDS: all of a single DAG's blocks up to 64 KB, or the
     // low block ids of each DAG of a batch
     // LDS: block maxima, block lists and the slots of the low blocks --
@@ -2092,7 +2205,7 @@ int launch_sim(insp_dag *dag, Workspace *ws, const insp_params &p, const int32_t
         ProfScope ps(st, "sim");
         if (ws->max_w <= 64) {
             if (int rc = set_lds_limit((const void *)&k_sim<1>, lds)) return rc;
-            hipLaunchKernelGGL(k_sim<1>, dim3(grid), dim3(64), lds, st, A);
+            hipLaunchKernelGGL(k_sim<1>, dim3(grid), dim3(2 * kWave), lds, st, A);
         } else if (ws->max_w <= 128) {
             if (int rc = set_lds_limit((const void *)&k_sim<2>, lds)) return rc;
             hipLaunchKernelGGL(k_sim<2>, dim3(grid), dim3(64), lds, st, A);
@@ -2182,13 +2295,16 @@ extern "C" int insp_schedule(const insp_dag *cdag, int32_t index, const insp_wor
     if (params->data_bw > 0 && !dag->dxc.p && (rc = dag->dxc.alloc(sizeof(int32_t) * std::max<int64_t>(dag->N, 1))))
         return rc;
     return launch_sim(dag, ws, *params, dur, est, worker, start, finish, makespan, ie_at_pop, mode_at_pop, trace,
-                      n_events, 1, 1, 4096, 0, st);
+                      n_events, 1, 1, 4096, 0, st, 0, kScan);
 }
 
-static void parse_tune(const char *key, int *waves, int *grid, int *sum_cap, int *slot_cap) {
+static void parse_tune(const char *key, int *waves, int *grid, int *sum_cap, int *slot_cap, int *prio, int *scan) {
     if (!key) return;
     std::string s(key);
     size_t a = s.find("waves="), b = s.find("grid="), c = s.find("lds_blocks="), d = s.find("lds_slots=");
+    size_t e = s.find("prio="), f = s.find("scan=");
+    if (e != std::string::npos) *prio = atoi(s.c_str() + e + 5);
+    if (f != std::string::npos) *scan = atoi(s.c_str() + f + 5);
     if (a != std::string::npos) *waves = atoi(s.c_str() + a + 6);
     if (b != std::string::npos) *grid = atoi(s.c_str() + b + 5);
     if (c != std::string::npos) *sum_cap = atoi(s.c_str() + c + 11);
@@ -2207,15 +2323,18 @@ int batch_prologue(insp_dag *dag, const insp_workers *workers, const int32_t *du
     if (dag->N > 0 && (!dur || !est || !worker || !start || !finish)) return set_error(INSP_E_INVAL, "null array");
     if ((((uintptr_t)dur | (uintptr_t)est) & 7) != 0) return set_error(INSP_E_INVAL, "dur/est rows must be 8-byte aligned");
     INSP_HIP(hipSetDevice(dag->device));
-    int waves = 1, grid = default_grid(dag->B), sum_cap = 256, slot_cap = 16;
-    parse_tune(tune_key, &waves, &grid, &sum_cap, &slot_cap);
-    if (grid < 1 || sum_cap < 0 || sum_cap > 8192 || slot_cap < 0 || lds_bytes(1, sum_cap, 16, slot_cap) > 150 * 1024)
+    int waves = 1, grid = default_grid(dag->B), sum_cap = 256, slot_cap = 16, prio = 0, scan = kScan;
+    parse_tune(tune_key, &waves, &grid, &sum_cap, &slot_cap, &prio, &scan);
+    if (grid < 1 || sum_cap < 0 || sum_cap > 8192 || slot_cap < 0 || prio < 0 || scan < 0 || scan > kScan ||
+        lds_bytes(1, sum_cap, 16, slot_cap) > 150 * 1024)
         return set_error(INSP_E_INVAL, "bad tune key '%s'", tune_key);
     // one wave simulates one DAG; no other shape is implemented
     if (waves != 1) return set_error(INSP_E_INVAL, "tune key '%s': only waves=1 is supported", tune_key);
     launch->grid = grid;
     launch->sum_cap = sum_cap;
     launch->slot_cap = slot_cap;
+    launch->prio = prio;
+    launch->scan = scan;
     return INSP_OK;
 }
 
@@ -2242,7 +2361,7 @@ extern "C" int insp_schedule_batch(const insp_dag *cdag, const insp_workers *wor
     if (params->data_bw > 0 && !dag->dxc.p && (rc = dag->dxc.alloc(sizeof(int32_t) * std::max<int64_t>(dag->N, 1))))
         return rc;
     return launch_sim(dag, ws, *params, dur, est, worker, start, finish, makespan, ie_at_pop, mode_at_pop, nullptr,
-                      nullptr, 1, bl.grid, bl.sum_cap, bl.slot_cap, st);
+                      nullptr, 1, bl.grid, bl.sum_cap, bl.slot_cap, st, bl.prio, bl.scan);
 }
 
 #ifdef INSP_PHASE_CLOCKS
