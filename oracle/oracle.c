@@ -235,25 +235,25 @@ int orc_transitive(int32_t n, const int32_t *rp, const int32_t *col, const int32
     int32_t *order = (int32_t *)malloc(sizeof(int32_t) * ((size_t)n + 1));
     int32_t *pos = (int32_t *)malloc(sizeof(int32_t) * ((size_t)n + 1));
     int64_t *EF = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
-    int32_t *hist = (int32_t *)calloc((size_t)n * 64 + 1, sizeof(int32_t)); /* members by ceil(log2 EF) */
+    /* within[v][j]: members of D(v) whose finish from v's start is <= 2^j */
+    int32_t *within = (int32_t *)calloc((size_t)n * 32 + 1, sizeof(int32_t));
     int rc = ORC_OK;
-    if (!order || !pos || !EF || !hist) { rc = ORC_E_NOMEM; goto out; }
+    if (!order || !pos || !EF || !within) { rc = ORC_E_NOMEM; goto out; }
     if ((rc = topo_order(n, rp, col, order))) goto out;
     for (int32_t i = 0; i < n; i++) pos[order[i]] = i;
     int64_t cp = 0;
     for (int32_t v = 0; v < n; v++) {
         memset(EF, 0, sizeof(int64_t) * (size_t)n);
         EF[v] = tau_of(est, n_gpu, v);
-        int32_t members = 0, within = 0;
+        int32_t members = 0, in_u = 0;
         for (int32_t i = pos[v]; i < n; i++) {
             int32_t u = order[i];
             if (EF[u] == 0) continue;  /* not reachable from v */
             members++;
             if (EF[u] > cp) cp = EF[u];
-            if (unit_time > 0 && EF[u] <= unit_time) within++;
-            int b = 0;
-            while (((int64_t)1 << b) < EF[u]) b++;
-            if (b < 64) hist[(int64_t)v * 64 + b]++;
+            if (unit_time > 0 && EF[u] <= unit_time) in_u++;
+            for (int j = 0; j < 32; j++)
+                if (EF[u] <= ((int64_t)1 << j)) within[(int64_t)v * 32 + j]++;
             for (int32_t e = rp[u]; e < rp[u + 1]; e++) {
                 int32_t s = col[e];
                 int64_t f = EF[u] + tau_of(est, n_gpu, s);
@@ -261,12 +261,14 @@ int orc_transitive(int32_t n, const int32_t *rp, const int32_t *col, const int32
             }
         }
         ia[v] = members;
-        ie[v] = within;
+        ie[v] = in_u;
     }
     if (longest) *longest = cp;
     if (cp >= ORC_MAX_PATH) { rc = ORC_E_RANGE; goto out; }
     int64_t U = unit_time;
     if (unit_time == 0) {
+        /* rungs 2^0 .. 2^J, 2^J the first power of two >= the longest path;
+           score = tasks with 0 < IE_T < IA_T; the larger U on a tie */
         int J = 0;
         while (((int64_t)1 << J) < cp) J++;
         int64_t bestScore = -1;
@@ -274,22 +276,17 @@ int orc_transitive(int32_t n, const int32_t *rp, const int32_t *col, const int32
         for (int j = 0; j <= J; j++) {
             int64_t score = 0;
             for (int32_t v = 0; v < n; v++) {
-                int32_t cum = 0;
-                for (int b = 0; b <= j; b++) cum += hist[(int64_t)v * 64 + b];
-                if (cum > 0 && cum < ia[v]) score++;
+                const int32_t w = within[(int64_t)v * 32 + j];
+                if (w > 0 && w < ia[v]) score++;
             }
             if (score >= bestScore) { bestScore = score; bestJ = j; }
         }
         U = (int64_t)1 << bestJ;
-        for (int32_t v = 0; v < n; v++) {
-            int32_t cum = 0;
-            for (int b = 0; b <= bestJ; b++) cum += hist[(int64_t)v * 64 + b];
-            ie[v] = cum;
-        }
+        for (int32_t v = 0; v < n; v++) ie[v] = within[(int64_t)v * 32 + bestJ];
     }
     if (U_used) *U_used = (int32_t)U;
 out:
-    free(order); free(pos); free(EF); free(hist);
+    free(order); free(pos); free(EF); free(within);
     return rc;
 }
 

@@ -50,8 +50,9 @@ MUTATIONS = {
     "rank_tie_latest_push": ("if (order == 3) return sq_a < sq_b;", "if (order == 3) return sq_a > sq_b;"),
     "trans_exclusive_count": ("            members++;\n", "            if (u != v) members++;\n"),
     "trans_shortest_path": ("if (f > EF[s]) EF[s] = f;", "if (EF[s] == 0 || f < EF[s]) EF[s] = f;"),
-    "trans_window_strict": ("if (unit_time > 0 && EF[u] <= unit_time) within++;",
-                            "if (unit_time > 0 && EF[u] < unit_time) within++;"),
+    "trans_window_strict": ("if (unit_time > 0 && EF[u] <= unit_time) in_u++;",
+                            "if (unit_time > 0 && EF[u] < unit_time) in_u++;"),
+    "trans_rung_strict": ("if (EF[u] <= ((int64_t)1 << j)) within[", "if (EF[u] < ((int64_t)1 << j)) within["),
     "trans_ladder_short": ("while (((int64_t)1 << J) < cp) J++;", "while (((int64_t)1 << J) < cp / 2) J++;"),
     "trans_ladder_tie_smaller": ("if (score >= bestScore) { bestScore = score; bestJ = j; }",
                                  "if (score > bestScore) { bestScore = score; bestJ = j; }"),
