@@ -17,15 +17,24 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-Wal
          "-I" + os.path.join(ROOT, "include"), "-I" + CSRC]
 
 
-def build(verbose: bool = False) -> str:
+# Host code under AddressSanitizer and UndefinedBehaviorSanitizer (device
+# code is built as usual); the result needs the clang ASan runtime preloaded.
+SANITIZE = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+            "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-fno-sanitize-recover=all"]
+
+
+def build(verbose: bool = False, sanitize: bool = False, out: str = None) -> str:
     """Compile every HIP source into one shared library (always recompiles)."""
     srcs = [os.path.join(CSRC, s) for s in SOURCES]
+    lib = out or LIB
+    objdir = os.path.join(os.path.dirname(lib) if out else CSRC, "_build_san" if sanitize else "_build")
+    extra = SANITIZE if sanitize else []
     objs = []
     procs = []
     for s in srcs:
-        o = os.path.join(CSRC, "_build", os.path.basename(s) + ".o")
+        o = os.path.join(objdir, os.path.basename(s) + ".o")
         os.makedirs(os.path.dirname(o), exist_ok=True)
-        cmd = [HIPCC, *[f for f in FLAGS if f != "-shared"], "-c", s, "-o", o]
+        cmd = [HIPCC, *[f for f in FLAGS if f != "-shared"], *extra, "-c", s, "-o", o]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((subprocess.Popen(cmd), s))
@@ -33,10 +42,10 @@ def build(verbose: bool = False) -> str:
     for p, s in procs:
         if p.wait() != 0:
             raise RuntimeError(f"hipcc failed on {s}")
-    tmp = LIB + ".tmp%d" % os.getpid()
+    tmp = lib + ".tmp%d" % os.getpid()
     subprocess.check_call([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs])
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":

@@ -14,7 +14,9 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libinspirit.so")
+# INSP_LIB points the binding at another build of the library (the
+# sanitizer test's host-instrumented one)
+LIB_PATH = os.environ.get("INSP_LIB") or os.path.join(_HERE, "libinspirit.so")
 
 OK, E_INVAL, E_CYCLE, E_RANGE, E_NOMEM, E_DEVICE, E_HANG = 0, 1, 2, 3, 4, 5, 6
 POLICY = {"inspirit": 0, "fifo": 1, "ability": 2, "efi": 3, "heft": 4, "locality": 5}
