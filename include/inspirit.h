@@ -306,6 +306,29 @@ int insp_schedule_batch_noalloc(const insp_dag *dag, const insp_workers *workers
                                 int64_t *finish, int64_t *makespan, int32_t *ie_at_pop, int8_t *mode_at_pop,
                                 const char *tune_key, void *stream);
 
+/*
+ * The batch step as a HIP graph the library owns (batching in one launch
+ * replayed without per-call host work).  insp_batch_graph_create takes the
+ * arguments of insp_schedule_batch: it runs one eager step on `stream`
+ * (which builds every buffer made on first use and synchronises the stream),
+ * then captures the same step -- the attribute pass, the persistent
+ * simulation and the unpacking of the schedules, kernel launches only -- on a
+ * stream of its own.  Each insp_batch_graph_launch enqueues one replay on
+ * `stream`, reading the input arrays given at creation and writing the same
+ * output arrays (update their contents in place between replays, never
+ * their addresses); failures are reported by insp_sync_status as for an
+ * eager call.  The handle and every array must outlive the graph, and the
+ * handle must not be used by other calls while a replay runs.
+ * insp_batch_graph_free releases the graph (NULL is ignored).
+ */
+typedef struct insp_graph insp_graph;
+int insp_batch_graph_create(const insp_dag *dag, const insp_workers *workers, const int32_t *dur,
+                            const int32_t *est, const insp_params *params, int32_t *worker, int64_t *start,
+                            int64_t *finish, int64_t *makespan, int32_t *ie_at_pop, int8_t *mode_at_pop,
+                            const char *tune_key, void *stream, insp_graph **out);
+int insp_batch_graph_launch(insp_graph *graph, void *stream);
+void insp_batch_graph_free(insp_graph *graph);
+
 /* Synchronise `stream` and report a device-side failure of the schedule
  * calls (insp_schedule, insp_schedule_batch) enqueued on the handle since the
  * last check: INSP_E_HANG, or INSP_E_RANGE for a tick value out of range, a

@@ -251,6 +251,8 @@ int set_lds_limit(const void *kernel, size_t bytes);
 
 // Kernel timing hook: brackets a launch with events when profiling is on.
 void prof_mark(hipStream_t st, const char *kernel, bool begin);
+// Stop (true) or resume (false) the calling thread's marks (graph capture).
+void prof_suspend(bool on);
 struct ProfScope {
     hipStream_t st;
     const char *name;

@@ -61,7 +61,13 @@ Prof &prof() {
 
 }  // namespace
 
+// Marks are not recorded while this thread captures a graph.
+static thread_local int t_suspended = 0;
+
+void prof_suspend(bool on) { t_suspended += on ? 1 : -1; }
+
 void prof_mark(hipStream_t st, const char *kernel, bool begin) {
+    if (t_suspended) return;
     Prof &p = prof();
     std::lock_guard<std::mutex> g(p.mu);
     if (!p.on) return;

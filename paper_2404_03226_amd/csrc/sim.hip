@@ -2364,6 +2364,59 @@ extern "C" int insp_schedule_batch(const insp_dag *cdag, const insp_workers *wor
                       nullptr, 1, bl.grid, bl.sum_cap, bl.slot_cap, st, bl.prio, bl.scan);
 }
 
+// A batch step captured in a HIP graph owned by the library.
+struct insp_graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int device = 0;
+};
+
+extern "C" void insp_batch_graph_free(insp_graph *g) {
+    if (!g) return;
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
+}
+
+extern "C" int insp_batch_graph_create(const insp_dag *cdag, const insp_workers *workers, const int32_t *dur,
+                                       const int32_t *est, const insp_params *params, int32_t *worker,
+                                       int64_t *start, int64_t *finish, int64_t *makespan, int32_t *ie_at_pop,
+                                       int8_t *mode_at_pop, const char *tune_key, void *stream, insp_graph **out) {
+    if (!out) return set_error(INSP_E_INVAL, "null out");
+    *out = nullptr;
+    // an eager step first: it builds every buffer made on first use and sets
+    // the kernels' attributes, so that the captured step only launches kernels
+    int rc = insp_schedule_batch(cdag, workers, dur, est, params, worker, start, finish, makespan, ie_at_pop,
+                                 mode_at_pop, tune_key, stream);
+    if (rc) return rc;
+    INSP_HIP(hipStreamSynchronize((hipStream_t)stream));
+    std::unique_ptr<insp_graph> g(new insp_graph());
+    g->device = cdag->device;
+    hipStream_t cs = nullptr;
+    INSP_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        prof_suspend(true);
+        rc = insp_schedule_batch(cdag, workers, dur, est, params, worker, start, finish, makespan, ie_at_pop,
+                                 mode_at_pop, tune_key, cs);
+        prof_suspend(false);
+        e = hipStreamEndCapture(cs, &g->graph);
+    }
+    (void)hipStreamDestroy(cs);
+    if (rc) return rc;
+    if (e != hipSuccess) return set_error(INSP_E_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
+    INSP_HIP(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
+    *out = g.release();
+    return INSP_OK;
+}
+
+extern "C" int insp_batch_graph_launch(insp_graph *g, void *stream) {
+    if (!g || !g->exec) return set_error(INSP_E_INVAL, "null graph");
+    INSP_HIP(hipSetDevice(g->device));
+    INSP_HIP(hipGraphLaunch(g->exec, (hipStream_t)stream));
+    return INSP_OK;
+}
+
 #ifdef INSP_PHASE_CLOCKS
 extern "C" int insp_debug_phase_clocks(unsigned long long *host, int count) {
     INSP_HIP(hipMemcpyFromSymbol(host, HIP_SYMBOL(g_phase_clk), sizeof(unsigned long long) * 32 * count));

@@ -28,7 +28,8 @@ ALL_DAGS = -1
 EXPORTS = ("insp_build_dag", "insp_set_task_data", "insp_free_dag", "insp_dag_info", "insp_attributes",
            "insp_transitive_attributes",
            "insp_schedule",
-           "insp_schedule_batch", "insp_schedule_batch_noalloc", "insp_sync_status", "insp_profile_enable", "insp_profile_read",
+           "insp_schedule_batch", "insp_schedule_batch_noalloc", "insp_batch_graph_create",
+           "insp_batch_graph_launch", "insp_batch_graph_free", "insp_sync_status", "insp_profile_enable", "insp_profile_read",
            "insp_mlp_create", "insp_mlp_free", "insp_mlp_grads", "insp_mlp_train_step", "insp_mlp_train", "insp_mlp_predict",
            "insp_mlp_state", "insp_last_error", "insp_test_fail_alloc")
 MLP_PARAMS = 74754
@@ -82,6 +83,10 @@ def load(path: str = LIB_PATH):
     lib.insp_schedule.argtypes = [P, i32, P, P, P, C.POINTER(Params), P, P, P, P, P, P, P, P, P]
     lib.insp_schedule_batch.argtypes = [P, P, P, P, C.POINTER(Params), P, P, P, P, P, P, C.c_char_p, P]
     lib.insp_schedule_batch_noalloc.argtypes = lib.insp_schedule_batch.argtypes
+    lib.insp_batch_graph_create.argtypes = lib.insp_schedule_batch.argtypes + [C.POINTER(P)]
+    lib.insp_batch_graph_launch.argtypes = [P, P]
+    lib.insp_batch_graph_free.argtypes = [P]
+    lib.insp_batch_graph_free.restype = None
     lib.insp_sync_status.argtypes = [P, P]
     lib.insp_profile_enable.argtypes = [C.c_int]
     lib.insp_profile_read.argtypes = [C.c_char_p, C.POINTER(C.c_double), C.POINTER(i64)]
@@ -321,6 +326,47 @@ def _batch(fn, dag, workers, dur, est, prm, tune_key, stream, out, with_pop):
               _dev(o.get("ie_at_pop"), "ie_at_pop", "i32", 1, n),
               _dev(o.get("mode_at_pop"), "mode_at_pop", "i8", 1, n), key, _stream(stream)))
     return o
+
+
+class BatchGraph:
+    """One batch step captured in a HIP graph the library owns; `out` holds
+    the device outputs every replay writes."""
+
+    def __init__(self, dag: Dag, workers, dur, est, prm: Params = None, tune_key=None, stream=None, out=None,
+                 with_pop=True):
+        import torch
+        prm = prm or params()
+        dev = dur.device
+        o = out or _outputs(int(dag.task_off[-1]), dev, with_pop)
+        o["makespan"] = o.get("makespan", torch.empty(dag.n_dags, dtype=torch.int64, device=dev))
+        key = tune_key.encode() if isinstance(tune_key, str) else tune_key
+        n, B = int(dag.task_off[-1]), dag.n_dags
+        self._keep = (dag, dur, est, prm, key, C.byref(prm))
+        self.out = o
+        self.handle = None
+        g = C.c_void_p()
+        _check(load().insp_batch_graph_create(
+            dag.handle, _workers(workers, B), _dev(dur, "dur", "i32", 2, n), _dev(est, "est", "i32", 2, n),
+            C.byref(prm), _dev(o["worker"], "worker", "i32", 1, n), _dev(o["start"], "start", "i64", 1, n),
+            _dev(o["finish"], "finish", "i64", 1, n), _dev(o["makespan"], "makespan", "i64", 1, B),
+            _dev(o.get("ie_at_pop"), "ie_at_pop", "i32", 1, n), _dev(o.get("mode_at_pop"), "mode_at_pop", "i8", 1, n),
+            key, _stream(stream), C.byref(g)))
+        self.handle = g.value
+
+    def launch(self, stream=None):
+        _check(load().insp_batch_graph_launch(self.handle, _stream(stream)))
+        return self.out
+
+    def free(self):
+        if self.handle:
+            load().insp_batch_graph_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
 
 
 def sync_status(dag: Dag, stream=None):

@@ -1265,3 +1265,53 @@ def test_graph_replays_every_mode(insp, mode):
         del junk
     insp.sync_status(dag)
     dag.free()
+
+
+@pytest.mark.parametrize("mode", ["inspirit", "fifo", "heft", "transitive", "data", "locality"])
+def test_library_graph_replays(insp, mode):
+    # the batch step captured by the library itself (insp_batch_graph_create):
+    # every replay, with eager work and synchronisations between, matches the
+    # oracle; the outputs are cleared before each replay
+    import torch
+    ws = synth.cfg3(select=list(range(29, 4096, 700))) + [_hubs(5)]
+    b = synth.concat(ws)
+    b.data_kib = np.concatenate([_kib(w, k, hi=90) for k, w in enumerate(ws)])
+    kw = {"inspirit": {}, "fifo": dict(policy="fifo"), "heft": dict(policy="heft"),
+          "transitive": dict(attr_mode="transitive"), "data": dict(data_bw=600),
+          "locality": dict(policy="locality", data_bw=600)}[mode]
+    say("library graph", mode, len(ws))
+    dag, dur, est = insp.batch_to_device(b)
+    insp.set_task_data(dag, torch_tensor(b.data_kib))
+    workers = [(w.n_cpu, w.n_gpu) for w in ws]
+    r = oracle.schedule_batch(b, **kw)
+    g = insp.BatchGraph(dag, workers, dur, est, insp.params(**kw))
+    out = g.out
+    for rep in range(3):
+        for k in out:
+            out[k].zero_()
+        junk = insp.schedule_batch(dag, workers, dur, est, insp.params(policy="ability"))  # eager work
+        torch.cuda.synchronize()
+        g.launch()
+        torch.cuda.synchronize()
+        for k in ("worker", "start", "finish", "ie_at_pop", "mode_at_pop"):
+            assert np.array_equal(out[k].cpu().numpy(), r[k]), (mode, rep, k)
+        assert np.array_equal(out["makespan"].cpu().numpy(), r["makespan"]), (mode, rep)
+        del junk
+    insp.sync_status(dag)
+    g.free()
+    dag.free()
+
+
+def test_library_graph_argument_errors(insp):
+    import torch
+    say("library graph errors")
+    ws = synth.cfg3(select=[3])
+    b = synth.concat(ws)
+    dag, dur, est = insp.batch_to_device(b)
+    with pytest.raises(insp.InspError) as e:
+        insp.BatchGraph(dag, [(0, 0)], dur, est)
+    assert e.value.code == insp.E_RANGE
+    lib = insp.load()
+    assert lib.insp_batch_graph_launch(None, None) == insp.E_INVAL
+    lib.insp_batch_graph_free(None)
+    dag.free()
