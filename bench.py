@@ -183,6 +183,8 @@ def main():
                     help="also time the transitive attribute pass and the schedule ordered by it (sampled check)")
     ap.add_argument("--data", action="store_true",
                     help="data model: every task leaves one 960x960 fp32 tile, moved at 60 KiB per tick")
+    ap.add_argument("--attr-only", action="store_true",
+                    help="only time the standalone attribute pass (warm and cold) on the workload")
     ap.add_argument("--print-sources-sha256", action="store_true")
     args = ap.parse_args()
     if args.print_sources_sha256:
@@ -212,6 +214,12 @@ def main():
     if args.data:
         b.data_kib = np.full(N, TILE_KIB, np.int32)
         inspirit.set_task_data(dag, torch.from_numpy(b.data_kib).to(dur.device))
+    if args.attr_only:
+        a = attr_measure(dag, workers, b, est, steps=max(args.steps, 1), warmup=max(args.warmup, 1))
+        print(json.dumps({"metric": "attribute pass, ms per call", "workload": desc, "tasks": N, "edges": M,
+                          "attributes": a}), flush=True)
+        dag.free()
+        return
     prm = inspirit.params(policy=args.policy, data_bw=data_bw)
     out = inspirit._outputs(N, dur.device)
     out["makespan"] = torch.empty(len(ws), dtype=torch.int64, device=dur.device)
