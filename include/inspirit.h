@@ -277,6 +277,24 @@ int insp_schedule_batch(const insp_dag *dag, const insp_workers *workers, const 
                         void *stream);
 
 /*
+ * insp_schedule_batch_trace -- insp_schedule_batch that also records every
+ * DAG's per-event trace (the Nready analysis of the paper's Section 5, per
+ * DAG of the batch).  trace is device insp_trace_rec [N + B] (N = tasks of
+ * the handle): DAG b's records start at index task_off[b] + b and number
+ * min(n_events[b], max_events or n_b + 1) -- a run takes at most n_b + 1
+ * events, so n_b + 1 slots always suffice.  n_events is device [B]: the
+ * events of each DAG's run (max_events + 1 when the run stopped at the
+ * max_events limit, which insp_sync_status reports as INSP_E_HANG; 0 for an
+ * empty DAG).  Both arrays are caller-owned and required (NULL is
+ * INSP_E_INVAL); every other argument, result and error is as for
+ * insp_schedule_batch.
+ */
+int insp_schedule_batch_trace(const insp_dag *dag, const insp_workers *workers, const int32_t *dur,
+                              const int32_t *est, const insp_params *params, int32_t *worker, int64_t *start,
+                              int64_t *finish, int64_t *makespan, int32_t *ie_at_pop, int8_t *mode_at_pop,
+                              insp_trace_rec *trace, int32_t *n_events, const char *tune_key, void *stream);
+
+/*
  * insp_schedule_batch_noalloc -- insp_schedule_batch for callers that cannot
  * allocate device memory: code under HIP graph capture, tight serving loops,
  * harnesses that forbid allocation.  Same arguments, results and status

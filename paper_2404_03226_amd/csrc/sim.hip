@@ -109,7 +109,7 @@ struct SimArgs {
     int32_t *stat;
     int32_t *counter;
     int64_t *makespan;
-    insp_trace_rec *trace;
+    insp_trace_rec *trace;     // DAG di's events from record (toff - base) + di on: n + 1 slots per DAG
     int32_t *n_events;
     int32_t s_inc, s_dec, dec_step, c, k_num, k_den, max_events;
     int32_t prio_top;          // DAGs dispensed before this one run at raised wave priority
@@ -688,7 +688,7 @@ __device__ void sim_dag(const SimArgs &A, int32_t di, const Lds &L) {
             rec.peak = peak;
             rec.pushed = r;
             rec.popped = popped;
-            A.trace[events - 1] = rec;
+            A.trace[(d.toff - A.base) + di + events - 1] = rec;
         }
         if (done == n) break;
         // --------------------------------------------------------- advance
@@ -1647,7 +1647,7 @@ __device__ bool sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
             rec.peak = peak;
             rec.pushed = r;
             rec.popped = popped;
-            A.trace[events - 1] = rec;
+            A.trace[(d.toff - A.base) + di + events - 1] = rec;
         }
         if (done == n) break;
         // --------------------------------------------------------- advance
@@ -2340,10 +2340,10 @@ int batch_prologue(insp_dag *dag, const insp_workers *workers, const int32_t *du
 
 }  // namespace insp
 
-extern "C" int insp_schedule_batch(const insp_dag *cdag, const insp_workers *workers, const int32_t *dur,
-                                   const int32_t *est, const insp_params *params, int32_t *worker, int64_t *start,
-                                   int64_t *finish, int64_t *makespan, int32_t *ie_at_pop, int8_t *mode_at_pop,
-                                   const char *tune_key, void *stream) {
+static int schedule_batch(const insp_dag *cdag, const insp_workers *workers, const int32_t *dur, const int32_t *est,
+                          const insp_params *params, int32_t *worker, int64_t *start, int64_t *finish,
+                          int64_t *makespan, int32_t *ie_at_pop, int8_t *mode_at_pop, insp_trace_rec *trace,
+                          int32_t *n_events, const char *tune_key, void *stream) {
     insp_dag *dag = const_cast<insp_dag *>(cdag);
     BatchLaunch bl;
     int rc;
@@ -2360,8 +2360,26 @@ extern "C" int insp_schedule_batch(const insp_dag *cdag, const insp_workers *wor
     if (params->data_bw > 0 && (rc = ensure_preds(dag, st))) return rc;
     if (params->data_bw > 0 && !dag->dxc.p && (rc = dag->dxc.alloc(sizeof(int32_t) * std::max<int64_t>(dag->N, 1))))
         return rc;
-    return launch_sim(dag, ws, *params, dur, est, worker, start, finish, makespan, ie_at_pop, mode_at_pop, nullptr,
-                      nullptr, 1, bl.grid, bl.sum_cap, bl.slot_cap, st, bl.prio, bl.scan);
+    return launch_sim(dag, ws, *params, dur, est, worker, start, finish, makespan, ie_at_pop, mode_at_pop, trace,
+                      n_events, 1, bl.grid, bl.sum_cap, bl.slot_cap, st, bl.prio, bl.scan);
+}
+
+extern "C" int insp_schedule_batch(const insp_dag *cdag, const insp_workers *workers, const int32_t *dur,
+                                   const int32_t *est, const insp_params *params, int32_t *worker, int64_t *start,
+                                   int64_t *finish, int64_t *makespan, int32_t *ie_at_pop, int8_t *mode_at_pop,
+                                   const char *tune_key, void *stream) {
+    return schedule_batch(cdag, workers, dur, est, params, worker, start, finish, makespan, ie_at_pop, mode_at_pop,
+                          nullptr, nullptr, tune_key, stream);
+}
+
+extern "C" int insp_schedule_batch_trace(const insp_dag *cdag, const insp_workers *workers, const int32_t *dur,
+                                         const int32_t *est, const insp_params *params, int32_t *worker,
+                                         int64_t *start, int64_t *finish, int64_t *makespan, int32_t *ie_at_pop,
+                                         int8_t *mode_at_pop, insp_trace_rec *trace, int32_t *n_events,
+                                         const char *tune_key, void *stream) {
+    if (!trace || !n_events) return set_error(INSP_E_INVAL, "insp_schedule_batch_trace: null trace or n_events");
+    return schedule_batch(cdag, workers, dur, est, params, worker, start, finish, makespan, ie_at_pop, mode_at_pop,
+                          trace, n_events, tune_key, stream);
 }
 
 // A batch step captured in a HIP graph owned by the library.

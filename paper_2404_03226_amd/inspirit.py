@@ -28,7 +28,7 @@ ALL_DAGS = -1
 EXPORTS = ("insp_build_dag", "insp_set_task_data", "insp_free_dag", "insp_dag_info", "insp_attributes",
            "insp_transitive_attributes",
            "insp_schedule",
-           "insp_schedule_batch", "insp_schedule_batch_noalloc", "insp_batch_graph_create",
+           "insp_schedule_batch", "insp_schedule_batch_trace", "insp_schedule_batch_noalloc", "insp_batch_graph_create",
            "insp_batch_graph_launch", "insp_batch_graph_free", "insp_sync_status", "insp_profile_enable", "insp_profile_read",
            "insp_mlp_create", "insp_mlp_free", "insp_mlp_grads", "insp_mlp_train_step", "insp_mlp_train", "insp_mlp_predict",
            "insp_mlp_state", "insp_last_error", "insp_test_fail_alloc")
@@ -83,6 +83,7 @@ def load(path: str = LIB_PATH):
     lib.insp_schedule.argtypes = [P, i32, P, P, P, C.POINTER(Params), P, P, P, P, P, P, P, P, P]
     lib.insp_schedule_batch.argtypes = [P, P, P, P, C.POINTER(Params), P, P, P, P, P, P, C.c_char_p, P]
     lib.insp_schedule_batch_noalloc.argtypes = lib.insp_schedule_batch.argtypes
+    lib.insp_schedule_batch_trace.argtypes = [P, P, P, P, C.POINTER(Params), P, P, P, P, P, P, P, P, C.c_char_p, P]
     lib.insp_batch_graph_create.argtypes = lib.insp_schedule_batch.argtypes + [C.POINTER(P)]
     lib.insp_batch_graph_launch.argtypes = [P, P]
     lib.insp_batch_graph_free.argtypes = [P]
@@ -295,9 +296,31 @@ def trace_records(trace_tensor, n_events):
 
 
 def schedule_batch(dag: Dag, workers, dur, est, prm: Params = None, tune_key=None, stream=None, out=None,
-                   with_pop=True):
-    """Simulate all DAGs in one persistent launch; returns device tensors."""
-    return _batch(load().insp_schedule_batch, dag, workers, dur, est, prm, tune_key, stream, out, with_pop)
+                   with_pop=True, trace=False):
+    """Simulate all DAGs in one persistent launch; returns device tensors.
+    trace=True also returns "trace" (raw records, DAG b's from index
+    task_off[b] + b on) and "n_events" [B]; see batch_trace_records."""
+    if not trace:
+        return _batch(load().insp_schedule_batch, dag, workers, dur, est, prm, tune_key, stream, out, with_pop)
+    import torch
+    dev = dur.device
+    o = out or _outputs(int(dag.task_off[-1]), dev, with_pop)
+    n, B = int(dag.task_off[-1]), dag.n_dags
+    o["trace"] = o.get("trace", torch.zeros((n + B) * TRACE_DTYPE.itemsize, dtype=torch.uint8, device=dev))
+    o["n_events"] = o.get("n_events", torch.zeros(max(B, 1), dtype=torch.int32, device=dev))
+    if o["trace"].dtype != torch.uint8 or o["trace"].numel() < (n + B) * TRACE_DTYPE.itemsize:
+        raise ValueError(f"trace needs {(n + B) * TRACE_DTYPE.itemsize} bytes (uint8)")
+    return _batch(load().insp_schedule_batch_trace, dag, workers, dur, est, prm, tune_key, stream, o, with_pop,
+                  extra=(_ptr(o["trace"]), _dev(o["n_events"], "n_events", "i32", 1, B)))
+
+
+def batch_trace_records(dag: Dag, out, b):
+    """DAG b's trace records (numpy, TRACE_DTYPE) from a traced schedule_batch."""
+    nev = int(out["n_events"][b].item())
+    lo = int(dag.task_off[b]) + b
+    cap = int(dag.task_off[b + 1] - dag.task_off[b]) + 1
+    raw = out["trace"].cpu().numpy().view(TRACE_DTYPE)
+    return raw[lo: lo + min(nev, cap)]
 
 
 NOALLOC_SCRATCH_BYTES = 64 << 20
@@ -310,7 +333,7 @@ def schedule_batch_noalloc(dag: Dag, workers, dur, est, prm: Params = None, tune
     return _batch(load().insp_schedule_batch_noalloc, dag, workers, dur, est, prm, tune_key, stream, out, with_pop)
 
 
-def _batch(fn, dag, workers, dur, est, prm, tune_key, stream, out, with_pop):
+def _batch(fn, dag, workers, dur, est, prm, tune_key, stream, out, with_pop, extra=()):
     import torch
     prm = prm or params()
     dev = dur.device
@@ -324,7 +347,7 @@ def _batch(fn, dag, workers, dur, est, prm, tune_key, stream, out, with_pop):
               _dev(o["finish"], "finish", "i64", 1, n),
               _dev(o["makespan"], "makespan", "i64", 1, B),
               _dev(o.get("ie_at_pop"), "ie_at_pop", "i32", 1, n),
-              _dev(o.get("mode_at_pop"), "mode_at_pop", "i8", 1, n), key, _stream(stream)))
+              _dev(o.get("mode_at_pop"), "mode_at_pop", "i8", 1, n), *extra, key, _stream(stream)))
     return o
 
 

@@ -1136,6 +1136,55 @@ def test_batch_with_empty_and_single_task_dags(insp):
     dag.free()
 
 
+def test_batch_trace_matches_oracle(insp):
+    """Per-DAG event traces of one batch call: every record of every DAG
+    against the oracle's trace of that DAG alone, under the one-wave loop's
+    policies, HEFT, transitive attributes and the data model."""
+    import torch
+    ws = [_empty(), _single(5)] + synth.cfg3(select=[9, 90, 700, 2048]) + [_hubs(8), synth.lu_workload(nb=5),
+                                                                             _empty(1, 0)]
+    for k, w in enumerate(ws):
+        w.data_kib = np.full(w.n, 7 + k, np.int32) if w.n else np.zeros(0, np.int32)
+    b = synth.concat(ws)
+    b.data_kib = np.concatenate([w.data_kib for w in ws])
+    workers = [(w.n_cpu, w.n_gpu) for w in ws]
+    dag, dur, est = insp.batch_to_device(b)
+    insp.set_task_data(dag, torch.from_numpy(b.data_kib).cuda())
+    cases = (("inspirit", {}, None), ("fifo", {}, None), ("efi", {}, "waves=1,grid=3,lds_blocks=0,lds_slots=0"),
+             ("heft", {}, None), ("inspirit", {"attr_mode": "transitive"}, None),
+             ("inspirit", {"data_bw": 300}, None), ("locality", {"data_bw": 300}, "waves=1,grid=2"))
+    for pol, kw, key in cases:
+        say("batch trace", pol, kw, key)
+        o = insp.schedule_batch(dag, workers, dur, est, insp.params(policy=pol, **kw), tune_key=key, trace=True)
+        insp.sync_status(dag)
+        r = oracle.schedule_batch(b, policy=pol, **kw)
+        for k in ("worker", "start", "finish", "ie_at_pop", "mode_at_pop"):
+            assert np.array_equal(o[k].cpu().numpy(), r[k]), (pol, kw, k)
+        nev = o["n_events"].cpu().numpy()
+        for k, w in enumerate(ws):
+            if w.n == 0:
+                assert nev[k] == 0, (pol, kw, k)
+                continue
+            ref = oracle.schedule(w, policy=pol, variant=oracle.HEAP, trace=True, **kw)
+            assert nev[k] == ref["n_events"] and nev[k] <= w.n + 1, (pol, kw, k)
+            g = insp.batch_trace_records(dag, o, k)
+            for f in ("t", "nready", "mode", "cnt", "peak", "pushed", "popped"):
+                assert np.array_equal(g[f], ref["trace"][f]), (pol, kw, k, f)
+    # the trace arrays are required
+    lib = insp.load()
+    P = insp.C.c_void_p
+    n, B = int(b.task_off[-1]), len(ws)
+    o = insp._outputs(n, dur.device)
+    ms = torch.empty(B, dtype=torch.int64, device=dur.device)
+    prm = insp.params()
+    rc = lib.insp_schedule_batch_trace(dag.handle, insp._workers(workers, B), P(dur.data_ptr()), P(est.data_ptr()),
+                                       insp.C.byref(prm), P(o["worker"].data_ptr()), P(o["start"].data_ptr()),
+                                       P(o["finish"].data_ptr()), P(ms.data_ptr()), None, None, None, None, None,
+                                       None)
+    assert rc == insp.E_INVAL
+    dag.free()
+
+
 def test_single_empty_dag(insp):
     import torch
     say("single empty dag")
