@@ -444,11 +444,14 @@ def transitive_measure(dag, workers, ws, b, dur, est, steps, warmup, tune_key):
     stream = torch.cuda.current_stream()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
+    inspirit.profile_enable(True)
     ev0.record(stream)
     for _ in range(steps):
         inspirit.schedule_batch(dag, workers, dur, est, prm, tune_key=tune_key, out=out)
     ev1.record(stream)
     torch.cuda.synchronize()
+    sim_tot, sim_cnt = inspirit.profile_read("sim")
+    inspirit.profile_enable(False)
     inspirit.sync_status(dag)
     sched_ms = ev0.elapsed_time(ev1) / steps
     # sampled check: every 64th DAG and the largest, attributes and schedules
@@ -482,6 +485,7 @@ def transitive_measure(dag, workers, ws, b, dur, est, steps, warmup, tune_key):
                           "frac": round(lds_ops / (k_ms * 1e-3) / lds_peak, 4),
                           "note": "LDS operations estimated from the mean out-degree"},
          "schedule_ms_per_step": round(sched_ms, 3), "schedule_tasks_per_s": round(N / (sched_ms * 1e-3), 1),
+         "schedule_sim_ms": round(sim_tot / max(sim_cnt, 1), 3),
          "sample_bit_exact": exact, "sample": f"{len(sample)} DAGs ({n_cpu_tasks} tasks): every 64th and the largest",
          "cpu_baseline": {"value": round(n_cpu_tasks / t_cpu, 1), "unit": "tasks/s", "cores": 1, "kind": "oracle",
                           "sample": "the sampled DAGs' transitive attributes, C oracle, one thread"}}

@@ -35,6 +35,7 @@
 #include <algorithm>
 #include <cstring>
 #include <string>
+#include <type_traits>
 
 #include "common.hpp"
 #include "internal.hpp"
@@ -1041,25 +1042,46 @@ struct KeyFmt {
     __device__ __forceinline__ uint32_t de() const { return 1u << sb; }
 };
 
-// The two key arrays of the LDS-resident slots and the 32-bit block maxima
-// (in the storage the general loop uses for its 64-bit keys and maxima).
-struct Keys32 {
-    uint32_t *ka, *ke;  // [64 * slot_cap]
-    uint32_t *mx;       // [2 * sum_cap]: max kA, max kE of each block
+// Queue keys of the one-wave loop.  Direct attributes: two 32-bit rule keys
+// per entry, kA (ability, or FIFO) and kE (efficiency), each raised in place
+// when the task's IE grows.  Fixed keys (HEFT ranks, transitive attributes):
+// one 64-bit key per entry in the general loop's format, from which key_of
+// derives the rule keys when an entry is read (zero stays zero: an empty slot).
+template <bool FIX>
+struct Keys {
+    using T = typename std::conditional<FIX, unsigned long long, uint32_t>::type;
+    T *ka, *ke;  // LDS slots [64 * slot_cap]: kA and kE, or (fixed) ka the key itself
+    T *mx;       // [2 * sum_cap]: the two rule maxima of each block summarised in LDS
+    int o0;      // fixed keys: the rule of maximum 0 (0 ability, 2 FIFO, 3 rank)
+    __device__ __forceinline__ T rule(uint64_t raw, int r) const {
+        if constexpr (FIX) return raw ? key_of(raw, r ? 1 : o0) : 0ull;
+        else return (uint32_t)(raw >> (r ? 32 : 0));
+    }
+    // rule-r key of the entry in LDS slot p
+    __device__ __forceinline__ T lds(int32_t p, int r) const {
+        if constexpr (FIX) return rule(ka[p], r);
+        else return (r ? ke : ka)[p];
+    }
 };
+
+__device__ __forceinline__ uint32_t wave_max_k(uint32_t x) { return wave_max_u32f(x); }
+__device__ __forceinline__ unsigned long long wave_max_k(unsigned long long x) { return wave_max_u64f(x); }
 
 // Rule-`r` keys of block b, one per lane (zero in empty slots).  b is
 // wave-uniform: the choice between LDS and global memory is a scalar branch,
 // and the global side waits for its load itself, so the LDS side carries no
 // wait for outstanding global accesses.
-__device__ __forceinline__ uint32_t block_keys32(const SlotPool &slots, const Keys32 &K, int32_t slc, int32_t b, int r) {
+template <bool FIX>
+__device__ __forceinline__ typename Keys<FIX>::T block_keys(const SlotPool &slots, const Keys<FIX> &K, int32_t slc,
+                                                            int32_t b, int r) {
     const int lane = lane_id();
-    uint32_t k;
+    typename Keys<FIX>::T k;
     if (b < slc) {
-        k = (r ? K.ke : K.ka)[b * 64 + lane];
+        k = K.lds(b * 64 + lane, r);
     } else {
-        k = (uint32_t)(wg_load(&slots.k[b * 64 + lane]) >> (r ? 32 : 0));
-        settle(k);
+        const uint64_t raw = wg_load(&slots.k[b * 64 + lane]);
+        settle(raw);
+        k = K.rule(raw, r);
     }
     return k;
 }
@@ -1067,14 +1089,13 @@ __device__ __forceinline__ uint32_t block_keys32(const SlotPool &slots, const Ke
 // Best rule-R key in column `lane` of the listed blocks (bits of `m` select
 // lanes of `bl`, which hold block ids), four loads in flight at a time;
 // FROM_LDS picks where the blocks' slots live.
-template <bool FROM_LDS, int R>
-__device__ __forceinline__ void scan_columns(const SlotPool &slots, const Keys32 &K, uint64_t m, int32_t bl,
-                                             uint32_t &best, int32_t &bp) {
+template <bool FIX, bool FROM_LDS, int R>
+__device__ __forceinline__ void scan_columns(const SlotPool &slots, const Keys<FIX> &K, uint64_t m, int32_t bl,
+                                             typename Keys<FIX>::T &best, int32_t &bp) {
     const int lane = lane_id();
-    const uint32_t *keys = R ? K.ke : K.ka;
     const int32_t b_last = read_lane(bl, 63 - (int)__builtin_clzll(m | 1));  // any listed block
     while (m) {
-        uint32_t kk[4];
+        typename Keys<FIX>::T kk[4];
         int32_t pp[4];
 #pragma unroll
         for (int u = 0; u < 4; u++) {
@@ -1084,7 +1105,7 @@ __device__ __forceinline__ void scan_columns(const SlotPool &slots, const Keys32
                 m &= m - 1;
             }
             pp[u] = b * 64 + lane;
-            kk[u] = FROM_LDS ? keys[pp[u]] : (uint32_t)(wg_load(&slots.k[pp[u]]) >> (R ? 32 : 0));
+            kk[u] = FROM_LDS ? K.lds(pp[u], R) : K.rule(wg_load(&slots.k[pp[u]]), R);
         }
 #pragma unroll
         for (int u = 0; u < 4; u++) {
@@ -1097,11 +1118,12 @@ __device__ __forceinline__ void scan_columns(const SlotPool &slots, const Keys32
 }
 
 // Rebuild both maxima of block b from its first `cnt` entries (wave-wide).
-__device__ __forceinline__ void rebuild_max32(const SlotPool &slots, const Keys32 &K, const Lds &L,
-                                              unsigned long long *sums, int32_t slc, int32_t sc, int32_t b) {
+template <bool FIX>
+__device__ __forceinline__ void rebuild_max(const SlotPool &slots, const Keys<FIX> &K, const Lds &L,
+                                            unsigned long long *sums, int32_t slc, int32_t sc, int32_t b) {
     const int lane = lane_id();
-    const uint32_t s0 = wave_max_u32f(block_keys32(slots, K, slc, b, 0));
-    const uint32_t s1 = wave_max_u32f(block_keys32(slots, K, slc, b, 1));
+    const auto s0 = wave_max_k(block_keys<FIX>(slots, K, slc, b, 0));
+    const auto s1 = wave_max_k(block_keys<FIX>(slots, K, slc, b, 1));
     if (lane == 0) {
         if (b < sc) {
             K.mx[2 * b] = s0;
@@ -1114,9 +1136,13 @@ __device__ __forceinline__ void rebuild_max32(const SlotPool &slots, const Keys3
     }
 }
 
-// Returns false, having changed nothing the general loop relies on, when the
-// DAG's keys do not fit in 32 bits.
+// FIX = false: direct attributes on 32-bit keys; returns false, having changed
+// nothing the general loop relies on, when the DAG's keys do not fit.
+// FIX = true: fixed 64-bit keys (HEFT ranks or transitive attributes); the
+// tasks' direct IE is still kept up to date for the records.
+template <bool FIX>
 __device__ bool sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
+    using KT = typename Keys<FIX>::T;
     const int lane = lane_id();
     const DagDesc d = A.desc[di];
     const int32_t n = d.n, ncpu = d.n_cpu, W = d.n_cpu + d.n_gpu;
@@ -1166,17 +1192,22 @@ __device__ bool sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
     mdeg = wave_max_u32f(mdeg);
     const uint32_t abits = mdeg == 0 ? 1 : 32 - __clz(mdeg);
     const uint32_t sbits = n <= 1 ? 1 : 32 - __clz(n - 1);
-    if (1 + 2 * abits + sbits > 32) return false;
+    if (!FIX && 1 + 2 * abits + sbits > 32) return false;
     KeyFmt kf;
     kf.sa = sbits;
     kf.sb = abits + sbits;
     kf.smask = (1u << sbits) - 1;
     kf.amask = (1u << abits) - 1;
     kf.fifo = A.policy == INSP_POLICY_FIFO;
-    Keys32 K;
-    K.ka = reinterpret_cast<uint32_t *>(L.sk);
-    K.ke = K.ka + 64 * SLC;
-    K.mx = reinterpret_cast<uint32_t *>(L.sum);
+    const bool heft = FIX && A.policy == INSP_POLICY_HEFT;
+    const bool tattr = FIX && A.attr_mode == INSP_ATTR_TRANSITIVE;
+    const int64_t *rk = A.rank + d.toff;
+    const int32_t *tia = A.tia + d.toff, *tie = A.tie + d.toff;
+    Keys<FIX> K;
+    K.ka = reinterpret_cast<KT *>(L.sk);
+    K.ke = FIX ? nullptr : K.ka + 64 * SLC;  // the two 32-bit arrays fill the 64-bit slot storage
+    K.mx = reinterpret_cast<KT *>(L.sum);
+    K.o0 = A.policy == INSP_POLICY_FIFO ? 2 : heft ? 3 : 0;
     const int32_t U = A.dag_u[d.id];
 
     const int32_t s_inc = A.s_inc > 0 ? A.s_inc : max(1, (W + 3) / 4);
@@ -1206,7 +1237,7 @@ __device__ bool sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
     for (int32_t b = 0; b < d.nblk; b++) {
         if (b < SLC) {
             K.ka[b * 64 + lane] = 0;
-            K.ke[b * 64 + lane] = 0;
+            if constexpr (!FIX) K.ke[b * 64 + lane] = 0;
         } else {
             slots.k[b * 64 + lane] = 0;
         }
@@ -1261,6 +1292,15 @@ __device__ bool sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
                     ie_l = fx.x;
                     ia_l = fx.y;
                     rs_l = fx.w;
+                    // fixed keys: the rank (low and high words), or the transitive attributes
+                    if (heft) {
+                        const int64_t rv = rk[v_l];
+                        ia_l = (int32_t)(uint32_t)rv;
+                        ie_l = (int32_t)(uint32_t)((uint64_t)rv >> 32);
+                    } else if (tattr) {
+                        ia_l = tia[v_l];
+                        ie_l = tie[v_l];
+                    }
                 }
             }
             if (ballot(ok && (d_l.x < 1 || d_l.x > INSP_MAX_TICK || d_l.y < 1 || d_l.y > INSP_MAX_TICK)))
@@ -1328,20 +1368,34 @@ __device__ bool sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
             // and the compiler keeps the stores of some lanes ahead of the
             // atomics of the others.
             const int32_t bq = pq >> 6;
-            uint32_t a0 = 0, a1 = 0;
+            KT a0 = 0, a1 = 0;
             if (ok) {
                 const bool g = wsj >= ncpu;
                 const int32_t ekl = g ? e_l.y : e_l.x, dkl = g ? d_l.y : d_l.x;
-                a0 = kf.ka((uint32_t)ia_l, (uint32_t)ie_l, (uint32_t)sqj);
-                a1 = kf.ke((uint32_t)ia_l, (uint32_t)ie_l, (uint32_t)sqj);
+                uint64_t raw;
+                if constexpr (FIX) {
+                    // the general loop's key: rank << 21 or IA << 42 | IE << 21, then the push order
+                    raw = heft ? ((uint64_t)(uint32_t)ie_l << 32 | (uint32_t)ia_l) << 21 | (M21 - (uint64_t)sqj)
+                               : (uint64_t)ia_l << 42 | (uint64_t)ie_l << 21 | (M21 - (uint64_t)sqj);
+                    a0 = K.rule(raw, 0);
+                    a1 = K.rule(raw, 1);
+                } else {
+                    a0 = kf.ka((uint32_t)ia_l, (uint32_t)ie_l, (uint32_t)sqj);
+                    a1 = kf.ke((uint32_t)ia_l, (uint32_t)ie_l, (uint32_t)sqj);
+                    raw = (uint64_t)a1 << 32 | a0;
+                }
                 const uint64_t xw = (uint64_t)v_l << 42 | (uint64_t)(dkl & M21) << 21 | (uint64_t)(ekl & M21);
                 if (bq < SLC) {
-                    K.ka[pq] = a0;
-                    K.ke[pq] = a1;
+                    if constexpr (FIX) {
+                        K.ka[pq] = raw;
+                    } else {
+                        K.ka[pq] = a0;
+                        K.ke[pq] = a1;
+                    }
                     L.sx[pq] = xw;
                     L.srs[pq] = rs_l;
                 } else {
-                    slots.k[pq] = (uint64_t)a1 << 32 | a0;
+                    slots.k[pq] = raw;
                     slots.x[pq] = xw;
                     slots.rs[pq] = rs_l;
                 }
@@ -1397,8 +1451,9 @@ __device__ bool sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
         }
         const int pmode = A.policy == INSP_POLICY_FIFO ? INSP_MODE_FIFO
                         : A.policy == INSP_POLICY_ABILITY_ONLY ? INSP_MODE_ABILITY
-                        : A.policy == INSP_POLICY_EFI_ONLY ? INSP_MODE_EFI : mode;
-        const int ord = pmode == INSP_MODE_FIFO ? 2 : pmode == INSP_MODE_ABILITY ? 0 : 1;
+                        : A.policy == INSP_POLICY_EFI_ONLY ? INSP_MODE_EFI
+                        : heft ? INSP_MODE_RANK : mode;
+        const int ord = heft ? 3 : pmode == INSP_MODE_FIFO ? 2 : pmode == INSP_MODE_ABILITY ? 0 : 1;
         const int slot = ord == 1 ? 1 : 0;
         // ------------------------------------------------------------- pop
         int32_t popped = 0;
@@ -1424,19 +1479,18 @@ __device__ bool sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
                 else if (lane < nbw) bl = L.blist[w * kLB + lane];
                 const uint64_t all = nbw == 1 ? 1ull : ballot(lane < nbw);
                 const uint64_t inl = nbw == 1 ? (lastw < SLC ? 1ull : 0ull) : ballot(lane < nbw && bl < SLC);
-                uint32_t best = 0;
+                KT best = 0;
                 int32_t bp = -1;
                 if (inl == all) {
                     // every block in LDS: blocks i .. i+3 of the list, the
                     // padding past the list re-reading its last block
-                    const uint32_t *keys = slot ? K.ke : K.ka;
                     for (int32_t i = 0; i < nbw; i += 4) {
-                        uint32_t kk[4];
+                        KT kk[4];
                         int32_t pp[4];
 #pragma unroll
                         for (int u = 0; u < 4; u++) {
                             pp[u] = read_lane(bl, min(i + u, nbw - 1)) * 64 + lane;
-                            kk[u] = keys[pp[u]];
+                            kk[u] = K.lds(pp[u], slot);
                         }
 #pragma unroll
                         for (int u = 0; u < 4; u++) {
@@ -1447,17 +1501,17 @@ __device__ bool sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
                         }
                     }
                 } else if (slot) {
-                    if (inl) scan_columns<true, 1>(slots, K, inl, bl, best, bp);
-                    scan_columns<false, 1>(slots, K, all & ~inl, bl, best, bp);
+                    if (inl) scan_columns<FIX, true, 1>(slots, K, inl, bl, best, bp);
+                    scan_columns<FIX, false, 1>(slots, K, all & ~inl, bl, best, bp);
                 } else {
-                    if (inl) scan_columns<true, 0>(slots, K, inl, bl, best, bp);
-                    scan_columns<false, 0>(slots, K, all & ~inl, bl, best, bp);
+                    if (inl) scan_columns<FIX, true, 0>(slots, K, inl, bl, best, bp);
+                    scan_columns<FIX, false, 0>(slots, K, all & ~inl, bl, best, bp);
                 }
-                const uint32_t km = wave_max_u32f(best);
+                const KT km = wave_max_k(best);
                 p = read_lane(bp, (int)__builtin_ctzll(ballot(best == km && bp >= 0)));
             } else {
                 // many blocks: rebuild stale maxima, pick the block, scan it
-                uint32_t bk = 0;
+                KT bk = 0;
                 int32_t bid = -1;
                 for (int32_t i0 = 0; i0 < nbw; i0 += kWave) {
                     const int32_t i = i0 + lane;
@@ -1477,14 +1531,14 @@ __device__ bool sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
                         const int l = (int)__builtin_ctzll(sm);
                         sm &= sm - 1;
                         const int32_t sb = read_lane(b, l);
-                        rebuild_max32(slots, K, L, sums, SLC, SC, sb);
+                        rebuild_max<FIX>(slots, K, L, sums, SLC, SC, sb);
                     }
                     if (b >= 0) {
-                        uint32_t k;
+                        KT k;
                         if (b < SC) {
                             k = K.mx[2 * b + slot];
                         } else {
-                            k = (uint32_t)wg_load(&sums[2 * b + slot]);
+                            k = (KT)wg_load(&sums[2 * b + slot]);
                             settle(k);
                         }
                         if (k > bk) {
@@ -1493,61 +1547,71 @@ __device__ bool sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
                         }
                     }
                 }
-                const uint32_t kmb = wave_max_u32f(bk);
+                const KT kmb = wave_max_k(bk);
                 const int32_t bb = read_lane(bid, (int)__builtin_ctzll(ballot(bk == kmb && bid >= 0)));
                 const int32_t cntb = bb == lastw ? lastpos + 1 : 64;
-                const uint32_t key = block_keys32(slots, K, SLC, bb, slot);
-                const uint32_t km = wave_max_u32f(key);
+                const KT key = block_keys<FIX>(slots, K, SLC, bb, slot);
+                const KT km = wave_max_k(key);
                 p = bb * 64 + (int)__builtin_ctzll(ballot(key == km && lane < cntb));
             }
             PCLK(11);
             // take the entry at p; the worker's final entry q fills the hole
             const int32_t bb = p >> 6;
             const int32_t q = lastw * 64 + lastpos;
-            uint32_t ve, ma = 0, me = 0;
-            uint64_t vx, mx = 0;
+            uint32_t ve = 0;
+            uint64_t vx, mx = 0, mkr = 0;  // mkr: the moved entry's key word (the two 32-bit keys, or the fixed key)
             int32_t vr, mr = 0;
             if (bb < SLC) {
-                ve = K.ke[p];
+                if constexpr (!FIX) ve = K.ke[p];
                 vx = L.sx[p];
                 vr = L.srs[p];
             } else {
-                ve = (uint32_t)(wg_load(&slots.k[p]) >> 32);
+                if constexpr (!FIX) {
+                    ve = (uint32_t)(wg_load(&slots.k[p]) >> 32);
+                    settle(ve);
+                }
                 vx = wg_load(&slots.x[p]);
                 vr = wg_load(&slots.rs[p]);
-                settle(ve);
                 settle(vx);
                 settle(vr);
             }
             if (p != q) {
                 if (lastw < SLC) {
-                    ma = K.ka[q];
-                    me = K.ke[q];
+                    if constexpr (FIX) mkr = K.ka[q];
+                    else mkr = (uint64_t)K.ke[q] << 32 | K.ka[q];
                     mx = L.sx[q];
                     mr = L.srs[q];
                 } else {
-                    const uint64_t mk = wg_load(&slots.k[q]);
+                    mkr = wg_load(&slots.k[q]);
                     mx = wg_load(&slots.x[q]);
                     mr = wg_load(&slots.rs[q]);
-                    settle(mk);
+                    settle(mkr);
                     settle(mx);
                     settle(mr);
-                    ma = (uint32_t)mk;
-                    me = (uint32_t)(mk >> 32);
                 }
             }
             const int32_t v = (int32_t)(vx >> 42);
             const int32_t dk = (int32_t)((vx >> 21) & M21), ek = (int32_t)(vx & M21);
-            const int32_t deg = (int32_t)((ve >> kf.sa) & kf.amask);
+            // out-degree and the IE to record, from the direct key (fixed keys:
+            // read from the task's record once the event's pops are done)
+            int32_t deg = 0, iev = 0;
+            if constexpr (!FIX) {
+                deg = (int32_t)((ve >> kf.sa) & kf.amask);
+                iev = (int32_t)((ve >> kf.sb) & kf.amask);
+            }
             if (p != q) {
                 if (lane == 0) {
                     if (bb < SLC) {
-                        K.ka[p] = ma;
-                        K.ke[p] = me;
+                        if constexpr (FIX) {
+                            K.ka[p] = mkr;
+                        } else {
+                            K.ka[p] = (uint32_t)mkr;
+                            K.ke[p] = (uint32_t)(mkr >> 32);
+                        }
                         L.sx[p] = mx;
                         L.srs[p] = mr;
                     } else {
-                        slots.k[p] = (uint64_t)me << 32 | ma;
+                        slots.k[p] = mkr;
                         slots.x[p] = mx;
                         slots.rs[p] = mr;
                     }
@@ -1561,7 +1625,7 @@ __device__ bool sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
             if (lane == 0) {
                 if (lastw < SLC) {
                     K.ka[q] = 0;
-                    K.ke[q] = 0;
+                    if constexpr (!FIX) K.ke[q] = 0;
                 } else {
                     slots.k[q] = 0;
                 }
@@ -1593,14 +1657,14 @@ __device__ bool sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
                 if (bb < SC) {
                     if (lane == 0) L.stale[bb] = 1;
                 } else {
-                    rebuild_max32(slots, K, L, sums, SLC, SC, bb);
+                    rebuild_max<FIX>(slots, K, L, sums, SLC, SC, bb);
                 }
             }
             if (lastw != bb && !freed) {
                 if (lastw < SC) {
                     if (lane == 0) L.stale[lastw] = 1;
                 } else {
-                    rebuild_max32(slots, K, L, sums, SLC, SC, lastw);
+                    rebuild_max<FIX>(slots, K, L, sums, SLC, SC, lastw);
                 }
             }
             PCLK(13);
@@ -1614,7 +1678,7 @@ __device__ bool sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
                 qest -= ek;
                 rsr = vr;
                 dgr = deg;
-                iep = (int32_t)((ve >> kf.sb) & kf.amask);
+                iep = iev;
                 popnow = true;
             }
             nready--;
@@ -1624,6 +1688,14 @@ __device__ bool sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
         // the event's pops write their records with one store (a worker pops
         // at most once per event, so the addresses differ), and prefetch the
         // first successors of the tasks they started
+        if constexpr (FIX) {
+            // every worker that took a task reads its out-degree and IE at once
+            if (popnow) {
+                const int4 fx = *reinterpret_cast<const int4 *>(&tr[run].iev);  // IE, IA, tau, first edge
+                dgr = fx.y;
+                iep = tattr ? tie[run] : fx.x;
+            }
+        }
         if (popnow) put_record(&tr[run], t, (int32_t)(fin - t), lane, iep, pmode);
         if (popnow && dgr > 0) {
             // entries past the row repeat its last successor (never used)
@@ -1775,6 +1847,15 @@ __device__ bool sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
                 fie = fx.x;
                 fa = fx.y;
                 frs = fx.w;
+                // fixed keys: the rank (low and high words), or the transitive attributes
+                if (heft) {
+                    const int64_t rv = rk[fv];
+                    fa = (int32_t)(uint32_t)rv;
+                    fie = (int32_t)(uint32_t)((uint64_t)rv >> 32);
+                } else if (tattr) {
+                    fa = tia[fv];
+                    fie = tie[fv];
+                }
             }
             const bool cond = u >= 0 && (int64_t)tu + ts <= (int64_t)U;
             PCLK(23);
@@ -1796,27 +1877,30 @@ __device__ bool sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
             if (lead) {
                 const int32_t nie = iu + mult;
                 tr[u].iev = nie;
-                if (qu >= 0) {
-                    const uint32_t na = kf.ka((uint32_t)au, (uint32_t)nie, (uint32_t)sq);
-                    const uint32_t ne = kf.ke((uint32_t)au, (uint32_t)nie, (uint32_t)sq);
-                    const int32_t bk = qu >> 6;
-                    if (bk < SLC) {
-                        K.ka[qu] = na;
-                        K.ke[qu] = ne;
-                    } else {
-                        slots.k[qu] = (uint64_t)ne << 32 | na;
-                    }
-                    if (bk < SC) {
-                        atomicMax(&K.mx[2 * bk], na);
-                        atomicMax(&K.mx[2 * bk + 1], ne);
-                    } else {
-                        wg_fetch_max(&sums[2 * bk], (unsigned long long)na);
-                        wg_fetch_max(&sums[2 * bk + 1], (unsigned long long)ne);
+                if constexpr (!FIX) {
+                    if (qu >= 0) {
+                        const uint32_t na = kf.ka((uint32_t)au, (uint32_t)nie, (uint32_t)sq);
+                        const uint32_t ne = kf.ke((uint32_t)au, (uint32_t)nie, (uint32_t)sq);
+                        const int32_t bk = qu >> 6;
+                        if (bk < SLC) {
+                            K.ka[qu] = na;
+                            K.ke[qu] = ne;
+                        } else {
+                            slots.k[qu] = (uint64_t)ne << 32 | na;
+                        }
+                        if (bk < SC) {
+                            atomicMax(&K.mx[2 * bk], na);
+                            atomicMax(&K.mx[2 * bk + 1], ne);
+                        } else {
+                            wg_fetch_max(&sums[2 * bk], (unsigned long long)na);
+                            wg_fetch_max(&sums[2 * bk + 1], (unsigned long long)ne);
+                        }
                     }
                 }
             }
             PCLK(24);
-            uint64_t lm = ballot(lead && qu == -1);
+            // a raised IE of a task staged for this event's pushes goes into its key
+            uint64_t lm = FIX ? 0 : ballot(lead && qu == -1);
             while (lm) {
                 const int l = (int)__builtin_ctzll(lm);
                 lm &= lm - 1;
@@ -1882,24 +1966,26 @@ __device__ bool sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
                         const int32_t pu = wg_load(&tr[u].qpos);
                         if ((int64_t)tu + ts <= (int64_t)U) {
                             wg_fetch_add(&tr[u].iev, 1);
-                            if (pu >= 0) {
-                                const int32_t bk = pu >> 6;
-                                uint32_t na, ne;
-                                if (bk < SLC) {
-                                    na = atomicAdd(&K.ka[pu], kf.da()) + kf.da();
-                                    ne = atomicAdd(&K.ke[pu], kf.de()) + kf.de();
-                                } else {
-                                    const unsigned long long inc = (unsigned long long)kf.de() << 32 | kf.da();
-                                    const uint64_t nk = wg_fetch_add(&slots.k[pu], inc) + inc;
-                                    na = (uint32_t)nk;
-                                    ne = (uint32_t)(nk >> 32);
-                                }
-                                if (bk < SC) {
-                                    atomicMax(&K.mx[2 * bk], na);
-                                    atomicMax(&K.mx[2 * bk + 1], ne);
-                                } else {
-                                    wg_fetch_max(&sums[2 * bk], (unsigned long long)na);
-                                    wg_fetch_max(&sums[2 * bk + 1], (unsigned long long)ne);
+                            if constexpr (!FIX) {
+                                if (pu >= 0) {
+                                    const int32_t bk = pu >> 6;
+                                    uint32_t na, ne;
+                                    if (bk < SLC) {
+                                        na = atomicAdd(&K.ka[pu], kf.da()) + kf.da();
+                                        ne = atomicAdd(&K.ke[pu], kf.de()) + kf.de();
+                                    } else {
+                                        const unsigned long long inc = (unsigned long long)kf.de() << 32 | kf.da();
+                                        const uint64_t nk = wg_fetch_add(&slots.k[pu], inc) + inc;
+                                        na = (uint32_t)nk;
+                                        ne = (uint32_t)(nk >> 32);
+                                    }
+                                    if (bk < SC) {
+                                        atomicMax(&K.mx[2 * bk], na);
+                                        atomicMax(&K.mx[2 * bk + 1], ne);
+                                    } else {
+                                        wg_fetch_max(&sums[2 * bk], (unsigned long long)na);
+                                        wg_fetch_max(&sums[2 * bk + 1], (unsigned long long)ne);
+                                    }
                                 }
                             }
                         }
@@ -2067,7 +2153,14 @@ __device__ void read_ahead(const SimArgs &A, int32_t di, const Lds &L) {
     L.hs[2] = (int32_t)sink;  // keeps the reads
 }
 
-template <int WPL>
+// Event loop a launch runs (one kernel each, so that each gets its own
+// register allocation): the one-wave loop on direct 32-bit keys (DAGs whose
+// keys do not fit fall back to the general loop), the one-wave loop on fixed
+// 64-bit keys (HEFT ranks, transitive attributes), or the general loop (the
+// data model, the locality policy, machines of more than 64 workers).
+enum SimLoop { kLoopDirect = 0, kLoopFixed = 1, kLoopGeneral = 2 };
+
+template <int WPL, int LOOP>
 __global__ __launch_bounds__(WPL == 1 ? 2 * kWave : kWave) void k_sim(SimArgs A) {
     const Lds L = carve_lds(A);
     const int lane = lane_id();
@@ -2090,12 +2183,10 @@ __global__ __launch_bounds__(WPL == 1 ? 2 * kWave : kWave) void k_sim(SimArgs A)
             // their waves win instruction issue over co-resident waves
             if (i < A.prio_top) __builtin_amdgcn_s_setprio(3);
             else __builtin_amdgcn_s_setprio(0);
-            if constexpr (WPL == 1) {
-                // fixed keys (HEFT, transitive attributes), the data model, the
-                // locality policy and keys wider than 32 bits take the 64-bit loop
-                if (A.policy == INSP_POLICY_HEFT || A.policy == INSP_POLICY_LOCALITY ||
-                    A.attr_mode == INSP_ATTR_TRANSITIVE || A.data_bw > 0 || !sim_lane(A, A.order[i], L))
-                    sim_dag<1>(A, A.order[i], L);
+            if constexpr (WPL == 1 && LOOP == kLoopDirect) {
+                if (!sim_lane<false>(A, A.order[i], L)) sim_dag<1>(A, A.order[i], L);
+            } else if constexpr (WPL == 1 && LOOP == kLoopFixed) {
+                sim_lane<true>(A, A.order[i], L);
             } else {
                 sim_dag<WPL>(A, A.order[i], L);
             }
@@ -2203,15 +2294,27 @@ int launch_sim(insp_dag *dag, Workspace *ws, const insp_params &p, const int32_t
     hipLaunchKernelGGL(k_counter_reset, dim3(1), dim3(64), 0, st, A.counter);
     {
         ProfScope ps(st, "sim");
-        if (ws->max_w <= 64) {
-            if (int rc = set_lds_limit((const void *)&k_sim<1>, lds)) return rc;
-            hipLaunchKernelGGL(k_sim<1>, dim3(grid), dim3(2 * kWave), lds, st, A);
+        // the data model and the locality rule need the general loop; fixed
+        // keys and direct keys have one-wave loops of their own
+        const bool general = p.data_bw > 0 || p.policy == INSP_POLICY_LOCALITY;
+        const bool fixed = p.policy == INSP_POLICY_HEFT || p.attr_mode == INSP_ATTR_TRANSITIVE;
+        if (ws->max_w <= 64 && !general) {
+            if (fixed) {
+                if (int rc = set_lds_limit((const void *)&k_sim<1, kLoopFixed>, lds)) return rc;
+                hipLaunchKernelGGL((k_sim<1, kLoopFixed>), dim3(grid), dim3(2 * kWave), lds, st, A);
+            } else {
+                if (int rc = set_lds_limit((const void *)&k_sim<1, kLoopDirect>, lds)) return rc;
+                hipLaunchKernelGGL((k_sim<1, kLoopDirect>), dim3(grid), dim3(2 * kWave), lds, st, A);
+            }
+        } else if (ws->max_w <= 64) {
+            if (int rc = set_lds_limit((const void *)&k_sim<1, kLoopGeneral>, lds)) return rc;
+            hipLaunchKernelGGL((k_sim<1, kLoopGeneral>), dim3(grid), dim3(2 * kWave), lds, st, A);
         } else if (ws->max_w <= 128) {
-            if (int rc = set_lds_limit((const void *)&k_sim<2>, lds)) return rc;
-            hipLaunchKernelGGL(k_sim<2>, dim3(grid), dim3(64), lds, st, A);
+            if (int rc = set_lds_limit((const void *)&k_sim<2, kLoopGeneral>, lds)) return rc;
+            hipLaunchKernelGGL((k_sim<2, kLoopGeneral>), dim3(grid), dim3(64), lds, st, A);
         } else {
-            if (int rc = set_lds_limit((const void *)&k_sim<16>, lds)) return rc;
-            hipLaunchKernelGGL(k_sim<16>, dim3(grid), dim3(64), lds, st, A);
+            if (int rc = set_lds_limit((const void *)&k_sim<16, kLoopGeneral>, lds)) return rc;
+            hipLaunchKernelGGL((k_sim<16, kLoopGeneral>), dim3(grid), dim3(64), lds, st, A);
         }
     }
     INSP_HIP(hipGetLastError());
