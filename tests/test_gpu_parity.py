@@ -307,7 +307,26 @@ def test_batch_small_matches_oracle(insp):
     # tuning must not change results
     for key in ("waves=1,grid=1", "waves=1,grid=3", "waves=1,grid=64"):
         o2 = insp.schedule_batch(dag, [(w.n_cpu, w.n_gpu) for w in ws], dur, est, tune_key=key)
-        assert np.array_equal(o2["start"].cpu().numpy(), r["start"]), key
+        insp.sync_status(dag)
+        for k in ("worker", "start", "finish", "ie_at_pop", "mode_at_pop"):
+            assert np.array_equal(o2[k].cpu().numpy(), r[k]), (key, k)
+    dag.free()
+
+
+@pytest.mark.skip(reason="several simulating waves per work-group (tune key waves=2..4) faulted the GPU in one "
+                         "run with no cause found by reading the code; the launch shape was taken out and waves=1 "
+                         "is the only accepted value")
+def test_several_simulating_waves_per_work_group(insp):
+    ws = synth.cfg3(select=list(range(0, 4096, 256)))
+    b = synth.concat(ws)
+    say("waves per work-group")
+    dag, dur, est = insp.batch_to_device(b)
+    r = oracle.schedule_batch(b)
+    for key in ("waves=2,grid=3", "waves=3,grid=2", "waves=4,grid=1", "waves=4,grid=256,lds_slots=0"):
+        o = insp.schedule_batch(dag, [(w.n_cpu, w.n_gpu) for w in ws], dur, est, tune_key=key)
+        insp.sync_status(dag)
+        for k in ("worker", "start", "finish", "ie_at_pop", "mode_at_pop"):
+            assert np.array_equal(o[k].cpu().numpy(), r[k]), (key, k)
     dag.free()
 
 
@@ -1108,14 +1127,15 @@ def test_batch_with_empty_and_single_task_dags(insp):
     insp.set_task_data(dag, torch.from_numpy(b.data_kib).cuda())
     for pol, kw in (("inspirit", {}), ("fifo", {}), ("heft", {}), ("inspirit", {"attr_mode": "transitive"}),
                     ("locality", {"data_bw": 300}), ("inspirit", {"data_bw": 300})):
-        say("edge batch", pol, kw)
-        o = insp.schedule_batch(dag, workers, dur, est, insp.params(policy=pol, **kw))
-        insp.sync_status(dag)
         r = oracle.schedule_batch(b, policy=pol, **kw)
-        for k in ("worker", "start", "finish", "ie_at_pop", "mode_at_pop"):
-            assert np.array_equal(o[k].cpu().numpy(), r[k]), (pol, kw, k)
-        ms = o["makespan"].cpu().numpy()
-        assert np.array_equal(ms, r["makespan"]) and ms[0] == 0 and ms[-1] == 0, (pol, kw)
+        for key in (None, "grid=2,lds_slots=0"):
+            say("edge batch", pol, kw, key)
+            o = insp.schedule_batch(dag, workers, dur, est, insp.params(policy=pol, **kw), tune_key=key)
+            insp.sync_status(dag)
+            for k in ("worker", "start", "finish", "ie_at_pop", "mode_at_pop"):
+                assert np.array_equal(o[k].cpu().numpy(), r[k]), (pol, kw, key, k)
+            ms = o["makespan"].cpu().numpy()
+            assert np.array_equal(ms, r["makespan"]) and ms[0] == 0 and ms[-1] == 0, (pol, kw, key)
     ia, ie, U, lp = insp.transitive_attributes(dag, insp.ALL_DAGS, est, workers)
     ia, ie = ia.cpu().numpy(), ie.cpu().numpy()
     for k, w in enumerate(ws):
