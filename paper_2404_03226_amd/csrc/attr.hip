@@ -24,7 +24,10 @@
 //   - k_attr_dag: one 1024-thread work-group per DAG (DAGs below kGridMin
 //     tasks) with the DAG's task words in LDS: pass A, the choice of U, then
 //     pass B while the DAG's rows are still in L2 -- every array crosses HBM
-//     once and no lookup leaves the CU.
+//     once and no lookup leaves the CU.  With the ladder's U = 2^j, pass A
+//     also leaves one decision word per row (count and the rungs of its least
+//     and largest tau(v) + tau(s)), and pass B takes a row per thread, reading
+//     the successors only of rows whose span U splits.
 //   - k_attr_pack / k_attr_big_a / k_attr_big_sel / k_attr_big_b: one large
 //     DAG over a persistent grid: its task words packed to one array, pass A
 //     leaving a summary per row (count of rem == 1 successors, least and
@@ -77,6 +80,8 @@ struct AttrArgs {
     int32_t *part;              // grid pass: per-block partial results [kBigGrid][32]
     uint32_t *pkg;              // grid pass: task words of the large DAG (by row)
     unsigned long long *summ;   // grid pass: each row's pass-A summary
+    uint32_t *srow;             // per-DAG pass, ladder U: each row's pass-A decision word (global task index;
+                                // scratch the simulation reuses later)
     int32_t first;              // DAG id of desc[0]
     const int32_t *rp, *col;
     const unsigned long long *word0;
@@ -168,6 +173,16 @@ __device__ __forceinline__ void unpack_summary(unsigned long long w, int32_t &cn
     cnt1 = (int32_t)(w & 0x1FFFFF);
     lo = (int32_t)(w >> 21 & 0x1FFFFF) + 1;
     hi = (int32_t)(w >> 42 & 0x1FFFFF) + 1;
+}
+
+// A row's pass-A result for a U that is a power of two, 2^j: the count of
+// successors with rem == 1 (< 2^22) and the rungs ceil(log2) of the least and
+// largest tau(v) + tau(s) over them (each <= 22).  Since x <= 2^j exactly when
+// ceil(log2 x) <= j, IE at U = 2^j is the count when the largest rung is <= j,
+// zero when the least is > j, and needs the row's successors only otherwise.
+__device__ __forceinline__ uint32_t decision_word(int32_t cnt1, int32_t lo, int32_t hi) {
+    if (cnt1 <= 0) return 0u;
+    return (uint32_t)cnt1 | (uint32_t)ceil_log2(lo) << 22 | (uint32_t)ceil_log2(hi) << 27;
 }
 
 // The task word from the inputs: rem (given, or the in-degree in the high
@@ -466,9 +481,13 @@ __global__ __launch_bounds__(kDagThreads) void k_attr_dag(AttrArgs a, AttrOut o)
     const int32_t *r = a.rp + d.toff + d.id;
     const int32_t *c = a.col + d.eoff;
     const bool ability = a.unit_time == 0;
+    uint32_t *srow = a.srow + d.toff;
     dag_pass<false>(r, c, d.n, pks, wv * kWave, kDagThreads, 0, dl[wv],
                     [&](int32_t v, int32_t, int32_t deg, int32_t cnt, int32_t lo, int32_t hi) {
-                        if (v < d.n && ability) add_rungs(hist, cnt, lo, hi, deg);
+                        if (v < d.n && ability) {
+                            add_rungs(hist, cnt, lo, hi, deg);
+                            srow[v] = decision_word(cnt, lo, hi);
+                        }
                     });
     __syncthreads();
     if (tid == 0) {
@@ -489,7 +508,30 @@ __global__ __launch_bounds__(kDagThreads) void k_attr_dag(AttrArgs a, AttrOut o)
         for (int32_t v = tid; v < d.n; v += kDagThreads) write_row(a, o, d, v, 0, 0, 0, 0, true);
         return;
     }
-    dag_pass<true>(r, c, d.n, pks, wv * kWave, kDagThreads, a.u[d.id], dl[wv],
+    const int32_t U = a.u[d.id];
+    if (ability) {
+        // U = 2^j from the ladder: a row per thread, IE from its decision
+        // word; a row that U splits counts its successors itself
+        const int j = __builtin_ctz((uint32_t)U);
+        for (int32_t v = tid; v < d.n; v += kDagThreads) {
+            const uint32_t w = srow[v];
+            const int32_t e0 = r[v], deg = r[v + 1] - e0;
+            const int32_t tv = (int32_t)(pks[v] & ~kRem1);
+            const int32_t cnt = (int32_t)(w & 0x3FFFFF), jl = (int32_t)(w >> 22 & 31), jh = (int32_t)(w >> 27);
+            int32_t ie = 0;
+            if (cnt > 0 && jh <= j) {
+                ie = cnt;
+            } else if (cnt > 0 && jl <= j) {
+                for (int32_t e = e0; e < e0 + deg; e++) {
+                    const uint32_t pv = pks[c[e]];
+                    if ((pv & kRem1) && (int64_t)tv + (int32_t)(pv & ~kRem1) <= (int64_t)U) ie++;
+                }
+            }
+            write_row(a, o, d, v, e0, deg, tv, ie, false);
+        }
+        return;
+    }
+    dag_pass<true>(r, c, d.n, pks, wv * kWave, kDagThreads, U, dl[wv],
                    [&](int32_t v, int32_t e0, int32_t deg, int32_t cnt, int32_t, int32_t) {
                        if (v < d.n) write_row(a, o, d, v, e0, deg, (int32_t)(pks[v] & ~kRem1), cnt, false);
                    });
@@ -768,6 +810,7 @@ static AttrArgs make_args(insp_dag *dag, Workspace *ws, const int32_t *est, int3
     a.part = ws->apart;
     a.pkg = ws->apkg;
     a.summ = ws->asumm;
+    a.srow = reinterpret_cast<uint32_t *>(ws->fbuf);
     a.first = ws->first;
     a.rp = dag->rp.as<int32_t>();
     a.col = dag->col.as<int32_t>();

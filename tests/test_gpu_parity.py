@@ -112,6 +112,50 @@ def test_attributes_match_oracle(insp, seed):
     dag.free()
 
 
+def _stars(seed, n_stars, k):
+    """n_stars out-stars of k leaves each (every leaf's only predecessor is
+    its hub, so every successor has rem == 1) with ticks spread over
+    U{1..2000}: the ladder's U lands inside the hubs' spans of tau(v) + tau(s)
+    and splits their rows."""
+    st = synth.Stream(seed, 2)
+    n = n_stars * (k + 1)
+    rp = np.zeros(n + 1, np.int32)
+    col = []
+    for h in range(n_stars):
+        base = h * (k + 1)
+        col += list(range(base + 1, base + k + 1))
+        rp[base + 1:] += k
+    col = np.array(col, np.int32)
+    d = st.randint(np.arange(2 * n), 1, 2001).astype(np.int32).reshape(n, 2)
+    return NS(n=n, row_ptr=rp, col=col, dur=d, est=d.copy(), n_cpu=4, n_gpu=2, m=int(col.size),
+              type=np.zeros(n, np.int32), name=f"stars-{n_stars}x{k}")
+
+
+def test_attributes_rows_split_by_u(insp):
+    """Rows whose tau(v) + tau(s) span straddles the ladder's U: IE from a
+    count of the row's successors, not from its pass-A summary."""
+    for seed, (n_stars, k) in enumerate([(1, 40), (30, 12), (200, 3)]):
+        w = _stars(seed, n_stars, k)
+        rp, col = oracle.canon(w.n, w.row_ptr, w.col)
+        ria, rie, rU = oracle.attributes(w.n, rp, col, w.est, w.n_gpu)
+        hubs = np.arange(0, w.n, k + 1)
+        split = int(((rie[hubs] > 0) & (rie[hubs] < ria[hubs])).sum())
+        say("attributes split rows", w.name, "U", rU, "split hubs", split)
+        assert split > 0
+        dag, dur, est = insp.to_device(w)
+        ia, ie, Ug = insp.attributes(dag, 0, est, (w.n_cpu, w.n_gpu))
+        assert Ug[0] == rU
+        assert np.array_equal(ia.cpu().numpy(), ria) and np.array_equal(ie.cpu().numpy(), rie)
+        # the same DAG scheduled: the records' IE at pop come from the same pass
+        prm = insp.params()
+        o = insp.schedule(dag, 0, (w.n_cpu, w.n_gpu), dur, est, prm)
+        insp.sync_status(dag)
+        r = oracle.schedule(w)
+        assert np.array_equal(o["start"][:w.n].cpu().numpy(), r["start"])
+        assert np.array_equal(o["ie_at_pop"][:w.n].cpu().numpy(), r["ie_at_pop"])
+        dag.free()
+
+
 def _hub_dag(seed, n, hubs):
     """A DAG of n tasks whose first rows have the given out-degrees (hub rows
     cut into pieces by the grid-wide attribute pass, straddling piece
