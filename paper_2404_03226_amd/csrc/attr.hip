@@ -21,8 +21,9 @@
 // search over the chunk's offsets in LDS; per-row counts and extremes are
 // LDS atomics.  Each task is looked up through one 32-bit word, tau with the
 // rem == 1 flag.  Two layouts:
-//   - k_attr_dag: one 1024-thread work-group per DAG (DAGs below kGridMin
-//     tasks) with the DAG's task words in LDS: pass A, the choice of U, then
+//   - k_attr_dag: one work-group per DAG (DAGs below kGridMin tasks; 1024
+//     threads above kMidTasks tasks, 256 below, so that several small DAGs
+//     share a CU) with the DAG's task words in LDS: pass A, the choice of U, then
 //     pass B while the DAG's rows are still in L2 -- every array crosses HBM
 //     once and no lookup leaves the CU.  With the ladder's U = 2^j, pass A
 //     also leaves one decision word per row (count and the rungs of its least
@@ -339,8 +340,9 @@ struct WaveSlots {
     int32_t bad;
 };
 
-constexpr int kDagThreads = 1024;
-constexpr int kDagWaves = kDagThreads / kWave;
+constexpr int kDagThreads = 1024;  // work-group of a DAG of more than kMidTasks tasks
+constexpr int kMidThreads = 256;   // ... of the others: several such DAGs share a CU
+constexpr int kMidTasks = 4096;
 
 // One wave's scratch in the per-DAG kernel.
 struct DagLds {
@@ -440,15 +442,17 @@ __device__ __forceinline__ void dag_pass(const int32_t *r, const int32_t *c, int
 }
 
 // One work-group per DAG: the DAG's task words in LDS, both passes and the
-// choice of U.  Dynamic LDS: 4 bytes per task of the largest DAG.
-template <bool HAS_REM>
-__global__ __launch_bounds__(kDagThreads) void k_attr_dag(AttrArgs a, AttrOut o) {
+// choice of U.  The DAGs taken are sorder[first + blockIdx.x]; dynamic LDS:
+// 4 bytes per task of the largest of them.
+template <bool HAS_REM, int TPB>
+__global__ __launch_bounds__(TPB) void k_attr_dag(AttrArgs a, AttrOut o, int32_t first) {
+    constexpr int kDagThreads = TPB, kDagWaves = TPB / kWave;
     extern __shared__ uint32_t pks[];
     __shared__ DagLds dl[kDagWaves];
     __shared__ WaveSlots ws;
     __shared__ int32_t hist[kRungs];
     const int tid = threadIdx.x, wv = tid / kWave, lane = tid & (kWave - 1);
-    const DagDesc d = a.desc[a.sorder[blockIdx.x]];
+    const DagDesc d = a.desc[a.sorder[first + blockIdx.x]];
     if (!o.sim_init && dev_load(a.anybad)) return;  // validated before: the call fails
     if (tid < kRungs) hist[tid] = 0;
     if (tid == 0) ws.bad = 0;
@@ -866,13 +870,30 @@ int run_attributes(insp_dag *dag, Workspace *ws, const int32_t *est, int32_t uni
     }
     if (ws->n_small > 0) {
         ProfScope ps(st, "attr_dag");
-        const size_t lds = 4 * (size_t)std::max(ws->max_small, 1);
+        // the DAGs above kMidTasks (first in sorder) get 1024 threads each,
+        // the others 256, so that several of them share a CU
+        int32_t n_big = 0;
+        while (n_big < ws->n_small && ws->h_desc[ws->h_sorder[n_big]].n > kMidTasks) n_big++;
+        const int32_t n_mid = ws->n_small - n_big;
+        const size_t lds_big = 4 * (size_t)std::max(ws->max_small, 1);
+        const size_t lds_mid = 4 * (size_t)std::max(n_mid > 0 ? ws->h_desc[ws->h_sorder[n_big]].n : 1, 1);
         if (rem) {
-            if (int rc = set_lds_limit((const void *)&k_attr_dag<true>, lds)) return rc;
-            hipLaunchKernelGGL(k_attr_dag<true>, dim3(ws->n_small), dim3(kDagThreads), lds, st, a, o);
+            if (n_big > 0) {
+                if (int rc = set_lds_limit((const void *)&k_attr_dag<true, kDagThreads>, lds_big)) return rc;
+                hipLaunchKernelGGL((k_attr_dag<true, kDagThreads>), dim3(n_big), dim3(kDagThreads), lds_big, st, a, o, 0);
+            }
+            if (n_mid > 0)
+                hipLaunchKernelGGL((k_attr_dag<true, kMidThreads>), dim3(n_mid), dim3(kMidThreads), lds_mid, st, a, o,
+                                   n_big);
         } else {
-            if (int rc = set_lds_limit((const void *)&k_attr_dag<false>, lds)) return rc;
-            hipLaunchKernelGGL(k_attr_dag<false>, dim3(ws->n_small), dim3(kDagThreads), lds, st, a, o);
+            if (n_big > 0) {
+                if (int rc = set_lds_limit((const void *)&k_attr_dag<false, kDagThreads>, lds_big)) return rc;
+                hipLaunchKernelGGL((k_attr_dag<false, kDagThreads>), dim3(n_big), dim3(kDagThreads), lds_big, st, a, o,
+                                   0);
+            }
+            if (n_mid > 0)
+                hipLaunchKernelGGL((k_attr_dag<false, kMidThreads>), dim3(n_mid), dim3(kMidThreads), lds_mid, st, a, o,
+                                   n_big);
         }
     }
     for (int32_t di : ws->h_large) {
