@@ -1140,7 +1140,11 @@ __device__ __forceinline__ void rebuild_max(const SlotPool &slots, const Keys<FI
 // nothing the general loop relies on, when the DAG's keys do not fit.
 // FIX = true: fixed 64-bit keys (HEFT ranks or transitive attributes); the
 // tasks' direct IE is still kept up to date for the records.
-template <bool FIX>
+// DATA = true: the data model (A.data_bw > 0), as the general loop runs it: a
+// push adds each worker's input transfer ticks to its cost and records the
+// task's input arrival time, a pop starts its task when the inputs are in,
+// and the efficiency-with-locality rule prefers tasks whose inputs are.
+template <bool FIX, bool DATA>
 __device__ bool sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
     using KT = typename Keys<FIX>::T;
     const int lane = lane_id();
@@ -1209,6 +1213,17 @@ __device__ bool sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
     K.mx = reinterpret_cast<KT *>(L.sum);
     K.o0 = A.policy == INSP_POLICY_FIFO ? 2 : heft ? 3 : 0;
     const int32_t U = A.dag_u[d.id];
+    // data model: inputs move between memory nodes (the host for the CPU
+    // workers, one per GPU worker)
+    const int32_t *prp = A.pprp + d.toff + d.id, *pred = A.ppred + d.eoff;
+    int32_t *dxc = A.dxc + d.toff;
+    long long *barr = A.barr + d.blk_off;
+    // block arrival bounds matter only where the locality rule can be used
+    const bool lrule = DATA && (A.policy == INSP_POLICY_INSPIRIT || A.policy == INSP_POLICY_LOCALITY);
+    const int32_t mynode = lane < ncpu ? 0 : 1 + lane - ncpu;  // this lane's worker's memory node
+    if constexpr (DATA)  // each output's transfer ticks, once per run (no division at the pushes)
+        for (int32_t i = lane; i < n; i += kWave)
+            dxc[i] = (int32_t)(((int64_t)1024 * A.dkib[d.toff + i] + A.data_bw - 1) / A.data_bw);
 
     const int32_t s_inc = A.s_inc > 0 ? A.s_inc : max(1, (W + 3) / 4);
     const int32_t s_dec = A.s_dec > 0 ? A.s_dec : max(1, (W + 1) / 2);
@@ -1222,7 +1237,7 @@ __device__ bool sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
     // this lane's worker
     const bool wok = lane < W;
     int32_t run = -1, len = 0, nb = 0, last = -1, rsr = 0, dgr = 0;
-    int64_t fin = 0, expend = 0, qest = 0;
+    int64_t fin = 0, expend = 0, qest = 0, st0 = 0;  // st0: the running task's start
     int32_t pf[kPF];
 #pragma unroll
     for (int j = 0; j < kPF; j++) pf[j] = 0;
@@ -1308,11 +1323,33 @@ __device__ bool sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
             PCLK(16);
             const int32_t cntj = min(kWave, r - i0);
             int32_t pq = 0, sqj = 0, wsj = 0;  // lane j: slot, push order and worker of task j
+            int64_t xsj = 0;                     // ... and (data model) its input transfer ticks
             for (int32_t j = 0; j < cntj; j++) {
                 const int32_t e0 = read_lane(e_l.x, j), e1 = read_lane(e_l.y, j);
+                // DMDA's transfer term: ticks to move the inputs whose home
+                // node is not this lane's worker's (an item stays where it was made)
+                int64_t xk = 0;
+                if constexpr (DATA) {
+                    const int32_t v = read_lane(v_l, j);
+                    const int32_t pa = prp[v], pz = prp[v + 1];
+                    for (int32_t c0 = pa; c0 < pz; c0 += kWave) {
+                        int32_t nu = 0, cu = 0;
+                        if (c0 + lane < pz) {
+                            const int32_t u = pred[c0 + lane];
+                            const int32_t wu = -2 - tr[u].qpos;  // worker of a finished task
+                            nu = wu < ncpu ? 0 : 1 + wu - ncpu;
+                            cu = dxc[u];
+                        }
+                        const int32_t cn = min(kWave, pz - c0);
+                        for (int32_t jj = 0; jj < cn; jj++) {
+                            const int32_t nj = read_lane(nu, jj), cj = read_lane(cu, jj);
+                            if (mynode != nj) xk += cj;
+                        }
+                    }
+                }
                 // least expected termination, ties to the lower worker: a
                 // 32-bit key (cost - t) << 6 | worker while it fits
-                const int64_t rc = ld + (lane < ncpu ? e0 : e1) - t;
+                const int64_t rc = ld + (lane < ncpu ? e0 : e1) + xk - t;
                 const uint32_t k32 = wok && rc < (1 << 26) ? (uint32_t)rc << 6 | (uint32_t)lane : ~0u;
                 const uint32_t m32 = wave_min_u32f(k32);
                 int32_t ws;
@@ -1323,6 +1360,11 @@ __device__ bool sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
                     ws = (int32_t)(wave_min_u64f(k64) & 63);
                 }
                 const int32_t ek = ws >= ncpu ? e1 : e0;
+                int64_t xs = 0;
+                if constexpr (DATA) {
+                    xs = (int64_t)read_lane64((uint64_t)xk, ws);
+                    if (xs > INSP_MAX_TICK) status |= ST_XFER;
+                }
                 const int32_t lenw = read_lane(len, ws);
                 const int32_t pos = lenw & 63;
                 int32_t blk;
@@ -1356,6 +1398,7 @@ __device__ bool sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
                     pq = blk * 64 + pos;
                     sqj = seq;
                     wsj = ws;
+                    xsj = xs;
                 }
                 seq++;
                 nready++;
@@ -1401,6 +1444,9 @@ __device__ bool sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
                 }
                 tr[v_l].qpos = pq;
                 tr[v_l].seq = sqj;
+                // data model: the record's first word holds the time the
+                // task's inputs arrive (transfers start now) until its pop
+                if constexpr (DATA) tr[v_l].word = (unsigned long long)(t + xsj);
                 if ((pq & 63) == 0) {
                     if (bq < SC) {
                         K.mx[2 * bq] = a0;
@@ -1410,6 +1456,8 @@ __device__ bool sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
                         sums[2 * bq] = a0;
                         sums[2 * bq + 1] = a1;
                     }
+                    // never lowered by pops: an upper bound for the block
+                    if (lrule) barr[bq] = t + xsj;
                 }
             }
             if (ok) {
@@ -1420,6 +1468,7 @@ __device__ bool sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
                     wg_fetch_max(&sums[2 * bq], (unsigned long long)a0);
                     wg_fetch_max(&sums[2 * bq + 1], (unsigned long long)a1);
                 }
+                if (lrule) wg_fetch_max(reinterpret_cast<unsigned long long *>(&barr[bq]), (unsigned long long)(t + xsj));
             }
         }
         PCLK(0);
@@ -1452,9 +1501,13 @@ __device__ bool sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
         const int pmode = A.policy == INSP_POLICY_FIFO ? INSP_MODE_FIFO
                         : A.policy == INSP_POLICY_ABILITY_ONLY ? INSP_MODE_ABILITY
                         : A.policy == INSP_POLICY_EFI_ONLY ? INSP_MODE_EFI
+                        : (DATA && A.policy == INSP_POLICY_LOCALITY) ? INSP_MODE_EFI_LOC
                         : heft ? INSP_MODE_RANK : mode;
         const int ord = heft ? 3 : pmode == INSP_MODE_FIFO ? 2 : pmode == INSP_MODE_ABILITY ? 0 : 1;
         const int slot = ord == 1 ? 1 : 0;
+        // efficiency with locality under the data model: tasks whose inputs
+        // have arrived first
+        const bool loc = DATA && pmode == INSP_MODE_EFI_LOC;
         // ------------------------------------------------------------- pop
         int32_t popped = 0;
         bool popnow = false;        // this lane's worker took a task in this event
@@ -1466,9 +1519,81 @@ __device__ bool sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
             idle &= idle - 1;
             const int32_t nbw = read_lane(nb, w), lenw = read_lane(len, w), lastw = read_lane(last, w);
             const int32_t lastpos = (lenw - 1) & 63;
-            int32_t p;
+            int32_t p = 0;
             PCLK(10);
-            if (nbw <= A.scan_max) {
+            bool lsel = false;  // the locality rule found a task whose inputs are in place
+            if constexpr (DATA) {
+                if (loc) {
+                    // the arrival times are not in the keys.  A block whose
+                    // latest input arrival has passed holds only tasks whose
+                    // inputs are in place, so its efficiency maximum stands;
+                    // the other blocks are scanned entry by entry
+                    KT bestk = 0;
+                    int32_t bestb = -1;
+                    for (int32_t i0 = 0; i0 < nbw; i0 += kWave) {
+                        const int32_t i = i0 + lane;
+                        int32_t b = -1;
+                        if (i < nbw) {
+                            if (i < kLB) {
+                                b = L.blist[w * kLB + i];
+                            } else {
+                                b = wg_load(&wblk[(int64_t)w * maxb + i]);
+                                settle(b);
+                            }
+                        }
+                        uint64_t sm = ballot(b >= 0 && b < SC && L.stale[b] != 0);
+                        while (sm) {
+                            const int l = (int)__builtin_ctzll(sm);
+                            sm &= sm - 1;
+                            rebuild_max<FIX>(slots, K, L, sums, SLC, SC, read_lane(b, l));
+                        }
+                        KT kk = 0;
+                        bool mix = false;
+                        if (b >= 0) {
+                            if ((int64_t)wg_load(&barr[b]) <= t) kk = b < SC ? K.mx[2 * b + 1] : (KT)wg_load(&sums[2 * b + 1]);
+                            else mix = true;
+                        }
+                        const KT km = wave_max_k(kk);
+                        if (km > bestk) {
+                            bestk = km;
+                            bestb = read_lane(b, (int)__builtin_ctzll(ballot(kk == km && b >= 0)));
+                        }
+                        uint64_t mm = ballot(mix);
+                        while (mm) {
+                            const int32_t bm = read_lane(b, (int)__builtin_ctzll(mm));
+                            mm &= mm - 1;
+                            KT ke = 0;
+                            if (lane < (bm == lastw ? lastpos + 1 : 64)) {
+                                const int32_t pe = bm * 64 + lane;
+                                const uint64_t xv = bm < SLC ? L.sx[pe] : wg_load(&slots.x[pe]);
+                                const KT kr = bm < SLC ? K.lds(pe, 1) : K.rule(wg_load(&slots.k[pe]), 1);
+                                if ((int64_t)wg_load(&tr[(int32_t)(xv >> 42)].word) <= t) ke = kr;
+                            }
+                            const KT kme = wave_max_k(ke);
+                            if (kme > bestk) {
+                                bestk = kme;
+                                bestb = bm;
+                            }
+                        }
+                    }
+                    if (bestb >= 0) {
+                        // the best entry of that block whose inputs are in place
+                        KT key = 0;
+                        if (lane < (bestb == lastw ? lastpos + 1 : 64)) {
+                            const int32_t pe = bestb * 64 + lane;
+                            const uint64_t xv = bestb < SLC ? L.sx[pe] : wg_load(&slots.x[pe]);
+                            const KT kr = bestb < SLC ? K.lds(pe, 1) : K.rule(wg_load(&slots.k[pe]), 1);
+                            if ((int64_t)wg_load(&tr[(int32_t)(xv >> 42)].word) <= t) key = kr;
+                        }
+                        const KT km = wave_max_k(key);
+                        p = bestb * 64 + (int)__builtin_ctzll(ballot(key == km && key != 0));
+                        lsel = true;
+                    }
+                }
+            }
+            if (lsel) {
+                // chosen by the locality rule
+            } else if (nbw <= A.scan_max) {
                 // lane l compares entry l of every block of the worker: the
                 // blocks held in LDS, then those in global memory (a single
                 // block is the last one, known without reading the list)
@@ -1592,6 +1717,9 @@ __device__ bool sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
             }
             const int32_t v = (int32_t)(vx >> 42);
             const int32_t dk = (int32_t)((vx >> 21) & M21), ek = (int32_t)(vx & M21);
+            // a task whose inputs are still moving holds the worker until they arrive
+            int64_t s0 = t;
+            if constexpr (DATA) s0 = max(t, (int64_t)wg_load(&tr[v].word));
             // out-degree and the IE to record, from the direct key (fixed keys:
             // read from the task's record once the event's pops are done)
             int32_t deg = 0, iev = 0;
@@ -1615,6 +1743,8 @@ __device__ bool sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
                         slots.x[p] = mx;
                         slots.rs[p] = mr;
                     }
+                    // the moved entry keeps block bb's arrival bound valid
+                    if (lrule && lastw != bb) barr[bb] = max(barr[bb], barr[lastw]);
                 }
                 if (lane == popped) {
                     mvt = (int32_t)(mx >> 42);
@@ -1673,8 +1803,9 @@ __device__ bool sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
                 nb = nbn;
                 last = newlast;
                 run = v;
-                fin = t + dk;
-                expend = t + ek;
+                st0 = s0;
+                fin = s0 + dk;
+                expend = s0 + ek;
                 qest -= ek;
                 rsr = vr;
                 dgr = deg;
@@ -1696,7 +1827,7 @@ __device__ bool sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
                 iep = tattr ? tie[run] : fx.x;
             }
         }
-        if (popnow) put_record(&tr[run], t, (int32_t)(fin - t), lane, iep, pmode);
+        if (popnow) put_record(&tr[run], DATA ? st0 : t, (int32_t)(fin - (DATA ? st0 : t)), lane, iep, pmode);
         if (popnow && dgr > 0) {
             // entries past the row repeat its last successor (never used)
 #pragma unroll
@@ -2154,11 +2285,11 @@ __device__ void read_ahead(const SimArgs &A, int32_t di, const Lds &L) {
 }
 
 // Event loop a launch runs (one kernel each, so that each gets its own
-// register allocation): the one-wave loop on direct 32-bit keys (DAGs whose
-// keys do not fit fall back to the general loop), the one-wave loop on fixed
-// 64-bit keys (HEFT ranks, transitive attributes), or the general loop (the
-// data model, the locality policy, machines of more than 64 workers).
-enum SimLoop { kLoopDirect = 0, kLoopFixed = 1, kLoopGeneral = 2 };
+// register allocation), for machines of at most 64 workers: the one-wave loop
+// on direct 32-bit keys (DAGs whose keys do not fit fall back to the general
+// loop) or on fixed 64-bit keys (HEFT ranks, transitive attributes), each
+// with or without the data model; for larger machines the general loop.
+enum SimLoop { kLoopDirect = 0, kLoopFixed = 1, kLoopGeneral = 2, kLoopData = 3, kLoopDataFixed = 4 };
 
 template <int WPL, int LOOP>
 __global__ __launch_bounds__(WPL == 1 ? 2 * kWave : kWave) void k_sim(SimArgs A) {
@@ -2183,10 +2314,10 @@ __global__ __launch_bounds__(WPL == 1 ? 2 * kWave : kWave) void k_sim(SimArgs A)
             // their waves win instruction issue over co-resident waves
             if (i < A.prio_top) __builtin_amdgcn_s_setprio(3);
             else __builtin_amdgcn_s_setprio(0);
-            if constexpr (WPL == 1 && LOOP == kLoopDirect) {
-                if (!sim_lane<false>(A, A.order[i], L)) sim_dag<1>(A, A.order[i], L);
-            } else if constexpr (WPL == 1 && LOOP == kLoopFixed) {
-                sim_lane<true>(A, A.order[i], L);
+            if constexpr (WPL == 1 && (LOOP == kLoopDirect || LOOP == kLoopData)) {
+                if (!sim_lane<false, LOOP == kLoopData>(A, A.order[i], L)) sim_dag<1>(A, A.order[i], L);
+            } else if constexpr (WPL == 1 && (LOOP == kLoopFixed || LOOP == kLoopDataFixed)) {
+                sim_lane<true, LOOP == kLoopDataFixed>(A, A.order[i], L);
             } else {
                 sim_dag<WPL>(A, A.order[i], L);
             }
@@ -2294,21 +2425,22 @@ int launch_sim(insp_dag *dag, Workspace *ws, const insp_params &p, const int32_t
     hipLaunchKernelGGL(k_counter_reset, dim3(1), dim3(64), 0, st, A.counter);
     {
         ProfScope ps(st, "sim");
-        // the data model and the locality rule need the general loop; fixed
-        // keys and direct keys have one-wave loops of their own
-        const bool general = p.data_bw > 0 || p.policy == INSP_POLICY_LOCALITY;
+        // one-wave loops for machines of at most 64 workers: fixed or direct
+        // keys, with or without the data model (the locality policy without
+        // it runs on the general loop)
+        const bool data = p.data_bw > 0;
         const bool fixed = p.policy == INSP_POLICY_HEFT || p.attr_mode == INSP_ATTR_TRANSITIVE;
-        if (ws->max_w <= 64 && !general) {
-            if (fixed) {
-                if (int rc = set_lds_limit((const void *)&k_sim<1, kLoopFixed>, lds)) return rc;
-                hipLaunchKernelGGL((k_sim<1, kLoopFixed>), dim3(grid), dim3(2 * kWave), lds, st, A);
-            } else {
-                if (int rc = set_lds_limit((const void *)&k_sim<1, kLoopDirect>, lds)) return rc;
-                hipLaunchKernelGGL((k_sim<1, kLoopDirect>), dim3(grid), dim3(2 * kWave), lds, st, A);
-            }
-        } else if (ws->max_w <= 64) {
+        if (ws->max_w <= 64 && !data && p.policy == INSP_POLICY_LOCALITY) {
             if (int rc = set_lds_limit((const void *)&k_sim<1, kLoopGeneral>, lds)) return rc;
             hipLaunchKernelGGL((k_sim<1, kLoopGeneral>), dim3(grid), dim3(2 * kWave), lds, st, A);
+        } else if (ws->max_w <= 64) {
+            const void *k = data ? (fixed ? (const void *)&k_sim<1, kLoopDataFixed> : (const void *)&k_sim<1, kLoopData>)
+                                 : (fixed ? (const void *)&k_sim<1, kLoopFixed> : (const void *)&k_sim<1, kLoopDirect>);
+            if (int rc = set_lds_limit(k, lds)) return rc;
+            if (data && fixed) hipLaunchKernelGGL((k_sim<1, kLoopDataFixed>), dim3(grid), dim3(2 * kWave), lds, st, A);
+            else if (data) hipLaunchKernelGGL((k_sim<1, kLoopData>), dim3(grid), dim3(2 * kWave), lds, st, A);
+            else if (fixed) hipLaunchKernelGGL((k_sim<1, kLoopFixed>), dim3(grid), dim3(2 * kWave), lds, st, A);
+            else hipLaunchKernelGGL((k_sim<1, kLoopDirect>), dim3(grid), dim3(2 * kWave), lds, st, A);
         } else if (ws->max_w <= 128) {
             if (int rc = set_lds_limit((const void *)&k_sim<2, kLoopGeneral>, lds)) return rc;
             hipLaunchKernelGGL((k_sim<2, kLoopGeneral>), dim3(grid), dim3(64), lds, st, A);
