@@ -314,7 +314,8 @@ def main():
     host = host_info()
     # the oracle on this host's cores, capped at the 16 cores a GPU's share
     # of the box has
-    threads = max(1, min(host["nproc"], 16))
+    # (the oracle takes one DAG per thread: a single DAG uses one)
+    threads = max(1, min(host["nproc"], 16, len(ws)))
     if not args.no_cpu_baseline or not args.no_verify:
         runs = 10 if not args.no_cpu_baseline else 1
         walls = []
