@@ -380,7 +380,7 @@ def main():
     if args.transitive:
         line["transitive"] = transitive_measure(dag, workers, ws, b, dur, est, args.steps, args.warmup, tune_key)
     if args.workload == "batch" and not args.no_learned:
-        line["learned_gap"] = learned_gap(dag, workers, b, args.epochs)
+        line["learned_gap"] = learned_gap(dag, workers, b, ws, args.epochs)
     print(json.dumps(line), flush=True)
     dag.free()
 
@@ -519,11 +519,15 @@ def compare_policies(dag, workers, b, dur, est, threads, data_bw=0):
     return out
 
 
-def learned_gap(dag, workers, b, epochs):
+def learned_gap(dag, workers, b, ws, epochs):
     """Train the device MLP on 1M simulator records, predict per-kind ticks for
     every task of the batch, and compare makespans against true durations for
-    est = truth, est = per-type table, est = MLP (all runs advance with truth)."""
+    est = truth, est = per-type table, est = MLP (all runs advance with truth).
+    The three schedules of a sample of DAGs (every 64th and the largest) are
+    checked against the oracle given the same integer estimates."""
     import torch
+    import oracle
+    from types import SimpleNamespace
     from paper_2404_03226_amd import costmodel, inspirit, synth
     t0 = time.time()
     rec = synth.cfg5_records()
@@ -556,8 +560,25 @@ def learned_gap(dag, workers, b, epochs):
         torch.cuda.synchronize()
         pred_ms = min(pred_ms, ev0.elapsed_time(ev1))
     del xd
-    ms = costmodel.evaluate(dag, workers, b.type, ticks, est_mlp, table)
+    ms, scheds = costmodel.evaluate(dag, workers, b.type, ticks, est_mlp, table, keep_schedules=True)
     gaps = costmodel.makespan_gaps(ms["true"], ms["plain"], ms["learned"])
+    # the sampled oracle check of all three runs
+    ests = {"true": ticks, "plain": table[b.type], "learned": est_mlp.cpu().numpy().reshape(-1, 2)}
+    big = int(np.argmax([w.n for w in ws]))
+    sample = sorted(set(range(0, len(ws), 64)) | {big})
+    exact = True
+    for k in sample:
+        a, z = int(b.task_off[k]), int(b.task_off[k + 1])
+        for name, est in ests.items():
+            w = SimpleNamespace(n=ws[k].n, row_ptr=ws[k].row_ptr, col=ws[k].col, n_cpu=ws[k].n_cpu,
+                                n_gpu=ws[k].n_gpu, dur=np.ascontiguousarray(ticks[a:z]),
+                                est=np.ascontiguousarray(est[a:z]))
+            r = oracle.schedule(w, variant=oracle.HEAP)
+            got = scheds[name]
+            exact &= all(np.array_equal(got[f][a:z], r[f]) for f in ("worker", "start", "finish"))
+            exact &= int(got["makespan"][k]) == r["makespan"]
+    gaps["schedules_bit_exact_sample"] = bool(exact)
+    gaps["sample"] = f"{len(sample)} DAGs (every 64th and the largest), each run's schedule against the oracle"
     gaps.update({"val_mse_ln_mlp": mse_mlp, "val_mse_ln_table": mse_tab, "train_steps": steps,
                  "train_s": round(train_ms / 1e3, 2), "predict_ms": round(pred_ms, 2),
                  "predict_tasks_per_s": round(len(b.type) / (pred_ms * 1e-3), 1),
