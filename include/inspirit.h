@@ -262,7 +262,10 @@ int insp_schedule(const insp_dag *dag, int32_t index, const insp_workers *worker
  * comma-separated string of "grid=<g>" (persistent work-groups, each one
  * wave simulating one DAG at a time), "lds_blocks=<b>" (queue blocks per DAG
  * whose maxima live in LDS, <= 8192), "lds_slots=<s>" (queue blocks per DAG
- * whose entries live in LDS), "prio=<k>" (the k largest DAGs run at raised
+ * whose entries live in LDS), "lds_keys=<k>" (queue blocks per DAG whose
+ * keys live in LDS, at least lds_slots: a pop's scan reads only keys; the
+ * default is 128 maxima, 24 full blocks and keys of 40, with three
+ * work-groups per CU), "prio=<k>" (the k largest DAGs run at raised
  * wave priority), "scan=<k>" (<= 16: a pop reads every queue entry of a
  * worker with at most k queue blocks, and picks a block by its maximum
  * first above that) and "waves=1" (the only accepted value; any other is

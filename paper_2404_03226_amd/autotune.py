@@ -29,8 +29,12 @@ def signature(dag, workers, prm) -> str:
 
 
 def candidates(n_dags, cus):
-    grids = sorted({min(n_dags, cus * k) for k in (4, 6, 8)})
-    return [f"grid={g},lds_blocks=256,lds_slots={s}" for g in grids for s in (8, 16, 24)]
+    # three work-groups per CU with more LDS-resident queue blocks (keys of
+    # further blocks beside full entries), or four with fewer
+    grids = sorted({min(n_dags, cus * k) for k in (3, 4)})
+    shapes = ("lds_blocks=256,lds_slots=16", "lds_blocks=256,lds_slots=24", "lds_blocks=128,lds_slots=32",
+              "lds_blocks=128,lds_slots=24,lds_keys=40", "lds_blocks=128,lds_slots=16,lds_keys=48")
+    return [f"grid={g},{sh}" for g in grids for sh in shapes]
 
 
 def tune(dag, workers, dur, est, prm, out, reps=2, use_cache=True, verbose=False) -> str:

@@ -302,7 +302,7 @@ int run_transitive(insp_dag *dag, Workspace *ws, const int32_t *est, int32_t uni
 
 // Launch shape of a batch call.
 struct BatchLaunch {
-    int grid = 1, sum_cap = 0, slot_cap = 0, prio = 0, scan = 16;
+    int grid = 1, sum_cap = 0, slot_cap = 0, key_cap = 0, prio = 0, scan = 16;
 };
 
 // Argument checks and the launch shape of a batch schedule call (host only;
@@ -314,6 +314,6 @@ int batch_prologue(insp_dag *dag, const insp_workers *workers, const int32_t *du
 int launch_sim(insp_dag *dag, Workspace *ws, const insp_params &p, const int32_t *dur, const int32_t *est,
                int32_t *worker, int64_t *start, int64_t *finish, int64_t *makespan, int32_t *ie_at_pop,
                int8_t *mode_at_pop, insp_trace_rec *trace, int32_t *n_events, int waves, int grid,
-               int sum_cap, int slot_cap, hipStream_t st, int prio_top, int scan_max);
+               int sum_cap, int slot_cap, int key_cap, hipStream_t st, int prio_top, int scan_max);
 
 }  // namespace insp

@@ -149,5 +149,5 @@ extern "C" int insp_schedule_batch_noalloc(const insp_dag *cdag, const insp_work
     if ((rc = prepare(dag, workers, ds, st))) return rc;
     if ((rc = run_attributes(dag, &ds->ws, est, params->unit_time, nullptr, nullptr, nullptr, true, st))) return rc;
     return launch_sim(dag, &ds->ws, *params, dur, est, worker, start, finish, makespan, ie_at_pop, mode_at_pop,
-                      nullptr, nullptr, 1, bl.grid, bl.sum_cap, bl.slot_cap, st, bl.prio, bl.scan);
+                      nullptr, nullptr, 1, bl.grid, bl.sum_cap, bl.slot_cap, bl.key_cap, st, bl.prio, bl.scan);
 }

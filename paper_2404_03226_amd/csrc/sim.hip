@@ -88,6 +88,7 @@ struct SimArgs {
     const DagDesc *desc;
     const int32_t *order;
     int32_t count, max_w, sum_cap, policy, lb, slot_cap;
+    int32_t key_cap;           // queue blocks whose keys live in LDS (>= slot_cap, whose payload does too)
     const int32_t *col;
     const int32_t *dur, *est;
     int64_t base;
@@ -130,16 +131,17 @@ struct Lds {
     int32_t *fr0, *fr1;                              // [kFC]
     int32_t *cs, *cu;                                // [kCC]
     int32_t *pre;                                    // [8 * kWave] staged frontier rows
-    unsigned long long *sk, *sx;                     // [64 * slot_cap] queue slots of the low blocks
-    int32_t *srs;                                    // [64 * slot_cap]
+    unsigned long long *sk;                          // [64 * key_cap] keys of the low blocks' entries
+    unsigned long long *sx;                          // [64 * slot_cap] payload (task, durations) of the lowest
+    int32_t *srs;                                    // [64 * slot_cap] ... and their first edges
     int32_t *fstk;                                   // [sum_cap] free block ids below sum_cap
     uint8_t *stale;                                  // [sum_cap] block maxima to rebuild before use
     int32_t *hs;                                     // [4] DAG index, simulation finished, helper sink
 };
 
-__host__ __device__ constexpr size_t lds_bytes(int mw, int sc, int lb, int slc) {
+__host__ __device__ constexpr size_t lds_bytes(int mw, int sc, int lb, int slc, int slk) {
     return (size_t)mw * (3 * 8 + 7 * 4 + (size_t)lb * 4) + (size_t)sc * (16 + 4 + 1) + kFC * 8 + kCC * 8 +
-           8 * 64 * 4 + (size_t)slc * 64 * 20 + 64 + 32;
+           8 * 64 * 4 + (size_t)slc * 64 * 12 + (size_t)slk * 64 * 8 + 64 + 32;
 }
 
 template <int WPL>
@@ -1050,7 +1052,7 @@ struct KeyFmt {
 template <bool FIX>
 struct Keys {
     using T = typename std::conditional<FIX, unsigned long long, uint32_t>::type;
-    T *ka, *ke;  // LDS slots [64 * slot_cap]: kA and kE, or (fixed) ka the key itself
+    T *ka, *ke;  // LDS keys [64 * key_cap]: kA and kE, or (fixed) ka the key itself
     T *mx;       // [2 * sum_cap]: the two rule maxima of each block summarised in LDS
     int o0;      // fixed keys: the rule of maximum 0 (0 ability, 2 FIFO, 3 rank)
     __device__ __forceinline__ T rule(uint64_t raw, int r) const {
@@ -1172,7 +1174,8 @@ __device__ bool sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
     const int32_t maxb = d.maxb;
     const int32_t SC = A.sum_cap;
     const int32_t kLB = A.lb;
-    const int32_t SLC = A.slot_cap;
+    const int32_t SLC = A.slot_cap;  // blocks [0, SLC) keep their entries' payload in LDS
+    const int32_t SLK = A.key_cap;   // blocks [0, SLK) (SLK >= SLC) keep their keys in LDS
 
     // initial frontier (tasks without predecessors, ascending) and the
     // largest out-degree, which sizes the key fields
@@ -1209,7 +1212,7 @@ __device__ bool sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
     const int32_t *tia = A.tia + d.toff, *tie = A.tie + d.toff;
     Keys<FIX> K;
     K.ka = reinterpret_cast<KT *>(L.sk);
-    K.ke = FIX ? nullptr : K.ka + 64 * SLC;  // the two 32-bit arrays fill the 64-bit slot storage
+    K.ke = FIX ? nullptr : K.ka + 64 * SLK;  // the two 32-bit arrays fill the 64-bit key storage
     K.mx = reinterpret_cast<KT *>(L.sum);
     K.o0 = A.policy == INSP_POLICY_FIFO ? 2 : heft ? 3 : 0;
     const int32_t U = A.dag_u[d.id];
@@ -1250,7 +1253,7 @@ __device__ bool sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
     int32_t nfl = nl, nfg = d.nblk - nl;
     // every slot starts empty (zero keys)
     for (int32_t b = 0; b < d.nblk; b++) {
-        if (b < SLC) {
+        if (b < SLK) {
             K.ka[b * 64 + lane] = 0;
             if constexpr (!FIX) K.ke[b * 64 + lane] = 0;
         } else {
@@ -1428,17 +1431,20 @@ __device__ bool sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
                     raw = (uint64_t)a1 << 32 | a0;
                 }
                 const uint64_t xw = (uint64_t)v_l << 42 | (uint64_t)(dkl & M21) << 21 | (uint64_t)(ekl & M21);
-                if (bq < SLC) {
+                if (bq < SLK) {
                     if constexpr (FIX) {
                         K.ka[pq] = raw;
                     } else {
                         K.ka[pq] = a0;
                         K.ke[pq] = a1;
                     }
+                } else {
+                    slots.k[pq] = raw;
+                }
+                if (bq < SLC) {
                     L.sx[pq] = xw;
                     L.srs[pq] = rs_l;
                 } else {
-                    slots.k[pq] = raw;
                     slots.x[pq] = xw;
                     slots.rs[pq] = rs_l;
                 }
@@ -1545,7 +1551,7 @@ __device__ bool sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
                         while (sm) {
                             const int l = (int)__builtin_ctzll(sm);
                             sm &= sm - 1;
-                            rebuild_max<FIX>(slots, K, L, sums, SLC, SC, read_lane(b, l));
+                            rebuild_max<FIX>(slots, K, L, sums, SLK, SC, read_lane(b, l));
                         }
                         KT kk = 0;
                         bool mix = false;
@@ -1566,7 +1572,7 @@ __device__ bool sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
                             if (lane < (bm == lastw ? lastpos + 1 : 64)) {
                                 const int32_t pe = bm * 64 + lane;
                                 const uint64_t xv = bm < SLC ? L.sx[pe] : wg_load(&slots.x[pe]);
-                                const KT kr = bm < SLC ? K.lds(pe, 1) : K.rule(wg_load(&slots.k[pe]), 1);
+                                const KT kr = bm < SLK ? K.lds(pe, 1) : K.rule(wg_load(&slots.k[pe]), 1);
                                 if ((int64_t)wg_load(&tr[(int32_t)(xv >> 42)].word) <= t) ke = kr;
                             }
                             const KT kme = wave_max_k(ke);
@@ -1582,7 +1588,7 @@ __device__ bool sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
                         if (lane < (bestb == lastw ? lastpos + 1 : 64)) {
                             const int32_t pe = bestb * 64 + lane;
                             const uint64_t xv = bestb < SLC ? L.sx[pe] : wg_load(&slots.x[pe]);
-                            const KT kr = bestb < SLC ? K.lds(pe, 1) : K.rule(wg_load(&slots.k[pe]), 1);
+                            const KT kr = bestb < SLK ? K.lds(pe, 1) : K.rule(wg_load(&slots.k[pe]), 1);
                             if ((int64_t)wg_load(&tr[(int32_t)(xv >> 42)].word) <= t) key = kr;
                         }
                         const KT km = wave_max_k(key);
@@ -1603,7 +1609,7 @@ __device__ bool sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
                 if (nbw == 1) bl = lastw;
                 else if (lane < nbw) bl = L.blist[w * kLB + lane];
                 const uint64_t all = nbw == 1 ? 1ull : ballot(lane < nbw);
-                const uint64_t inl = nbw == 1 ? (lastw < SLC ? 1ull : 0ull) : ballot(lane < nbw && bl < SLC);
+                const uint64_t inl = nbw == 1 ? (lastw < SLK ? 1ull : 0ull) : ballot(lane < nbw && bl < SLK);
                 KT best = 0;
                 int32_t bp = -1;
                 if (inl == all) {
@@ -1656,7 +1662,7 @@ __device__ bool sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
                         const int l = (int)__builtin_ctzll(sm);
                         sm &= sm - 1;
                         const int32_t sb = read_lane(b, l);
-                        rebuild_max<FIX>(slots, K, L, sums, SLC, SC, sb);
+                        rebuild_max<FIX>(slots, K, L, sums, SLK, SC, sb);
                     }
                     if (b >= 0) {
                         KT k;
@@ -1675,7 +1681,7 @@ __device__ bool sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
                 const KT kmb = wave_max_k(bk);
                 const int32_t bb = read_lane(bid, (int)__builtin_ctzll(ballot(bk == kmb && bid >= 0)));
                 const int32_t cntb = bb == lastw ? lastpos + 1 : 64;
-                const KT key = block_keys<FIX>(slots, K, SLC, bb, slot);
+                const KT key = block_keys<FIX>(slots, K, SLK, bb, slot);
                 const KT km = wave_max_k(key);
                 p = bb * 64 + (int)__builtin_ctzll(ballot(key == km && lane < cntb));
             }
@@ -1687,30 +1693,36 @@ __device__ bool sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
             uint64_t vx, mx = 0, mkr = 0;  // mkr: the moved entry's key word (the two 32-bit keys, or the fixed key)
             int32_t vr, mr = 0;
             if (bb < SLC) {
-                if constexpr (!FIX) ve = K.ke[p];
                 vx = L.sx[p];
                 vr = L.srs[p];
             } else {
-                if constexpr (!FIX) {
-                    ve = (uint32_t)(wg_load(&slots.k[p]) >> 32);
-                    settle(ve);
-                }
                 vx = wg_load(&slots.x[p]);
                 vr = wg_load(&slots.rs[p]);
                 settle(vx);
                 settle(vr);
             }
+            if constexpr (!FIX) {
+                if (bb < SLK) {
+                    ve = K.ke[p];
+                } else {
+                    ve = (uint32_t)(wg_load(&slots.k[p]) >> 32);
+                    settle(ve);
+                }
+            }
             if (p != q) {
-                if (lastw < SLC) {
+                if (lastw < SLK) {
                     if constexpr (FIX) mkr = K.ka[q];
                     else mkr = (uint64_t)K.ke[q] << 32 | K.ka[q];
+                } else {
+                    mkr = wg_load(&slots.k[q]);
+                    settle(mkr);
+                }
+                if (lastw < SLC) {
                     mx = L.sx[q];
                     mr = L.srs[q];
                 } else {
-                    mkr = wg_load(&slots.k[q]);
                     mx = wg_load(&slots.x[q]);
                     mr = wg_load(&slots.rs[q]);
-                    settle(mkr);
                     settle(mx);
                     settle(mr);
                 }
@@ -1729,17 +1741,20 @@ __device__ bool sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
             }
             if (p != q) {
                 if (lane == 0) {
-                    if (bb < SLC) {
+                    if (bb < SLK) {
                         if constexpr (FIX) {
                             K.ka[p] = mkr;
                         } else {
                             K.ka[p] = (uint32_t)mkr;
                             K.ke[p] = (uint32_t)(mkr >> 32);
                         }
+                    } else {
+                        slots.k[p] = mkr;
+                    }
+                    if (bb < SLC) {
                         L.sx[p] = mx;
                         L.srs[p] = mr;
                     } else {
-                        slots.k[p] = mkr;
                         slots.x[p] = mx;
                         slots.rs[p] = mr;
                     }
@@ -1753,7 +1768,7 @@ __device__ bool sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
             }
             // the worker's final slot is now empty
             if (lane == 0) {
-                if (lastw < SLC) {
+                if (lastw < SLK) {
                     K.ka[q] = 0;
                     if constexpr (!FIX) K.ke[q] = 0;
                 } else {
@@ -1787,14 +1802,14 @@ __device__ bool sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
                 if (bb < SC) {
                     if (lane == 0) L.stale[bb] = 1;
                 } else {
-                    rebuild_max<FIX>(slots, K, L, sums, SLC, SC, bb);
+                    rebuild_max<FIX>(slots, K, L, sums, SLK, SC, bb);
                 }
             }
             if (lastw != bb && !freed) {
                 if (lastw < SC) {
                     if (lane == 0) L.stale[lastw] = 1;
                 } else {
-                    rebuild_max<FIX>(slots, K, L, sums, SLC, SC, lastw);
+                    rebuild_max<FIX>(slots, K, L, sums, SLK, SC, lastw);
                 }
             }
             PCLK(13);
@@ -2013,7 +2028,7 @@ __device__ bool sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
                         const uint32_t na = kf.ka((uint32_t)au, (uint32_t)nie, (uint32_t)sq);
                         const uint32_t ne = kf.ke((uint32_t)au, (uint32_t)nie, (uint32_t)sq);
                         const int32_t bk = qu >> 6;
-                        if (bk < SLC) {
+                        if (bk < SLK) {
                             K.ka[qu] = na;
                             K.ke[qu] = ne;
                         } else {
@@ -2101,7 +2116,7 @@ __device__ bool sim_lane(const SimArgs &A, int32_t di, const Lds &L) {
                                 if (pu >= 0) {
                                     const int32_t bk = pu >> 6;
                                     uint32_t na, ne;
-                                    if (bk < SLC) {
+                                    if (bk < SLK) {
                                         na = atomicAdd(&K.ka[pu], kf.da()) + kf.da();
                                         ne = atomicAdd(&K.ke[pu], kf.de()) + kf.de();
                                     } else {
@@ -2181,7 +2196,7 @@ __device__ __forceinline__ Lds carve_lds(const SimArgs &A) {
     L.qest = lds64 + 2 * MW;
     L.sum = reinterpret_cast<unsigned long long *>(lds64 + 3 * MW);
     L.sk = L.sum + 2 * A.sum_cap;
-    L.sx = L.sk + 64 * A.slot_cap;
+    L.sx = L.sk + 64 * A.key_cap;
     int32_t *l32 = reinterpret_cast<int32_t *>(L.sx + 64 * A.slot_cap);
     L.run = l32;
     L.len = l32 + MW;
@@ -2352,7 +2367,7 @@ __global__ __launch_bounds__(256) void k_records(const TaskRec *tr, int64_t n, i
 int launch_sim(insp_dag *dag, Workspace *ws, const insp_params &p, const int32_t *dur, const int32_t *est,
                int32_t *worker, int64_t *start, int64_t *finish, int64_t *makespan, int32_t *ie_at_pop,
                int8_t *mode_at_pop, insp_trace_rec *trace, int32_t *n_events, int waves, int grid,
-               int sum_cap, int slot_cap, hipStream_t st, int prio_top, int scan_max) {
+               int sum_cap, int slot_cap, int key_cap, hipStream_t st, int prio_top, int scan_max) {
     (void)waves;
     SimArgs A;
     memset(&A, 0, sizeof A);
@@ -2410,16 +2425,20 @@ int launch_sim(insp_dag *dag, Workspace *ws, const insp_params &p, const int32_t
     // machines of hundreds of workers: shorter LDS block lists, then fewer
     // LDS block maxima, until the per-worker state fits (the rest lives in
     // global memory)
-    while (lb > 1 && (int64_t)lds_bytes(ws->max_w, (int)sc, (int)lb, 0) > budget) lb /= 2;
-    while (sc > 0 && (int64_t)lds_bytes(ws->max_w, (int)sc, (int)lb, 0) > budget) sc /= 2;
+    while (lb > 1 && (int64_t)lds_bytes(ws->max_w, (int)sc, (int)lb, 0, 0) > budget) lb /= 2;
+    while (sc > 0 && (int64_t)lds_bytes(ws->max_w, (int)sc, (int)lb, 0, 0) > budget) sc /= 2;
     int64_t slc = slot_cap;
-    if (one) slc = (budget - (int64_t)lds_bytes(ws->max_w, (int)sc, (int)lb, 0)) / (64 * 20);
+    if (one) slc = (budget - (int64_t)lds_bytes(ws->max_w, (int)sc, (int)lb, 0, 0)) / (64 * 20);
     slc = std::max<int64_t>(0, std::min<int64_t>(ws->max_nblk, slc));
-    while (slc > 0 && (int64_t)lds_bytes(ws->max_w, (int)sc, (int)lb, (int)slc) > budget) slc--;
+    while (slc > 0 && (int64_t)lds_bytes(ws->max_w, (int)sc, (int)lb, (int)slc, (int)slc) > budget) slc--;
+    // keys of further blocks in what LDS is left (a pop's scan reads only keys)
+    int64_t slk = std::max<int64_t>(slc, std::min<int64_t>(ws->max_nblk, key_cap));
+    while (slk > slc && (int64_t)lds_bytes(ws->max_w, (int)sc, (int)lb, (int)slc, (int)slk) > budget) slk--;
     A.sum_cap = (int32_t)sc;
     A.lb = (int32_t)lb;
     A.slot_cap = (int32_t)slc;
-    const size_t lds = lds_bytes(ws->max_w, A.sum_cap, A.lb, A.slot_cap);
+    A.key_cap = (int32_t)slk;
+    const size_t lds = lds_bytes(ws->max_w, A.sum_cap, A.lb, A.slot_cap, A.key_cap);
     if (lds > 160 * 1024) return set_error(INSP_E_RANGE, "simulation state of %d workers exceeds LDS", ws->max_w);
     grid = std::max(1, std::min(grid, ws->count));
     hipLaunchKernelGGL(k_counter_reset, dim3(1), dim3(64), 0, st, A.counter);
@@ -2495,13 +2514,16 @@ static int check_workers(const insp_workers *w, int32_t count) {
     return INSP_OK;
 }
 
+// Three work-groups per CU: what the default LDS shape (128 block maxima, 24
+// blocks of full entries, keys of 40) leaves room for on machines of up to 20
+// workers; larger grids only add work-groups that start when the DAGs are gone.
 static int default_grid(int count) {
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) == hipSuccess) {
         hipDeviceProp_t prop;
         if (hipGetDeviceProperties(&prop, dev) == hipSuccess) cus = prop.multiProcessorCount;
     }
-    return std::min(count, cus * 8);
+    return std::max(1, std::min(count, cus * 3));
 }
 
 extern "C" int insp_schedule(const insp_dag *cdag, int32_t index, const insp_workers *workers, const int32_t *dur,
@@ -2530,14 +2552,16 @@ extern "C" int insp_schedule(const insp_dag *cdag, int32_t index, const insp_wor
     if (params->data_bw > 0 && !dag->dxc.p && (rc = dag->dxc.alloc(sizeof(int32_t) * std::max<int64_t>(dag->N, 1))))
         return rc;
     return launch_sim(dag, ws, *params, dur, est, worker, start, finish, makespan, ie_at_pop, mode_at_pop, trace,
-                      n_events, 1, 1, 4096, 0, st, 0, kScan);
+                      n_events, 1, 1, 4096, 0, 0, st, 0, kScan);
 }
 
-static void parse_tune(const char *key, int *waves, int *grid, int *sum_cap, int *slot_cap, int *prio, int *scan) {
+static void parse_tune(const char *key, int *waves, int *grid, int *sum_cap, int *slot_cap, int *key_cap, int *prio,
+                       int *scan) {
     if (!key) return;
     std::string s(key);
     size_t a = s.find("waves="), b = s.find("grid="), c = s.find("lds_blocks="), d = s.find("lds_slots=");
-    size_t e = s.find("prio="), f = s.find("scan=");
+    size_t e = s.find("prio="), f = s.find("scan="), g = s.find("lds_keys=");
+    if (g != std::string::npos) *key_cap = atoi(s.c_str() + g + 9);
     if (e != std::string::npos) *prio = atoi(s.c_str() + e + 5);
     if (f != std::string::npos) *scan = atoi(s.c_str() + f + 5);
     if (a != std::string::npos) *waves = atoi(s.c_str() + a + 6);
@@ -2558,16 +2582,17 @@ int batch_prologue(insp_dag *dag, const insp_workers *workers, const int32_t *du
     if (dag->N > 0 && (!dur || !est || !worker || !start || !finish)) return set_error(INSP_E_INVAL, "null array");
     if ((((uintptr_t)dur | (uintptr_t)est) & 7) != 0) return set_error(INSP_E_INVAL, "dur/est rows must be 8-byte aligned");
     INSP_HIP(hipSetDevice(dag->device));
-    int waves = 1, grid = default_grid(dag->B), sum_cap = 256, slot_cap = 16, prio = 0, scan = kScan;
-    parse_tune(tune_key, &waves, &grid, &sum_cap, &slot_cap, &prio, &scan);
-    if (grid < 1 || sum_cap < 0 || sum_cap > 8192 || slot_cap < 0 || prio < 0 || scan < 0 || scan > kScan ||
-        lds_bytes(1, sum_cap, 16, slot_cap) > 150 * 1024)
+    int waves = 1, grid = default_grid(dag->B), sum_cap = 128, slot_cap = 24, key_cap = 40, prio = 0, scan = kScan;
+    parse_tune(tune_key, &waves, &grid, &sum_cap, &slot_cap, &key_cap, &prio, &scan);
+    if (grid < 1 || sum_cap < 0 || sum_cap > 8192 || slot_cap < 0 || key_cap < 0 || prio < 0 || scan < 0 ||
+        scan > kScan || lds_bytes(1, sum_cap, 16, slot_cap, std::max(slot_cap, key_cap)) > 150 * 1024)
         return set_error(INSP_E_INVAL, "bad tune key '%s'", tune_key);
     // one wave simulates one DAG; no other shape is implemented
     if (waves != 1) return set_error(INSP_E_INVAL, "tune key '%s': only waves=1 is supported", tune_key);
     launch->grid = grid;
     launch->sum_cap = sum_cap;
     launch->slot_cap = slot_cap;
+    launch->key_cap = key_cap;
     launch->prio = prio;
     launch->scan = scan;
     return INSP_OK;
@@ -2596,7 +2621,7 @@ static int schedule_batch(const insp_dag *cdag, const insp_workers *workers, con
     if (params->data_bw > 0 && !dag->dxc.p && (rc = dag->dxc.alloc(sizeof(int32_t) * std::max<int64_t>(dag->N, 1))))
         return rc;
     return launch_sim(dag, ws, *params, dur, est, worker, start, finish, makespan, ie_at_pop, mode_at_pop, trace,
-                      n_events, 1, bl.grid, bl.sum_cap, bl.slot_cap, st, bl.prio, bl.scan);
+                      n_events, 1, bl.grid, bl.sum_cap, bl.slot_cap, bl.key_cap, st, bl.prio, bl.scan);
 }
 
 extern "C" int insp_schedule_batch(const insp_dag *cdag, const insp_workers *workers, const int32_t *dur,

@@ -349,7 +349,8 @@ def test_batch_small_matches_oracle(insp):
         assert np.array_equal(o[k].cpu().numpy(), r[k]), k
     assert np.array_equal(o["makespan"].cpu().numpy(), r["makespan"])
     # tuning must not change results
-    for key in ("waves=1,grid=1", "waves=1,grid=3", "waves=1,grid=64"):
+    for key in ("waves=1,grid=1", "waves=1,grid=3", "waves=1,grid=64", "grid=3,lds_slots=2,lds_keys=40",
+                "grid=64,lds_slots=0,lds_keys=8", "grid=5,lds_blocks=4,lds_slots=1,lds_keys=3"):
         o2 = insp.schedule_batch(dag, [(w.n_cpu, w.n_gpu) for w in ws], dur, est, tune_key=key)
         insp.sync_status(dag)
         for k in ("worker", "start", "finish", "ie_at_pop", "mode_at_pop"):
@@ -757,7 +758,8 @@ def test_queue_spill_paths_batch_small_lds(insp):
     dag, dur, est = insp.batch_to_device(b)
     r = oracle.schedule_batch(b)
     for key in ("waves=1,grid=6,lds_blocks=4,lds_slots=3", "waves=1,grid=2,lds_blocks=0,lds_slots=0",
-                "waves=1,grid=3,lds_blocks=64,lds_slots=40"):
+                "waves=1,grid=3,lds_blocks=64,lds_slots=40", "grid=4,lds_blocks=8,lds_slots=2,lds_keys=50",
+                "grid=3,lds_blocks=0,lds_slots=0,lds_keys=12"):
         o = insp.schedule_batch(dag, [(w.n_cpu, w.n_gpu) for w in ws], dur, est, tune_key=key)
         insp.sync_status(dag)
         for k in ("worker", "start", "finish", "ie_at_pop", "mode_at_pop"):
@@ -1172,7 +1174,7 @@ def test_batch_with_empty_and_single_task_dags(insp):
     for pol, kw in (("inspirit", {}), ("fifo", {}), ("heft", {}), ("inspirit", {"attr_mode": "transitive"}),
                     ("locality", {"data_bw": 300}), ("inspirit", {"data_bw": 300})):
         r = oracle.schedule_batch(b, policy=pol, **kw)
-        for key in (None, "grid=2,lds_slots=0"):
+        for key in (None, "grid=2,lds_slots=0", "grid=3,lds_slots=1,lds_keys=24"):
             say("edge batch", pol, kw, key)
             o = insp.schedule_batch(dag, workers, dur, est, insp.params(policy=pol, **kw), tune_key=key)
             insp.sync_status(dag)

@@ -108,7 +108,7 @@ def test_policies(insp, policy):
 
 def test_launch_shapes(insp):
     ws, b = batch(list(range(1, 4096, 300)))
-    for key in ("grid=1", "grid=3,lds_blocks=4,lds_slots=0", "grid=64,lds_slots=24"):
+    for key in ("grid=1", "grid=3,lds_blocks=4,lds_slots=0", "grid=64,lds_slots=24", "grid=7,lds_slots=3,lds_keys=30"):
         say("noalloc tune", key)
         dag, dur, est, wk, ref, got = run_both(insp, ws, b, tune_key=key)
         same(got, ref, key)
