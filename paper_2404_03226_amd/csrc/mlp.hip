@@ -449,7 +449,8 @@ __global__ __launch_bounds__(64 * NW) void k_infer(const float *x, int64_t rows,
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int wn = wv * (kHid / NW), lc = lane & 15, lk = (lane >> 4) * 8;
     bf16x8 w1f[CT], w2f[8][CT];
-    float bias1[CT][4], bias2[CT][4], w30[CT][4], w31[CT][4];
+    float bias1[CT][4], bias2[CT][4];
+    bf16x2_t w30[CT][2], w31[CT][2];  // output weights of hidden units (i, i + 1), as packed bf16 pairs
 #pragma unroll
     for (int ct = 0; ct < CT; ct++) {
         const int n = wn + ct * 16 + lc;
@@ -469,8 +470,12 @@ __global__ __launch_bounds__(64 * NW) void k_infer(const float *x, int64_t rows,
             const int h = wn + ct * 16 + (lane >> 4) * 4 + i;
             bias1[ct][i] = b1[h];
             bias2[ct][i] = b2[h];
-            w30[ct][i] = bf2f(W3[h * 2]);
-            w31[ct][i] = bf2f(W3[h * 2 + 1]);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; i += 2) {
+            const int h = wn + ct * 16 + (lane >> 4) * 4 + i;
+            w30[ct][i / 2] = __builtin_bit_cast(bf16x2_t, (uint32_t)W3[h * 2] | (uint32_t)W3[h * 2 + 2] << 16);
+            w31[ct][i / 2] = __builtin_bit_cast(bf16x2_t, (uint32_t)W3[h * 2 + 1] | (uint32_t)W3[h * 2 + 3] << 16);
         }
     }
     const float b30 = b3[0], b31 = b3[1];
@@ -538,14 +543,13 @@ __global__ __launch_bounds__(64 * NW) void k_infer(const float *x, int64_t rows,
             for (int ct = 0; ct < CT; ct++)
 #pragma unroll
                 for (int i = 0; i < 4; i += 2) {
-                    // the bf16 rounding of H2, two units per conversion
-                    const uint32_t q = f2bf2(fmaxf(acc[ct][i] + bias2[ct][i], 0.f),
-                                             fmaxf(acc[ct][i + 1] + bias2[ct][i + 1], 0.f));
-                    const float h0 = __uint_as_float(q << 16), h1 = __uint_as_float(q & 0xFFFF0000u);
-                    s0 += h0 * w30[ct][i];
-                    s1 += h0 * w31[ct][i];
-                    s0 += h1 * w30[ct][i + 1];
-                    s1 += h1 * w31[ct][i + 1];
+                    // the bf16 rounding of H2, two units per conversion, and
+                    // their products with the output weights as one bf16 dot
+                    // product per output
+                    const bf16x2_t q = __builtin_bit_cast(bf16x2_t, f2bf2(fmaxf(acc[ct][i] + bias2[ct][i], 0.f),
+                                                                      fmaxf(acc[ct][i + 1] + bias2[ct][i + 1], 0.f)));
+                    s0 = __builtin_amdgcn_fdot2_f32_bf16(q, w30[ct][i / 2], s0, false);
+                    s1 = __builtin_amdgcn_fdot2_f32_bf16(q, w31[ct][i / 2], s1, false);
                 }
             p0[rt] = s0;
             p1[rt] = s1;
