@@ -435,6 +435,15 @@ __global__ void k_shadow(const float *p, uint16_t *w1, uint16_t *w2, uint16_t *w
 // NW = 4, so two waves share each SIMD and one's MFMA overlaps the other's
 // conversions and LDS traffic.
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+
+// ReLU of two packed bf16 values at once: a bf16 is negative exactly when its
+// bit pattern is as a 16-bit integer, and rounding keeps the sign, so this is
+// the rounding of max(x, 0) (with -0 turned into +0).
+__device__ __forceinline__ uint32_t relu_bf2(uint32_t q) {
+    const s16x2 z = {0, 0};
+    return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(s16x2, q), z));
+}
 constexpr int kRT = 64, kH1Row = kHid + 8;
 
 constexpr int kInferWaves = 8;
@@ -516,8 +525,8 @@ __global__ __launch_bounds__(64 * NW) void k_infer(const float *x, int64_t rows,
                 f32x4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1f[ct], af1[rt], f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0,
                                                                     0);
                 uint2 h;
-                h.x = f2bf2(fmaxf(acc[0] + bias1[ct][0], 0.f), fmaxf(acc[1] + bias1[ct][1], 0.f));
-                h.y = f2bf2(fmaxf(acc[2] + bias1[ct][2], 0.f), fmaxf(acc[3] + bias1[ct][3], 0.f));
+                h.x = relu_bf2(f2bf2(acc[0] + bias1[ct][0], acc[1] + bias1[ct][1]));
+                h.y = relu_bf2(f2bf2(acc[2] + bias1[ct][2], acc[3] + bias1[ct][3]));
                 *reinterpret_cast<uint2 *>(&H1s[(rt * 16 + lc) * kH1Row + wn + ct * 16 + (lane >> 4) * 4]) = h;
             }
         }
@@ -546,8 +555,8 @@ __global__ __launch_bounds__(64 * NW) void k_infer(const float *x, int64_t rows,
                     // the bf16 rounding of H2, two units per conversion, and
                     // their products with the output weights as one bf16 dot
                     // product per output
-                    const bf16x2_t q = __builtin_bit_cast(bf16x2_t, f2bf2(fmaxf(acc[ct][i] + bias2[ct][i], 0.f),
-                                                                      fmaxf(acc[ct][i + 1] + bias2[ct][i + 1], 0.f)));
+                    const bf16x2_t q = __builtin_bit_cast(
+                        bf16x2_t, relu_bf2(f2bf2(acc[ct][i] + bias2[ct][i], acc[ct][i + 1] + bias2[ct][i + 1])));
                     s0 = __builtin_amdgcn_fdot2_f32_bf16(q, w30[ct][i / 2], s0, false);
                     s1 = __builtin_amdgcn_fdot2_f32_bf16(q, w31[ct][i / 2], s1, false);
                 }
