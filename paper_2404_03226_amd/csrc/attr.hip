@@ -300,9 +300,11 @@ __device__ __forceinline__ void add_rungs(int32_t *hist, int32_t cnt1, int32_t l
 }
 
 // The outputs of one row: IA/IE for an attribute call, else the simulation
-// record (an "unscheduled" record when the DAG's estimates failed).
-__device__ __forceinline__ void write_row(const AttrArgs &a, const AttrOut &o, const DagDesc &d, int32_t v,
-                                          int32_t e0, int32_t deg, int32_t tau, int32_t ie, bool failed) {
+// record and dependency word (w0, the row's initial word) -- or an
+// "unscheduled" record when the DAG's estimates failed.
+__device__ __forceinline__ void write_row_w(const AttrArgs &a, const AttrOut &o, const DagDesc &d, int32_t v,
+                                            int32_t e0, int32_t deg, int32_t tau, int32_t ie, unsigned long long w0,
+                                            bool failed = false) {
     const int64_t ub = d.toff - a.base;
     if (o.sim_init) {
         const int64_t t = d.toff + v;
@@ -311,7 +313,7 @@ __device__ __forceinline__ void write_row(const AttrArgs &a, const AttrOut &o, c
             memset(&rec, 0, sizeof rec);
             rec.qpos = -1;
         } else {
-            o.dep[t] = a.word0[t];
+            o.dep[t] = w0;
             rec.word = 0;
             rec.iev = ie;
             rec.qpos = -1;
@@ -325,6 +327,11 @@ __device__ __forceinline__ void write_row(const AttrArgs &a, const AttrOut &o, c
         if (o.ia_out) o.ia_out[ub + v] = deg;
         if (o.ie_out) o.ie_out[ub + v] = ie;
     }
+}
+__device__ __forceinline__ void write_row(const AttrArgs &a, const AttrOut &o, const DagDesc &d, int32_t v,
+                                          int32_t e0, int32_t deg, int32_t tau, int32_t ie, bool failed) {
+    const unsigned long long w0 = o.sim_init && !failed ? a.word0[d.toff + v] : 0ull;
+    write_row_w(a, o, d, v, e0, deg, tau, ie, w0, failed);
 }
 
 // Whether the call writes nothing for DAG d: a schedule skips a DAG whose
@@ -357,9 +364,9 @@ struct DagLds {
 // read while the current chunk is worked on.  Per row, `done` receives
 // (row, first edge, out-degree, count, least, largest) as chunk_scan defines
 // them.
-template <bool PASS_B, typename Done>
-__device__ __forceinline__ void dag_pass(const int32_t *r, const int32_t *c, int32_t n, const uint32_t *pks,
-                                         int32_t c0, int32_t stride, int64_t U, DagLds &L, Done done) {
+template <bool PASS_B, typename PK, typename Done>
+__device__ __forceinline__ void dag_pass(const int32_t *r, const int32_t *c, int32_t n, PK pks, int32_t c0,
+                                         int32_t stride, int64_t U, DagLds &L, Done done) {
     const int lane = lane_id();
     if (c0 >= n) return;
     // the current chunk: row offsets, degrees, prefix, first successors
@@ -407,9 +414,9 @@ __device__ __forceinline__ void dag_pass(const int32_t *r, const int32_t *c, int
                 int32_t q = 0;
 #pragma unroll
                 for (int step = 32; step >= 1; step >>= 1) q += L.pre[q + step] <= k ? step : 0;
-                const uint32_t pv = pks[sv[u]];
+                const uint32_t pv = pks(sv[u]);
                 if (k0 + u * kWave + lane < total && (pv & kRem1)) {
-                    const int32_t x = (int32_t)(pks[c0 + q] & ~kRem1) + (int32_t)(pv & ~kRem1);
+                    const int32_t x = (int32_t)(pks(c0 + q) & ~kRem1) + (int32_t)(pv & ~kRem1);
                     if (PASS_B) {
                         if ((int64_t)x <= U) atomicAdd(&L.cnt[q], 1);
                     } else {
@@ -441,52 +448,27 @@ __device__ __forceinline__ void dag_pass(const int32_t *r, const int32_t *c, int
     }
 }
 
-// One work-group per DAG: the DAG's task words in LDS, both passes and the
-// choice of U.  The DAGs taken are sorder[first + blockIdx.x]; dynamic LDS:
-// 4 bytes per task of the largest of them.
-template <bool HAS_REM, int TPB>
-__global__ __launch_bounds__(TPB) void k_attr_dag(AttrArgs a, AttrOut o, int32_t first) {
+// 16-bit copy of a task word for the per-DAG kernel's LDS: tau (saturated at
+// 2^15 - 1) in bits 0..14, rem == 1 in bit 15.  It is exact, and used, only
+// for DAGs whose largest tau is below 2^15 ticks.
+constexpr uint32_t kTau16 = 0x7FFF;
+__device__ __forceinline__ uint16_t word16(uint32_t w) {
+    return (uint16_t)(min(w & ~kRem1, kTau16) | ((w & kRem1) ? 0x8000u : 0u));
+}
+__device__ __forceinline__ uint32_t word32(uint32_t h) { return (h & kTau16) | (h & 0x8000u) << 16; }
+
+// Pass A, the choice of U and pass B of one DAG in the per-DAG kernel, with
+// the task words looked up through pk (LDS or the inputs).
+template <int TPB, typename PK>
+__device__ __forceinline__ void dag_passes(const AttrArgs &a, const AttrOut &o, const DagDesc &d, PK pk,
+                                           DagLds *dl, WaveSlots &ws, int32_t *hist) {
     constexpr int kDagThreads = TPB, kDagWaves = TPB / kWave;
-    extern __shared__ uint32_t pks[];
-    __shared__ DagLds dl[kDagWaves];
-    __shared__ WaveSlots ws;
-    __shared__ int32_t hist[kRungs];
-    const int tid = threadIdx.x, wv = tid / kWave, lane = tid & (kWave - 1);
-    const DagDesc d = a.desc[a.sorder[first + blockIdx.x]];
-    if (!o.sim_init && dev_load(a.anybad)) return;  // validated before: the call fails
-    if (tid < kRungs) hist[tid] = 0;
-    if (tid == 0) ws.bad = 0;
-    uint32_t tmax = 0;
-    unsigned long long tsum = 0;
-    bool bad = false;
-    constexpr int kTW = 4;  // task words loaded per thread at a time
-    for (int32_t v0 = tid; v0 < d.n; v0 += kTW * kDagThreads) {
-        uint32_t w[kTW];
-        bool b[kTW];
-#pragma unroll
-        for (int k = 0; k < kTW; k++) w[k] = task_word<HAS_REM>(a, d, min(v0 + k * kDagThreads, d.n - 1), b[k]);
-#pragma unroll
-        for (int k = 0; k < kTW; k++) {
-            if (v0 + k * kDagThreads >= d.n) continue;
-            pks[v0 + k * kDagThreads] = w[k];
-            bad |= b[k];
-            tmax = max(tmax, w[k] & ~kRem1);
-            tsum += w[k] & ~kRem1;
-        }
-    }
-    tmax = wave_max_u32(tmax);
-    tsum = wave_sum_u64(tsum);
-    if (ballot(bad) && lane == 0) ws.bad = 1;
-    if (lane == 0) {
-        ws.wmax[wv] = tmax;
-        ws.wsum[wv] = tsum;
-    }
-    __syncthreads();
+    const int tid = threadIdx.x, wv = tid / kWave;
     const int32_t *r = a.rp + d.toff + d.id;
     const int32_t *c = a.col + d.eoff;
     const bool ability = a.unit_time == 0;
     uint32_t *srow = a.srow + d.toff;
-    dag_pass<false>(r, c, d.n, pks, wv * kWave, kDagThreads, 0, dl[wv],
+    dag_pass<false>(r, c, d.n, pk, wv * kWave, kDagThreads, 0, dl[wv],
                     [&](int32_t v, int32_t, int32_t deg, int32_t cnt, int32_t lo, int32_t hi) {
                         if (v < d.n && ability) {
                             add_rungs(hist, cnt, lo, hi, deg);
@@ -515,30 +497,106 @@ __global__ __launch_bounds__(TPB) void k_attr_dag(AttrArgs a, AttrOut o, int32_t
     const int32_t U = a.u[d.id];
     if (ability) {
         // U = 2^j from the ladder: a row per thread, IE from its decision
-        // word; a row that U splits counts its successors itself
+        // word; a row that U splits counts its successors itself.  Each
+        // thread loads kRB rows' words before it uses any of them.
+        constexpr int kRB = 4;
         const int j = __builtin_ctz((uint32_t)U);
-        for (int32_t v = tid; v < d.n; v += kDagThreads) {
-            const uint32_t w = srow[v];
-            const int32_t e0 = r[v], deg = r[v + 1] - e0;
-            const int32_t tv = (int32_t)(pks[v] & ~kRem1);
-            const int32_t cnt = (int32_t)(w & 0x3FFFFF), jl = (int32_t)(w >> 22 & 31), jh = (int32_t)(w >> 27);
-            int32_t ie = 0;
-            if (cnt > 0 && jh <= j) {
-                ie = cnt;
-            } else if (cnt > 0 && jl <= j) {
-                for (int32_t e = e0; e < e0 + deg; e++) {
-                    const uint32_t pv = pks[c[e]];
-                    if ((pv & kRem1) && (int64_t)tv + (int32_t)(pv & ~kRem1) <= (int64_t)U) ie++;
-                }
+        for (int32_t v0 = tid; v0 < d.n; v0 += kRB * kDagThreads) {
+            uint32_t sw[kRB];
+            int32_t e0[kRB], e1[kRB];
+            unsigned long long w0[kRB];
+#pragma unroll
+            for (int k = 0; k < kRB; k++) {
+                const int32_t vv = min(v0 + k * kDagThreads, d.n - 1);
+                sw[k] = srow[vv];
+                e0[k] = r[vv];
+                e1[k] = r[vv + 1];
+                w0[k] = o.sim_init ? a.word0[d.toff + vv] : 0ull;
             }
-            write_row(a, o, d, v, e0, deg, tv, ie, false);
+#pragma unroll
+            for (int k = 0; k < kRB; k++) {
+                const int32_t v = v0 + k * kDagThreads;
+                if (v >= d.n) break;
+                const uint32_t w = sw[k];
+                const int32_t tv = (int32_t)(pk(v) & ~kRem1);
+                const int32_t cnt = (int32_t)(w & 0x3FFFFF), jl = (int32_t)(w >> 22 & 31), jh = (int32_t)(w >> 27);
+                int32_t ie = 0;
+                if (cnt > 0 && jh <= j) {
+                    ie = cnt;
+                } else if (cnt > 0 && jl <= j) {
+                    for (int32_t e = e0[k]; e < e1[k]; e++) {
+                        const uint32_t pv = pk(c[e]);
+                        if ((pv & kRem1) && (int64_t)tv + (int32_t)(pv & ~kRem1) <= (int64_t)U) ie++;
+                    }
+                }
+                write_row_w(a, o, d, v, e0[k], e1[k] - e0[k], tv, ie, w0[k]);
+            }
         }
         return;
     }
-    dag_pass<true>(r, c, d.n, pks, wv * kWave, kDagThreads, U, dl[wv],
+    dag_pass<true>(r, c, d.n, pk, wv * kWave, kDagThreads, U, dl[wv],
                    [&](int32_t v, int32_t e0, int32_t deg, int32_t cnt, int32_t, int32_t) {
-                       if (v < d.n) write_row(a, o, d, v, e0, deg, (int32_t)(pks[v] & ~kRem1), cnt, false);
+                       if (v < d.n) write_row(a, o, d, v, e0, deg, (int32_t)(pk(v) & ~kRem1), cnt, false);
                    });
+}
+
+// One work-group per DAG: the DAG's task words in LDS, both passes and the
+// choice of U.  The words take 16 bits each and the kernel at most 64 VGPRs,
+// so that two work-groups of the largest DAGs (eight of the smaller ones)
+// share a CU; a DAG with a tau of 2^15 ticks or more looks its task words up
+// from the inputs instead.  The DAGs taken are sorder[first + blockIdx.x];
+// dynamic LDS: 2 bytes per task of the largest of them.
+template <bool HAS_REM, int TPB>
+__global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(8))) void k_attr_dag(AttrArgs a, AttrOut o,
+                                                                                         int32_t first) {
+    constexpr int kDagThreads = TPB, kDagWaves = TPB / kWave;
+    extern __shared__ uint16_t pks16[];
+    __shared__ DagLds dl[kDagWaves];
+    __shared__ WaveSlots ws;
+    __shared__ int32_t hist[kRungs];
+    const int tid = threadIdx.x, wv = tid / kWave, lane = tid & (kWave - 1);
+    const DagDesc d = a.desc[a.sorder[first + blockIdx.x]];
+    if (!o.sim_init && dev_load(a.anybad)) return;  // validated before: the call fails
+    if (tid < kRungs) hist[tid] = 0;
+    if (tid == 0) ws.bad = 0;
+    uint32_t tmax = 0;
+    unsigned long long tsum = 0;
+    bool bad = false;
+    constexpr int kTW = 4;  // task words loaded per thread at a time
+    for (int32_t v0 = tid; v0 < d.n; v0 += kTW * kDagThreads) {
+        uint32_t w[kTW];
+        bool b[kTW];
+#pragma unroll
+        for (int k = 0; k < kTW; k++) w[k] = task_word<HAS_REM>(a, d, min(v0 + k * kDagThreads, d.n - 1), b[k]);
+#pragma unroll
+        for (int k = 0; k < kTW; k++) {
+            if (v0 + k * kDagThreads >= d.n) continue;
+            pks16[v0 + k * kDagThreads] = word16(w[k]);
+            bad |= b[k];
+            tmax = max(tmax, w[k] & ~kRem1);
+            tsum += w[k] & ~kRem1;
+        }
+    }
+    tmax = wave_max_u32(tmax);
+    tsum = wave_sum_u64(tsum);
+    if (ballot(bad) && lane == 0) ws.bad = 1;
+    if (lane == 0) {
+        ws.wmax[wv] = tmax;
+        ws.wsum[wv] = tsum;
+    }
+    __syncthreads();
+    uint32_t m = 0;
+    for (int w = 0; w < kDagWaves; w++) m = max(m, ws.wmax[w]);
+    if (m <= kTau16) {
+        dag_passes<TPB>(a, o, d, [&](int32_t s) { return word32(pks16[s]); }, dl, ws, hist);
+    } else {
+        dag_passes<TPB>(a, o, d,
+                        [&](int32_t s) {
+                            bool b;
+                            return task_word<HAS_REM>(a, d, s, b);
+                        },
+                        dl, ws, hist);
+    }
 }
 
 // ---- grid pass over one large DAG -------------------------------------
@@ -875,8 +933,8 @@ int run_attributes(insp_dag *dag, Workspace *ws, const int32_t *est, int32_t uni
         int32_t n_big = 0;
         while (n_big < ws->n_small && ws->h_desc[ws->h_sorder[n_big]].n > kMidTasks) n_big++;
         const int32_t n_mid = ws->n_small - n_big;
-        const size_t lds_big = 4 * (size_t)std::max(ws->max_small, 1);
-        const size_t lds_mid = 4 * (size_t)std::max(n_mid > 0 ? ws->h_desc[ws->h_sorder[n_big]].n : 1, 1);
+        const size_t lds_big = 4 * (((size_t)std::max(ws->max_small, 1) + 1) / 2);
+        const size_t lds_mid = 4 * (((size_t)std::max(n_mid > 0 ? ws->h_desc[ws->h_sorder[n_big]].n : 1, 1) + 1) / 2);
         if (rem) {
             if (n_big > 0) {
                 if (int rc = set_lds_limit((const void *)&k_attr_dag<true, kDagThreads>, lds_big)) return rc;

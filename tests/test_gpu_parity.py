@@ -176,6 +176,39 @@ def _hub_dag(seed, n, hubs):
               type=np.zeros(n, np.int32), name=f"hubs-{n}")
 
 
+@pytest.mark.parametrize("hi", [32767, 32768])
+def test_per_dag_pass_at_the_16_bit_word_limit(insp, hi):
+    """The per-DAG kernel keeps 16-bit task words in LDS when every tau is
+    below 2^15 ticks and looks them up from the inputs otherwise: taus just
+    below and at that limit, sums of two taus around the explicit U, both
+    work-group sizes, the ladder U, a given rem, and a schedule, against the
+    oracle."""
+    import torch
+    for sel in (1, 0):  # 1,529 and 5,477 tasks: 256- and 1024-thread work-groups
+        w = synth.cfg3(select=[sel])[0]
+        st = synth.Stream(sel, 5)
+        est = (hi - st.randint(np.arange(2 * w.n), 0, 40)).astype(np.int32).reshape(w.n, 2)
+        est[0] = hi
+        w = synth.Workload(w.name, w.n, w.row_ptr, w.col, w.type, est.copy(), est, w.n_cpu, w.n_gpu)
+        say("16-bit word limit", w.name, w.n, hi)
+        dag, dur, est_d = insp.to_device(w)
+        rp, col = oracle.canon(w.n, w.row_ptr, w.col)
+        for n_gpu in (0, 4):
+            for U in (0, 2 * hi - 40, 2 * hi - 20, 2 * hi - 1):
+                ia, ie, Ug = insp.attributes(dag, 0, est_d, (16, n_gpu), unit_time=U)
+                ria, rie, rU = oracle.attributes(w.n, rp, col, w.est, n_gpu, unit_time=U)
+                assert Ug[0] == rU, (sel, n_gpu, U)
+                assert np.array_equal(ia.cpu().numpy(), ria) and np.array_equal(ie.cpu().numpy(), rie), (sel, n_gpu, U)
+        finished = st.uniform(np.arange(w.n)) < 0.3
+        src = np.repeat(np.arange(w.n), np.diff(rp))
+        rem = np.bincount(col[~finished[src]], minlength=w.n).astype(np.int32)
+        ia, ie, Ug = insp.attributes(dag, 0, est_d, (16, 4), unit_time=0, rem=torch.from_numpy(rem).cuda())
+        ria, rie, rU = oracle.attributes(w.n, rp, col, w.est, 4, rem=rem)
+        assert Ug[0] == rU and np.array_equal(ie.cpu().numpy(), rie)
+        dag.free()
+        assert_same(run_gpu(insp, w), oracle.schedule(w, variant=oracle.HEAP), w.name)
+
+
 @pytest.mark.parametrize("case", ["hubs", "powerlaw"])
 def test_grid_attribute_pass_with_hub_rows(insp, case):
     # DAGs of at least 32,768 tasks take the grid-wide attribute pass, where
