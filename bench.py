@@ -239,7 +239,7 @@ def main():
         log(f"warmup step {i + 1}/{args.warmup} done")
     inspirit.sync_status(dag)
     torch.cuda.synchronize()
-    inspirit.profile_enable(True)
+    inspirit.profile_enable(2)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     ev0.record(stream)
@@ -397,7 +397,7 @@ def attr_measure(dag, workers, b, est, steps=7, warmup=3):
     for mode in ("warm", "cold"):
         for _ in range(warmup):
             inspirit.attributes(dag, inspirit.ALL_DAGS, est, workers)
-        inspirit.profile_enable(True)
+        inspirit.profile_enable(2)
         for _ in range(steps):
             if mode == "cold":
                 flush.fill_(1)
@@ -425,7 +425,7 @@ def transitive_measure(dag, workers, ws, b, dur, est, steps, warmup, tune_key):
     N = int(b.task_off[-1])
     for _ in range(max(warmup, 1)):
         ia, ie, U, lp = inspirit.transitive_attributes(dag, inspirit.ALL_DAGS, est, workers)
-    inspirit.profile_enable(True)
+    inspirit.profile_enable(2)
     t0 = time.time()
     for _ in range(steps):
         ia, ie, U, lp = inspirit.transitive_attributes(dag, inspirit.ALL_DAGS, est, workers)
@@ -445,7 +445,7 @@ def transitive_measure(dag, workers, ws, b, dur, est, steps, warmup, tune_key):
     stream = torch.cuda.current_stream()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
-    inspirit.profile_enable(True)
+    inspirit.profile_enable(2)
     ev0.record(stream)
     for _ in range(steps):
         inspirit.schedule_batch(dag, workers, dur, est, prm, tune_key=tune_key, out=out)

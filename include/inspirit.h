@@ -370,8 +370,11 @@ int insp_sync_status(const insp_dag *dag, void *stream);
  * stream; insp_profile_read waits for the recorded events and returns the
  * summed elapsed time and launch count of the kernels whose name starts with
  * `kernel` ("sim", "attr_a", "attr_b", "attr_select", "" for all).
- * insp_profile_enable(0) stops recording and drops pending records.  The
- * recorder is process-wide and not meant for concurrent streams.
+ * insp_profile_enable(0) stops recording and drops pending records;
+ * insp_profile_enable(2) records only the outermost scope of each call (the
+ * whole attribute pass, the simulation, the unpacking), so that no event
+ * record sits between the kernels it brackets.  The recorder is process-wide
+ * and not meant for concurrent streams.
  */
 int insp_profile_enable(int on);
 int insp_profile_read(const char *kernel, double *total_ms, int64_t *launches);

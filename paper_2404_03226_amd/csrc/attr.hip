@@ -30,14 +30,14 @@
 //     and largest tau(v) + tau(s)), and pass B takes a row per thread, reading
 //     the successors only of rows whose span U splits.
 //   - k_attr_pack / k_attr_big_a / k_attr_big_sel / k_attr_big_b: one large
-//     DAG over a persistent grid: its task words packed to one array, pass A
-//     leaving a summary per row (count of rem == 1 successors, least and
-//     largest tau(v) + tau(s)) and a partial score per work-group, U from
-//     the partial scores, then pass B deciding IE from the summary for every
-//     row whose count U does not split.  Rows with more than kHubDeg
-//     successors (listed once per handle, largest first) get a wave each,
-//     or one per kPiece successors when longer than kPieceMin; the select
-//     kernel combines the pieces.
+//     DAG over a persistent grid: its task words packed to one array (and a
+//     16-bit copy for the gathers), pass A leaving a summary per row (count
+//     of rem == 1 successors, least and largest tau(v) + tau(s)) and a
+//     partial score per work-group, U from the partial scores, then pass B
+//     deciding IE from the summary for every row whose count U does not
+//     split.  Rows with more than kHubDeg successors (listed once per handle,
+//     largest first) get a wave each, or one per kPiece successors when
+//     longer than kPieceMin; the select kernel combines the pieces.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -457,6 +457,22 @@ __device__ __forceinline__ uint16_t word16(uint32_t w) {
 }
 __device__ __forceinline__ uint32_t word32(uint32_t h) { return (h & kTau16) | (h & 0x8000u) << 16; }
 
+// The grid pass keeps a 16-bit copy of the large DAG's task words beside the
+// 32-bit ones (in the decision-word scratch of its own rows, which only the
+// per-DAG kernel uses), so that the successor gathers of pass A touch half
+// the bytes; a saturated copy sends the lookup to the 32-bit word.
+__device__ __forceinline__ uint16_t *pk16_of(const AttrArgs &a, const DagDesc &d) {
+    return reinterpret_cast<uint16_t *>(a.srow + d.toff);
+}
+struct GridWords {
+    const uint32_t *pkg;
+    const uint16_t *p16;
+    __device__ uint32_t operator()(int32_t s) const {
+        const uint32_t h = p16[s];
+        return (h & kTau16) == kTau16 ? pkg[s] : word32(h);
+    }
+};
+
 // Pass A, the choice of U and pass B of one DAG in the per-DAG kernel, with
 // the task words looked up through pk (LDS or the inputs).
 template <int TPB, typename PK>
@@ -620,6 +636,7 @@ __global__ __launch_bounds__(kBigThreads) void k_attr_pack(AttrArgs a, int32_t d
         bool b;
         const uint32_t w = task_word<HAS_REM>(a, d, v, b);
         a.pkg[v] = w;
+        pk16_of(a, d)[v] = word16(w);
         bad |= b;
         tmax = max(tmax, w & ~kRem1);
         tsum += w & ~kRem1;
@@ -663,7 +680,7 @@ __device__ void scan_hub(const AttrArgs &a, const DagDesc &d, int32_t e0, int32_
 #pragma unroll
         for (int u = 0; u < kWin; u++) sv[u] = c[min(b + u * kWave + lane, e1 - 1)];
 #pragma unroll
-        for (int u = 0; u < kWin; u++) pv[u] = a.pkg[sv[u]];
+        for (int u = 0; u < kWin; u++) pv[u] = GridWords{a.pkg, pk16_of(a, d)}(sv[u]);
 #pragma unroll
         for (int u = 0; u < kWin; u++) {
             const int32_t x = tv + (int32_t)(pv[u] & ~kRem1);
@@ -687,7 +704,8 @@ __device__ void scan_hub(const AttrArgs &a, const DagDesc &d, int32_t e0, int32_
 // Pass A: each wave takes 64-row chunks (hub rows left out), then hub rows
 // (largest first), in grid stride, and leaves each row's summary in `summ`;
 // each block leaves its score histogram in its partial slot.
-__global__ __launch_bounds__(kBigThreads) void k_attr_big_a(AttrArgs a, int32_t di) {
+__global__ __launch_bounds__(kBigThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_attr_big_a(AttrArgs a,
+                                                                                                  int32_t di) {
     __shared__ ChunkLds cl[kBigWaves];
     __shared__ int32_t hist[kRungs];
     const int tid = threadIdx.x, wv = tid / kWave, lane = tid & (kWave - 1);
@@ -699,7 +717,7 @@ __global__ __launch_bounds__(kBigThreads) void k_attr_big_a(AttrArgs a, int32_t 
     const int32_t *r = a.rp + d.toff + d.id;
     const int32_t *c = a.col + d.eoff;
     const uint32_t *pkg = a.pkg;
-    auto pk = [&](int32_t s) { return pkg[s]; };
+    const GridWords pk{pkg, pk16_of(a, d)};
     for (int32_t p = w0; p < d.nhub; p += nw) {
         const int4 h = a.hub[d.hub0 + p];  // row, piece, pieces, first piece slot
         const int32_t v = h.x, e0 = r[v], e1 = r[v + 1];
@@ -753,12 +771,19 @@ __global__ __launch_bounds__(kSelThreads) void k_attr_big_sel(AttrArgs a, int32_
     for (int32_t p = tid; p < d.nlong; p += kSelThreads) {
         const int4 h = a.lrow[d.long0 + p];  // row, 0, pieces, first slot
         int32_t c1 = 0, lo = INT_MAX, hi = 0;
-        for (int32_t k = 0; k < h.z; k++) {
-            const int4 x = reinterpret_cast<const int4 *>(a.pslot)[h.w + k];
-            c1 += x.x;
-            if (x.x > 0) {
-                lo = min(lo, x.y);
-                hi = max(hi, x.z);
+        // the pieces' partials kPL at a time, their loads issued together
+        constexpr int kPL = 8;
+        for (int32_t k0 = 0; k0 < h.z; k0 += kPL) {
+            int4 x[kPL];
+#pragma unroll
+            for (int k = 0; k < kPL; k++) x[k] = reinterpret_cast<const int4 *>(a.pslot)[h.w + min(k0 + k, h.z - 1)];
+#pragma unroll
+            for (int k = 0; k < kPL; k++) {
+                if (k0 + k < h.z && x[k].x > 0) {
+                    c1 += x[k].x;
+                    lo = min(lo, x[k].y);
+                    hi = max(hi, x[k].z);
+                }
             }
         }
         a.summ[h.x] = pack_summary(c1, lo, hi);
@@ -785,9 +810,12 @@ __global__ __launch_bounds__(kSelThreads) void k_attr_big_sel(AttrArgs a, int32_
         sm += (unsigned long long)(uint32_t)xs[25] | (unsigned long long)(uint32_t)xs[26] << 32;
         b2 |= xs[27] != 0;
     }
+    // a wave's sums first: one LDS atomic per rung and wave
 #pragma unroll
-    for (int j = 0; j < kRungs; j++)
-        if (hs[j]) atomicAdd(&hist[j], hs[j]);
+    for (int j = 0; j < kRungs; j++) {
+        const int32_t t = wave_sum_i32(hs[j]);
+        if (lane == 0 && t) atomicAdd(&hist[j], t);
+    }
     m = wave_max_u32(m);
     sm = wave_sum_u64(sm);
     if (ballot(b2) && lane == 0) ws.bad = 1;
@@ -825,7 +853,7 @@ __global__ __launch_bounds__(kBigThreads) void k_attr_big_b(AttrArgs a, AttrOut 
     const int32_t *r = a.rp + d.toff + d.id;
     const int32_t *c = a.col + d.eoff;
     const uint32_t *pkg = a.pkg;
-    auto pk = [&](int32_t s) { return pkg[s]; };
+    const GridWords pk{pkg, pk16_of(a, d)};
     for (int32_t p = w0; p < d.nhub; p += nw) {
         const int4 h = a.hub[d.hub0 + p];
         if (h.y != 0) continue;  // a row's first piece writes it

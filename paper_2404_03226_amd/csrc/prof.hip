@@ -19,7 +19,7 @@ struct Rec {
 
 struct Prof {
     std::mutex mu;
-    bool on = false;
+    int on = 0;  // 0 off, 1 every scope, 2 outermost scopes only
     std::vector<Rec> pending;
     std::vector<hipEvent_t> pool;
     std::vector<std::pair<std::string, std::pair<double, int64_t>>> done;
@@ -63,14 +63,17 @@ Prof &prof() {
 
 // Marks are not recorded while this thread captures a graph.
 static thread_local int t_suspended = 0;
+// Nesting depth of this thread's scopes (mode 2 records the outermost only).
+static thread_local int t_depth = 0;
 
 void prof_suspend(bool on) { t_suspended += on ? 1 : -1; }
 
 void prof_mark(hipStream_t st, const char *kernel, bool begin) {
+    const int depth = begin ? ++t_depth : t_depth--;
     if (t_suspended) return;
     Prof &p = prof();
     std::lock_guard<std::mutex> g(p.mu);
-    if (!p.on) return;
+    if (p.on == 0 || (p.on == 2 && depth != 1)) return;
     if (begin) {
         Rec r;
         r.name = kernel;
@@ -102,7 +105,7 @@ extern "C" int insp_profile_enable(int on) {
         p.pending.clear();
         p.done.clear();
     }
-    p.on = on != 0;
+    p.on = on == 2 ? 2 : (on != 0 ? 1 : 0);
     return INSP_OK;
 }
 

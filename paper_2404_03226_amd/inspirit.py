@@ -397,7 +397,10 @@ def sync_status(dag: Dag, stream=None):
 
 
 def profile_enable(on=True):
-    _check(load().insp_profile_enable(1 if on else 0))
+    """True or 1: time every library scope; 2: only the outermost scope of
+    each call (no event records between the kernels it brackets); False/0: off."""
+    mode = 1 if on is True else 0 if on is False else int(on)
+    _check(load().insp_profile_enable(mode))
 
 
 def profile_read(kernel=""):
