@@ -91,7 +91,8 @@ struct AttrArgs {
     int64_t tasks;
     int32_t count;
     int32_t unit_time;
-    int32_t *maxtau, *score, *u, *taubar, *done;
+    int32_t *maxtau;  // per DAG: a large DAG's largest tau when above kTau8, else 0
+    int32_t *score, *u, *taubar, *done;
     int32_t *stat;    // this call's status words (stride 2)
     int32_t *sticky;  // schedule calls: failures of earlier calls kept for insp_sync_status (nullable)
     int32_t *anybad;  // [1]: some DAG of the call has an estimate out of range
@@ -112,6 +113,7 @@ __global__ void k_attr_clear(AttrArgs a) {
     if (i >= a.count) return;
     int32_t id = a.desc[i].id;
     a.done[id] = 0;
+    a.maxtau[id] = 0;
     a.u[id] = a.unit_time > 0 ? a.unit_time : 1;
     a.taubar[id] = 1;
     // a schedule call keeps the previous call's failures until they are
@@ -457,12 +459,22 @@ __device__ __forceinline__ uint16_t word16(uint32_t w) {
 }
 __device__ __forceinline__ uint32_t word32(uint32_t h) { return (h & kTau16) | (h & 0x8000u) << 16; }
 
-// The grid pass keeps a 16-bit copy of the large DAG's task words beside the
-// 32-bit ones (in the decision-word scratch of its own rows, which only the
-// per-DAG kernel uses), so that the successor gathers of pass A touch half
-// the bytes; a saturated copy sends the lookup to the 32-bit word.
+// The grid pass keeps narrow copies of the large DAG's task words beside the
+// 32-bit ones, in the decision-word scratch of its own rows (4 bytes per row,
+// which only the per-DAG kernel uses): 16 bits at byte 0 and 8 bits (tau
+// saturated at kTau8, rem == 1 in bit 7) at byte 2n.  When no tau of the DAG
+// exceeds kTau8 the gathers of both passes read the 8-bit copy (a 2 MB array
+// for 2M tasks, which the L2 holds), otherwise the 16-bit one, a saturated
+// entry sending the lookup to the 32-bit word.
+constexpr uint32_t kTau8 = 0x7E;
+__device__ __forceinline__ uint8_t word8(uint32_t w) {
+    return (uint8_t)(min(w & ~kRem1, kTau8 + 1) | ((w & kRem1) ? 0x80u : 0u));
+}
 __device__ __forceinline__ uint16_t *pk16_of(const AttrArgs &a, const DagDesc &d) {
     return reinterpret_cast<uint16_t *>(a.srow + d.toff);
+}
+__device__ __forceinline__ uint8_t *pk8_of(const AttrArgs &a, const DagDesc &d) {
+    return reinterpret_cast<uint8_t *>(a.srow + d.toff) + 2 * (int64_t)d.n;
 }
 struct GridWords {
     const uint32_t *pkg;
@@ -470,6 +482,13 @@ struct GridWords {
     __device__ uint32_t operator()(int32_t s) const {
         const uint32_t h = p16[s];
         return (h & kTau16) == kTau16 ? pkg[s] : word32(h);
+    }
+};
+struct GridBytes {
+    const uint8_t *p8;
+    __device__ uint32_t operator()(int32_t s) const {
+        const uint32_t h = p8[s];
+        return (h & 0x7Fu) | (h & 0x80u) << 24;
     }
 };
 
@@ -629,6 +648,9 @@ __global__ __launch_bounds__(kBigThreads) void k_attr_pack(AttrArgs a, int32_t d
     const DagDesc d = a.desc[di];
     if (tid == 0) ws.bad = 0;
     __syncthreads();
+    // partial slots past the grid read as zero in the select kernel
+    for (int32_t i = gridDim.x + blockIdx.x; i < kBigGrid; i += gridDim.x)
+        if (tid < 32) a.part[32 * (int64_t)i + tid] = 0;
     uint32_t tmax = 0;
     unsigned long long tsum = 0;
     bool bad = false;
@@ -637,6 +659,7 @@ __global__ __launch_bounds__(kBigThreads) void k_attr_pack(AttrArgs a, int32_t d
         const uint32_t w = task_word<HAS_REM>(a, d, v, b);
         a.pkg[v] = w;
         pk16_of(a, d)[v] = word16(w);
+        pk8_of(a, d)[v] = word8(w);
         bad |= b;
         tmax = max(tmax, w & ~kRem1);
         tsum += w & ~kRem1;
@@ -656,6 +679,7 @@ __global__ __launch_bounds__(kBigThreads) void k_attr_pack(AttrArgs a, int32_t d
             m = max(m, ws.wmax[w]);
             sm += ws.wsum[w];
         }
+        if (m > kTau8 && dev_load(&a.maxtau[d.id]) < (int32_t)m) atomicMax(&a.maxtau[d.id], (int32_t)m);
         int32_t *slot = a.part + 32 * blockIdx.x;
         slot[24] = (int32_t)m;
         slot[25] = (int32_t)(uint32_t)sm;
@@ -667,8 +691,8 @@ __global__ __launch_bounds__(kBigThreads) void k_attr_pack(AttrArgs a, int32_t d
 // A hub row (more than kHubDeg successors), one wave: the row's successors
 // kWin * 64 at a time.  Pass A: count of rem == 1 successors and the
 // extremes of tau(v) + tau(s); pass B: the count within U.
-template <bool PASS_B>
-__device__ void scan_hub(const AttrArgs &a, const DagDesc &d, int32_t e0, int32_t e1, int32_t tv, int64_t U,
+template <bool PASS_B, typename PK>
+__device__ void scan_hub(const AttrArgs &a, const DagDesc &d, PK pk, int32_t e0, int32_t e1, int32_t tv, int64_t U,
                          int32_t *cnt, int32_t *lo, int32_t *hi) {
     const int lane = lane_id();
     const int32_t *c = a.col + d.eoff;
@@ -680,7 +704,7 @@ __device__ void scan_hub(const AttrArgs &a, const DagDesc &d, int32_t e0, int32_
 #pragma unroll
         for (int u = 0; u < kWin; u++) sv[u] = c[min(b + u * kWave + lane, e1 - 1)];
 #pragma unroll
-        for (int u = 0; u < kWin; u++) pv[u] = GridWords{a.pkg, pk16_of(a, d)}(sv[u]);
+        for (int u = 0; u < kWin; u++) pv[u] = pk(sv[u]);
 #pragma unroll
         for (int u = 0; u < kWin; u++) {
             const int32_t x = tv + (int32_t)(pv[u] & ~kRem1);
@@ -703,27 +727,21 @@ __device__ void scan_hub(const AttrArgs &a, const DagDesc &d, int32_t e0, int32_
 
 // Pass A: each wave takes 64-row chunks (hub rows left out), then hub rows
 // (largest first), in grid stride, and leaves each row's summary in `summ`;
-// each block leaves its score histogram in its partial slot.
-__global__ __launch_bounds__(kBigThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_attr_big_a(AttrArgs a,
-                                                                                                  int32_t di) {
-    __shared__ ChunkLds cl[kBigWaves];
-    __shared__ int32_t hist[kRungs];
+// the block's score histogram goes to `hist`.  Task words through pk.
+template <typename PK>
+__device__ __forceinline__ void big_pass_a(const AttrArgs &a, const DagDesc &d, PK pk, ChunkLds *cl, int32_t *hist) {
     const int tid = threadIdx.x, wv = tid / kWave, lane = tid & (kWave - 1);
-    const DagDesc d = a.desc[di];
-    if (tid < kRungs) hist[tid] = 0;
-    __syncthreads();
     const int32_t nw = gridDim.x * kBigWaves, w0 = blockIdx.x * kBigWaves + wv;
     const int32_t skip = d.nhub > 0 ? kHubDeg : INT_MAX;
     const int32_t *r = a.rp + d.toff + d.id;
     const int32_t *c = a.col + d.eoff;
     const uint32_t *pkg = a.pkg;
-    const GridWords pk{pkg, pk16_of(a, d)};
     for (int32_t p = w0; p < d.nhub; p += nw) {
         const int4 h = a.hub[d.hub0 + p];  // row, piece, pieces, first piece slot
         const int32_t v = h.x, e0 = r[v], e1 = r[v + 1];
         const int32_t pe0 = e0 + h.y * kPiece, pe1 = h.z > 1 ? min(e1, pe0 + kPiece) : e1;
         int32_t cnt, lo, hi;
-        scan_hub<false>(a, d, pe0, pe1, (int32_t)(pkg[v] & ~kRem1), 0, &cnt, &lo, &hi);
+        scan_hub<false>(a, d, pk, pe0, pe1, (int32_t)(pkg[v] & ~kRem1), 0, &cnt, &lo, &hi);
         if (lane == 0) {
             if (h.z > 1) {
                 // one piece of a long row: combined by the select kernel
@@ -751,6 +769,20 @@ __global__ __launch_bounds__(kBigThreads) __attribute__((amdgpu_waves_per_eu(8))
             if (a.unit_time == 0) add_rungs(hist, cnt, lo, hi, deg);
         }
     }
+}
+
+// Pass A over the grid; each block leaves its score histogram in its
+// partial slot.
+__global__ __launch_bounds__(kBigThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_attr_big_a(AttrArgs a,
+                                                                                                  int32_t di) {
+    __shared__ ChunkLds cl[kBigWaves];
+    __shared__ int32_t hist[kRungs];
+    const int tid = threadIdx.x;
+    const DagDesc d = a.desc[di];
+    if (tid < kRungs) hist[tid] = 0;
+    __syncthreads();
+    if (dev_load(&a.maxtau[d.id]) == 0) big_pass_a(a, d, GridBytes{pk8_of(a, d)}, cl, hist);
+    else big_pass_a(a, d, GridWords{a.pkg, pk16_of(a, d)}, cl, hist);
     __syncthreads();
     if (tid < kRungs) a.part[32 * blockIdx.x + tid] = hist[tid];
 }
@@ -762,75 +794,91 @@ constexpr int kSelThreads = 1024;
 __global__ __launch_bounds__(kSelThreads) void k_attr_big_sel(AttrArgs a, int32_t di, int32_t blocks) {
     __shared__ WaveSlots ws;
     __shared__ int32_t hist[kRungs];
-    const int tid = threadIdx.x, wv = tid / kWave, lane = tid & (kWave - 1);
+    const int tid = threadIdx.x;
     const DagDesc d = a.desc[di];
     if (tid < kRungs) hist[tid] = 0;
     if (tid == 0) ws.bad = 0;
     __syncthreads();
+    // every block's partial slot (rungs 0..23, then max tau, the tau sum's
+    // low and high words, the estimate flag), read along the slots: thread
+    // (g, j) combines word j of slots 64g .. 64g + 63 (all kBigGrid rows;
+    // the pack kernel zeroes those past the grid).  The first long row's
+    // descriptor is loaded with them, so that both wait for one round trip.
+    constexpr int kGroups = kSelThreads / 32, kU = kBigGrid / kGroups;
+    __shared__ long long colsum[kGroups][32];
+    int4 h0 = make_int4(0, 0, 0, 0);
+    if (tid < d.nlong) h0 = a.lrow[d.long0 + tid];  // row, 0, pieces, first slot
+    {
+        const int j = tid & 31, g = tid >> 5;
+        const uint32_t o = (uint32_t)(32 * g * kU + j);  // 32-bit offsets from the uniform base
+        int32_t x[kU];
+#pragma unroll
+        for (int u = 0; u < kU; u++) x[u] = a.part[o + 32u * u];
+        // 32-bit arithmetic (a sum of 32-bit words as the sums of their halves)
+        long long acc = 0;
+        if (j == 25 || j == 26) {
+            uint32_t lo16 = 0, hi16 = 0;
+#pragma unroll
+            for (int u = 0; u < kU; u++) {
+                lo16 += (uint32_t)x[u] & 0xFFFFu;
+                hi16 += (uint32_t)x[u] >> 16;
+            }
+            acc = (long long)lo16 + ((long long)hi16 << 16);
+        } else if (j == 24) {
+            uint32_t mx = 0;
+#pragma unroll
+            for (int u = 0; u < kU; u++) mx = max(mx, (uint32_t)x[u]);
+            acc = mx;
+        } else if (j == 27) {
+            int32_t any = 0;
+#pragma unroll
+            for (int u = 0; u < kU; u++) any |= x[u];
+            acc = any != 0;
+        } else {
+            int32_t t = 0;
+#pragma unroll
+            for (int u = 0; u < kU; u++) t += x[u];
+            acc = t;
+        }
+        colsum[g][j] = acc;
+    }
     const int32_t *r = a.rp + d.toff + d.id;
     for (int32_t p = tid; p < d.nlong; p += kSelThreads) {
-        const int4 h = a.lrow[d.long0 + p];  // row, 0, pieces, first slot
+        const int4 h = p == tid ? h0 : a.lrow[d.long0 + p];
+        const int32_t deg = r[h.x + 1] - r[h.x];
         int32_t c1 = 0, lo = INT_MAX, hi = 0;
         // the pieces' partials kPL at a time, their loads issued together
         constexpr int kPL = 8;
         for (int32_t k0 = 0; k0 < h.z; k0 += kPL) {
-            int4 x[kPL];
+            int4 y[kPL];
 #pragma unroll
-            for (int k = 0; k < kPL; k++) x[k] = reinterpret_cast<const int4 *>(a.pslot)[h.w + min(k0 + k, h.z - 1)];
+            for (int k = 0; k < kPL; k++) y[k] = reinterpret_cast<const int4 *>(a.pslot)[h.w + min(k0 + k, h.z - 1)];
 #pragma unroll
             for (int k = 0; k < kPL; k++) {
-                if (k0 + k < h.z && x[k].x > 0) {
-                    c1 += x[k].x;
-                    lo = min(lo, x[k].y);
-                    hi = max(hi, x[k].z);
+                if (k0 + k < h.z && y[k].x > 0) {
+                    c1 += y[k].x;
+                    lo = min(lo, y[k].y);
+                    hi = max(hi, y[k].z);
                 }
             }
         }
         a.summ[h.x] = pack_summary(c1, lo, hi);
-        if (a.unit_time == 0) add_rungs(hist, c1, lo, hi, r[h.x + 1] - r[h.x]);
+        if (a.unit_time == 0) add_rungs(hist, c1, lo, hi, deg);
     }
-    uint32_t m = 0;
-    unsigned long long sm = 0;
-    bool b2 = false;
-    int32_t hs[kRungs];
-#pragma unroll
-    for (int j = 0; j < kRungs; j++) hs[j] = 0;
-#pragma unroll
-    for (int k = 0; k < kBigGrid / kSelThreads; k++) {
-        const int32_t i = tid + k * kSelThreads;
-        if (i >= blocks) continue;
-        const int4 *sl = reinterpret_cast<const int4 *>(a.part + 32 * i);
-        int4 x[7];
-#pragma unroll
-        for (int j = 0; j < 7; j++) x[j] = sl[j];
-        const int32_t *xs = reinterpret_cast<const int32_t *>(x);
-#pragma unroll
-        for (int j = 0; j < kRungs; j++) hs[j] += xs[j];
-        m = max(m, (uint32_t)xs[24]);
-        sm += (unsigned long long)(uint32_t)xs[25] | (unsigned long long)(uint32_t)xs[26] << 32;
-        b2 |= xs[27] != 0;
-    }
-    // a wave's sums first: one LDS atomic per rung and wave
-#pragma unroll
-    for (int j = 0; j < kRungs; j++) {
-        const int32_t t = wave_sum_i32(hs[j]);
-        if (lane == 0 && t) atomicAdd(&hist[j], t);
-    }
-    m = wave_max_u32(m);
-    sm = wave_sum_u64(sm);
-    if (ballot(b2) && lane == 0) ws.bad = 1;
-    if (lane == 0) {
-        ws.wmax[wv] = m;
-        ws.wsum[wv] = sm;
+    __syncthreads();
+    if (tid < 28) {
+        long long t = 0;
+        for (int g = 0; g < kGroups; g++) t = tid == 24 ? max(t, colsum[g][tid]) : t + colsum[g][tid];
+        if (tid < kRungs) atomicAdd(&hist[tid], (int32_t)t);
+        else if (tid == 24) ws.wmax[0] = (uint32_t)t;
+        else if (tid == 25) ws.wsum[0] = (unsigned long long)t;
+        else if (tid == 26) ws.wsum[1] = (unsigned long long)t;
+        else if (t) ws.bad = 1;
     }
     __syncthreads();
     if (tid == 0) {
-        uint32_t mm = 0;
-        unsigned long long ss = 0;
-        for (int w = 0; w < kSelThreads / kWave; w++) {
-            mm = max(mm, ws.wmax[w]);
-            ss += ws.wsum[w];
-        }
+        const uint32_t mm = ws.wmax[0];
+        const unsigned long long ss = ws.wsum[0] + (ws.wsum[1] << 32);
         select_unit(a, d.id, d.n, (int32_t)mm, ss, hist);
         if (ws.bad) {
             atomicOr(&a.stat[2 * d.id], ST_EST);
@@ -864,7 +912,7 @@ __global__ __launch_bounds__(kBigThreads) void k_attr_big_b(AttrArgs a, AttrOut 
         int32_t ie = c1 == 0 || U < lo ? 0 : c1;
         if (!failed && c1 > 0 && lo <= U && U < hi) {
             int32_t l2, h2;
-            scan_hub<true>(a, d, e0, e1, tau, U, &ie, &l2, &h2);
+            scan_hub<true>(a, d, pk, e0, e1, tau, U, &ie, &l2, &h2);
         }
         if (lane == 0) write_row(a, o, d, v, e0, e1 - e0, tau, ie, failed);
     }

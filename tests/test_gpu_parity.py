@@ -240,6 +240,30 @@ def test_grid_attribute_pass_with_hub_rows(insp, case):
     dag.free()
 
 
+@pytest.mark.parametrize("hi", [126, 127, 32767, 32768])
+def test_grid_pass_at_the_word_limits(insp, hi):
+    """The grid pass gathers 8-bit task words when no tau of the DAG exceeds
+    126 ticks and 16-bit ones (a saturated entry read from the 32-bit word)
+    otherwise: taus just below and at both limits, hub rows and rows cut into
+    pieces, sums of two taus around the explicit U, the ladder U and a
+    schedule, against the oracle."""
+    w = _hub_dag(5, 33000, [1500, 70, 600, 3000])
+    est = (hi - synth.Stream(hi, 6).randint(np.arange(2 * w.n), 0, 40)).astype(np.int32).reshape(w.n, 2)
+    est[0] = hi
+    w = NS(**{**vars(w), "est": est, "dur": est.copy()})
+    say("grid word limit", w.n, hi)
+    dag, dur, est_d = insp.to_device(w)
+    rp, col = oracle.canon(w.n, w.row_ptr, w.col)
+    for n_gpu in (0, 2):
+        for U in (0, 2 * hi - 20, 2 * hi - 1):
+            ia, ie, Ug = insp.attributes(dag, 0, est_d, (6, n_gpu), unit_time=U)
+            ria, rie, rU = oracle.attributes(w.n, rp, col, w.est, n_gpu, unit_time=U)
+            assert Ug[0] == rU, (n_gpu, U)
+            assert np.array_equal(ia.cpu().numpy(), ria) and np.array_equal(ie.cpu().numpy(), rie), (n_gpu, U)
+    dag.free()
+    assert_same(run_gpu(insp, w), oracle.schedule(w, variant=oracle.HEAP), f"hubs {hi}")
+
+
 def test_attribute_paths_in_one_batch(insp):
     # small DAGs (one work-group each) beside a large one (the whole grid) and
     # an empty one, in one call: attributes of every DAG and every schedule
