@@ -847,8 +847,9 @@ __global__ __launch_bounds__(kSelThreads) void k_attr_big_sel(AttrArgs a, int32_
         const int4 h = p == tid ? h0 : a.lrow[d.long0 + p];
         const int32_t deg = r[h.x + 1] - r[h.x];
         int32_t c1 = 0, lo = INT_MAX, hi = 0;
-        // the pieces' partials kPL at a time, their loads issued together
-        constexpr int kPL = 8;
+        // the pieces' partials kPL at a time (every row of up to 8,192
+        // successors in one round), their loads issued together
+        constexpr int kPL = 16;
         for (int32_t k0 = 0; k0 < h.z; k0 += kPL) {
             int4 y[kPL];
 #pragma unroll
