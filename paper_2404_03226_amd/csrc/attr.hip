@@ -306,7 +306,7 @@ __device__ __forceinline__ void add_rungs(int32_t *hist, int32_t cnt1, int32_t l
 // "unscheduled" record when the DAG's estimates failed.
 __device__ __forceinline__ void write_row_w(const AttrArgs &a, const AttrOut &o, const DagDesc &d, int32_t v,
                                             int32_t e0, int32_t deg, int32_t tau, int32_t ie, unsigned long long w0,
-                                            bool failed = false) {
+                                            bool failed = false, bool put_dep = true) {
     const int64_t ub = d.toff - a.base;
     if (o.sim_init) {
         const int64_t t = d.toff + v;
@@ -315,7 +315,7 @@ __device__ __forceinline__ void write_row_w(const AttrArgs &a, const AttrOut &o,
             memset(&rec, 0, sizeof rec);
             rec.qpos = -1;
         } else {
-            o.dep[t] = w0;
+            if (put_dep) o.dep[t] = w0;
             rec.word = 0;
             rec.iev = ie;
             rec.qpos = -1;
@@ -331,9 +331,10 @@ __device__ __forceinline__ void write_row_w(const AttrArgs &a, const AttrOut &o,
     }
 }
 __device__ __forceinline__ void write_row(const AttrArgs &a, const AttrOut &o, const DagDesc &d, int32_t v,
-                                          int32_t e0, int32_t deg, int32_t tau, int32_t ie, bool failed) {
-    const unsigned long long w0 = o.sim_init && !failed ? a.word0[d.toff + v] : 0ull;
-    write_row_w(a, o, d, v, e0, deg, tau, ie, w0, failed);
+                                          int32_t e0, int32_t deg, int32_t tau, int32_t ie, bool failed,
+                                          bool put_dep = true) {
+    const unsigned long long w0 = o.sim_init && !failed && put_dep ? a.word0[d.toff + v] : 0ull;
+    write_row_w(a, o, d, v, e0, deg, tau, ie, w0, failed, put_dep);
 }
 
 // Whether the call writes nothing for DAG d: a schedule skips a DAG whose
@@ -494,7 +495,9 @@ struct GridBytes {
 
 // Pass A, the choice of U and pass B of one DAG in the per-DAG kernel, with
 // the task words looked up through pk (LDS or the inputs).
-template <int TPB, typename PK>
+// SIM: a schedule call whose pack phase has already copied the dependency
+// words (an attribute-only call keeps the general path).
+template <bool SIM, int TPB, typename PK>
 __device__ __forceinline__ void dag_passes(const AttrArgs &a, const AttrOut &o, const DagDesc &d, PK pk,
                                            DagLds *dl, WaveSlots &ws, int32_t *hist) {
     constexpr int kDagThreads = TPB, kDagWaves = TPB / kWave;
@@ -546,7 +549,7 @@ __device__ __forceinline__ void dag_passes(const AttrArgs &a, const AttrOut &o, 
                 sw[k] = srow[vv];
                 e0[k] = r[vv];
                 e1[k] = r[vv + 1];
-                w0[k] = o.sim_init ? a.word0[d.toff + vv] : 0ull;
+                w0[k] = !SIM && o.sim_init ? a.word0[d.toff + vv] : 0ull;
             }
 #pragma unroll
             for (int k = 0; k < kRB; k++) {
@@ -564,14 +567,14 @@ __device__ __forceinline__ void dag_passes(const AttrArgs &a, const AttrOut &o, 
                         if ((pv & kRem1) && (int64_t)tv + (int32_t)(pv & ~kRem1) <= (int64_t)U) ie++;
                     }
                 }
-                write_row_w(a, o, d, v, e0[k], e1[k] - e0[k], tv, ie, w0[k]);
+                write_row_w(a, o, d, v, e0[k], e1[k] - e0[k], tv, ie, w0[k], false, !SIM);
             }
         }
         return;
     }
     dag_pass<true>(r, c, d.n, pk, wv * kWave, kDagThreads, U, dl[wv],
                    [&](int32_t v, int32_t e0, int32_t deg, int32_t cnt, int32_t, int32_t) {
-                       if (v < d.n) write_row(a, o, d, v, e0, deg, (int32_t)(pk(v) & ~kRem1), cnt, false);
+                       if (v < d.n) write_row(a, o, d, v, e0, deg, (int32_t)(pk(v) & ~kRem1), cnt, false, !SIM);
                    });
 }
 
@@ -581,10 +584,11 @@ __device__ __forceinline__ void dag_passes(const AttrArgs &a, const AttrOut &o, 
 // share a CU; a DAG with a tau of 2^15 ticks or more looks its task words up
 // from the inputs instead.  The DAGs taken are sorder[first + blockIdx.x];
 // dynamic LDS: 2 bytes per task of the largest of them.
-template <bool HAS_REM, int TPB>
-__global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(8))) void k_attr_dag(AttrArgs a, AttrOut o,
+template <bool HAS_REM, bool SIM, int TPB>
+__global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(8))) void k_attr_dag(AttrArgs a, AttrOut oin,
                                                                                          int32_t first) {
     constexpr int kDagThreads = TPB, kDagWaves = TPB / kWave;
+    const AttrOut &o = oin;
     extern __shared__ uint16_t pks16[];
     __shared__ DagLds dl[kDagWaves];
     __shared__ WaveSlots ws;
@@ -601,8 +605,26 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(8))) void k
     for (int32_t v0 = tid; v0 < d.n; v0 += kTW * kDagThreads) {
         uint32_t w[kTW];
         bool b[kTW];
+        unsigned long long w0[kTW];
+        if constexpr (!HAS_REM && SIM) {
+            // a schedule call: each dependency word read whole, its in-degree
+            // the task's rem, and copied to the simulation's array here, so
+            // that pass B need not read it again
 #pragma unroll
-        for (int k = 0; k < kTW; k++) w[k] = task_word<HAS_REM>(a, d, min(v0 + k * kDagThreads, d.n - 1), b[k]);
+            for (int k = 0; k < kTW; k++) {
+                const int32_t vv = min(v0 + k * kDagThreads, d.n - 1);
+                w0[k] = a.word0[d.toff + vv];
+                const int2 e = reinterpret_cast<const int2 *>(a.est)[d.toff - a.base + vv];
+                b[k] = e.x < 1 || e.x > INSP_MAX_TICK || e.y < 1 || e.y > INSP_MAX_TICK;
+                w[k] = (uint32_t)(d.n_gpu > 0 ? e.y : e.x) | ((w0[k] >> 43) == 1 ? kRem1 : 0u);
+            }
+#pragma unroll
+            for (int k = 0; k < kTW; k++)
+                if (v0 + k * kDagThreads < d.n) o.dep[d.toff + v0 + k * kDagThreads] = w0[k];
+        } else {
+#pragma unroll
+            for (int k = 0; k < kTW; k++) w[k] = task_word<HAS_REM>(a, d, min(v0 + k * kDagThreads, d.n - 1), b[k]);
+        }
 #pragma unroll
         for (int k = 0; k < kTW; k++) {
             if (v0 + k * kDagThreads >= d.n) continue;
@@ -623,9 +645,9 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(8))) void k
     uint32_t m = 0;
     for (int w = 0; w < kDagWaves; w++) m = max(m, ws.wmax[w]);
     if (m <= kTau16) {
-        dag_passes<TPB>(a, o, d, [&](int32_t s) { return word32(pks16[s]); }, dl, ws, hist);
+        dag_passes<SIM, TPB>(a, o, d, [&](int32_t s) { return word32(pks16[s]); }, dl, ws, hist);
     } else {
-        dag_passes<TPB>(a, o, d,
+        dag_passes<SIM, TPB>(a, o, d,
                         [&](int32_t s) {
                             bool b;
                             return task_word<HAS_REM>(a, d, s, b);
@@ -977,8 +999,25 @@ static int big_grid(int32_t n, int32_t nhub) {
     return (int)std::max<int64_t>(1, std::min<int64_t>(kBigGrid, (waves + kBigWaves - 1) / kBigWaves));
 }
 
+// The per-DAG kernel for a call's mode: DAGs above kMidTasks (first in
+// sorder) with 1024 threads, the others with 256.
+template <bool HAS_REM, bool SIM>
+static int launch_attr_dag(const AttrArgs &a, const AttrOut &o, int32_t n_big, int32_t n_mid, size_t lds_big,
+                           size_t lds_mid, hipStream_t st) {
+    if (n_big > 0) {
+        if (int rc = set_lds_limit((const void *)&k_attr_dag<HAS_REM, SIM, kDagThreads>, lds_big)) return rc;
+        hipLaunchKernelGGL((k_attr_dag<HAS_REM, SIM, kDagThreads>), dim3(n_big), dim3(kDagThreads), lds_big, st, a, o,
+                           0);
+    }
+    if (n_mid > 0)
+        hipLaunchKernelGGL((k_attr_dag<HAS_REM, SIM, kMidThreads>), dim3(n_mid), dim3(kMidThreads), lds_mid, st, a, o,
+                           n_big);
+    return INSP_OK;
+}
+
 int run_attributes(insp_dag *dag, Workspace *ws, const int32_t *est, int32_t unit_time, const int32_t *rem,
                    int32_t *ia_out, int32_t *ie_out, bool sim_init, hipStream_t st) {
+    if (rem && sim_init) return set_error(INSP_E_INVAL, "a schedule starts from the initial in-degrees");
     AttrArgs a = make_args(dag, ws, est, unit_time, rem);
     if (!sim_init) {
         // an attribute-only call has status words of its own: it neither
@@ -1012,24 +1051,10 @@ int run_attributes(insp_dag *dag, Workspace *ws, const int32_t *est, int32_t uni
         const int32_t n_mid = ws->n_small - n_big;
         const size_t lds_big = 4 * (((size_t)std::max(ws->max_small, 1) + 1) / 2);
         const size_t lds_mid = 4 * (((size_t)std::max(n_mid > 0 ? ws->h_desc[ws->h_sorder[n_big]].n : 1, 1) + 1) / 2);
-        if (rem) {
-            if (n_big > 0) {
-                if (int rc = set_lds_limit((const void *)&k_attr_dag<true, kDagThreads>, lds_big)) return rc;
-                hipLaunchKernelGGL((k_attr_dag<true, kDagThreads>), dim3(n_big), dim3(kDagThreads), lds_big, st, a, o, 0);
-            }
-            if (n_mid > 0)
-                hipLaunchKernelGGL((k_attr_dag<true, kMidThreads>), dim3(n_mid), dim3(kMidThreads), lds_mid, st, a, o,
-                                   n_big);
-        } else {
-            if (n_big > 0) {
-                if (int rc = set_lds_limit((const void *)&k_attr_dag<false, kDagThreads>, lds_big)) return rc;
-                hipLaunchKernelGGL((k_attr_dag<false, kDagThreads>), dim3(n_big), dim3(kDagThreads), lds_big, st, a, o,
-                                   0);
-            }
-            if (n_mid > 0)
-                hipLaunchKernelGGL((k_attr_dag<false, kMidThreads>), dim3(n_mid), dim3(kMidThreads), lds_mid, st, a, o,
-                                   n_big);
-        }
+        int rc = rem        ? launch_attr_dag<true, false>(a, o, n_big, n_mid, lds_big, lds_mid, st)
+                 : sim_init ? launch_attr_dag<false, true>(a, o, n_big, n_mid, lds_big, lds_mid, st)
+                            : launch_attr_dag<false, false>(a, o, n_big, n_mid, lds_big, lds_mid, st);
+        if (rc) return rc;
     }
     for (int32_t di : ws->h_large) {
         const DagDesc &d = ws->h_desc[di];
