@@ -1474,6 +1474,40 @@ def test_library_graph_replays(insp, mode):
     dag.free()
 
 
+def test_library_graph_replays_with_large_dags(insp):
+    # two DAGs above the per-DAG kernel's limit in one batch, one whose taus
+    # fit the grid pass's 8-bit words and one that needs the 16-bit ones,
+    # beside small DAGs: the library-owned graph of the step, replayed with
+    # eager work between, matches the oracle every time
+    import torch
+    narrow = _hub_dag(21, 33000, [1500, 70, 600, 3000])
+    narrow = NS(**{**vars(narrow), "est": (narrow.est % 120 + 1).astype(np.int32)})
+    narrow.dur = narrow.est.copy()
+    wide = _hub_dag(22, 34000, [2100, 90, 5000])
+    ws = synth.cfg3(select=[5, 1200]) + [narrow, wide] + synth.cfg3(select=[77])
+    b = synth.concat(ws)
+    say("library graph, large DAGs", [w.n for w in ws])
+    dag, dur, est = insp.batch_to_device(b)
+    workers = [(w.n_cpu, w.n_gpu) for w in ws]
+    r = oracle.schedule_batch(b)
+    g = insp.BatchGraph(dag, workers, dur, est, insp.params())
+    out = g.out
+    for rep in range(3):
+        for k in out:
+            out[k].zero_()
+        junk = insp.schedule_batch(dag, workers, dur, est, insp.params(policy="efi"))  # eager work
+        torch.cuda.synchronize()
+        g.launch()
+        torch.cuda.synchronize()
+        for k in ("worker", "start", "finish", "ie_at_pop", "mode_at_pop"):
+            assert np.array_equal(out[k].cpu().numpy(), r[k]), (rep, k)
+        assert np.array_equal(out["makespan"].cpu().numpy(), r["makespan"]), rep
+        del junk
+    insp.sync_status(dag)
+    g.free()
+    dag.free()
+
+
 def test_library_graph_argument_errors(insp):
     import torch
     say("library graph errors")
