@@ -129,19 +129,20 @@ __device__ __forceinline__ void store_tile(uint4 v, int mode, int tid, uint16_t 
     }
 }
 
-__global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
+// One 64x64 output tile (bx, by) of g, K split bz when g.ksplit > 1.
+__device__ __forceinline__ void gemm_tile(const GemmArgs &g, int bx, int by, int bz) {
     __shared__ __attribute__((aligned(16))) uint16_t As[kSub][kTM * kLdsRow];
     __shared__ __attribute__((aligned(16))) uint16_t Bs[kSub][kTN * kLdsRow];
     __shared__ float cpart[2 * kTN];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int m0 = blockIdx.y * kTM, n0 = blockIdx.x * kTN;
+    const int m0 = by * kTM, n0 = bx * kTN;
     const int wm = (wv >> 1) * 32, wn = (wv & 1) * 32;
     f32x4 acc[2][2];
 #pragma unroll
     for (int a = 0; a < 2; a++)
 #pragma unroll
         for (int b = 0; b < 2; b++) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
-    const int kbeg = g.ksplit > 1 ? (int)blockIdx.z * g.kchunk : 0;
+    const int kbeg = g.ksplit > 1 ? bz * g.kchunk : 0;
     const int kend = g.ksplit > 1 ? min(g.K, kbeg + g.kchunk) : g.K;
     for (int k0 = kbeg; k0 < kend; k0 += kSub * kTK) {
         // stage kSub tiles of A [64 x 32] and B^T [64 x 32]: all reads first
@@ -181,7 +182,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
     }
     // accumulator layout: value i of a lane is row 4*(lane/16)+i, column lane%16
     if (g.ksplit > 1) {
-        float *P = g.C32 + (int64_t)blockIdx.z * g.pstride;
+        float *P = g.C32 + (int64_t)bz * g.pstride;
 #pragma unroll
         for (int b = 0; b < 2; b++) {
             const int n = n0 + wn + b * 16 + (lane & 15);
@@ -225,7 +226,22 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
         __syncthreads();
         // the two row halves of the tile, in order; one partial per M-tile
         if (tid < kTN && n0 + tid < g.N)
-            g.colpart[(int64_t)blockIdx.y * g.N + n0 + tid] = cpart[tid] + cpart[kTN + tid];
+            g.colpart[(int64_t)by * g.N + n0 + tid] = cpart[tid] + cpart[kTN + tid];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_gemm(GemmArgs g) { gemm_tile(g, blockIdx.x, blockIdx.y, blockIdx.z); }
+
+// Two independent products in one launch: blocks [0, n0) take g0's tiles
+// (x fastest, then y, then the K split), the rest g1's.
+__global__ __launch_bounds__(256) void k_gemm2(GemmArgs g0, int gx0, int gy0, int n0, GemmArgs g1, int gx1,
+                                                int gy1) {
+    int b = blockIdx.x;
+    if (b < n0) {
+        gemm_tile(g0, b % gx0, b / gx0 % gy0, b / (gx0 * gy0));
+    } else {
+        b -= n0;
+        gemm_tile(g1, b % gx1, b / gx1 % gy1, b / (gx1 * gy1));
     }
 }
 
@@ -254,6 +270,26 @@ __global__ __launch_bounds__(1024) void k_colreduce(const float *part, int rows,
     const int c = blockIdx.x * 64 + (threadIdx.x & 63);
     const float t = col_sum(part, rows, cols, c);
     if (threadIdx.x < 64 && c < cols) out[c] = t;
+}
+
+// k_colreduce over its first `cb` work-groups and, in the others, the sum of
+// S split-K partials (k_ksum's order), one output per thread: two
+// independent reductions in one launch.
+__global__ __launch_bounds__(1024) void k_colreduce_ksum(const float *part, int rows, int cols, float *out, int cb,
+                                                          const float *kpart, int S, int64_t pstride, int64_t n,
+                                                          float *kout) {
+    if ((int)blockIdx.x < cb) {
+        const int c = blockIdx.x * 64 + (threadIdx.x & 63);
+        const float t = col_sum(part, rows, cols, c);
+        if (threadIdx.x < 64 && c < cols) out[c] = t;
+        return;
+    }
+    const int64_t i = (int64_t)(blockIdx.x - cb) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float s = kpart[i];
+#pragma unroll 8
+    for (int z = 1; z < S; z++) s += kpart[z * pstride + i];
+    kout[i] = s;
 }
 
 // -------------------------------------------------------------- helpers
@@ -612,33 +648,48 @@ static bool aligned16(const void *p) { return ((uintptr_t)p & 15) == 0; }
 // Launch C = A B.  A plain fp32 product with a contiguous C (ldc == N) and
 // few output tiles splits K over the partial buffer `kpart`
 // (kKSplitFloats floats) so that the grid fills the chip.
-static void gemm(hipStream_t st, GemmArgs g, float *kpart = nullptr) {
+// A product's launch shape: operand read modes, the output tiles (gx, gy)
+// and, for a plain fp32 output when kpart is given, a split of K over S
+// work-groups whose partials go to kpart (out: where their sum belongs).
+struct GemmPlan {
+    int gx, gy, S;
+    float *out;
+};
+static GemmPlan gemm_plan(GemmArgs &g, float *kpart) {
     g.amode = (g.sak == 1 && g.sam % 8 == 0 && g.K % 8 == 0 && aligned16(g.A)) ? 1
               : (g.sam == 1 && g.sak % 8 == 0 && g.M % 8 == 0 && aligned16(g.A)) ? 2 : 0;
     g.bmode = (g.sbk == 1 && g.sbn % 8 == 0 && g.K % 8 == 0 && aligned16(g.B)) ? 1
               : (g.sbn == 1 && g.sbk % 8 == 0 && g.N % 8 == 0 && aligned16(g.B)) ? 2 : 0;
-    const int gx = (g.N + kTN - 1) / kTN, gy = (g.M + kTM - 1) / kTM;
+    GemmPlan pl;
+    pl.gx = (g.N + kTN - 1) / kTN;
+    pl.gy = (g.M + kTM - 1) / kTM;
+    pl.out = g.C32;
     const int kt = (g.K + kTK - 1) / kTK;
     int S = 1;
     if (kpart && g.C32 && !g.C16 && !g.bias && !g.relu && !g.mask && !g.colpart && g.ldc == g.N) {
         const int64_t mn = (int64_t)g.M * g.N;
-        S = std::min<int64_t>({(int64_t)kt, std::max(1, 256 / (gx * gy)), kKSplitFloats / std::max<int64_t>(mn, 1)});
+        S = std::min<int64_t>({(int64_t)kt, std::max(1, 256 / (pl.gx * pl.gy)),
+                               kKSplitFloats / std::max<int64_t>(mn, 1)});
         if (S > 1) {
             g.kchunk = ((kt + S - 1) / S) * kTK;
             S = (g.K + g.kchunk - 1) / g.kchunk;
         }
     }
-    if (S <= 1) {
-        g.ksplit = 1;
-        hipLaunchKernelGGL(k_gemm, dim3(gx, gy), dim3(256), 0, st, g);
-        return;
+    pl.S = std::max(S, 1);
+    g.ksplit = pl.S;
+    if (pl.S > 1) {
+        g.pstride = (int64_t)g.M * g.N;
+        g.C32 = kpart;
     }
-    float *out = g.C32;
-    g.ksplit = S;
-    g.pstride = (int64_t)g.M * g.N;
-    g.C32 = kpart;
-    hipLaunchKernelGGL(k_gemm, dim3(gx, gy, S), dim3(256), 0, st, g);
-    hipLaunchKernelGGL(k_ksum, dim3(blocks(g.pstride, 256)), dim3(256), 0, st, kpart, S, g.pstride, g.pstride, out);
+    return pl;
+}
+
+static void gemm(hipStream_t st, GemmArgs g, float *kpart = nullptr) {
+    const GemmPlan pl = gemm_plan(g, kpart);
+    hipLaunchKernelGGL(k_gemm, dim3(pl.gx, pl.gy, pl.S), dim3(256), 0, st, g);
+    if (pl.S > 1)
+        hipLaunchKernelGGL(k_ksum, dim3(blocks(g.pstride, 256)), dim3(256), 0, st, kpart, pl.S, g.pstride, g.pstride,
+                           pl.out);
 }
 
 }  // namespace insp
@@ -744,25 +795,34 @@ static int mlp_backward(insp_mlp *m, const float *x, const float *t, int64_t B, 
     hipLaunchKernelGGL(k_reduce_out, dim3(blocks(kHid + 3, 64)), dim3(1024), 0, st, part, ob, G,
                        m->loss.as<float>(), tab);
     hipLaunchKernelGGL(k_dw3, dim3(kHid), dim3(256), 0, st, m->h2.as<uint16_t>(), m->y.as<float>(), t, B, G);
-    GemmArgs g;
+    // dW2 = H1^T dH2 (K split over work-groups) and dH1 = (dH2 W2^T) * (H1 > 0)
+    // with its per-tile column sums, both from dH2: one launch; then the sum
+    // of dW2's partials and db1 (the column sums in order): one more
+    GemmArgs g, gh;
     memset(&g, 0, sizeof g);
-    // dW2 = H1^T dH2
     g.M = kHid; g.N = kHid; g.K = (int)B;
     g.A = m->h1.as<uint16_t>(); g.sam = 1; g.sak = kHid;
     g.B = m->dh2.as<uint16_t>(); g.sbk = kHid; g.sbn = 1;
     g.C32 = G + kOffW2; g.ldc = kHid;
-    gemm(st, g, m->kpart.as<float>());
-    // dH1 = (dH2 W2^T) * (H1 > 0); db1 = column sums (per tile, then in order)
-    memset(&g, 0, sizeof g);
-    g.M = (int)B; g.N = kHid; g.K = kHid;
-    g.A = m->dh2.as<uint16_t>(); g.sam = kHid; g.sak = 1;
-    g.B = m->w2.as<uint16_t>(); g.sbk = 1; g.sbn = kHid;
-    g.mask = m->h1.as<uint16_t>(); g.smm = kHid; g.smn = 1;
-    g.C16 = m->dh1.as<uint16_t>(); g.ldc16 = kHid;
-    g.colpart = part;
-    gemm(st, g);
-    hipLaunchKernelGGL(k_colreduce, dim3(blocks(kHid, 64)), dim3(1024), 0, st, part, (int)((B + kTM - 1) / kTM), kHid,
-                       G + kOffB1);
+    const GemmPlan pw = gemm_plan(g, m->kpart.as<float>());
+    memset(&gh, 0, sizeof gh);
+    gh.M = (int)B; gh.N = kHid; gh.K = kHid;
+    gh.A = m->dh2.as<uint16_t>(); gh.sam = kHid; gh.sak = 1;
+    gh.B = m->w2.as<uint16_t>(); gh.sbk = 1; gh.sbn = kHid;
+    gh.mask = m->h1.as<uint16_t>(); gh.smm = kHid; gh.smn = 1;
+    gh.C16 = m->dh1.as<uint16_t>(); gh.ldc16 = kHid;
+    gh.colpart = part;
+    const GemmPlan ph = gemm_plan(gh, nullptr);
+    const int nw = pw.gx * pw.gy * pw.S, nh = ph.gx * ph.gy;
+    hipLaunchKernelGGL(k_gemm2, dim3(nw + nh), dim3(256), 0, st, g, pw.gx, pw.gy, nw, gh, ph.gx, ph.gy);
+    const int cb = (int)blocks(kHid, 64);
+    if (pw.S > 1)
+        hipLaunchKernelGGL(k_colreduce_ksum, dim3(cb + (int)blocks(g.pstride, 1024)), dim3(1024), 0, st, part,
+                           (int)((B + kTM - 1) / kTM), kHid, G + kOffB1, cb, m->kpart.as<float>(), pw.S, g.pstride,
+                           g.pstride, pw.out);
+    else
+        hipLaunchKernelGGL(k_colreduce, dim3(cb), dim3(1024), 0, st, part, (int)((B + kTM - 1) / kTM), kHid,
+                           G + kOffB1);
     // dW1 = X^T dH1
     memset(&g, 0, sizeof g);
     g.M = kIn; g.N = kHid; g.K = (int)B;
