@@ -813,7 +813,7 @@ constexpr int kSelThreads = 1024;
 
 // The large DAG's U (one work-group): the rows cut into pieces combined into
 // their summaries and score contributions, then every block's partial slot.
-__global__ __launch_bounds__(kSelThreads) void k_attr_big_sel(AttrArgs a, int32_t di, int32_t blocks) {
+__global__ __launch_bounds__(kSelThreads) void k_attr_big_sel(AttrArgs a, int32_t di) {
     __shared__ WaveSlots ws;
     __shared__ int32_t hist[kRungs];
     const int tid = threadIdx.x;
@@ -1070,7 +1070,7 @@ int run_attributes(insp_dag *dag, Workspace *ws, const int32_t *est, int32_t uni
         }
         {
             ProfScope ps(st, "attr_sel");
-            hipLaunchKernelGGL(k_attr_big_sel, dim3(1), dim3(kSelThreads), 0, st, a, di, gb);
+            hipLaunchKernelGGL(k_attr_big_sel, dim3(1), dim3(kSelThreads), 0, st, a, di);
         }
         {
             ProfScope ps(st, "attr_b");
