@@ -81,7 +81,7 @@ struct AttrArgs {
     int32_t *part;              // grid pass: per-block partial results [kBigGrid][32]
     uint32_t *pkg;              // grid pass: task words of the large DAG (by row)
     unsigned long long *summ;   // grid pass: each row's pass-A summary
-    uint32_t *srow;             // per-DAG pass, ladder U: each row's pass-A decision word (global task index;
+    uint32_t *srow;             // per-DAG pass, ladder U: each row's pass-A decision word, 16 bits (global task index;
                                 // scratch the simulation reuses later)
     int32_t first;              // DAG id of desc[0]
     const int32_t *rp, *col;
@@ -183,9 +183,13 @@ __device__ __forceinline__ void unpack_summary(unsigned long long w, int32_t &cn
 // largest tau(v) + tau(s) over them (each <= 22).  Since x <= 2^j exactly when
 // ceil(log2 x) <= j, IE at U = 2^j is the count when the largest rung is <= j,
 // zero when the least is > j, and needs the row's successors only otherwise.
-__device__ __forceinline__ uint32_t decision_word(int32_t cnt1, int32_t lo, int32_t hi) {
-    if (cnt1 <= 0) return 0u;
-    return (uint32_t)cnt1 | (uint32_t)ceil_log2(lo) << 22 | (uint32_t)ceil_log2(hi) << 27;
+// Kept in 16 bits: the count in bits 0..5, the rungs in 6..10 and 11..15; a
+// count of 63 or more is stored as 63 with rungs 0 and 31, which sends the row
+// to the rescan at every U of the ladder.
+__device__ __forceinline__ uint16_t decision_word(int32_t cnt1, int32_t lo, int32_t hi) {
+    if (cnt1 <= 0) return 0;
+    if (cnt1 >= 63) return (uint16_t)(63u | 31u << 11);
+    return (uint16_t)((uint32_t)cnt1 | (uint32_t)ceil_log2(lo) << 6 | (uint32_t)ceil_log2(hi) << 11);
 }
 
 // The task word from the inputs: rem (given, or the in-degree in the high
@@ -505,7 +509,7 @@ __device__ __forceinline__ void dag_passes(const AttrArgs &a, const AttrOut &o, 
     const int32_t *r = a.rp + d.toff + d.id;
     const int32_t *c = a.col + d.eoff;
     const bool ability = a.unit_time == 0;
-    uint32_t *srow = a.srow + d.toff;
+    uint16_t *srow = reinterpret_cast<uint16_t *>(a.srow) + d.toff;
     dag_pass<false>(r, c, d.n, pk, wv * kWave, kDagThreads, 0, dl[wv],
                     [&](int32_t v, int32_t, int32_t deg, int32_t cnt, int32_t lo, int32_t hi) {
                         if (v < d.n && ability) {
@@ -557,7 +561,7 @@ __device__ __forceinline__ void dag_passes(const AttrArgs &a, const AttrOut &o, 
                 if (v >= d.n) break;
                 const uint32_t w = sw[k];
                 const int32_t tv = (int32_t)(pk(v) & ~kRem1);
-                const int32_t cnt = (int32_t)(w & 0x3FFFFF), jl = (int32_t)(w >> 22 & 31), jh = (int32_t)(w >> 27);
+                const int32_t cnt = (int32_t)(w & 63), jl = (int32_t)(w >> 6 & 31), jh = (int32_t)(w >> 11 & 31);
                 int32_t ie = 0;
                 if (cnt > 0 && jh <= j) {
                     ie = cnt;

@@ -133,8 +133,10 @@ def _stars(seed, n_stars, k):
 
 def test_attributes_rows_split_by_u(insp):
     """Rows whose tau(v) + tau(s) span straddles the ladder's U: IE from a
-    count of the row's successors, not from its pass-A summary."""
-    for seed, (n_stars, k) in enumerate([(1, 40), (30, 12), (200, 3)]):
+    count of the row's successors, not from its pass-A summary; rows of 63 or
+    more ready successors, whose 16-bit decision word sends them to that
+    count whatever their span."""
+    for seed, (n_stars, k) in enumerate([(1, 40), (30, 12), (200, 3), (3, 63), (2, 150), (40, 62)]):
         w = _stars(seed, n_stars, k)
         rp, col = oracle.canon(w.n, w.row_ptr, w.col)
         ria, rie, rU = oracle.attributes(w.n, rp, col, w.est, w.n_gpu)
